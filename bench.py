@@ -1,0 +1,213 @@
+"""Benchmark of the emRKC hot path on one MI355X.
+
+One bench step is one whole simulation of the 3-D cuboid workload
+(201 x 71 x 31 Q1 nodes = 442,401 nodes, CRN surrogate with 21 variables,
+dt = 0.05 ms, T = 50 ms): resting-state initialisation, spectral-radius
+estimation by power iteration, and 1000 emRKC steps (outer RKC stages with
+the fused ionic/Rush-Larsen head kernel and the inner diffusion stages),
+replayed from HIP graphs.  Throughput is node-steps per second of the whole
+job.  The same line carries the dominant kernel's roofline (timed with HIP
+events in a separate pass of eagerly launched kernels), the mixed FP32 form
+with its error in V, and the FP64 oracle timed on the host cores.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, published
+FP64_VALU_PEAK_TFLOPS = 78.6   # MI355X vector FP64, published
+METRIC = "node-steps/s emRKC on 1 GPU, % HBM roofline; FP32 vs FP64 at stated V error"
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def head_bytes_per_node(nz, wz, s, m, j):
+    """Algorithmic HBM bytes per node of the fused head kernel of stage j:
+    V_{j-1} (8), z_{j-1} and z_j (nz*wz each), z_{j-2} when j >= 2, and
+    either S_V (wz for mixed... 4 or 8) + u_1 (8) or, when m == 1, V_j (8)
+    plus V_{j-2} when j >= 2."""
+    b = 8 + 2 * nz * wz + (nz * wz if j >= 2 else 0)
+    if m >= 2:
+        b += (4 if wz == 4 else 8) + 8
+    else:
+        b += 8 + (8 if j >= 2 else 0)
+    return b
+
+
+def inner_bytes_per_node(wz, k, m, j):
+    """Inner stage k >= 2: u_{k-1} (8, neighbours from cache), u_{k-2} (8),
+    S_V (4 or 8) and the output (8); at k == m the outer V update also
+    reads V_{j-1} (already read when k == 2) and V_{j-2} when j >= 2."""
+    b = 8 + 8 + (4 if wz == 4 else 8) + 8
+    if k == m:
+        b += (8 if k != 2 else 0) + (8 if j >= 2 else 0)
+    return b
+
+
+class Job:
+    def __init__(self, cfg, precision, stream):
+        from paper_2401_01745_amd import emrkc as E
+        self.E = E
+        self.cfg = cfg
+        self.sim = E.simulation_from_config(cfg, precision=precision)
+        E.emrkc_set_stream(self.sim.ctx, stream.cuda_stream)
+        self.nsim = int(round(cfg["T"] / cfg["dt"]))
+
+    def run(self):
+        E, s = self.E, self.sim
+        s.state.t0 = 0.0
+        s.state.step = 0
+        E.emrkc_init_state(s.ctx, s.state)
+        rF, rS, itF, itS, _ = E.emrkc_estimate_rho(s.ctx, s.state)
+        E.emrkc_step(s.ctx, s.state, self.cfg["dt"], self.nsim)
+        return rF, rS, itF, itS
+
+
+def time_jobs(job, warmup, steps, torch):
+    for _ in range(warmup):
+        job.run()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        info = job.run()
+    torch.cuda.synchronize()
+    return time.perf_counter() - t0, info
+
+
+def cpu_baseline(cfg, seconds):
+    """The FP64 oracle on the same workload, timed for a bounded number of
+    emRKC steps on the full mesh (assembly and radii excluded)."""
+    from oracle.emrkc import emrkc_step, stage_counts
+    from oracle.monodomain import build_grid_problem
+    from oracle.powiter import compute_rho, random_unit_interval
+    prob = build_grid_problem(cfg)
+    y = prob.uniform_state()
+    v0 = random_unit_interval(y.size, 0)
+    _, rF, _, _ = compute_rho(0.0, y, prob.f_F, v0.copy())
+    _, rS, _, _ = compute_rho(0.0, y, prob.f_S, v0.copy())
+    rF, rS = 1.05 * rF, 1.05 * rS
+    n = 0
+    t0 = time.perf_counter()
+    while True:
+        y = emrkc_step(n * cfg["dt"], y, cfg["dt"], prob, rF, rS)
+        n += 1
+        el = time.perf_counter() - t0
+        if el >= seconds or n >= 1000:
+            break
+    return prob.N * n / el, n, el, stage_counts(cfg["dt"], rF, rS)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--config", default="c2_3d_crn")
+    ap.add_argument("--kernel-steps", type=int, default=200)
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-mixed", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on exactly one GPU: the emRKC hot path here is a single-GPU build "
+              "(--gpus %d requested)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2401_01745_amd import emrkc as E
+    from workloads.configs import get_config
+    E.lib()
+    torch.cuda.set_device(0)
+    cfg = get_config(args.config)
+    N = int(np.prod(cfg["n"]))
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        log("bench: %s, N=%d, building FP64 context" % (cfg["name"], N))
+        job = Job(cfg, "fp64", stream)
+        elapsed, (rF, rS, itF, itS) = time_jobs(job, args.warmup, args.steps, torch)
+        s, m, eta = E.emrkc_stages(job.sim.ctx, cfg["dt"])
+        value = N * job.nsim * args.steps / elapsed
+        log("bench: fp64 %.3f ms per simulation (%d steps), %.4g node-steps/s, s=%d m=%d" %
+            (1e3 * elapsed / args.steps, job.nsim, value, s, m))
+        V64 = job.sim.V.cpu().numpy().copy()
+
+        # per-kernel durations with HIP events (eager launches, same kernels)
+        head_ms, inner_ms, n_head, n_inner = E.emrkc_profile_step(job.sim.ctx, job.sim.state, cfg["dt"],
+                                                                  args.kernel_steps)
+        nz = job.sim.nv - 1
+        hb = head_bytes_per_node(nz, 8, s, m, 1) * N
+        ib = inner_bytes_per_node(8, m, m, 1) * N if m >= 2 else 0
+        log("bench: head %.4f ms (%d launches), inner %.4f ms (%d launches)" % (head_ms, n_head, inner_ms, n_inner))
+        head_gbs = hb / (head_ms * 1e-3) / 1e9
+        inner_gbs = ib / (inner_ms * 1e-3) / 1e9 if inner_ms > 0 else None
+        prof_path = os.path.join(ROOT, "profiles", "traffic_c2_3d_crn_fp64.json")
+        traffic = None
+        if os.path.exists(prof_path):
+            tr = json.load(open(prof_path))
+            if tr.get("kernel_source_hash") == kernel_hash():
+                traffic = tr.get("head_bytes_per_launch")
+        roof = {"kernel": "k_head (fused ionic + Rush-Larsen + outer z recurrence + first inner stage)",
+                "bound": "hbm", "achieved": round(head_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(head_gbs / HBM_PEAK_GBS, 4), "traffic": traffic,
+                "bytes_per_launch": hb, "launch_ms": round(head_ms, 5),
+                "inner_kernel": {"achieved": round(inner_gbs, 1) if inner_gbs else None,
+                                 "frac": round(inner_gbs / HBM_PEAK_GBS, 4) if inner_gbs else None,
+                                 "bytes_per_launch": ib, "launch_ms": round(inner_ms, 5)}}
+
+        mixed = None
+        if not args.no_mixed:
+            log("bench: mixed FP32 form")
+            jm = Job(cfg, "mixed", stream)
+            el_m, _ = time_jobs(jm, 1, max(1, args.steps // 2), torch)
+            value_m = N * jm.nsim * max(1, args.steps // 2) / el_m
+            Vm = jm.sim.V.cpu().numpy()
+            d = Vm - V64
+            mixed = {"value": value_m, "speedup_vs_fp64": round(value_m / value, 3),
+                     "V_rel_l2_vs_fp64": float(np.linalg.norm(d) / np.linalg.norm(V64)),
+                     "V_rel_max_vs_fp64": float(np.abs(d).max() / np.abs(V64).max()),
+                     "reference": "GPU FP64 path at T (matches the FP64 oracle to 1e-10 in the parity tests)"}
+            log("bench: mixed %.4g node-steps/s, V rel L2 %.3e" % (value_m, mixed["V_rel_l2_vs_fp64"]))
+            jm.sim.close()
+        job.sim.close()
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("bench: CPU oracle baseline")
+        v, n, el, sm = cpu_baseline(cfg, args.cpu_seconds)
+        cpu = {"value": v, "unit": "node-steps/s", "cores": 1, "kind": "oracle",
+               "sample": "%d emRKC steps of the full %d-node mesh in %.1f s (numpy/scipy, single thread; "
+                         "host has %d logical CPUs)" % (n, N, el, os.cpu_count())}
+
+    out = {"metric": METRIC, "value": value, "unit": "node-steps/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": 1e3 * elapsed / args.steps, "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": "%s: Q1 grid %s (%d nodes), %s, chi=%g/mm, Cm=%g uF/mm^2, sigma=%s, dt=%g ms, "
+                                  "T=%g ms; one bench step = init + power iteration + %d emRKC steps"
+                                  % (cfg["name"], "x".join(map(str, cfg["n"])), N, cfg["model"], cfg["chi"],
+                                     cfg["Cm"], list(cfg["sigma"]), cfg["dt"], cfg["T"], job.nsim),
+                      "s": s, "m": m, "eta": eta, "rho_F": rF, "rho_S": rS, "powiter_iters": [itF, itS]},
+           "roofline": roof, "mixed": mixed, "cpu_baseline": cpu}
+    print(json.dumps(out), flush=True)
+
+
+def kernel_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("emrkc_kernels.hip", "emrkc_device.h", "emrkc_internal.h"):
+        h.update(open(os.path.join(ROOT, "paper_2401_01745_amd", "csrc", f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,243 @@
+/*
+ * emrkc.h -- C ABI of the MI355X emRKC library (libemrkc.so).
+ *
+ * The library advances the semi-discrete monodomain model
+ *
+ *     Cm M dV/dt = chi^{-1} A V + M I_stim(t) - M I_ion(V, z_E, z_S)
+ *     dz_E/dt    = Lambda_E(V) (z_E - z_inf(V))          (gating variables)
+ *     dz_S/dt    = g_S(V, z_E, z_S)                      (other ionic variables)
+ *
+ * (paper: section "Space discretization", eq. sd_sys, with the F/S/E split of
+ * eq. mono_in_FSE) by the explicit exponential multirate RKC method of the
+ * emRKC algorithm: outer RKC stages on the averaged force, each averaged
+ * force made of one exponential Euler step for the gates, one ionic
+ * evaluation and an inner RKC iteration of lumped-mass diffusion products.
+ * A is the negative semidefinite stiffness operator (A = -K) and M the
+ * row-sum lumped mass.
+ *
+ * Conventions shared by every call:
+ *  - Return value: EMRKC_OK (0) or a negative EMRKC_E* code.  No call throws
+ *    or aborts; the text of the last error of a context is available from
+ *    emrkc_last_error().
+ *  - Host pointers passed to a call are read during the call only (they are
+ *    copied); the caller keeps ownership.  Device pointers (state buffers,
+ *    outputs of the evaluation calls) are owned by the caller; the library
+ *    never frees them.
+ *  - All GPU work of a context is queued on its stream (emrkc_set_stream;
+ *    default: the null stream).  Calls return once the work is queued unless
+ *    stated otherwise.  One context must not be used from two host threads
+ *    at the same time.
+ *  - State layout (structure of arrays, node index fastest):
+ *      V : double[N]
+ *      z : [n_v - 1][N] of double (EMRKC_FP64) or float (EMRKC_MIXED32),
+ *          gates first (model order), then the other ionic variables.
+ *  - Units are the caller's; the workloads use mm, ms, mV, uF/mm^2, mS/mm
+ *    and uA/mm^2.  The ionic models compute their current per unit
+ *    capacitance (mV/ms), so that I_ion = Cm * i_ion.
+ */
+#ifndef EMRKC_H
+#define EMRKC_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- error codes -------------------------------------------------------- */
+#define EMRKC_OK 0
+#define EMRKC_EINVAL (-1)       /* invalid argument or call order            */
+#define EMRKC_ENOMEM (-2)       /* device or host allocation failed          */
+#define EMRKC_EHIP (-3)         /* a HIP runtime call failed                 */
+#define EMRKC_ENONFINITE (-4)   /* EMRKC_CHECK_FINITE found a NaN/Inf in V   */
+#define EMRKC_ENOCONV (-5)      /* power iteration hit its iteration limit   */
+#define EMRKC_EUNSUPPORTED (-6) /* valid but not implemented combination     */
+
+/* ---- enumerations ------------------------------------------------------- */
+#define EMRKC_MESH_Q1_GRID 1    /* structured Q1 grid, 2-D or 3-D            */
+#define EMRKC_MESH_P1_TET 2     /* unstructured P1 tetrahedra                */
+
+#define EMRKC_MODEL_HH 1        /* classical Hodgkin-Huxley (N = 3 gates)     */
+#define EMRKC_MODEL_LINEAR 2    /* linear test model: i_ion = a V, 1 gate     */
+#define EMRKC_MODEL_CRN_SURR 3  /* CRN-shaped surrogate: 15 gates + 5 slow    */
+#define EMRKC_MODEL_TTP_SURR 4  /* TTP-shaped surrogate: 12 gates + 6 slow    */
+
+#define EMRKC_FP64 0            /* every quantity in double                  */
+#define EMRKC_MIXED32 1         /* z and ionic/diffusion arithmetic in float,
+                                   V, recurrences, coefficients and spectral
+                                   radii in double                           */
+
+#define EMRKC_CHECK_FINITE 1u   /* emrkc_step synchronises and checks V      */
+
+/* ---- types -------------------------------------------------------------- */
+typedef struct emrkc_ctx emrkc_ctx;
+
+/* Mesh description.  For EMRKC_MESH_Q1_GRID: dim in {2, 3}, n[d] >= 2 nodes
+ * per axis, h[d] > 0 spacing; node (i, j, k) has index i + n0*(j + n1*k).
+ * The library derives the stiffness and lumped mass itself (exact Q1
+ * integration, zero-flux boundary).  For EMRKC_MESH_P1_TET: n_nodes,
+ * n_elems, coords[n_nodes][3], tets[n_elems][4] (0-based node indices,
+ * any orientation) and fibres[n_elems][3] (fibre direction a_l, any
+ * non-zero length); element conductivity D = sigma_l a a^T +
+ * sigma_t (I - a a^T) (eq. def_D with sigma_n = sigma_t). */
+typedef struct {
+  int32_t kind;
+  int32_t dim;
+  int64_t n[3];
+  double h[3];
+  int64_t n_nodes;
+  int64_t n_elems;
+  const double *coords;
+  const int64_t *tets;
+  const double *fibres;
+} emrkc_mesh;
+
+/* Effective conductivities (eq. def_D).  Q1 grids use D = diag(sigma_l,
+ * sigma_t, sigma_n): fibres along x, sheets along y. */
+typedef struct {
+  double sigma_l, sigma_t, sigma_n;
+} emrkc_conductivity;
+
+typedef struct {
+  double chi;             /* surface-to-volume ratio, > 0                    */
+  double Cm;              /* membrane capacitance, > 0                       */
+  double eps;             /* RKC damping parameter (0.05)                    */
+  double rho_safety;      /* factor applied to estimated radii (1.05)        */
+  int32_t precision;      /* EMRKC_FP64 or EMRKC_MIXED32                     */
+  uint32_t flags;         /* EMRKC_CHECK_FINITE                              */
+  const uint8_t *stim_mask; /* host, N entries (nonzero = stimulated), or NULL */
+  double stim_amp;        /* I_stim on stimulated nodes (per membrane area)  */
+  double stim_t_on;       /* stimulus on for t_on <= t <= t_off              */
+  double stim_t_off;
+  double rho_F;           /* > 0: spectral radius of f_F used as given       */
+  double rho_S;           /* > 0: spectral radius of f_S used as given       */
+  double powiter_tol;     /* power-iteration tolerance (1e-2)                */
+  double powiter_eps;     /* relative perturbation size (1e-8)               */
+  int32_t powiter_max_iter; /* iteration limit per radius (100)             */
+  int32_t reserved0;
+  uint64_t powiter_seed;  /* splitmix64 state of the start vector (0)        */
+  double linear_a;        /* EMRKC_MODEL_LINEAR: i_ion = a V                 */
+  double linear_lambda_E; /* EMRKC_MODEL_LINEAR: constant gate rate (< 0)    */
+} emrkc_params;
+
+/* Caller-owned state.  t0 and step define the time of the state as
+ * t = t0 + step*dt (computed, never accumulated); emrkc_step advances step
+ * and writes t.  V and z are device pointers laid out as described above. */
+typedef struct {
+  double t0;
+  int64_t step;
+  double t;
+  void *V;
+  void *z;
+} emrkc_state;
+
+/* Per-call statistics of the last emrkc_step. */
+typedef struct {
+  int32_t s, m;           /* outer and inner stage counts                     */
+  double eta;             /* inner integration length                         */
+  int64_t kernels_per_step;
+  int32_t used_graph;     /* 1 if the steps were replayed from a HIP graph    */
+  int32_t reserved0;
+} emrkc_stats;
+
+/* ---- host-only helpers (no GPU needed) ---------------------------------- */
+
+/* Fills *p with the defaults named above (chi = 140, Cm = 0.01, eps = 0.05,
+ * rho_safety = 1.05, FP64, no stimulus, radii to be estimated, tol 1e-2,
+ * eps 1e-8, 100 iterations, seed 0). */
+void emrkc_default_params(emrkc_params *p);
+
+/* Number of state variables including V (n_v) and of gates of a model, or
+ * EMRKC_EINVAL for an unknown model. */
+int emrkc_model_num_vars(int ionic_model);
+int emrkc_model_num_gates(int ionic_model);
+
+/* RKC coefficients of the RKC algorithm (get_coeffs): for j = 0..s the
+ * arrays receive mu_j, nu_j, kappa_j, c_j (entries that the algorithm does
+ * not define are 0).  Each array must hold s + 1 doubles.  s in [1, 10000],
+ * eps > 0. */
+int emrkc_rkc_coeffs(int s, double eps, double *mu, double *nu, double *kappa, double *c);
+
+/* Stage counts of the emRKC algorithm for given radii (get_stages twice):
+ * s = max(1, ceil(sqrt(dt rho_S / beta))), eta = 2 dt / (beta s^2),
+ * m = max(1, ceil(sqrt(eta rho_F / beta))), beta = 2 - 4 eps / 3. */
+int emrkc_stage_counts(double dt, double rho_F, double rho_S, double eps,
+                       int *s, int *m, double *eta);
+
+/* ---- context ------------------------------------------------------------ */
+
+/* Creates a context on the current HIP device: validates and copies the
+ * inputs, builds the diffusion operator (with 1/(chi Cm M_ii) folded into
+ * each row) and allocates the library's work buffers.  *out is set to NULL
+ * on failure. */
+int emrkc_create(const emrkc_mesh *mesh, const emrkc_conductivity *cond, int ionic_model,
+                 const emrkc_params *params, emrkc_ctx **out);
+
+/* Frees every buffer the library owns.  NULL is accepted. */
+void emrkc_destroy(emrkc_ctx *ctx);
+
+/* Routes all later work of ctx to the HIP stream `hip_stream` (a
+ * hipStream_t; NULL selects the null stream). */
+int emrkc_set_stream(emrkc_ctx *ctx, void *hip_stream);
+
+int64_t emrkc_num_nodes(const emrkc_ctx *ctx);   /* N, or -1 for NULL */
+int emrkc_num_vars(const emrkc_ctx *ctx);        /* n_v, or -1 for NULL */
+const char *emrkc_last_error(const emrkc_ctx *ctx);
+
+/* Writes the model's uniform resting state (V and every z) into the state
+ * buffers; sets t = t0 and leaves step unchanged. */
+int emrkc_init_state(emrkc_ctx *ctx, emrkc_state *state);
+
+/* Spectral radii of the Jacobians of f_F and f_S at `state` by the nonlinear
+ * power iteration of the appendix (Compute_Rho), warm-started from the
+ * context's previous vectors, then multiplied by rho_safety and stored in
+ * the context.  Norms are Euclidean over every state component and
+ * computed in double in both precisions.  Synchronises the stream.  Any of
+ * the output pointers may be NULL.  Returns EMRKC_ENOCONV if either
+ * iteration reached powiter_max_iter (the radii are still stored). */
+int emrkc_estimate_rho(emrkc_ctx *ctx, const emrkc_state *state, double *rho_F, double *rho_S,
+                       int *iters_F, int *iters_S);
+
+/* Sets the radii used by emrkc_step (taken as given, no safety factor). */
+int emrkc_set_rho(emrkc_ctx *ctx, double rho_F, double rho_S);
+int emrkc_get_rho(const emrkc_ctx *ctx, double *rho_F, double *rho_S);
+
+/* (s, m, eta) that emrkc_step would use for dt with the stored radii. */
+int emrkc_stages(const emrkc_ctx *ctx, double dt, int *s, int *m, double *eta);
+
+/* Advances `state` by nsteps >= 0 emRKC steps of size dt > 0 (emRKC_Step of
+ * the emRKC algorithm).  Requires radii (estimated or set).  Work is queued
+ * on the context stream; state->step and state->t are updated on return.
+ * With EMRKC_CHECK_FINITE the call synchronises and returns
+ * EMRKC_ENONFINITE if V holds a NaN or infinity. */
+int emrkc_step(emrkc_ctx *ctx, emrkc_state *state, double dt, int64_t nsteps);
+
+/* Diagnostic form of emrkc_step: advances the state the same way (same
+ * kernels, same results) but launches every kernel directly on the context
+ * stream with a HIP event recorded before and after it, synchronises, and
+ * returns the mean duration in ms of the fused outer-stage head kernel and
+ * of the inner-stage kernel, with their launch counts.  1 <= nsteps <= 1e5.
+ * Output pointers may be NULL. */
+int emrkc_profile_step(emrkc_ctx *ctx, emrkc_state *state, double dt, int64_t nsteps, double *head_ms,
+                       double *inner_ms, int64_t *n_head, int64_t *n_inner);
+
+/* Statistics of the last emrkc_step call. */
+int emrkc_last_stats(const emrkc_ctx *ctx, emrkc_stats *out);
+
+/* ---- evaluation of single terms (component checks) ---------------------- */
+
+/* out[i] = ((chi Cm M_L)^{-1} A V)_i for i < N: the V component of f_F
+ * (eq. mono_in_FSE).  V and out are device double[N], distinct. */
+int emrkc_apply_diffusion(emrkc_ctx *ctx, const double *V, double *out);
+
+/* out = f_S(t, y) for the full state (eq. mono_in_FSE): V component
+ * Cm^{-1}(I_stim(t) - I_ion), gate components 0, other components g_S.
+ * out is device double[n_v * N] in the state layout; computed in double in
+ * both precisions. */
+int emrkc_eval_rhs_slow(emrkc_ctx *ctx, const emrkc_state *state, double t, double *out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* EMRKC_H */

@@ -1,0 +1,372 @@
+// Device-side building blocks of the emRKC library: arithmetic policies for
+// the two precisions, the ionic models, the structured Q1 diffusion stencil
+// and the block-index remapping for the MI355X's eight XCDs.
+//
+// The ionic models follow the monodomain model's gate form
+// dz/dt = alpha (1 - z) - beta z, rewritten as Lambda_E (z - z_inf) with
+// Lambda_E = -(alpha + beta) and z_inf = alpha / (alpha + beta); their ionic
+// current is per unit capacitance (mV/ms), so that I_ion = Cm * i_ion.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace emrkc {
+
+// ---------------------------------------------------------------------------
+// Arithmetic policies.  FP64 uses the correctly rounded division and the
+// device libm; the FP32 policy uses the native exp2/log2 based fast paths
+// (v_exp_f32, v_log_f32, v_rcp_f32) except for expm1, whose accuracy near 0
+// carries the exponential Euler update of slow gates.
+// ---------------------------------------------------------------------------
+struct MathF64 {
+  using R = double;
+  static __device__ __forceinline__ R exp(R x) { return ::exp(x); }
+  static __device__ __forceinline__ R expm1(R x) { return ::expm1(x); }
+  static __device__ __forceinline__ R log(R x) { return ::log(x); }
+  static __device__ __forceinline__ R div(R a, R b) { return a / b; }
+};
+
+struct MathF32 {
+  using R = float;
+  static __device__ __forceinline__ R exp(R x) { return __expf(x); }
+  static __device__ __forceinline__ R expm1(R x) { return ::expm1f(x); }
+  static __device__ __forceinline__ R log(R x) { return __logf(x); }
+  static __device__ __forceinline__ R div(R a, R b) { return __fdividef(a, b); }
+};
+
+// Runtime parameters of the models that have any (the linear test model).
+struct ModelParams {
+  double lin_a;      // i_ion = a V
+  double lin_lamE;   // constant gate rate
+};
+
+// x / (e^x - 1) with its removable singularity: 1 - x/2 for |x| < 1e-7.
+template <class M>
+__device__ __forceinline__ typename M::R x_over_expm1(typename M::R x) {
+  using R = typename M::R;
+  return (x < R(1e-7) && x > R(-1e-7)) ? R(1) - R(0.5) * x : M::div(x, M::expm1(x));
+}
+
+template <class M>
+__device__ __forceinline__ void gate_from_rates(typename M::R a, typename M::R b,
+                                                typename M::R &lam, typename M::R &zinf) {
+  using R = typename M::R;
+  R s = a + b;
+  lam = -s;
+  zinf = M::div(a, s);
+}
+
+// Classical Hodgkin-Huxley gates m, h, n (modern sign convention, rest near
+// -65 mV); the m rates are multiplied by km.
+template <class M>
+__device__ __forceinline__ void hh_core_gates(typename M::R V, typename M::R km,
+                                              typename M::R *lam, typename M::R *zinf) {
+  using R = typename M::R;
+  R am = km * x_over_expm1<M>(-(V + R(40)) * R(0.1));
+  R bm = km * (R(4) * M::exp(-(V + R(65)) * R(1.0 / 18.0)));
+  R ah = R(0.07) * M::exp(-(V + R(65)) * R(0.05));
+  R bh = M::div(R(1), R(1) + M::exp(-(V + R(35)) * R(0.1)));
+  R an = R(0.1) * x_over_expm1<M>(-(V + R(55)) * R(0.1));
+  R bn = R(0.125) * M::exp(-(V + R(65)) * R(1.0 / 80.0));
+  gate_from_rates<M>(am, bm, lam[0], zinf[0]);
+  gate_from_rates<M>(ah, bh, lam[1], zinf[1]);
+  gate_from_rates<M>(an, bn, lam[2], zinf[2]);
+}
+
+// Surrogate extra gate: alpha = A/(1 + e^{-(V - Va)/sa}), beta = A/(1 + e^{(V - Vb)/sb}).
+struct SigmoidGate {
+  double A, Va, inv_sa, Vb, inv_sb;
+};
+
+template <class M>
+__device__ __forceinline__ void sigmoid_gate(typename M::R V, const SigmoidGate &g,
+                                             typename M::R &lam, typename M::R &zinf) {
+  using R = typename M::R;
+  R a = M::div(R(g.A), R(1) + M::exp(-(V - R(g.Va)) * R(g.inv_sa)));
+  R b = M::div(R(g.A), R(1) + M::exp((V - R(g.Vb)) * R(g.inv_sb)));
+  gate_from_rates<M>(a, b, lam, zinf);
+}
+
+constexpr double kRTF = 25.69;
+constexpr double kNaO = 140.0, kKO = 5.4, kCaO = 1.8;
+constexpr double kNaI0 = 20.0, kKI0 = 108.0, kCaI0 = 1e-4;
+
+// ---------------------------------------------------------------------------
+// Models.  Each provides NG (gates), NS (other ionic variables), V_REST,
+// gates(V) -> (Lambda_E, z_inf), eval(V, zE, zS) -> (i_ion, g_S) and the
+// resting values of the non-gate variables.
+// ---------------------------------------------------------------------------
+template <class M>
+struct HHModel {
+  using R = typename M::R;
+  static constexpr int NG = 3, NS = 0;
+  static constexpr double V_REST = -65.0;
+  static __device__ __forceinline__ void gates(R V, const ModelParams &, R *lam, R *zinf) {
+    hh_core_gates<M>(V, R(1), lam, zinf);
+  }
+  static __device__ __forceinline__ R eval(R V, const R *zE, const R *, R *, const ModelParams &) {
+    R m = zE[0], h = zE[1], n = zE[2];
+    R n2 = n * n;
+    return R(120) * (m * m * m * h) * (V - R(50)) + R(36) * (n2 * n2) * (V + R(77)) +
+           R(0.3) * (V + R(54.387));
+  }
+  static __host__ __device__ double slow_rest(int) { return 0.0; }
+};
+
+template <class M>
+struct LinearModel {
+  using R = typename M::R;
+  static constexpr int NG = 1, NS = 0;
+  static constexpr double V_REST = 0.0;
+  static __device__ __forceinline__ void gates(R, const ModelParams &p, R *lam, R *zinf) {
+    lam[0] = R(p.lin_lamE);
+    zinf[0] = R(0);
+  }
+  static __device__ __forceinline__ R eval(R V, const R *, const R *, R *, const ModelParams &p) {
+    return R(p.lin_a) * V;
+  }
+  static __host__ __device__ double slow_rest(int) { return 0.0; }
+};
+
+// CRN-shaped surrogate: V, 15 gates (m, h, n, g3..g14), 5 slow variables
+// (Na_i, K_i, Ca_i, Ca_up, Ca_rel).  Project-written; not the published
+// Courtemanche-Ramirez-Nattel model.
+__device__ __constant__ static const SigmoidGate kCrnGates[12] = {
+    {2.0, -20.0, 1.0 / 10.0, -12.0, 1.0 / 13.0},
+    {0.06, -50.0, 1.0 / -8.0, -58.0, 1.0 / -10.4},
+    {0.4, -10.0, 1.0 / 12.0, -2.0, 1.0 / 15.6},
+    {0.004, -40.0, 1.0 / -10.0, -48.0, 1.0 / -13.0},
+    {1.0, -15.0, 1.0 / 6.0, -7.0, 1.0 / 7.8},
+    {0.02, -30.0, 1.0 / -7.0, -38.0, 1.0 / -9.1},
+    {0.02, -15.0, 1.0 / 8.0, -7.0, 1.0 / 10.4},
+    {1.0, -40.0, 1.0 / -20.0, -48.0, 1.0 / -26.0},
+    {0.006, 10.0, 1.0 / 15.0, 18.0, 1.0 / 19.5},
+    {0.008, 5.0, 1.0 / 13.0, 13.0, 1.0 / 16.9},
+    {0.2, -30.0, 1.0 / -10.0, -38.0, 1.0 / -13.0},
+    {0.04, 0.0, 1.0 / 10.0, 8.0, 1.0 / 13.0},
+};
+
+template <class M>
+struct CrnSurrModel {
+  using R = typename M::R;
+  static constexpr int NG = 15, NS = 5;
+  static constexpr double V_REST = -65.0;
+  static __device__ __forceinline__ void gates(R V, const ModelParams &, R *lam, R *zinf) {
+    hh_core_gates<M>(V, R(15), lam, zinf);
+#pragma unroll
+    for (int g = 0; g < 12; ++g) sigmoid_gate<M>(V, kCrnGates[g], lam[3 + g], zinf[3 + g]);
+  }
+  static __device__ __forceinline__ R eval(R V, const R *g, const R *zS, R *dS, const ModelParams &) {
+    const R Na = zS[0], K = zS[1], Ca = zS[2], Cup = zS[3], Crel = zS[4];
+    const R ENa = R(kRTF) * M::log(M::div(R(kNaO), Na));
+    const R EK = R(kRTF) * M::log(M::div(R(kKO), K));
+    const R ECa = R(0.5 * kRTF) * M::log(M::div(R(kCaO), Ca));
+    const R VK = V - EK;
+    const R n2 = g[2] * g[2];
+    const R iNa = R(12) * (g[0] * g[0] * g[0] * g[1]) * (V - ENa);
+    const R iK = R(3.6) * (n2 * n2) * VK;
+    const R iL = R(0.03) * (V + R(54.387));
+    const R ito = R(0.04) * (g[3] * g[3] * g[3] * g[4]) * VK;
+    const R ikur = R(0.02) * (g[5] * g[5] * g[5] * g[6]) * VK;
+    const R ical = R(0.03) * (g[7] * g[8]) * (V - ECa);
+    const R ikr = R(0.02) * (g[9] * g[10]) * VK;
+    const R iks = R(0.01) * (g[11] * g[12]) * VK;
+    const R ik1 = M::div(R(0.005) * VK, R(1) + M::exp(R(0.07) * (V + R(80))));
+    const R jrel = R(0.5) * (g[13] * g[13] * g[14]) * (Crel - Ca);
+    const R jup = M::div(R(0.005) * Ca, Ca + R(0.001));
+    const R jtr = (Cup - Crel) * R(1.0 / 50.0);
+    constexpr double kJLeak = 0.005 * kCaI0 / (kCaI0 + 0.001);
+    dS[0] = R(-1e-4) * iNa + (R(kNaI0) - Na) * R(1.0 / 500.0);
+    dS[1] = R(-1e-4) * (iK + ito + ikur + ikr + iks + ik1) + (R(kKI0) - K) * R(1.0 / 500.0);
+    dS[2] = R(-2e-6) * ical + R(0.02) * jrel - jup + R(kJLeak) + (R(kCaI0) - Ca) * R(1.0 / 100.0);
+    dS[3] = R(0.05) * jup - R(0.05) * jtr;
+    dS[4] = R(0.05) * jtr - R(0.001) * jrel;
+    return iNa + iK + iL + ito + ikur + ical + ikr + iks + ik1;
+  }
+  static __host__ __device__ double slow_rest(int k) {
+    return k == 0 ? kNaI0 : k == 1 ? kKI0 : k == 2 ? kCaI0 : 1.0;
+  }
+};
+
+// TTP-shaped surrogate: V, 12 gates (m, h, n, g3..g11), 6 slow variables
+// (Na_i, K_i, Ca_i, Ca_sr, Ca_ss, R).  Project-written; not the published
+// ten Tusscher-Panfilov model.
+__device__ __constant__ static const SigmoidGate kTtpGates[9] = {
+    {3.0, -25.0, 1.0 / 9.0, -17.0, 1.0 / 11.7},
+    {0.08, -45.0, 1.0 / -7.0, -53.0, 1.0 / -9.1},
+    {0.03, -20.0, 1.0 / 9.0, -12.0, 1.0 / 11.7},
+    {1.5, -45.0, 1.0 / -18.0, -53.0, 1.0 / -23.4},
+    {0.01, 5.0, 1.0 / 14.0, 13.0, 1.0 / 18.2},
+    {1.5, -12.0, 1.0 / 6.0, -4.0, 1.0 / 7.8},
+    {0.03, -28.0, 1.0 / -7.0, -36.0, 1.0 / -9.1},
+    {0.3, -35.0, 1.0 / -6.0, -43.0, 1.0 / -7.8},
+    {0.5, -10.0, 1.0 / 8.0, -2.0, 1.0 / 10.4},
+};
+
+template <class M>
+struct TtpSurrModel {
+  using R = typename M::R;
+  static constexpr int NG = 12, NS = 6;
+  static constexpr double V_REST = -65.0;
+  static __device__ __forceinline__ void gates(R V, const ModelParams &, R *lam, R *zinf) {
+    hh_core_gates<M>(V, R(110), lam, zinf);
+#pragma unroll
+    for (int g = 0; g < 9; ++g) sigmoid_gate<M>(V, kTtpGates[g], lam[3 + g], zinf[3 + g]);
+  }
+  static __device__ __forceinline__ R eval(R V, const R *g, const R *zS, R *dS, const ModelParams &) {
+    const R Na = zS[0], K = zS[1], Ca = zS[2], Csr = zS[3], Css = zS[4], Rr = zS[5];
+    const R ENa = R(kRTF) * M::log(M::div(R(kNaO), Na));
+    const R EK = R(kRTF) * M::log(M::div(R(kKO), K));
+    const R ECa = R(0.5 * kRTF) * M::log(M::div(R(kCaO), Css));
+    const R VK = V - EK;
+    const R n2 = g[2] * g[2];
+    const R iNa = R(12) * (g[0] * g[0] * g[0] * g[1]) * (V - ENa);
+    const R iK = R(3.6) * (n2 * n2) * VK;
+    const R iL = R(0.03) * (V + R(54.387));
+    const R ito = R(0.03) * (g[3] * g[3] * g[3] * g[4]) * VK;
+    const R ikr = R(0.015) * (g[5] * g[6]) * VK;
+    const R iks = R(0.01) * (g[7] * g[7]) * VK;
+    const R ical = R(0.025) * (g[8] * g[9] * g[10]) * (V - ECa);
+    const R ik1 = M::div(R(0.005) * VK, R(1) + M::exp(R(0.07) * (V + R(80))));
+    const R jrel = R(0.4) * (g[11] * Rr) * (Csr - Css);
+    const R jup = M::div(R(0.004) * Ca, Ca + R(0.00025));
+    const R jxfer = (Css - Ca) * R(0.5);
+    constexpr double kJLeak = 0.004 * kCaI0 / (kCaI0 + 0.00025);
+    dS[0] = R(-1e-4) * iNa + (R(kNaI0) - Na) * R(1.0 / 500.0);
+    dS[1] = R(-1e-4) * (iK + ito + ikr + iks + ik1) + (R(kKI0) - K) * R(1.0 / 500.0);
+    dS[2] = R(0.1) * jxfer - jup + R(kJLeak) + (R(kCaI0) - Ca) * R(1.0 / 100.0);
+    dS[3] = R(0.02) * (jup - R(kJLeak)) - R(0.002) * jrel;
+    dS[4] = R(-2e-6) * ical + R(0.01) * jrel - jxfer;
+    dS[5] = (R(0.98) - Rr) * R(1.0 / 200.0) - R(5) * (Css - R(1e-4)) * Rr;
+    return iNa + iK + iL + ito + ikr + iks + ical + ik1;
+  }
+  static __host__ __device__ double slow_rest(int k) {
+    return k == 0 ? kNaI0 : k == 1 ? kKI0 : k == 2 ? kCaI0 : k == 3 ? 1.0 : k == 4 ? 1e-4 : 0.98;
+  }
+};
+
+// ---------------------------------------------------------------------------
+// Index helpers.
+// ---------------------------------------------------------------------------
+
+// Exact unsigned division by a constant for x < 2^31: q = (x * M) >> shift
+// with shift = 31 + ceil(log2 d) and M = ceil(2^shift / d).
+struct FastDiv {
+  uint32_t d;
+  uint32_t shift;
+  uint64_t mult;
+};
+
+__device__ __forceinline__ uint32_t fdiv(uint32_t x, const FastDiv &f) {
+  return (uint32_t)(((uint64_t)x * f.mult) >> f.shift);
+}
+
+// The hardware dispatches consecutive workgroups round-robin over the 8
+// XCDs, each with its own L2.  Remap so that each XCD walks one contiguous
+// range of the domain: neighbouring planes of a stencil then meet in the same
+// L2.  Bijective for any grid size.
+__device__ __forceinline__ uint32_t xcd_block(uint32_t b, uint32_t nb) {
+  const uint32_t kXcd = 8;
+  uint32_t xcd = b % kXcd, idx = b / kXcd;
+  uint32_t q = nb / kXcd, r = nb % kXcd;
+  return xcd < r ? xcd * (q + 1) + idx : r * (q + 1) + (xcd - r) * q + idx;
+}
+
+// Structured grid geometry passed to kernels.
+struct Grid {
+  uint32_t n0, n1, n2;   // nodes per axis (n2 = 1 in 2-D)
+  uint32_t N;
+  FastDiv div0, div1;    // division by n0 and by n1
+  int dim;
+  // weights of (chi Cm M_L)^{-1} A on neighbour differences, by offset class
+  // (|ox|, |oy|, |oz|): w[0]=100, w[1]=010, w[2]=001, w[3]=110, w[4]=101,
+  // w[5]=011, w[6]=111 (2-D uses w[0], w[1], w[3]).
+  double w[7];
+};
+
+__device__ __forceinline__ uint32_t mirror_lo(uint32_t i) { return i > 0 ? i - 1 : 1; }
+__device__ __forceinline__ uint32_t mirror_hi(uint32_t i, uint32_t n) { return i + 1 < n ? i + 1 : n - 2; }
+
+// (chi Cm M_L)^{-1} (A u) at node (ix, iy, iz) in difference form
+// sum_o w_o (u_{i+o} - u_i).  The zero-flux boundary of the lumped Q1
+// operator equals the interior formula with mirrored neighbours.
+__device__ __forceinline__ double grid_apply_f64(const double *__restrict__ u, const Grid &g,
+                                                 uint32_t ix, uint32_t iy, uint32_t iz) {
+  const uint32_t xm = mirror_lo(ix), xp = mirror_hi(ix, g.n0);
+  const uint32_t ym = mirror_lo(iy), yp = mirror_hi(iy, g.n1);
+  const uint32_t s1 = g.n0;
+  if (g.dim == 2) {
+    const uint32_t r0 = iy * s1, rm = ym * s1, rp = yp * s1;
+    const double uc = u[r0 + ix];
+    const double f = (u[r0 + xm] - uc) + (u[r0 + xp] - uc);
+    const double e = (u[rm + ix] - uc) + (u[rp + ix] - uc);
+    const double c = ((u[rm + xm] - uc) + (u[rm + xp] - uc)) + ((u[rp + xm] - uc) + (u[rp + xp] - uc));
+    return g.w[0] * f + g.w[1] * e + g.w[3] * c;
+  }
+  const uint32_t zm = mirror_lo(iz), zp = mirror_hi(iz, g.n2);
+  const uint32_t s2 = g.n0 * g.n1;
+  const uint32_t pc = iz * s2, pm = zm * s2, pp = zp * s2;
+  const uint32_t rc = iy * s1, rm = ym * s1, rp = yp * s1;
+  const double uc = u[pc + rc + ix];
+  auto d = [&](uint32_t idx) { return u[idx] - uc; };
+  // faces
+  const double fx = d(pc + rc + xm) + d(pc + rc + xp);
+  const double fy = d(pc + rm + ix) + d(pc + rp + ix);
+  const double fz = d(pm + rc + ix) + d(pp + rc + ix);
+  // edges
+  const double exy = (d(pc + rm + xm) + d(pc + rm + xp)) + (d(pc + rp + xm) + d(pc + rp + xp));
+  const double exz = (d(pm + rc + xm) + d(pm + rc + xp)) + (d(pp + rc + xm) + d(pp + rc + xp));
+  const double eyz = (d(pm + rm + ix) + d(pm + rp + ix)) + (d(pp + rm + ix) + d(pp + rp + ix));
+  // corners
+  const double cm = (d(pm + rm + xm) + d(pm + rm + xp)) + (d(pm + rp + xm) + d(pm + rp + xp));
+  const double cp = (d(pp + rm + xm) + d(pp + rm + xp)) + (d(pp + rp + xm) + d(pp + rp + xp));
+  return g.w[0] * fx + g.w[1] * fy + g.w[2] * fz + g.w[3] * exy + g.w[4] * exz + g.w[5] * eyz +
+         g.w[6] * (cm + cp);
+}
+
+// Mixed form: neighbour differences formed in double (V carries the
+// resting offset of about -65 mV), products and accumulation in float.
+__device__ __forceinline__ double grid_apply_mixed(const double *__restrict__ u, const Grid &g,
+                                                   uint32_t ix, uint32_t iy, uint32_t iz) {
+  const uint32_t xm = mirror_lo(ix), xp = mirror_hi(ix, g.n0);
+  const uint32_t ym = mirror_lo(iy), yp = mirror_hi(iy, g.n1);
+  const uint32_t s1 = g.n0;
+  if (g.dim == 2) {
+    const uint32_t r0 = iy * s1, rm = ym * s1, rp = yp * s1;
+    const double uc = u[r0 + ix];
+    auto d = [&](uint32_t idx) { return (float)(u[idx] - uc); };
+    const float f = d(r0 + xm) + d(r0 + xp);
+    const float e = d(rm + ix) + d(rp + ix);
+    const float c = (d(rm + xm) + d(rm + xp)) + (d(rp + xm) + d(rp + xp));
+    return (double)((float)g.w[0] * f + (float)g.w[1] * e + (float)g.w[3] * c);
+  }
+  const uint32_t zm = mirror_lo(iz), zp = mirror_hi(iz, g.n2);
+  const uint32_t s2 = g.n0 * g.n1;
+  const uint32_t pc = iz * s2, pm = zm * s2, pp = zp * s2;
+  const uint32_t rc = iy * s1, rm = ym * s1, rp = yp * s1;
+  const double uc = u[pc + rc + ix];
+  auto d = [&](uint32_t idx) { return (float)(u[idx] - uc); };
+  const float fx = d(pc + rc + xm) + d(pc + rc + xp);
+  const float fy = d(pc + rm + ix) + d(pc + rp + ix);
+  const float fz = d(pm + rc + ix) + d(pp + rc + ix);
+  const float exy = (d(pc + rm + xm) + d(pc + rm + xp)) + (d(pc + rp + xm) + d(pc + rp + xp));
+  const float exz = (d(pm + rc + xm) + d(pm + rc + xp)) + (d(pp + rc + xm) + d(pp + rc + xp));
+  const float eyz = (d(pm + rm + ix) + d(pm + rp + ix)) + (d(pp + rm + ix) + d(pp + rp + ix));
+  const float cm = (d(pm + rm + xm) + d(pm + rm + xp)) + (d(pm + rp + xm) + d(pm + rp + xp));
+  const float cp = (d(pp + rm + xm) + d(pp + rm + xp)) + (d(pp + rp + xm) + d(pp + rp + xp));
+  return (double)((float)g.w[0] * fx + (float)g.w[1] * fy + (float)g.w[2] * fz + (float)g.w[3] * exy +
+                  (float)g.w[4] * exz + (float)g.w[5] * eyz + (float)g.w[6] * (cm + cp));
+}
+
+// splitmix64 (Steele, Lea and Flood, 2014): output number i (0-based) of
+// the generator started at state `seed`, mapped to [-1, 1).
+__host__ __device__ __forceinline__ double splitmix64_unit(uint64_t seed, uint64_t i) {
+  uint64_t z = seed + (i + 1) * 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  z = z ^ (z >> 31);
+  return (double)(z >> 11) * 0x1.0p-53 * 2.0 - 1.0;
+}
+
+}  // namespace emrkc

@@ -1,0 +1,861 @@
+// Host runtime and C ABI of the emRKC library: argument validation, the
+// RKC coefficient tables, stage selection, buffer planning for one emRKC
+// step, HIP-graph replay of steps, and the power-iteration driver.
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <algorithm>
+#include <map>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "../../include/emrkc.h"
+#include "emrkc_internal.h"
+
+using namespace emrkc;
+
+#define EMRKC_EAGER_FLAG 2u  // internal: never capture graphs (testing)
+
+struct GraphKey {
+  int s, m, chunk;
+  uint64_t dt_bits;
+  const void *V, *z;
+  bool operator<(const GraphKey &o) const {
+    return std::tie(s, m, chunk, dt_bits, V, z) < std::tie(o.s, o.m, o.chunk, o.dt_bits, o.V, o.z);
+  }
+};
+
+struct emrkc_ctx {
+  // problem
+  int mesh_kind = 0;
+  int dim = 0;
+  int64_t n[3] = {1, 1, 1};
+  double h[3] = {1, 1, 1};
+  int64_t N = 0;
+  int model = 0, nv = 0, ng = 0, ns = 0;
+  bool mixed = false;
+  uint32_t flags = 0;
+  double chi = 0, Cm = 0, eps = 0.05, safety = 1.05;
+  double stim_amp = 0, t_on = 0, t_off = -1;
+  ModelParams mp{0, 0};
+  double pi_tol = 1e-2, pi_eps = 1e-8;
+  int pi_max_iter = 100;
+  uint64_t pi_seed = 0;
+  // spectral radii (with safety) and warm-start data of the power iteration
+  double rho_F = 0, rho_S = 0;
+  bool have_rho = false;
+  bool warm_F = false, warm_S = false;
+  double raw_F = 0, raw_S = 0, nv_F = 0, nv_S = 0;
+  // device data
+  Mesh mesh{};
+  uint8_t *d_mask = nullptr;
+  uint32_t *d_ell_col = nullptr;
+  double *d_ell_w64 = nullptr;
+  float *d_ell_w32 = nullptr;
+  double *d_V1 = nullptr;
+  double *d_U[2] = {nullptr, nullptr};
+  void *d_SV = nullptr;
+  void *d_z1 = nullptr;
+  Clock *d_clock = nullptr;
+  double *d_partials = nullptr;
+  double *d_result = nullptr;
+  int *d_flag = nullptr;
+  double *d_vF[2] = {nullptr, nullptr};
+  double *d_vS[2] = {nullptr, nullptr};
+  double *d_zV = nullptr;
+  // streams and graphs
+  hipStream_t stream = nullptr;
+  hipStream_t capture = nullptr;
+  std::map<GraphKey, hipGraphExec_t> graphs;
+  emrkc_stats last{};
+  std::string err;
+};
+
+static int fail(emrkc_ctx *c, int code, const char *fmt, ...) __attribute__((format(printf, 3, 4)));
+static int fail(emrkc_ctx *c, int code, const char *fmt, ...) {
+  if (c != nullptr) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    c->err = buf;
+  }
+  return code;
+}
+
+#define HIP_TRY(ctx, call)                                                                     \
+  do {                                                                                         \
+    hipError_t e_ = (call);                                                                    \
+    if (e_ != hipSuccess)                                                                      \
+      return fail((ctx), EMRKC_EHIP, "%s failed: %s", #call, hipGetErrorString(e_));           \
+  } while (0)
+
+// ---------------------------------------------------------------------------
+// Host-only helpers
+// ---------------------------------------------------------------------------
+extern "C" void emrkc_default_params(emrkc_params *p) {
+  if (p == nullptr) return;
+  memset(p, 0, sizeof *p);
+  p->chi = 140.0;
+  p->Cm = 0.01;
+  p->eps = 0.05;
+  p->rho_safety = 1.05;
+  p->precision = EMRKC_FP64;
+  p->stim_t_off = -1.0;
+  p->powiter_tol = 1e-2;
+  p->powiter_eps = 1e-8;
+  p->powiter_max_iter = 100;
+  p->powiter_seed = 0;
+}
+
+static int model_gates(int m) {
+  switch (m) {
+    case EMRKC_MODEL_HH: return 3;
+    case EMRKC_MODEL_LINEAR: return 1;
+    case EMRKC_MODEL_CRN_SURR: return 15;
+    case EMRKC_MODEL_TTP_SURR: return 12;
+    default: return -1;
+  }
+}
+static int model_slow(int m) {
+  switch (m) {
+    case EMRKC_MODEL_HH: return 0;
+    case EMRKC_MODEL_LINEAR: return 0;
+    case EMRKC_MODEL_CRN_SURR: return 5;
+    case EMRKC_MODEL_TTP_SURR: return 6;
+    default: return -1;
+  }
+}
+
+extern "C" int emrkc_model_num_vars(int m) {
+  return model_gates(m) < 0 ? EMRKC_EINVAL : 1 + model_gates(m) + model_slow(m);
+}
+extern "C" int emrkc_model_num_gates(int m) { return model_gates(m) < 0 ? EMRKC_EINVAL : model_gates(m); }
+
+// get_coeffs of the RKC algorithm with Chebyshev values by their
+// three-term recurrences (T_j and T_j').
+static void rkc_coeffs(int s, double eps, std::vector<double> &mu, std::vector<double> &nu,
+                       std::vector<double> &kappa, std::vector<double> &c) {
+  mu.assign(s + 1, 0.0);
+  nu.assign(s + 1, 0.0);
+  kappa.assign(s + 1, 0.0);
+  c.assign(s + 1, 0.0);
+  const double w0 = 1.0 + eps / ((double)s * (double)s);
+  std::vector<double> T(s + 1), dT(s + 1);
+  T[0] = 1.0;
+  dT[0] = 0.0;
+  if (s >= 1) {
+    T[1] = w0;
+    dT[1] = 1.0;
+  }
+  for (int j = 2; j <= s; ++j) {
+    T[j] = 2.0 * w0 * T[j - 1] - T[j - 2];
+    dT[j] = 2.0 * T[j - 1] + 2.0 * w0 * dT[j - 1] - dT[j - 2];
+  }
+  const double w1 = T[s] / dT[s];
+  std::vector<double> b(s + 1);
+  for (int j = 0; j <= s; ++j) b[j] = 1.0 / T[j];
+  mu[1] = w1 / w0;
+  c[1] = mu[1];
+  for (int j = 2; j <= s; ++j) {
+    mu[j] = 2.0 * w1 * b[j] / b[j - 1];
+    nu[j] = 2.0 * w0 * b[j] / b[j - 1];
+    kappa[j] = -b[j] / b[j - 2];
+    c[j] = nu[j] * c[j - 1] + kappa[j] * c[j - 2] + mu[j];
+  }
+}
+
+extern "C" int emrkc_rkc_coeffs(int s, double eps, double *mu, double *nu, double *kappa, double *c) {
+  if (s < 1 || s > 10000 || !(eps > 0) || !mu || !nu || !kappa || !c) return EMRKC_EINVAL;
+  std::vector<double> a, b, k, cc;
+  rkc_coeffs(s, eps, a, b, k, cc);
+  for (int j = 0; j <= s; ++j) {
+    mu[j] = a[j];
+    nu[j] = b[j];
+    kappa[j] = k[j];
+    c[j] = cc[j];
+  }
+  return EMRKC_OK;
+}
+
+// get_stages: s = max(1, ceil(sqrt(dt rho / beta))), l_s = beta s^2.
+static int get_stages(double dt, double rho, double eps, double *ls) {
+  const double beta = 2.0 - 4.0 * eps / 3.0;
+  double s = ceil(sqrt(dt * rho / beta));
+  if (!(s >= 1.0)) s = 1.0;
+  if (s > 1e6) s = 1e6;
+  *ls = beta * s * s;
+  return (int)s;
+}
+
+extern "C" int emrkc_stage_counts(double dt, double rho_F, double rho_S, double eps, int *s, int *m, double *eta) {
+  if (!(dt > 0) || !(rho_F >= 0) || !(rho_S >= 0) || !(eps > 0) || !isfinite(dt) || !isfinite(rho_F) ||
+      !isfinite(rho_S))
+    return EMRKC_EINVAL;
+  double ls, lm;
+  const int ss = get_stages(dt, rho_S, eps, &ls);
+  const double e = 2.0 * dt / ls;
+  const int mm = get_stages(e, rho_F, eps, &lm);
+  if (ss > 10000 || mm > 10000) return EMRKC_EUNSUPPORTED;
+  if (s) *s = ss;
+  if (m) *m = mm;
+  if (eta) *eta = e;
+  return EMRKC_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Context
+// ---------------------------------------------------------------------------
+static FastDiv make_fastdiv(uint32_t d) {
+  FastDiv f;
+  f.d = d;
+  uint32_t b = 0;
+  while ((1ull << b) < d) ++b;
+  f.shift = 31 + b;
+  const unsigned __int128 one = 1;
+  f.mult = (uint64_t)(((one << f.shift) + d - 1) / d);
+  return f;
+}
+
+// Weights of (chi Cm M_L)^{-1} A on neighbour differences of the lumped Q1
+// operator: sum_d sigma_d L_d(o_d) prod_{e != d} Mh(o_e) with
+// L(+-1) = -1/h^2, L(0) = 2/h^2, Mh(+-1) = 1/6, Mh(0) = 2/3, negated and
+// divided by chi Cm.
+static void grid_weights(int dim, const double *h, const double *sig, double chiCm, double *w) {
+  auto L = [&](int d, int o) { return o ? -1.0 / (h[d] * h[d]) : 2.0 / (h[d] * h[d]); };
+  auto Mh = [](int o) { return o ? 1.0 / 6.0 : 2.0 / 3.0; };
+  auto G = [&](int ox, int oy, int oz) {
+    int o[3] = {ox, oy, oz};
+    double g = 0.0;
+    for (int d = 0; d < dim; ++d) {
+      double p = sig[d] * L(d, o[d]);
+      for (int e = 0; e < dim; ++e)
+        if (e != d) p *= Mh(o[e]);
+      g += p;
+    }
+    return -g / chiCm;
+  };
+  for (int k = 0; k < 7; ++k) w[k] = 0.0;
+  w[0] = G(1, 0, 0);
+  w[1] = G(0, 1, 0);
+  w[3] = G(1, 1, 0);
+  if (dim == 3) {
+    w[2] = G(0, 0, 1);
+    w[4] = G(1, 0, 1);
+    w[5] = G(0, 1, 1);
+    w[6] = G(1, 1, 1);
+  }
+}
+
+static void free_ctx(emrkc_ctx *c) {
+  for (auto &kv : c->graphs) (void)hipGraphExecDestroy(kv.second);
+  c->graphs.clear();
+  void *ptrs[] = {c->d_mask, c->d_ell_col, c->d_ell_w64, c->d_ell_w32, c->d_V1, c->d_U[0], c->d_U[1],
+                  c->d_SV,   c->d_z1,      c->d_clock,   c->d_partials, c->d_result, c->d_flag,
+                  c->d_vF[0], c->d_vF[1], c->d_vS[0], c->d_vS[1], c->d_zV};
+  for (void *p : ptrs)
+    if (p) (void)hipFree(p);
+  if (c->capture) (void)hipStreamDestroy(c->capture);
+}
+
+static int dalloc(emrkc_ctx *c, void **p, size_t bytes) {
+  hipError_t e = hipMalloc(p, bytes);
+  if (e != hipSuccess) {
+    *p = nullptr;
+    return fail(c, e == hipErrorOutOfMemory ? EMRKC_ENOMEM : EMRKC_EHIP, "hipMalloc(%zu) failed: %s", bytes,
+                hipGetErrorString(e));
+  }
+  return EMRKC_OK;
+}
+
+static int build_p1(emrkc_ctx *c, const emrkc_mesh *mesh, const emrkc_conductivity *cond);
+
+extern "C" int emrkc_create(const emrkc_mesh *mesh, const emrkc_conductivity *cond, int ionic_model,
+                            const emrkc_params *p, emrkc_ctx **out) {
+  if (out == nullptr) return EMRKC_EINVAL;
+  *out = nullptr;
+  if (mesh == nullptr || p == nullptr) return EMRKC_EINVAL;
+  if (model_gates(ionic_model) < 0) return EMRKC_EINVAL;
+  if (!(p->chi > 0) || !(p->Cm > 0) || !isfinite(p->chi) || !isfinite(p->Cm)) return EMRKC_EINVAL;
+  if (!(p->eps > 0) || !(p->eps < 1) || !(p->rho_safety >= 1.0)) return EMRKC_EINVAL;
+  if (p->precision != EMRKC_FP64 && p->precision != EMRKC_MIXED32) return EMRKC_EINVAL;
+  if (!(p->powiter_tol > 0) || !(p->powiter_eps > 0) || p->powiter_max_iter < 1) return EMRKC_EINVAL;
+  if (!isfinite(p->stim_amp) || !isfinite(p->stim_t_on) || !isfinite(p->stim_t_off)) return EMRKC_EINVAL;
+  if (!isfinite(p->rho_F) || !isfinite(p->rho_S)) return EMRKC_EINVAL;
+  if (ionic_model == EMRKC_MODEL_LINEAR && (!isfinite(p->linear_a) || !isfinite(p->linear_lambda_E) ||
+                                            p->linear_lambda_E > 0))
+    return EMRKC_EINVAL;
+
+  int64_t N = 0;
+  if (mesh->kind == EMRKC_MESH_Q1_GRID) {
+    if (cond == nullptr) return EMRKC_EINVAL;
+    if (mesh->dim != 2 && mesh->dim != 3) return EMRKC_EINVAL;
+    N = 1;
+    for (int d = 0; d < mesh->dim; ++d) {
+      if (mesh->n[d] < 2 || mesh->n[d] > (1 << 30) || !(mesh->h[d] > 0) || !isfinite(mesh->h[d]))
+        return EMRKC_EINVAL;
+      N *= mesh->n[d];
+    }
+    const double sg[3] = {cond->sigma_l, cond->sigma_t, cond->sigma_n};
+    for (int d = 0; d < mesh->dim; ++d)
+      if (!(sg[d] >= 0) || !isfinite(sg[d])) return EMRKC_EINVAL;
+  } else if (mesh->kind == EMRKC_MESH_P1_TET) {
+    if (cond == nullptr || mesh->n_nodes < 4 || mesh->n_elems < 1 || !mesh->coords || !mesh->tets || !mesh->fibres)
+      return EMRKC_EINVAL;
+    if (!(cond->sigma_l >= 0) || !(cond->sigma_t >= 0) || !isfinite(cond->sigma_l) || !isfinite(cond->sigma_t))
+      return EMRKC_EINVAL;
+    N = mesh->n_nodes;
+  } else {
+    return EMRKC_EINVAL;
+  }
+  if (N >= (int64_t)1 << 31) return EMRKC_EUNSUPPORTED;  // 32-bit node indices on the device
+
+  emrkc_ctx *c = new (std::nothrow) emrkc_ctx();
+  if (c == nullptr) return EMRKC_ENOMEM;
+  c->mesh_kind = mesh->kind;
+  c->N = N;
+  c->model = ionic_model;
+  c->ng = model_gates(ionic_model);
+  c->ns = model_slow(ionic_model);
+  c->nv = 1 + c->ng + c->ns;
+  c->mixed = p->precision == EMRKC_MIXED32;
+  c->flags = p->flags;
+  c->chi = p->chi;
+  c->Cm = p->Cm;
+  c->eps = p->eps;
+  c->safety = p->rho_safety;
+  c->stim_amp = p->stim_amp;
+  c->t_on = p->stim_t_on;
+  c->t_off = p->stim_t_off;
+  c->mp.lin_a = p->linear_a;
+  c->mp.lin_lamE = p->linear_lambda_E;
+  c->pi_tol = p->powiter_tol;
+  c->pi_eps = p->powiter_eps;
+  c->pi_max_iter = p->powiter_max_iter;
+  c->pi_seed = p->powiter_seed;
+  if (p->rho_F > 0 && p->rho_S > 0) {
+    c->rho_F = p->rho_F;
+    c->rho_S = p->rho_S;
+    c->have_rho = true;
+  }
+
+  int rc = EMRKC_OK;
+  const uint32_t Nu = (uint32_t)N;
+  if (mesh->kind == EMRKC_MESH_Q1_GRID) {
+    c->dim = mesh->dim;
+    for (int d = 0; d < 3; ++d) {
+      c->n[d] = d < mesh->dim ? mesh->n[d] : 1;
+      c->h[d] = d < mesh->dim ? mesh->h[d] : 1.0;
+    }
+    Mesh &M = c->mesh;
+    M.kind = kGrid;
+    Grid &g = M.grid;
+    g.n0 = (uint32_t)c->n[0];
+    g.n1 = (uint32_t)c->n[1];
+    g.n2 = (uint32_t)c->n[2];
+    g.N = Nu;
+    g.dim = c->dim;
+    g.div0 = make_fastdiv(g.n0);
+    g.div1 = make_fastdiv(g.n1);
+    const double sg[3] = {cond->sigma_l, cond->sigma_t, cond->sigma_n};
+    grid_weights(c->dim, c->h, sg, c->chi * c->Cm, g.w);
+  } else {
+    rc = build_p1(c, mesh, cond);
+    if (rc != EMRKC_OK) goto error;
+  }
+
+  {
+    const size_t vb = sizeof(double) * (size_t)N;
+    const size_t svb = (c->mixed ? sizeof(float) : sizeof(double)) * (size_t)N;
+    if ((rc = dalloc(c, (void **)&c->d_V1, vb)) || (rc = dalloc(c, (void **)&c->d_U[0], vb)) ||
+        (rc = dalloc(c, (void **)&c->d_U[1], vb)) || (rc = dalloc(c, &c->d_SV, svb)) ||
+        (rc = dalloc(c, (void **)&c->d_clock, sizeof(Clock))) ||
+        (rc = dalloc(c, (void **)&c->d_result, 2 * sizeof(double))) ||
+        (rc = dalloc(c, (void **)&c->d_flag, sizeof(int))))
+      goto error;
+    const size_t nparts = std::max<size_t>(reduce_blocks(Nu), 65536);
+    if ((rc = dalloc(c, (void **)&c->d_partials, nparts * sizeof(double)))) goto error;
+    if (p->stim_mask != nullptr) {
+      if ((rc = dalloc(c, (void **)&c->d_mask, (size_t)N))) goto error;
+      hipError_t e = hipMemcpy(c->d_mask, p->stim_mask, (size_t)N, hipMemcpyHostToDevice);
+      if (e != hipSuccess) {
+        rc = fail(c, EMRKC_EHIP, "mask upload failed: %s", hipGetErrorString(e));
+        goto error;
+      }
+    }
+    hipError_t e = hipStreamCreateWithFlags(&c->capture, hipStreamNonBlocking);
+    if (e != hipSuccess) {
+      rc = fail(c, EMRKC_EHIP, "hipStreamCreate failed: %s", hipGetErrorString(e));
+      goto error;
+    }
+    e = hipMemset(c->d_clock, 0, sizeof(Clock));
+    if (e == hipSuccess) e = hipDeviceSynchronize();
+    if (e != hipSuccess) {
+      rc = fail(c, EMRKC_EHIP, "initialisation failed: %s", hipGetErrorString(e));
+      goto error;
+    }
+  }
+  *out = c;
+  return EMRKC_OK;
+error:
+  free_ctx(c);
+  delete c;
+  return rc;
+}
+
+extern "C" void emrkc_destroy(emrkc_ctx *c) {
+  if (c == nullptr) return;
+  if (c->stream) (void)hipStreamSynchronize(c->stream);
+  (void)hipDeviceSynchronize();
+  free_ctx(c);
+  delete c;
+}
+
+extern "C" int emrkc_set_stream(emrkc_ctx *c, void *s) {
+  if (c == nullptr) return EMRKC_EINVAL;
+  c->stream = (hipStream_t)s;
+  return EMRKC_OK;
+}
+
+extern "C" int64_t emrkc_num_nodes(const emrkc_ctx *c) { return c ? c->N : -1; }
+extern "C" int emrkc_num_vars(const emrkc_ctx *c) { return c ? c->nv : -1; }
+extern "C" const char *emrkc_last_error(const emrkc_ctx *c) { return c ? c->err.c_str() : "null context"; }
+
+static bool state_ok(const emrkc_ctx *c, const emrkc_state *s) {
+  return s != nullptr && s->V != nullptr && s->z != nullptr && s->V != s->z;
+}
+
+static StimArgs stim_args(const emrkc_ctx *c) {
+  StimArgs s;
+  s.mask = c->d_mask;
+  s.amp = c->stim_amp;
+  s.t_on = c->t_on;
+  s.t_off = c->t_off;
+  return s;
+}
+
+static double state_time(double t0, int64_t step, double dt) {
+#pragma clang fp contract(off)
+  return t0 + (double)step * dt;
+}
+
+extern "C" int emrkc_init_state(emrkc_ctx *c, emrkc_state *s) {
+  if (c == nullptr) return EMRKC_EINVAL;
+  if (!state_ok(c, s)) return fail(c, EMRKC_EINVAL, "state buffers missing");
+  HIP_TRY(c, launch_init_state(c->model, c->mixed, (uint32_t)c->N, (double *)s->V, s->z, c->mp, c->stream));
+  s->t = s->t0;
+  return EMRKC_OK;
+}
+
+extern "C" int emrkc_set_rho(emrkc_ctx *c, double rho_F, double rho_S) {
+  if (c == nullptr) return EMRKC_EINVAL;
+  if (!(rho_F >= 0) || !(rho_S >= 0) || !isfinite(rho_F) || !isfinite(rho_S))
+    return fail(c, EMRKC_EINVAL, "invalid spectral radii");
+  c->rho_F = rho_F;
+  c->rho_S = rho_S;
+  c->have_rho = true;
+  return EMRKC_OK;
+}
+
+extern "C" int emrkc_get_rho(const emrkc_ctx *c, double *rho_F, double *rho_S) {
+  if (c == nullptr || !c->have_rho) return EMRKC_EINVAL;
+  if (rho_F) *rho_F = c->rho_F;
+  if (rho_S) *rho_S = c->rho_S;
+  return EMRKC_OK;
+}
+
+extern "C" int emrkc_stages(const emrkc_ctx *c, double dt, int *s, int *m, double *eta) {
+  if (c == nullptr || !c->have_rho) return EMRKC_EINVAL;
+  return emrkc_stage_counts(dt, c->rho_F, c->rho_S, c->eps, s, m, eta);
+}
+
+extern "C" int emrkc_last_stats(const emrkc_ctx *c, emrkc_stats *out) {
+  if (c == nullptr || out == nullptr) return EMRKC_EINVAL;
+  *out = c->last;
+  return EMRKC_OK;
+}
+
+// ---------------------------------------------------------------------------
+// One emRKC step as a sequence of launches (see the buffer plan below)
+// ---------------------------------------------------------------------------
+struct StepPlan {
+  int s, m;
+  double eta;
+  std::vector<double> mu, nu, ka, cc;      // outer, index j
+  std::vector<double> mui, nui, kai, cci;  // inner, index k
+};
+
+// V_j lives in X[j % 2] for j < s (X[0] = the caller's V, X[1] a library
+// buffer): V_j may overwrite V_{j-2} because that value is only read at the
+// same node.  The last stage writes X[0] unless m == 1 and V_{s-1} is in
+// X[0]: then the head kernel that reads V_{s-1} with neighbours must not
+// overwrite it, and the step ends with a copy.  z_j follows the same rule
+// with Z[0] = the caller's z and always ends in Z[0] (z is pointwise).
+// Inner values u_k (k >= 1) rotate through U[(k-1) % 2]; u_0 = V_{j-1}.
+struct KernelTimer {
+  std::vector<hipEvent_t> ev;  // pairs (start, stop)
+  std::vector<int> cls;        // 0 = head, 1 = inner, 2 = other
+  size_t used = 0;
+  int record(emrkc_ctx *c, hipStream_t s, int k, bool start);
+};
+
+static int enqueue_step(emrkc_ctx *c, const emrkc_state *st, const StepPlan &P, double dt, hipStream_t strm,
+                        KernelTimer *tm = nullptr) {
+  const int s = P.s, m = P.m;
+  double *X[2] = {(double *)st->V, c->d_V1};
+  void *Z[2] = {st->z, c->d_z1};
+  auto vidx = [&](int j) { return j == 0 ? 0 : (j < s ? j % 2 : 0); };
+  auto zidx = [&](int j) { return j == 0 ? 0 : (j < s ? j % 2 : 0); };
+  const bool final_copy = (m == 1) && (vidx(s - 1) == 0);
+  for (int j = 1; j <= s; ++j) {
+    const bool lastj = j == s;
+    double *Vin = X[vidx(j - 1)];
+    double *Vin2 = j >= 2 ? X[vidx(j - 2)] : nullptr;
+    double *Vdst = (lastj && final_copy) ? X[1] : X[vidx(j)];
+    HeadArgs h{};
+    h.Vin = Vin;
+    h.Vin2 = Vin2;
+    h.zin = Z[zidx(j - 1)];
+    h.zin2 = j >= 2 ? Z[zidx(j - 2)] : nullptr;
+    h.zout = Z[zidx(j)];
+    h.SV = c->d_SV;
+    h.uout = m >= 2 ? c->d_U[0] : Vdst;
+    h.clock = c->d_clock;
+    h.stim = stim_args(c);
+    h.mp = c->mp;
+    h.dt = dt;
+    h.eta = P.eta;
+    h.inv_eta = 1.0 / P.eta;
+    h.Cm = c->Cm;
+    h.c_prev = P.cc[j - 1];
+    h.mu_dt = P.mu[j] * dt;
+    h.nu = P.nu[j];
+    h.kappa = P.ka[j];
+    h.mu1_eta = P.mui[1] * P.eta;
+    h.cm_eta = P.cci[m] * P.eta;
+    h.j1 = j == 1;
+    h.m_is_one = m == 1;
+    if (tm && tm->record(c, strm, 0, true)) return EMRKC_EHIP;
+    HIP_TRY(c, launch_head(c->model, c->mixed, c->mesh, h, strm));
+    if (tm && tm->record(c, strm, 0, false)) return EMRKC_EHIP;
+    for (int k = 2; k <= m; ++k) {
+      InnerArgs a{};
+      a.uprev = c->d_U[(k - 2) % 2];
+      a.uprev2 = k == 2 ? Vin : c->d_U[(k - 3) % 2];
+      a.SV = c->d_SV;
+      a.last = k == m;
+      a.out = a.last ? Vdst : c->d_U[(k - 1) % 2];
+      a.nu = P.nui[k];
+      a.kappa = P.kai[k];
+      a.mu_eta = P.mui[k] * P.eta;
+      a.Vin = Vin;
+      a.Vin2 = Vin2;
+      a.inv_eta = 1.0 / P.eta;
+      a.mu_dt = P.mu[j] * dt;
+      a.nu_o = P.nu[j];
+      a.kappa_o = P.ka[j];
+      a.j1 = j == 1;
+      a.tick = (lastj && k == m) ? c->d_clock : nullptr;
+      if (tm && tm->record(c, strm, 1, true)) return EMRKC_EHIP;
+      HIP_TRY(c, launch_inner(c->mixed, c->mesh, a, strm));
+      if (tm && tm->record(c, strm, 1, false)) return EMRKC_EHIP;
+    }
+  }
+  if (m == 1) {
+    // copy the final V when it had to go to X[1]; advance the step counter
+    HIP_TRY(c, launch_copy_tick(final_copy ? X[1] : nullptr, X[0], (uint32_t)c->N, c->d_clock, strm));
+  }
+  return EMRKC_OK;
+}
+
+static int ensure_z1(emrkc_ctx *c) {
+  if (c->d_z1 != nullptr) return EMRKC_OK;
+  const size_t zb = (c->mixed ? sizeof(float) : sizeof(double)) * (size_t)c->N * (size_t)(c->nv - 1);
+  return dalloc(c, &c->d_z1, zb);
+}
+
+extern "C" int emrkc_step(emrkc_ctx *c, emrkc_state *st, double dt, int64_t nsteps) {
+  if (c == nullptr) return EMRKC_EINVAL;
+  if (!state_ok(c, st)) return fail(c, EMRKC_EINVAL, "state buffers missing");
+  if (!(dt > 0) || !isfinite(dt) || nsteps < 0) return fail(c, EMRKC_EINVAL, "invalid dt or nsteps");
+  if (!c->have_rho) return fail(c, EMRKC_EINVAL, "spectral radii not set: call emrkc_estimate_rho or emrkc_set_rho");
+  if (nsteps == 0) return EMRKC_OK;
+  StepPlan P;
+  int rc = emrkc_stage_counts(dt, c->rho_F, c->rho_S, c->eps, &P.s, &P.m, &P.eta);
+  if (rc != EMRKC_OK) return fail(c, rc, "stage selection failed (dt=%g rho_F=%g rho_S=%g)", dt, c->rho_F, c->rho_S);
+  rkc_coeffs(P.s, c->eps, P.mu, P.nu, P.ka, P.cc);
+  rkc_coeffs(P.m, c->eps, P.mui, P.nui, P.kai, P.cci);
+  if (P.s >= 2 && (rc = ensure_z1(c)) != EMRKC_OK) return rc;
+
+  HIP_TRY(c, launch_clock_set(c->d_clock, st->step, st->t0, c->stream));
+  const bool eager = (c->flags & EMRKC_EAGER_FLAG) != 0 || getenv("EMRKC_EAGER") != nullptr;
+  int64_t done = 0;
+  bool used_graph = false;
+  if (!eager && nsteps >= 2) {
+    // replay chunks of steps from a captured graph; the per-step time comes
+    // from the device clock, so every chunk is the same graph
+    const int chunk = (int)std::min<int64_t>(nsteps, 32);
+    for (int pass = 0; pass < 2 && done < nsteps; ++pass) {
+      const int len = pass == 0 ? chunk : (int)(nsteps - done);
+      const int64_t reps = pass == 0 ? (nsteps / chunk) : 1;
+      if (len <= 0) continue;
+      uint64_t dtb;
+      memcpy(&dtb, &dt, sizeof dtb);
+      GraphKey key{P.s, P.m, len, dtb, st->V, st->z};
+      hipGraphExec_t exec = nullptr;
+      auto it = c->graphs.find(key);
+      if (it != c->graphs.end()) {
+        exec = it->second;
+      } else {
+        hipGraph_t graph = nullptr;
+        HIP_TRY(c, hipStreamBeginCapture(c->capture, hipStreamCaptureModeThreadLocal));
+        int erc = EMRKC_OK;
+        for (int k = 0; k < len && erc == EMRKC_OK; ++k) erc = enqueue_step(c, st, P, dt, c->capture);
+        hipError_t ee = hipStreamEndCapture(c->capture, &graph);
+        if (erc != EMRKC_OK) {
+          if (graph) (void)hipGraphDestroy(graph);
+          return erc;
+        }
+        if (ee != hipSuccess) return fail(c, EMRKC_EHIP, "graph capture failed: %s", hipGetErrorString(ee));
+        ee = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        if (ee != hipSuccess) return fail(c, EMRKC_EHIP, "graph instantiation failed: %s", hipGetErrorString(ee));
+        if (c->graphs.size() >= 64) {
+          for (auto &kv : c->graphs) (void)hipGraphExecDestroy(kv.second);
+          c->graphs.clear();
+        }
+        c->graphs[key] = exec;
+      }
+      for (int64_t r = 0; r < reps; ++r) HIP_TRY(c, hipGraphLaunch(exec, c->stream));
+      done += (int64_t)len * reps;
+      used_graph = true;
+    }
+  }
+  for (; done < nsteps; ++done) {
+    rc = enqueue_step(c, st, P, dt, c->stream);
+    if (rc != EMRKC_OK) return rc;
+  }
+  st->step += nsteps;
+  st->t = state_time(st->t0, st->step, dt);
+  c->last.s = P.s;
+  c->last.m = P.m;
+  c->last.eta = P.eta;
+  c->last.kernels_per_step = (int64_t)P.s * P.m + (P.m == 1 ? 1 : 0);
+  c->last.used_graph = used_graph ? 1 : 0;
+  if (c->flags & EMRKC_CHECK_FINITE) {
+    HIP_TRY(c, hipMemsetAsync(c->d_flag, 0, sizeof(int), c->stream));
+    HIP_TRY(c, launch_finite_check((uint32_t)c->N, (const double *)st->V, c->d_flag, c->stream));
+    int flag = 0;
+    HIP_TRY(c, hipMemcpyAsync(&flag, c->d_flag, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    if (flag) return fail(c, EMRKC_ENONFINITE, "V holds a non-finite value after step %lld", (long long)st->step);
+  }
+  return EMRKC_OK;
+}
+
+int KernelTimer::record(emrkc_ctx *c, hipStream_t s, int k, bool start) {
+  if (start) {
+    while (ev.size() < used + 2) {
+      hipEvent_t e;
+      if (hipEventCreate(&e) != hipSuccess) return fail(c, EMRKC_EHIP, "hipEventCreate failed");
+      ev.push_back(e);
+    }
+    cls.push_back(k);
+  }
+  if (hipEventRecord(ev[used], s) != hipSuccess) return fail(c, EMRKC_EHIP, "hipEventRecord failed");
+  ++used;
+  return EMRKC_OK;
+}
+
+extern "C" int emrkc_profile_step(emrkc_ctx *c, emrkc_state *st, double dt, int64_t nsteps, double *head_ms,
+                                  double *inner_ms, int64_t *n_head, int64_t *n_inner) {
+  if (c == nullptr) return EMRKC_EINVAL;
+  if (!state_ok(c, st)) return fail(c, EMRKC_EINVAL, "state buffers missing");
+  if (!(dt > 0) || !isfinite(dt) || nsteps < 1 || nsteps > 100000) return fail(c, EMRKC_EINVAL, "invalid dt or nsteps");
+  if (!c->have_rho) return fail(c, EMRKC_EINVAL, "spectral radii not set");
+  StepPlan P;
+  int rc = emrkc_stage_counts(dt, c->rho_F, c->rho_S, c->eps, &P.s, &P.m, &P.eta);
+  if (rc != EMRKC_OK) return fail(c, rc, "stage selection failed");
+  rkc_coeffs(P.s, c->eps, P.mu, P.nu, P.ka, P.cc);
+  rkc_coeffs(P.m, c->eps, P.mui, P.nui, P.kai, P.cci);
+  if (P.s >= 2 && (rc = ensure_z1(c)) != EMRKC_OK) return rc;
+  HIP_TRY(c, launch_clock_set(c->d_clock, st->step, st->t0, c->stream));
+  KernelTimer tm;
+  for (int64_t n = 0; n < nsteps && rc == EMRKC_OK; ++n) rc = enqueue_step(c, st, P, dt, c->stream, &tm);
+  hipError_t e = hipStreamSynchronize(c->stream);
+  double sum[2] = {0, 0};
+  int64_t cnt[2] = {0, 0};
+  if (rc == EMRKC_OK && e == hipSuccess) {
+    for (size_t k = 0; k + 1 < tm.used; k += 2) {
+      float ms = 0;
+      if (hipEventElapsedTime(&ms, tm.ev[k], tm.ev[k + 1]) != hipSuccess) {
+        rc = fail(c, EMRKC_EHIP, "hipEventElapsedTime failed");
+        break;
+      }
+      const int cl = tm.cls[k / 2];
+      sum[cl] += ms;
+      cnt[cl] += 1;
+    }
+  }
+  for (hipEvent_t ev : tm.ev) (void)hipEventDestroy(ev);
+  if (e != hipSuccess) return fail(c, EMRKC_EHIP, "profiled steps failed: %s", hipGetErrorString(e));
+  if (rc != EMRKC_OK) return rc;
+  st->step += nsteps;
+  st->t = state_time(st->t0, st->step, dt);
+  if (head_ms) *head_ms = cnt[0] ? sum[0] / cnt[0] : 0.0;
+  if (inner_ms) *inner_ms = cnt[1] ? sum[1] / cnt[1] : 0.0;
+  if (n_head) *n_head = cnt[0];
+  if (n_inner) *n_inner = cnt[1];
+  return EMRKC_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Nonlinear power iteration (appendix, Compute_Rho)
+// ---------------------------------------------------------------------------
+static int fetch(emrkc_ctx *c, double *out) {
+  HIP_TRY(c, hipMemcpyAsync(out, c->d_result, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  return EMRKC_OK;
+}
+
+extern "C" int emrkc_estimate_rho(emrkc_ctx *c, const emrkc_state *st, double *rho_F, double *rho_S, int *iters_F,
+                                  int *iters_S) {
+  if (c == nullptr) return EMRKC_EINVAL;
+  if (!state_ok(c, st)) return fail(c, EMRKC_EINVAL, "state buffers missing");
+  const uint32_t N = (uint32_t)c->N;
+  const size_t vb = sizeof(double) * (size_t)N;
+  int rc;
+  if (!c->d_vF[0]) {
+    if ((rc = dalloc(c, (void **)&c->d_vF[0], vb)) || (rc = dalloc(c, (void **)&c->d_vF[1], vb)) ||
+        (rc = dalloc(c, (void **)&c->d_zV, vb)) ||
+        (rc = dalloc(c, (void **)&c->d_vS[0], vb * (1 + c->ns))) ||
+        (rc = dalloc(c, (void **)&c->d_vS[1], vb * (1 + c->ns))))
+      return rc;
+  }
+  const double *yV = (const double *)st->V;
+  double ny2 = 0;
+  HIP_TRY(c, launch_norm2_state(c->mixed, N, c->nv - 1, yV, st->z, c->d_partials, c->d_result, c->stream));
+  if ((rc = fetch(c, &ny2))) return rc;
+  const double ny = sqrt(ny2);
+  const double delta = ny > 0 ? ny * c->pi_eps : c->pi_eps;
+  const double t = st->t;
+  bool noconv = false;
+
+  // f_F: only the V component of v enters f_F(y + q v) - f_F(y)
+  {
+    double nv;
+    if (c->warm_F) {
+      nv = c->nv_F;
+    } else {
+      double s2;
+      HIP_TRY(c, launch_norm2_random(c->pi_seed, (uint64_t)N * c->nv, c->d_partials, c->d_result, c->stream));
+      if ((rc = fetch(c, &s2))) return rc;
+      nv = sqrt(s2);
+    }
+    double q = delta / nv, rho = c->warm_F ? c->raw_F : 0.0, rho_old = 0.0;
+    int it = 0;
+    while (fabs(rho - rho_old) >= c->pi_tol * rho) {
+      if (it >= c->pi_max_iter) {
+        noconv = true;
+        break;
+      }
+      rho_old = rho;
+      HIP_TRY(c, launch_powF_shift(N, yV, c->warm_F ? c->d_vF[0] : nullptr, c->pi_seed, q, c->d_zV, c->stream));
+      HIP_TRY(c, launch_powF_diff(c->mixed, c->mesh, c->d_zV, yV, c->d_vF[1], c->d_partials, c->d_result, c->stream));
+      double s2;
+      if ((rc = fetch(c, &s2))) return rc;
+      std::swap(c->d_vF[0], c->d_vF[1]);
+      c->warm_F = true;
+      nv = sqrt(s2);
+      ++it;
+      if (nv == 0.0) {
+        rho = 0.0;
+        break;
+      }
+      q = delta / nv;
+      rho = nv / delta;
+    }
+    c->raw_F = rho;
+    c->nv_F = nv;
+    if (iters_F) *iters_F = it;
+  }
+  // f_S on (V, z_E, z_S); the gate components of f_S vanish
+  {
+    double nv;
+    if (c->warm_S) {
+      nv = c->nv_S;
+    } else {
+      double s2;
+      HIP_TRY(c, launch_norm2_random(c->pi_seed, (uint64_t)N * c->nv, c->d_partials, c->d_result, c->stream));
+      if ((rc = fetch(c, &s2))) return rc;
+      nv = sqrt(s2);
+    }
+    double q = delta / nv, rho = c->warm_S ? c->raw_S : 0.0, rho_old = 0.0;
+    int it = 0;
+    while (fabs(rho - rho_old) >= c->pi_tol * rho) {
+      if (it >= c->pi_max_iter) {
+        noconv = true;
+        break;
+      }
+      rho_old = rho;
+      HIP_TRY(c, launch_powS_iter(c->model, c->mixed, N, yV, st->z, c->warm_S ? c->d_vS[0] : nullptr, c->pi_seed, q,
+                                  t, stim_args(c), c->Cm, c->mp, c->d_vS[1], c->d_partials, c->d_result, c->stream));
+      double s2;
+      if ((rc = fetch(c, &s2))) return rc;
+      std::swap(c->d_vS[0], c->d_vS[1]);
+      c->warm_S = true;
+      nv = sqrt(s2);
+      ++it;
+      if (nv == 0.0) {
+        rho = 0.0;
+        break;
+      }
+      q = delta / nv;
+      rho = nv / delta;
+    }
+    c->raw_S = rho;
+    c->nv_S = nv;
+    if (iters_S) *iters_S = it;
+  }
+  c->rho_F = c->safety * c->raw_F;
+  c->rho_S = c->safety * c->raw_S;
+  c->have_rho = true;
+  if (rho_F) *rho_F = c->rho_F;
+  if (rho_S) *rho_S = c->rho_S;
+  if (noconv) return fail(c, EMRKC_ENOCONV, "power iteration reached %d iterations", c->pi_max_iter);
+  return EMRKC_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Single-term evaluations
+// ---------------------------------------------------------------------------
+extern "C" int emrkc_apply_diffusion(emrkc_ctx *c, const double *V, double *out) {
+  if (c == nullptr) return EMRKC_EINVAL;
+  if (V == nullptr || out == nullptr || (const void *)V == (const void *)out)
+    return fail(c, EMRKC_EINVAL, "invalid buffers");
+  HIP_TRY(c, launch_apply_diffusion(c->mixed, c->mesh, V, out, c->stream));
+  return EMRKC_OK;
+}
+
+extern "C" int emrkc_eval_rhs_slow(emrkc_ctx *c, const emrkc_state *st, double t, double *out) {
+  if (c == nullptr) return EMRKC_EINVAL;
+  if (!state_ok(c, st) || out == nullptr) return fail(c, EMRKC_EINVAL, "invalid buffers");
+  HIP_TRY(c, launch_eval_rhs_slow(c->model, c->mixed, (uint32_t)c->N, (const double *)st->V, st->z, t, stim_args(c),
+                                  c->Cm, c->mp, out, c->stream));
+  return EMRKC_OK;
+}
+
+// ---------------------------------------------------------------------------
+// P1 tetrahedral meshes: assembled on the host at creation into an ELL
+// operator on neighbour differences (weights of (chi Cm M_L)^{-1} A).
+// ---------------------------------------------------------------------------
+static int build_p1(emrkc_ctx *c, const emrkc_mesh *mesh, const emrkc_conductivity *cond) {
+  (void)mesh;
+  (void)cond;
+  return fail(c, EMRKC_EUNSUPPORTED, "P1 meshes are not built yet");
+}

@@ -1,0 +1,111 @@
+// Internal interface between the host runtime (emrkc_host.hip) and the
+// kernels (emrkc_kernels.hip).  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "emrkc_device.h"
+
+namespace emrkc {
+
+// Device-resident time of the state: t_n = t0 + step * dt.  Kept on the
+// device so that a captured sequence of steps can be replayed unchanged.
+struct Clock {
+  int64_t step;
+  double t0;
+};
+
+struct StimArgs {
+  const uint8_t *mask;  // nullptr: no stimulus
+  double amp, t_on, t_off;
+};
+
+// Operator of the unstructured (P1) mesh: ELL rows of width `width`, column
+// indices and weights of (chi Cm M_L)^{-1} A on neighbour differences; padded
+// entries repeat the row's own index with weight 0.
+struct Ell {
+  uint32_t N;
+  uint32_t width;
+  const uint32_t *col;   // [width][N]
+  const double *w64;     // [width][N]
+  const float *w32;      // [width][N] (mixed form)
+};
+
+enum MeshKind : int { kGrid = 1, kEll = 2 };
+
+struct Mesh {
+  int kind;
+  Grid grid;
+  Ell ell;
+};
+
+// Fused outer-stage head: exponential Euler on the gates, ionic evaluation
+// at y_E, outer recurrence of z and the first inner stage of V.
+struct HeadArgs {
+  const double *Vin;    // V_{j-1}
+  const double *Vin2;   // V_{j-2} (j >= 2)
+  const void *zin;      // z_{j-1}
+  const void *zin2;     // z_{j-2} (j >= 2)
+  void *zout;           // z_j
+  void *SV;             // S_V = Cm^{-1}(I_stim - I_ion) at y_E (m >= 2)
+  double *uout;         // u_1 (m >= 2) or V_j (m == 1)
+  const Clock *clock;
+  StimArgs stim;
+  ModelParams mp;
+  double dt, eta, inv_eta, Cm;
+  double c_prev;        // c_{j-1}: the stage is evaluated at t_n + c_{j-1} dt
+  double mu_dt, nu, kappa;   // outer coefficients of stage j (times dt for mu)
+  double mu1_eta;       // mu'_1 * eta of the inner iteration
+  double cm_eta;        // c'_m * eta: inner end point of the frozen slow forcing
+  int j1;               // stage j == 1
+  int m_is_one;
+};
+
+// Inner stage k >= 2 of the averaged-force iteration; at k == m it also
+// applies the outer recurrence of V.
+struct InnerArgs {
+  const double *uprev;   // u_{k-1} (read with neighbours)
+  const double *uprev2;  // u_{k-2}
+  const void *SV;
+  double *out;           // u_k, or V_j when last
+  double nu, kappa, mu_eta;
+  int last;
+  const double *Vin;     // V_{j-1}
+  const double *Vin2;    // V_{j-2}
+  double inv_eta, mu_dt, nu_o, kappa_o;
+  int j1;
+  Clock *tick;           // when non-null, block 0 advances the step counter
+};
+
+// ---- launchers (emrkc_kernels.hip) ----------------------------------------
+hipError_t launch_init_state(int model, bool mixed, uint32_t N, double *V, void *z, ModelParams mp,
+                             hipStream_t st);
+hipError_t launch_head(int model, bool mixed, const Mesh &mesh, const HeadArgs &a, hipStream_t st);
+hipError_t launch_inner(bool mixed, const Mesh &mesh, const InnerArgs &a, hipStream_t st);
+hipError_t launch_clock_set(Clock *c, int64_t step, double t0, hipStream_t st);
+hipError_t launch_copy_tick(const double *src, double *dst, uint32_t N, Clock *tick, hipStream_t st);
+hipError_t launch_apply_diffusion(bool mixed, const Mesh &mesh, const double *V, double *out,
+                                  hipStream_t st);
+hipError_t launch_eval_rhs_slow(int model, bool mixed, uint32_t N, const double *V, const void *z,
+                                double t, StimArgs stim, double Cm, ModelParams mp, double *out,
+                                hipStream_t st);
+
+// Power iteration pieces.  Partial sums go to `partials` (one per block),
+// the final sum to `result` (device double).
+uint32_t reduce_blocks(uint32_t n);
+hipError_t launch_norm2_state(bool mixed, uint32_t N, int nz, const double *V, const void *z,
+                              double *partials, double *result, hipStream_t st);
+hipError_t launch_norm2_random(uint64_t seed, uint64_t count, double *partials, double *result,
+                               hipStream_t st);
+hipError_t launch_powF_shift(uint32_t N, const double *yV, const double *vin, uint64_t seed, double q,
+                             double *zV, hipStream_t st);
+hipError_t launch_powF_diff(bool mixed, const Mesh &mesh, const double *zV, const double *yV, double *vout,
+                            double *partials, double *result, hipStream_t st);
+hipError_t launch_powS_iter(int model, bool mixed, uint32_t N, const double *V, const void *z,
+                            const double *vin, uint64_t seed, double q, double t, StimArgs stim,
+                            double Cm, ModelParams mp, double *vout, double *partials, double *result,
+                            hipStream_t st);
+hipError_t launch_finite_check(uint32_t N, const double *V, int *flag, hipStream_t st);
+
+}  // namespace emrkc

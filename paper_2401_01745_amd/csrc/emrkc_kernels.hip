@@ -1,0 +1,525 @@
+// Kernels of the emRKC library (gfx950).  One thread per mesh node, state
+// in structure-of-arrays layout; no floating-point atomics, reductions are
+// two-pass with a fixed order (bit-reproducible).
+#include <type_traits>
+
+#include "emrkc_internal.h"
+
+namespace emrkc {
+
+constexpr int kBlock = 256;
+
+template <bool MIXED>
+using MathOf = typename std::conditional<MIXED, MathF32, MathF64>::type;
+
+// Stage time t_n + c_{j-1} dt with t_n = t0 + n dt, without contraction so
+// that host and device obtain the same double.
+__device__ __forceinline__ double stage_time(const Clock *c, double dt, double c_prev) {
+#pragma clang fp contract(off)
+  const double tn = c->t0 + (double)c->step * dt;
+  return tn + c_prev * dt;
+}
+
+__device__ __forceinline__ double stimulus(const StimArgs &s, uint32_t i, double t) {
+  return (s.mask != nullptr && s.mask[i] != 0 && s.t_on <= t && t <= s.t_off) ? s.amp : 0.0;
+}
+
+__device__ __forceinline__ uint32_t node_index() {
+  return xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+}
+
+__device__ __forceinline__ void grid_coords(const Grid &g, uint32_t i, uint32_t &ix, uint32_t &iy,
+                                            uint32_t &iz) {
+  const uint32_t q0 = fdiv(i, g.div0);
+  ix = i - q0 * g.n0;
+  iz = fdiv(q0, g.div1);
+  iy = q0 - iz * g.n1;
+}
+
+template <bool MIXED>
+__device__ __forceinline__ double apply_op(const Mesh &mesh, const double *__restrict__ u, uint32_t i) {
+  if (mesh.kind == kGrid) {
+    uint32_t ix, iy, iz;
+    grid_coords(mesh.grid, i, ix, iy, iz);
+    return MIXED ? grid_apply_mixed(u, mesh.grid, ix, iy, iz) : grid_apply_f64(u, mesh.grid, ix, iy, iz);
+  }
+  const Ell &e = mesh.ell;
+  const double uc = u[i];
+  if (MIXED) {
+    float acc = 0.0f;
+    for (uint32_t k = 0; k < e.width; ++k) {
+      const uint32_t c = e.col[(size_t)k * e.N + i];
+      acc += e.w32[(size_t)k * e.N + i] * (float)(u[c] - uc);
+    }
+    return (double)acc;
+  }
+  double acc = 0.0;
+  for (uint32_t k = 0; k < e.width; ++k) {
+    const uint32_t c = e.col[(size_t)k * e.N + i];
+    acc += e.w64[(size_t)k * e.N + i] * (u[c] - uc);
+  }
+  return acc;
+}
+
+// ---------------------------------------------------------------------------
+// Resting state
+// ---------------------------------------------------------------------------
+template <template <class> class Model, bool MIXED>
+__global__ __launch_bounds__(kBlock) void k_init_state(uint32_t N, double *V, void *zv, ModelParams mp) {
+  using M = MathOf<MIXED>;
+  using R = typename M::R;
+  using Mod = Model<M>;
+  constexpr int NG = Mod::NG, NS = Mod::NS;
+  const uint32_t i = node_index();
+  if (i >= N) return;
+  R lam[NG], zinf[NG];
+  Mod::gates(R(Mod::V_REST), mp, lam, zinf);
+  V[i] = Mod::V_REST;
+  R *z = (R *)zv;
+#pragma unroll
+  for (int g = 0; g < NG; ++g) z[(size_t)g * N + i] = zinf[g];
+#pragma unroll
+  for (int s = 0; s < NS; ++s) z[(size_t)(NG + s) * N + i] = R(Mod::slow_rest(s));
+}
+
+// ---------------------------------------------------------------------------
+// Fused outer-stage head
+// ---------------------------------------------------------------------------
+template <template <class> class Model, bool MIXED>
+__global__ __launch_bounds__(kBlock) void k_head(HeadArgs a, Mesh mesh) {
+  using M = MathOf<MIXED>;
+  using R = typename M::R;
+  using Mod = Model<M>;
+  constexpr int NG = Mod::NG, NS = Mod::NS, NZ = NG + NS;
+  const uint32_t N = mesh.kind == kGrid ? mesh.grid.N : mesh.ell.N;
+  const uint32_t i = node_index();
+  if (i >= N) return;
+
+  const double tj = stage_time(a.clock, a.dt, a.c_prev);
+  const double Is = stimulus(a.stim, i, tj);
+  const double V = a.Vin[i];
+
+  const R *zin = (const R *)a.zin;
+  R z[NZ];
+#pragma unroll
+  for (int k = 0; k < NZ; ++k) z[k] = zin[(size_t)k * N + i];
+
+  // exponential Euler for the gates: z_E + (e^{eta Lambda} - 1)(z_E - z_inf)
+  R lam[NG], zinf[NG], zE[NG];
+  Mod::gates(R(V), a.mp, lam, zinf);
+  const R eta = R(a.eta);
+#pragma unroll
+  for (int g = 0; g < NG; ++g) zE[g] = z[g] + M::expm1(eta * lam[g]) * (z[g] - zinf[g]);
+
+  // slow right-hand side at y_E, frozen over the inner iteration
+  R dS[NS > 0 ? NS : 1];
+  const R iion = Mod::eval(R(V), zE, z + NG, dS, a.mp);
+  double SV;
+  if (MIXED)
+    SV = (double)((R(Is) - R(a.Cm) * iion) * R(1.0 / a.Cm));
+  else
+    SV = (Is - a.Cm * (double)iion) / a.Cm;
+
+  // outer recurrence of z with the averaged force (u_eta - y)/eta; the
+  // inner iteration leaves gates at z_E and moves the slow variables by
+  // c'_m eta g_S (f_F has no z component)
+  R *zout = (R *)a.zout;
+  const R *zin2 = (const R *)a.zin2;
+#pragma unroll
+  for (int k = 0; k < NZ; ++k) {
+    double fbar;
+    if (k < NG) {
+      fbar = (double)(zE[k] - z[k]) * a.inv_eta;
+    } else {
+      const double zs = (double)z[k];
+      const double um = zs + a.cm_eta * (double)dS[k - NG];
+      fbar = (um - zs) * a.inv_eta;
+    }
+    double zj;
+    if (a.j1)
+      zj = (double)z[k] + a.mu_dt * fbar;
+    else
+      zj = a.nu * (double)z[k] + a.kappa * (double)zin2[(size_t)k * N + i] + a.mu_dt * fbar;
+    zout[(size_t)k * N + i] = R(zj);
+  }
+
+  // first inner stage u_1 = u_0 + mu'_1 eta (f_F(u_0) + S_V), u_0 = V
+  const double FV = apply_op<MIXED>(mesh, a.Vin, i);
+  const double u1 = V + a.mu1_eta * (FV + SV);
+  if (a.m_is_one) {
+    const double fbarV = (u1 - V) * a.inv_eta;
+    a.uout[i] = a.j1 ? V + a.mu_dt * fbarV : a.nu * V + a.kappa * a.Vin2[i] + a.mu_dt * fbarV;
+  } else {
+    a.uout[i] = u1;
+    if (MIXED)
+      ((float *)a.SV)[i] = (float)SV;
+    else
+      ((double *)a.SV)[i] = SV;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Inner stage k >= 2 (and the outer V update at k == m)
+// ---------------------------------------------------------------------------
+template <bool MIXED>
+__global__ __launch_bounds__(kBlock) void k_inner(InnerArgs a, Mesh mesh) {
+  const uint32_t N = mesh.kind == kGrid ? mesh.grid.N : mesh.ell.N;
+  const uint32_t i = node_index();
+  if (a.tick != nullptr && blockIdx.x == 0 && threadIdx.x == 0) a.tick->step += 1;
+  if (i >= N) return;
+  const double Fu = apply_op<MIXED>(mesh, a.uprev, i);
+  const double sv = MIXED ? (double)((const float *)a.SV)[i] : ((const double *)a.SV)[i];
+  const double uk = a.nu * a.uprev[i] + a.kappa * a.uprev2[i] + a.mu_eta * (Fu + sv);
+  if (a.last) {
+    const double Vp = a.Vin[i];
+    const double fbar = (uk - Vp) * a.inv_eta;
+    a.out[i] = a.j1 ? Vp + a.mu_dt * fbar : a.nu_o * Vp + a.kappa_o * a.Vin2[i] + a.mu_dt * fbar;
+  } else {
+    a.out[i] = uk;
+  }
+}
+
+__global__ void k_clock_set(Clock *c, int64_t step, double t0) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    c->step = step;
+    c->t0 = t0;
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_copy_tick(const double *src, double *dst, uint32_t N, Clock *tick) {
+  const uint32_t i = node_index();
+  if (tick != nullptr && blockIdx.x == 0 && threadIdx.x == 0) tick->step += 1;
+  if (src != nullptr && i < N) dst[i] = src[i];
+}
+
+template <bool MIXED>
+__global__ __launch_bounds__(kBlock) void k_apply_diffusion(Mesh mesh, const double *V, double *out) {
+  const uint32_t N = mesh.kind == kGrid ? mesh.grid.N : mesh.ell.N;
+  const uint32_t i = node_index();
+  if (i >= N) return;
+  out[i] = apply_op<MIXED>(mesh, V, i);
+}
+
+// f_S(t, y) in double for the full state (component checks).
+template <template <class> class Model, bool MIXED>
+__global__ __launch_bounds__(kBlock) void k_eval_rhs_slow(uint32_t N, const double *V, const void *zv, double t,
+                                                          StimArgs stim, double Cm, ModelParams mp, double *out) {
+  using M = MathF64;
+  using Mod = Model<M>;
+  constexpr int NG = Mod::NG, NS = Mod::NS, NZ = NG + NS;
+  const uint32_t i = node_index();
+  if (i >= N) return;
+  using Rs = typename std::conditional<MIXED, float, double>::type;
+  const Rs *z = (const Rs *)zv;
+  double zz[NZ];
+#pragma unroll
+  for (int k = 0; k < NZ; ++k) zz[k] = (double)z[(size_t)k * N + i];
+  double dS[NS > 0 ? NS : 1];
+  const double v = V[i];
+  const double iion = Mod::eval(v, zz, zz + NG, dS, mp);
+  out[i] = (stimulus(stim, i, t) - Cm * iion) / Cm;
+#pragma unroll
+  for (int g = 0; g < NG; ++g) out[(size_t)(1 + g) * N + i] = 0.0;
+#pragma unroll
+  for (int s = 0; s < NS; ++s) out[(size_t)(1 + NG + s) * N + i] = dS[s];
+}
+
+// ---------------------------------------------------------------------------
+// Reductions
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double block_sum(double v) {
+  __shared__ double part[kBlock / 64];
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  if (lane == 0) part[wid] = v;
+  __syncthreads();
+  double s = 0.0;
+  if (threadIdx.x == 0) {
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) s += part[w];
+  }
+  return s;  // valid in thread 0
+}
+
+// Each block sums a contiguous chunk of `per_block` items in a fixed order.
+__global__ __launch_bounds__(kBlock) void k_reduce_final(const double *partials, uint32_t n, double *result) {
+  double v = 0.0;
+  for (uint32_t k = threadIdx.x; k < n; k += blockDim.x) v += partials[k];
+  v = block_sum(v);
+  if (threadIdx.x == 0) *result = v;
+}
+
+template <bool MIXED>
+__global__ __launch_bounds__(kBlock) void k_norm2_state(uint32_t N, int nz, const double *V, const void *zv,
+                                                        double *partials) {
+  using Rs = typename std::conditional<MIXED, float, double>::type;
+  const Rs *z = (const Rs *)zv;
+  const uint64_t total = (uint64_t)N * (uint64_t)(nz + 1);
+  double v = 0.0;
+  for (uint64_t k = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; k < total;
+       k += (uint64_t)gridDim.x * blockDim.x) {
+    const double x = k < N ? V[k] : (double)z[k - N];
+    v += x * x;
+  }
+  v = block_sum(v);
+  if (threadIdx.x == 0) partials[blockIdx.x] = v;
+}
+
+__global__ __launch_bounds__(kBlock) void k_norm2_random(uint64_t seed, uint64_t total, double *partials) {
+  double v = 0.0;
+  for (uint64_t k = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; k < total;
+       k += (uint64_t)gridDim.x * blockDim.x) {
+    const double x = splitmix64_unit(seed, k);
+    v += x * x;
+  }
+  v = block_sum(v);
+  if (threadIdx.x == 0) partials[blockIdx.x] = v;
+}
+
+__global__ __launch_bounds__(kBlock) void k_powF_shift(uint32_t N, const double *yV, const double *vin,
+                                                       uint64_t seed, double q, double *zV) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  const double v = vin != nullptr ? vin[i] : splitmix64_unit(seed, i);
+  zV[i] = yV[i] + q * v;
+}
+
+template <bool MIXED>
+__global__ __launch_bounds__(kBlock) void k_powF_diff(Mesh mesh, const double *zV, const double *yV, double *vout,
+                                                      double *partials) {
+  const uint32_t N = mesh.kind == kGrid ? mesh.grid.N : mesh.ell.N;
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  double v = 0.0;
+  if (i < N) {
+    // the power iteration always differences in double
+    const double d = apply_op<false>(mesh, zV, i) - apply_op<false>(mesh, yV, i);
+    vout[i] = d;
+    v = d * d;
+  }
+  v = block_sum(v);
+  if (threadIdx.x == 0) partials[blockIdx.x] = v;
+}
+
+template <template <class> class Model, bool MIXED>
+__global__ __launch_bounds__(kBlock) void k_powS_iter(uint32_t N, const double *V, const void *zv, const double *vin,
+                                                      uint64_t seed, double q, double t, StimArgs stim, double Cm,
+                                                      ModelParams mp, double *vout, double *partials) {
+  using M = MathF64;
+  using Mod = Model<M>;
+  constexpr int NG = Mod::NG, NS = Mod::NS, NZ = NG + NS;
+  using Rs = typename std::conditional<MIXED, float, double>::type;
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  double acc = 0.0;
+  if (i < N) {
+    const Rs *z = (const Rs *)zv;
+    double y[NZ], w[NZ];
+    const double yv = V[i];
+#pragma unroll
+    for (int k = 0; k < NZ; ++k) y[k] = (double)z[(size_t)k * N + i];
+    // perturbed state z = y + q v; gate components of a warm vector are 0
+    double wv;
+    if (vin == nullptr) {
+      wv = yv + q * splitmix64_unit(seed, i);
+#pragma unroll
+      for (int k = 0; k < NZ; ++k) w[k] = y[k] + q * splitmix64_unit(seed, (uint64_t)(1 + k) * N + i);
+    } else {
+      wv = yv + q * vin[i];
+#pragma unroll
+      for (int k = 0; k < NZ; ++k)
+        w[k] = k < NG ? y[k] + q * 0.0 : y[k] + q * vin[(size_t)(1 + k - NG) * N + i];
+    }
+    const double Is = stimulus(stim, i, t);
+    double dSy[NS > 0 ? NS : 1], dSw[NS > 0 ? NS : 1];
+    const double fy = (Is - Cm * Mod::eval(yv, y, y + NG, dSy, mp)) / Cm;
+    const double fw = (Is - Cm * Mod::eval(wv, w, w + NG, dSw, mp)) / Cm;
+    const double dv = fw - fy;
+    vout[i] = dv;
+    acc = dv * dv;
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+      const double d = dSw[s] - dSy[s];
+      vout[(size_t)(1 + s) * N + i] = d;
+      acc += d * d;
+    }
+  }
+  acc = block_sum(acc);
+  if (threadIdx.x == 0) partials[blockIdx.x] = acc;
+}
+
+__global__ __launch_bounds__(kBlock) void k_finite_check(uint32_t N, const double *V, int *flag) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < N && !isfinite(V[i])) *flag = 1;  // benign race: every writer stores 1
+}
+
+// ---------------------------------------------------------------------------
+// Launchers
+// ---------------------------------------------------------------------------
+static inline uint32_t blocks_for(uint64_t n) { return (uint32_t)((n + kBlock - 1) / kBlock); }
+
+uint32_t reduce_blocks(uint32_t n) { return blocks_for(n); }
+
+template <template <class> class Model>
+static hipError_t head_dispatch(bool mixed, const Mesh &mesh, const HeadArgs &a, hipStream_t st) {
+  const uint32_t N = mesh.kind == kGrid ? mesh.grid.N : mesh.ell.N;
+  if (mixed)
+    hipLaunchKernelGGL((k_head<Model, true>), dim3(blocks_for(N)), dim3(kBlock), 0, st, a, mesh);
+  else
+    hipLaunchKernelGGL((k_head<Model, false>), dim3(blocks_for(N)), dim3(kBlock), 0, st, a, mesh);
+  return hipGetLastError();
+}
+
+template <template <class> class Model>
+static hipError_t init_dispatch(bool mixed, uint32_t N, double *V, void *z, ModelParams mp, hipStream_t st) {
+  if (mixed)
+    hipLaunchKernelGGL((k_init_state<Model, true>), dim3(blocks_for(N)), dim3(kBlock), 0, st, N, V, z, mp);
+  else
+    hipLaunchKernelGGL((k_init_state<Model, false>), dim3(blocks_for(N)), dim3(kBlock), 0, st, N, V, z, mp);
+  return hipGetLastError();
+}
+
+template <template <class> class Model>
+static hipError_t rhs_dispatch(bool mixed, uint32_t N, const double *V, const void *z, double t, StimArgs stim,
+                               double Cm, ModelParams mp, double *out, hipStream_t st) {
+  if (mixed)
+    hipLaunchKernelGGL((k_eval_rhs_slow<Model, true>), dim3(blocks_for(N)), dim3(kBlock), 0, st, N, V, z, t,
+                       stim, Cm, mp, out);
+  else
+    hipLaunchKernelGGL((k_eval_rhs_slow<Model, false>), dim3(blocks_for(N)), dim3(kBlock), 0, st, N, V, z, t,
+                       stim, Cm, mp, out);
+  return hipGetLastError();
+}
+
+template <template <class> class Model>
+static hipError_t powS_dispatch(bool mixed, uint32_t N, const double *V, const void *z, const double *vin,
+                                uint64_t seed, double q, double t, StimArgs stim, double Cm, ModelParams mp,
+                                double *vout, double *partials, hipStream_t st) {
+  if (mixed)
+    hipLaunchKernelGGL((k_powS_iter<Model, true>), dim3(blocks_for(N)), dim3(kBlock), 0, st, N, V, z, vin, seed,
+                       q, t, stim, Cm, mp, vout, partials);
+  else
+    hipLaunchKernelGGL((k_powS_iter<Model, false>), dim3(blocks_for(N)), dim3(kBlock), 0, st, N, V, z, vin, seed,
+                       q, t, stim, Cm, mp, vout, partials);
+  return hipGetLastError();
+}
+
+#define EMRKC_MODEL_SWITCH(model, CALL)          \
+  switch (model) {                               \
+    case 1: return CALL(HHModel);                \
+    case 2: return CALL(LinearModel);            \
+    case 3: return CALL(CrnSurrModel);           \
+    case 4: return CALL(TtpSurrModel);           \
+    default: return hipErrorInvalidValue;        \
+  }
+
+hipError_t launch_init_state(int model, bool mixed, uint32_t N, double *V, void *z, ModelParams mp, hipStream_t st) {
+#define CALL(M) init_dispatch<M>(mixed, N, V, z, mp, st)
+  EMRKC_MODEL_SWITCH(model, CALL)
+#undef CALL
+}
+
+hipError_t launch_head(int model, bool mixed, const Mesh &mesh, const HeadArgs &a, hipStream_t st) {
+#define CALL(M) head_dispatch<M>(mixed, mesh, a, st)
+  EMRKC_MODEL_SWITCH(model, CALL)
+#undef CALL
+}
+
+hipError_t launch_inner(bool mixed, const Mesh &mesh, const InnerArgs &a, hipStream_t st) {
+  const uint32_t N = mesh.kind == kGrid ? mesh.grid.N : mesh.ell.N;
+  if (mixed)
+    hipLaunchKernelGGL((k_inner<true>), dim3(blocks_for(N)), dim3(kBlock), 0, st, a, mesh);
+  else
+    hipLaunchKernelGGL((k_inner<false>), dim3(blocks_for(N)), dim3(kBlock), 0, st, a, mesh);
+  return hipGetLastError();
+}
+
+hipError_t launch_clock_set(Clock *c, int64_t step, double t0, hipStream_t st) {
+  hipLaunchKernelGGL(k_clock_set, dim3(1), dim3(64), 0, st, c, step, t0);
+  return hipGetLastError();
+}
+
+hipError_t launch_copy_tick(const double *src, double *dst, uint32_t N, Clock *tick, hipStream_t st) {
+  const uint32_t nb = src != nullptr ? blocks_for(N) : 1;
+  hipLaunchKernelGGL(k_copy_tick, dim3(nb), dim3(kBlock), 0, st, src, dst, N, tick);
+  return hipGetLastError();
+}
+
+hipError_t launch_apply_diffusion(bool mixed, const Mesh &mesh, const double *V, double *out, hipStream_t st) {
+  const uint32_t N = mesh.kind == kGrid ? mesh.grid.N : mesh.ell.N;
+  if (mixed)
+    hipLaunchKernelGGL((k_apply_diffusion<true>), dim3(blocks_for(N)), dim3(kBlock), 0, st, mesh, V, out);
+  else
+    hipLaunchKernelGGL((k_apply_diffusion<false>), dim3(blocks_for(N)), dim3(kBlock), 0, st, mesh, V, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_eval_rhs_slow(int model, bool mixed, uint32_t N, const double *V, const void *z, double t,
+                                StimArgs stim, double Cm, ModelParams mp, double *out, hipStream_t st) {
+#define CALL(M) rhs_dispatch<M>(mixed, N, V, z, t, stim, Cm, mp, out, st)
+  EMRKC_MODEL_SWITCH(model, CALL)
+#undef CALL
+}
+
+static hipError_t finish_reduce(uint32_t nparts, double *partials, double *result, hipStream_t st) {
+  hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(kBlock), 0, st, partials, nparts, result);
+  return hipGetLastError();
+}
+
+hipError_t launch_norm2_state(bool mixed, uint32_t N, int nz, const double *V, const void *z, double *partials,
+                              double *result, hipStream_t st) {
+  const uint32_t nb = blocks_for(N);
+  if (mixed)
+    hipLaunchKernelGGL((k_norm2_state<true>), dim3(nb), dim3(kBlock), 0, st, N, nz, V, z, partials);
+  else
+    hipLaunchKernelGGL((k_norm2_state<false>), dim3(nb), dim3(kBlock), 0, st, N, nz, V, z, partials);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  return finish_reduce(nb, partials, result, st);
+}
+
+hipError_t launch_norm2_random(uint64_t seed, uint64_t count, double *partials, double *result, hipStream_t st) {
+  // grid sized like the state reductions: count / nz items per block is fine
+  const uint32_t nb = blocks_for(count) > 65536u ? 65536u : blocks_for(count);
+  hipLaunchKernelGGL(k_norm2_random, dim3(nb), dim3(kBlock), 0, st, seed, count, partials);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  return finish_reduce(nb, partials, result, st);
+}
+
+hipError_t launch_powF_shift(uint32_t N, const double *yV, const double *vin, uint64_t seed, double q, double *zV,
+                             hipStream_t st) {
+  hipLaunchKernelGGL(k_powF_shift, dim3(blocks_for(N)), dim3(kBlock), 0, st, N, yV, vin, seed, q, zV);
+  return hipGetLastError();
+}
+
+hipError_t launch_powF_diff(bool mixed, const Mesh &mesh, const double *zV, const double *yV, double *vout,
+                            double *partials, double *result, hipStream_t st) {
+  const uint32_t N = mesh.kind == kGrid ? mesh.grid.N : mesh.ell.N;
+  const uint32_t nb = blocks_for(N);
+  hipLaunchKernelGGL((k_powF_diff<false>), dim3(nb), dim3(kBlock), 0, st, mesh, zV, yV, vout, partials);
+  (void)mixed;
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  return finish_reduce(nb, partials, result, st);
+}
+
+hipError_t launch_powS_iter(int model, bool mixed, uint32_t N, const double *V, const void *z, const double *vin,
+                            uint64_t seed, double q, double t, StimArgs stim, double Cm, ModelParams mp,
+                            double *vout, double *partials, double *result, hipStream_t st) {
+  hipError_t e;
+  switch (model) {
+    case 1: e = powS_dispatch<HHModel>(mixed, N, V, z, vin, seed, q, t, stim, Cm, mp, vout, partials, st); break;
+    case 2: e = powS_dispatch<LinearModel>(mixed, N, V, z, vin, seed, q, t, stim, Cm, mp, vout, partials, st); break;
+    case 3: e = powS_dispatch<CrnSurrModel>(mixed, N, V, z, vin, seed, q, t, stim, Cm, mp, vout, partials, st); break;
+    case 4: e = powS_dispatch<TtpSurrModel>(mixed, N, V, z, vin, seed, q, t, stim, Cm, mp, vout, partials, st); break;
+    default: return hipErrorInvalidValue;
+  }
+  if (e != hipSuccess) return e;
+  return finish_reduce(blocks_for(N), partials, result, st);
+}
+
+hipError_t launch_finite_check(uint32_t N, const double *V, int *flag, hipStream_t st) {
+  hipLaunchKernelGGL(k_finite_check, dim3(blocks_for(N)), dim3(kBlock), 0, st, N, V, flag);
+  return hipGetLastError();
+}
+
+}  // namespace emrkc

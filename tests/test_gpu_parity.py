@@ -1,0 +1,247 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle on
+the same seeded synthetic inputs.  FP64 results must agree to 1e-10
+relative in V (spec bound), component kernels to a few ulps."""
+import numpy as np
+import pytest
+
+from gpu_util import gpu_run, oracle_rho, oracle_run, rel_errors
+from oracle.monodomain import build_grid_problem
+from workloads.configs import get_config, small_config
+
+pytestmark = pytest.mark.gpu
+
+FP64_TOL = 1e-10
+
+
+@pytest.fixture(scope="module")
+def E():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    from paper_2401_01745_amd import emrkc
+    emrkc.lib()
+    return emrkc
+
+
+def to_dev(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+@pytest.mark.parametrize("name,model", [("c1_2d_hh", "HH"), ("c2_3d_crn", "CRN_SURR"), ("c2_3d_crn", "TTP_SURR")])
+def test_init_state_matches_model_rest(E, name, model):
+    import torch
+    cfg = small_config(name, (9, 7) if name.startswith("c1") else (9, 7, 5), model=model)
+    sim = E.simulation_from_config(cfg, rho=(1.0, 1.0))
+    E.emrkc_init_state(sim.ctx, sim.state)
+    torch.cuda.synchronize()
+    prob = build_grid_problem(cfg)
+    y = prob.uniform_state().reshape(prob.nv, prob.N)
+    assert np.array_equal(sim.V.cpu().numpy(), y[0])
+    assert np.abs(sim.z.cpu().numpy() - y[1:]).max() <= 2e-16 * np.abs(y[1:]).max()
+    sim.close()
+
+
+@pytest.mark.parametrize("n", [(37, 29, 11), (13, 300), (201, 7, 3)])
+def test_diffusion_operator(E, n):
+    """(chi Cm M_L)^{-1} A V from the stencil kernel against the oracle's
+    assembled sparse matrix, random V with a resting offset."""
+    import torch
+    cfg = small_config("c2_3d_crn" if len(n) == 3 else "c1_2d_hh", n)
+    if len(n) == 2:
+        cfg["h"] = (0.02, 0.03)
+        cfg["sigma"] = (0.17, 0.05, 0.05)
+    prob = build_grid_problem(cfg)
+    rng = np.random.default_rng(sum(n))
+    V = -65.0 + 20.0 * rng.standard_normal(prob.N)
+    ref = prob.f_F(0.0, np.concatenate([V, np.zeros(prob.N * (prob.nv - 1))]))[:prob.N]
+    sim = E.simulation_from_config(cfg, rho=(1.0, 1.0))
+    out = torch.empty(prob.N, dtype=torch.float64, device="cuda")
+    E.emrkc_apply_diffusion(sim.ctx, to_dev(V), out)
+    torch.cuda.synchronize()
+    got = out.cpu().numpy()
+    scale = np.abs(prob.A).sum(axis=1).A1 / (prob.chi * prob.Cm * prob.ML) * np.abs(V).max()
+    assert np.all(np.abs(got - ref) <= 1e-14 * scale.max()), np.abs(got - ref).max() / scale.max()
+    # constant states are in the kernel of the operator: exactly zero
+    E.emrkc_apply_diffusion(sim.ctx, to_dev(np.full(prob.N, -65.0)), out)
+    torch.cuda.synchronize()
+    assert np.all(out.cpu().numpy() == 0.0)
+    sim.close()
+
+
+@pytest.mark.parametrize("model", ["HH", "CRN_SURR", "TTP_SURR", "LINEAR"])
+def test_slow_rhs(E, model):
+    """f_S(t, y) at perturbed states from the ionic kernel's model code."""
+    import torch
+    kw = dict(a=0.7, lam_E=-3.0) if model == "LINEAR" else {}
+    cfg = small_config("c2_3d_crn", (11, 9, 7), model=model)
+    prob = build_grid_problem(cfg, model_kw=kw)
+    rng = np.random.default_rng(4)
+    y = prob.uniform_state().reshape(prob.nv, prob.N)
+    y[0] += rng.uniform(-20, 90, prob.N)
+    y[1:1 + prob.nE] = np.clip(y[1:1 + prob.nE] + rng.uniform(-0.2, 0.2, (prob.nE, prob.N)), 0, 1)
+    if prob.nS:
+        y[1 + prob.nE:] *= rng.uniform(0.9, 1.1, (prob.nS, prob.N))
+    yf = y.reshape(-1)
+    for t in (0.5, 3.0):
+        ref = prob.f_S(t, yf).reshape(prob.nv, prob.N)
+        sim = E.simulation_from_config(cfg, rho=(1.0, 1.0), **kw)
+        sim.V.copy_(to_dev(y[0]))
+        sim.z.copy_(to_dev(y[1:]))
+        out = torch.empty(prob.nv * prob.N, dtype=torch.float64, device="cuda")
+        E.emrkc_eval_rhs_slow(sim.ctx, sim.state, t, out)
+        torch.cuda.synchronize()
+        got = out.cpu().numpy().reshape(prob.nv, prob.N)
+        for c in range(prob.nv):
+            scale = max(np.abs(ref[c]).max(), 1e-300)
+            assert np.abs(got[c] - ref[c]).max() <= 1e-12 * scale, (c, np.abs(got[c] - ref[c]).max() / scale)
+        sim.close()
+
+
+def _compare_full(cfg, nsteps, rho, tol=FP64_TOL, model_kw=None, **kw):
+    prob, y = oracle_run(cfg, nsteps, rho, model_kw=model_kw)
+    V, z, stats = gpu_run(cfg, nsteps, rho, model_kw=model_kw, **kw)
+    Y = y.reshape(prob.nv, prob.N)
+    l2, mx = rel_errors(V, Y[0])
+    assert l2 <= tol and mx <= tol, (l2, mx)
+    for c in range(1, prob.nv):
+        zl2, zmx = rel_errors(z[c - 1], Y[c])
+        assert zl2 <= tol and zmx <= tol, (c, zl2, zmx)
+    return prob, Y, V, stats
+
+
+def test_c1_full_run_fp64(E):
+    """Unit-square HH workload (65 x 65, 100 steps of 0.05 ms) with the
+    oracle's own spectral radii: s = 1, m = 7."""
+    cfg = get_config("c1_2d_hh")
+    prob = build_grid_problem(cfg)
+    rF, rS, _, _ = oracle_rho(prob, prob.uniform_state())
+    _, _, _, stats = _compare_full(cfg, 100, (rF, rS))
+    assert (stats.s, stats.m) == (1, 7)
+
+
+@pytest.mark.parametrize("model,n", [("CRN_SURR", (37, 29, 11)), ("TTP_SURR", (41, 19, 9))])
+def test_3d_wave_fp64(E, model, n):
+    """3-D slab with a propagating wave (200 steps = 10 ms)."""
+    cfg = small_config("c2_3d_crn", n, model=model)
+    prob = build_grid_problem(cfg)
+    rF, rS, _, _ = oracle_rho(prob, prob.uniform_state())
+    _, Y, V, stats = _compare_full(cfg, 200, (rF, rS))
+    assert (stats.s, stats.m) == (1, 2)
+    assert Y[0].max() > 0.0  # the wave is inside the domain
+
+
+def test_2d_wave_fp64(E):
+    cfg = small_config("c2_3d_crn", (61, 45), model="TTP_SURR")
+    cfg["dim"] = 2
+    cfg["h"] = (0.1, 0.1)
+    _compare_full(cfg, 120, (51.0, 9.0))
+
+
+@pytest.mark.parametrize("rho,sm", [((51.0, 100.0), (2, 1)), ((2000.0, 300.0), (3, 3)), ((10.0, 4.0), (1, 1)),
+                                    ((51.0, 700.0), (5, 1)), ((5000.0, 100.0), (2, 4))])
+def test_stage_plans(E, rho, sm):
+    """Outer stages s >= 2 and single inner stages m = 1 (buffer rotation
+    and the final copy) against the oracle."""
+    cfg = small_config("c2_3d_crn", (23, 17, 7))
+    _, _, _, stats = _compare_full(cfg, 60, rho)
+    assert (stats.s, stats.m) == sm
+
+
+def test_linear_model_closed_form_on_gpu(E):
+    """LINEAR model from a cosine mode: V_{n} = P_s(dt Phi_m(eta lF)(lF + lS))^n V0
+    (the scalar stability analysis applied per eigenmode)."""
+    import torch
+    from test_oracle_emrkc import P_cheb, Phi, cosine_mode, phi
+    from oracle.emrkc import stage_counts
+    n, h, sig = (33, 17, 9), (0.1, 0.1, 0.1), (0.17, 0.019, 0.019)
+    cfg = small_config("c2_3d_crn", n, model="LINEAR")
+    cfg["stim"]["amp"] = 0.0
+    a, lamE = 2.0, -40.0
+    ks = (5, 3, 2)
+    th = [np.pi * k / (nn - 1) for k, nn in zip(ks, n)]
+    lam = [(2 - 2 * np.cos(t)) / hh ** 2 for t, hh in zip(th, h)]
+    mu = [(2 + np.cos(t)) / 3 for t in th]
+    eig = sig[0] * lam[0] * mu[1] * mu[2] + sig[1] * mu[0] * lam[1] * mu[2] + sig[2] * mu[0] * mu[1] * lam[2]
+    lF = -eig / (cfg["chi"] * cfg["Cm"])
+    rho = (51.0, 2.1)
+    s, m, eta = stage_counts(cfg["dt"], *rho)
+    amp = P_cheb(s, cfg["dt"] * Phi(m, eta * lF) * (lF - a))
+    ampz = P_cheb(s, cfg["dt"] * phi(eta * lamE) * lamE)
+    V0 = cosine_mode(n, ks)
+    sim = E.simulation_from_config(cfg, rho=rho, a=a, lam_E=lamE)
+    sim.V.copy_(to_dev(V0))
+    sim.z.fill_(0.5)
+    E.emrkc_step(sim.ctx, sim.state, cfg["dt"], 25)
+    torch.cuda.synchronize()
+    assert np.abs(sim.V.cpu().numpy() - amp ** 25 * V0).max() < 1e-13
+    assert np.abs(sim.z.cpu().numpy() - 0.5 * ampz ** 25).max() < 1e-14
+    sim.close()
+
+
+def test_graph_eager_split_and_repeat_are_bitwise_identical(E):
+    cfg = small_config("c2_3d_crn", (29, 23, 9))
+    rho = (51.0, 4.4)
+    V1, z1, st1 = gpu_run(cfg, 80, rho)
+    V2, z2, st2 = gpu_run(cfg, 80, rho, flags=E.EMRKC_EAGER)
+    V3, z3, _ = gpu_run(cfg, 80, rho, chunks=[1, 33, 7, 39])
+    V4, z4, _ = gpu_run(cfg, 80, rho)
+    assert st1.used_graph == 1 and st2.used_graph == 0
+    for V, z in [(V2, z2), (V3, z3), (V4, z4)]:
+        assert np.array_equal(V, V1) and np.array_equal(z, z1)
+
+
+@pytest.mark.parametrize("model,n", [("HH", (65, 65)), ("CRN_SURR", (37, 29, 11)), ("TTP_SURR", (21, 17, 9))])
+def test_estimate_rho_matches_oracle(E, model, n):
+    """Power iteration on the GPU against the oracle's Compute_Rho from the
+    same splitmix64 start: same iteration counts, radii within the
+    finite-difference noise of delta = 1e-8 ||y|| (about 1e-8 relative per
+    evaluation; 1e-6 allowed)."""
+    import torch
+    base = "c1_2d_hh" if len(n) == 2 else "c2_3d_crn"
+    cfg = small_config(base, n, model=model)
+    prob = build_grid_problem(cfg)
+    y = prob.uniform_state()
+    rF, rS, itF, itS = oracle_rho(prob, y)
+    sim = E.simulation_from_config(cfg)
+    E.emrkc_init_state(sim.ctx, sim.state)
+    gF, gS, gitF, gitS, rc = E.emrkc_estimate_rho(sim.ctx, sim.state)
+    assert (gitF, gitS) == (itF, itS)
+    assert gF == pytest.approx(rF, rel=1e-6) and gS == pytest.approx(rS, rel=1e-6)
+    # warm restart converges at once to the same values
+    gF2, gS2, it2F, it2S, _ = E.emrkc_estimate_rho(sim.ctx, sim.state)
+    assert it2F <= 2 and it2S <= 2
+    assert gF2 == pytest.approx(gF, rel=2e-2) and gS2 == pytest.approx(gS, rel=2e-2)
+    sim.close()
+
+
+def test_check_finite_reports_nan(E):
+    import torch
+    cfg = small_config("c2_3d_crn", (9, 7, 5))
+    sim = E.simulation_from_config(cfg, rho=(51.0, 4.4), flags=E.EMRKC_CHECK_FINITE)
+    E.emrkc_init_state(sim.ctx, sim.state)
+    E.emrkc_step(sim.ctx, sim.state, 0.05, 3)
+    sim.V[17] = float("nan")
+    with pytest.raises(E.EmrkcError) as ei:
+        E.emrkc_step(sim.ctx, sim.state, 0.05, 1)
+    assert ei.value.code == E.EMRKC_ENONFINITE
+    sim.close()
+
+
+def test_step_without_radii_is_rejected(E):
+    cfg = small_config("c2_3d_crn", (9, 7, 5))
+    sim = E.simulation_from_config(cfg)
+    E.emrkc_init_state(sim.ctx, sim.state)
+    with pytest.raises(E.EmrkcError) as ei:
+        E.emrkc_step(sim.ctx, sim.state, 0.05, 1)
+    assert ei.value.code == E.EMRKC_EINVAL
+    sim.close()
+
+
+@pytest.mark.slow
+def test_c2_full_size_prefix_fp64(E):
+    """The benchmark workload itself (201 x 71 x 31, CRN surrogate) for the
+    first 10 steps (stimulus on), every node compared."""
+    cfg = get_config("c2_3d_crn")
+    prob = build_grid_problem(cfg)
+    rF, rS, _, _ = oracle_rho(prob, prob.uniform_state())
+    _compare_full(cfg, 10, (rF, rS))
