@@ -27,10 +27,12 @@ def gpu_run(cfg, nsteps, rho, precision="fp64", flags=0, chunks=None, model_kw=N
     return out
 
 
-def oracle_run(cfg, nsteps, rho, model_kw=None, y0=None):
+def oracle_run(cfg, nsteps, rho, model_kw=None, y0=None, track=None):
+    """Oracle run; ``track`` (a list) receives max V after every step."""
     prob = build_grid_problem(cfg, model_kw=model_kw)
     y = prob.uniform_state() if y0 is None else y0
-    y = emrkc_run(prob, y, 0.0, cfg["dt"], nsteps, rho[0], rho[1])
+    cb = None if track is None else (lambda n, yy: track.append(float(yy[:prob.N].max())))
+    y = emrkc_run(prob, y, 0.0, cfg["dt"], nsteps, rho[0], rho[1], callback=cb)
     return prob, y
 
 

@@ -97,8 +97,9 @@ def test_slow_rhs(E, model):
         sim.close()
 
 
-def _compare_full(cfg, nsteps, rho, tol=FP64_TOL, model_kw=None, **kw):
-    prob, y = oracle_run(cfg, nsteps, rho, model_kw=model_kw)
+def _compare_full(cfg, nsteps, rho, tol=FP64_TOL, model_kw=None, track=None, **kw):
+    prob, y = oracle_run(cfg, nsteps, rho, model_kw=model_kw, track=track)
+    assert np.all(np.isfinite(y)), "oracle run not finite: pick a stable case"
     V, z, stats = gpu_run(cfg, nsteps, rho, model_kw=model_kw, **kw)
     Y = y.reshape(prob.nv, prob.N)
     l2, mx = rel_errors(V, Y[0])
@@ -121,13 +122,15 @@ def test_c1_full_run_fp64(E):
 
 @pytest.mark.parametrize("model,n", [("CRN_SURR", (37, 29, 11)), ("TTP_SURR", (41, 19, 9))])
 def test_3d_wave_fp64(E, model, n):
-    """3-D slab with a propagating wave (200 steps = 10 ms)."""
+    """3-D slab with a propagating wave (200 steps = 10 ms): excitation,
+    propagation through the slab and recovery."""
     cfg = small_config("c2_3d_crn", n, model=model)
     prob = build_grid_problem(cfg)
     rF, rS, _, _ = oracle_rho(prob, prob.uniform_state())
-    _, Y, V, stats = _compare_full(cfg, 200, (rF, rS))
+    vmax = []
+    _, Y, V, stats = _compare_full(cfg, 200, (rF, rS), track=vmax)
     assert (stats.s, stats.m) == (1, 2)
-    assert Y[0].max() > 0.0  # the wave is inside the domain
+    assert max(vmax) > 20.0  # an action potential fired
 
 
 def test_2d_wave_fp64(E):
@@ -137,12 +140,14 @@ def test_2d_wave_fp64(E):
     _compare_full(cfg, 120, (51.0, 9.0))
 
 
-@pytest.mark.parametrize("rho,sm", [((51.0, 100.0), (2, 1)), ((2000.0, 300.0), (3, 3)), ((10.0, 4.0), (1, 1)),
-                                    ((51.0, 700.0), (5, 1)), ((5000.0, 100.0), (2, 4))])
-def test_stage_plans(E, rho, sm):
+@pytest.mark.parametrize("rho,dt,sm", [((51.0, 100.0), 0.05, (2, 1)), ((2000.0, 300.0), 0.05, (3, 3)),
+                                       ((51.0, 4.4), 0.025, (1, 1)), ((51.0, 700.0), 0.05, (5, 1)),
+                                       ((5000.0, 100.0), 0.05, (2, 6)), ((150.0, 30.0), 0.1, (2, 2))])
+def test_stage_plans(E, rho, dt, sm):
     """Outer stages s >= 2 and single inner stages m = 1 (buffer rotation
-    and the final copy) against the oracle."""
-    cfg = small_config("c2_3d_crn", (23, 17, 7))
+    and the final copy) against the oracle.  Radii are over-estimates of the
+    true ones (rho_F = 48.6, rho_S = 4.2), which keeps every case stable."""
+    cfg = small_config("c2_3d_crn", (23, 17, 7), dt=dt)
     _, _, _, stats = _compare_full(cfg, 60, rho)
     assert (stats.s, stats.m) == sm
 
