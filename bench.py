@@ -32,27 +32,25 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def head_bytes_per_node(nz, wz, s, m, j):
-    """Algorithmic HBM bytes per node of the fused head kernel of stage j:
-    V_{j-1} (8), z_{j-1} and z_j (nz*wz each), z_{j-2} when j >= 2, and
-    either S_V (wz for mixed... 4 or 8) + u_1 (8) or, when m == 1, V_j (8)
-    plus V_{j-2} when j >= 2."""
-    b = 8 + 2 * nz * wz + (nz * wz if j >= 2 else 0)
-    if m >= 2:
-        b += (4 if wz == 4 else 8) + 8
-    else:
-        b += 8 + (8 if j >= 2 else 0)
-    return b
-
-
-def inner_bytes_per_node(wz, k, m, j):
-    """Inner stage k >= 2: u_{k-1} (8, neighbours from cache), u_{k-2} (8),
-    S_V (4 or 8) and the output (8); at k == m the outer V update also
-    reads V_{j-1} (already read when k == 2) and V_{j-2} when j >= 2."""
-    b = 8 + 8 + (4 if wz == 4 else 8) + 8
-    if k == m:
-        b += (8 if k != 2 else 0) + (8 if j >= 2 else 0)
-    return b
+def bytes_per_node(kind, nz, wz, m):
+    """Algorithmic HBM bytes per node of one launch (s = 1): V and u values
+    are doubles, z has width wz, S_V has width sv (4 in the mixed form).
+    head : V (8), z read and written (2 nz wz), S_V (sv) and u_1 (8) written
+    fused: last inner stage of the previous step -- u_{m-1} (8), u_{m-2} (8,
+           only when m >= 3: for m = 2 it is V), V (8), S_V (sv) -- plus the
+           head without its V read, plus V^n written (8)
+    inner: u_{k-1}, u_{k-2}, S_V, u_k
+    tail : u_{m-1}, u_{m-2} (m >= 3), V, S_V, V written"""
+    sv = 4 if wz == 4 else 8
+    if kind == "head":
+        return 8 + 2 * nz * wz + sv + 8
+    if kind == "fused":
+        return 8 + (8 if m >= 3 else 0) + 8 + sv + 2 * nz * wz + sv + 8 + 8
+    if kind == "inner":
+        return 8 + 8 + sv + 8
+    if kind == "tail":
+        return 8 + (8 if m >= 3 else 0) + 8 + sv + 8
+    raise ValueError(kind)
 
 
 class Job:
@@ -118,6 +116,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--calib-copy-mib", type=int, default=0,
+                    help="copy a buffer of this size once (calibrates rocprof FETCH/WRITE counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on exactly one GPU: the emRKC hot path here is a single-GPU build "
@@ -132,6 +132,14 @@ def main():
     cfg = get_config(args.config)
     N = int(np.prod(cfg["n"]))
     stream = torch.cuda.Stream()
+    if args.calib_copy_mib > 0:
+        src = torch.ones(args.calib_copy_mib << 18, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log("bench: calibration copy of %d MiB done" % args.calib_copy_mib)
+        del src, dst
     with torch.cuda.stream(stream):
         log("bench: %s, N=%d, building FP64 context" % (cfg["name"], N))
         job = Job(cfg, "fp64", stream)
@@ -143,27 +151,27 @@ def main():
         V64 = job.sim.V.cpu().numpy().copy()
 
         # per-kernel durations with HIP events (eager launches, same kernels)
-        head_ms, inner_ms, n_head, n_inner = E.emrkc_profile_step(job.sim.ctx, job.sim.state, cfg["dt"],
-                                                                  args.kernel_steps)
+        prof = E.emrkc_profile_step(job.sim.ctx, job.sim.state, cfg["dt"], args.kernel_steps)
         nz = job.sim.nv - 1
-        hb = head_bytes_per_node(nz, 8, s, m, 1) * N
-        ib = inner_bytes_per_node(8, m, m, 1) * N if m >= 2 else 0
-        log("bench: head %.4f ms (%d launches), inner %.4f ms (%d launches)" % (head_ms, n_head, inner_ms, n_inner))
-        head_gbs = hb / (head_ms * 1e-3) / 1e9
-        inner_gbs = ib / (inner_ms * 1e-3) / 1e9 if inner_ms > 0 else None
-        prof_path = os.path.join(ROOT, "profiles", "traffic_c2_3d_crn_fp64.json")
+        log("bench: kernel means (ms, launches): %s" % prof)
+        dom = "fused" if prof["fused"][1] > 0 else "head"
+        dom_ms = prof[dom][0]
+        db = bytes_per_node(dom, nz, 8, m) * N
+        dom_gbs = db / (dom_ms * 1e-3) / 1e9
+        prof_path = os.path.join(ROOT, "profiles", "traffic_k_%s_c2_3d_crn_fp64.json" % dom)
         traffic = None
         if os.path.exists(prof_path):
             tr = json.load(open(prof_path))
             if tr.get("kernel_source_hash") == kernel_hash():
-                traffic = tr.get("head_bytes_per_launch")
-        roof = {"kernel": "k_head (fused ionic + Rush-Larsen + outer z recurrence + first inner stage)",
-                "bound": "hbm", "achieved": round(head_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(head_gbs / HBM_PEAK_GBS, 4), "traffic": traffic,
-                "bytes_per_launch": hb, "launch_ms": round(head_ms, 5),
-                "inner_kernel": {"achieved": round(inner_gbs, 1) if inner_gbs else None,
-                                 "frac": round(inner_gbs / HBM_PEAK_GBS, 4) if inner_gbs else None,
-                                 "bytes_per_launch": ib, "launch_ms": round(inner_ms, 5)}}
+                traffic = tr.get("bytes_per_launch")
+        names = {"fused": "k_fused (last inner stage of step n-1 + exponential Euler, ionic model, outer z "
+                          "recurrence and first inner stage of step n)",
+                 "head": "k_head (exponential Euler, ionic model, outer z recurrence, first inner stage)"}
+        roof = {"kernel": names[dom], "bound": "hbm", "achieved": round(dom_gbs, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(dom_gbs / HBM_PEAK_GBS, 4), "traffic": traffic,
+                "bytes_per_launch": db, "launch_ms": round(dom_ms, 5),
+                "kernels_ms": {k: round(v[0], 5) for k, v in prof.items()},
+                "launches": {k: v[1] for k, v in prof.items()}}
 
         mixed = None
         if not args.no_mixed:

@@ -213,13 +213,14 @@ int emrkc_stages(const emrkc_ctx *ctx, double dt, int *s, int *m, double *eta);
 int emrkc_step(emrkc_ctx *ctx, emrkc_state *state, double dt, int64_t nsteps);
 
 /* Diagnostic form of emrkc_step: advances the state the same way (same
- * kernels, same results) but launches every kernel directly on the context
- * stream with a HIP event recorded before and after it, synchronises, and
- * returns the mean duration in ms of the fused outer-stage head kernel and
- * of the inner-stage kernel, with their launch counts.  1 <= nsteps <= 1e5.
- * Output pointers may be NULL. */
-int emrkc_profile_step(emrkc_ctx *ctx, emrkc_state *state, double dt, int64_t nsteps, double *head_ms,
-                       double *inner_ms, int64_t *n_head, int64_t *n_inner);
+ * kernels, same results) as one chunk of nsteps steps, but launches every
+ * kernel directly on the context stream with a HIP event recorded before
+ * and after it, synchronises, and writes the mean duration in ms and the
+ * launch count of each kernel class: [0] outer-stage head, [1] inner stage
+ * (including the last one of a chunk), [2] fused last-inner-stage + head.
+ * 1 <= nsteps <= 1e5.  ms and counts (3 entries each) may be NULL. */
+int emrkc_profile_step(emrkc_ctx *ctx, emrkc_state *state, double dt, int64_t nsteps, double *ms,
+                       int64_t *counts);
 
 /* Statistics of the last emrkc_step call. */
 int emrkc_last_stats(const emrkc_ctx *ctx, emrkc_stats *out);

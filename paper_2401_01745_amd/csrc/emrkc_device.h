@@ -11,20 +11,32 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 namespace emrkc {
 
 // ---------------------------------------------------------------------------
-// Arithmetic policies.  FP64 uses the correctly rounded division and the
-// device libm; the FP32 policy uses the native exp2/log2 based fast paths
-// (v_exp_f32, v_log_f32, v_rcp_f32) except for expm1, whose accuracy near 0
-// carries the exponential Euler update of slow gates.
+// Arithmetic policies.  FP64 uses the device libm for exp/expm1/log and a
+// Newton-refined hardware reciprocal for divisions; the FP32 policy uses the
+// native exp2/log2/rcp based fast paths (v_exp_f32, v_log_f32, v_rcp_f32)
+// except for expm1, whose accuracy near 0 carries the exponential Euler
+// update of slow gates.
 // ---------------------------------------------------------------------------
 struct MathF64 {
   using R = double;
   static __device__ __forceinline__ R exp(R x) { return ::exp(x); }
   static __device__ __forceinline__ R expm1(R x) { return ::expm1(x); }
   static __device__ __forceinline__ R log(R x) { return ::log(x); }
-  static __device__ __forceinline__ R div(R a, R b) { return a / b; }
+  // 1/b from the hardware estimate refined by two Newton steps (within an
+  // ulp or two; every divisor in the models is positive and finite)
+  static __device__ __forceinline__ R rcp(R b) {
+    R r = __builtin_amdgcn_rcp(b);
+    R e = __builtin_fma(-b, r, 1.0);
+    r = __builtin_fma(r, e, r);
+    e = __builtin_fma(-b, r, 1.0);
+    return __builtin_fma(r, e, r);
+  }
+  static __device__ __forceinline__ R div(R a, R b) { return a * rcp(b); }
 };
 
 struct MathF32 {
@@ -32,7 +44,8 @@ struct MathF32 {
   static __device__ __forceinline__ R exp(R x) { return __expf(x); }
   static __device__ __forceinline__ R expm1(R x) { return ::expm1f(x); }
   static __device__ __forceinline__ R log(R x) { return __logf(x); }
-  static __device__ __forceinline__ R div(R a, R b) { return __fdividef(a, b); }
+  static __device__ __forceinline__ R rcp(R b) { return __builtin_amdgcn_rcpf(b); }
+  static __device__ __forceinline__ R div(R a, R b) { return a * __builtin_amdgcn_rcpf(b); }
 };
 
 // Runtime parameters of the models that have any (the linear test model).
@@ -54,7 +67,7 @@ __device__ __forceinline__ void gate_from_rates(typename M::R a, typename M::R b
   using R = typename M::R;
   R s = a + b;
   lam = -s;
-  zinf = M::div(a, s);
+  zinf = a * M::rcp(s);
 }
 
 // Classical Hodgkin-Huxley gates m, h, n (modern sign convention, rest near
@@ -83,9 +96,19 @@ template <class M>
 __device__ __forceinline__ void sigmoid_gate(typename M::R V, const SigmoidGate &g,
                                              typename M::R &lam, typename M::R &zinf) {
   using R = typename M::R;
-  R a = M::div(R(g.A), R(1) + M::exp(-(V - R(g.Va)) * R(g.inv_sa)));
-  R b = M::div(R(g.A), R(1) + M::exp((V - R(g.Vb)) * R(g.inv_sb)));
-  gate_from_rates<M>(a, b, lam, zinf);
+  // alpha = A/p, beta = A/q with p = 1 + e^{-(V-Va)/sa}, q = 1 + e^{(V-Vb)/sb}:
+  // Lambda = -A (p+q)/(p q), z_inf = q/(p+q)
+  const R p = R(1) + M::exp(-(V - R(g.Va)) * R(g.inv_sa));
+  const R q = R(1) + M::exp((V - R(g.Vb)) * R(g.inv_sb));
+  const R pq = p * q, spq = p + q;
+  if (sizeof(R) == 8) {
+    const R r = M::rcp(pq * spq);  // one reciprocal serves both (no overflow in double)
+    lam = -R(g.A) * (spq * spq) * r;
+    zinf = q * (pq * r);
+  } else {
+    lam = -R(g.A) * spq * M::rcp(pq);
+    zinf = q * M::rcp(spq);
+  }
 }
 
 constexpr double kRTF = 25.69;
@@ -288,75 +311,52 @@ struct Grid {
 __device__ __forceinline__ uint32_t mirror_lo(uint32_t i) { return i > 0 ? i - 1 : 1; }
 __device__ __forceinline__ uint32_t mirror_hi(uint32_t i, uint32_t n) { return i + 1 < n ? i + 1 : n - 2; }
 
-// (chi Cm M_L)^{-1} (A u) at node (ix, iy, iz) in difference form
-// sum_o w_o (u_{i+o} - u_i).  The zero-flux boundary of the lumped Q1
-// operator equals the interior formula with mirrored neighbours.
-__device__ __forceinline__ double grid_apply_f64(const double *__restrict__ u, const Grid &g,
-                                                 uint32_t ix, uint32_t iy, uint32_t iz) {
-  const uint32_t xm = mirror_lo(ix), xp = mirror_hi(ix, g.n0);
-  const uint32_t ym = mirror_lo(iy), yp = mirror_hi(iy, g.n1);
-  const uint32_t s1 = g.n0;
-  if (g.dim == 2) {
-    const uint32_t r0 = iy * s1, rm = ym * s1, rp = yp * s1;
-    const double uc = u[r0 + ix];
-    const double f = (u[r0 + xm] - uc) + (u[r0 + xp] - uc);
-    const double e = (u[rm + ix] - uc) + (u[rp + ix] - uc);
-    const double c = ((u[rm + xm] - uc) + (u[rm + xp] - uc)) + ((u[rp + xm] - uc) + (u[rp + xp] - uc));
-    return g.w[0] * f + g.w[1] * e + g.w[3] * c;
+// (chi Cm M_L)^{-1} (A u) at one node in difference form sum_o w_o (u_o - u_c),
+// grouped by offset class.  get(dx, dy, dz) returns the neighbour value with
+// the boundary already resolved: the zero-flux boundary of the lumped Q1
+// operator equals the interior formula with mirrored neighbours.  FP64:
+// differences and products in double.  Mixed: differences in double (V
+// carries a resting offset of about -65 mV), products and sums in float.
+template <int DIM, bool MIXED, class Get>
+__device__ __forceinline__ double grid_stencil(const double *w, Get get) {
+  using T = typename std::conditional<MIXED, float, double>::type;
+  const double uc = get(0, 0, 0);
+  auto d = [&](int dx, int dy, int dz) { return (T)(get(dx, dy, dz) - uc); };
+  if (DIM == 2) {
+    const T f = d(-1, 0, 0) + d(1, 0, 0);
+    const T e = d(0, -1, 0) + d(0, 1, 0);
+    const T c = (d(-1, -1, 0) + d(1, -1, 0)) + (d(-1, 1, 0) + d(1, 1, 0));
+    return (double)((T)w[0] * f + (T)w[1] * e + (T)w[3] * c);
   }
-  const uint32_t zm = mirror_lo(iz), zp = mirror_hi(iz, g.n2);
-  const uint32_t s2 = g.n0 * g.n1;
-  const uint32_t pc = iz * s2, pm = zm * s2, pp = zp * s2;
-  const uint32_t rc = iy * s1, rm = ym * s1, rp = yp * s1;
-  const double uc = u[pc + rc + ix];
-  auto d = [&](uint32_t idx) { return u[idx] - uc; };
-  // faces
-  const double fx = d(pc + rc + xm) + d(pc + rc + xp);
-  const double fy = d(pc + rm + ix) + d(pc + rp + ix);
-  const double fz = d(pm + rc + ix) + d(pp + rc + ix);
-  // edges
-  const double exy = (d(pc + rm + xm) + d(pc + rm + xp)) + (d(pc + rp + xm) + d(pc + rp + xp));
-  const double exz = (d(pm + rc + xm) + d(pm + rc + xp)) + (d(pp + rc + xm) + d(pp + rc + xp));
-  const double eyz = (d(pm + rm + ix) + d(pm + rp + ix)) + (d(pp + rm + ix) + d(pp + rp + ix));
-  // corners
-  const double cm = (d(pm + rm + xm) + d(pm + rm + xp)) + (d(pm + rp + xm) + d(pm + rp + xp));
-  const double cp = (d(pp + rm + xm) + d(pp + rm + xp)) + (d(pp + rp + xm) + d(pp + rp + xp));
-  return g.w[0] * fx + g.w[1] * fy + g.w[2] * fz + g.w[3] * exy + g.w[4] * exz + g.w[5] * eyz +
-         g.w[6] * (cm + cp);
+  const T fx = d(-1, 0, 0) + d(1, 0, 0);
+  const T fy = d(0, -1, 0) + d(0, 1, 0);
+  const T fz = d(0, 0, -1) + d(0, 0, 1);
+  const T exy = (d(-1, -1, 0) + d(1, -1, 0)) + (d(-1, 1, 0) + d(1, 1, 0));
+  const T exz = (d(-1, 0, -1) + d(1, 0, -1)) + (d(-1, 0, 1) + d(1, 0, 1));
+  const T eyz = (d(0, -1, -1) + d(0, 1, -1)) + (d(0, -1, 1) + d(0, 1, 1));
+  const T cm = (d(-1, -1, -1) + d(1, -1, -1)) + (d(-1, 1, -1) + d(1, 1, -1));
+  const T cp = (d(-1, -1, 1) + d(1, -1, 1)) + (d(-1, 1, 1) + d(1, 1, 1));
+  return (double)((T)w[0] * fx + (T)w[1] * fy + (T)w[2] * fz + (T)w[3] * exy + (T)w[4] * exz +
+                  (T)w[5] * eyz + (T)w[6] * (cm + cp));
 }
 
-// Mixed form: neighbour differences formed in double (V carries the
-// resting offset of about -65 mV), products and accumulation in float.
-__device__ __forceinline__ double grid_apply_mixed(const double *__restrict__ u, const Grid &g,
-                                                   uint32_t ix, uint32_t iy, uint32_t iz) {
-  const uint32_t xm = mirror_lo(ix), xp = mirror_hi(ix, g.n0);
-  const uint32_t ym = mirror_lo(iy), yp = mirror_hi(iy, g.n1);
+// The stencil on a global array at node (ix, iy, iz).
+template <int DIM, bool MIXED>
+__device__ __forceinline__ double grid_apply(const double *__restrict__ u, const Grid &g, uint32_t ix,
+                                             uint32_t iy, uint32_t iz) {
+  const uint32_t xs[3] = {mirror_lo(ix), ix, mirror_hi(ix, g.n0)};
   const uint32_t s1 = g.n0;
-  if (g.dim == 2) {
-    const uint32_t r0 = iy * s1, rm = ym * s1, rp = yp * s1;
-    const double uc = u[r0 + ix];
-    auto d = [&](uint32_t idx) { return (float)(u[idx] - uc); };
-    const float f = d(r0 + xm) + d(r0 + xp);
-    const float e = d(rm + ix) + d(rp + ix);
-    const float c = (d(rm + xm) + d(rm + xp)) + (d(rp + xm) + d(rp + xp));
-    return (double)((float)g.w[0] * f + (float)g.w[1] * e + (float)g.w[3] * c);
-  }
-  const uint32_t zm = mirror_lo(iz), zp = mirror_hi(iz, g.n2);
+  const uint32_t ys[3] = {mirror_lo(iy) * s1, iy * s1, mirror_hi(iy, g.n1) * s1};
   const uint32_t s2 = g.n0 * g.n1;
-  const uint32_t pc = iz * s2, pm = zm * s2, pp = zp * s2;
-  const uint32_t rc = iy * s1, rm = ym * s1, rp = yp * s1;
-  const double uc = u[pc + rc + ix];
-  auto d = [&](uint32_t idx) { return (float)(u[idx] - uc); };
-  const float fx = d(pc + rc + xm) + d(pc + rc + xp);
-  const float fy = d(pc + rm + ix) + d(pc + rp + ix);
-  const float fz = d(pm + rc + ix) + d(pp + rc + ix);
-  const float exy = (d(pc + rm + xm) + d(pc + rm + xp)) + (d(pc + rp + xm) + d(pc + rp + xp));
-  const float exz = (d(pm + rc + xm) + d(pm + rc + xp)) + (d(pp + rc + xm) + d(pp + rc + xp));
-  const float eyz = (d(pm + rm + ix) + d(pm + rp + ix)) + (d(pp + rm + ix) + d(pp + rp + ix));
-  const float cm = (d(pm + rm + xm) + d(pm + rm + xp)) + (d(pm + rp + xm) + d(pm + rp + xp));
-  const float cp = (d(pp + rm + xm) + d(pp + rm + xp)) + (d(pp + rp + xm) + d(pp + rp + xp));
-  return (double)((float)g.w[0] * fx + (float)g.w[1] * fy + (float)g.w[2] * fz + (float)g.w[3] * exy +
-                  (float)g.w[4] * exz + (float)g.w[5] * eyz + (float)g.w[6] * (cm + cp));
+  uint32_t zs[3] = {0, 0, 0};
+  if (DIM == 3) {
+    zs[0] = mirror_lo(iz) * s2;
+    zs[1] = iz * s2;
+    zs[2] = mirror_hi(iz, g.n2) * s2;
+  }
+  return grid_stencil<DIM, MIXED>(g.w, [&](int dx, int dy, int dz) {
+    return u[zs[dz + 1] + ys[dy + 1] + xs[dx + 1]];
+  });
 }
 
 // splitmix64 (Steele, Lea and Flood, 2014): output number i (0-based) of

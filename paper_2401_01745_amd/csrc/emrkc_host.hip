@@ -18,7 +18,8 @@
 
 using namespace emrkc;
 
-#define EMRKC_EAGER_FLAG 2u  // internal: never capture graphs (testing)
+#define EMRKC_EAGER_FLAG 2u     // internal: never capture graphs (testing)
+#define EMRKC_NO_FUSE_FLAG 4u   // internal: separate tail and head kernels (testing)
 
 struct GraphKey {
   int s, m, chunk;
@@ -57,8 +58,10 @@ struct emrkc_ctx {
   double *d_ell_w64 = nullptr;
   float *d_ell_w32 = nullptr;
   double *d_V1 = nullptr;
-  double *d_U[2] = {nullptr, nullptr};
+  double *d_U[3] = {nullptr, nullptr, nullptr};
   void *d_SV = nullptr;
+  void *d_SV2 = nullptr;
+  bool use_fused = true;
   void *d_z1 = nullptr;
   Clock *d_clock = nullptr;
   double *d_partials = nullptr;
@@ -256,7 +259,7 @@ static void free_ctx(emrkc_ctx *c) {
   for (auto &kv : c->graphs) (void)hipGraphExecDestroy(kv.second);
   c->graphs.clear();
   void *ptrs[] = {c->d_mask, c->d_ell_col, c->d_ell_w64, c->d_ell_w32, c->d_V1, c->d_U[0], c->d_U[1],
-                  c->d_SV,   c->d_z1,      c->d_clock,   c->d_partials, c->d_result, c->d_flag,
+                  c->d_U[2], c->d_SV, c->d_SV2,   c->d_z1,      c->d_clock,   c->d_partials, c->d_result, c->d_flag,
                   c->d_vF[0], c->d_vF[1], c->d_vS[0], c->d_vS[1], c->d_zV};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
@@ -325,6 +328,7 @@ extern "C" int emrkc_create(const emrkc_mesh *mesh, const emrkc_conductivity *co
   c->nv = 1 + c->ng + c->ns;
   c->mixed = p->precision == EMRKC_MIXED32;
   c->flags = p->flags;
+  c->use_fused = getenv("EMRKC_NO_FUSE") == nullptr && (p->flags & EMRKC_NO_FUSE_FLAG) == 0;
   c->chi = p->chi;
   c->Cm = p->Cm;
   c->eps = p->eps;
@@ -373,7 +377,8 @@ extern "C" int emrkc_create(const emrkc_mesh *mesh, const emrkc_conductivity *co
     const size_t vb = sizeof(double) * (size_t)N;
     const size_t svb = (c->mixed ? sizeof(float) : sizeof(double)) * (size_t)N;
     if ((rc = dalloc(c, (void **)&c->d_V1, vb)) || (rc = dalloc(c, (void **)&c->d_U[0], vb)) ||
-        (rc = dalloc(c, (void **)&c->d_U[1], vb)) || (rc = dalloc(c, &c->d_SV, svb)) ||
+        (rc = dalloc(c, (void **)&c->d_U[1], vb)) || (rc = dalloc(c, (void **)&c->d_U[2], vb)) ||
+        (rc = dalloc(c, &c->d_SV, svb)) || (rc = dalloc(c, &c->d_SV2, svb)) ||
         (rc = dalloc(c, (void **)&c->d_clock, sizeof(Clock))) ||
         (rc = dalloc(c, (void **)&c->d_result, 2 * sizeof(double))) ||
         (rc = dalloc(c, (void **)&c->d_flag, sizeof(int))))
@@ -481,7 +486,7 @@ extern "C" int emrkc_last_stats(const emrkc_ctx *c, emrkc_stats *out) {
 }
 
 // ---------------------------------------------------------------------------
-// One emRKC step as a sequence of launches (see the buffer plan below)
+// emRKC steps as sequences of launches
 // ---------------------------------------------------------------------------
 struct StepPlan {
   int s, m;
@@ -490,6 +495,57 @@ struct StepPlan {
   std::vector<double> mui, nui, kai, cci;  // inner, index k
 };
 
+struct KernelTimer {
+  std::vector<hipEvent_t> ev;  // pairs (start, stop)
+  std::vector<int> cls;        // 0 = head, 1 = inner, 2 = fused
+  size_t used = 0;
+  int record(emrkc_ctx *c, hipStream_t s, int k, bool start);
+};
+
+#define TIMED(cls, call)                                                  \
+  do {                                                                    \
+    if (tm && tm->record(c, strm, (cls), true)) return EMRKC_EHIP;        \
+    HIP_TRY(c, call);                                                     \
+    if (tm && tm->record(c, strm, (cls), false)) return EMRKC_EHIP;       \
+  } while (0)
+
+static HeadArgs make_head(emrkc_ctx *c, const StepPlan &P, double dt, int j, int step_off) {
+  HeadArgs h{};
+  h.SV = c->d_SV;
+  h.clock = c->d_clock;
+  h.step_off = step_off;
+  h.stim = stim_args(c);
+  h.mp = c->mp;
+  h.dt = dt;
+  h.eta = P.eta;
+  h.inv_eta = 1.0 / P.eta;
+  h.Cm = c->Cm;
+  h.c_prev = P.cc[j - 1];
+  h.mu_dt = P.mu[j] * dt;
+  h.nu = P.nu[j];
+  h.kappa = P.ka[j];
+  h.mu1_eta = P.mui[1] * P.eta;
+  h.cm_eta = P.cci[P.m] * P.eta;
+  h.j1 = j == 1;
+  h.m_is_one = P.m == 1;
+  return h;
+}
+
+static TailArgs make_stage(const StepPlan &P, double dt, int j, int k) {
+  TailArgs t{};
+  t.nu = P.nui[k];
+  t.kappa = P.kai[k];
+  t.mu_eta = P.mui[k] * P.eta;
+  t.inv_eta = 1.0 / P.eta;
+  t.mu_dt = P.mu[j] * dt;
+  t.nu_o = P.nu[j];
+  t.kappa_o = P.ka[j];
+  t.j1 = j == 1;
+  return t;
+}
+
+// One step, any (s, m), with separate head and inner kernels.
+//
 // V_j lives in X[j % 2] for j < s (X[0] = the caller's V, X[1] a library
 // buffer): V_j may overwrite V_{j-2} because that value is only read at the
 // same node.  The last stage writes X[0] unless m == 1 and V_{s-1} is in
@@ -497,15 +553,9 @@ struct StepPlan {
 // overwrite it, and the step ends with a copy.  z_j follows the same rule
 // with Z[0] = the caller's z and always ends in Z[0] (z is pointwise).
 // Inner values u_k (k >= 1) rotate through U[(k-1) % 2]; u_0 = V_{j-1}.
-struct KernelTimer {
-  std::vector<hipEvent_t> ev;  // pairs (start, stop)
-  std::vector<int> cls;        // 0 = head, 1 = inner, 2 = other
-  size_t used = 0;
-  int record(emrkc_ctx *c, hipStream_t s, int k, bool start);
-};
-
-static int enqueue_step(emrkc_ctx *c, const emrkc_state *st, const StepPlan &P, double dt, hipStream_t strm,
-                        KernelTimer *tm = nullptr) {
+// The last kernel of the chunk advances the device clock by tick_by.
+static int enqueue_step_generic(emrkc_ctx *c, const emrkc_state *st, const StepPlan &P, double dt, int step_off,
+                                int64_t tick_by, hipStream_t strm, KernelTimer *tm) {
   const int s = P.s, m = P.m;
   double *X[2] = {(double *)st->V, c->d_V1};
   void *Z[2] = {st->z, c->d_z1};
@@ -517,58 +567,110 @@ static int enqueue_step(emrkc_ctx *c, const emrkc_state *st, const StepPlan &P, 
     double *Vin = X[vidx(j - 1)];
     double *Vin2 = j >= 2 ? X[vidx(j - 2)] : nullptr;
     double *Vdst = (lastj && final_copy) ? X[1] : X[vidx(j)];
-    HeadArgs h{};
+    HeadArgs h = make_head(c, P, dt, j, step_off);
     h.Vin = Vin;
     h.Vin2 = Vin2;
     h.zin = Z[zidx(j - 1)];
     h.zin2 = j >= 2 ? Z[zidx(j - 2)] : nullptr;
     h.zout = Z[zidx(j)];
-    h.SV = c->d_SV;
     h.uout = m >= 2 ? c->d_U[0] : Vdst;
-    h.clock = c->d_clock;
-    h.stim = stim_args(c);
-    h.mp = c->mp;
-    h.dt = dt;
-    h.eta = P.eta;
-    h.inv_eta = 1.0 / P.eta;
-    h.Cm = c->Cm;
-    h.c_prev = P.cc[j - 1];
-    h.mu_dt = P.mu[j] * dt;
-    h.nu = P.nu[j];
-    h.kappa = P.ka[j];
-    h.mu1_eta = P.mui[1] * P.eta;
-    h.cm_eta = P.cci[m] * P.eta;
-    h.j1 = j == 1;
-    h.m_is_one = m == 1;
-    if (tm && tm->record(c, strm, 0, true)) return EMRKC_EHIP;
-    HIP_TRY(c, launch_head(c->model, c->mixed, c->mesh, h, strm));
-    if (tm && tm->record(c, strm, 0, false)) return EMRKC_EHIP;
+    TIMED(0, launch_head(c->model, c->mixed, c->mesh, h, strm));
     for (int k = 2; k <= m; ++k) {
       InnerArgs a{};
-      a.uprev = c->d_U[(k - 2) % 2];
-      a.uprev2 = k == 2 ? Vin : c->d_U[(k - 3) % 2];
-      a.SV = c->d_SV;
+      a.t = make_stage(P, dt, j, k);
+      a.t.uprev = c->d_U[(k - 2) % 2];
+      a.t.uprev2 = k == 2 ? Vin : c->d_U[(k - 3) % 2];
+      a.t.SV = c->d_SV;
+      a.t.Vin = Vin;
+      a.t.Vin2 = Vin2;
       a.last = k == m;
       a.out = a.last ? Vdst : c->d_U[(k - 1) % 2];
-      a.nu = P.nui[k];
-      a.kappa = P.kai[k];
-      a.mu_eta = P.mui[k] * P.eta;
-      a.Vin = Vin;
-      a.Vin2 = Vin2;
-      a.inv_eta = 1.0 / P.eta;
-      a.mu_dt = P.mu[j] * dt;
-      a.nu_o = P.nu[j];
-      a.kappa_o = P.ka[j];
-      a.j1 = j == 1;
-      a.tick = (lastj && k == m) ? c->d_clock : nullptr;
-      if (tm && tm->record(c, strm, 1, true)) return EMRKC_EHIP;
-      HIP_TRY(c, launch_inner(c->mixed, c->mesh, a, strm));
-      if (tm && tm->record(c, strm, 1, false)) return EMRKC_EHIP;
+      a.tick = (lastj && k == m && tick_by > 0) ? c->d_clock : nullptr;
+      a.tick_by = tick_by;
+      TIMED(1, launch_inner(c->mixed, c->mesh, a, strm));
     }
   }
-  if (m == 1) {
-    // copy the final V when it had to go to X[1]; advance the step counter
-    HIP_TRY(c, launch_copy_tick(final_copy ? X[1] : nullptr, X[0], (uint32_t)c->N, c->d_clock, strm));
+  if (m == 1 && (final_copy || tick_by > 0)) {
+    HIP_TRY(c, launch_copy_tick(final_copy ? X[1] : nullptr, X[0], (uint32_t)c->N, tick_by > 0 ? c->d_clock : nullptr,
+                                tick_by, strm));
+  }
+  return EMRKC_OK;
+}
+
+// L steps with s == 1 and m >= 2 on a grid: head of step 0, then for each
+// later step one fused kernel (last inner stage of the previous step + head
+// of this step), and the last inner stage of step L-1 on its own.  Within
+// the chunk V^n alternates X[n % 2] (the fused kernel reads V^{n-1} of
+// neighbouring tiles while writing V^n), S_V alternates SV[n % 2], and
+// u_k of step n lives in B[(b_n + k - 1) % 3] with b_{n+1} = b_n + m - 1, so
+// the values the fused kernel reads (u_{m-1}, u_{m-2} of step n-1) never
+// share a buffer with the u_1 it writes.  V^L ends in X[0].
+static int enqueue_chunk_fused(emrkc_ctx *c, const emrkc_state *st, const StepPlan &P, double dt, int L,
+                               hipStream_t strm, KernelTimer *tm) {
+  const int m = P.m;
+  double *X[2] = {(double *)st->V, c->d_V1};
+  double *B[3] = {c->d_U[0], c->d_U[1], c->d_U[2]};
+  void *S[2] = {c->d_SV, c->d_SV2};
+  int base = 0;
+  auto inner_range = [&](int n, int b) -> int {
+    for (int k = 2; k <= m - 1; ++k) {
+      InnerArgs a{};
+      a.t = make_stage(P, dt, 1, k);
+      a.t.uprev = B[(b + k - 2) % 3];
+      a.t.uprev2 = k == 2 ? X[n % 2] : B[(b + k - 3) % 3];
+      a.t.SV = S[n % 2];
+      a.last = 0;
+      a.out = B[(b + k - 1) % 3];
+      TIMED(1, launch_inner(c->mixed, c->mesh, a, strm));
+    }
+    return EMRKC_OK;
+  };
+  auto tail_of = [&](int n, int b) {  // last inner stage of step n
+    TailArgs t = make_stage(P, dt, 1, m);
+    t.uprev = B[(b + m - 2) % 3];
+    t.uprev2 = m == 2 ? X[n % 2] : B[(b + m - 3) % 3];
+    t.SV = S[n % 2];
+    t.Vin = X[n % 2];
+    t.Vin2 = nullptr;
+    return t;
+  };
+  HeadArgs h = make_head(c, P, dt, 1, 0);
+  h.Vin = X[0];
+  h.zin = h.zout = st->z;
+  h.SV = S[0];
+  h.uout = B[base];
+  TIMED(0, launch_head(c->model, c->mixed, c->mesh, h, strm));
+  int rc = inner_range(0, base);
+  if (rc != EMRKC_OK) return rc;
+  for (int n = 1; n < L; ++n) {
+    FusedArgs f{};
+    f.t = tail_of(n - 1, base);
+    f.Vout = X[n % 2];
+    base = (base + m - 1) % 3;
+    f.h = make_head(c, P, dt, 1, n);
+    f.h.zin = f.h.zout = st->z;
+    f.h.SV = S[n % 2];
+    f.h.uout = B[base];
+    TIMED(2, launch_fused(c->model, c->mixed, c->mesh, f, strm));
+    if ((rc = inner_range(n, base)) != EMRKC_OK) return rc;
+  }
+  InnerArgs a{};
+  a.t = tail_of(L - 1, base);
+  a.last = 1;
+  a.out = X[0];
+  a.tick = c->d_clock;
+  a.tick_by = L;
+  TIMED(1, launch_inner(c->mixed, c->mesh, a, strm));
+  return EMRKC_OK;
+}
+
+static int enqueue_chunk(emrkc_ctx *c, const emrkc_state *st, const StepPlan &P, double dt, int L, hipStream_t strm,
+                         KernelTimer *tm = nullptr) {
+  if (c->use_fused && P.s == 1 && P.m >= 2 && fused_supported(c->mesh))
+    return enqueue_chunk_fused(c, st, P, dt, L, strm, tm);
+  for (int n = 0; n < L; ++n) {
+    int rc = enqueue_step_generic(c, st, P, dt, n, n == L - 1 ? L : 0, strm, tm);
+    if (rc != EMRKC_OK) return rc;
   }
   return EMRKC_OK;
 }
@@ -594,58 +696,58 @@ extern "C" int emrkc_step(emrkc_ctx *c, emrkc_state *st, double dt, int64_t nste
 
   HIP_TRY(c, launch_clock_set(c->d_clock, st->step, st->t0, c->stream));
   const bool eager = (c->flags & EMRKC_EAGER_FLAG) != 0 || getenv("EMRKC_EAGER") != nullptr;
-  int64_t done = 0;
+  // chunks of up to 32 steps; with graphs every chunk of one length is one
+  // captured graph replayed (the step time comes from the device clock)
+  const int chunk = (int)std::min<int64_t>(nsteps, 32);
+  const int64_t full = nsteps / chunk;
+  const int rem = (int)(nsteps - full * chunk);
   bool used_graph = false;
-  if (!eager && nsteps >= 2) {
-    // replay chunks of steps from a captured graph; the per-step time comes
-    // from the device clock, so every chunk is the same graph
-    const int chunk = (int)std::min<int64_t>(nsteps, 32);
-    for (int pass = 0; pass < 2 && done < nsteps; ++pass) {
-      const int len = pass == 0 ? chunk : (int)(nsteps - done);
-      const int64_t reps = pass == 0 ? (nsteps / chunk) : 1;
-      if (len <= 0) continue;
-      uint64_t dtb;
-      memcpy(&dtb, &dt, sizeof dtb);
-      GraphKey key{P.s, P.m, len, dtb, st->V, st->z};
-      hipGraphExec_t exec = nullptr;
-      auto it = c->graphs.find(key);
-      if (it != c->graphs.end()) {
-        exec = it->second;
-      } else {
-        hipGraph_t graph = nullptr;
-        HIP_TRY(c, hipStreamBeginCapture(c->capture, hipStreamCaptureModeThreadLocal));
-        int erc = EMRKC_OK;
-        for (int k = 0; k < len && erc == EMRKC_OK; ++k) erc = enqueue_step(c, st, P, dt, c->capture);
-        hipError_t ee = hipStreamEndCapture(c->capture, &graph);
-        if (erc != EMRKC_OK) {
-          if (graph) (void)hipGraphDestroy(graph);
-          return erc;
-        }
-        if (ee != hipSuccess) return fail(c, EMRKC_EHIP, "graph capture failed: %s", hipGetErrorString(ee));
-        ee = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
-        (void)hipGraphDestroy(graph);
-        if (ee != hipSuccess) return fail(c, EMRKC_EHIP, "graph instantiation failed: %s", hipGetErrorString(ee));
-        if (c->graphs.size() >= 64) {
-          for (auto &kv : c->graphs) (void)hipGraphExecDestroy(kv.second);
-          c->graphs.clear();
-        }
-        c->graphs[key] = exec;
-      }
-      for (int64_t r = 0; r < reps; ++r) HIP_TRY(c, hipGraphLaunch(exec, c->stream));
-      done += (int64_t)len * reps;
-      used_graph = true;
+  for (int pass = 0; pass < 2; ++pass) {
+    const int len = pass == 0 ? chunk : rem;
+    const int64_t reps = pass == 0 ? full : (rem > 0 ? 1 : 0);
+    if (len <= 0 || reps <= 0) continue;
+    if (eager) {
+      for (int64_t r = 0; r < reps; ++r)
+        if ((rc = enqueue_chunk(c, st, P, dt, len, c->stream)) != EMRKC_OK) return rc;
+      continue;
     }
-  }
-  for (; done < nsteps; ++done) {
-    rc = enqueue_step(c, st, P, dt, c->stream);
-    if (rc != EMRKC_OK) return rc;
+    uint64_t dtb;
+    memcpy(&dtb, &dt, sizeof dtb);
+    GraphKey key{P.s, P.m, len, dtb, st->V, st->z};
+    hipGraphExec_t exec = nullptr;
+    auto it = c->graphs.find(key);
+    if (it != c->graphs.end()) {
+      exec = it->second;
+    } else {
+      hipGraph_t graph = nullptr;
+      HIP_TRY(c, hipStreamBeginCapture(c->capture, hipStreamCaptureModeThreadLocal));
+      const int erc = enqueue_chunk(c, st, P, dt, len, c->capture);
+      hipError_t ee = hipStreamEndCapture(c->capture, &graph);
+      if (erc != EMRKC_OK) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return erc;
+      }
+      if (ee != hipSuccess) return fail(c, EMRKC_EHIP, "graph capture failed: %s", hipGetErrorString(ee));
+      ee = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(graph);
+      if (ee != hipSuccess) return fail(c, EMRKC_EHIP, "graph instantiation failed: %s", hipGetErrorString(ee));
+      if (c->graphs.size() >= 64) {
+        for (auto &kv : c->graphs) (void)hipGraphExecDestroy(kv.second);
+        c->graphs.clear();
+      }
+      c->graphs[key] = exec;
+    }
+    for (int64_t r = 0; r < reps; ++r) HIP_TRY(c, hipGraphLaunch(exec, c->stream));
+    used_graph = true;
   }
   st->step += nsteps;
   st->t = state_time(st->t0, st->step, dt);
   c->last.s = P.s;
   c->last.m = P.m;
   c->last.eta = P.eta;
-  c->last.kernels_per_step = (int64_t)P.s * P.m + (P.m == 1 ? 1 : 0);
+  c->last.kernels_per_step = (c->use_fused && P.s == 1 && P.m >= 2 && fused_supported(c->mesh))
+                                 ? (int64_t)P.m - 1
+                                 : (int64_t)P.s * P.m + (P.m == 1 ? 1 : 0);
   c->last.used_graph = used_graph ? 1 : 0;
   if (c->flags & EMRKC_CHECK_FINITE) {
     HIP_TRY(c, hipMemsetAsync(c->d_flag, 0, sizeof(int), c->stream));
@@ -672,8 +774,8 @@ int KernelTimer::record(emrkc_ctx *c, hipStream_t s, int k, bool start) {
   return EMRKC_OK;
 }
 
-extern "C" int emrkc_profile_step(emrkc_ctx *c, emrkc_state *st, double dt, int64_t nsteps, double *head_ms,
-                                  double *inner_ms, int64_t *n_head, int64_t *n_inner) {
+extern "C" int emrkc_profile_step(emrkc_ctx *c, emrkc_state *st, double dt, int64_t nsteps, double *ms,
+                                  int64_t *counts) {
   if (c == nullptr) return EMRKC_EINVAL;
   if (!state_ok(c, st)) return fail(c, EMRKC_EINVAL, "state buffers missing");
   if (!(dt > 0) || !isfinite(dt) || nsteps < 1 || nsteps > 100000) return fail(c, EMRKC_EINVAL, "invalid dt or nsteps");
@@ -686,19 +788,19 @@ extern "C" int emrkc_profile_step(emrkc_ctx *c, emrkc_state *st, double dt, int6
   if (P.s >= 2 && (rc = ensure_z1(c)) != EMRKC_OK) return rc;
   HIP_TRY(c, launch_clock_set(c->d_clock, st->step, st->t0, c->stream));
   KernelTimer tm;
-  for (int64_t n = 0; n < nsteps && rc == EMRKC_OK; ++n) rc = enqueue_step(c, st, P, dt, c->stream, &tm);
+  rc = enqueue_chunk(c, st, P, dt, (int)nsteps, c->stream, &tm);
   hipError_t e = hipStreamSynchronize(c->stream);
-  double sum[2] = {0, 0};
-  int64_t cnt[2] = {0, 0};
+  double sum[3] = {0, 0, 0};
+  int64_t cnt[3] = {0, 0, 0};
   if (rc == EMRKC_OK && e == hipSuccess) {
     for (size_t k = 0; k + 1 < tm.used; k += 2) {
-      float ms = 0;
-      if (hipEventElapsedTime(&ms, tm.ev[k], tm.ev[k + 1]) != hipSuccess) {
+      float t_ms = 0;
+      if (hipEventElapsedTime(&t_ms, tm.ev[k], tm.ev[k + 1]) != hipSuccess) {
         rc = fail(c, EMRKC_EHIP, "hipEventElapsedTime failed");
         break;
       }
       const int cl = tm.cls[k / 2];
-      sum[cl] += ms;
+      sum[cl] += t_ms;
       cnt[cl] += 1;
     }
   }
@@ -707,10 +809,10 @@ extern "C" int emrkc_profile_step(emrkc_ctx *c, emrkc_state *st, double dt, int6
   if (rc != EMRKC_OK) return rc;
   st->step += nsteps;
   st->t = state_time(st->t0, st->step, dt);
-  if (head_ms) *head_ms = cnt[0] ? sum[0] / cnt[0] : 0.0;
-  if (inner_ms) *inner_ms = cnt[1] ? sum[1] / cnt[1] : 0.0;
-  if (n_head) *n_head = cnt[0];
-  if (n_inner) *n_inner = cnt[1];
+  for (int k = 0; k < 3; ++k) {
+    if (ms) ms[k] = cnt[k] ? sum[k] / cnt[k] : 0.0;
+    if (counts) counts[k] = cnt[k];
+  }
   return EMRKC_OK;
 }
 

@@ -50,7 +50,8 @@ struct HeadArgs {
   void *zout;           // z_j
   void *SV;             // S_V = Cm^{-1}(I_stim - I_ion) at y_E (m >= 2)
   double *uout;         // u_1 (m >= 2) or V_j (m == 1)
-  const Clock *clock;
+  const Clock *clock;   // chunk base step and t0
+  int step_off;         // step index within the chunk
   StimArgs stim;
   ModelParams mp;
   double dt, eta, inv_eta, Cm;
@@ -62,20 +63,33 @@ struct HeadArgs {
   int m_is_one;
 };
 
-// Inner stage k >= 2 of the averaged-force iteration; at k == m it also
-// applies the outer recurrence of V.
-struct InnerArgs {
-  const double *uprev;   // u_{k-1} (read with neighbours)
-  const double *uprev2;  // u_{k-2}
+// Last inner stage k = m of stage j together with the outer V update.
+struct TailArgs {
+  const double *uprev;   // u_{m-1} (read with neighbours)
+  const double *uprev2;  // u_{m-2} (u_0 = V_{j-1} when m == 2)
   const void *SV;
-  double *out;           // u_k, or V_j when last
-  double nu, kappa, mu_eta;
-  int last;
   const double *Vin;     // V_{j-1}
-  const double *Vin2;    // V_{j-2}
-  double inv_eta, mu_dt, nu_o, kappa_o;
+  const double *Vin2;    // V_{j-2} (j >= 2)
+  double nu, kappa, mu_eta;      // inner coefficients of stage m
+  double inv_eta, mu_dt, nu_o, kappa_o;  // outer coefficients of stage j
   int j1;
-  Clock *tick;           // when non-null, block 0 advances the step counter
+};
+
+// Inner stage k >= 2; at k == m (last) it also applies the outer V update.
+struct InnerArgs {
+  TailArgs t;            // uprev, uprev2, SV and the inner coefficients are used for every k
+  double *out;           // u_k, or V_j when last
+  int last;
+  Clock *tick;           // when non-null, block 0 adds tick_by to the chunk base step
+  int64_t tick_by;
+};
+
+// Tail of the previous step (on the tile plus a one-node halo, staged in
+// LDS) fused with the head of the next step (s == 1, m >= 2, grids).
+struct FusedArgs {
+  TailArgs t;
+  double *Vout;          // V^n (tile nodes)
+  HeadArgs h;            // h.Vin unused: V comes from the tail
 };
 
 // ---- launchers (emrkc_kernels.hip) ----------------------------------------
@@ -83,8 +97,11 @@ hipError_t launch_init_state(int model, bool mixed, uint32_t N, double *V, void 
                              hipStream_t st);
 hipError_t launch_head(int model, bool mixed, const Mesh &mesh, const HeadArgs &a, hipStream_t st);
 hipError_t launch_inner(bool mixed, const Mesh &mesh, const InnerArgs &a, hipStream_t st);
+hipError_t launch_fused(int model, bool mixed, const Mesh &mesh, const FusedArgs &a, hipStream_t st);
+bool fused_supported(const Mesh &mesh);
 hipError_t launch_clock_set(Clock *c, int64_t step, double t0, hipStream_t st);
-hipError_t launch_copy_tick(const double *src, double *dst, uint32_t N, Clock *tick, hipStream_t st);
+hipError_t launch_copy_tick(const double *src, double *dst, uint32_t N, Clock *tick, int64_t tick_by,
+                            hipStream_t st);
 hipError_t launch_apply_diffusion(bool mixed, const Mesh &mesh, const double *V, double *out,
                                   hipStream_t st);
 hipError_t launch_eval_rhs_slow(int model, bool mixed, uint32_t N, const double *V, const void *z,

@@ -12,11 +12,11 @@ constexpr int kBlock = 256;
 template <bool MIXED>
 using MathOf = typename std::conditional<MIXED, MathF32, MathF64>::type;
 
-// Stage time t_n + c_{j-1} dt with t_n = t0 + n dt, without contraction so
-// that host and device obtain the same double.
-__device__ __forceinline__ double stage_time(const Clock *c, double dt, double c_prev) {
+// Stage time t_n + c_{j-1} dt with t_n = t0 + n dt, n = chunk base + offset,
+// without contraction so that host and device obtain the same double.
+__device__ __forceinline__ double stage_time(const Clock *c, int step_off, double dt, double c_prev) {
 #pragma clang fp contract(off)
-  const double tn = c->t0 + (double)c->step * dt;
+  const double tn = c->t0 + (double)(c->step + step_off) * dt;
   return tn + c_prev * dt;
 }
 
@@ -37,13 +37,7 @@ __device__ __forceinline__ void grid_coords(const Grid &g, uint32_t i, uint32_t 
 }
 
 template <bool MIXED>
-__device__ __forceinline__ double apply_op(const Mesh &mesh, const double *__restrict__ u, uint32_t i) {
-  if (mesh.kind == kGrid) {
-    uint32_t ix, iy, iz;
-    grid_coords(mesh.grid, i, ix, iy, iz);
-    return MIXED ? grid_apply_mixed(u, mesh.grid, ix, iy, iz) : grid_apply_f64(u, mesh.grid, ix, iy, iz);
-  }
-  const Ell &e = mesh.ell;
+__device__ __forceinline__ double ell_apply(const Ell &e, const double *__restrict__ u, uint32_t i) {
   const double uc = u[i];
   if (MIXED) {
     float acc = 0.0f;
@@ -59,6 +53,17 @@ __device__ __forceinline__ double apply_op(const Mesh &mesh, const double *__res
     acc += e.w64[(size_t)k * e.N + i] * (u[c] - uc);
   }
   return acc;
+}
+
+template <bool MIXED>
+__device__ __forceinline__ double apply_op(const Mesh &mesh, const double *__restrict__ u, uint32_t i) {
+  if (mesh.kind == kGrid) {
+    uint32_t ix, iy, iz;
+    grid_coords(mesh.grid, i, ix, iy, iz);
+    return mesh.grid.dim == 3 ? grid_apply<3, MIXED>(u, mesh.grid, ix, iy, iz)
+                              : grid_apply<2, MIXED>(u, mesh.grid, ix, iy, iz);
+  }
+  return ell_apply<MIXED>(mesh.ell, u, i);
 }
 
 // ---------------------------------------------------------------------------
@@ -83,21 +88,17 @@ __global__ __launch_bounds__(kBlock) void k_init_state(uint32_t N, double *V, vo
 }
 
 // ---------------------------------------------------------------------------
-// Fused outer-stage head
+// Outer-stage head at one node, given V_{j-1} and f_F(V_{j-1}) there
 // ---------------------------------------------------------------------------
 template <template <class> class Model, bool MIXED>
-__global__ __launch_bounds__(kBlock) void k_head(HeadArgs a, Mesh mesh) {
+__device__ __forceinline__ void head_node(const HeadArgs &a, uint32_t N, uint32_t i, double V, double FV) {
   using M = MathOf<MIXED>;
   using R = typename M::R;
   using Mod = Model<M>;
   constexpr int NG = Mod::NG, NS = Mod::NS, NZ = NG + NS;
-  const uint32_t N = mesh.kind == kGrid ? mesh.grid.N : mesh.ell.N;
-  const uint32_t i = node_index();
-  if (i >= N) return;
 
-  const double tj = stage_time(a.clock, a.dt, a.c_prev);
+  const double tj = stage_time(a.clock, a.step_off, a.dt, a.c_prev);
   const double Is = stimulus(a.stim, i, tj);
-  const double V = a.Vin[i];
 
   const R *zin = (const R *)a.zin;
   R z[NZ];
@@ -144,7 +145,6 @@ __global__ __launch_bounds__(kBlock) void k_head(HeadArgs a, Mesh mesh) {
   }
 
   // first inner stage u_1 = u_0 + mu'_1 eta (f_F(u_0) + S_V), u_0 = V
-  const double FV = apply_op<MIXED>(mesh, a.Vin, i);
   const double u1 = V + a.mu1_eta * (FV + SV);
   if (a.m_is_one) {
     const double fbarV = (u1 - V) * a.inv_eta;
@@ -158,25 +158,99 @@ __global__ __launch_bounds__(kBlock) void k_head(HeadArgs a, Mesh mesh) {
   }
 }
 
+template <template <class> class Model, bool MIXED>
+__global__ __launch_bounds__(kBlock) void k_head(HeadArgs a, Mesh mesh) {
+  const uint32_t N = mesh.kind == kGrid ? mesh.grid.N : mesh.ell.N;
+  const uint32_t i = node_index();
+  if (i >= N) return;
+  const double V = a.Vin[i];
+  const double FV = apply_op<MIXED>(mesh, a.Vin, i);
+  head_node<Model, MIXED>(a, N, i, V, FV);
+}
+
 // ---------------------------------------------------------------------------
-// Inner stage k >= 2 (and the outer V update at k == m)
+// Inner stages
 // ---------------------------------------------------------------------------
+__device__ __forceinline__ double load_sv(const void *SV, bool mixed, uint32_t i) {
+  return mixed ? (double)((const float *)SV)[i] : ((const double *)SV)[i];
+}
+
+// u_k = nu u_{k-1} + kappa u_{k-2} + mu eta (f_F(u_{k-1}) + S_V)
+__device__ __forceinline__ double inner_value(const TailArgs &t, double Fu, double sv, uint32_t i) {
+  return t.nu * t.uprev[i] + t.kappa * t.uprev2[i] + t.mu_eta * (Fu + sv);
+}
+
+// outer V update from the last inner value: V_j = nu V_{j-1} + kappa V_{j-2}
+// + mu dt (u_m - V_{j-1})/eta
+__device__ __forceinline__ double tail_from_um(const TailArgs &t, double um, uint32_t i) {
+  const double Vp = t.Vin[i];
+  const double fbar = (um - Vp) * t.inv_eta;
+  return t.j1 ? Vp + t.mu_dt * fbar : t.nu_o * Vp + t.kappa_o * t.Vin2[i] + t.mu_dt * fbar;
+}
+
 template <bool MIXED>
 __global__ __launch_bounds__(kBlock) void k_inner(InnerArgs a, Mesh mesh) {
   const uint32_t N = mesh.kind == kGrid ? mesh.grid.N : mesh.ell.N;
   const uint32_t i = node_index();
-  if (a.tick != nullptr && blockIdx.x == 0 && threadIdx.x == 0) a.tick->step += 1;
+  if (a.tick != nullptr && blockIdx.x == 0 && threadIdx.x == 0) a.tick->step += a.tick_by;
   if (i >= N) return;
-  const double Fu = apply_op<MIXED>(mesh, a.uprev, i);
-  const double sv = MIXED ? (double)((const float *)a.SV)[i] : ((const double *)a.SV)[i];
-  const double uk = a.nu * a.uprev[i] + a.kappa * a.uprev2[i] + a.mu_eta * (Fu + sv);
-  if (a.last) {
-    const double Vp = a.Vin[i];
-    const double fbar = (uk - Vp) * a.inv_eta;
-    a.out[i] = a.j1 ? Vp + a.mu_dt * fbar : a.nu_o * Vp + a.kappa_o * a.Vin2[i] + a.mu_dt * fbar;
-  } else {
-    a.out[i] = uk;
+  const double Fu = apply_op<MIXED>(mesh, a.t.uprev, i);
+  const double uk = inner_value(a.t, Fu, load_sv(a.t.SV, MIXED, i), i);
+  a.out[i] = a.last ? tail_from_um(a.t, uk, i) : uk;
+}
+
+// ---------------------------------------------------------------------------
+// Fused tail + head on a structured grid.  Each block owns a TX x TY x TZ
+// tile; phase 1 computes V^n on the tile plus a one-node halo (mirrored at
+// the domain boundary) into LDS, phase 2 runs the head of the next step on
+// the tile's own nodes with f_F(V^n) taken from LDS.  The arithmetic is the
+// same as k_inner (last) followed by k_head.
+// ---------------------------------------------------------------------------
+template <int DIM>
+struct Tile {
+  static constexpr int TX = DIM == 3 ? 16 : 64, TY = 4, TZ = DIM == 3 ? 4 : 1;
+  static constexpr int SX = TX + 2, SY = TY + 2, SZ = DIM == 3 ? TZ + 2 : 1;
+  static constexpr int NS = SX * SY * SZ;
+};
+
+__device__ __forceinline__ uint32_t mirror_any(int c, uint32_t n) {
+  int r = c < 0 ? -c : (c >= (int)n ? 2 * ((int)n - 1) - c : c);
+  r = r < 0 ? 0 : (r > (int)n - 1 ? (int)n - 1 : r);
+  return (uint32_t)r;
+}
+
+template <template <class> class Model, bool MIXED, int DIM>
+__global__ __launch_bounds__(kBlock) void k_fused(FusedArgs a, Grid g, uint32_t ntx, uint32_t nty) {
+  using T = Tile<DIM>;
+  __shared__ double sV[T::NS];
+  const uint32_t b = xcd_block(blockIdx.x, gridDim.x);
+  const uint32_t bx = b % ntx, byz = b / ntx;
+  const uint32_t by = byz % nty, bz = byz / nty;
+  const int x0 = (int)(bx * T::TX), y0 = (int)(by * T::TY), z0 = (int)(bz * T::TZ);
+
+  for (int r = threadIdx.x; r < T::NS; r += kBlock) {
+    const int hx = r % T::SX, hy = (r / T::SX) % T::SY, hz = r / (T::SX * T::SY);
+    const uint32_t gx = mirror_any(x0 + hx - 1, g.n0);
+    const uint32_t gy = mirror_any(y0 + hy - 1, g.n1);
+    const uint32_t gz = DIM == 3 ? mirror_any(z0 + hz - 1, g.n2) : 0u;
+    const uint32_t i = gx + g.n0 * (gy + g.n1 * gz);
+    const double Fu = grid_apply<DIM, MIXED>(a.t.uprev, g, gx, gy, gz);
+    const double um = inner_value(a.t, Fu, load_sv(a.t.SV, MIXED, i), i);
+    sV[r] = tail_from_um(a.t, um, i);
   }
+  __syncthreads();
+
+  const int lx = threadIdx.x % T::TX, ly = (threadIdx.x / T::TX) % T::TY, lz = threadIdx.x / (T::TX * T::TY);
+  const uint32_t gx = (uint32_t)(x0 + lx), gy = (uint32_t)(y0 + ly), gz = (uint32_t)(z0 + lz);
+  if (gx >= g.n0 || gy >= g.n1 || (DIM == 3 && gz >= g.n2)) return;
+  const uint32_t i = gx + g.n0 * (gy + g.n1 * (DIM == 3 ? gz : 0u));
+  const int c = ((DIM == 3 ? lz + 1 : 0) * T::SY + (ly + 1)) * T::SX + (lx + 1);
+  const double V = sV[c];
+  a.Vout[i] = V;
+  const double FV = grid_stencil<DIM, MIXED>(g.w, [&](int dx, int dy, int dz) {
+    return sV[c + (DIM == 3 ? dz * T::SX * T::SY : 0) + dy * T::SX + dx];
+  });
+  head_node<Model, MIXED>(a.h, g.N, i, V, FV);
 }
 
 __global__ void k_clock_set(Clock *c, int64_t step, double t0) {
@@ -186,9 +260,10 @@ __global__ void k_clock_set(Clock *c, int64_t step, double t0) {
   }
 }
 
-__global__ __launch_bounds__(kBlock) void k_copy_tick(const double *src, double *dst, uint32_t N, Clock *tick) {
+__global__ __launch_bounds__(kBlock) void k_copy_tick(const double *src, double *dst, uint32_t N, Clock *tick,
+                                                      int64_t tick_by) {
   const uint32_t i = node_index();
-  if (tick != nullptr && blockIdx.x == 0 && threadIdx.x == 0) tick->step += 1;
+  if (tick != nullptr && blockIdx.x == 0 && threadIdx.x == 0) tick->step += tick_by;
   if (src != nullptr && i < N) dst[i] = src[i];
 }
 
@@ -432,14 +507,47 @@ hipError_t launch_inner(bool mixed, const Mesh &mesh, const InnerArgs &a, hipStr
   return hipGetLastError();
 }
 
+bool fused_supported(const Mesh &mesh) { return mesh.kind == kGrid; }
+
+template <template <class> class Model>
+static hipError_t fused_dispatch(bool mixed, const Grid &g, const FusedArgs &a, hipStream_t st) {
+  if (g.dim == 3) {
+    using T = Tile<3>;
+    const uint32_t ntx = (g.n0 + T::TX - 1) / T::TX, nty = (g.n1 + T::TY - 1) / T::TY,
+                   ntz = (g.n2 + T::TZ - 1) / T::TZ;
+    const dim3 grid(ntx * nty * ntz);
+    if (mixed)
+      hipLaunchKernelGGL((k_fused<Model, true, 3>), grid, dim3(kBlock), 0, st, a, g, ntx, nty);
+    else
+      hipLaunchKernelGGL((k_fused<Model, false, 3>), grid, dim3(kBlock), 0, st, a, g, ntx, nty);
+  } else {
+    using T = Tile<2>;
+    const uint32_t ntx = (g.n0 + T::TX - 1) / T::TX, nty = (g.n1 + T::TY - 1) / T::TY;
+    const dim3 grid(ntx * nty);
+    if (mixed)
+      hipLaunchKernelGGL((k_fused<Model, true, 2>), grid, dim3(kBlock), 0, st, a, g, ntx, nty);
+    else
+      hipLaunchKernelGGL((k_fused<Model, false, 2>), grid, dim3(kBlock), 0, st, a, g, ntx, nty);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_fused(int model, bool mixed, const Mesh &mesh, const FusedArgs &a, hipStream_t st) {
+  if (mesh.kind != kGrid) return hipErrorInvalidValue;
+#define CALL(M) fused_dispatch<M>(mixed, mesh.grid, a, st)
+  EMRKC_MODEL_SWITCH(model, CALL)
+#undef CALL
+}
+
 hipError_t launch_clock_set(Clock *c, int64_t step, double t0, hipStream_t st) {
   hipLaunchKernelGGL(k_clock_set, dim3(1), dim3(64), 0, st, c, step, t0);
   return hipGetLastError();
 }
 
-hipError_t launch_copy_tick(const double *src, double *dst, uint32_t N, Clock *tick, hipStream_t st) {
+hipError_t launch_copy_tick(const double *src, double *dst, uint32_t N, Clock *tick, int64_t tick_by,
+                            hipStream_t st) {
   const uint32_t nb = src != nullptr ? blocks_for(N) : 1;
-  hipLaunchKernelGGL(k_copy_tick, dim3(nb), dim3(kBlock), 0, st, src, dst, N, tick);
+  hipLaunchKernelGGL(k_copy_tick, dim3(nb), dim3(kBlock), 0, st, src, dst, N, tick, tick_by);
   return hipGetLastError();
 }
 

@@ -29,6 +29,7 @@ EMRKC_MIXED32 = 1
 PRECISIONS = {"fp64": EMRKC_FP64, "mixed": EMRKC_MIXED32}
 EMRKC_CHECK_FINITE = 1
 EMRKC_EAGER = 2          # library-internal flag: no HIP-graph replay
+EMRKC_NO_FUSE = 4        # library-internal flag: no fused tail+head kernel
 
 
 class Mesh(C.Structure):
@@ -84,7 +85,7 @@ EXPORTS = {
     "emrkc_step": (C.c_int, [C.c_void_p, C.POINTER(State), C.c_double, C.c_int64]),
     "emrkc_last_stats": (C.c_int, [C.c_void_p, C.POINTER(Stats)]),
     "emrkc_profile_step": (C.c_int, [C.c_void_p, C.POINTER(State), C.c_double, C.c_int64, C.POINTER(C.c_double),
-                                     C.POINTER(C.c_double), C.POINTER(C.c_int64), C.POINTER(C.c_int64)]),
+                                     C.POINTER(C.c_int64)]),
     "emrkc_apply_diffusion": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
     "emrkc_eval_rhs_slow": (C.c_int, [C.c_void_p, C.POINTER(State), C.c_double, C.c_void_p]),
 }
@@ -198,11 +199,15 @@ def emrkc_step(ctx, state, dt, nsteps):
     return _check(lib().emrkc_step(ctx, C.byref(state), dt, int(nsteps)), ctx)
 
 
+PROFILE_CLASSES = ("head", "inner", "fused")
+
+
 def emrkc_profile_step(ctx, state, dt, nsteps):
-    hm, im, nh, ni = C.c_double(), C.c_double(), C.c_int64(), C.c_int64()
-    _check(lib().emrkc_profile_step(ctx, C.byref(state), dt, int(nsteps), C.byref(hm), C.byref(im), C.byref(nh),
-                                    C.byref(ni)), ctx)
-    return hm.value, im.value, nh.value, ni.value
+    """{class: (mean ms, launches)} for the head, inner and fused kernels."""
+    ms = (C.c_double * 3)()
+    cnt = (C.c_int64 * 3)()
+    _check(lib().emrkc_profile_step(ctx, C.byref(state), dt, int(nsteps), ms, cnt), ctx)
+    return {k: (ms[i], cnt[i]) for i, k in enumerate(PROFILE_CLASSES)}
 
 
 def emrkc_last_stats(ctx):
