@@ -54,11 +54,11 @@ def bytes_per_node(kind, nz, wz, m):
 
 
 class Job:
-    def __init__(self, cfg, precision, stream):
+    def __init__(self, cfg, precision, stream, flags=0):
         from paper_2401_01745_amd import emrkc as E
         self.E = E
         self.cfg = cfg
-        self.sim = E.simulation_from_config(cfg, precision=precision)
+        self.sim = E.simulation_from_config(cfg, precision=precision, flags=flags)
         E.emrkc_set_stream(self.sim.ctx, stream.cuda_stream)
         self.nsim = int(round(cfg["T"] / cfg["dt"]))
 
@@ -116,6 +116,7 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--fuse", action="store_true", help="fused last-inner-stage + head kernel")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="copy a buffer of this size once (calibrates rocprof FETCH/WRITE counters)")
     args = ap.parse_args()
@@ -142,7 +143,8 @@ def main():
         del src, dst
     with torch.cuda.stream(stream):
         log("bench: %s, N=%d, building FP64 context" % (cfg["name"], N))
-        job = Job(cfg, "fp64", stream)
+        flags = E.EMRKC_FUSE if args.fuse else 0
+        job = Job(cfg, "fp64", stream, flags)
         elapsed, (rF, rS, itF, itS) = time_jobs(job, args.warmup, args.steps, torch)
         s, m, eta = E.emrkc_stages(job.sim.ctx, cfg["dt"])
         value = N * job.nsim * args.steps / elapsed
@@ -167,16 +169,23 @@ def main():
         names = {"fused": "k_fused (last inner stage of step n-1 + exponential Euler, ionic model, outer z "
                           "recurrence and first inner stage of step n)",
                  "head": "k_head (exponential Euler, ionic model, outer z recurrence, first inner stage)"}
+        # the inner kernel in this pass is the last inner stage (stencil +
+        # Chebyshev recurrence + outer V update) when m == 2
+        ib = bytes_per_node("tail" if m == 2 else "inner", nz, 8, m) * N
+        inner_gbs = ib / (prof["inner"][0] * 1e-3) / 1e9 if prof["inner"][1] else None
         roof = {"kernel": names[dom], "bound": "hbm", "achieved": round(dom_gbs, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(dom_gbs / HBM_PEAK_GBS, 4), "traffic": traffic,
                 "bytes_per_launch": db, "launch_ms": round(dom_ms, 5),
                 "kernels_ms": {k: round(v[0], 5) for k, v in prof.items()},
-                "launches": {k: v[1] for k, v in prof.items()}}
+                "launches": {k: v[1] for k, v in prof.items()},
+                "inner_stencil_kernel": {"achieved_GBs": round(inner_gbs, 1) if inner_gbs else None,
+                                         "frac": round(inner_gbs / HBM_PEAK_GBS, 4) if inner_gbs else None,
+                                         "bytes_per_launch": ib}}
 
         mixed = None
         if not args.no_mixed:
             log("bench: mixed FP32 form")
-            jm = Job(cfg, "mixed", stream)
+            jm = Job(cfg, "mixed", stream, flags)
             el_m, _ = time_jobs(jm, 1, max(1, args.steps // 2), torch)
             value_m = N * jm.nsim * max(1, args.steps // 2) / el_m
             Vm = jm.sim.V.cpu().numpy()

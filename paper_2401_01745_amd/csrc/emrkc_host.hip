@@ -19,7 +19,8 @@
 using namespace emrkc;
 
 #define EMRKC_EAGER_FLAG 2u     // internal: never capture graphs (testing)
-#define EMRKC_NO_FUSE_FLAG 4u   // internal: separate tail and head kernels (testing)
+#define EMRKC_FUSE_FLAG 4u      // internal: fused tail+head kernel (s == 1, m >= 2, grids)
+#define EMRKC_FLAT_FLAG 8u      // internal: flat global-load kernels on grids (testing)
 
 struct GraphKey {
   int s, m, chunk;
@@ -61,7 +62,8 @@ struct emrkc_ctx {
   double *d_U[3] = {nullptr, nullptr, nullptr};
   void *d_SV = nullptr;
   void *d_SV2 = nullptr;
-  bool use_fused = true;
+  bool use_fused = false;
+  bool flat = false;
   void *d_z1 = nullptr;
   Clock *d_clock = nullptr;
   double *d_partials = nullptr;
@@ -328,7 +330,8 @@ extern "C" int emrkc_create(const emrkc_mesh *mesh, const emrkc_conductivity *co
   c->nv = 1 + c->ng + c->ns;
   c->mixed = p->precision == EMRKC_MIXED32;
   c->flags = p->flags;
-  c->use_fused = getenv("EMRKC_NO_FUSE") == nullptr && (p->flags & EMRKC_NO_FUSE_FLAG) == 0;
+  c->use_fused = getenv("EMRKC_FUSE") != nullptr || (p->flags & EMRKC_FUSE_FLAG) != 0;
+  c->flat = (p->flags & EMRKC_FLAT_FLAG) != 0;
   c->chi = p->chi;
   c->Cm = p->Cm;
   c->eps = p->eps;
@@ -666,6 +669,7 @@ static int enqueue_chunk_fused(emrkc_ctx *c, const emrkc_state *st, const StepPl
 
 static int enqueue_chunk(emrkc_ctx *c, const emrkc_state *st, const StepPlan &P, double dt, int L, hipStream_t strm,
                          KernelTimer *tm = nullptr) {
+  set_flat_kernels(c->flat);
   if (c->use_fused && P.s == 1 && P.m >= 2 && fused_supported(c->mesh))
     return enqueue_chunk_fused(c, st, P, dt, L, strm, tm);
   for (int n = 0; n < L; ++n) {

@@ -99,6 +99,9 @@ hipError_t launch_head(int model, bool mixed, const Mesh &mesh, const HeadArgs &
 hipError_t launch_inner(bool mixed, const Mesh &mesh, const InnerArgs &a, hipStream_t st);
 hipError_t launch_fused(int model, bool mixed, const Mesh &mesh, const FusedArgs &a, hipStream_t st);
 bool fused_supported(const Mesh &mesh);
+// Testing switch: use the flat (one node per thread, global-load stencil)
+// kernels on grids instead of the LDS-tiled ones.  Process-wide.
+void set_flat_kernels(bool flat);
 hipError_t launch_clock_set(Clock *c, int64_t step, double t0, hipStream_t st);
 hipError_t launch_copy_tick(const double *src, double *dst, uint32_t N, Clock *tick, int64_t tick_by,
                             hipStream_t st);

@@ -90,8 +90,10 @@ __global__ __launch_bounds__(kBlock) void k_init_state(uint32_t N, double *V, vo
 // ---------------------------------------------------------------------------
 // Outer-stage head at one node, given V_{j-1} and f_F(V_{j-1}) there
 // ---------------------------------------------------------------------------
-template <template <class> class Model, bool MIXED>
-__device__ __forceinline__ void head_node(const HeadArgs &a, uint32_t N, uint32_t i, double V, double FV) {
+// FVf() evaluates f_F(V_{j-1}) at the node; it is called after the z update
+// so that the stencil operands are not live across the ionic model.
+template <template <class> class Model, bool MIXED, class FVf>
+__device__ __forceinline__ void head_node(const HeadArgs &a, uint32_t N, uint32_t i, double V, FVf FVfun) {
   using M = MathOf<MIXED>;
   using R = typename M::R;
   using Mod = Model<M>;
@@ -145,6 +147,7 @@ __device__ __forceinline__ void head_node(const HeadArgs &a, uint32_t N, uint32_
   }
 
   // first inner stage u_1 = u_0 + mu'_1 eta (f_F(u_0) + S_V), u_0 = V
+  const double FV = FVfun();
   const double u1 = V + a.mu1_eta * (FV + SV);
   if (a.m_is_one) {
     const double fbarV = (u1 - V) * a.inv_eta;
@@ -164,8 +167,7 @@ __global__ __launch_bounds__(kBlock) void k_head(HeadArgs a, Mesh mesh) {
   const uint32_t i = node_index();
   if (i >= N) return;
   const double V = a.Vin[i];
-  const double FV = apply_op<MIXED>(mesh, a.Vin, i);
-  head_node<Model, MIXED>(a, N, i, V, FV);
+  head_node<Model, MIXED>(a, N, i, V, [&]() { return apply_op<MIXED>(mesh, a.Vin, i); });
 }
 
 // ---------------------------------------------------------------------------
@@ -247,10 +249,92 @@ __global__ __launch_bounds__(kBlock) void k_fused(FusedArgs a, Grid g, uint32_t 
   const int c = ((DIM == 3 ? lz + 1 : 0) * T::SY + (ly + 1)) * T::SX + (lx + 1);
   const double V = sV[c];
   a.Vout[i] = V;
-  const double FV = grid_stencil<DIM, MIXED>(g.w, [&](int dx, int dy, int dz) {
-    return sV[c + (DIM == 3 ? dz * T::SX * T::SY : 0) + dy * T::SX + dx];
+  head_node<Model, MIXED>(a.h, g.N, i, V, [&]() {
+    return grid_stencil<DIM, MIXED>(g.w, [&](int dx, int dy, int dz) {
+      return sV[c + (DIM == 3 ? dz * T::SX * T::SY : 0) + dy * T::SX + dx];
+    });
   });
-  head_node<Model, MIXED>(a.h, g.N, i, V, FV);
+}
+
+// ---------------------------------------------------------------------------
+// LDS-tiled head and inner kernels for structured grids.  Each block owns a
+// tile, stages the operand of the stencil on the tile plus a one-node halo
+// (mirrored at the domain boundary) in LDS with coalesced loads, and
+// evaluates the stencil from LDS; the arithmetic is the same as the flat
+// kernels'.
+// ---------------------------------------------------------------------------
+template <int DIM>
+__device__ __forceinline__ void tile_origin(uint32_t ntx, uint32_t nty, int &x0, int &y0, int &z0) {
+  using T = Tile<DIM>;
+  const uint32_t b = xcd_block(blockIdx.x, gridDim.x);
+  const uint32_t bx = b % ntx, byz = b / ntx;
+  const uint32_t by = byz % nty, bz = byz / nty;
+  x0 = (int)(bx * T::TX);
+  y0 = (int)(by * T::TY);
+  z0 = (int)(bz * T::TZ);
+}
+
+template <int DIM>
+__device__ __forceinline__ void stage_halo(double *sU, const double *__restrict__ u, const Grid &g, int x0, int y0,
+                                           int z0) {
+  using T = Tile<DIM>;
+  for (int r = threadIdx.x; r < T::NS; r += kBlock) {
+    const int hx = r % T::SX, hy = (r / T::SX) % T::SY, hz = r / (T::SX * T::SY);
+    const uint32_t gx = mirror_any(x0 + hx - 1, g.n0);
+    const uint32_t gy = mirror_any(y0 + hy - 1, g.n1);
+    const uint32_t gz = DIM == 3 ? mirror_any(z0 + hz - 1, g.n2) : 0u;
+    sU[r] = u[gx + g.n0 * (gy + g.n1 * gz)];
+  }
+}
+
+// Own node of this thread in the tile: global index (or false when outside
+// the grid) and the LDS index of the node's centre.
+template <int DIM>
+__device__ __forceinline__ bool tile_node(const Grid &g, int x0, int y0, int z0, uint32_t &i, int &c) {
+  using T = Tile<DIM>;
+  const int lx = threadIdx.x % T::TX, ly = (threadIdx.x / T::TX) % T::TY, lz = threadIdx.x / (T::TX * T::TY);
+  const uint32_t gx = (uint32_t)(x0 + lx), gy = (uint32_t)(y0 + ly), gz = (uint32_t)(z0 + lz);
+  if (gx >= g.n0 || gy >= g.n1 || (DIM == 3 && gz >= g.n2)) return false;
+  i = gx + g.n0 * (gy + g.n1 * (DIM == 3 ? gz : 0u));
+  c = ((DIM == 3 ? lz + 1 : 0) * T::SY + (ly + 1)) * T::SX + (lx + 1);
+  return true;
+}
+
+template <int DIM, bool MIXED>
+__device__ __forceinline__ double lds_stencil(const double *sU, const Grid &g, int c) {
+  using T = Tile<DIM>;
+  return grid_stencil<DIM, MIXED>(g.w, [&](int dx, int dy, int dz) {
+    return sU[c + (DIM == 3 ? dz * T::SX * T::SY : 0) + dy * T::SX + dx];
+  });
+}
+
+template <template <class> class Model, bool MIXED, int DIM>
+__global__ __launch_bounds__(kBlock) void k_head_tiled(HeadArgs a, Grid g, uint32_t ntx, uint32_t nty) {
+  __shared__ double sV[Tile<DIM>::NS];
+  int x0, y0, z0;
+  tile_origin<DIM>(ntx, nty, x0, y0, z0);
+  stage_halo<DIM>(sV, a.Vin, g, x0, y0, z0);
+  __syncthreads();
+  uint32_t i;
+  int c;
+  if (!tile_node<DIM>(g, x0, y0, z0, i, c)) return;
+  head_node<Model, MIXED>(a, g.N, i, sV[c], [&]() { return lds_stencil<DIM, MIXED>(sV, g, c); });
+}
+
+template <bool MIXED, int DIM>
+__global__ __launch_bounds__(kBlock) void k_inner_tiled(InnerArgs a, Grid g, uint32_t ntx, uint32_t nty) {
+  __shared__ double sU[Tile<DIM>::NS];
+  if (a.tick != nullptr && blockIdx.x == 0 && threadIdx.x == 0) a.tick->step += a.tick_by;
+  int x0, y0, z0;
+  tile_origin<DIM>(ntx, nty, x0, y0, z0);
+  stage_halo<DIM>(sU, a.t.uprev, g, x0, y0, z0);
+  __syncthreads();
+  uint32_t i;
+  int c;
+  if (!tile_node<DIM>(g, x0, y0, z0, i, c)) return;
+  const double Fu = lds_stencil<DIM, MIXED>(sU, g, c);
+  const double uk = inner_value(a.t, Fu, load_sv(a.t.SV, MIXED, i), i);
+  a.out[i] = a.last ? tail_from_um(a.t, uk, i) : uk;
 }
 
 __global__ void k_clock_set(Clock *c, int64_t step, double t0) {
@@ -433,9 +517,39 @@ static inline uint32_t blocks_for(uint64_t n) { return (uint32_t)((n + kBlock - 
 
 uint32_t reduce_blocks(uint32_t n) { return blocks_for(n); }
 
+template <int DIM>
+static dim3 tile_grid(const Grid &g, uint32_t &ntx, uint32_t &nty) {
+  using T = Tile<DIM>;
+  ntx = (g.n0 + T::TX - 1) / T::TX;
+  nty = (g.n1 + T::TY - 1) / T::TY;
+  const uint32_t ntz = DIM == 3 ? (g.n2 + T::TZ - 1) / T::TZ : 1;
+  return dim3(ntx * nty * ntz);
+}
+
+static bool g_flat_kernels = false;
+void set_flat_kernels(bool flat) { g_flat_kernels = flat; }
+
 template <template <class> class Model>
 static hipError_t head_dispatch(bool mixed, const Mesh &mesh, const HeadArgs &a, hipStream_t st) {
   const uint32_t N = mesh.kind == kGrid ? mesh.grid.N : mesh.ell.N;
+  if (mesh.kind == kGrid && !g_flat_kernels) {
+    uint32_t ntx, nty;
+    const Grid &g = mesh.grid;
+    if (g.dim == 3) {
+      const dim3 grid = tile_grid<3>(g, ntx, nty);
+      if (mixed)
+        hipLaunchKernelGGL((k_head_tiled<Model, true, 3>), grid, dim3(kBlock), 0, st, a, g, ntx, nty);
+      else
+        hipLaunchKernelGGL((k_head_tiled<Model, false, 3>), grid, dim3(kBlock), 0, st, a, g, ntx, nty);
+    } else {
+      const dim3 grid = tile_grid<2>(g, ntx, nty);
+      if (mixed)
+        hipLaunchKernelGGL((k_head_tiled<Model, true, 2>), grid, dim3(kBlock), 0, st, a, g, ntx, nty);
+      else
+        hipLaunchKernelGGL((k_head_tiled<Model, false, 2>), grid, dim3(kBlock), 0, st, a, g, ntx, nty);
+    }
+    return hipGetLastError();
+  }
   if (mixed)
     hipLaunchKernelGGL((k_head<Model, true>), dim3(blocks_for(N)), dim3(kBlock), 0, st, a, mesh);
   else
@@ -500,6 +614,24 @@ hipError_t launch_head(int model, bool mixed, const Mesh &mesh, const HeadArgs &
 
 hipError_t launch_inner(bool mixed, const Mesh &mesh, const InnerArgs &a, hipStream_t st) {
   const uint32_t N = mesh.kind == kGrid ? mesh.grid.N : mesh.ell.N;
+  if (mesh.kind == kGrid && !g_flat_kernels) {
+    uint32_t ntx, nty;
+    const Grid &g = mesh.grid;
+    if (g.dim == 3) {
+      const dim3 grid = tile_grid<3>(g, ntx, nty);
+      if (mixed)
+        hipLaunchKernelGGL((k_inner_tiled<true, 3>), grid, dim3(kBlock), 0, st, a, g, ntx, nty);
+      else
+        hipLaunchKernelGGL((k_inner_tiled<false, 3>), grid, dim3(kBlock), 0, st, a, g, ntx, nty);
+    } else {
+      const dim3 grid = tile_grid<2>(g, ntx, nty);
+      if (mixed)
+        hipLaunchKernelGGL((k_inner_tiled<true, 2>), grid, dim3(kBlock), 0, st, a, g, ntx, nty);
+      else
+        hipLaunchKernelGGL((k_inner_tiled<false, 2>), grid, dim3(kBlock), 0, st, a, g, ntx, nty);
+    }
+    return hipGetLastError();
+  }
   if (mixed)
     hipLaunchKernelGGL((k_inner<true>), dim3(blocks_for(N)), dim3(kBlock), 0, st, a, mesh);
   else

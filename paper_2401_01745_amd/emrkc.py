@@ -29,7 +29,8 @@ EMRKC_MIXED32 = 1
 PRECISIONS = {"fp64": EMRKC_FP64, "mixed": EMRKC_MIXED32}
 EMRKC_CHECK_FINITE = 1
 EMRKC_EAGER = 2          # library-internal flag: no HIP-graph replay
-EMRKC_NO_FUSE = 4        # library-internal flag: no fused tail+head kernel
+EMRKC_FUSE = 4           # library-internal flag: fused tail+head kernel
+EMRKC_FLAT = 8           # library-internal flag: flat (untiled) grid kernels
 
 
 class Mesh(C.Structure):

@@ -187,8 +187,8 @@ def test_linear_model_closed_form_on_gpu(E):
                                               ((37, 11), (900.0, 4.4), "fp64"), ((19, 13, 7), (150.0, 4.4), "fp64")])
 def test_graph_eager_fused_split_and_repeat_are_bitwise_identical(E, n, rho, precision):
     """HIP-graph replay, eager launches, the fused tail+head kernel, the
-    separate kernels, arbitrary call splits and repeated runs all give the
-    same bits (m = 2, 2-D with m = 5, and m = 3)."""
+    LDS-tiled and the flat kernels, arbitrary call splits and repeated runs
+    all give the same bits (m = 2, 2-D with m = 5, and m = 3)."""
     cfg = small_config("c2_3d_crn", n)
     if len(n) == 2:
         cfg["dim"] = 2
@@ -196,10 +196,12 @@ def test_graph_eager_fused_split_and_repeat_are_bitwise_identical(E, n, rho, pre
     V2, z2, st2 = gpu_run(cfg, 80, rho, precision=precision, flags=E.EMRKC_EAGER)
     V3, z3, _ = gpu_run(cfg, 80, rho, precision=precision, chunks=[1, 33, 7, 39])
     V4, z4, _ = gpu_run(cfg, 80, rho, precision=precision)
-    V5, z5, st5 = gpu_run(cfg, 80, rho, precision=precision, flags=E.EMRKC_NO_FUSE)
+    V5, z5, st5 = gpu_run(cfg, 80, rho, precision=precision, flags=E.EMRKC_FUSE)
+    V6, z6, _ = gpu_run(cfg, 80, rho, precision=precision, flags=E.EMRKC_FLAT)
+    V7, z7, _ = gpu_run(cfg, 80, rho, precision=precision, flags=E.EMRKC_FLAT | E.EMRKC_EAGER)
     assert st1.used_graph == 1 and st2.used_graph == 0
-    assert st1.kernels_per_step == st1.m - 1 and st5.kernels_per_step == st5.m
-    for V, z in [(V2, z2), (V3, z3), (V4, z4), (V5, z5)]:
+    assert st1.kernels_per_step == st1.m and st5.kernels_per_step == st5.m - 1
+    for V, z in [(V2, z2), (V3, z3), (V4, z4), (V5, z5), (V6, z6), (V7, z7)]:
         assert np.array_equal(V, V1) and np.array_equal(z, z1)
 
 
