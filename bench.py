@@ -32,10 +32,13 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def bytes_per_node(kind, nz, wz, m):
+def bytes_per_node(kind, nz, wz, m, mat=0):
     """Algorithmic HBM bytes per node of one launch (s = 1): V and u values
-    are doubles, z has width wz, S_V has width sv (4 in the mixed form).
-    head : V (8), z read and written (2 nz wz), S_V (sv) and u_1 (8) written
+    are doubles, z has width wz, S_V has width sv (4 in the mixed form), and
+    every diffusion product on an unstructured mesh adds the ELL row `mat`
+    (column indices and weights; 0 on grids, whose stencil is implicit).
+    head : V (8), z read and written (2 nz wz), S_V (sv) and u_1 (8) written;
+           with m == 1 it writes V_{n+1} (8) instead of S_V and u_1
     fused: last inner stage of the previous step -- u_{m-1} (8), u_{m-2} (8,
            only when m >= 3: for m = 2 it is V), V (8), S_V (sv) -- plus the
            head without its V read, plus V^n written (8)
@@ -43,22 +46,25 @@ def bytes_per_node(kind, nz, wz, m):
     tail : u_{m-1}, u_{m-2} (m >= 3), V, S_V, V written"""
     sv = 4 if wz == 4 else 8
     if kind == "head":
-        return 8 + 2 * nz * wz + sv + 8
+        return 8 + 2 * nz * wz + (8 if m == 1 else sv + 8) + mat
     if kind == "fused":
-        return 8 + (8 if m >= 3 else 0) + 8 + sv + 2 * nz * wz + sv + 8 + 8
+        return 8 + (8 if m >= 3 else 0) + 8 + sv + 2 * nz * wz + sv + 8 + 8 + 2 * mat
     if kind == "inner":
-        return 8 + 8 + sv + 8
+        return 8 + 8 + sv + 8 + mat
     if kind == "tail":
-        return 8 + (8 if m >= 3 else 0) + 8 + sv + 8
+        return 8 + (8 if m >= 3 else 0) + 8 + sv + 8 + mat
     raise ValueError(kind)
 
 
 class Job:
-    def __init__(self, cfg, precision, stream, flags=0):
+    def __init__(self, cfg, precision, stream, flags=0, tet=None):
         from paper_2401_01745_amd import emrkc as E
         self.E = E
         self.cfg = cfg
-        self.sim = E.simulation_from_config(cfg, precision=precision, flags=flags)
+        if tet is not None:
+            self.sim = E.simulation_from_tet_config(cfg, tet[0], tet[1], precision=precision, flags=flags)
+        else:
+            self.sim = E.simulation_from_config(cfg, precision=precision, flags=flags)
         E.emrkc_set_stream(self.sim.ctx, stream.cuda_stream)
         self.nsim = int(round(cfg["T"] / cfg["dt"]))
 
@@ -83,13 +89,13 @@ def time_jobs(job, warmup, steps, torch):
     return time.perf_counter() - t0, info
 
 
-def cpu_baseline(cfg, seconds):
+def cpu_baseline(cfg, seconds, tet=None):
     """The FP64 oracle on the same workload, timed for a bounded number of
     emRKC steps on the full mesh (assembly and radii excluded)."""
     from oracle.emrkc import emrkc_step, stage_counts
-    from oracle.monodomain import build_grid_problem
+    from oracle.monodomain import build_grid_problem, build_tet_problem
     from oracle.powiter import compute_rho, random_unit_interval
-    prob = build_grid_problem(cfg)
+    prob = build_tet_problem(cfg, *tet) if tet is not None else build_grid_problem(cfg)
     y = prob.uniform_state()
     v0 = random_unit_interval(y.size, 0)
     _, rF, _, _ = compute_rho(0.0, y, prob.f_F, v0.copy())
@@ -130,8 +136,15 @@ def main():
     from workloads.configs import get_config
     E.lib()
     torch.cuda.set_device(0)
-    cfg = get_config(args.config)
-    N = int(np.prod(cfg["n"]))
+    tet = None
+    if args.config.startswith("c3"):
+        from workloads.tetmesh import build_shell, shell_config
+        cfg = shell_config()
+        tet = build_shell(cfg)
+        N = tet[0]["coords"].shape[0]
+    else:
+        cfg = get_config(args.config)
+        N = int(np.prod(cfg["n"]))
     stream = torch.cuda.Stream()
     if args.calib_copy_mib > 0:
         src = torch.ones(args.calib_copy_mib << 18, dtype=torch.float32, device="cuda")
@@ -144,7 +157,7 @@ def main():
     with torch.cuda.stream(stream):
         log("bench: %s, N=%d, building FP64 context" % (cfg["name"], N))
         flags = E.EMRKC_FUSE if args.fuse else 0
-        job = Job(cfg, "fp64", stream, flags)
+        job = Job(cfg, "fp64", stream, flags, tet)
         elapsed, (rF, rS, itF, itS) = time_jobs(job, args.warmup, args.steps, torch)
         s, m, eta = E.emrkc_stages(job.sim.ctx, cfg["dt"])
         value = N * job.nsim * args.steps / elapsed
@@ -158,9 +171,11 @@ def main():
         log("bench: kernel means (ms, launches): %s" % prof)
         dom = "fused" if prof["fused"][1] > 0 else "head"
         dom_ms = prof[dom][0]
-        db = bytes_per_node(dom, nz, 8, m) * N
+        width = E.lib().emrkc_ell_width(job.sim.ctx) if tet is not None else 0
+        mat = width * (4 + 8)
+        db = bytes_per_node(dom, nz, 8, m, mat) * N
         dom_gbs = db / (dom_ms * 1e-3) / 1e9
-        prof_path = os.path.join(ROOT, "profiles", "traffic_k_%s_c2_3d_crn_fp64.json" % dom)
+        prof_path = os.path.join(ROOT, "profiles", "traffic_k_%s_%s_fp64.json" % (dom, cfg["name"]))
         traffic = None
         if os.path.exists(prof_path):
             tr = json.load(open(prof_path))
@@ -171,7 +186,7 @@ def main():
                  "head": "k_head (exponential Euler, ionic model, outer z recurrence, first inner stage)"}
         # the inner kernel in this pass is the last inner stage (stencil +
         # Chebyshev recurrence + outer V update) when m == 2
-        ib = bytes_per_node("tail" if m == 2 else "inner", nz, 8, m) * N
+        ib = bytes_per_node("tail" if m == 2 else "inner", nz, 8, m, mat) * N
         inner_gbs = ib / (prof["inner"][0] * 1e-3) / 1e9 if prof["inner"][1] else None
         roof = {"kernel": names[dom], "bound": "hbm", "achieved": round(dom_gbs, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(dom_gbs / HBM_PEAK_GBS, 4), "traffic": traffic,
@@ -185,7 +200,7 @@ def main():
         mixed = None
         if not args.no_mixed:
             log("bench: mixed FP32 form")
-            jm = Job(cfg, "mixed", stream, flags)
+            jm = Job(cfg, "mixed", stream, flags, tet)
             el_m, _ = time_jobs(jm, 1, max(1, args.steps // 2), torch)
             value_m = N * jm.nsim * max(1, args.steps // 2) / el_m
             Vm = jm.sim.V.cpu().numpy()
@@ -201,7 +216,7 @@ def main():
     cpu = None
     if not args.no_cpu_baseline:
         log("bench: CPU oracle baseline")
-        v, n, el, sm = cpu_baseline(cfg, args.cpu_seconds)
+        v, n, el, sm = cpu_baseline(cfg, args.cpu_seconds, tet)
         cpu = {"value": v, "unit": "node-steps/s", "cores": 1, "kind": "oracle",
                "sample": "%d emRKC steps of the full %d-node mesh in %.1f s (numpy/scipy, single thread; "
                          "host has %d logical CPUs)" % (n, N, el, os.cpu_count())}
@@ -209,10 +224,12 @@ def main():
     out = {"metric": METRIC, "value": value, "unit": "node-steps/s", "n_gpus": 1, "steps": args.steps,
            "warmup": args.warmup, "ms_per_step": 1e3 * elapsed / args.steps, "higher_is_better": True,
            "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
-           "config": {"workload": "%s: Q1 grid %s (%d nodes), %s, chi=%g/mm, Cm=%g uF/mm^2, sigma=%s, dt=%g ms, "
+           "config": {"workload": "%s: %s (%d nodes), %s, chi=%g/mm, Cm=%g uF/mm^2, sigma=%s, dt=%g ms, "
                                   "T=%g ms; one bench step = init + power iteration + %d emRKC steps"
-                                  % (cfg["name"], "x".join(map(str, cfg["n"])), N, cfg["model"], cfg["chi"],
-                                     cfg["Cm"], list(cfg["sigma"]), cfg["dt"], cfg["T"], job.nsim),
+                                  % (cfg["name"], ("P1 tetrahedral shell %s" % "x".join(map(str, cfg["dims"])))
+                                     if tet is not None else ("Q1 grid %s" % "x".join(map(str, cfg["n"]))),
+                                     N, cfg["model"], cfg["chi"], cfg["Cm"], list(cfg["sigma"]), cfg["dt"], cfg["T"],
+                                     job.nsim),
                       "s": s, "m": m, "eta": eta, "rho_F": rF, "rho_S": rS, "powiter_iters": [itF, itS]},
            "roofline": roof, "mixed": mixed, "cpu_baseline": cpu}
     print(json.dumps(out), flush=True)

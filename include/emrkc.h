@@ -182,6 +182,9 @@ int emrkc_set_stream(emrkc_ctx *ctx, void *hip_stream);
 
 int64_t emrkc_num_nodes(const emrkc_ctx *ctx);   /* N, or -1 for NULL */
 int emrkc_num_vars(const emrkc_ctx *ctx);        /* n_v, or -1 for NULL */
+/* Row width of the unstructured operator (ELL slots per node), 0 on grids,
+ * -1 for NULL. */
+int emrkc_ell_width(const emrkc_ctx *ctx);
 const char *emrkc_last_error(const emrkc_ctx *ctx);
 
 /* Writes the model's uniform resting state (V and every z) into the state

@@ -99,20 +99,23 @@ def conductivity_from_fibre(a, sigma_l, sigma_t):
 
 
 def assemble_p1_tets(coords, tets, fibres, sigma_l, sigma_t):
-    """K (csr), lumped mass and consistent mass for a P1 tetrahedral mesh."""
+    """K (csr), lumped mass and consistent mass for a P1 tetrahedral mesh.
+    Element by element, vectorised over elements: the same formulas as
+    p1_tet_element and conductivity_from_fibre applied to every element."""
     N = coords.shape[0]
-    rows, cols, kv, mv = [], [], [], []
-    for e in range(tets.shape[0]):
-        idx = tets[e]
-        D = conductivity_from_fibre(fibres[e], sigma_l, sigma_t)
-        Ke, Me, _ = p1_tet_element(coords[idx], D)
-        rows.append(np.repeat(idx, 4))
-        cols.append(np.tile(idx, 4))
-        kv.append(Ke.reshape(-1))
-        mv.append(Me.reshape(-1))
-    rows = np.concatenate(rows)
-    cols = np.concatenate(cols)
-    K = sp.coo_matrix((np.concatenate(kv), (rows, cols)), shape=(N, N)).tocsr()
-    M = sp.coo_matrix((np.concatenate(mv), (rows, cols)), shape=(N, N)).tocsr()
+    X = coords[tets]                                   # E x 4 x 3
+    B = np.stack([X[:, 1] - X[:, 0], X[:, 2] - X[:, 0], X[:, 3] - X[:, 0]], axis=2)  # columns
+    vol = np.abs(np.linalg.det(B)) / 6.0
+    Binv = np.linalg.inv(B)                            # rows: gradients of lambda_1..3
+    G = np.concatenate([-Binv.sum(axis=1, keepdims=True), Binv], axis=1)   # E x 4 x 3
+    a = fibres / np.linalg.norm(fibres, axis=1)[:, None]
+    aa = np.einsum("ei,ej->eij", a, a)
+    D = sigma_l * aa + sigma_t * (np.eye(3)[None] - aa)
+    Ke = vol[:, None, None] * np.einsum("eai,eij,ebj->eab", G, D, G)
+    Me = (vol / 20.0)[:, None, None] * (np.ones((4, 4)) + np.eye(4))[None]
+    rows = np.repeat(tets, 4, axis=1).reshape(-1)
+    cols = np.tile(tets, (1, 4)).reshape(-1)
+    K = sp.coo_matrix((Ke.reshape(-1), (rows, cols)), shape=(N, N)).tocsr()
+    M = sp.coo_matrix((Me.reshape(-1), (rows, cols)), shape=(N, N)).tocsr()
     ML = np.asarray(M.sum(axis=1)).reshape(-1)
     return K, ML, M

@@ -91,3 +91,11 @@ def build_grid_problem(cfg, model_kw=None, stim_mask=None):
     st = cfg["stim"]
     mask = make_mask(cfg) if stim_mask is None else stim_mask
     return Monodomain(K, ML, cfg["chi"], cfg["Cm"], model, mask, st["amp"], st["t_on"], st["t_off"])
+
+
+def build_tet_problem(cfg, mesh, mask, model_kw=None):
+    """Monodomain problem on a P1 tetrahedral mesh (unstructured workload)."""
+    K, ML, _ = fem.assemble_p1_tets(mesh["coords"], mesh["tets"], mesh["fibres"], cfg["sigma"][0], cfg["sigma"][1])
+    model = make_model(cfg["model"], **(model_kw or {}))
+    st = cfg["stim"]
+    return Monodomain(K, ML, cfg["chi"], cfg["Cm"], model, mask, st["amp"], st["t_on"], st["t_off"])

@@ -432,6 +432,9 @@ extern "C" int emrkc_set_stream(emrkc_ctx *c, void *s) {
 
 extern "C" int64_t emrkc_num_nodes(const emrkc_ctx *c) { return c ? c->N : -1; }
 extern "C" int emrkc_num_vars(const emrkc_ctx *c) { return c ? c->nv : -1; }
+extern "C" int emrkc_ell_width(const emrkc_ctx *c) {
+  return c ? (c->mesh.kind == kEll ? (int)c->mesh.ell.width : 0) : -1;
+}
 extern "C" const char *emrkc_last_error(const emrkc_ctx *c) { return c ? c->err.c_str() : "null context"; }
 
 static bool state_ok(const emrkc_ctx *c, const emrkc_state *s) {
@@ -667,11 +670,29 @@ static int enqueue_chunk_fused(emrkc_ctx *c, const emrkc_state *st, const StepPl
   return EMRKC_OK;
 }
 
+// L steps with s == m == 1: the head kernel computes V^{n+1} directly from
+// V^n read with neighbours, so V ping-pongs between X[0] and X[1] and only
+// an odd chunk ends with one copy back to X[0].
+static int enqueue_chunk_s1m1(emrkc_ctx *c, const emrkc_state *st, const StepPlan &P, double dt, int L,
+                              hipStream_t strm, KernelTimer *tm) {
+  double *X[2] = {(double *)st->V, c->d_V1};
+  for (int n = 0; n < L; ++n) {
+    HeadArgs h = make_head(c, P, dt, 1, n);
+    h.Vin = X[n % 2];
+    h.zin = h.zout = st->z;
+    h.uout = X[(n + 1) % 2];
+    TIMED(0, launch_head(c->model, c->mixed, c->mesh, h, strm));
+  }
+  HIP_TRY(c, launch_copy_tick(L % 2 ? X[1] : nullptr, X[0], (uint32_t)c->N, c->d_clock, L, strm));
+  return EMRKC_OK;
+}
+
 static int enqueue_chunk(emrkc_ctx *c, const emrkc_state *st, const StepPlan &P, double dt, int L, hipStream_t strm,
                          KernelTimer *tm = nullptr) {
   set_flat_kernels(c->flat);
   if (c->use_fused && P.s == 1 && P.m >= 2 && fused_supported(c->mesh))
     return enqueue_chunk_fused(c, st, P, dt, L, strm, tm);
+  if (P.s == 1 && P.m == 1) return enqueue_chunk_s1m1(c, st, P, dt, L, strm, tm);
   for (int n = 0; n < L; ++n) {
     int rc = enqueue_step_generic(c, st, P, dt, n, n == L - 1 ? L : 0, strm, tm);
     if (rc != EMRKC_OK) return rc;
@@ -751,7 +772,7 @@ extern "C" int emrkc_step(emrkc_ctx *c, emrkc_state *st, double dt, int64_t nste
   c->last.eta = P.eta;
   c->last.kernels_per_step = (c->use_fused && P.s == 1 && P.m >= 2 && fused_supported(c->mesh))
                                  ? (int64_t)P.m - 1
-                                 : (int64_t)P.s * P.m + (P.m == 1 ? 1 : 0);
+                                 : (P.s == 1 && P.m == 1) ? 1 : (int64_t)P.s * P.m + (P.m == 1 ? 1 : 0);
   c->last.used_graph = used_graph ? 1 : 0;
   if (c->flags & EMRKC_CHECK_FINITE) {
     HIP_TRY(c, hipMemsetAsync(c->d_flag, 0, sizeof(int), c->stream));
@@ -957,11 +978,117 @@ extern "C" int emrkc_eval_rhs_slow(emrkc_ctx *c, const emrkc_state *st, double t
 }
 
 // ---------------------------------------------------------------------------
-// P1 tetrahedral meshes: assembled on the host at creation into an ELL
-// operator on neighbour differences (weights of (chi Cm M_L)^{-1} A).
+// P1 tetrahedral meshes: assembled on the host at creation (element
+// stiffness |T| G D G^T, row-sum lumped mass |T|/4 per vertex) into an ELL
+// operator on neighbour differences: w_ij = -K_ij / (chi Cm M_L,i) for the
+// off-diagonal entries of each row, so that (chi Cm M_L)^{-1} A V =
+// sum_j w_ij (V_j - V_i) (rows of K sum to zero).  Columns are ordered by
+// first appearance in the element list; unused slots repeat the row index
+// with weight 0.
 // ---------------------------------------------------------------------------
 static int build_p1(emrkc_ctx *c, const emrkc_mesh *mesh, const emrkc_conductivity *cond) {
-  (void)mesh;
-  (void)cond;
-  return fail(c, EMRKC_EUNSUPPORTED, "P1 meshes are not built yet");
+  const int64_t N = mesh->n_nodes, E = mesh->n_elems;
+  const double *X = mesh->coords;
+  const int64_t *T = mesh->tets;
+  constexpr int kMaxDeg = 32;
+  std::vector<uint32_t> ncol((size_t)N * kMaxDeg);
+  std::vector<double> nval((size_t)N * kMaxDeg, 0.0);
+  std::vector<uint8_t> deg((size_t)N, 0);
+  std::vector<double> ML((size_t)N, 0.0);
+  for (int64_t e = 0; e < E; ++e) {
+    int64_t v[4];
+    for (int a = 0; a < 4; ++a) {
+      v[a] = T[4 * e + a];
+      if (v[a] < 0 || v[a] >= N) return fail(c, EMRKC_EINVAL, "element %lld has node index %lld out of range",
+                                              (long long)e, (long long)v[a]);
+    }
+    double B[3][3];  // columns x_a - x_0
+    for (int a = 0; a < 3; ++a)
+      for (int d = 0; d < 3; ++d) B[d][a] = X[3 * v[a + 1] + d] - X[3 * v[0] + d];
+    const double det = B[0][0] * (B[1][1] * B[2][2] - B[1][2] * B[2][1]) -
+                       B[0][1] * (B[1][0] * B[2][2] - B[1][2] * B[2][0]) +
+                       B[0][2] * (B[1][0] * B[2][1] - B[1][1] * B[2][0]);
+    if (!(fabs(det) > 0) || !isfinite(det))
+      return fail(c, EMRKC_EINVAL, "element %lld is degenerate", (long long)e);
+    // inverse by cofactors: rows of B^{-1} are the gradients of lambda_1..3
+    double Bi[3][3];
+    Bi[0][0] = (B[1][1] * B[2][2] - B[1][2] * B[2][1]) / det;
+    Bi[0][1] = (B[0][2] * B[2][1] - B[0][1] * B[2][2]) / det;
+    Bi[0][2] = (B[0][1] * B[1][2] - B[0][2] * B[1][1]) / det;
+    Bi[1][0] = (B[1][2] * B[2][0] - B[1][0] * B[2][2]) / det;
+    Bi[1][1] = (B[0][0] * B[2][2] - B[0][2] * B[2][0]) / det;
+    Bi[1][2] = (B[0][2] * B[1][0] - B[0][0] * B[1][2]) / det;
+    Bi[2][0] = (B[1][0] * B[2][1] - B[1][1] * B[2][0]) / det;
+    Bi[2][1] = (B[0][1] * B[2][0] - B[0][0] * B[2][1]) / det;
+    Bi[2][2] = (B[0][0] * B[1][1] - B[0][1] * B[1][0]) / det;
+    double G[4][3];
+    for (int d = 0; d < 3; ++d) {
+      G[1][d] = Bi[0][d];
+      G[2][d] = Bi[1][d];
+      G[3][d] = Bi[2][d];
+      G[0][d] = -(Bi[0][d] + Bi[1][d] + Bi[2][d]);
+    }
+    const double *f = mesh->fibres + 3 * e;
+    const double fn = sqrt(f[0] * f[0] + f[1] * f[1] + f[2] * f[2]);
+    if (!(fn > 0) || !isfinite(fn)) return fail(c, EMRKC_EINVAL, "element %lld has no fibre direction", (long long)e);
+    const double a3[3] = {f[0] / fn, f[1] / fn, f[2] / fn};
+    double D[3][3];
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j)
+        D[i][j] = cond->sigma_l * a3[i] * a3[j] + cond->sigma_t * ((i == j ? 1.0 : 0.0) - a3[i] * a3[j]);
+    const double vol = fabs(det) / 6.0;
+    for (int a = 0; a < 4; ++a) {
+      ML[v[a]] += vol / 4.0;
+      double DGa[3];
+      for (int i = 0; i < 3; ++i) DGa[i] = D[i][0] * G[a][0] + D[i][1] * G[a][1] + D[i][2] * G[a][2];
+      for (int b = 0; b < 4; ++b) {
+        if (b == a) continue;
+        const double kab = vol * (G[b][0] * DGa[0] + G[b][1] * DGa[1] + G[b][2] * DGa[2]);
+        const size_t row = (size_t)v[a] * kMaxDeg;
+        int k = 0;
+        while (k < deg[v[a]] && ncol[row + k] != (uint32_t)v[b]) ++k;
+        if (k == deg[v[a]]) {
+          if (k == kMaxDeg) return fail(c, EMRKC_EUNSUPPORTED, "node %lld has more than %d neighbours",
+                                        (long long)v[a], kMaxDeg);
+          ncol[row + k] = (uint32_t)v[b];
+          deg[v[a]] = (uint8_t)(k + 1);
+        }
+        nval[row + k] += kab;
+      }
+    }
+  }
+  uint32_t width = 1;
+  for (int64_t i = 0; i < N; ++i) {
+    if (!(ML[i] > 0)) return fail(c, EMRKC_EINVAL, "node %lld belongs to no element", (long long)i);
+    width = std::max<uint32_t>(width, deg[i]);
+  }
+  const double chiCm = c->chi * c->Cm;
+  std::vector<uint32_t> col((size_t)width * N);
+  std::vector<double> w64((size_t)width * N);
+  std::vector<float> w32((size_t)width * N);
+  for (int64_t i = 0; i < N; ++i) {
+    for (uint32_t k = 0; k < width; ++k) {
+      const bool used = k < deg[i];
+      const size_t o = (size_t)k * N + i;
+      col[o] = used ? ncol[(size_t)i * kMaxDeg + k] : (uint32_t)i;
+      w64[o] = used ? -nval[(size_t)i * kMaxDeg + k] / (chiCm * ML[i]) : 0.0;
+      w32[o] = (float)w64[o];
+    }
+  }
+  int rc;
+  if ((rc = dalloc(c, (void **)&c->d_ell_col, col.size() * sizeof(uint32_t))) ||
+      (rc = dalloc(c, (void **)&c->d_ell_w64, w64.size() * sizeof(double))) ||
+      (rc = dalloc(c, (void **)&c->d_ell_w32, w32.size() * sizeof(float))))
+    return rc;
+  HIP_TRY(c, hipMemcpy(c->d_ell_col, col.data(), col.size() * sizeof(uint32_t), hipMemcpyHostToDevice));
+  HIP_TRY(c, hipMemcpy(c->d_ell_w64, w64.data(), w64.size() * sizeof(double), hipMemcpyHostToDevice));
+  HIP_TRY(c, hipMemcpy(c->d_ell_w32, w32.data(), w32.size() * sizeof(float), hipMemcpyHostToDevice));
+  c->mesh.kind = kEll;
+  c->mesh.ell.N = (uint32_t)N;
+  c->mesh.ell.width = width;
+  c->mesh.ell.col = c->d_ell_col;
+  c->mesh.ell.w64 = c->d_ell_w64;
+  c->mesh.ell.w32 = c->d_ell_w32;
+  c->dim = 3;
+  return EMRKC_OK;
 }

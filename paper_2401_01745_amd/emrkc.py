@@ -75,6 +75,7 @@ EXPORTS = {
     "emrkc_set_stream": (C.c_int, [C.c_void_p, C.c_void_p]),
     "emrkc_num_nodes": (C.c_int64, [C.c_void_p]),
     "emrkc_num_vars": (C.c_int, [C.c_void_p]),
+    "emrkc_ell_width": (C.c_int, [C.c_void_p]),
     "emrkc_last_error": (C.c_char_p, [C.c_void_p]),
     "emrkc_init_state": (C.c_int, [C.c_void_p, C.POINTER(State)]),
     "emrkc_estimate_rho": (C.c_int, [C.c_void_p, C.POINTER(State), C.POINTER(C.c_double), C.POINTER(C.c_double),
@@ -312,3 +313,28 @@ def simulation_from_config(cfg, precision=None, rho=None, flags=0, stim_mask=Non
     p.linear_a = model_kw.get("a", 0.0)
     p.linear_lambda_E = model_kw.get("lam_E", 0.0)
     return Simulation(mesh, cond, cfg["model"], p, keep=(mask,))
+
+
+def simulation_from_tet_config(cfg, mesh, mask, precision=None, rho=None, flags=0):
+    """Simulation for an unstructured P1 workload (see workloads.tetmesh)."""
+    import numpy as np
+    prec = PRECISIONS[precision or cfg.get("precision", "fp64")]
+    coords = np.ascontiguousarray(mesh["coords"], dtype=np.float64)
+    tets = np.ascontiguousarray(mesh["tets"], dtype=np.int64)
+    fib = np.ascontiguousarray(mesh["fibres"], dtype=np.float64)
+    m = tet_mesh(coords, tets, fib)
+    cond = Conductivity(cfg["sigma"][0], cfg["sigma"][1], cfg["sigma"][1])
+    p = emrkc_default_params()
+    p.chi = cfg["chi"]
+    p.Cm = cfg["Cm"]
+    p.precision = prec
+    p.flags = flags
+    mask = np.ascontiguousarray(mask, dtype=np.uint8)
+    p.stim_mask = mask.ctypes.data
+    st = cfg["stim"]
+    p.stim_amp = st["amp"]
+    p.stim_t_on = st["t_on"]
+    p.stim_t_off = st["t_off"]
+    if rho is not None:
+        p.rho_F, p.rho_S = rho
+    return Simulation(m, cond, cfg["model"], p, keep=(coords, tets, fib, mask))

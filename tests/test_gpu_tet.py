@@ -1,0 +1,97 @@
+"""GPU parity on the unstructured P1 shell (ELL operator assembled by the
+library on the host, flat head and inner kernels) against the oracle's own
+vectorised assembly."""
+import numpy as np
+import pytest
+
+from gpu_util import oracle_rho, rel_errors
+from oracle.emrkc import emrkc_run
+from oracle.monodomain import build_tet_problem
+from workloads.tetmesh import build_shell, shell_config, small_shell_config
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def small():
+    cfg = small_shell_config()
+    mesh, mask = build_shell(cfg)
+    prob = build_tet_problem(cfg, mesh, mask)
+    return cfg, mesh, mask, prob
+
+
+def test_tet_diffusion_operator(small):
+    import torch
+    from paper_2401_01745_amd import emrkc as E
+    cfg, mesh, mask, prob = small
+    rng = np.random.default_rng(9)
+    V = -65.0 + 20.0 * rng.standard_normal(prob.N)
+    ref = prob.f_F(0.0, np.concatenate([V, np.zeros(prob.N * (prob.nv - 1))]))[:prob.N]
+    sim = E.simulation_from_tet_config(cfg, mesh, mask, rho=(1.0, 1.0))
+    out = torch.empty(prob.N, dtype=torch.float64, device="cuda")
+    E.emrkc_apply_diffusion(sim.ctx, torch.from_numpy(V).cuda(), out)
+    torch.cuda.synchronize()
+    scale = (np.abs(prob.A).sum(axis=1).A1 / (prob.chi * prob.Cm * prob.ML)).max() * np.abs(V).max()
+    assert np.abs(out.cpu().numpy() - ref).max() <= 1e-13 * scale
+    sim.close()
+
+
+@pytest.mark.parametrize("precision,tol,rhoF", [("fp64", 1e-10, None), ("mixed", 1e-4, None),
+                                                ("fp64", 1e-10, 100.0), ("fp64", 1e-10, 900.0)])
+def test_small_shell_run(small, precision, tol, rhoF):
+    """The coarse shell has a small rho_F (m = 1: one head kernel per step);
+    over-estimated radii force m = 2 and m = 5 (ELL inner stages)."""
+    import torch
+    from paper_2401_01745_amd import emrkc as E
+    cfg, mesh, mask, prob = small
+    rF, rS, _, _ = oracle_rho(prob, prob.uniform_state())
+    if rhoF is not None:
+        rF = rhoF
+    nsteps = 120
+    vmax = []
+    y = emrkc_run(prob, prob.uniform_state(), 0.0, cfg["dt"], nsteps, rF, rS,
+                  callback=lambda n, yy: vmax.append(yy[:prob.N].max()))
+    assert max(vmax) > 0.0  # the patch excited the shell
+    sim = E.simulation_from_tet_config(cfg, mesh, mask, precision=precision, rho=(rF, rS))
+    E.emrkc_init_state(sim.ctx, sim.state)
+    E.emrkc_step(sim.ctx, sim.state, cfg["dt"], nsteps)
+    torch.cuda.synchronize()
+    Y = y.reshape(prob.nv, prob.N)
+    l2, mx = rel_errors(sim.V.cpu().numpy(), Y[0])
+    assert l2 <= tol and mx <= 10 * tol, (l2, mx)
+    st = E.emrkc_last_stats(sim.ctx)
+    assert st.s == 1 and st.m == {None: 1, 100.0: 2, 900.0: 5}[rhoF]
+    sim.close()
+
+
+def test_tet_estimate_rho(small):
+    from paper_2401_01745_amd import emrkc as E
+    cfg, mesh, mask, prob = small
+    rF, rS, itF, itS = oracle_rho(prob, prob.uniform_state())
+    sim = E.simulation_from_tet_config(cfg, mesh, mask)
+    E.emrkc_init_state(sim.ctx, sim.state)
+    gF, gS, gitF, gitS, _ = E.emrkc_estimate_rho(sim.ctx, sim.state)
+    assert (gitF, gitS) == (itF, itS)
+    assert gF == pytest.approx(rF, rel=1e-6) and gS == pytest.approx(rS, rel=1e-6)
+    sim.close()
+
+
+@pytest.mark.slow
+def test_full_shell_prefix_fp64():
+    """The unstructured workload at full size (1.03 M nodes, 5.8 M
+    tetrahedra), the first 10 steps, every node compared."""
+    import torch
+    from paper_2401_01745_amd import emrkc as E
+    cfg = shell_config()
+    mesh, mask = build_shell(cfg)
+    prob = build_tet_problem(cfg, mesh, mask)
+    rF, rS, _, _ = oracle_rho(prob, prob.uniform_state())
+    y = emrkc_run(prob, prob.uniform_state(), 0.0, cfg["dt"], 10, rF, rS)
+    sim = E.simulation_from_tet_config(cfg, mesh, mask, rho=(rF, rS))
+    E.emrkc_init_state(sim.ctx, sim.state)
+    E.emrkc_step(sim.ctx, sim.state, cfg["dt"], 10)
+    torch.cuda.synchronize()
+    Y = y.reshape(prob.nv, prob.N)
+    l2, mx = rel_errors(sim.V.cpu().numpy(), Y[0])
+    assert l2 <= 1e-10 and mx <= 1e-10, (l2, mx)
+    sim.close()
