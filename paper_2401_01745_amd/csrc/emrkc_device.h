@@ -302,6 +302,10 @@ struct Grid {
   uint32_t N;
   FastDiv div0, div1;    // division by n0 and by n1
   int dim;
+  // inner-stage kernel for 3-D grids: 0 = 3-D tiles, 1 = z-marching columns
+  // of zc planes per block (2.5-D); chosen by the host
+  int inner_variant;
+  uint32_t zc;
   // weights of (chi Cm M_L)^{-1} A on neighbour differences, by offset class
   // (|ox|, |oy|, |oz|): w[0]=100, w[1]=010, w[2]=001, w[3]=110, w[4]=101,
   // w[5]=011, w[6]=111 (2-D uses w[0], w[1], w[3]).

@@ -21,6 +21,7 @@ using namespace emrkc;
 #define EMRKC_EAGER_FLAG 2u     // internal: never capture graphs (testing)
 #define EMRKC_FUSE_FLAG 4u      // internal: fused tail+head kernel (s == 1, m >= 2, grids)
 #define EMRKC_FLAT_FLAG 8u      // internal: flat global-load kernels on grids (testing)
+#define EMRKC_MARCH_FLAG 16u    // internal: z-marching inner kernel with 4 planes per block (testing)
 
 struct GraphKey {
   int s, m, chunk;
@@ -371,6 +372,20 @@ extern "C" int emrkc_create(const emrkc_mesh *mesh, const emrkc_conductivity *co
     g.div1 = make_fastdiv(g.n1);
     const double sg[3] = {cond->sigma_l, cond->sigma_t, cond->sigma_n};
     grid_weights(c->dim, c->h, sg, c->chi * c->Cm, g.w);
+    // default inner-stage kernel: z-marching columns on 3-D grids, with the
+    // number of planes per block chosen for at least ~4 blocks per CU
+    {
+      const uint32_t cols = ((g.n0 + 31) / 32) * ((g.n1 + 7) / 8);
+      uint32_t zc = 16;
+      while (zc > 1 && cols * ((g.n2 + zc - 1) / zc) < 2048) zc /= 2;
+      g.zc = zc;
+      // short columns re-read too much halo: small grids keep 3-D tiles
+      g.inner_variant = (c->dim == 3 && zc >= 4) ? 1 : 0;
+      if (c->dim == 3 && (p->flags & EMRKC_MARCH_FLAG)) {
+        g.inner_variant = 1;
+        g.zc = 4;
+      }
+    }
   } else {
     rc = build_p1(c, mesh, cond);
     if (rc != EMRKC_OK) goto error;

@@ -337,6 +337,83 @@ __global__ __launch_bounds__(kBlock) void k_inner_tiled(InnerArgs a, Grid g, uin
   a.out[i] = a.last ? tail_from_um(a.t, uk, i) : uk;
 }
 
+// ---------------------------------------------------------------------------
+// Inner stage on 3-D grids by z-marching columns (2.5-D): a block owns an
+// MX x MY column of zc planes and keeps the planes z-1, z, z+1 of u_{k-1}
+// (with a one-node mirrored halo in x and y) in an LDS ring; plane z+2 is
+// loaded into registers while plane z is computed.  Each plane is read
+// from memory once per column instead of once per neighbouring tile.
+// ---------------------------------------------------------------------------
+constexpr int MX = 32, MY = 8;
+constexpr int MSX = MX + 2, MSY = MY + 2, MPL = MSX * MSY;
+constexpr int MSLOT = (MPL + kBlock - 1) / kBlock;
+
+template <bool MIXED>
+__global__ __launch_bounds__(kBlock) void k_inner_march(InnerArgs a, Grid g, uint32_t ncx, uint32_t ncy) {
+  __shared__ double ring[3][MPL];
+  if (a.tick != nullptr && blockIdx.x == 0 && threadIdx.x == 0) a.tick->step += a.tick_by;
+  const uint32_t b = xcd_block(blockIdx.x, gridDim.x);
+  const uint32_t bx = b % ncx, byz = b / ncx;
+  const uint32_t by = byz % ncy, bz = byz / ncy;
+  const int x0 = (int)(bx * MX), y0 = (int)(by * MY);
+  const int zb = (int)(bz * g.zc);
+  const int ze = min(zb + (int)g.zc, (int)g.n2);
+  const uint32_t plane = g.n0 * g.n1;
+  // this thread's staging slots of a plane (xy offsets with mirrored halo)
+  uint32_t off[MSLOT];
+  bool act[MSLOT];
+#pragma unroll
+  for (int k = 0; k < MSLOT; ++k) {
+    const int r = threadIdx.x + k * kBlock;
+    act[k] = r < MPL;
+    const int hx = r % MSX, hy = r / MSX;
+    off[k] = act[k] ? mirror_any(x0 + hx - 1, g.n0) + g.n0 * mirror_any(y0 + hy - 1, g.n1) : 0u;
+  }
+  const double *__restrict__ u = a.t.uprev;
+  auto gplane = [&](int z) { return (size_t)mirror_any(z, g.n2) * plane; };
+  auto stage = [&](double *dst, int z) {
+    const size_t pz = gplane(z);
+#pragma unroll
+    for (int k = 0; k < MSLOT; ++k)
+      if (act[k]) dst[threadIdx.x + k * kBlock] = u[pz + off[k]];
+  };
+  stage(ring[(zb + 2) % 3], zb - 1);   // slot of plane p is p mod 3 (p >= -1)
+  stage(ring[zb % 3], zb);
+  double pre[MSLOT];
+  {
+    const size_t pz = gplane(zb + 1);
+#pragma unroll
+    for (int k = 0; k < MSLOT; ++k) pre[k] = act[k] ? u[pz + off[k]] : 0.0;
+  }
+  const int lx = threadIdx.x % MX, ly = threadIdx.x / MX;
+  const uint32_t gx = (uint32_t)(x0 + lx), gy = (uint32_t)(y0 + ly);
+  const bool own = gx < g.n0 && gy < g.n1;
+  const int c = (ly + 1) * MSX + (lx + 1);
+  for (int z = zb; z < ze; ++z) {
+    double *nxt = ring[(z + 1) % 3];
+#pragma unroll
+    for (int k = 0; k < MSLOT; ++k)
+      if (act[k]) nxt[threadIdx.x + k * kBlock] = pre[k];
+    __syncthreads();
+    if (z + 1 < ze) {
+      const size_t pz = gplane(z + 2);
+#pragma unroll
+      for (int k = 0; k < MSLOT; ++k) pre[k] = act[k] ? u[pz + off[k]] : 0.0;
+    }
+    if (own) {
+      const double *pm = ring[(z + 2) % 3], *pc = ring[z % 3], *pp = ring[(z + 1) % 3];
+      const double Fu = grid_stencil<3, MIXED>(g.w, [&](int dx, int dy, int dz) {
+        const double *pl = dz < 0 ? pm : (dz > 0 ? pp : pc);
+        return pl[c + dy * MSX + dx];
+      });
+      const uint32_t i = gx + g.n0 * gy + plane * (uint32_t)z;
+      const double uk = inner_value(a.t, Fu, load_sv(a.t.SV, MIXED, i), i);
+      a.out[i] = a.last ? tail_from_um(a.t, uk, i) : uk;
+    }
+    __syncthreads();
+  }
+}
+
 __global__ void k_clock_set(Clock *c, int64_t step, double t0) {
   if (threadIdx.x == 0 && blockIdx.x == 0) {
     c->step = step;
@@ -617,6 +694,14 @@ hipError_t launch_inner(bool mixed, const Mesh &mesh, const InnerArgs &a, hipStr
   if (mesh.kind == kGrid && !g_flat_kernels) {
     uint32_t ntx, nty;
     const Grid &g = mesh.grid;
+    if (g.dim == 3 && g.inner_variant == 1) {
+      const uint32_t ncx = (g.n0 + MX - 1) / MX, ncy = (g.n1 + MY - 1) / MY, ncz = (g.n2 + g.zc - 1) / g.zc;
+      if (mixed)
+        hipLaunchKernelGGL((k_inner_march<true>), dim3(ncx * ncy * ncz), dim3(kBlock), 0, st, a, g, ncx, ncy);
+      else
+        hipLaunchKernelGGL((k_inner_march<false>), dim3(ncx * ncy * ncz), dim3(kBlock), 0, st, a, g, ncx, ncy);
+      return hipGetLastError();
+    }
     if (g.dim == 3) {
       const dim3 grid = tile_grid<3>(g, ntx, nty);
       if (mixed)

@@ -31,6 +31,7 @@ EMRKC_CHECK_FINITE = 1
 EMRKC_EAGER = 2          # library-internal flag: no HIP-graph replay
 EMRKC_FUSE = 4           # library-internal flag: fused tail+head kernel
 EMRKC_FLAT = 8           # library-internal flag: flat (untiled) grid kernels
+EMRKC_MARCH = 16         # library-internal flag: z-marching inner kernel, 4 planes per block
 
 
 class Mesh(C.Structure):

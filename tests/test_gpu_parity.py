@@ -187,8 +187,9 @@ def test_linear_model_closed_form_on_gpu(E):
                                               ((37, 11), (900.0, 4.4), "fp64"), ((19, 13, 7), (150.0, 4.4), "fp64")])
 def test_graph_eager_fused_split_and_repeat_are_bitwise_identical(E, n, rho, precision):
     """HIP-graph replay, eager launches, the fused tail+head kernel, the
-    LDS-tiled and the flat kernels, arbitrary call splits and repeated runs
-    all give the same bits (m = 2, 2-D with m = 5, and m = 3)."""
+    LDS-tiled, z-marching (ragged 4-plane columns) and flat kernels,
+    arbitrary call splits and repeated runs all give the same bits (m = 2,
+    2-D with m = 5, and m = 3)."""
     cfg = small_config("c2_3d_crn", n)
     if len(n) == 2:
         cfg["dim"] = 2
@@ -199,9 +200,10 @@ def test_graph_eager_fused_split_and_repeat_are_bitwise_identical(E, n, rho, pre
     V5, z5, st5 = gpu_run(cfg, 80, rho, precision=precision, flags=E.EMRKC_FUSE)
     V6, z6, _ = gpu_run(cfg, 80, rho, precision=precision, flags=E.EMRKC_FLAT)
     V7, z7, _ = gpu_run(cfg, 80, rho, precision=precision, flags=E.EMRKC_FLAT | E.EMRKC_EAGER)
+    V8, z8, _ = gpu_run(cfg, 80, rho, precision=precision, flags=E.EMRKC_MARCH)
     assert st1.used_graph == 1 and st2.used_graph == 0
     assert st1.kernels_per_step == st1.m and st5.kernels_per_step == st5.m - 1
-    for V, z in [(V2, z2), (V3, z3), (V4, z4), (V5, z5), (V6, z6), (V7, z7)]:
+    for V, z in [(V2, z2), (V3, z3), (V4, z4), (V5, z5), (V6, z6), (V7, z7), (V8, z8)]:
         assert np.array_equal(V, V1) and np.array_equal(z, z1)
 
 
