@@ -57,11 +57,13 @@ def bytes_per_node(kind, nz, wz, m, mat=0):
 
 
 class Job:
-    def __init__(self, cfg, precision, stream, flags=0, tet=None):
+    def __init__(self, cfg, precision, stream, flags=0, tet=None, batch=None):
         from paper_2401_01745_amd import emrkc as E
         self.E = E
         self.cfg = cfg
-        if tet is not None:
+        if batch is not None:
+            self.sim = E.simulation_from_batch(batch, precision=precision, flags=flags)
+        elif tet is not None:
             self.sim = E.simulation_from_tet_config(cfg, tet[0], tet[1], precision=precision, flags=flags)
         else:
             self.sim = E.simulation_from_config(cfg, precision=precision, flags=flags)
@@ -91,11 +93,15 @@ def time_jobs(job, warmup, steps, torch):
 
 def cpu_baseline(cfg, seconds, tet=None):
     """The FP64 oracle on the same workload, timed for a bounded number of
-    emRKC steps on the full mesh (assembly and radii excluded)."""
+    emRKC steps on the full mesh (assembly and radii excluded).  For the
+    ensemble the sample is its first instance."""
     from oracle.emrkc import emrkc_step, stage_counts
     from oracle.monodomain import build_grid_problem, build_tet_problem
     from oracle.powiter import compute_rho, random_unit_interval
-    prob = build_tet_problem(cfg, *tet) if tet is not None else build_grid_problem(cfg)
+    if tet is not None:
+        prob = build_tet_problem(cfg, *tet)
+    else:
+        prob = build_grid_problem(cfg, stim_mask=cfg.get("mask"))
     y = prob.uniform_state()
     v0 = random_unit_interval(y.size, 0)
     _, rF, _, _ = compute_rho(0.0, y, prob.f_F, v0.copy())
@@ -137,7 +143,13 @@ def main():
     E.lib()
     torch.cuda.set_device(0)
     tet = None
-    if args.config.startswith("c3"):
+    batch = None
+    if args.config.startswith("c4"):
+        from workloads.ensemble import ensemble
+        batch = ensemble()
+        cfg = dict(batch[0], name="c4_ensemble64", T=batch[0]["T"])
+        N = int(sum(np.prod(c["n"]) for c in batch))
+    elif args.config.startswith("c3"):
         from workloads.tetmesh import build_shell, shell_config
         cfg = shell_config()
         tet = build_shell(cfg)
@@ -157,7 +169,7 @@ def main():
     with torch.cuda.stream(stream):
         log("bench: %s, N=%d, building FP64 context" % (cfg["name"], N))
         flags = E.EMRKC_FUSE if args.fuse else 0
-        job = Job(cfg, "fp64", stream, flags, tet)
+        job = Job(cfg, "fp64", stream, flags, tet, batch)
         elapsed, (rF, rS, itF, itS) = time_jobs(job, args.warmup, args.steps, torch)
         s, m, eta = E.emrkc_stages(job.sim.ctx, cfg["dt"])
         value = N * job.nsim * args.steps / elapsed
@@ -173,7 +185,12 @@ def main():
         dom_ms = prof[dom][0]
         width = E.lib().emrkc_ell_width(job.sim.ctx) if tet is not None else 0
         mat = width * (4 + 8)
-        db = bytes_per_node(dom, nz, 8, m, mat) * N
+        if batch is not None:
+            off, ms, _, _ = E.emrkc_batch_info(job.sim.ctx, cfg["dt"])
+            sizes = np.diff(off)
+            db = int(sum(n * bytes_per_node("head", nz, 8, mk) for n, mk in zip(sizes, ms)))
+        else:
+            db = bytes_per_node(dom, nz, 8, m, mat) * N
         dom_gbs = db / (dom_ms * 1e-3) / 1e9
         prof_path = os.path.join(ROOT, "profiles", "traffic_k_%s_%s_fp64.json" % (dom, cfg["name"]))
         traffic = None
@@ -186,7 +203,10 @@ def main():
                  "head": "k_head (exponential Euler, ionic model, outer z recurrence, first inner stage)"}
         # the inner kernel in this pass is the last inner stage (stencil +
         # Chebyshev recurrence + outer V update) when m == 2
-        ib = bytes_per_node("tail" if m == 2 else "inner", nz, 8, m, mat) * N
+        if batch is not None:
+            ib = int(sum(n * bytes_per_node("tail", nz, 8, 2) for n, mk in zip(sizes, ms) if mk == 2))
+        else:
+            ib = bytes_per_node("tail" if m == 2 else "inner", nz, 8, m, mat) * N
         inner_gbs = ib / (prof["inner"][0] * 1e-3) / 1e9 if prof["inner"][1] else None
         roof = {"kernel": names[dom], "bound": "hbm", "achieved": round(dom_gbs, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(dom_gbs / HBM_PEAK_GBS, 4), "traffic": traffic,
@@ -200,7 +220,7 @@ def main():
         mixed = None
         if not args.no_mixed:
             log("bench: mixed FP32 form")
-            jm = Job(cfg, "mixed", stream, flags, tet)
+            jm = Job(cfg, "mixed", stream, flags, tet, batch)
             el_m, _ = time_jobs(jm, 1, max(1, args.steps // 2), torch)
             value_m = N * jm.nsim * max(1, args.steps // 2) / el_m
             Vm = jm.sim.V.cpu().numpy()
@@ -227,7 +247,9 @@ def main():
            "config": {"workload": "%s: %s (%d nodes), %s, chi=%g/mm, Cm=%g uF/mm^2, sigma=%s, dt=%g ms, "
                                   "T=%g ms; one bench step = init + power iteration + %d emRKC steps"
                                   % (cfg["name"], ("P1 tetrahedral shell %s" % "x".join(map(str, cfg["dims"])))
-                                     if tet is not None else ("Q1 grid %s" % "x".join(map(str, cfg["n"]))),
+                                     if tet is not None else
+                                     ("ensemble of %d 2-D/3-D Q1 slabs, one batched context" % len(batch))
+                                     if batch is not None else ("Q1 grid %s" % "x".join(map(str, cfg["n"]))),
                                      N, cfg["model"], cfg["chi"], cfg["Cm"], list(cfg["sigma"]), cfg["dt"], cfg["T"],
                                      job.nsim),
                       "s": s, "m": m, "eta": eta, "rho_F": rF, "rho_S": rS, "powiter_iters": [itF, itS]},

@@ -228,6 +228,35 @@ int emrkc_profile_step(emrkc_ctx *ctx, emrkc_state *state, double dt, int64_t ns
 /* Statistics of the last emrkc_step call. */
 int emrkc_last_stats(const emrkc_ctx *ctx, emrkc_stats *out);
 
+/* ---- batched ensembles ---------------------------------------------------- */
+
+/* Creates one context for n_inst independent instances advanced together
+ * (same ionic model, precision and time step; own Q1 grid, conductivity,
+ * chi, Cm, stimulus and spectral radii).  meshes, conds and params are
+ * arrays of n_inst entries; precision, eps, rho_safety, flags and the
+ * power-iteration settings are taken from params[0].  Instances are
+ * concatenated: instance k owns nodes [off_k, off_k + N_k) of V and of every
+ * z plane, planes are N_total apart (offsets from emrkc_batch_info).  Every
+ * call above accepts a batch context: the state holds N_total nodes,
+ * emrkc_estimate_rho estimates each instance's radii (the outputs are the
+ * largest ones), and emrkc_step advances all instances with one launch per
+ * stage.  The outer stage count s is common (from the largest rho_S) and
+ * must be 1 (EMRKC_EUNSUPPORTED otherwise); each instance uses its own
+ * inner stage count m_k.  emrkc_eval_rhs_slow rejects batch contexts. */
+int emrkc_create_batch(int n_inst, const emrkc_mesh *meshes, const emrkc_conductivity *conds, int ionic_model,
+                       const emrkc_params *params, emrkc_ctx **out);
+
+/* Number of instances (1 for a single context), -1 for NULL. */
+int emrkc_batch_size(const emrkc_ctx *ctx);
+
+/* offsets[n_inst + 1] (node offsets, last = N_total), m[n_inst] (inner stage
+ * counts at dt; 0 before radii are known), rho_F[n_inst], rho_S[n_inst];
+ * any output may be NULL. */
+int emrkc_batch_info(const emrkc_ctx *ctx, double dt, int64_t *offsets, int *m, double *rho_F, double *rho_S);
+
+/* Sets every instance's radii (taken as given). */
+int emrkc_batch_set_rho(emrkc_ctx *ctx, const double *rho_F, const double *rho_S);
+
 /* ---- evaluation of single terms (component checks) ---------------------- */
 
 /* out[i] = ((chi Cm M_L)^{-1} A V)_i for i < N: the V component of f_F

@@ -32,6 +32,37 @@ struct GraphKey {
   }
 };
 
+// One instance of a batched ensemble.
+struct Inst {
+  Mesh mesh;
+  uint32_t off = 0, N = 0;
+  double chi = 0, Cm = 0, amp = 0, t_on = 0, t_off = -1;
+  double rho_F = 0, rho_S = 0;
+  bool have_rho = false;
+  bool warm_F = false, warm_S = false;
+  int sel_F = 0, sel_S = 0;
+  double raw_F = 0, raw_S = 0, nv_F = 0, nv_S = 0;
+  int m = 0;  // inner stages of the current plan
+};
+
+// Device tables of the batched step for one (dt, radii): per parity of the
+// step (V^n in X[n % 2]) one head launch over all instances and one launch
+// per inner stage k = 2..m_max over the instances with m_i >= k.
+struct BatchLaunch {
+  BatchInst *tab = nullptr;
+  uint16_t *map = nullptr;
+  uint32_t nblocks = 0;
+};
+struct BatchDev {
+  bool valid = false;
+  uint64_t dt_bits = 0;
+  const void *V = nullptr, *z = nullptr;  // state buffers the tables point into
+  int s = 0, m_max = 0;
+  double eta = 0;
+  BatchLaunch head[2];
+  std::vector<BatchLaunch> inner[2];
+};
+
 struct emrkc_ctx {
   // problem
   int mesh_kind = 0;
@@ -52,7 +83,12 @@ struct emrkc_ctx {
   double rho_F = 0, rho_S = 0;
   bool have_rho = false;
   bool warm_F = false, warm_S = false;
+  int sel_F = 0, sel_S = 0;
   double raw_F = 0, raw_S = 0, nv_F = 0, nv_S = 0;
+  // batched ensembles (emrkc_create_batch)
+  bool batch = false;
+  std::vector<struct Inst> inst;
+  BatchDev bdev;
   // device data
   Mesh mesh{};
   uint8_t *d_mask = nullptr;
@@ -258,7 +294,30 @@ static void grid_weights(int dim, const double *h, const double *sig, double chi
   }
 }
 
+static void free_batch_tables(emrkc_ctx *c) {
+  auto rel = [](BatchLaunch &b) {
+    if (b.tab) (void)hipFree(b.tab);
+    if (b.map) (void)hipFree(b.map);
+    b = BatchLaunch{};
+  };
+  for (int p = 0; p < 2; ++p) {
+    rel(c->bdev.head[p]);
+    for (auto &b : c->bdev.inner[p]) rel(b);
+    c->bdev.inner[p].clear();
+  }
+  c->bdev.valid = false;
+}
+
+static void clear_graphs(emrkc_ctx *c) {
+  for (auto &kv : c->graphs) (void)hipGraphExecDestroy(kv.second);
+  c->graphs.clear();
+}
+
 static void free_ctx(emrkc_ctx *c) {
+  if (c->batch) {
+    (void)hipDeviceSynchronize();
+    free_batch_tables(c);
+  }
   for (auto &kv : c->graphs) (void)hipGraphExecDestroy(kv.second);
   c->graphs.clear();
   void *ptrs[] = {c->d_mask, c->d_ell_col, c->d_ell_w64, c->d_ell_w32, c->d_V1, c->d_U[0], c->d_U[1],
@@ -485,6 +544,14 @@ extern "C" int emrkc_set_rho(emrkc_ctx *c, double rho_F, double rho_S) {
   c->rho_F = rho_F;
   c->rho_S = rho_S;
   c->have_rho = true;
+  for (auto &I : c->inst) {
+    I.rho_F = rho_F;
+    I.rho_S = rho_S;
+  }
+  if (c->batch) {
+    clear_graphs(c);
+    c->bdev.valid = false;
+  }
   return EMRKC_OK;
 }
 
@@ -702,9 +769,13 @@ static int enqueue_chunk_s1m1(emrkc_ctx *c, const emrkc_state *st, const StepPla
   return EMRKC_OK;
 }
 
+static int enqueue_chunk_batch(emrkc_ctx *c, const emrkc_state *st, const StepPlan &P, double dt, int L,
+                               hipStream_t strm, KernelTimer *tm);
+
 static int enqueue_chunk(emrkc_ctx *c, const emrkc_state *st, const StepPlan &P, double dt, int L, hipStream_t strm,
                          KernelTimer *tm = nullptr) {
   set_flat_kernels(c->flat);
+  if (c->batch) return enqueue_chunk_batch(c, st, P, dt, L, strm, tm);
   if (c->use_fused && P.s == 1 && P.m >= 2 && fused_supported(c->mesh))
     return enqueue_chunk_fused(c, st, P, dt, L, strm, tm);
   if (P.s == 1 && P.m == 1) return enqueue_chunk_s1m1(c, st, P, dt, L, strm, tm);
@@ -721,6 +792,31 @@ static int ensure_z1(emrkc_ctx *c) {
   return dalloc(c, &c->d_z1, zb);
 }
 
+static int build_batch_tables(emrkc_ctx *c, const emrkc_state *st, double dt, const StepPlan &P);
+
+// (s, m, eta) and the coefficient tables for dt; for a batch, s and eta are
+// common (from the largest rho_S) and m is the largest per-instance m.
+static int make_plan(emrkc_ctx *c, double dt, StepPlan &P) {
+  int rc = emrkc_stage_counts(dt, c->rho_F, c->rho_S, c->eps, &P.s, &P.m, &P.eta);
+  if (rc != EMRKC_OK) return fail(c, rc, "stage selection failed (dt=%g rho_F=%g rho_S=%g)", dt, c->rho_F, c->rho_S);
+  if (c->batch) {
+    if (P.s != 1) return fail(c, EMRKC_EUNSUPPORTED, "batched ensembles need s = 1 (dt=%g gives s=%d)", dt, P.s);
+    P.m = 1;
+    for (auto &I : c->inst) {
+      int si, mi;
+      double ei;
+      rc = emrkc_stage_counts(dt, I.rho_F, c->rho_S, c->eps, &si, &mi, &ei);
+      if (rc != EMRKC_OK) return fail(c, rc, "stage selection failed for an instance");
+      I.m = mi;
+      P.m = std::max(P.m, mi);
+    }
+  }
+  rkc_coeffs(P.s, c->eps, P.mu, P.nu, P.ka, P.cc);
+  rkc_coeffs(P.m, c->eps, P.mui, P.nui, P.kai, P.cci);
+  if (P.s >= 2 && (rc = ensure_z1(c)) != EMRKC_OK) return rc;
+  return EMRKC_OK;
+}
+
 extern "C" int emrkc_step(emrkc_ctx *c, emrkc_state *st, double dt, int64_t nsteps) {
   if (c == nullptr) return EMRKC_EINVAL;
   if (!state_ok(c, st)) return fail(c, EMRKC_EINVAL, "state buffers missing");
@@ -728,11 +824,9 @@ extern "C" int emrkc_step(emrkc_ctx *c, emrkc_state *st, double dt, int64_t nste
   if (!c->have_rho) return fail(c, EMRKC_EINVAL, "spectral radii not set: call emrkc_estimate_rho or emrkc_set_rho");
   if (nsteps == 0) return EMRKC_OK;
   StepPlan P;
-  int rc = emrkc_stage_counts(dt, c->rho_F, c->rho_S, c->eps, &P.s, &P.m, &P.eta);
-  if (rc != EMRKC_OK) return fail(c, rc, "stage selection failed (dt=%g rho_F=%g rho_S=%g)", dt, c->rho_F, c->rho_S);
-  rkc_coeffs(P.s, c->eps, P.mu, P.nu, P.ka, P.cc);
-  rkc_coeffs(P.m, c->eps, P.mui, P.nui, P.kai, P.cci);
-  if (P.s >= 2 && (rc = ensure_z1(c)) != EMRKC_OK) return rc;
+  int rc = make_plan(c, dt, P);
+  if (rc != EMRKC_OK) return rc;
+  if (c->batch && (rc = build_batch_tables(c, st, dt, P)) != EMRKC_OK) return rc;
 
   HIP_TRY(c, launch_clock_set(c->d_clock, st->step, st->t0, c->stream));
   const bool eager = (c->flags & EMRKC_EAGER_FLAG) != 0 || getenv("EMRKC_EAGER") != nullptr;
@@ -785,7 +879,8 @@ extern "C" int emrkc_step(emrkc_ctx *c, emrkc_state *st, double dt, int64_t nste
   c->last.s = P.s;
   c->last.m = P.m;
   c->last.eta = P.eta;
-  c->last.kernels_per_step = (c->use_fused && P.s == 1 && P.m >= 2 && fused_supported(c->mesh))
+  c->last.kernels_per_step = c->batch ? (int64_t)P.m
+                              : (c->use_fused && P.s == 1 && P.m >= 2 && fused_supported(c->mesh))
                                  ? (int64_t)P.m - 1
                                  : (P.s == 1 && P.m == 1) ? 1 : (int64_t)P.s * P.m + (P.m == 1 ? 1 : 0);
   c->last.used_graph = used_graph ? 1 : 0;
@@ -821,11 +916,9 @@ extern "C" int emrkc_profile_step(emrkc_ctx *c, emrkc_state *st, double dt, int6
   if (!(dt > 0) || !isfinite(dt) || nsteps < 1 || nsteps > 100000) return fail(c, EMRKC_EINVAL, "invalid dt or nsteps");
   if (!c->have_rho) return fail(c, EMRKC_EINVAL, "spectral radii not set");
   StepPlan P;
-  int rc = emrkc_stage_counts(dt, c->rho_F, c->rho_S, c->eps, &P.s, &P.m, &P.eta);
-  if (rc != EMRKC_OK) return fail(c, rc, "stage selection failed");
-  rkc_coeffs(P.s, c->eps, P.mu, P.nu, P.ka, P.cc);
-  rkc_coeffs(P.m, c->eps, P.mui, P.nui, P.kai, P.cci);
-  if (P.s >= 2 && (rc = ensure_z1(c)) != EMRKC_OK) return rc;
+  int rc = make_plan(c, dt, P);
+  if (rc != EMRKC_OK) return rc;
+  if (c->batch && (rc = build_batch_tables(c, st, dt, P)) != EMRKC_OK) return rc;
   HIP_TRY(c, launch_clock_set(c->d_clock, st->step, st->t0, c->stream));
   KernelTimer tm;
   rc = enqueue_chunk(c, st, P, dt, (int)nsteps, c->stream, &tm);
@@ -865,105 +958,130 @@ static int fetch(emrkc_ctx *c, double *out) {
   return EMRKC_OK;
 }
 
+// One instance seen by the power iteration: its operator, its node range
+// (component planes `stride` apart) and its warm-start data.  The warm
+// vectors live in two buffers; sel says which one holds the current v.
+struct RhoView {
+  Mesh mesh;
+  uint32_t N;
+  size_t stride;
+  const double *V;
+  const void *z;
+  StimArgs stim;
+  double Cm;
+  double *vF[2], *vS[2], *zV;
+  int *selF, *selS;
+  bool *warm_F, *warm_S;
+  double *raw_F, *raw_S, *nv_F, *nv_S;
+};
+
+// Compute_Rho of the appendix for f_F and f_S of one instance.
+static int estimate_view(emrkc_ctx *c, const RhoView &v, double t, int *iters_F, int *iters_S, bool *noconv) {
+  int rc;
+  double ny2 = 0;
+  HIP_TRY(c, launch_norm2_state(c->mixed, v.N, v.stride, c->nv - 1, v.V, v.z, c->d_partials, c->d_result, c->stream));
+  if ((rc = fetch(c, &ny2))) return rc;
+  const double ny = sqrt(ny2);
+  const double delta = ny > 0 ? ny * c->pi_eps : c->pi_eps;
+  for (int which = 0; which < 2; ++which) {
+    bool &warm = which == 0 ? *v.warm_F : *v.warm_S;
+    int &sel = which == 0 ? *v.selF : *v.selS;
+    double *const *buf = which == 0 ? v.vF : v.vS;
+    double &raw = which == 0 ? *v.raw_F : *v.raw_S;
+    double &nvs = which == 0 ? *v.nv_F : *v.nv_S;
+    double nv;
+    if (warm) {
+      nv = nvs;
+    } else {
+      double s2;
+      HIP_TRY(c, launch_norm2_random(c->pi_seed, (uint64_t)v.N * c->nv, c->d_partials, c->d_result, c->stream));
+      if ((rc = fetch(c, &s2))) return rc;
+      nv = sqrt(s2);
+    }
+    double q = delta / nv, rho = warm ? raw : 0.0, rho_old = 0.0;
+    int it = 0;
+    while (fabs(rho - rho_old) >= c->pi_tol * rho) {
+      if (it >= c->pi_max_iter) {
+        *noconv = true;
+        break;
+      }
+      rho_old = rho;
+      const double *vin = warm ? buf[sel] : nullptr;
+      double *vout = buf[1 - sel];
+      if (which == 0) {
+        // only the V component of v enters f_F(y + q v) - f_F(y)
+        HIP_TRY(c, launch_powF_shift(v.N, v.V, vin, c->pi_seed, q, v.zV, c->stream));
+        HIP_TRY(c, launch_powF_diff(c->mixed, v.mesh, v.zV, v.V, vout, c->d_partials, c->d_result, c->stream));
+      } else {
+        // f_S on (V, z_E, z_S); the gate components of f_S vanish
+        HIP_TRY(c, launch_powS_iter(c->model, c->mixed, v.N, v.stride, v.V, v.z, vin, c->pi_seed, q, t, v.stim, v.Cm,
+                                    c->mp, vout, c->d_partials, c->d_result, c->stream));
+      }
+      double s2;
+      if ((rc = fetch(c, &s2))) return rc;
+      sel = 1 - sel;
+      warm = true;
+      nv = sqrt(s2);
+      ++it;
+      if (nv == 0.0) {
+        rho = 0.0;
+        break;
+      }
+      q = delta / nv;
+      rho = nv / delta;
+    }
+    raw = rho;
+    nvs = nv;
+    if (which == 0 && iters_F) *iters_F = it;
+    if (which == 1 && iters_S) *iters_S = it;
+  }
+  return EMRKC_OK;
+}
+
+static int alloc_rho_buffers(emrkc_ctx *c) {
+  if (c->d_vF[0]) return EMRKC_OK;
+  const size_t vb = sizeof(double) * (size_t)c->N;
+  int rc;
+  if ((rc = dalloc(c, (void **)&c->d_vF[0], vb)) || (rc = dalloc(c, (void **)&c->d_vF[1], vb)) ||
+      (rc = dalloc(c, (void **)&c->d_zV, vb)) || (rc = dalloc(c, (void **)&c->d_vS[0], vb * (1 + c->ns))) ||
+      (rc = dalloc(c, (void **)&c->d_vS[1], vb * (1 + c->ns))))
+    return rc;
+  return EMRKC_OK;
+}
+
+static int estimate_batch(emrkc_ctx *c, const emrkc_state *st, double *rho_F, double *rho_S, int *iters_F,
+                          int *iters_S);
+
 extern "C" int emrkc_estimate_rho(emrkc_ctx *c, const emrkc_state *st, double *rho_F, double *rho_S, int *iters_F,
                                   int *iters_S) {
   if (c == nullptr) return EMRKC_EINVAL;
   if (!state_ok(c, st)) return fail(c, EMRKC_EINVAL, "state buffers missing");
-  const uint32_t N = (uint32_t)c->N;
-  const size_t vb = sizeof(double) * (size_t)N;
-  int rc;
-  if (!c->d_vF[0]) {
-    if ((rc = dalloc(c, (void **)&c->d_vF[0], vb)) || (rc = dalloc(c, (void **)&c->d_vF[1], vb)) ||
-        (rc = dalloc(c, (void **)&c->d_zV, vb)) ||
-        (rc = dalloc(c, (void **)&c->d_vS[0], vb * (1 + c->ns))) ||
-        (rc = dalloc(c, (void **)&c->d_vS[1], vb * (1 + c->ns))))
-      return rc;
-  }
-  const double *yV = (const double *)st->V;
-  double ny2 = 0;
-  HIP_TRY(c, launch_norm2_state(c->mixed, N, c->nv - 1, yV, st->z, c->d_partials, c->d_result, c->stream));
-  if ((rc = fetch(c, &ny2))) return rc;
-  const double ny = sqrt(ny2);
-  const double delta = ny > 0 ? ny * c->pi_eps : c->pi_eps;
-  const double t = st->t;
+  int rc = alloc_rho_buffers(c);
+  if (rc != EMRKC_OK) return rc;
+  if (c->batch) return estimate_batch(c, st, rho_F, rho_S, iters_F, iters_S);
+  RhoView v{};
+  v.mesh = c->mesh;
+  v.N = (uint32_t)c->N;
+  v.stride = (size_t)c->N;
+  v.V = (const double *)st->V;
+  v.z = st->z;
+  v.stim = stim_args(c);
+  v.Cm = c->Cm;
+  v.vF[0] = c->d_vF[0];
+  v.vF[1] = c->d_vF[1];
+  v.vS[0] = c->d_vS[0];
+  v.vS[1] = c->d_vS[1];
+  v.zV = c->d_zV;
+  v.selF = &c->sel_F;
+  v.selS = &c->sel_S;
+  v.warm_F = &c->warm_F;
+  v.warm_S = &c->warm_S;
+  v.raw_F = &c->raw_F;
+  v.raw_S = &c->raw_S;
+  v.nv_F = &c->nv_F;
+  v.nv_S = &c->nv_S;
   bool noconv = false;
-
-  // f_F: only the V component of v enters f_F(y + q v) - f_F(y)
-  {
-    double nv;
-    if (c->warm_F) {
-      nv = c->nv_F;
-    } else {
-      double s2;
-      HIP_TRY(c, launch_norm2_random(c->pi_seed, (uint64_t)N * c->nv, c->d_partials, c->d_result, c->stream));
-      if ((rc = fetch(c, &s2))) return rc;
-      nv = sqrt(s2);
-    }
-    double q = delta / nv, rho = c->warm_F ? c->raw_F : 0.0, rho_old = 0.0;
-    int it = 0;
-    while (fabs(rho - rho_old) >= c->pi_tol * rho) {
-      if (it >= c->pi_max_iter) {
-        noconv = true;
-        break;
-      }
-      rho_old = rho;
-      HIP_TRY(c, launch_powF_shift(N, yV, c->warm_F ? c->d_vF[0] : nullptr, c->pi_seed, q, c->d_zV, c->stream));
-      HIP_TRY(c, launch_powF_diff(c->mixed, c->mesh, c->d_zV, yV, c->d_vF[1], c->d_partials, c->d_result, c->stream));
-      double s2;
-      if ((rc = fetch(c, &s2))) return rc;
-      std::swap(c->d_vF[0], c->d_vF[1]);
-      c->warm_F = true;
-      nv = sqrt(s2);
-      ++it;
-      if (nv == 0.0) {
-        rho = 0.0;
-        break;
-      }
-      q = delta / nv;
-      rho = nv / delta;
-    }
-    c->raw_F = rho;
-    c->nv_F = nv;
-    if (iters_F) *iters_F = it;
-  }
-  // f_S on (V, z_E, z_S); the gate components of f_S vanish
-  {
-    double nv;
-    if (c->warm_S) {
-      nv = c->nv_S;
-    } else {
-      double s2;
-      HIP_TRY(c, launch_norm2_random(c->pi_seed, (uint64_t)N * c->nv, c->d_partials, c->d_result, c->stream));
-      if ((rc = fetch(c, &s2))) return rc;
-      nv = sqrt(s2);
-    }
-    double q = delta / nv, rho = c->warm_S ? c->raw_S : 0.0, rho_old = 0.0;
-    int it = 0;
-    while (fabs(rho - rho_old) >= c->pi_tol * rho) {
-      if (it >= c->pi_max_iter) {
-        noconv = true;
-        break;
-      }
-      rho_old = rho;
-      HIP_TRY(c, launch_powS_iter(c->model, c->mixed, N, yV, st->z, c->warm_S ? c->d_vS[0] : nullptr, c->pi_seed, q,
-                                  t, stim_args(c), c->Cm, c->mp, c->d_vS[1], c->d_partials, c->d_result, c->stream));
-      double s2;
-      if ((rc = fetch(c, &s2))) return rc;
-      std::swap(c->d_vS[0], c->d_vS[1]);
-      c->warm_S = true;
-      nv = sqrt(s2);
-      ++it;
-      if (nv == 0.0) {
-        rho = 0.0;
-        break;
-      }
-      q = delta / nv;
-      rho = nv / delta;
-    }
-    c->raw_S = rho;
-    c->nv_S = nv;
-    if (iters_S) *iters_S = it;
-  }
+  if ((rc = estimate_view(c, v, st->t, iters_F, iters_S, &noconv)) != EMRKC_OK) return rc;
   c->rho_F = c->safety * c->raw_F;
   c->rho_S = c->safety * c->raw_S;
   c->have_rho = true;
@@ -978,6 +1096,12 @@ extern "C" int emrkc_estimate_rho(emrkc_ctx *c, const emrkc_state *st, double *r
 // ---------------------------------------------------------------------------
 extern "C" int emrkc_apply_diffusion(emrkc_ctx *c, const double *V, double *out) {
   if (c == nullptr) return EMRKC_EINVAL;
+  if (c->batch) {
+    if (V == nullptr || out == nullptr || (const void *)V == (const void *)out)
+      return fail(c, EMRKC_EINVAL, "invalid buffers");
+    for (auto &I : c->inst) HIP_TRY(c, launch_apply_diffusion(c->mixed, I.mesh, V + I.off, out + I.off, c->stream));
+    return EMRKC_OK;
+  }
   if (V == nullptr || out == nullptr || (const void *)V == (const void *)out)
     return fail(c, EMRKC_EINVAL, "invalid buffers");
   HIP_TRY(c, launch_apply_diffusion(c->mixed, c->mesh, V, out, c->stream));
@@ -986,6 +1110,7 @@ extern "C" int emrkc_apply_diffusion(emrkc_ctx *c, const double *V, double *out)
 
 extern "C" int emrkc_eval_rhs_slow(emrkc_ctx *c, const emrkc_state *st, double t, double *out) {
   if (c == nullptr) return EMRKC_EINVAL;
+  if (c->batch) return fail(c, EMRKC_EUNSUPPORTED, "emrkc_eval_rhs_slow takes single-instance contexts");
   if (!state_ok(c, st) || out == nullptr) return fail(c, EMRKC_EINVAL, "invalid buffers");
   HIP_TRY(c, launch_eval_rhs_slow(c->model, c->mixed, (uint32_t)c->N, (const double *)st->V, st->z, t, stim_args(c),
                                   c->Cm, c->mp, out, c->stream));
@@ -1105,5 +1230,354 @@ static int build_p1(emrkc_ctx *c, const emrkc_mesh *mesh, const emrkc_conductivi
   c->mesh.ell.w64 = c->d_ell_w64;
   c->mesh.ell.w32 = c->d_ell_w32;
   c->dim = 3;
+  return EMRKC_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Batched ensembles
+// ---------------------------------------------------------------------------
+extern "C" int emrkc_create_batch(int n_inst, const emrkc_mesh *meshes, const emrkc_conductivity *conds,
+                                  int ionic_model, const emrkc_params *params, emrkc_ctx **out) {
+  if (out == nullptr) return EMRKC_EINVAL;
+  *out = nullptr;
+  if (n_inst < 1 || n_inst > 65535 || meshes == nullptr || conds == nullptr || params == nullptr)
+    return EMRKC_EINVAL;
+  if (model_gates(ionic_model) < 0) return EMRKC_EINVAL;
+  const emrkc_params &p0 = params[0];
+  if (p0.precision != EMRKC_FP64 && p0.precision != EMRKC_MIXED32) return EMRKC_EINVAL;
+  if (!(p0.eps > 0) || !(p0.eps < 1) || !(p0.rho_safety >= 1.0)) return EMRKC_EINVAL;
+  if (!(p0.powiter_tol > 0) || !(p0.powiter_eps > 0) || p0.powiter_max_iter < 1) return EMRKC_EINVAL;
+  int64_t Ntot = 0;
+  for (int k = 0; k < n_inst; ++k) {
+    const emrkc_mesh &m = meshes[k];
+    const emrkc_params &p = params[k];
+    if (m.kind != EMRKC_MESH_Q1_GRID) return EMRKC_EUNSUPPORTED;
+    if (m.dim != 2 && m.dim != 3) return EMRKC_EINVAL;
+    int64_t N = 1;
+    for (int d = 0; d < m.dim; ++d) {
+      if (m.n[d] < 2 || m.n[d] > (1 << 30) || !(m.h[d] > 0) || !isfinite(m.h[d])) return EMRKC_EINVAL;
+      N *= m.n[d];
+    }
+    if (!(p.chi > 0) || !(p.Cm > 0) || !isfinite(p.chi) || !isfinite(p.Cm)) return EMRKC_EINVAL;
+    if (!isfinite(p.stim_amp) || !isfinite(p.stim_t_on) || !isfinite(p.stim_t_off)) return EMRKC_EINVAL;
+    const double sg[3] = {conds[k].sigma_l, conds[k].sigma_t, conds[k].sigma_n};
+    for (int d = 0; d < m.dim; ++d)
+      if (!(sg[d] >= 0) || !isfinite(sg[d])) return EMRKC_EINVAL;
+    Ntot += N;
+  }
+  if (Ntot >= (int64_t)1 << 31) return EMRKC_EUNSUPPORTED;
+
+  emrkc_ctx *c = new (std::nothrow) emrkc_ctx();
+  if (c == nullptr) return EMRKC_ENOMEM;
+  c->batch = true;
+  c->mesh_kind = EMRKC_MESH_Q1_GRID;
+  c->N = Ntot;
+  c->model = ionic_model;
+  c->ng = model_gates(ionic_model);
+  c->ns = model_slow(ionic_model);
+  c->nv = 1 + c->ng + c->ns;
+  c->mixed = p0.precision == EMRKC_MIXED32;
+  c->flags = p0.flags;
+  c->chi = p0.chi;
+  c->Cm = p0.Cm;
+  c->eps = p0.eps;
+  c->safety = p0.rho_safety;
+  c->mp.lin_a = p0.linear_a;
+  c->mp.lin_lamE = p0.linear_lambda_E;
+  c->pi_tol = p0.powiter_tol;
+  c->pi_eps = p0.powiter_eps;
+  c->pi_max_iter = p0.powiter_max_iter;
+  c->pi_seed = p0.powiter_seed;
+  c->mesh.kind = kGrid;
+  c->inst.resize(n_inst);
+  std::vector<uint8_t> mask((size_t)Ntot, 0);
+  bool any_mask = false, all_rho = true;
+  uint32_t off = 0;
+  for (int k = 0; k < n_inst; ++k) {
+    const emrkc_mesh &m = meshes[k];
+    const emrkc_params &p = params[k];
+    Inst &I = c->inst[k];
+    Grid &g = I.mesh.grid;
+    I.mesh.kind = kGrid;
+    g.dim = m.dim;
+    g.n0 = (uint32_t)m.n[0];
+    g.n1 = (uint32_t)m.n[1];
+    g.n2 = m.dim == 3 ? (uint32_t)m.n[2] : 1u;
+    g.N = g.n0 * g.n1 * g.n2;
+    g.div0 = make_fastdiv(g.n0);
+    g.div1 = make_fastdiv(g.n1);
+    g.inner_variant = 0;
+    g.zc = 1;
+    const double h[3] = {m.h[0], m.h[1], m.dim == 3 ? m.h[2] : 1.0};
+    const double sg[3] = {conds[k].sigma_l, conds[k].sigma_t, conds[k].sigma_n};
+    grid_weights(m.dim, h, sg, p.chi * p.Cm, g.w);
+    I.off = off;
+    I.N = g.N;
+    I.chi = p.chi;
+    I.Cm = p.Cm;
+    I.amp = p.stim_amp;
+    I.t_on = p.stim_t_on;
+    I.t_off = p.stim_t_off;
+    if (p.stim_mask != nullptr) {
+      memcpy(mask.data() + off, p.stim_mask, g.N);
+      any_mask = true;
+    }
+    if (p.rho_F > 0 && p.rho_S > 0) {
+      I.rho_F = p.rho_F;
+      I.rho_S = p.rho_S;
+      I.have_rho = true;
+    } else {
+      all_rho = false;
+    }
+    off += g.N;
+  }
+  if (all_rho) {
+    c->have_rho = true;
+    for (auto &I : c->inst) {
+      c->rho_F = std::max(c->rho_F, I.rho_F);
+      c->rho_S = std::max(c->rho_S, I.rho_S);
+    }
+  }
+  int rc = EMRKC_OK;
+  {
+    const size_t vb = sizeof(double) * (size_t)Ntot;
+    const size_t svb = (c->mixed ? sizeof(float) : sizeof(double)) * (size_t)Ntot;
+    if ((rc = dalloc(c, (void **)&c->d_V1, vb)) || (rc = dalloc(c, (void **)&c->d_U[0], vb)) ||
+        (rc = dalloc(c, (void **)&c->d_U[1], vb)) || (rc = dalloc(c, (void **)&c->d_U[2], vb)) ||
+        (rc = dalloc(c, &c->d_SV, svb)) || (rc = dalloc(c, &c->d_SV2, svb)) ||
+        (rc = dalloc(c, (void **)&c->d_clock, sizeof(Clock))) ||
+        (rc = dalloc(c, (void **)&c->d_result, 2 * sizeof(double))) ||
+        (rc = dalloc(c, (void **)&c->d_flag, sizeof(int))))
+      goto error;
+    const size_t nparts = std::max<size_t>(reduce_blocks((uint32_t)Ntot), 65536);
+    if ((rc = dalloc(c, (void **)&c->d_partials, nparts * sizeof(double)))) goto error;
+    if (any_mask) {
+      if ((rc = dalloc(c, (void **)&c->d_mask, (size_t)Ntot))) goto error;
+      hipError_t e = hipMemcpy(c->d_mask, mask.data(), (size_t)Ntot, hipMemcpyHostToDevice);
+      if (e != hipSuccess) {
+        rc = fail(c, EMRKC_EHIP, "mask upload failed: %s", hipGetErrorString(e));
+        goto error;
+      }
+    }
+    hipError_t e = hipStreamCreateWithFlags(&c->capture, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipMemset(c->d_clock, 0, sizeof(Clock));
+    if (e == hipSuccess) e = hipDeviceSynchronize();
+    if (e != hipSuccess) {
+      rc = fail(c, EMRKC_EHIP, "initialisation failed: %s", hipGetErrorString(e));
+      goto error;
+    }
+  }
+  *out = c;
+  return EMRKC_OK;
+error:
+  free_ctx(c);
+  delete c;
+  return rc;
+}
+
+static int estimate_batch(emrkc_ctx *c, const emrkc_state *st, double *rho_F, double *rho_S, int *iters_F,
+                          int *iters_S) {
+  const size_t Ntot = (size_t)c->N;
+  const size_t zw = c->mixed ? sizeof(float) : sizeof(double);
+  bool noconv = false;
+  int maxF = 0, maxS = 0;
+  c->rho_F = c->rho_S = 0.0;
+  for (auto &I : c->inst) {
+    RhoView v{};
+    v.mesh = I.mesh;
+    v.N = I.N;
+    v.stride = Ntot;
+    v.V = (const double *)st->V + I.off;
+    v.z = (const char *)st->z + zw * I.off;
+    v.stim.mask = c->d_mask ? c->d_mask + I.off : nullptr;
+    v.stim.amp = I.amp;
+    v.stim.t_on = I.t_on;
+    v.stim.t_off = I.t_off;
+    v.Cm = I.Cm;
+    for (int b = 0; b < 2; ++b) {
+      v.vF[b] = c->d_vF[b] + I.off;
+      v.vS[b] = c->d_vS[b] + I.off;
+    }
+    v.zV = c->d_zV + I.off;
+    v.selF = &I.sel_F;
+    v.selS = &I.sel_S;
+    v.warm_F = &I.warm_F;
+    v.warm_S = &I.warm_S;
+    v.raw_F = &I.raw_F;
+    v.raw_S = &I.raw_S;
+    v.nv_F = &I.nv_F;
+    v.nv_S = &I.nv_S;
+    int itF = 0, itS = 0;
+    int rc = estimate_view(c, v, st->t, &itF, &itS, &noconv);
+    if (rc != EMRKC_OK) return rc;
+    maxF = std::max(maxF, itF);
+    maxS = std::max(maxS, itS);
+    I.rho_F = c->safety * I.raw_F;
+    I.rho_S = c->safety * I.raw_S;
+    I.have_rho = true;
+    c->rho_F = std::max(c->rho_F, I.rho_F);
+    c->rho_S = std::max(c->rho_S, I.rho_S);
+  }
+  c->have_rho = true;
+  clear_graphs(c);
+  c->bdev.valid = false;
+  if (rho_F) *rho_F = c->rho_F;
+  if (rho_S) *rho_S = c->rho_S;
+  if (iters_F) *iters_F = maxF;
+  if (iters_S) *iters_S = maxS;
+  if (noconv) return fail(c, EMRKC_ENOCONV, "power iteration reached %d iterations", c->pi_max_iter);
+  return EMRKC_OK;
+}
+
+// Tables of the batched step (see BatchDev): instance coefficients from the
+// instance's own m_i, pointers into the concatenated buffers.
+static int build_batch_tables(emrkc_ctx *c, const emrkc_state *st, double dt, const StepPlan &P) {
+  uint64_t dtb;
+  memcpy(&dtb, &dt, sizeof dtb);
+  if (c->bdev.valid && c->bdev.dt_bits == dtb && c->bdev.V == st->V && c->bdev.z == st->z) return EMRKC_OK;
+  (void)hipStreamSynchronize(c->stream);
+  clear_graphs(c);
+  free_batch_tables(c);
+  double *X[2] = {(double *)st->V, c->d_V1};
+  auto upload = [&](BatchLaunch &L, const std::vector<BatchInst> &tab, const std::vector<uint16_t> &map) -> int {
+    L.nblocks = (uint32_t)map.size();
+    int rc;
+    if ((rc = dalloc(c, (void **)&L.tab, std::max<size_t>(1, tab.size()) * sizeof(BatchInst))) ||
+        (rc = dalloc(c, (void **)&L.map, std::max<size_t>(1, map.size()) * sizeof(uint16_t))))
+      return rc;
+    if (!tab.empty()) HIP_TRY(c, hipMemcpy(L.tab, tab.data(), tab.size() * sizeof(BatchInst), hipMemcpyHostToDevice));
+    if (!map.empty()) HIP_TRY(c, hipMemcpy(L.map, map.data(), map.size() * sizeof(uint16_t), hipMemcpyHostToDevice));
+    return EMRKC_OK;
+  };
+  for (int par = 0; par < 2; ++par) {
+    for (int k = 1; k <= P.m; ++k) {  // k == 1: the head launch
+      std::vector<BatchInst> tab;
+      std::vector<uint16_t> map;
+      for (auto &I : c->inst) {
+        if (I.m < k) continue;
+        std::vector<double> mu, nu, ka, cc;
+        rkc_coeffs(I.m, c->eps, mu, nu, ka, cc);
+        BatchInst b{};
+        b.g = I.mesh.grid;
+        b.off = I.off;
+        b.tile0 = (uint32_t)map.size();
+        const uint32_t nt = grid_tiles(b.g, b.ntx, b.nty);
+        if (k == 1) {
+          HeadArgs &h = b.h;
+          h.Vin = X[par];
+          h.zin = h.zout = st->z;
+          h.SV = c->d_SV;
+          h.uout = I.m == 1 ? X[1 - par] : c->d_U[0];
+          h.clock = c->d_clock;
+          h.stim.mask = c->d_mask;
+          h.stim.amp = I.amp;
+          h.stim.t_on = I.t_on;
+          h.stim.t_off = I.t_off;
+          h.mp = c->mp;
+          h.dt = dt;
+          h.eta = P.eta;
+          h.inv_eta = 1.0 / P.eta;
+          h.Cm = I.Cm;
+          h.c_prev = 0.0;
+          h.mu_dt = P.mu[1] * dt;
+          h.mu1_eta = mu[1] * P.eta;
+          h.cm_eta = cc[I.m] * P.eta;
+          h.j1 = 1;
+          h.m_is_one = I.m == 1;
+        } else {
+          InnerArgs &a = b.in;
+          a.t.nu = nu[k];
+          a.t.kappa = ka[k];
+          a.t.mu_eta = mu[k] * P.eta;
+          a.t.inv_eta = 1.0 / P.eta;
+          a.t.mu_dt = P.mu[1] * dt;
+          a.t.j1 = 1;
+          a.t.uprev = c->d_U[(k - 2) % 2];
+          a.t.uprev2 = k == 2 ? X[par] : c->d_U[(k - 3) % 2];
+          a.t.SV = c->d_SV;
+          a.t.Vin = X[par];
+          a.last = k == I.m;
+          a.out = a.last ? X[1 - par] : c->d_U[(k - 1) % 2];
+        }
+        const uint16_t slot = (uint16_t)tab.size();
+        tab.push_back(b);
+        map.insert(map.end(), nt, slot);
+      }
+      BatchLaunch L;
+      int rc = upload(L, tab, map);
+      if (rc != EMRKC_OK) return rc;
+      if (k == 1)
+        c->bdev.head[par] = L;
+      else
+        c->bdev.inner[par].push_back(L);
+    }
+  }
+  c->bdev.valid = true;
+  c->bdev.dt_bits = dtb;
+  c->bdev.V = st->V;
+  c->bdev.z = st->z;
+  c->bdev.s = P.s;
+  c->bdev.m_max = P.m;
+  c->bdev.eta = P.eta;
+  return EMRKC_OK;
+}
+
+// L batched steps: V^n ping-pongs between X[0] and X[1]; an odd chunk ends
+// with one copy back to X[0].
+static int enqueue_chunk_batch(emrkc_ctx *c, const emrkc_state *st, const StepPlan &P, double dt, int L,
+                               hipStream_t strm, KernelTimer *tm) {
+  (void)dt;
+  (void)P;
+  const uint32_t Ntot = (uint32_t)c->N;
+  for (int n = 0; n < L; ++n) {
+    const int par = n % 2;
+    const BatchLaunch &H = c->bdev.head[par];
+    TIMED(0, launch_head_batch(c->model, c->mixed, H.tab, H.map, H.nblocks, Ntot, n, strm));
+    for (const BatchLaunch &B : c->bdev.inner[par])
+      if (B.nblocks) TIMED(1, launch_inner_batch(c->mixed, B.tab, B.map, B.nblocks, Ntot, strm));
+  }
+  double *X1 = c->d_V1;
+  HIP_TRY(c, launch_copy_tick(L % 2 ? X1 : nullptr, (double *)st->V, Ntot, c->d_clock, L, strm));
+  return EMRKC_OK;
+}
+
+extern "C" int emrkc_batch_size(const emrkc_ctx *c) { return c == nullptr ? -1 : (c->batch ? (int)c->inst.size() : 1); }
+
+extern "C" int emrkc_batch_info(const emrkc_ctx *c, double dt, int64_t *offsets, int *m, double *rho_F, double *rho_S) {
+  if (c == nullptr) return EMRKC_EINVAL;
+  const int n = c->batch ? (int)c->inst.size() : 1;
+  for (int k = 0; k < n; ++k) {
+    if (offsets) offsets[k] = c->batch ? c->inst[k].off : 0;
+    const double rF = c->batch ? c->inst[k].rho_F : c->rho_F;
+    const double rS = c->batch ? c->inst[k].rho_S : c->rho_S;
+    if (rho_F) rho_F[k] = rF;
+    if (rho_S) rho_S[k] = rS;
+    if (m) {
+      int si = 0, mi = 0;
+      double ei;
+      m[k] = (c->have_rho && emrkc_stage_counts(dt, rF, c->rho_S, c->eps, &si, &mi, &ei) == EMRKC_OK) ? mi : 0;
+    }
+  }
+  if (offsets) offsets[n] = c->N;
+  return EMRKC_OK;
+}
+
+extern "C" int emrkc_batch_set_rho(emrkc_ctx *c, const double *rho_F, const double *rho_S) {
+  if (c == nullptr || rho_F == nullptr || rho_S == nullptr) return EMRKC_EINVAL;
+  if (!c->batch) return emrkc_set_rho(c, rho_F[0], rho_S[0]);
+  for (size_t k = 0; k < c->inst.size(); ++k)
+    if (!(rho_F[k] >= 0) || !(rho_S[k] >= 0) || !isfinite(rho_F[k]) || !isfinite(rho_S[k]))
+      return fail(c, EMRKC_EINVAL, "invalid spectral radii for instance %zu", k);
+  c->rho_F = c->rho_S = 0.0;
+  for (size_t k = 0; k < c->inst.size(); ++k) {
+    c->inst[k].rho_F = rho_F[k];
+    c->inst[k].rho_S = rho_S[k];
+    c->inst[k].have_rho = true;
+    c->rho_F = std::max(c->rho_F, rho_F[k]);
+    c->rho_S = std::max(c->rho_S, rho_S[k]);
+  }
+  c->have_rho = true;
+  clear_graphs(c);
+  c->bdev.valid = false;
   return EMRKC_OK;
 }

@@ -92,7 +92,26 @@ struct FusedArgs {
   HeadArgs h;            // h.Vin unused: V comes from the tail
 };
 
+// One instance of a batched (ensemble) launch.  Instances are concatenated:
+// node i of the instance is node off + i of every global array, component
+// planes are N_total apart.  Logical blocks tile0 .. tile0 + ntiles - 1 of
+// the launch belong to the instance.
+struct BatchInst {
+  Grid g;
+  uint32_t off;
+  uint32_t tile0;
+  uint32_t ntx, nty;
+  HeadArgs h;    // head launches: this instance's coefficients (pointers global)
+  InnerArgs in;  // inner launches: this instance's coefficients (pointers global)
+};
+
 // ---- launchers (emrkc_kernels.hip) ----------------------------------------
+// Tiles of a grid in the LDS-tiled layout (3-D 16x4x4, 2-D 64x4).
+uint32_t grid_tiles(const Grid &g, uint32_t &ntx, uint32_t &nty);
+hipError_t launch_head_batch(int model, bool mixed, const BatchInst *tab, const uint16_t *map, uint32_t nblocks,
+                             uint32_t Ntot, int step_off, hipStream_t st);
+hipError_t launch_inner_batch(bool mixed, const BatchInst *tab, const uint16_t *map, uint32_t nblocks,
+                              uint32_t Ntot, hipStream_t st);
 hipError_t launch_init_state(int model, bool mixed, uint32_t N, double *V, void *z, ModelParams mp,
                              hipStream_t st);
 hipError_t launch_head(int model, bool mixed, const Mesh &mesh, const HeadArgs &a, hipStream_t st);
@@ -114,7 +133,7 @@ hipError_t launch_eval_rhs_slow(int model, bool mixed, uint32_t N, const double 
 // Power iteration pieces.  Partial sums go to `partials` (one per block),
 // the final sum to `result` (device double).
 uint32_t reduce_blocks(uint32_t n);
-hipError_t launch_norm2_state(bool mixed, uint32_t N, int nz, const double *V, const void *z,
+hipError_t launch_norm2_state(bool mixed, uint32_t N, size_t stride, int nz, const double *V, const void *z,
                               double *partials, double *result, hipStream_t st);
 hipError_t launch_norm2_random(uint64_t seed, uint64_t count, double *partials, double *result,
                                hipStream_t st);
@@ -122,7 +141,7 @@ hipError_t launch_powF_shift(uint32_t N, const double *yV, const double *vin, ui
                              double *zV, hipStream_t st);
 hipError_t launch_powF_diff(bool mixed, const Mesh &mesh, const double *zV, const double *yV, double *vout,
                             double *partials, double *result, hipStream_t st);
-hipError_t launch_powS_iter(int model, bool mixed, uint32_t N, const double *V, const void *z,
+hipError_t launch_powS_iter(int model, bool mixed, uint32_t N, size_t stride, const double *V, const void *z,
                             const double *vin, uint64_t seed, double q, double t, StimArgs stim,
                             double Cm, ModelParams mp, double *vout, double *partials, double *result,
                             hipStream_t st);

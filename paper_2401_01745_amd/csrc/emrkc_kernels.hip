@@ -414,6 +414,78 @@ __global__ __launch_bounds__(kBlock) void k_inner_march(InnerArgs a, Grid g, uin
   }
 }
 
+// ---------------------------------------------------------------------------
+// Batched ensembles: one launch covers the tiles of every participating
+// instance; each block finds its instance through a block map and runs the
+// LDS-tiled head or inner stage with that instance's grid and coefficients.
+// ---------------------------------------------------------------------------
+template <int DIM>
+__device__ __forceinline__ void tile_xyz(const BatchInst &I, uint32_t tile, int &x0, int &y0, int &z0) {
+  using T = Tile<DIM>;
+  const uint32_t bx = tile % I.ntx, byz = tile / I.ntx;
+  const uint32_t by = byz % I.nty, bz = byz / I.nty;
+  x0 = (int)(bx * T::TX);
+  y0 = (int)(by * T::TY);
+  z0 = (int)(bz * T::TZ);
+}
+
+template <template <class> class Model, bool MIXED, int DIM>
+__device__ __forceinline__ void head_tile(const BatchInst &I, const HeadArgs &h, uint32_t tile, double *sV,
+                                          uint32_t Ntot) {
+  int x0, y0, z0;
+  tile_xyz<DIM>(I, tile, x0, y0, z0);
+  stage_halo<DIM>(sV, h.Vin + I.off, I.g, x0, y0, z0);
+  __syncthreads();
+  uint32_t i;
+  int c;
+  if (!tile_node<DIM>(I.g, x0, y0, z0, i, c)) return;
+  head_node<Model, MIXED>(h, Ntot, I.off + i, sV[c], [&]() { return lds_stencil<DIM, MIXED>(sV, I.g, c); });
+}
+
+constexpr int kBatchLds = Tile<3>::NS > Tile<2>::NS ? Tile<3>::NS : Tile<2>::NS;
+
+template <template <class> class Model, bool MIXED>
+__global__ __launch_bounds__(kBlock) void k_head_batch(const BatchInst *__restrict__ tab,
+                                                       const uint16_t *__restrict__ map, uint32_t Ntot, int step_off) {
+  __shared__ double sV[kBatchLds];
+  const uint32_t lb = xcd_block(blockIdx.x, gridDim.x);
+  const BatchInst &I = tab[map[lb]];
+  HeadArgs h = I.h;
+  h.step_off = step_off;
+  if (I.g.dim == 3)
+    head_tile<Model, MIXED, 3>(I, h, lb - I.tile0, sV, Ntot);
+  else
+    head_tile<Model, MIXED, 2>(I, h, lb - I.tile0, sV, Ntot);
+}
+
+template <bool MIXED, int DIM>
+__device__ __forceinline__ void inner_tile(const BatchInst &I, uint32_t tile, double *sU) {
+  int x0, y0, z0;
+  tile_xyz<DIM>(I, tile, x0, y0, z0);
+  const InnerArgs &a = I.in;
+  stage_halo<DIM>(sU, a.t.uprev + I.off, I.g, x0, y0, z0);
+  __syncthreads();
+  uint32_t il;
+  int c;
+  if (!tile_node<DIM>(I.g, x0, y0, z0, il, c)) return;
+  const uint32_t i = I.off + il;
+  const double Fu = lds_stencil<DIM, MIXED>(sU, I.g, c);
+  const double uk = inner_value(a.t, Fu, load_sv(a.t.SV, MIXED, i), i);
+  a.out[i] = a.last ? tail_from_um(a.t, uk, i) : uk;
+}
+
+template <bool MIXED>
+__global__ __launch_bounds__(kBlock) void k_inner_batch(const BatchInst *__restrict__ tab,
+                                                        const uint16_t *__restrict__ map) {
+  __shared__ double sU[kBatchLds];
+  const uint32_t lb = xcd_block(blockIdx.x, gridDim.x);
+  const BatchInst &I = tab[map[lb]];
+  if (I.g.dim == 3)
+    inner_tile<MIXED, 3>(I, lb - I.tile0, sU);
+  else
+    inner_tile<MIXED, 2>(I, lb - I.tile0, sU);
+}
+
 __global__ void k_clock_set(Clock *c, int64_t step, double t0) {
   if (threadIdx.x == 0 && blockIdx.x == 0) {
     c->step = step;
@@ -485,17 +557,20 @@ __global__ __launch_bounds__(kBlock) void k_reduce_final(const double *partials,
   if (threadIdx.x == 0) *result = v;
 }
 
+// ||y||^2 over every component; z planes are `stride` apart.
 template <bool MIXED>
 __global__ __launch_bounds__(kBlock) void k_norm2_state(uint32_t N, int nz, const double *V, const void *zv,
-                                                        double *partials) {
+                                                        size_t stride, double *partials) {
   using Rs = typename std::conditional<MIXED, float, double>::type;
   const Rs *z = (const Rs *)zv;
-  const uint64_t total = (uint64_t)N * (uint64_t)(nz + 1);
   double v = 0.0;
-  for (uint64_t k = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; k < total;
-       k += (uint64_t)gridDim.x * blockDim.x) {
-    const double x = k < N ? V[k] : (double)z[k - N];
-    v += x * x;
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < N) {
+    v = V[i] * V[i];
+    for (int c = 0; c < nz; ++c) {
+      const double x = (double)z[(size_t)c * stride + i];
+      v += x * x;
+    }
   }
   v = block_sum(v);
   if (threadIdx.x == 0) partials[blockIdx.x] = v;
@@ -536,10 +611,13 @@ __global__ __launch_bounds__(kBlock) void k_powF_diff(Mesh mesh, const double *z
   if (threadIdx.x == 0) partials[blockIdx.x] = v;
 }
 
+// z and the vectors v have component planes `stride` apart; the random start
+// vector is indexed as in a state of N nodes (component c at c*N + i).
 template <template <class> class Model, bool MIXED>
-__global__ __launch_bounds__(kBlock) void k_powS_iter(uint32_t N, const double *V, const void *zv, const double *vin,
-                                                      uint64_t seed, double q, double t, StimArgs stim, double Cm,
-                                                      ModelParams mp, double *vout, double *partials) {
+__global__ __launch_bounds__(kBlock) void k_powS_iter(uint32_t N, size_t stride, const double *V, const void *zv,
+                                                      const double *vin, uint64_t seed, double q, double t,
+                                                      StimArgs stim, double Cm, ModelParams mp, double *vout,
+                                                      double *partials) {
   using M = MathF64;
   using Mod = Model<M>;
   constexpr int NG = Mod::NG, NS = Mod::NS, NZ = NG + NS;
@@ -551,7 +629,7 @@ __global__ __launch_bounds__(kBlock) void k_powS_iter(uint32_t N, const double *
     double y[NZ], w[NZ];
     const double yv = V[i];
 #pragma unroll
-    for (int k = 0; k < NZ; ++k) y[k] = (double)z[(size_t)k * N + i];
+    for (int k = 0; k < NZ; ++k) y[k] = (double)z[(size_t)k * stride + i];
     // perturbed state z = y + q v; gate components of a warm vector are 0
     double wv;
     if (vin == nullptr) {
@@ -562,7 +640,7 @@ __global__ __launch_bounds__(kBlock) void k_powS_iter(uint32_t N, const double *
       wv = yv + q * vin[i];
 #pragma unroll
       for (int k = 0; k < NZ; ++k)
-        w[k] = k < NG ? y[k] + q * 0.0 : y[k] + q * vin[(size_t)(1 + k - NG) * N + i];
+        w[k] = k < NG ? y[k] + q * 0.0 : y[k] + q * vin[(size_t)(1 + k - NG) * stride + i];
     }
     const double Is = stimulus(stim, i, t);
     double dSy[NS > 0 ? NS : 1], dSw[NS > 0 ? NS : 1];
@@ -574,7 +652,7 @@ __global__ __launch_bounds__(kBlock) void k_powS_iter(uint32_t N, const double *
 #pragma unroll
     for (int s = 0; s < NS; ++s) {
       const double d = dSw[s] - dSy[s];
-      vout[(size_t)(1 + s) * N + i] = d;
+      vout[(size_t)(1 + s) * stride + i] = d;
       acc += d * d;
     }
   }
@@ -656,15 +734,15 @@ static hipError_t rhs_dispatch(bool mixed, uint32_t N, const double *V, const vo
 }
 
 template <template <class> class Model>
-static hipError_t powS_dispatch(bool mixed, uint32_t N, const double *V, const void *z, const double *vin,
-                                uint64_t seed, double q, double t, StimArgs stim, double Cm, ModelParams mp,
-                                double *vout, double *partials, hipStream_t st) {
+static hipError_t powS_dispatch(bool mixed, uint32_t N, size_t stride, const double *V, const void *z,
+                                const double *vin, uint64_t seed, double q, double t, StimArgs stim, double Cm,
+                                ModelParams mp, double *vout, double *partials, hipStream_t st) {
   if (mixed)
-    hipLaunchKernelGGL((k_powS_iter<Model, true>), dim3(blocks_for(N)), dim3(kBlock), 0, st, N, V, z, vin, seed,
-                       q, t, stim, Cm, mp, vout, partials);
+    hipLaunchKernelGGL((k_powS_iter<Model, true>), dim3(blocks_for(N)), dim3(kBlock), 0, st, N, stride, V, z, vin,
+                       seed, q, t, stim, Cm, mp, vout, partials);
   else
-    hipLaunchKernelGGL((k_powS_iter<Model, false>), dim3(blocks_for(N)), dim3(kBlock), 0, st, N, V, z, vin, seed,
-                       q, t, stim, Cm, mp, vout, partials);
+    hipLaunchKernelGGL((k_powS_iter<Model, false>), dim3(blocks_for(N)), dim3(kBlock), 0, st, N, stride, V, z, vin,
+                       seed, q, t, stim, Cm, mp, vout, partials);
   return hipGetLastError();
 }
 
@@ -725,6 +803,37 @@ hipError_t launch_inner(bool mixed, const Mesh &mesh, const InnerArgs &a, hipStr
 }
 
 bool fused_supported(const Mesh &mesh) { return mesh.kind == kGrid; }
+
+uint32_t grid_tiles(const Grid &g, uint32_t &ntx, uint32_t &nty) {
+  return g.dim == 3 ? tile_grid<3>(g, ntx, nty).x : tile_grid<2>(g, ntx, nty).x;
+}
+
+template <template <class> class Model>
+static hipError_t head_batch_dispatch(bool mixed, const BatchInst *tab, const uint16_t *map, uint32_t nb,
+                                      uint32_t Ntot, int step_off, hipStream_t st) {
+  if (mixed)
+    hipLaunchKernelGGL((k_head_batch<Model, true>), dim3(nb), dim3(kBlock), 0, st, tab, map, Ntot, step_off);
+  else
+    hipLaunchKernelGGL((k_head_batch<Model, false>), dim3(nb), dim3(kBlock), 0, st, tab, map, Ntot, step_off);
+  return hipGetLastError();
+}
+
+hipError_t launch_head_batch(int model, bool mixed, const BatchInst *tab, const uint16_t *map, uint32_t nblocks,
+                             uint32_t Ntot, int step_off, hipStream_t st) {
+#define CALL(M) head_batch_dispatch<M>(mixed, tab, map, nblocks, Ntot, step_off, st)
+  EMRKC_MODEL_SWITCH(model, CALL)
+#undef CALL
+}
+
+hipError_t launch_inner_batch(bool mixed, const BatchInst *tab, const uint16_t *map, uint32_t nblocks,
+                              uint32_t Ntot, hipStream_t st) {
+  (void)Ntot;
+  if (mixed)
+    hipLaunchKernelGGL((k_inner_batch<true>), dim3(nblocks), dim3(kBlock), 0, st, tab, map);
+  else
+    hipLaunchKernelGGL((k_inner_batch<false>), dim3(nblocks), dim3(kBlock), 0, st, tab, map);
+  return hipGetLastError();
+}
 
 template <template <class> class Model>
 static hipError_t fused_dispatch(bool mixed, const Grid &g, const FusedArgs &a, hipStream_t st) {
@@ -789,13 +898,13 @@ static hipError_t finish_reduce(uint32_t nparts, double *partials, double *resul
   return hipGetLastError();
 }
 
-hipError_t launch_norm2_state(bool mixed, uint32_t N, int nz, const double *V, const void *z, double *partials,
-                              double *result, hipStream_t st) {
+hipError_t launch_norm2_state(bool mixed, uint32_t N, size_t stride, int nz, const double *V, const void *z,
+                              double *partials, double *result, hipStream_t st) {
   const uint32_t nb = blocks_for(N);
   if (mixed)
-    hipLaunchKernelGGL((k_norm2_state<true>), dim3(nb), dim3(kBlock), 0, st, N, nz, V, z, partials);
+    hipLaunchKernelGGL((k_norm2_state<true>), dim3(nb), dim3(kBlock), 0, st, N, nz, V, z, stride, partials);
   else
-    hipLaunchKernelGGL((k_norm2_state<false>), dim3(nb), dim3(kBlock), 0, st, N, nz, V, z, partials);
+    hipLaunchKernelGGL((k_norm2_state<false>), dim3(nb), dim3(kBlock), 0, st, N, nz, V, z, stride, partials);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   return finish_reduce(nb, partials, result, st);
@@ -827,17 +936,19 @@ hipError_t launch_powF_diff(bool mixed, const Mesh &mesh, const double *zV, cons
   return finish_reduce(nb, partials, result, st);
 }
 
-hipError_t launch_powS_iter(int model, bool mixed, uint32_t N, const double *V, const void *z, const double *vin,
-                            uint64_t seed, double q, double t, StimArgs stim, double Cm, ModelParams mp,
-                            double *vout, double *partials, double *result, hipStream_t st) {
+hipError_t launch_powS_iter(int model, bool mixed, uint32_t N, size_t stride, const double *V, const void *z,
+                            const double *vin, uint64_t seed, double q, double t, StimArgs stim, double Cm,
+                            ModelParams mp, double *vout, double *partials, double *result, hipStream_t st) {
   hipError_t e;
+#define CALL(M) powS_dispatch<M>(mixed, N, stride, V, z, vin, seed, q, t, stim, Cm, mp, vout, partials, st)
   switch (model) {
-    case 1: e = powS_dispatch<HHModel>(mixed, N, V, z, vin, seed, q, t, stim, Cm, mp, vout, partials, st); break;
-    case 2: e = powS_dispatch<LinearModel>(mixed, N, V, z, vin, seed, q, t, stim, Cm, mp, vout, partials, st); break;
-    case 3: e = powS_dispatch<CrnSurrModel>(mixed, N, V, z, vin, seed, q, t, stim, Cm, mp, vout, partials, st); break;
-    case 4: e = powS_dispatch<TtpSurrModel>(mixed, N, V, z, vin, seed, q, t, stim, Cm, mp, vout, partials, st); break;
+    case 1: e = CALL(HHModel); break;
+    case 2: e = CALL(LinearModel); break;
+    case 3: e = CALL(CrnSurrModel); break;
+    case 4: e = CALL(TtpSurrModel); break;
     default: return hipErrorInvalidValue;
   }
+#undef CALL
   if (e != hipSuccess) return e;
   return finish_reduce(blocks_for(N), partials, result, st);
 }

@@ -90,6 +90,12 @@ EXPORTS = {
     "emrkc_profile_step": (C.c_int, [C.c_void_p, C.POINTER(State), C.c_double, C.c_int64, C.POINTER(C.c_double),
                                      C.POINTER(C.c_int64)]),
     "emrkc_apply_diffusion": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
+    "emrkc_create_batch": (C.c_int, [C.c_int, C.POINTER(Mesh), C.POINTER(Conductivity), C.c_int, C.POINTER(Params),
+                                     C.POINTER(C.c_void_p)]),
+    "emrkc_batch_size": (C.c_int, [C.c_void_p]),
+    "emrkc_batch_info": (C.c_int, [C.c_void_p, C.c_double, C.POINTER(C.c_int64), C.POINTER(C.c_int),
+                                   C.POINTER(C.c_double), C.POINTER(C.c_double)]),
+    "emrkc_batch_set_rho": (C.c_int, [C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_double)]),
     "emrkc_eval_rhs_slow": (C.c_int, [C.c_void_p, C.POINTER(State), C.c_double, C.c_void_p]),
 }
 
@@ -255,14 +261,45 @@ def tet_mesh(coords, tets, fibres):
     return m
 
 
+def emrkc_create_batch(meshes, conds, model, params):
+    n = len(meshes)
+    M = (Mesh * n)(*meshes)
+    Cd = (Conductivity * n)(*conds)
+    P = (Params * n)(*params)
+    ctx = C.c_void_p()
+    rc = lib().emrkc_create_batch(n, M, Cd, MODELS.get(model, model) if isinstance(model, str) else model, P,
+                                  C.byref(ctx))
+    if rc != EMRKC_OK:
+        raise EmrkcError(rc, "emrkc_create_batch failed")
+    return ctx
+
+
+def emrkc_batch_info(ctx, dt):
+    n = lib().emrkc_batch_size(ctx)
+    off = (C.c_int64 * (n + 1))()
+    m = (C.c_int * n)()
+    rf = (C.c_double * n)()
+    rs = (C.c_double * n)()
+    _check(lib().emrkc_batch_info(ctx, dt, off, m, rf, rs), ctx)
+    return list(off), list(m), list(rf), list(rs)
+
+
+def emrkc_batch_set_rho(ctx, rho_F, rho_S):
+    n = len(rho_F)
+    _check(lib().emrkc_batch_set_rho(ctx, (C.c_double * n)(*rho_F), (C.c_double * n)(*rho_S)), ctx)
+
+
 class Simulation:
     """Owns one context and the caller-side state tensors (V, z) on the
     current HIP device.  All numerical work is done by the library."""
 
-    def __init__(self, mesh, cond, model, params, keep=()):
+    def __init__(self, mesh, cond, model, params, keep=(), batch=None):
         import torch
         self._keep = keep
-        self.ctx = emrkc_create(mesh, cond, model, params)
+        if batch is not None:
+            self.ctx = emrkc_create_batch(batch[0], batch[1], model, batch[2])
+        else:
+            self.ctx = emrkc_create(mesh, cond, model, params)
         self.N = lib().emrkc_num_nodes(self.ctx)
         self.nv = lib().emrkc_num_vars(self.ctx)
         zdt = torch.float32 if params.precision == EMRKC_MIXED32 else torch.float64
@@ -339,3 +376,34 @@ def simulation_from_tet_config(cfg, mesh, mask, precision=None, rho=None, flags=
     if rho is not None:
         p.rho_F, p.rho_S = rho
     return Simulation(m, cond, cfg["model"], p, keep=(coords, tets, fib, mask))
+
+
+def simulation_from_batch(cfgs, precision=None, rho=None, flags=0):
+    """One batched Simulation for a list of grid workload dictionaries with
+    their own masks (see workloads.ensemble).  rho = (list of rho_F, list of
+    rho_S) fixes per-instance radii."""
+    import numpy as np
+    meshes, conds, params, keep = [], [], [], []
+    prec = PRECISIONS[precision or cfgs[0].get("precision", "fp64")]
+    for k, cfg in enumerate(cfgs):
+        d = cfg["dim"]
+        meshes.append(grid_mesh(cfg["n"][:d], cfg["h"][:d]))
+        sig = list(cfg["sigma"]) + [cfg["sigma"][-1]] * (3 - len(cfg["sigma"]))
+        conds.append(Conductivity(sig[0], sig[1], sig[2]))
+        p = emrkc_default_params()
+        p.chi = cfg["chi"]
+        p.Cm = cfg["Cm"]
+        p.precision = prec
+        p.flags = flags
+        mask = np.ascontiguousarray(cfg["mask"], dtype=np.uint8)
+        keep.append(mask)
+        p.stim_mask = mask.ctypes.data
+        st = cfg["stim"]
+        p.stim_amp = st["amp"]
+        p.stim_t_on = st["t_on"]
+        p.stim_t_off = st["t_off"]
+        if rho is not None:
+            p.rho_F, p.rho_S = rho[0][k], rho[1][k]
+        params.append(p)
+    p0 = params[0]
+    return Simulation(None, None, cfgs[0]["model"], p0, keep=tuple(keep), batch=(meshes, conds, params))

@@ -1,0 +1,105 @@
+"""Batched ensemble (uneven 2-D and 3-D instances in one context, one launch
+per stage): each instance against the oracle, against its own
+single-instance run (bitwise), graph against eager, and the per-instance
+power iteration."""
+import numpy as np
+import pytest
+
+from gpu_util import oracle_rho, rel_errors
+from oracle.emrkc import emrkc_run, stage_counts
+from oracle.monodomain import build_grid_problem
+from workloads.ensemble import small_ensemble
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ens():
+    cfgs = small_ensemble()
+    probs = [build_grid_problem(c, stim_mask=c["mask"]) for c in cfgs]
+    rhos = [oracle_rho(p, p.uniform_state()) for p in probs]
+    return cfgs, probs, rhos
+
+
+def run_batch(cfgs, rho, nsteps, precision="fp64", flags=0, chunks=None):
+    import torch
+    from paper_2401_01745_amd import emrkc as E
+    sim = E.simulation_from_batch(cfgs, precision=precision, rho=rho, flags=flags)
+    E.emrkc_init_state(sim.ctx, sim.state)
+    for n in (chunks or [nsteps]):
+        E.emrkc_step(sim.ctx, sim.state, cfgs[0]["dt"], n)
+    torch.cuda.synchronize()
+    off, m, rF, rS = E.emrkc_batch_info(sim.ctx, cfgs[0]["dt"])
+    out = sim.V.cpu().numpy().copy(), sim.z.cpu().numpy().astype(np.float64), off, m
+    sim.close()
+    return out
+
+
+def test_batch_matches_oracle_per_instance(ens):
+    cfgs, probs, rhos = ens
+    rF = [r[0] for r in rhos]
+    rS = [r[1] for r in rhos]
+    rSmax = max(rS)
+    nsteps = 80
+    V, z, off, m = run_batch(cfgs, (rF, rS), nsteps)
+    for k, (cfg, prob) in enumerate(zip(cfgs, probs)):
+        s_k, m_k, _ = stage_counts(cfg["dt"], rF[k], rSmax)
+        assert m[k] == m_k and s_k == 1
+        y = emrkc_run(prob, prob.uniform_state(), 0.0, cfg["dt"], nsteps, rF[k], rSmax)
+        Y = y.reshape(prob.nv, prob.N)
+        sl = slice(off[k], off[k + 1])
+        l2, mx = rel_errors(V[sl], Y[0])
+        assert l2 <= 1e-10 and mx <= 1e-10, (k, l2, mx)
+        for c in range(1, prob.nv):
+            zl2, zmx = rel_errors(z[c - 1, sl], Y[c])
+            assert zl2 <= 1e-10 and zmx <= 1e-10, (k, c, zl2, zmx)
+
+
+def test_batch_equals_single_runs_bitwise_and_graph_equals_eager(ens):
+    from paper_2401_01745_amd import emrkc as E
+    cfgs, probs, rhos = ens
+    rF = [r[0] for r in rhos]
+    rS = [max(r[1] for r in rhos)] * len(rhos)
+    V, z, off, m = run_batch(cfgs, (rF, rS), 41)
+    V2, z2, _, _ = run_batch(cfgs, (rF, rS), 41, flags=E.EMRKC_EAGER)
+    V3, z3, _, _ = run_batch(cfgs, (rF, rS), 41, chunks=[3, 32, 6])
+    assert np.array_equal(V, V2) and np.array_equal(z, z2)
+    assert np.array_equal(V, V3) and np.array_equal(z, z3)
+    # single-instance contexts with the same masks
+    import torch
+    for k, cfg in enumerate(cfgs):
+        sim = E.simulation_from_config(cfg, rho=(rF[k], rS[k]), stim_mask=cfg["mask"])
+        E.emrkc_init_state(sim.ctx, sim.state)
+        E.emrkc_step(sim.ctx, sim.state, cfg["dt"], 41)
+        torch.cuda.synchronize()
+        sl = slice(off[k], off[k + 1])
+        assert np.array_equal(sim.V.cpu().numpy(), V[sl]), k
+        assert np.array_equal(sim.z.cpu().numpy().astype(np.float64), z[:, sl]), k
+        sim.close()
+
+
+def test_batch_estimate_rho_per_instance(ens):
+    import torch  # noqa: F401
+    from paper_2401_01745_amd import emrkc as E
+    cfgs, probs, rhos = ens
+    sim = E.simulation_from_batch(cfgs)
+    E.emrkc_init_state(sim.ctx, sim.state)
+    gF, gS, itF, itS, _ = E.emrkc_estimate_rho(sim.ctx, sim.state)
+    off, m, rF, rS = E.emrkc_batch_info(sim.ctx, cfgs[0]["dt"])
+    for k, r in enumerate(rhos):
+        assert rF[k] == pytest.approx(r[0], rel=1e-6) and rS[k] == pytest.approx(r[1], rel=1e-6)
+    assert gF == pytest.approx(max(r[0] for r in rhos), rel=1e-6)
+    assert gS == pytest.approx(max(r[1] for r in rhos), rel=1e-6)
+    sim.close()
+
+
+def test_batch_mixed_precision(ens):
+    cfgs, probs, rhos = ens
+    rF = [r[0] for r in rhos]
+    rS = [max(r[1] for r in rhos)] * len(rhos)
+    V, z, off, m = run_batch(cfgs, (rF, rS), 80, precision="mixed")
+    V64, _, _, _ = run_batch(cfgs, (rF, rS), 80)
+    for k in range(len(cfgs)):
+        sl = slice(off[k], off[k + 1])
+        l2, mx = rel_errors(V[sl], V64[sl])
+        assert l2 <= 1e-4, (k, l2)
