@@ -115,7 +115,7 @@ def cpu_baseline(cfg, seconds, tet=None):
         el = time.perf_counter() - t0
         if el >= seconds or n >= 1000:
             break
-    return prob.N * n / el, n, el, stage_counts(cfg["dt"], rF, rS)
+    return prob.N * n / el, n, el, stage_counts(cfg["dt"], rF, rS), prob.N
 
 
 def main():
@@ -236,10 +236,11 @@ def main():
     cpu = None
     if not args.no_cpu_baseline:
         log("bench: CPU oracle baseline")
-        v, n, el, sm = cpu_baseline(cfg, args.cpu_seconds, tet)
+        v, n, el, sm, Ns = cpu_baseline(cfg, args.cpu_seconds, tet)
+        what = ("the full %d-node mesh" % Ns) if Ns == N else ("instance 0 (%d nodes) of the ensemble" % Ns)
         cpu = {"value": v, "unit": "node-steps/s", "cores": 1, "kind": "oracle",
-               "sample": "%d emRKC steps of the full %d-node mesh in %.1f s (numpy/scipy, single thread; "
-                         "host has %d logical CPUs)" % (n, N, el, os.cpu_count())}
+               "sample": "%d emRKC steps of %s in %.1f s (numpy/scipy, single thread; host has %d logical CPUs)"
+                         % (n, what, el, os.cpu_count())}
 
     out = {"metric": METRIC, "value": value, "unit": "node-steps/s", "n_gpus": 1, "steps": args.steps,
            "warmup": args.warmup, "ms_per_step": 1e3 * elapsed / args.steps, "higher_is_better": True,
