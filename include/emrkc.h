@@ -269,6 +269,15 @@ int emrkc_apply_diffusion(emrkc_ctx *ctx, const double *V, double *out);
  * both precisions. */
 int emrkc_eval_rhs_slow(emrkc_ctx *ctx, const emrkc_state *state, double t, double *out);
 
+/* Elementary functions of the ionic models as the kernels evaluate them:
+ * y[i] = f(x[i]) for i < n with f = exp (fn 0), expm1 (fn 1) or log (fn 2),
+ * in double (precision EMRKC_FP64) or in single precision (EMRKC_MIXED32:
+ * x rounded to float, result widened to double).  x and y are device
+ * double[n]; the work is queued on `hip_stream` (NULL: null stream) and the
+ * call waits for it.  EMRKC_EINVAL for an unknown fn or precision, n < 0 or
+ * NULL pointers with n > 0. */
+int emrkc_eval_elementary(int fn, int precision, const double *x, double *y, int64_t n, void *hip_stream);
+
 #ifdef __cplusplus
 }
 #endif

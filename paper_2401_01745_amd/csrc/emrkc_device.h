@@ -16,33 +16,145 @@
 namespace emrkc {
 
 // ---------------------------------------------------------------------------
-// Arithmetic policies.  FP64 uses the device libm for exp/expm1/log and a
-// Newton-refined hardware reciprocal for divisions; the FP32 policy uses the
-// native exp2/log2/rcp based fast paths (v_exp_f32, v_log_f32, v_rcp_f32)
-// except for expm1, whose accuracy near 0 carries the exponential Euler
+// Elementary functions.  The ionic models spend most of their arithmetic in
+// exp, expm1 and log; the device libm versions of the double functions cost
+// 40 to 100 vector instructions each, so double precision uses the short
+// forms below (all on finite arguments):
+//   * exp / expm1: reduction x = k ln2 + r, |r| <= ln2/2, with ln2 split in
+//     a rounded part and its remainder and both products taken with fused
+//     multiply-adds (Cody and Waite); e^r - 1 from its Taylor series to
+//     degree 13 (remainder below 5e-18 relative) and reconstruction
+//     e^x = 2^k (1 + q), e^x - 1 = 2^k q + (2^k - 1) (exact for k = 0, so
+//     expm1 keeps full relative accuracy near 0).  About 1 ulp (exp) and 3
+//     ulp (expm1); e^x underflows to 0 below -745 and overflows above 709.8;
+//     an infinite argument yields NaN (non-finite in, non-finite out).
+//   * log: x = 2^e m with m in [sqrt(1/2), sqrt(2)), log m = 2 atanh(s),
+//     s = (m - 1)/(m + 1), |s| <= 0.172, from the odd series of atanh to
+//     s^21 (remainder below 1e-17 relative); log x = e ln2 + log m.  About
+//     2 ulp; 0 gives -inf, inf gives inf, negative or NaN gives NaN.
+// The single precision forms use the native exp2/log2/rcp instructions and a
+// degree-7 version of the reduced expm1 above.
+// ---------------------------------------------------------------------------
+namespace detail {
+constexpr double kLn2Hi = 0.6931471805599453;       // ln 2 rounded to double
+constexpr double kLn2Lo = 2.3190468138462996e-17;   // ln 2 - kLn2Hi
+constexpr double kLog2E = 1.4426950408889634;
+constexpr float kLn2HiF = 0.6931472f;
+constexpr float kLn2LoF = -1.9046542e-09f;
+constexpr float kLog2EF = 1.442695f;
+
+// e^r - 1 for x = k ln2 + r; returns q and sets k.
+__device__ __forceinline__ double expm1_reduced(double x, int &k) {
+  const double kd = __builtin_rint(x * kLog2E);
+  double r = __builtin_fma(-kd, kLn2Hi, x);
+  r = __builtin_fma(-kd, kLn2Lo, r);
+  // q = r + r^2 (1/2! + r/3! + ... + r^11/13!)
+  double p = 1.0 / 6227020800.0;
+  p = __builtin_fma(p, r, 1.0 / 479001600.0);
+  p = __builtin_fma(p, r, 1.0 / 39916800.0);
+  p = __builtin_fma(p, r, 1.0 / 3628800.0);
+  p = __builtin_fma(p, r, 1.0 / 362880.0);
+  p = __builtin_fma(p, r, 1.0 / 40320.0);
+  p = __builtin_fma(p, r, 1.0 / 5040.0);
+  p = __builtin_fma(p, r, 1.0 / 720.0);
+  p = __builtin_fma(p, r, 1.0 / 120.0);
+  p = __builtin_fma(p, r, 1.0 / 24.0);
+  p = __builtin_fma(p, r, 1.0 / 6.0);
+  p = __builtin_fma(p, r, 0.5);
+  k = (int)kd;  // saturates for |x| > 1.4e9, where 2^k is 0 or inf anyway
+  return __builtin_fma(p * r, r, r);
+}
+
+__device__ __forceinline__ float expm1_reduced(float x, int &k) {
+  const float kf = __builtin_rintf(x * kLog2EF);
+  float r = __builtin_fmaf(-kf, kLn2HiF, x);
+  r = __builtin_fmaf(-kf, kLn2LoF, r);
+  float p = 1.0f / 5040.0f;
+  p = __builtin_fmaf(p, r, 1.0f / 720.0f);
+  p = __builtin_fmaf(p, r, 1.0f / 120.0f);
+  p = __builtin_fmaf(p, r, 1.0f / 24.0f);
+  p = __builtin_fmaf(p, r, 1.0f / 6.0f);
+  p = __builtin_fmaf(p, r, 0.5f);
+  k = (int)kf;
+  return __builtin_fmaf(p * r, r, r);
+}
+
+__device__ __forceinline__ double exp_f64(double x) {
+  int k;
+  const double q = expm1_reduced(x, k);
+  return __builtin_amdgcn_ldexp(q + 1.0, k);
+}
+
+__device__ __forceinline__ double expm1_f64(double x) {
+  int k;
+  const double q = expm1_reduced(x, k);
+  return __builtin_amdgcn_ldexp(q, k) + (__builtin_amdgcn_ldexp(1.0, k) - 1.0);
+}
+
+__device__ __forceinline__ float expm1_f32(float x) {
+  int k;
+  const float q = expm1_reduced(x, k);
+  return __builtin_amdgcn_ldexpf(q, k) + (__builtin_amdgcn_ldexpf(1.0f, k) - 1.0f);
+}
+
+__device__ __forceinline__ double rcp_f64(double b) {
+  // hardware estimate refined by two Newton steps (within an ulp or two)
+  double r = __builtin_amdgcn_rcp(b);
+  double e = __builtin_fma(-b, r, 1.0);
+  r = __builtin_fma(r, e, r);
+  e = __builtin_fma(-b, r, 1.0);
+  return __builtin_fma(r, e, r);
+}
+
+__device__ __forceinline__ double log_f64(double x) {
+  int e = __builtin_amdgcn_frexp_exp(x);
+  double m = __builtin_amdgcn_frexp_mant(x);  // [1/2, 1)
+  if (m < 0.70710678118654752) {
+    m = m + m;
+    e -= 1;
+  }
+  const double s = (m - 1.0) * rcp_f64(m + 1.0);
+  const double s2 = s * s;
+  // atanh(s)/s = sum_{j>=0} s^{2j}/(2j+1)
+  double p = 1.0 / 21.0;
+  p = __builtin_fma(p, s2, 1.0 / 19.0);
+  p = __builtin_fma(p, s2, 1.0 / 17.0);
+  p = __builtin_fma(p, s2, 1.0 / 15.0);
+  p = __builtin_fma(p, s2, 1.0 / 13.0);
+  p = __builtin_fma(p, s2, 1.0 / 11.0);
+  p = __builtin_fma(p, s2, 1.0 / 9.0);
+  p = __builtin_fma(p, s2, 1.0 / 7.0);
+  p = __builtin_fma(p, s2, 1.0 / 5.0);
+  p = __builtin_fma(p, s2, 1.0 / 3.0);
+  const double lm = __builtin_fma(2.0 * s * s2, p, 2.0 * s);
+  const double ed = (double)e;
+  const double r = __builtin_fma(ed, kLn2Hi, __builtin_fma(ed, kLn2Lo, lm));
+  const double inf = __builtin_inf();
+  const double bad = (x == 0.0) ? -inf : (x > 0.0 ? x : __builtin_nan(""));
+  return (x > 0.0 && x < inf) ? r : bad;
+}
+}  // namespace detail
+
+// ---------------------------------------------------------------------------
+// Arithmetic policies.  FP64 uses the elementary functions above and a
+// Newton-refined hardware reciprocal for divisions; FP32 uses the native
+// exp2/log2/rcp based fast paths (v_exp_f32, v_log_f32, v_rcp_f32) and the
+// reduced expm1, whose relative accuracy near 0 carries the exponential Euler
 // update of slow gates.
 // ---------------------------------------------------------------------------
 struct MathF64 {
   using R = double;
-  static __device__ __forceinline__ R exp(R x) { return ::exp(x); }
-  static __device__ __forceinline__ R expm1(R x) { return ::expm1(x); }
-  static __device__ __forceinline__ R log(R x) { return ::log(x); }
-  // 1/b from the hardware estimate refined by two Newton steps (within an
-  // ulp or two; every divisor in the models is positive and finite)
-  static __device__ __forceinline__ R rcp(R b) {
-    R r = __builtin_amdgcn_rcp(b);
-    R e = __builtin_fma(-b, r, 1.0);
-    r = __builtin_fma(r, e, r);
-    e = __builtin_fma(-b, r, 1.0);
-    return __builtin_fma(r, e, r);
-  }
-  static __device__ __forceinline__ R div(R a, R b) { return a * rcp(b); }
+  static __device__ __forceinline__ R exp(R x) { return detail::exp_f64(x); }
+  static __device__ __forceinline__ R expm1(R x) { return detail::expm1_f64(x); }
+  static __device__ __forceinline__ R log(R x) { return detail::log_f64(x); }
+  static __device__ __forceinline__ R rcp(R b) { return detail::rcp_f64(b); }
+  static __device__ __forceinline__ R div(R a, R b) { return a * detail::rcp_f64(b); }
 };
 
 struct MathF32 {
   using R = float;
   static __device__ __forceinline__ R exp(R x) { return __expf(x); }
-  static __device__ __forceinline__ R expm1(R x) { return ::expm1f(x); }
+  static __device__ __forceinline__ R expm1(R x) { return detail::expm1_f32(x); }
   static __device__ __forceinline__ R log(R x) { return __logf(x); }
   static __device__ __forceinline__ R rcp(R b) { return __builtin_amdgcn_rcpf(b); }
   static __device__ __forceinline__ R div(R a, R b) { return a * __builtin_amdgcn_rcpf(b); }

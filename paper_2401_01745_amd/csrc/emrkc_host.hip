@@ -250,6 +250,17 @@ extern "C" int emrkc_stage_counts(double dt, double rho_F, double rho_S, double 
   return EMRKC_OK;
 }
 
+extern "C" int emrkc_eval_elementary(int fn, int precision, const double *x, double *y, int64_t n,
+                                     void *hip_stream) {
+  if (fn < 0 || fn > 2 || (precision != EMRKC_FP64 && precision != EMRKC_MIXED32) || n < 0 ||
+      n > (int64_t)UINT32_MAX - 1024 || (n > 0 && (!x || !y)))
+    return EMRKC_EINVAL;
+  if (n == 0) return EMRKC_OK;
+  hipStream_t st = (hipStream_t)hip_stream;
+  if (launch_elementary(fn, precision == EMRKC_MIXED32, x, y, (uint32_t)n, st) != hipSuccess) return EMRKC_EHIP;
+  return hipStreamSynchronize(st) == hipSuccess ? EMRKC_OK : EMRKC_EHIP;
+}
+
 // ---------------------------------------------------------------------------
 // Context
 // ---------------------------------------------------------------------------

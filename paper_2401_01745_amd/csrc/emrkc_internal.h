@@ -145,6 +145,7 @@ hipError_t launch_powS_iter(int model, bool mixed, uint32_t N, size_t stride, co
                             const double *vin, uint64_t seed, double q, double t, StimArgs stim,
                             double Cm, ModelParams mp, double *vout, double *partials, double *result,
                             hipStream_t st);
+hipError_t launch_elementary(int fn, bool mixed, const double *x, double *y, uint32_t n, hipStream_t st);
 hipError_t launch_finite_check(uint32_t N, const double *V, int *flag, hipStream_t st);
 
 }  // namespace emrkc

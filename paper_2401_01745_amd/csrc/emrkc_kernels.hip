@@ -665,6 +665,15 @@ __global__ __launch_bounds__(kBlock) void k_finite_check(uint32_t N, const doubl
   if (i < N && !isfinite(V[i])) *flag = 1;  // benign race: every writer stores 1
 }
 
+template <class M>
+__global__ __launch_bounds__(kBlock) void k_elementary(int fn, const double *x, double *y, uint32_t n) {
+  using R = typename M::R;
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const R v = R(x[i]);
+  y[i] = double(fn == 0 ? M::exp(v) : (fn == 1 ? M::expm1(v) : M::log(v)));
+}
+
 // ---------------------------------------------------------------------------
 // Launchers
 // ---------------------------------------------------------------------------
@@ -951,6 +960,14 @@ hipError_t launch_powS_iter(int model, bool mixed, uint32_t N, size_t stride, co
 #undef CALL
   if (e != hipSuccess) return e;
   return finish_reduce(blocks_for(N), partials, result, st);
+}
+
+hipError_t launch_elementary(int fn, bool mixed, const double *x, double *y, uint32_t n, hipStream_t st) {
+  if (mixed)
+    hipLaunchKernelGGL(k_elementary<MathF32>, dim3(blocks_for(n)), dim3(kBlock), 0, st, fn, x, y, n);
+  else
+    hipLaunchKernelGGL(k_elementary<MathF64>, dim3(blocks_for(n)), dim3(kBlock), 0, st, fn, x, y, n);
+  return hipGetLastError();
 }
 
 hipError_t launch_finite_check(uint32_t N, const double *V, int *flag, hipStream_t st) {

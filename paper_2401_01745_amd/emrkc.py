@@ -70,6 +70,7 @@ EXPORTS = {
     "emrkc_rkc_coeffs": (C.c_int, [C.c_int, C.c_double] + [C.POINTER(C.c_double)] * 4),
     "emrkc_stage_counts": (C.c_int, [C.c_double, C.c_double, C.c_double, C.c_double, C.POINTER(C.c_int),
                                      C.POINTER(C.c_int), C.POINTER(C.c_double)]),
+    "emrkc_eval_elementary": (C.c_int, [C.c_int, C.c_int, C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p]),
     "emrkc_create": (C.c_int, [C.POINTER(Mesh), C.POINTER(Conductivity), C.c_int, C.POINTER(Params),
                                C.POINTER(C.c_void_p)]),
     "emrkc_destroy": (None, [C.c_void_p]),
@@ -156,6 +157,22 @@ def emrkc_stage_counts(dt, rho_F, rho_S, eps=0.05):
     s, m, eta = C.c_int(), C.c_int(), C.c_double()
     _check(lib().emrkc_stage_counts(dt, rho_F, rho_S, eps, C.byref(s), C.byref(m), C.byref(eta)))
     return s.value, m.value, eta.value
+
+
+ELEMENTARY = {"exp": 0, "expm1": 1, "log": 2}
+
+
+def emrkc_eval_elementary(fn, x, precision="fp64", stream=None):
+    """y = f(x) on the device as the kernels evaluate it (x: CUDA float64 tensor)."""
+    import torch
+    x = x.contiguous()
+    if x.dtype != torch.float64 or not x.is_cuda:
+        raise ValueError("x must be a CUDA float64 tensor")
+    y = torch.empty_like(x)
+    st = stream if stream is not None else torch.cuda.current_stream(x.device).cuda_stream
+    _check(lib().emrkc_eval_elementary(ELEMENTARY[fn], PRECISIONS.get(precision, precision), x.data_ptr(),
+                                       y.data_ptr(), x.numel(), st))
+    return y
 
 
 def emrkc_create(mesh, cond, model, params):
