@@ -70,6 +70,17 @@ class Job:
         E.emrkc_set_stream(self.sim.ctx, stream.cuda_stream)
         self.nsim = int(round(cfg["T"] / cfg["dt"]))
 
+    def tune(self, variants=None):
+        """Kernel shapes: given, or chosen by the library's autotuner on the
+        resting state (outside the timed region, like compilation)."""
+        E, s = self.E, self.sim
+        if variants is not None:
+            E.emrkc_set_variants(s.ctx, variants)
+            return tuple(variants)
+        E.emrkc_init_state(s.ctx, s.state)
+        E.emrkc_estimate_rho(s.ctx, s.state)
+        return E.emrkc_autotune(s.ctx, s.state, self.cfg["dt"], reps=3)
+
     def run(self):
         E, s = self.E, self.sim
         s.state.t0 = 0.0
@@ -129,6 +140,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--fuse", action="store_true", help="fused last-inner-stage + head kernel")
+    ap.add_argument("--variants", default=None,
+                    help="kernel shapes 'head,head_planes,inner,inner_planes' instead of autotuning")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="copy a buffer of this size once (calibrates rocprof FETCH/WRITE counters)")
     args = ap.parse_args()
@@ -170,6 +183,9 @@ def main():
         log("bench: %s, N=%d, building FP64 context" % (cfg["name"], N))
         flags = E.EMRKC_FUSE if args.fuse else 0
         job = Job(cfg, "fp64", stream, flags, tet, batch)
+        forced = tuple(int(x) for x in args.variants.split(",")) if args.variants else None
+        variants = job.tune(forced)
+        log("bench: fp64 kernel shapes %s" % (variants,))
         elapsed, (rF, rS, itF, itS) = time_jobs(job, args.warmup, args.steps, torch)
         s, m, eta = E.emrkc_stages(job.sim.ctx, cfg["dt"])
         value = N * job.nsim * args.steps / elapsed
@@ -198,9 +214,11 @@ def main():
             tr = json.load(open(prof_path))
             if tr.get("kernel_source_hash") == kernel_hash():
                 traffic = tr.get("bytes_per_launch")
+        head_kernel = ("k_head_batch" if batch is not None else "k_head" if tet is not None else
+                       {0: "k_head_tiled", 1: "k_head_march", 2: "k_head_march_lds"}[variants[0]])
         names = {"fused": "k_fused (last inner stage of step n-1 + exponential Euler, ionic model, outer z "
                           "recurrence and first inner stage of step n)",
-                 "head": "k_head (exponential Euler, ionic model, outer z recurrence, first inner stage)"}
+                 "head": "%s (exponential Euler, ionic model, outer z recurrence, first inner stage)" % head_kernel}
         # the inner kernel in this pass is the last inner stage (stencil +
         # Chebyshev recurrence + outer V update) when m == 2
         if batch is not None:
@@ -221,11 +239,13 @@ def main():
         if not args.no_mixed:
             log("bench: mixed FP32 form")
             jm = Job(cfg, "mixed", stream, flags, tet, batch)
+            variants_m = jm.tune(forced)
+            log("bench: mixed kernel shapes %s" % (variants_m,))
             el_m, _ = time_jobs(jm, 1, max(1, args.steps // 2), torch)
             value_m = N * jm.nsim * max(1, args.steps // 2) / el_m
             Vm = jm.sim.V.cpu().numpy()
             d = Vm - V64
-            mixed = {"value": value_m, "speedup_vs_fp64": round(value_m / value, 3),
+            mixed = {"value": value_m, "speedup_vs_fp64": round(value_m / value, 3), "kernel_shapes": variants_m,
                      "V_rel_l2_vs_fp64": float(np.linalg.norm(d) / np.linalg.norm(V64)),
                      "V_rel_max_vs_fp64": float(np.abs(d).max() / np.abs(V64).max()),
                      "reference": "GPU FP64 path at T (matches the FP64 oracle to 1e-10 in the parity tests)"}
@@ -253,7 +273,7 @@ def main():
                                      if batch is not None else ("Q1 grid %s" % "x".join(map(str, cfg["n"]))),
                                      N, cfg["model"], cfg["chi"], cfg["Cm"], list(cfg["sigma"]), cfg["dt"], cfg["T"],
                                      job.nsim),
-                      "s": s, "m": m, "eta": eta, "rho_F": rF, "rho_S": rS, "powiter_iters": [itF, itS]},
+                      "kernel_shapes": variants, "s": s, "m": m, "eta": eta, "rho_F": rF, "rho_S": rS, "powiter_iters": [itF, itS]},
            "roofline": roof, "mixed": mixed, "cpu_baseline": cpu}
     print(json.dumps(out), flush=True)
 

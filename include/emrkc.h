@@ -257,6 +257,31 @@ int emrkc_batch_info(const emrkc_ctx *ctx, double dt, int64_t *offsets, int *m, 
 /* Sets every instance's radii (taken as given). */
 int emrkc_batch_set_rho(emrkc_ctx *ctx, const double *rho_F, const double *rho_S);
 
+/* ---- kernel shapes (3-D structured grids) --------------------------------
+ * variants[4] = {head kernel, head planes per column, inner kernel, inner
+ * planes per column}.  Head kernel: 0 = 3-D tiles of 16x4x4 nodes, 1 =
+ * z-marching columns of 32x8 nodes with the ionic state of the next plane
+ * prefetched into registers, 2 = z-marching columns with that state staged
+ * through LDS by direct global-to-LDS loads.  Inner kernel: 0 = 3-D tiles,
+ * 1 = z-marching columns.  Planes per column in [1, 64] and at most n[2]
+ * (0 when the kernel is 0).  Every variant gives bit-identical results; only
+ * speed differs.  Other meshes and batch contexts have one shape (all 0). */
+
+/* Times every candidate shape for a few steps (`reps` timed steps each, on
+ * a copy of `state`, which is not modified) and keeps the fastest head and
+ * inner kernels.  Candidates: tiles, and columns of 4, 8, 16 or 32 planes
+ * that leave at least 256 blocks.  Needs the radii.  Writes the choice to
+ * `variants` when non-NULL.  Allocates a temporary copy of the state.
+ * Synchronises the stream.  A no-op (returning the fixed shape) where
+ * nothing can be tuned or with the fused tail+head kernel. */
+int emrkc_autotune(emrkc_ctx *ctx, const emrkc_state *state, double dt, int reps, int *variants);
+
+int emrkc_get_variants(const emrkc_ctx *ctx, int *variants);
+
+/* Sets the shapes; EMRKC_EINVAL for values out of range, EMRKC_EUNSUPPORTED
+ * for non-zero values where nothing can be tuned. */
+int emrkc_set_variants(emrkc_ctx *ctx, const int *variants);
+
 /* ---- evaluation of single terms (component checks) ---------------------- */
 
 /* out[i] = ((chi Cm M_L)^{-1} A V)_i for i < N: the V component of f_F

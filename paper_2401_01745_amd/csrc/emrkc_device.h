@@ -414,10 +414,12 @@ struct Grid {
   uint32_t N;
   FastDiv div0, div1;    // division by n0 and by n1
   int dim;
-  // inner-stage kernel for 3-D grids: 0 = 3-D tiles, 1 = z-marching columns
-  // of zc planes per block (2.5-D); chosen by the host
+  // inner-stage and head kernels for 3-D grids: 0 = 3-D tiles, 1 = z-marching
+  // columns of zc (head_zc) planes per block (2.5-D); chosen by the host
   int inner_variant;
   uint32_t zc;
+  int head_variant;
+  uint32_t head_zc;
   // weights of (chi Cm M_L)^{-1} A on neighbour differences, by offset class
   // (|ox|, |oy|, |oz|): w[0]=100, w[1]=010, w[2]=001, w[3]=110, w[4]=101,
   // w[5]=011, w[6]=111 (2-D uses w[0], w[1], w[3]).
@@ -433,8 +435,15 @@ __device__ __forceinline__ uint32_t mirror_hi(uint32_t i, uint32_t n) { return i
 // operator equals the interior formula with mirrored neighbours.  FP64:
 // differences and products in double.  Mixed: differences in double (V
 // carries a resting offset of about -65 mV), products and sums in float.
+__device__ __forceinline__ double fma_t(double a, double b, double c) { return __builtin_fma(a, b, c); }
+__device__ __forceinline__ float fma_t(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+
+// Written with explicit fused multiply-adds in a fixed order and no further
+// contraction, so that the flat, LDS-tiled and z-marching kernels round
+// identically.
 template <int DIM, bool MIXED, class Get>
 __device__ __forceinline__ double grid_stencil(const double *w, Get get) {
+#pragma clang fp contract(off)
   using T = typename std::conditional<MIXED, float, double>::type;
   const double uc = get(0, 0, 0);
   auto d = [&](int dx, int dy, int dz) { return (T)(get(dx, dy, dz) - uc); };
@@ -442,7 +451,7 @@ __device__ __forceinline__ double grid_stencil(const double *w, Get get) {
     const T f = d(-1, 0, 0) + d(1, 0, 0);
     const T e = d(0, -1, 0) + d(0, 1, 0);
     const T c = (d(-1, -1, 0) + d(1, -1, 0)) + (d(-1, 1, 0) + d(1, 1, 0));
-    return (double)((T)w[0] * f + (T)w[1] * e + (T)w[3] * c);
+    return (double)fma_t((T)w[3], c, fma_t((T)w[1], e, (T)w[0] * f));
   }
   const T fx = d(-1, 0, 0) + d(1, 0, 0);
   const T fy = d(0, -1, 0) + d(0, 1, 0);
@@ -452,8 +461,13 @@ __device__ __forceinline__ double grid_stencil(const double *w, Get get) {
   const T eyz = (d(0, -1, -1) + d(0, 1, -1)) + (d(0, -1, 1) + d(0, 1, 1));
   const T cm = (d(-1, -1, -1) + d(1, -1, -1)) + (d(-1, 1, -1) + d(1, 1, -1));
   const T cp = (d(-1, -1, 1) + d(1, -1, 1)) + (d(-1, 1, 1) + d(1, 1, 1));
-  return (double)((T)w[0] * fx + (T)w[1] * fy + (T)w[2] * fz + (T)w[3] * exy + (T)w[4] * exz +
-                  (T)w[5] * eyz + (T)w[6] * (cm + cp));
+  T r = (T)w[0] * fx;
+  r = fma_t((T)w[1], fy, r);
+  r = fma_t((T)w[2], fz, r);
+  r = fma_t((T)w[3], exy, r);
+  r = fma_t((T)w[4], exz, r);
+  r = fma_t((T)w[5], eyz, r);
+  return (double)fma_t((T)w[6], cm + cp, r);
 }
 
 // The stencil on a global array at node (ix, iy, iz).

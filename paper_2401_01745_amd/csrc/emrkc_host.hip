@@ -21,7 +21,6 @@ using namespace emrkc;
 #define EMRKC_EAGER_FLAG 2u     // internal: never capture graphs (testing)
 #define EMRKC_FUSE_FLAG 4u      // internal: fused tail+head kernel (s == 1, m >= 2, grids)
 #define EMRKC_FLAT_FLAG 8u      // internal: flat global-load kernels on grids (testing)
-#define EMRKC_MARCH_FLAG 16u    // internal: z-marching inner kernel with 4 planes per block (testing)
 
 struct GraphKey {
   int s, m, chunk;
@@ -451,10 +450,10 @@ extern "C" int emrkc_create(const emrkc_mesh *mesh, const emrkc_conductivity *co
       g.zc = zc;
       // short columns re-read too much halo: small grids keep 3-D tiles
       g.inner_variant = (c->dim == 3 && zc >= 4) ? 1 : 0;
-      if (c->dim == 3 && (p->flags & EMRKC_MARCH_FLAG)) {
-        g.inner_variant = 1;
-        g.zc = 4;
-      }
+      // head: z-marching with the ionic state staged through LDS where the
+      // columns are long enough, else 3-D tiles (emrkc_autotune refines both)
+      g.head_variant = g.inner_variant ? ((uint64_t)g.N * sizeof(double) < (1ull << 32) ? 2 : 1) : 0;
+      g.head_zc = g.zc;
     }
   } else {
     rc = build_p1(c, mesh, cond);
@@ -961,6 +960,160 @@ extern "C" int emrkc_profile_step(emrkc_ctx *c, emrkc_state *st, double dt, int6
 }
 
 // ---------------------------------------------------------------------------
+// Kernel shapes of 3-D grids and their autotuning
+// ---------------------------------------------------------------------------
+static bool tunable(const emrkc_ctx *c) {
+  return !c->batch && c->mesh.kind == kGrid && c->dim == 3 && !c->flat;
+}
+
+static void get_variants(const emrkc_ctx *c, int *v) {
+  const Grid &g = c->mesh.grid;
+  v[0] = g.head_variant;
+  v[1] = g.head_variant ? (int)g.head_zc : 0;
+  v[2] = g.inner_variant;
+  v[3] = g.inner_variant ? (int)g.zc : 0;
+}
+
+static int check_variants(const emrkc_ctx *c, const int *v) {
+  if (!tunable(c)) return (v[0] | v[1] | v[2] | v[3]) == 0 ? EMRKC_OK : EMRKC_EUNSUPPORTED;
+  const int n2 = (int)c->mesh.grid.n2;
+  if (v[0] < 0 || v[0] > 2 || v[2] < 0 || v[2] > 1) return EMRKC_EINVAL;
+  // the LDS-staged head addresses a component plane with 32-bit byte offsets
+  if (v[0] == 2 && (uint64_t)c->N * sizeof(double) >= (1ull << 32)) return EMRKC_EUNSUPPORTED;
+  if (v[0] != 0 && (v[1] < 1 || v[1] > 64 || v[1] > n2)) return EMRKC_EINVAL;
+  if (v[2] != 0 && (v[3] < 1 || v[3] > 64 || v[3] > n2)) return EMRKC_EINVAL;
+  return EMRKC_OK;
+}
+
+static void set_variants(emrkc_ctx *c, const int *v) {
+  Grid &g = c->mesh.grid;
+  g.head_variant = v[0];
+  g.head_zc = v[0] ? (uint32_t)v[1] : 1u;
+  g.inner_variant = v[2];
+  g.zc = v[2] ? (uint32_t)v[3] : 1u;
+  clear_graphs(c);
+}
+
+extern "C" int emrkc_get_variants(const emrkc_ctx *c, int *variants) {
+  if (c == nullptr || variants == nullptr) return EMRKC_EINVAL;
+  if (!tunable(c)) {
+    for (int k = 0; k < 4; ++k) variants[k] = 0;
+    return EMRKC_OK;
+  }
+  get_variants(c, variants);
+  return EMRKC_OK;
+}
+
+extern "C" int emrkc_set_variants(emrkc_ctx *c, const int *variants) {
+  if (c == nullptr || variants == nullptr) return EMRKC_EINVAL;
+  const int rc = check_variants(c, variants);
+  if (rc != EMRKC_OK) return fail(c, rc, "kernel variants (%d,%d,%d,%d) not valid for this context", variants[0],
+                                  variants[1], variants[2], variants[3]);
+  if (tunable(c)) set_variants(c, variants);
+  return EMRKC_OK;
+}
+
+// Mean duration per launch of the head (cls 0) and inner (cls 1) kernels
+// over `reps` steps on state `st` (advanced).
+static int time_classes(emrkc_ctx *c, emrkc_state *st, const StepPlan &P, double dt, int reps, double *ms) {
+  HIP_TRY(c, launch_clock_set(c->d_clock, st->step, st->t0, c->stream));
+  int rc = enqueue_chunk(c, st, P, dt, 1, c->stream, nullptr);  // untimed: first launch of each kernel
+  if (rc != EMRKC_OK) return rc;
+  KernelTimer tm;
+  rc = enqueue_chunk(c, st, P, dt, reps, c->stream, &tm);
+  hipError_t e = hipStreamSynchronize(c->stream);
+  double sum[3] = {0, 0, 0};
+  int cnt[3] = {0, 0, 0};
+  if (rc == EMRKC_OK && e == hipSuccess) {
+    for (size_t k = 0; k + 1 < tm.used; k += 2) {
+      float t_ms = 0;
+      if (hipEventElapsedTime(&t_ms, tm.ev[k], tm.ev[k + 1]) != hipSuccess) {
+        rc = fail(c, EMRKC_EHIP, "hipEventElapsedTime failed");
+        break;
+      }
+      sum[tm.cls[k / 2]] += t_ms;
+      cnt[tm.cls[k / 2]] += 1;
+    }
+  }
+  for (hipEvent_t ev : tm.ev) (void)hipEventDestroy(ev);
+  if (e != hipSuccess) return fail(c, EMRKC_EHIP, "autotuning steps failed: %s", hipGetErrorString(e));
+  if (rc != EMRKC_OK) return rc;
+  for (int k = 0; k < 2; ++k) ms[k] = cnt[k] ? sum[k] / cnt[k] : 0.0;
+  return EMRKC_OK;
+}
+
+extern "C" int emrkc_autotune(emrkc_ctx *c, const emrkc_state *st, double dt, int reps, int *variants) {
+  if (c == nullptr) return EMRKC_EINVAL;
+  if (!state_ok(c, st)) return fail(c, EMRKC_EINVAL, "state buffers missing");
+  if (!(dt > 0) || !isfinite(dt) || reps < 1 || reps > 1000) return fail(c, EMRKC_EINVAL, "invalid dt or reps");
+  if (!c->have_rho) return fail(c, EMRKC_EINVAL, "spectral radii not set");
+  if (!tunable(c) || c->use_fused) return emrkc_get_variants(c, variants);
+  StepPlan P;
+  int rc = make_plan(c, dt, P);
+  if (rc != EMRKC_OK) return rc;
+  const Grid &g = c->mesh.grid;
+  // candidates: 3-D tiles, and z-marching columns of zc planes for every
+  // zc in {4, 8, 16, 32} that leaves at least one block per compute unit
+  const uint32_t cols = ((g.n0 + MX - 1) / MX) * ((g.n1 + MY - 1) / MY);
+  std::vector<int> zcs;
+  for (int zc : {4, 8, 16, 32})
+    if (zc <= (int)g.n2 && cols * ((g.n2 + zc - 1) / zc) >= 256) zcs.push_back(zc);
+  std::vector<std::pair<int, int>> heads{{0, 0}}, inners{{0, 0}};
+  const bool lds_ok = (uint64_t)c->N * sizeof(double) < (1ull << 32);
+  for (int zc : zcs) {
+    heads.push_back({1, zc});
+    if (lds_ok) heads.push_back({2, zc});
+    inners.push_back({1, zc});
+  }
+  int orig[4];
+  get_variants(c, orig);
+  // timing runs on a copy of the state
+  const size_t zb = (size_t)(c->nv - 1) * (size_t)c->N * (c->mixed ? sizeof(float) : sizeof(double));
+  void *V = nullptr, *Z = nullptr;
+  if (hipMalloc(&V, (size_t)c->N * sizeof(double)) != hipSuccess || hipMalloc(&Z, zb) != hipSuccess) {
+    if (V) (void)hipFree(V);
+    return fail(c, EMRKC_ENOMEM, "autotuning: no memory for a state copy");
+  }
+  emrkc_state tmp = *st;
+  tmp.V = V;
+  tmp.z = Z;
+  double best_h = 1e300, best_i = 1e300;
+  int choice[4] = {orig[0], orig[1], orig[2], orig[3]};
+  const size_t ncand = std::max(heads.size(), inners.size());
+  rc = EMRKC_OK;
+  if (hipMemcpyAsync(V, st->V, (size_t)c->N * sizeof(double), hipMemcpyDeviceToDevice, c->stream) != hipSuccess ||
+      hipMemcpyAsync(Z, st->z, zb, hipMemcpyDeviceToDevice, c->stream) != hipSuccess)
+    rc = fail(c, EMRKC_EHIP, "autotuning: state copy failed");
+  for (size_t k = 0; k < ncand && rc == EMRKC_OK; ++k) {
+    const auto hv = heads[k % heads.size()], iv = inners[k % inners.size()];
+    const int v[4] = {hv.first, hv.second, iv.first, iv.second};
+    set_variants(c, v);
+    double ms[2];
+    rc = time_classes(c, &tmp, P, dt, reps, ms);
+    if (rc != EMRKC_OK) break;
+    if (getenv("EMRKC_VERBOSE"))
+      fprintf(stderr, "emrkc_autotune: head %d/%d %.5f ms, inner %d/%d %.5f ms\n", v[0], v[1], ms[0], v[2], v[3],
+              ms[1]);
+    if (ms[0] > 0 && ms[0] < best_h) {
+      best_h = ms[0];
+      choice[0] = v[0];
+      choice[1] = v[1];
+    }
+    if (ms[1] > 0 && ms[1] < best_i) {
+      best_i = ms[1];
+      choice[2] = v[2];
+      choice[3] = v[3];
+    }
+  }
+  (void)hipStreamSynchronize(c->stream);
+  (void)hipFree(V);
+  (void)hipFree(Z);
+  set_variants(c, rc == EMRKC_OK ? choice : orig);
+  if (rc == EMRKC_OK && variants) get_variants(c, variants);
+  return rc;
+}
+
+// ---------------------------------------------------------------------------
 // Nonlinear power iteration (appendix, Compute_Rho)
 // ---------------------------------------------------------------------------
 static int fetch(emrkc_ctx *c, double *out) {
@@ -1317,8 +1470,8 @@ extern "C" int emrkc_create_batch(int n_inst, const emrkc_mesh *meshes, const em
     g.N = g.n0 * g.n1 * g.n2;
     g.div0 = make_fastdiv(g.n0);
     g.div1 = make_fastdiv(g.n1);
-    g.inner_variant = 0;
-    g.zc = 1;
+    g.inner_variant = g.head_variant = 0;
+    g.zc = g.head_zc = 1;
     const double h[3] = {m.h[0], m.h[1], m.dim == 3 ? m.h[2] : 1.0};
     const double sg[3] = {conds[k].sigma_l, conds[k].sigma_t, conds[k].sigma_n};
     grid_weights(m.dim, h, sg, p.chi * p.Cm, g.w);

@@ -105,6 +105,9 @@ struct BatchInst {
   InnerArgs in;  // inner launches: this instance's coefficients (pointers global)
 };
 
+// Column cross-section (nodes in x and y) of the z-marching kernels.
+constexpr int MX = 32, MY = 8;
+
 // ---- launchers (emrkc_kernels.hip) ----------------------------------------
 // Tiles of a grid in the LDS-tiled layout (3-D 16x4x4, 2-D 64x4).
 uint32_t grid_tiles(const Grid &g, uint32_t &ntx, uint32_t &nty);

@@ -43,14 +43,14 @@ __device__ __forceinline__ double ell_apply(const Ell &e, const double *__restri
     float acc = 0.0f;
     for (uint32_t k = 0; k < e.width; ++k) {
       const uint32_t c = e.col[(size_t)k * e.N + i];
-      acc += e.w32[(size_t)k * e.N + i] * (float)(u[c] - uc);
+      acc = __builtin_fmaf(e.w32[(size_t)k * e.N + i], (float)(u[c] - uc), acc);
     }
     return (double)acc;
   }
   double acc = 0.0;
   for (uint32_t k = 0; k < e.width; ++k) {
     const uint32_t c = e.col[(size_t)k * e.N + i];
-    acc += e.w64[(size_t)k * e.N + i] * (u[c] - uc);
+    acc = __builtin_fma(e.w64[(size_t)k * e.N + i], u[c] - uc, acc);
   }
   return acc;
 }
@@ -92,20 +92,40 @@ __global__ __launch_bounds__(kBlock) void k_init_state(uint32_t N, double *V, vo
 // ---------------------------------------------------------------------------
 // FVf() evaluates f_F(V_{j-1}) at the node; it is called after the z update
 // so that the stencil operands are not live across the ionic model.
+// z_{j-1} of node i (all ionic components, SoA planes N apart)
+template <template <class> class Model, bool MIXED>
+struct HeadZ {
+  using R = typename MathOf<MIXED>::R;
+  static constexpr int NZ = Model<MathOf<MIXED>>::NG + Model<MathOf<MIXED>>::NS;
+  R z[NZ];
+  __device__ __forceinline__ void load(const void *zin, uint32_t N, uint32_t i) {
+    const R *p = (const R *)zin;
+#pragma unroll
+    for (int k = 0; k < NZ; ++k) z[k] = p[(size_t)k * N + i];
+  }
+};
+
+template <template <class> class Model, bool MIXED, class FVf>
+__device__ __forceinline__ void head_node_z(const HeadArgs &a, uint32_t N, uint32_t i, double V,
+                                            const typename MathOf<MIXED>::R *z, double Is, FVf FVfun);
+
 template <template <class> class Model, bool MIXED, class FVf>
 __device__ __forceinline__ void head_node(const HeadArgs &a, uint32_t N, uint32_t i, double V, FVf FVfun) {
+  HeadZ<Model, MIXED> hz;
+  hz.load(a.zin, N, i);
+  const double tj = stage_time(a.clock, a.step_off, a.dt, a.c_prev);
+  head_node_z<Model, MIXED>(a, N, i, V, hz.z, stimulus(a.stim, i, tj), FVfun);
+}
+
+// The head at node i with z_{j-1} and the stimulus current I_stim(t_j) at
+// the node given.
+template <template <class> class Model, bool MIXED, class FVf>
+__device__ __forceinline__ void head_node_z(const HeadArgs &a, uint32_t N, uint32_t i, double V,
+                                            const typename MathOf<MIXED>::R *z, double Is, FVf FVfun) {
   using M = MathOf<MIXED>;
   using R = typename M::R;
   using Mod = Model<M>;
   constexpr int NG = Mod::NG, NS = Mod::NS, NZ = NG + NS;
-
-  const double tj = stage_time(a.clock, a.step_off, a.dt, a.c_prev);
-  const double Is = stimulus(a.stim, i, tj);
-
-  const R *zin = (const R *)a.zin;
-  R z[NZ];
-#pragma unroll
-  for (int k = 0; k < NZ; ++k) z[k] = zin[(size_t)k * N + i];
 
   // exponential Euler for the gates: z_E + (e^{eta Lambda} - 1)(z_E - z_inf)
   R lam[NG], zinf[NG], zE[NG];
@@ -178,16 +198,29 @@ __device__ __forceinline__ double load_sv(const void *SV, bool mixed, uint32_t i
 }
 
 // u_k = nu u_{k-1} + kappa u_{k-2} + mu eta (f_F(u_{k-1}) + S_V)
+// The combinations are written with explicit fused multiply-adds and no
+// further contraction, so that every kernel that evaluates them (flat,
+// tiled, z-marching, fused, batched) rounds identically.
+__device__ __forceinline__ double inner_combine(const TailArgs &t, double uc, double u2, double Fu, double sv) {
+#pragma clang fp contract(off)
+  return __builtin_fma(t.nu, uc, __builtin_fma(t.kappa, u2, t.mu_eta * (Fu + sv)));
+}
+
+__device__ __forceinline__ double tail_combine(const TailArgs &t, double um, double vp, double vp2) {
+#pragma clang fp contract(off)
+  const double fbar = (um - vp) * t.inv_eta;
+  return t.j1 ? __builtin_fma(t.mu_dt, fbar, vp)
+              : __builtin_fma(t.nu_o, vp, __builtin_fma(t.kappa_o, vp2, t.mu_dt * fbar));
+}
+
 __device__ __forceinline__ double inner_value(const TailArgs &t, double Fu, double sv, uint32_t i) {
-  return t.nu * t.uprev[i] + t.kappa * t.uprev2[i] + t.mu_eta * (Fu + sv);
+  return inner_combine(t, t.uprev[i], t.uprev2[i], Fu, sv);
 }
 
 // outer V update from the last inner value: V_j = nu V_{j-1} + kappa V_{j-2}
 // + mu dt (u_m - V_{j-1})/eta
 __device__ __forceinline__ double tail_from_um(const TailArgs &t, double um, uint32_t i) {
-  const double Vp = t.Vin[i];
-  const double fbar = (um - Vp) * t.inv_eta;
-  return t.j1 ? Vp + t.mu_dt * fbar : t.nu_o * Vp + t.kappa_o * t.Vin2[i] + t.mu_dt * fbar;
+  return tail_combine(t, um, t.Vin[i], t.j1 ? 0.0 : t.Vin2[i]);
 }
 
 template <bool MIXED>
@@ -344,9 +377,33 @@ __global__ __launch_bounds__(kBlock) void k_inner_tiled(InnerArgs a, Grid g, uin
 // loaded into registers while plane z is computed.  Each plane is read
 // from memory once per column instead of once per neighbouring tile.
 // ---------------------------------------------------------------------------
-constexpr int MX = 32, MY = 8;
 constexpr int MSX = MX + 2, MSY = MY + 2, MPL = MSX * MSY;
 constexpr int MSLOT = (MPL + kBlock - 1) / kBlock;
+
+// Pointwise operands of an inner stage at one node, loaded a plane ahead.
+struct InnerPoint {
+  double u2, sv, vp, vp2;
+};
+
+template <bool MIXED>
+__device__ __forceinline__ InnerPoint load_point(const InnerArgs &a, uint32_t i) {
+  InnerPoint p;
+  p.u2 = a.t.uprev2[i];
+  p.sv = load_sv(a.t.SV, MIXED, i);
+  p.vp = 0.0;
+  p.vp2 = 0.0;
+  if (a.last) {
+    p.vp = a.t.uprev2 == a.t.Vin ? p.u2 : a.t.Vin[i];  // m == 2: u_0 is V_{j-1}
+    if (!a.t.j1) p.vp2 = a.t.Vin2[i];
+  }
+  return p;
+}
+
+// inner_value / tail_from_um with the operands given (same expressions)
+__device__ __forceinline__ double inner_point(const InnerArgs &a, double uc, double Fu, const InnerPoint &p) {
+  const double uk = inner_combine(a.t, uc, p.u2, Fu, p.sv);
+  return a.last ? tail_combine(a.t, uk, p.vp, p.vp2) : uk;
+}
 
 template <bool MIXED>
 __global__ __launch_bounds__(kBlock) void k_inner_march(InnerArgs a, Grid g, uint32_t ncx, uint32_t ncy) {
@@ -389,16 +446,21 @@ __global__ __launch_bounds__(kBlock) void k_inner_march(InnerArgs a, Grid g, uin
   const uint32_t gx = (uint32_t)(x0 + lx), gy = (uint32_t)(y0 + ly);
   const bool own = gx < g.n0 && gy < g.n1;
   const int c = (ly + 1) * MSX + (lx + 1);
-  for (int z = zb; z < ze; ++z) {
+  uint32_t i = gx + g.n0 * gy + plane * (uint32_t)zb;
+  InnerPoint pt{0.0, 0.0, 0.0, 0.0};
+  if (own) pt = load_point<MIXED>(a, i);
+  for (int z = zb; z < ze; ++z, i += plane) {
     double *nxt = ring[(z + 1) % 3];
 #pragma unroll
     for (int k = 0; k < MSLOT; ++k)
       if (act[k]) nxt[threadIdx.x + k * kBlock] = pre[k];
     __syncthreads();
+    const InnerPoint cur = pt;
     if (z + 1 < ze) {
       const size_t pz = gplane(z + 2);
 #pragma unroll
       for (int k = 0; k < MSLOT; ++k) pre[k] = act[k] ? u[pz + off[k]] : 0.0;
+      if (own) pt = load_point<MIXED>(a, i + plane);
     }
     if (own) {
       const double *pm = ring[(z + 2) % 3], *pc = ring[z % 3], *pp = ring[(z + 1) % 3];
@@ -406,9 +468,233 @@ __global__ __launch_bounds__(kBlock) void k_inner_march(InnerArgs a, Grid g, uin
         const double *pl = dz < 0 ? pm : (dz > 0 ? pp : pc);
         return pl[c + dy * MSX + dx];
       });
-      const uint32_t i = gx + g.n0 * gy + plane * (uint32_t)z;
-      const double uk = inner_value(a.t, Fu, load_sv(a.t.SV, MIXED, i), i);
-      a.out[i] = a.last ? tail_from_um(a.t, uk, i) : uk;
+      a.out[i] = inner_point(a, pc[c], Fu, cur);
+    }
+    __syncthreads();
+  }
+}
+
+// Head on 3-D grids by z-marching columns: the MX x MY column layout and
+// LDS ring of V_{j-1} of k_inner_march, with the ionic state z_{j-1} of the
+// next plane loaded into registers while the current plane is computed, so
+// that every wave keeps loads in flight during its ionic arithmetic.
+template <template <class> class Model, bool MIXED>
+__global__ __launch_bounds__(kBlock) void k_head_march(HeadArgs a, Grid g, uint32_t ncx, uint32_t ncy) {
+  __shared__ double ring[3][MPL];
+  const uint32_t b = xcd_block(blockIdx.x, gridDim.x);
+  const uint32_t bx = b % ncx, byz = b / ncx;
+  const uint32_t by = byz % ncy, bz = byz / ncy;
+  const int x0 = (int)(bx * MX), y0 = (int)(by * MY);
+  const int zb = (int)(bz * g.zc);
+  const int ze = min(zb + (int)g.zc, (int)g.n2);
+  const uint32_t plane = g.n0 * g.n1;
+  uint32_t off[MSLOT];
+  bool act[MSLOT];
+#pragma unroll
+  for (int k = 0; k < MSLOT; ++k) {
+    const int r = threadIdx.x + k * kBlock;
+    act[k] = r < MPL;
+    const int hx = r % MSX, hy = r / MSX;
+    off[k] = act[k] ? mirror_any(x0 + hx - 1, g.n0) + g.n0 * mirror_any(y0 + hy - 1, g.n1) : 0u;
+  }
+  const double *__restrict__ u = a.Vin;
+  auto gplane = [&](int z) { return (size_t)mirror_any(z, g.n2) * plane; };
+  auto stage = [&](double *dst, int z) {
+    const size_t pz = gplane(z);
+#pragma unroll
+    for (int k = 0; k < MSLOT; ++k)
+      if (act[k]) dst[threadIdx.x + k * kBlock] = u[pz + off[k]];
+  };
+  stage(ring[(zb + 2) % 3], zb - 1);
+  stage(ring[zb % 3], zb);
+  double pre[MSLOT];
+  {
+    const size_t pz = gplane(zb + 1);
+#pragma unroll
+    for (int k = 0; k < MSLOT; ++k) pre[k] = act[k] ? u[pz + off[k]] : 0.0;
+  }
+  const int lx = threadIdx.x % MX, ly = threadIdx.x / MX;
+  const uint32_t gx = (uint32_t)(x0 + lx), gy = (uint32_t)(y0 + ly);
+  const bool own = gx < g.n0 && gy < g.n1;
+  const int c = (ly + 1) * MSX + (lx + 1);
+  uint32_t i = gx + g.n0 * gy + plane * (uint32_t)zb;
+  HeadZ<Model, MIXED> nz;
+  if (own) nz.load(a.zin, g.N, i);
+  const double tj = stage_time(a.clock, a.step_off, a.dt, a.c_prev);
+  for (int z = zb; z < ze; ++z, i += plane) {
+    double *nxt = ring[(z + 1) % 3];
+#pragma unroll
+    for (int k = 0; k < MSLOT; ++k)
+      if (act[k]) nxt[threadIdx.x + k * kBlock] = pre[k];
+    __syncthreads();
+    const HeadZ<Model, MIXED> cz = nz;
+    if (z + 1 < ze) {
+      const size_t pz = gplane(z + 2);
+#pragma unroll
+      for (int k = 0; k < MSLOT; ++k) pre[k] = act[k] ? u[pz + off[k]] : 0.0;
+      if (own) nz.load(a.zin, g.N, i + plane);
+    }
+    if (own) {
+      const double *pm = ring[(z + 2) % 3], *pc = ring[z % 3], *pp = ring[(z + 1) % 3];
+      head_node_z<Model, MIXED>(a, g.N, i, pc[c], cz.z, stimulus(a.stim, i, tj), [&]() {
+        return grid_stencil<3, MIXED>(g.w, [&](int dx, int dy, int dz) {
+          const double *pl = dz < 0 ? pm : (dz > 0 ? pp : pc);
+          return pl[c + dy * MSX + dx];
+        });
+      });
+    }
+    __syncthreads();
+  }
+}
+
+// Head by z-marching columns with the ionic state staged through LDS: each
+// wave copies z_{j-1} of its own 64 nodes of the next plane into its LDS
+// slice with direct global-to-LDS loads (no registers held while in
+// flight), and reads the current plane's slice into registers first.  Only
+// the wave that loads a slice reads it, so the slices need no barrier; the
+// V ring is shared as in k_inner_march.
+typedef __attribute__((address_space(3))) void lds_void_t;
+typedef __attribute__((address_space(1))) void glb_void_t;
+
+// `lds` is an LDS byte address (an offset into the workgroup's LDS, which
+// may be 0); it is converted to an LDS pointer directly, never through a
+// generic pointer, whose null value would map to the LDS null (-1).
+__device__ __forceinline__ void lds_dma_dword(const void *src, uint32_t lds) {
+  __builtin_amdgcn_global_load_lds((glb_void_t *)src, (lds_void_t *)(uintptr_t)lds, 4, 0, 0);
+}
+// Waits (and orders the compiler's memory accesses) for this wave's
+// outstanding vector-memory loads, including the LDS copies, or for its LDS
+// reads.
+__device__ __forceinline__ void wait_vm() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
+__device__ __forceinline__ void wait_lgkm() { asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory"); }
+
+template <template <class> class Model, bool MIXED>
+struct ZSlice {
+  using R = typename MathOf<MIXED>::R;
+  static constexpr int NZ = HeadZ<Model, MIXED>::NZ;
+  static constexpr int DW = sizeof(R) / 4;          // dwords per value
+  static constexpr int SLICE = NZ * 64 * (int)sizeof(R);
+  static constexpr int BYTES = (kBlock / 64) * SLICE;
+  // Copies component k of the lane's nodes (byte offsets voff[h] within a
+  // component plane) to bytes [k * 64 * sizeof(R), ...) of the wave's slice
+  // at LDS address `slice`.  `zb` is the state base, made opaque per call so
+  // that the per-component addresses are formed here and not kept live.
+  static __device__ __forceinline__ void copy(uint32_t slice, const char *zb, uint64_t plane_bytes,
+                                              const uint32_t voff[DW]) {
+    asm volatile("" : "+s"(zb));
+    asm volatile("" : "+s"(slice));
+#pragma unroll
+    for (int k = 0; k < NZ; ++k) {
+#pragma unroll
+      for (int h = 0; h < DW; ++h)
+        lds_dma_dword(zb + voff[h], slice + (uint32_t)((k * 64 + h * 32) * sizeof(R)));
+      zb += plane_bytes;
+    }
+  }
+  static __device__ __forceinline__ void read(const char *lds, R *z) {
+    const uint32_t lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const R *src = (const R *)(lds + (size_t)w * SLICE);
+#pragma unroll
+    for (int k = 0; k < NZ; ++k) z[k] = src[k * 64 + lane];
+  }
+};
+
+template <template <class> class Model, bool MIXED>
+__global__ __launch_bounds__(kBlock) void k_head_march_lds(HeadArgs a, Grid g, uint32_t ncx, uint32_t ncy) {
+  using ZS = ZSlice<Model, MIXED>;
+  using R = typename ZS::R;
+  __shared__ double ring[3][MPL];
+  __shared__ __attribute__((aligned(16))) char zlds[ZS::BYTES];
+  const uint32_t b = xcd_block(blockIdx.x, gridDim.x);
+  const uint32_t bx = b % ncx, byz = b / ncx;
+  const uint32_t by = byz % ncy, bz = byz / ncy;
+  const int x0 = (int)(bx * MX), y0 = (int)(by * MY);
+  const int zb = (int)(bz * g.zc);
+  const int ze = min(zb + (int)g.zc, (int)g.n2);
+  const uint32_t plane = g.n0 * g.n1;
+  uint32_t off[MSLOT];
+  bool act[MSLOT];
+#pragma unroll
+  for (int k = 0; k < MSLOT; ++k) {
+    const int r = threadIdx.x + k * kBlock;
+    act[k] = r < MPL;
+    const int hx = r % MSX, hy = r / MSX;
+    off[k] = act[k] ? mirror_any(x0 + hx - 1, g.n0) + g.n0 * mirror_any(y0 + hy - 1, g.n1) : 0u;
+  }
+  const double *__restrict__ u = a.Vin;
+  auto gplane = [&](int z) { return (size_t)mirror_any(z, g.n2) * plane; };
+  auto stage = [&](double *dst, int z) {
+    const size_t pz = gplane(z);
+#pragma unroll
+    for (int k = 0; k < MSLOT; ++k)
+      if (act[k]) dst[threadIdx.x + k * kBlock] = u[pz + off[k]];
+  };
+  // byte offsets (within a component plane, at plane z = 0) of the dwords
+  // this lane copies: nodes of this wave, those outside the grid clamped
+  // onto it (their values are never used)
+  const uint32_t lane = threadIdx.x & 63, wbase = threadIdx.x & ~63u;
+  uint32_t voff0[ZS::DW];
+#pragma unroll
+  for (int h = 0; h < ZS::DW; ++h) {
+    const uint32_t t = wbase + (ZS::DW == 2 ? h * 32 + (lane >> 1) : lane);
+    const uint32_t cx = min((uint32_t)x0 + t % MX, g.n0 - 1), cy = min((uint32_t)y0 + t / MX, g.n1 - 1);
+    voff0[h] = (cx + g.n0 * cy) * (uint32_t)sizeof(R) + (ZS::DW == 2 ? (lane & 1) * 4u : 0u);
+  }
+  const uint32_t slice = (uint32_t)(uintptr_t)(lds_void_t *)(zlds) +
+                         (uint32_t)__builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6)) * (uint32_t)ZS::SLICE;
+  const uint64_t comp_bytes = (uint64_t)g.N * sizeof(R);
+  auto copy_plane = [&](int z) {
+    uint32_t voff[ZS::DW];
+#pragma unroll
+    for (int h = 0; h < ZS::DW; ++h) voff[h] = voff0[h] + (uint32_t)z * plane * (uint32_t)sizeof(R);
+    ZS::copy(slice, (const char *)a.zin, comp_bytes, voff);
+  };
+  const int lx = threadIdx.x % MX, ly = threadIdx.x / MX;
+  const uint32_t gx = (uint32_t)(x0 + lx), gy = (uint32_t)(y0 + ly);
+  const bool own = gx < g.n0 && gy < g.n1;
+  const int c = (ly + 1) * MSX + (lx + 1);
+  uint32_t i = gx + g.n0 * gy + plane * (uint32_t)zb;
+  // the stage time is uniform; the stimulus mask of the next plane is
+  // loaded with its state copy, so no load is waited for during the ionic
+  // arithmetic
+  const double tj = stage_time(a.clock, a.step_off, a.dt, a.c_prev);
+  const bool stim_on = a.stim.mask != nullptr && a.stim.t_on <= tj && tj <= a.stim.t_off;
+  uint8_t mnext = (stim_on && own) ? a.stim.mask[i] : (uint8_t)0;
+  stage(ring[(zb + 2) % 3], zb - 1);
+  stage(ring[zb % 3], zb);
+  double pre[MSLOT];
+  {
+    const size_t pz = gplane(zb + 1);
+#pragma unroll
+    for (int k = 0; k < MSLOT; ++k) pre[k] = act[k] ? u[pz + off[k]] : 0.0;
+  }
+  copy_plane(zb);
+  for (int z = zb; z < ze; ++z, i += plane) {
+    double *nxt = ring[(z + 1) % 3];
+#pragma unroll
+    for (int k = 0; k < MSLOT; ++k)
+      if (act[k]) nxt[threadIdx.x + k * kBlock] = pre[k];
+    const uint8_t mcur = mnext;
+    wait_vm();  // this wave's slice of plane z, the mask byte
+    __syncthreads();
+    R zc[ZS::NZ];
+    ZS::read(zlds, zc);
+    wait_lgkm();  // slice read before it is overwritten
+    if (z + 1 < ze) {
+      mnext = (stim_on && own) ? a.stim.mask[i + plane] : (uint8_t)0;
+      const size_t pz = gplane(z + 2);
+#pragma unroll
+      for (int k = 0; k < MSLOT; ++k) pre[k] = act[k] ? u[pz + off[k]] : 0.0;
+      copy_plane(z + 1);
+    }
+    if (own) {
+      const double *pm = ring[(z + 2) % 3], *pc = ring[z % 3], *pp = ring[(z + 1) % 3];
+      head_node_z<Model, MIXED>(a, g.N, i, pc[c], zc, mcur != 0 ? a.stim.amp : 0.0, [&]() {
+        return grid_stencil<3, MIXED>(g.w, [&](int dx, int dy, int dz) {
+          const double *pl = dz < 0 ? pm : (dz > 0 ? pp : pc);
+          return pl[c + dy * MSX + dx];
+        });
+      });
     }
     __syncthreads();
   }
@@ -699,7 +985,23 @@ static hipError_t head_dispatch(bool mixed, const Mesh &mesh, const HeadArgs &a,
   if (mesh.kind == kGrid && !g_flat_kernels) {
     uint32_t ntx, nty;
     const Grid &g = mesh.grid;
-    if (g.dim == 3) {
+    if (g.dim == 3 && (g.head_variant == 1 || g.head_variant == 2)) {
+      Grid gm = g;
+      gm.zc = g.head_zc;
+      const uint32_t ncx = (g.n0 + MX - 1) / MX, ncy = (g.n1 + MY - 1) / MY, ncz = (g.n2 + gm.zc - 1) / gm.zc;
+      const dim3 grid(ncx * ncy * ncz);
+      if (g.head_variant == 1) {
+        if (mixed)
+          hipLaunchKernelGGL((k_head_march<Model, true>), grid, dim3(kBlock), 0, st, a, gm, ncx, ncy);
+        else
+          hipLaunchKernelGGL((k_head_march<Model, false>), grid, dim3(kBlock), 0, st, a, gm, ncx, ncy);
+      } else {
+        if (mixed)
+          hipLaunchKernelGGL((k_head_march_lds<Model, true>), grid, dim3(kBlock), 0, st, a, gm, ncx, ncy);
+        else
+          hipLaunchKernelGGL((k_head_march_lds<Model, false>), grid, dim3(kBlock), 0, st, a, gm, ncx, ncy);
+      }
+    } else if (g.dim == 3) {
       const dim3 grid = tile_grid<3>(g, ntx, nty);
       if (mixed)
         hipLaunchKernelGGL((k_head_tiled<Model, true, 3>), grid, dim3(kBlock), 0, st, a, g, ntx, nty);

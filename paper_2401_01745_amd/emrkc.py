@@ -31,7 +31,6 @@ EMRKC_CHECK_FINITE = 1
 EMRKC_EAGER = 2          # library-internal flag: no HIP-graph replay
 EMRKC_FUSE = 4           # library-internal flag: fused tail+head kernel
 EMRKC_FLAT = 8           # library-internal flag: flat (untiled) grid kernels
-EMRKC_MARCH = 16         # library-internal flag: z-marching inner kernel, 4 planes per block
 
 
 class Mesh(C.Structure):
@@ -71,6 +70,9 @@ EXPORTS = {
     "emrkc_stage_counts": (C.c_int, [C.c_double, C.c_double, C.c_double, C.c_double, C.POINTER(C.c_int),
                                      C.POINTER(C.c_int), C.POINTER(C.c_double)]),
     "emrkc_eval_elementary": (C.c_int, [C.c_int, C.c_int, C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p]),
+    "emrkc_autotune": (C.c_int, [C.c_void_p, C.POINTER(State), C.c_double, C.c_int, C.POINTER(C.c_int)]),
+    "emrkc_get_variants": (C.c_int, [C.c_void_p, C.POINTER(C.c_int)]),
+    "emrkc_set_variants": (C.c_int, [C.c_void_p, C.POINTER(C.c_int)]),
     "emrkc_create": (C.c_int, [C.POINTER(Mesh), C.POINTER(Conductivity), C.c_int, C.POINTER(Params),
                                C.POINTER(C.c_void_p)]),
     "emrkc_destroy": (None, [C.c_void_p]),
@@ -234,6 +236,25 @@ def emrkc_profile_step(ctx, state, dt, nsteps):
     cnt = (C.c_int64 * 3)()
     _check(lib().emrkc_profile_step(ctx, C.byref(state), dt, int(nsteps), ms, cnt), ctx)
     return {k: (ms[i], cnt[i]) for i, k in enumerate(PROFILE_CLASSES)}
+
+
+def emrkc_autotune(ctx, state, dt, reps=3):
+    """Times the kernel shapes and keeps the fastest; returns the chosen
+    (head, head planes, inner, inner planes)."""
+    v = (C.c_int * 4)()
+    _check(lib().emrkc_autotune(ctx, C.byref(state), dt, int(reps), v), ctx)
+    return tuple(v)
+
+
+def emrkc_get_variants(ctx):
+    v = (C.c_int * 4)()
+    _check(lib().emrkc_get_variants(ctx, v), ctx)
+    return tuple(v)
+
+
+def emrkc_set_variants(ctx, variants):
+    v = (C.c_int * 4)(*variants)
+    _check(lib().emrkc_set_variants(ctx, v), ctx)
 
 
 def emrkc_last_stats(ctx):

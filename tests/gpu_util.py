@@ -14,10 +14,12 @@ def oracle_rho(prob, y, t=0.0, safety=1.05, seed=0):
     return safety * rF, safety * rS, itF, itS
 
 
-def gpu_run(cfg, nsteps, rho, precision="fp64", flags=0, chunks=None, model_kw=None):
+def gpu_run(cfg, nsteps, rho, precision="fp64", flags=0, chunks=None, model_kw=None, variants=None):
     import torch
     from paper_2401_01745_amd import emrkc as E
     sim = E.simulation_from_config(cfg, precision=precision, rho=rho, flags=flags, **(model_kw or {}))
+    if variants is not None:
+        E.emrkc_set_variants(sim.ctx, variants)
     E.emrkc_init_state(sim.ctx, sim.state)
     for n in (chunks or [nsteps]):
         E.emrkc_step(sim.ctx, sim.state, cfg["dt"], n)

@@ -200,11 +200,42 @@ def test_graph_eager_fused_split_and_repeat_are_bitwise_identical(E, n, rho, pre
     V5, z5, st5 = gpu_run(cfg, 80, rho, precision=precision, flags=E.EMRKC_FUSE)
     V6, z6, _ = gpu_run(cfg, 80, rho, precision=precision, flags=E.EMRKC_FLAT)
     V7, z7, _ = gpu_run(cfg, 80, rho, precision=precision, flags=E.EMRKC_FLAT | E.EMRKC_EAGER)
-    V8, z8, _ = gpu_run(cfg, 80, rho, precision=precision, flags=E.EMRKC_MARCH)
+    runs = [(V2, z2), (V3, z3), (V4, z4), (V5, z5), (V6, z6), (V7, z7)]
+    if len(n) == 3:
+        # z-marching head (register and LDS-staged) and inner kernels with
+        # ragged columns and plane counts that do not divide n[2]
+        for v in [(1, 4, 1, 4), (2, 4, 1, 4), (2, 2, 1, 3), (1, n[2], 1, n[2]), (2, 5, 0, 0), (0, 0, 1, 2)]:
+            runs.append(gpu_run(cfg, 80, rho, precision=precision, variants=v)[:2])
     assert st1.used_graph == 1 and st2.used_graph == 0
     assert st1.kernels_per_step == st1.m and st5.kernels_per_step == st5.m - 1
-    for V, z in [(V2, z2), (V3, z3), (V4, z4), (V5, z5), (V6, z6), (V7, z7), (V8, z8)]:
+    for V, z in runs:
         assert np.array_equal(V, V1) and np.array_equal(z, z1)
+
+
+def test_autotune_keeps_state_and_results(E):
+    """The autotuner leaves the state untouched, picks valid shapes, and the
+    run with its choice equals the default run bit for bit."""
+    import torch
+    cfg = small_config("c2_3d_crn", (41, 19, 33))
+    rho = (51.0, 4.4)
+    V1, z1, _ = gpu_run(cfg, 30, rho)
+    sim = E.simulation_from_config(cfg, rho=rho)
+    E.emrkc_init_state(sim.ctx, sim.state)
+    V0, z0 = sim.V.clone(), sim.z.clone()
+    v = E.emrkc_autotune(sim.ctx, sim.state, cfg["dt"], reps=2)
+    assert torch.equal(sim.V, V0) and torch.equal(sim.z, z0)
+    assert v == E.emrkc_get_variants(sim.ctx)
+    assert v[0] in (0, 1, 2) and v[2] in (0, 1)
+    assert (v[0] == 0) == (v[1] == 0) and (v[2] == 0) == (v[3] == 0)
+    E.emrkc_step(sim.ctx, sim.state, cfg["dt"], 30)
+    torch.cuda.synchronize()
+    assert np.array_equal(sim.V.cpu().numpy(), V1)
+    assert np.array_equal(sim.z.cpu().numpy().astype(np.float64), z1)
+    with pytest.raises(E.EmrkcError):
+        E.emrkc_set_variants(sim.ctx, (3, 4, 0, 0))
+    with pytest.raises(E.EmrkcError):
+        E.emrkc_set_variants(sim.ctx, (1, 34, 0, 0))
+    sim.close()
 
 
 @pytest.mark.parametrize("model,n", [("HH", (65, 65)), ("CRN_SURR", (37, 29, 11)), ("TTP_SURR", (21, 17, 9))])
