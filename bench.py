@@ -79,7 +79,7 @@ class Job:
             return tuple(variants)
         E.emrkc_init_state(s.ctx, s.state)
         E.emrkc_estimate_rho(s.ctx, s.state)
-        return E.emrkc_autotune(s.ctx, s.state, self.cfg["dt"], reps=3)
+        return E.emrkc_autotune(s.ctx, s.state, self.cfg["dt"], reps=10)
 
     def run(self):
         E, s = self.E, self.sim
@@ -139,9 +139,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
-    ap.add_argument("--fuse", action="store_true", help="fused last-inner-stage + head kernel")
     ap.add_argument("--variants", default=None,
-                    help="kernel shapes 'head,head_planes,inner,inner_planes' instead of autotuning")
+                    help="kernel shapes 'head,head_planes,inner,inner_planes,fused' instead of autotuning")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="copy a buffer of this size once (calibrates rocprof FETCH/WRITE counters)")
     args = ap.parse_args()
@@ -181,7 +180,7 @@ def main():
         del src, dst
     with torch.cuda.stream(stream):
         log("bench: %s, N=%d, building FP64 context" % (cfg["name"], N))
-        flags = E.EMRKC_FUSE if args.fuse else 0
+        flags = 0
         job = Job(cfg, "fp64", stream, flags, tet, batch)
         forced = tuple(int(x) for x in args.variants.split(",")) if args.variants else None
         variants = job.tune(forced)
@@ -193,11 +192,13 @@ def main():
             (1e3 * elapsed / args.steps, job.nsim, value, s, m))
         V64 = job.sim.V.cpu().numpy().copy()
 
-        # per-kernel durations with HIP events (eager launches, same kernels)
+        # per-launch kernel durations: HIP events around every kernel on the
+        # job's stream, over kernel-steps further steps of the same
+        # simulation (eager launches of the kernels the timed graphs replay)
         prof = E.emrkc_profile_step(job.sim.ctx, job.sim.state, cfg["dt"], args.kernel_steps)
         nz = job.sim.nv - 1
         log("bench: kernel means (ms, launches): %s" % prof)
-        dom = "fused" if prof["fused"][1] > 0 else "head"
+        dom = "fused" if prof["fused"][1] > prof["head"][1] else "head"
         dom_ms = prof[dom][0]
         width = E.lib().emrkc_ell_width(job.sim.ctx) if tet is not None else 0
         mat = width * (4 + 8)
@@ -215,7 +216,8 @@ def main():
             if tr.get("kernel_source_hash") == kernel_hash():
                 traffic = tr.get("bytes_per_launch")
         head_kernel = ("k_head_batch" if batch is not None else "k_head" if tet is not None else
-                       {0: "k_head_tiled", 1: "k_head_march", 2: "k_head_march_lds"}[variants[0]])
+                       {0: "k_head_tiled", 1: "k_head_march", 2: "k_head_march_lds", 3: "k_head_tiled_occ<6 waves/SIMD>",
+                        4: "k_head_tiled_occ<8 waves/SIMD>"}[variants[0]])
         names = {"fused": "k_fused (last inner stage of step n-1 + exponential Euler, ionic model, outer z "
                           "recurrence and first inner stage of step n)",
                  "head": "%s (exponential Euler, ionic model, outer z recurrence, first inner stage)" % head_kernel}

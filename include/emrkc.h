@@ -257,29 +257,38 @@ int emrkc_batch_info(const emrkc_ctx *ctx, double dt, int64_t *offsets, int *m, 
 /* Sets every instance's radii (taken as given). */
 int emrkc_batch_set_rho(emrkc_ctx *ctx, const double *rho_F, const double *rho_S);
 
-/* ---- kernel shapes (3-D structured grids) --------------------------------
- * variants[4] = {head kernel, head planes per column, inner kernel, inner
- * planes per column}.  Head kernel: 0 = 3-D tiles of 16x4x4 nodes, 1 =
+/* ---- kernel shapes --------------------------------------------------------
+ * variants[5] = {head kernel, head planes per column, inner kernel, inner
+ * planes per column, fused}.
+ * On 3-D structured grids, head kernel: 0 = 3-D tiles of 16x4x4 nodes, 1 =
  * z-marching columns of 32x8 nodes with the ionic state of the next plane
  * prefetched into registers, 2 = z-marching columns with that state staged
- * through LDS by direct global-to-LDS loads.  Inner kernel: 0 = 3-D tiles,
- * 1 = z-marching columns.  Planes per column in [1, 64] and at most n[2]
- * (0 when the kernel is 0).  Every variant gives bit-identical results; only
- * speed differs.  Other meshes and batch contexts have one shape (all 0). */
+ * through LDS by direct global-to-LDS loads (grids with 8 N < 2^32 only),
+ * 3 and 4 = the 3-D tiles compiled for at least 6 and 8 resident waves per
+ * SIMD (fewer registers).
+ * Inner kernel: 0 = 3-D tiles, 1 = z-marching columns.  Planes per column
+ * in [1, 64] and at most n[2] for the column kernels, else 0.  Other meshes have
+ * one head and one inner shape (entries 0..3 are 0).
+ * fused = 1 (structured grids, single contexts): when s == 1 and m >= 2,
+ * the last inner stage of each step and the head of the next are one
+ * kernel on 3-D or 2-D tiles.
+ * Every variant gives bit-identical results; only speed differs. */
 
-/* Times every candidate shape for a few steps (`reps` timed steps each, on
- * a copy of `state`, which is not modified) and keeps the fastest head and
- * inner kernels.  Candidates: tiles, and columns of 4, 8, 16 or 32 planes
- * that leave at least 256 blocks.  Needs the radii.  Writes the choice to
- * `variants` when non-NULL.  Allocates a temporary copy of the state.
- * Synchronises the stream.  A no-op (returning the fixed shape) where
- * nothing can be tuned or with the fused tail+head kernel. */
+/* Times the candidate shapes for a few steps each (`reps` timed steps, on a
+ * copy of `state`, which is not modified) and keeps the fastest head and
+ * inner kernels, then the fused kernel if a step with it is faster.
+ * Candidates: tiles (three register budgets for the head), and columns of
+ * 2, 3, 4, 8, 16 or 32 planes that leave at least 256 blocks.  Needs the
+ * radii (the stage plan at dt decides whether the fused kernel applies).  Writes the choice to `variants`
+ * (int[5]) when non-NULL.  Allocates a temporary copy of the state;
+ * synchronises the stream.  Returns the fixed choice where nothing can be
+ * tuned. */
 int emrkc_autotune(emrkc_ctx *ctx, const emrkc_state *state, double dt, int reps, int *variants);
 
-int emrkc_get_variants(const emrkc_ctx *ctx, int *variants);
+int emrkc_get_variants(const emrkc_ctx *ctx, int *variants);   /* int[5] */
 
-/* Sets the shapes; EMRKC_EINVAL for values out of range, EMRKC_EUNSUPPORTED
- * for non-zero values where nothing can be tuned. */
+/* Sets the shapes (int[5]); EMRKC_EINVAL for values out of range,
+ * EMRKC_EUNSUPPORTED for a shape this context cannot use. */
 int emrkc_set_variants(emrkc_ctx *ctx, const int *variants);
 
 /* ---- evaluation of single terms (component checks) ---------------------- */

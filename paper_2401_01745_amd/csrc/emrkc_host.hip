@@ -960,46 +960,82 @@ extern "C" int emrkc_profile_step(emrkc_ctx *c, emrkc_state *st, double dt, int6
 }
 
 // ---------------------------------------------------------------------------
+// Timing on a private copy of a state
+// ---------------------------------------------------------------------------
+struct StateCopy {
+  void *V = nullptr, *Z = nullptr;
+  emrkc_state st{};
+  ~StateCopy() {
+    if (V) (void)hipFree(V);
+    if (Z) (void)hipFree(Z);
+  }
+};
+
+static int copy_state(emrkc_ctx *c, const emrkc_state *src, StateCopy &cp) {
+  const size_t vb = (size_t)c->N * sizeof(double);
+  const size_t zb = (size_t)(c->nv - 1) * (size_t)c->N * (c->mixed ? sizeof(float) : sizeof(double));
+  if (hipMalloc(&cp.V, vb) != hipSuccess || hipMalloc(&cp.Z, zb) != hipSuccess)
+    return fail(c, EMRKC_ENOMEM, "no memory for a copy of the state");
+  if (hipMemcpyAsync(cp.V, src->V, vb, hipMemcpyDeviceToDevice, c->stream) != hipSuccess ||
+      hipMemcpyAsync(cp.Z, src->z, zb, hipMemcpyDeviceToDevice, c->stream) != hipSuccess)
+    return fail(c, EMRKC_EHIP, "state copy failed");
+  cp.st = *src;
+  cp.st.V = cp.V;
+  cp.st.z = cp.Z;
+  return EMRKC_OK;
+}
+
+// ---------------------------------------------------------------------------
 // Kernel shapes of 3-D grids and their autotuning
 // ---------------------------------------------------------------------------
-static bool tunable(const emrkc_ctx *c) {
+// Kernel shapes: variants[5] = {head kernel, head planes per column, inner
+// kernel, inner planes per column, fused tail+head}.
+static bool tunable(const emrkc_ctx *c) {  // the 3-D shapes
   return !c->batch && c->mesh.kind == kGrid && c->dim == 3 && !c->flat;
+}
+static bool fusable(const emrkc_ctx *c) {  // the fused kernel (used when s == 1 and m >= 2)
+  return !c->batch && !c->flat && fused_supported(c->mesh);
 }
 
 static void get_variants(const emrkc_ctx *c, int *v) {
   const Grid &g = c->mesh.grid;
-  v[0] = g.head_variant;
-  v[1] = g.head_variant ? (int)g.head_zc : 0;
-  v[2] = g.inner_variant;
-  v[3] = g.inner_variant ? (int)g.zc : 0;
+  const bool t = tunable(c);
+  v[0] = t ? g.head_variant : 0;
+  v[1] = t && (g.head_variant == 1 || g.head_variant == 2) ? (int)g.head_zc : 0;
+  v[2] = t ? g.inner_variant : 0;
+  v[3] = t && g.inner_variant ? (int)g.zc : 0;
+  v[4] = c->use_fused ? 1 : 0;
 }
 
 static int check_variants(const emrkc_ctx *c, const int *v) {
+  if (v[4] < 0 || v[4] > 1 || (v[4] == 1 && !fusable(c))) return EMRKC_EUNSUPPORTED;
   if (!tunable(c)) return (v[0] | v[1] | v[2] | v[3]) == 0 ? EMRKC_OK : EMRKC_EUNSUPPORTED;
   const int n2 = (int)c->mesh.grid.n2;
-  if (v[0] < 0 || v[0] > 2 || v[2] < 0 || v[2] > 1) return EMRKC_EINVAL;
+  if (v[0] < 0 || v[0] > 4 || v[2] < 0 || v[2] > 1) return EMRKC_EINVAL;
   // the LDS-staged head addresses a component plane with 32-bit byte offsets
   if (v[0] == 2 && (uint64_t)c->N * sizeof(double) >= (1ull << 32)) return EMRKC_EUNSUPPORTED;
-  if (v[0] != 0 && (v[1] < 1 || v[1] > 64 || v[1] > n2)) return EMRKC_EINVAL;
+  const bool head_cols = v[0] == 1 || v[0] == 2;
+  if (head_cols && (v[1] < 1 || v[1] > 64 || v[1] > n2)) return EMRKC_EINVAL;
   if (v[2] != 0 && (v[3] < 1 || v[3] > 64 || v[3] > n2)) return EMRKC_EINVAL;
+  if (!head_cols && v[1] != 0) return EMRKC_EINVAL;
+  if (v[2] == 0 && v[3] != 0) return EMRKC_EINVAL;
   return EMRKC_OK;
 }
 
 static void set_variants(emrkc_ctx *c, const int *v) {
-  Grid &g = c->mesh.grid;
-  g.head_variant = v[0];
-  g.head_zc = v[0] ? (uint32_t)v[1] : 1u;
-  g.inner_variant = v[2];
-  g.zc = v[2] ? (uint32_t)v[3] : 1u;
+  if (tunable(c)) {
+    Grid &g = c->mesh.grid;
+    g.head_variant = v[0];
+    g.head_zc = (v[0] == 1 || v[0] == 2) ? (uint32_t)v[1] : 1u;
+    g.inner_variant = v[2];
+    g.zc = v[2] ? (uint32_t)v[3] : 1u;
+  }
+  c->use_fused = v[4] != 0;
   clear_graphs(c);
 }
 
 extern "C" int emrkc_get_variants(const emrkc_ctx *c, int *variants) {
   if (c == nullptr || variants == nullptr) return EMRKC_EINVAL;
-  if (!tunable(c)) {
-    for (int k = 0; k < 4; ++k) variants[k] = 0;
-    return EMRKC_OK;
-  }
   get_variants(c, variants);
   return EMRKC_OK;
 }
@@ -1007,13 +1043,14 @@ extern "C" int emrkc_get_variants(const emrkc_ctx *c, int *variants) {
 extern "C" int emrkc_set_variants(emrkc_ctx *c, const int *variants) {
   if (c == nullptr || variants == nullptr) return EMRKC_EINVAL;
   const int rc = check_variants(c, variants);
-  if (rc != EMRKC_OK) return fail(c, rc, "kernel variants (%d,%d,%d,%d) not valid for this context", variants[0],
-                                  variants[1], variants[2], variants[3]);
-  if (tunable(c)) set_variants(c, variants);
+  if (rc != EMRKC_OK)
+    return fail(c, rc, "kernel variants (%d,%d,%d,%d,%d) not valid for this context", variants[0], variants[1],
+                variants[2], variants[3], variants[4]);
+  set_variants(c, variants);
   return EMRKC_OK;
 }
 
-// Mean duration per launch of the head (cls 0) and inner (cls 1) kernels
+// Mean duration per launch of the head (0), inner (1) and fused (2) kernels
 // over `reps` steps on state `st` (advanced).
 static int time_classes(emrkc_ctx *c, emrkc_state *st, const StepPlan &P, double dt, int reps, double *ms) {
   HIP_TRY(c, launch_clock_set(c->d_clock, st->step, st->t0, c->stream));
@@ -1038,7 +1075,7 @@ static int time_classes(emrkc_ctx *c, emrkc_state *st, const StepPlan &P, double
   for (hipEvent_t ev : tm.ev) (void)hipEventDestroy(ev);
   if (e != hipSuccess) return fail(c, EMRKC_EHIP, "autotuning steps failed: %s", hipGetErrorString(e));
   if (rc != EMRKC_OK) return rc;
-  for (int k = 0; k < 2; ++k) ms[k] = cnt[k] ? sum[k] / cnt[k] : 0.0;
+  for (int k = 0; k < 3; ++k) ms[k] = cnt[k] ? sum[k] / cnt[k] : 0.0;
   return EMRKC_OK;
 }
 
@@ -1047,67 +1084,86 @@ extern "C" int emrkc_autotune(emrkc_ctx *c, const emrkc_state *st, double dt, in
   if (!state_ok(c, st)) return fail(c, EMRKC_EINVAL, "state buffers missing");
   if (!(dt > 0) || !isfinite(dt) || reps < 1 || reps > 1000) return fail(c, EMRKC_EINVAL, "invalid dt or reps");
   if (!c->have_rho) return fail(c, EMRKC_EINVAL, "spectral radii not set");
-  if (!tunable(c) || c->use_fused) return emrkc_get_variants(c, variants);
   StepPlan P;
   int rc = make_plan(c, dt, P);
   if (rc != EMRKC_OK) return rc;
-  const Grid &g = c->mesh.grid;
-  // candidates: 3-D tiles, and z-marching columns of zc planes for every
-  // zc in {4, 8, 16, 32} that leaves at least one block per compute unit
-  const uint32_t cols = ((g.n0 + MX - 1) / MX) * ((g.n1 + MY - 1) / MY);
-  std::vector<int> zcs;
-  for (int zc : {4, 8, 16, 32})
-    if (zc <= (int)g.n2 && cols * ((g.n2 + zc - 1) / zc) >= 256) zcs.push_back(zc);
+  const bool fuse_ok = fusable(c) && P.s == 1 && P.m >= 2;
+  if (!tunable(c) && !fuse_ok) return emrkc_get_variants(c, variants);
+  // shape candidates (3-D grids): 3-D tiles, and z-marching columns of zc
+  // planes for every zc in {2, 3, 4, 8, 16, 32} that leaves at least one
+  // block per compute unit
   std::vector<std::pair<int, int>> heads{{0, 0}}, inners{{0, 0}};
-  const bool lds_ok = (uint64_t)c->N * sizeof(double) < (1ull << 32);
-  for (int zc : zcs) {
-    heads.push_back({1, zc});
-    if (lds_ok) heads.push_back({2, zc});
-    inners.push_back({1, zc});
+  if (tunable(c)) {
+    heads.push_back({3, 0});  // tiles, 6 and 8 waves per SIMD
+    heads.push_back({4, 0});
+    const Grid &g = c->mesh.grid;
+    const uint32_t cols = ((g.n0 + MX - 1) / MX) * ((g.n1 + MY - 1) / MY);
+    const bool lds_ok = (uint64_t)c->N * sizeof(double) < (1ull << 32);
+    for (int zc : {2, 3, 4, 8, 16, 32}) {
+      if (zc > (int)g.n2 || cols * ((g.n2 + zc - 1) / zc) < 256) continue;
+      heads.push_back({1, zc});
+      if (lds_ok) heads.push_back({2, zc});
+      inners.push_back({1, zc});
+    }
   }
-  int orig[4];
+  int orig[5];
   get_variants(c, orig);
   // timing runs on a copy of the state
-  const size_t zb = (size_t)(c->nv - 1) * (size_t)c->N * (c->mixed ? sizeof(float) : sizeof(double));
-  void *V = nullptr, *Z = nullptr;
-  if (hipMalloc(&V, (size_t)c->N * sizeof(double)) != hipSuccess || hipMalloc(&Z, zb) != hipSuccess) {
-    if (V) (void)hipFree(V);
-    return fail(c, EMRKC_ENOMEM, "autotuning: no memory for a state copy");
-  }
-  emrkc_state tmp = *st;
-  tmp.V = V;
-  tmp.z = Z;
+  StateCopy cp;
+  if ((rc = copy_state(c, st, cp)) != EMRKC_OK) return rc;
+  const bool verbose = getenv("EMRKC_VERBOSE") != nullptr;
   double best_h = 1e300, best_i = 1e300;
-  int choice[4] = {orig[0], orig[1], orig[2], orig[3]};
+  int choice[5] = {orig[0], orig[1], orig[2], orig[3], 0};
   const size_t ncand = std::max(heads.size(), inners.size());
-  rc = EMRKC_OK;
-  if (hipMemcpyAsync(V, st->V, (size_t)c->N * sizeof(double), hipMemcpyDeviceToDevice, c->stream) != hipSuccess ||
-      hipMemcpyAsync(Z, st->z, zb, hipMemcpyDeviceToDevice, c->stream) != hipSuccess)
-    rc = fail(c, EMRKC_EHIP, "autotuning: state copy failed");
-  for (size_t k = 0; k < ncand && rc == EMRKC_OK; ++k) {
+  for (size_t k = 0; k < ncand && rc == EMRKC_OK && tunable(c); ++k) {
     const auto hv = heads[k % heads.size()], iv = inners[k % inners.size()];
-    const int v[4] = {hv.first, hv.second, iv.first, iv.second};
+    const int v[5] = {hv.first, hv.second, iv.first, iv.second, 0};
     set_variants(c, v);
-    double ms[2];
-    rc = time_classes(c, &tmp, P, dt, reps, ms);
+    double ms[3];
+    rc = time_classes(c, &cp.st, P, dt, reps, ms);
     if (rc != EMRKC_OK) break;
-    if (getenv("EMRKC_VERBOSE"))
+    if (verbose)
       fprintf(stderr, "emrkc_autotune: head %d/%d %.5f ms, inner %d/%d %.5f ms\n", v[0], v[1], ms[0], v[2], v[3],
               ms[1]);
-    if (ms[0] > 0 && ms[0] < best_h) {
+    // a later candidate must be faster by 2% to replace the current choice
+    // (the first candidates are the defaults), so that timing noise does
+    // not pick among equals
+    if (ms[0] > 0 && ms[0] < 0.98 * best_h) {
       best_h = ms[0];
       choice[0] = v[0];
       choice[1] = v[1];
     }
-    if (ms[1] > 0 && ms[1] < best_i) {
+    if (ms[1] > 0 && ms[1] < 0.98 * best_i) {
       best_i = ms[1];
       choice[2] = v[2];
       choice[3] = v[3];
     }
   }
+  // fused tail+head (s == 1, m >= 2): one kernel per step in place of the
+  // head and the last inner stage; compared by the time per step
+  if (rc == EMRKC_OK && fuse_ok) {
+    double ms[3];
+    choice[4] = 0;
+    set_variants(c, choice);
+    if (!tunable(c)) {
+      rc = time_classes(c, &cp.st, P, dt, reps, ms);
+      best_h = ms[0];
+      best_i = ms[1];
+    }
+    if (rc == EMRKC_OK) {
+      const int vf[5] = {choice[0], choice[1], choice[2], choice[3], 1};
+      set_variants(c, vf);
+      rc = time_classes(c, &cp.st, P, dt, reps, ms);
+      if (rc == EMRKC_OK) {
+        const double plain = best_h + (P.m - 1) * best_i, fused = ms[2] + (P.m - 2) * ms[1];
+        if (verbose)
+          fprintf(stderr, "emrkc_autotune: step %.5f ms separate, %.5f ms fused (fused kernel %.5f ms)\n", plain,
+                  fused, ms[2]);
+        choice[4] = fused < 0.98 * plain ? 1 : 0;
+      }
+    }
+  }
   (void)hipStreamSynchronize(c->stream);
-  (void)hipFree(V);
-  (void)hipFree(Z);
   set_variants(c, rc == EMRKC_OK ? choice : orig);
   if (rc == EMRKC_OK && variants) get_variants(c, variants);
   return rc;

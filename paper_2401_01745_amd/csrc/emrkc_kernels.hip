@@ -354,6 +354,22 @@ __global__ __launch_bounds__(kBlock) void k_head_tiled(HeadArgs a, Grid g, uint3
   head_node<Model, MIXED>(a, g.N, i, sV[c], [&]() { return lds_stencil<DIM, MIXED>(sV, g, c); });
 }
 
+// The tiled head compiled for at least WPE resident waves per SIMD (fewer
+// registers, possibly spilled): one round of blocks on small grids.
+template <template <class> class Model, bool MIXED, int DIM, int WPE>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(WPE))) void k_head_tiled_occ(
+    HeadArgs a, Grid g, uint32_t ntx, uint32_t nty) {
+  __shared__ double sV[Tile<DIM>::NS];
+  int x0, y0, z0;
+  tile_origin<DIM>(ntx, nty, x0, y0, z0);
+  stage_halo<DIM>(sV, a.Vin, g, x0, y0, z0);
+  __syncthreads();
+  uint32_t i;
+  int c;
+  if (!tile_node<DIM>(g, x0, y0, z0, i, c)) return;
+  head_node<Model, MIXED>(a, g.N, i, sV[c], [&]() { return lds_stencil<DIM, MIXED>(sV, g, c); });
+}
+
 template <bool MIXED, int DIM>
 __global__ __launch_bounds__(kBlock) void k_inner_tiled(InnerArgs a, Grid g, uint32_t ntx, uint32_t nty) {
   __shared__ double sU[Tile<DIM>::NS];
@@ -1000,6 +1016,19 @@ static hipError_t head_dispatch(bool mixed, const Mesh &mesh, const HeadArgs &a,
           hipLaunchKernelGGL((k_head_march_lds<Model, true>), grid, dim3(kBlock), 0, st, a, gm, ncx, ncy);
         else
           hipLaunchKernelGGL((k_head_march_lds<Model, false>), grid, dim3(kBlock), 0, st, a, gm, ncx, ncy);
+      }
+    } else if (g.dim == 3 && (g.head_variant == 3 || g.head_variant == 4)) {
+      const dim3 grid = tile_grid<3>(g, ntx, nty);
+      if (g.head_variant == 3) {
+        if (mixed)
+          hipLaunchKernelGGL((k_head_tiled_occ<Model, true, 3, 6>), grid, dim3(kBlock), 0, st, a, g, ntx, nty);
+        else
+          hipLaunchKernelGGL((k_head_tiled_occ<Model, false, 3, 6>), grid, dim3(kBlock), 0, st, a, g, ntx, nty);
+      } else {
+        if (mixed)
+          hipLaunchKernelGGL((k_head_tiled_occ<Model, true, 3, 8>), grid, dim3(kBlock), 0, st, a, g, ntx, nty);
+        else
+          hipLaunchKernelGGL((k_head_tiled_occ<Model, false, 3, 8>), grid, dim3(kBlock), 0, st, a, g, ntx, nty);
       }
     } else if (g.dim == 3) {
       const dim3 grid = tile_grid<3>(g, ntx, nty);

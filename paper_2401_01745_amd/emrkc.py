@@ -240,20 +240,22 @@ def emrkc_profile_step(ctx, state, dt, nsteps):
 
 def emrkc_autotune(ctx, state, dt, reps=3):
     """Times the kernel shapes and keeps the fastest; returns the chosen
-    (head, head planes, inner, inner planes)."""
-    v = (C.c_int * 4)()
+    (head, head planes, inner, inner planes, fused)."""
+    v = (C.c_int * 5)()
     _check(lib().emrkc_autotune(ctx, C.byref(state), dt, int(reps), v), ctx)
     return tuple(v)
 
 
 def emrkc_get_variants(ctx):
-    v = (C.c_int * 4)()
+    v = (C.c_int * 5)()
     _check(lib().emrkc_get_variants(ctx, v), ctx)
     return tuple(v)
 
 
 def emrkc_set_variants(ctx, variants):
-    v = (C.c_int * 4)(*variants)
+    if len(variants) != 5:
+        raise ValueError("variants has 5 entries")
+    v = (C.c_int * 5)(*variants)
     _check(lib().emrkc_set_variants(ctx, v), ctx)
 
 

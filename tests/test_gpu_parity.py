@@ -204,7 +204,8 @@ def test_graph_eager_fused_split_and_repeat_are_bitwise_identical(E, n, rho, pre
     if len(n) == 3:
         # z-marching head (register and LDS-staged) and inner kernels with
         # ragged columns and plane counts that do not divide n[2]
-        for v in [(1, 4, 1, 4), (2, 4, 1, 4), (2, 2, 1, 3), (1, n[2], 1, n[2]), (2, 5, 0, 0), (0, 0, 1, 2)]:
+        for v in [(1, 4, 1, 4, 0), (2, 4, 1, 4, 0), (2, 2, 1, 3, 0), (1, n[2], 1, n[2], 0), (2, 5, 0, 0, 0),
+                  (0, 0, 1, 2, 0), (2, 3, 1, 4, 1), (3, 0, 1, 4, 0), (4, 0, 0, 0, 1)]:
             runs.append(gpu_run(cfg, 80, rho, precision=precision, variants=v)[:2])
     assert st1.used_graph == 1 and st2.used_graph == 0
     assert st1.kernels_per_step == st1.m and st5.kernels_per_step == st5.m - 1
@@ -225,16 +226,18 @@ def test_autotune_keeps_state_and_results(E):
     v = E.emrkc_autotune(sim.ctx, sim.state, cfg["dt"], reps=2)
     assert torch.equal(sim.V, V0) and torch.equal(sim.z, z0)
     assert v == E.emrkc_get_variants(sim.ctx)
-    assert v[0] in (0, 1, 2) and v[2] in (0, 1)
+    assert len(v) == 5 and v[0] in (0, 1, 2) and v[2] in (0, 1) and v[4] in (0, 1)
     assert (v[0] == 0) == (v[1] == 0) and (v[2] == 0) == (v[3] == 0)
     E.emrkc_step(sim.ctx, sim.state, cfg["dt"], 30)
     torch.cuda.synchronize()
     assert np.array_equal(sim.V.cpu().numpy(), V1)
     assert np.array_equal(sim.z.cpu().numpy().astype(np.float64), z1)
     with pytest.raises(E.EmrkcError):
-        E.emrkc_set_variants(sim.ctx, (3, 4, 0, 0))
+        E.emrkc_set_variants(sim.ctx, (3, 4, 0, 0, 0))
     with pytest.raises(E.EmrkcError):
-        E.emrkc_set_variants(sim.ctx, (1, 34, 0, 0))
+        E.emrkc_set_variants(sim.ctx, (1, 34, 0, 0, 0))
+    with pytest.raises(E.EmrkcError):
+        E.emrkc_set_variants(sim.ctx, (0, 0, 0, 0, 2))
     sim.close()
 
 
@@ -293,3 +296,4 @@ def test_c2_full_size_prefix_fp64(E):
     prob = build_grid_problem(cfg)
     rF, rS, _, _ = oracle_rho(prob, prob.uniform_state())
     _compare_full(cfg, 10, (rF, rS))
+
