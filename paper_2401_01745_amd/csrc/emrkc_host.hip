@@ -597,14 +597,19 @@ struct KernelTimer {
   std::vector<hipEvent_t> ev;  // pairs (start, stop)
   std::vector<int> cls;        // 0 = head, 1 = inner, 2 = fused
   size_t used = 0;
-  int record(emrkc_ctx *c, hipStream_t s, int k, bool start);
+  int arm(emrkc_ctx *c, int k);
 };
 
+// With a timer, the kernel launch itself records the pair of events (its
+// dispatch timestamps), so the interval holds the kernel's execution only.
 #define TIMED(cls, call)                                                  \
   do {                                                                    \
-    if (tm && tm->record(c, strm, (cls), true)) return EMRKC_EHIP;        \
-    HIP_TRY(c, call);                                                     \
-    if (tm && tm->record(c, strm, (cls), false)) return EMRKC_EHIP;       \
+    if (tm && tm->arm(c, (cls))) return EMRKC_EHIP;                       \
+    const hipError_t timed_e_ = (call);                                   \
+    if (tm) set_launch_events(nullptr, nullptr);                          \
+    if (timed_e_ != hipSuccess)                                           \
+      return fail(c, EMRKC_EHIP, "%s failed: %s", #call,                  \
+                  hipGetErrorString(timed_e_));                           \
   } while (0)
 
 static HeadArgs make_head(emrkc_ctx *c, const StepPlan &P, double dt, int j, int step_off) {
@@ -905,17 +910,15 @@ extern "C" int emrkc_step(emrkc_ctx *c, emrkc_state *st, double dt, int64_t nste
   return EMRKC_OK;
 }
 
-int KernelTimer::record(emrkc_ctx *c, hipStream_t s, int k, bool start) {
-  if (start) {
-    while (ev.size() < used + 2) {
-      hipEvent_t e;
-      if (hipEventCreate(&e) != hipSuccess) return fail(c, EMRKC_EHIP, "hipEventCreate failed");
-      ev.push_back(e);
-    }
-    cls.push_back(k);
+int KernelTimer::arm(emrkc_ctx *c, int k) {
+  while (ev.size() < used + 2) {
+    hipEvent_t e;
+    if (hipEventCreate(&e) != hipSuccess) return fail(c, EMRKC_EHIP, "hipEventCreate failed");
+    ev.push_back(e);
   }
-  if (hipEventRecord(ev[used], s) != hipSuccess) return fail(c, EMRKC_EHIP, "hipEventRecord failed");
-  ++used;
+  cls.push_back(k);
+  set_launch_events(ev[used], ev[used + 1]);
+  used += 2;
   return EMRKC_OK;
 }
 
@@ -1125,15 +1128,15 @@ extern "C" int emrkc_autotune(emrkc_ctx *c, const emrkc_state *st, double dt, in
     if (verbose)
       fprintf(stderr, "emrkc_autotune: head %d/%d %.5f ms, inner %d/%d %.5f ms\n", v[0], v[1], ms[0], v[2], v[3],
               ms[1]);
-    // a later candidate must be faster by 2% to replace the current choice
-    // (the first candidates are the defaults), so that timing noise does
-    // not pick among equals
-    if (ms[0] > 0 && ms[0] < 0.98 * best_h) {
+    // a later candidate must be faster by 5% to replace the current choice
+    // (the first candidates are the plain tiles), so that timing noise does
+    // not pick among near-equals
+    if (ms[0] > 0 && ms[0] < 0.95 * best_h) {
       best_h = ms[0];
       choice[0] = v[0];
       choice[1] = v[1];
     }
-    if (ms[1] > 0 && ms[1] < 0.98 * best_i) {
+    if (ms[1] > 0 && ms[1] < 0.95 * best_i) {
       best_i = ms[1];
       choice[2] = v[2];
       choice[3] = v[3];
@@ -1159,7 +1162,7 @@ extern "C" int emrkc_autotune(emrkc_ctx *c, const emrkc_state *st, double dt, in
         if (verbose)
           fprintf(stderr, "emrkc_autotune: step %.5f ms separate, %.5f ms fused (fused kernel %.5f ms)\n", plain,
                   fused, ms[2]);
-        choice[4] = fused < 0.98 * plain ? 1 : 0;
+        choice[4] = fused < 0.95 * plain ? 1 : 0;
       }
     }
   }

@@ -109,6 +109,9 @@ struct BatchInst {
 constexpr int MX = 32, MY = 8;
 
 // ---- launchers (emrkc_kernels.hip) ----------------------------------------
+// Events recorded by the next kernel launches of this thread around the
+// kernel's execution (profiling); nullptr to stop.
+void set_launch_events(hipEvent_t start, hipEvent_t stop);
 // Tiles of a grid in the LDS-tiled layout (3-D 16x4x4, 2-D 64x4).
 uint32_t grid_tiles(const Grid &g, uint32_t &ntx, uint32_t &nty);
 hipError_t launch_head_batch(int model, bool mixed, const BatchInst *tab, const uint16_t *map, uint32_t nblocks,

@@ -1,11 +1,29 @@
 // Kernels of the emRKC library (gfx950).  One thread per mesh node, state
 // in structure-of-arrays layout; no floating-point atomics, reductions are
 // two-pass with a fixed order (bit-reproducible).
+#include <hip/hip_ext.h>
 #include <type_traits>
 
 #include "emrkc_internal.h"
 
 namespace emrkc {
+
+// Events that the next launches record around the kernel itself (from the
+// dispatch's own timestamps); set by the host's profiling pass, null
+// otherwise.
+static thread_local hipEvent_t g_ev_start = nullptr, g_ev_stop = nullptr;
+void set_launch_events(hipEvent_t start, hipEvent_t stop) {
+  g_ev_start = start;
+  g_ev_stop = stop;
+}
+
+#define EMRKC_LAUNCH(kern, grid, block, shm, st, ...)                                               \
+  do {                                                                                              \
+    if (g_ev_start != nullptr)                                                                      \
+      hipExtLaunchKernelGGL(kern, grid, block, shm, st, g_ev_start, g_ev_stop, 0u, __VA_ARGS__);    \
+    else                                                                                            \
+      hipLaunchKernelGGL(kern, grid, block, shm, st, __VA_ARGS__);                                  \
+  } while (0)
 
 constexpr int kBlock = 256;
 
@@ -1008,56 +1026,56 @@ static hipError_t head_dispatch(bool mixed, const Mesh &mesh, const HeadArgs &a,
       const dim3 grid(ncx * ncy * ncz);
       if (g.head_variant == 1) {
         if (mixed)
-          hipLaunchKernelGGL((k_head_march<Model, true>), grid, dim3(kBlock), 0, st, a, gm, ncx, ncy);
+          EMRKC_LAUNCH((k_head_march<Model, true>), grid, dim3(kBlock), 0, st, a, gm, ncx, ncy);
         else
-          hipLaunchKernelGGL((k_head_march<Model, false>), grid, dim3(kBlock), 0, st, a, gm, ncx, ncy);
+          EMRKC_LAUNCH((k_head_march<Model, false>), grid, dim3(kBlock), 0, st, a, gm, ncx, ncy);
       } else {
         if (mixed)
-          hipLaunchKernelGGL((k_head_march_lds<Model, true>), grid, dim3(kBlock), 0, st, a, gm, ncx, ncy);
+          EMRKC_LAUNCH((k_head_march_lds<Model, true>), grid, dim3(kBlock), 0, st, a, gm, ncx, ncy);
         else
-          hipLaunchKernelGGL((k_head_march_lds<Model, false>), grid, dim3(kBlock), 0, st, a, gm, ncx, ncy);
+          EMRKC_LAUNCH((k_head_march_lds<Model, false>), grid, dim3(kBlock), 0, st, a, gm, ncx, ncy);
       }
     } else if (g.dim == 3 && (g.head_variant == 3 || g.head_variant == 4)) {
       const dim3 grid = tile_grid<3>(g, ntx, nty);
       if (g.head_variant == 3) {
         if (mixed)
-          hipLaunchKernelGGL((k_head_tiled_occ<Model, true, 3, 6>), grid, dim3(kBlock), 0, st, a, g, ntx, nty);
+          EMRKC_LAUNCH((k_head_tiled_occ<Model, true, 3, 6>), grid, dim3(kBlock), 0, st, a, g, ntx, nty);
         else
-          hipLaunchKernelGGL((k_head_tiled_occ<Model, false, 3, 6>), grid, dim3(kBlock), 0, st, a, g, ntx, nty);
+          EMRKC_LAUNCH((k_head_tiled_occ<Model, false, 3, 6>), grid, dim3(kBlock), 0, st, a, g, ntx, nty);
       } else {
         if (mixed)
-          hipLaunchKernelGGL((k_head_tiled_occ<Model, true, 3, 8>), grid, dim3(kBlock), 0, st, a, g, ntx, nty);
+          EMRKC_LAUNCH((k_head_tiled_occ<Model, true, 3, 8>), grid, dim3(kBlock), 0, st, a, g, ntx, nty);
         else
-          hipLaunchKernelGGL((k_head_tiled_occ<Model, false, 3, 8>), grid, dim3(kBlock), 0, st, a, g, ntx, nty);
+          EMRKC_LAUNCH((k_head_tiled_occ<Model, false, 3, 8>), grid, dim3(kBlock), 0, st, a, g, ntx, nty);
       }
     } else if (g.dim == 3) {
       const dim3 grid = tile_grid<3>(g, ntx, nty);
       if (mixed)
-        hipLaunchKernelGGL((k_head_tiled<Model, true, 3>), grid, dim3(kBlock), 0, st, a, g, ntx, nty);
+        EMRKC_LAUNCH((k_head_tiled<Model, true, 3>), grid, dim3(kBlock), 0, st, a, g, ntx, nty);
       else
-        hipLaunchKernelGGL((k_head_tiled<Model, false, 3>), grid, dim3(kBlock), 0, st, a, g, ntx, nty);
+        EMRKC_LAUNCH((k_head_tiled<Model, false, 3>), grid, dim3(kBlock), 0, st, a, g, ntx, nty);
     } else {
       const dim3 grid = tile_grid<2>(g, ntx, nty);
       if (mixed)
-        hipLaunchKernelGGL((k_head_tiled<Model, true, 2>), grid, dim3(kBlock), 0, st, a, g, ntx, nty);
+        EMRKC_LAUNCH((k_head_tiled<Model, true, 2>), grid, dim3(kBlock), 0, st, a, g, ntx, nty);
       else
-        hipLaunchKernelGGL((k_head_tiled<Model, false, 2>), grid, dim3(kBlock), 0, st, a, g, ntx, nty);
+        EMRKC_LAUNCH((k_head_tiled<Model, false, 2>), grid, dim3(kBlock), 0, st, a, g, ntx, nty);
     }
     return hipGetLastError();
   }
   if (mixed)
-    hipLaunchKernelGGL((k_head<Model, true>), dim3(blocks_for(N)), dim3(kBlock), 0, st, a, mesh);
+    EMRKC_LAUNCH((k_head<Model, true>), dim3(blocks_for(N)), dim3(kBlock), 0, st, a, mesh);
   else
-    hipLaunchKernelGGL((k_head<Model, false>), dim3(blocks_for(N)), dim3(kBlock), 0, st, a, mesh);
+    EMRKC_LAUNCH((k_head<Model, false>), dim3(blocks_for(N)), dim3(kBlock), 0, st, a, mesh);
   return hipGetLastError();
 }
 
 template <template <class> class Model>
 static hipError_t init_dispatch(bool mixed, uint32_t N, double *V, void *z, ModelParams mp, hipStream_t st) {
   if (mixed)
-    hipLaunchKernelGGL((k_init_state<Model, true>), dim3(blocks_for(N)), dim3(kBlock), 0, st, N, V, z, mp);
+    EMRKC_LAUNCH((k_init_state<Model, true>), dim3(blocks_for(N)), dim3(kBlock), 0, st, N, V, z, mp);
   else
-    hipLaunchKernelGGL((k_init_state<Model, false>), dim3(blocks_for(N)), dim3(kBlock), 0, st, N, V, z, mp);
+    EMRKC_LAUNCH((k_init_state<Model, false>), dim3(blocks_for(N)), dim3(kBlock), 0, st, N, V, z, mp);
   return hipGetLastError();
 }
 
@@ -1065,10 +1083,10 @@ template <template <class> class Model>
 static hipError_t rhs_dispatch(bool mixed, uint32_t N, const double *V, const void *z, double t, StimArgs stim,
                                double Cm, ModelParams mp, double *out, hipStream_t st) {
   if (mixed)
-    hipLaunchKernelGGL((k_eval_rhs_slow<Model, true>), dim3(blocks_for(N)), dim3(kBlock), 0, st, N, V, z, t,
+    EMRKC_LAUNCH((k_eval_rhs_slow<Model, true>), dim3(blocks_for(N)), dim3(kBlock), 0, st, N, V, z, t,
                        stim, Cm, mp, out);
   else
-    hipLaunchKernelGGL((k_eval_rhs_slow<Model, false>), dim3(blocks_for(N)), dim3(kBlock), 0, st, N, V, z, t,
+    EMRKC_LAUNCH((k_eval_rhs_slow<Model, false>), dim3(blocks_for(N)), dim3(kBlock), 0, st, N, V, z, t,
                        stim, Cm, mp, out);
   return hipGetLastError();
 }
@@ -1078,10 +1096,10 @@ static hipError_t powS_dispatch(bool mixed, uint32_t N, size_t stride, const dou
                                 const double *vin, uint64_t seed, double q, double t, StimArgs stim, double Cm,
                                 ModelParams mp, double *vout, double *partials, hipStream_t st) {
   if (mixed)
-    hipLaunchKernelGGL((k_powS_iter<Model, true>), dim3(blocks_for(N)), dim3(kBlock), 0, st, N, stride, V, z, vin,
+    EMRKC_LAUNCH((k_powS_iter<Model, true>), dim3(blocks_for(N)), dim3(kBlock), 0, st, N, stride, V, z, vin,
                        seed, q, t, stim, Cm, mp, vout, partials);
   else
-    hipLaunchKernelGGL((k_powS_iter<Model, false>), dim3(blocks_for(N)), dim3(kBlock), 0, st, N, stride, V, z, vin,
+    EMRKC_LAUNCH((k_powS_iter<Model, false>), dim3(blocks_for(N)), dim3(kBlock), 0, st, N, stride, V, z, vin,
                        seed, q, t, stim, Cm, mp, vout, partials);
   return hipGetLastError();
 }
@@ -1115,30 +1133,30 @@ hipError_t launch_inner(bool mixed, const Mesh &mesh, const InnerArgs &a, hipStr
     if (g.dim == 3 && g.inner_variant == 1) {
       const uint32_t ncx = (g.n0 + MX - 1) / MX, ncy = (g.n1 + MY - 1) / MY, ncz = (g.n2 + g.zc - 1) / g.zc;
       if (mixed)
-        hipLaunchKernelGGL((k_inner_march<true>), dim3(ncx * ncy * ncz), dim3(kBlock), 0, st, a, g, ncx, ncy);
+        EMRKC_LAUNCH((k_inner_march<true>), dim3(ncx * ncy * ncz), dim3(kBlock), 0, st, a, g, ncx, ncy);
       else
-        hipLaunchKernelGGL((k_inner_march<false>), dim3(ncx * ncy * ncz), dim3(kBlock), 0, st, a, g, ncx, ncy);
+        EMRKC_LAUNCH((k_inner_march<false>), dim3(ncx * ncy * ncz), dim3(kBlock), 0, st, a, g, ncx, ncy);
       return hipGetLastError();
     }
     if (g.dim == 3) {
       const dim3 grid = tile_grid<3>(g, ntx, nty);
       if (mixed)
-        hipLaunchKernelGGL((k_inner_tiled<true, 3>), grid, dim3(kBlock), 0, st, a, g, ntx, nty);
+        EMRKC_LAUNCH((k_inner_tiled<true, 3>), grid, dim3(kBlock), 0, st, a, g, ntx, nty);
       else
-        hipLaunchKernelGGL((k_inner_tiled<false, 3>), grid, dim3(kBlock), 0, st, a, g, ntx, nty);
+        EMRKC_LAUNCH((k_inner_tiled<false, 3>), grid, dim3(kBlock), 0, st, a, g, ntx, nty);
     } else {
       const dim3 grid = tile_grid<2>(g, ntx, nty);
       if (mixed)
-        hipLaunchKernelGGL((k_inner_tiled<true, 2>), grid, dim3(kBlock), 0, st, a, g, ntx, nty);
+        EMRKC_LAUNCH((k_inner_tiled<true, 2>), grid, dim3(kBlock), 0, st, a, g, ntx, nty);
       else
-        hipLaunchKernelGGL((k_inner_tiled<false, 2>), grid, dim3(kBlock), 0, st, a, g, ntx, nty);
+        EMRKC_LAUNCH((k_inner_tiled<false, 2>), grid, dim3(kBlock), 0, st, a, g, ntx, nty);
     }
     return hipGetLastError();
   }
   if (mixed)
-    hipLaunchKernelGGL((k_inner<true>), dim3(blocks_for(N)), dim3(kBlock), 0, st, a, mesh);
+    EMRKC_LAUNCH((k_inner<true>), dim3(blocks_for(N)), dim3(kBlock), 0, st, a, mesh);
   else
-    hipLaunchKernelGGL((k_inner<false>), dim3(blocks_for(N)), dim3(kBlock), 0, st, a, mesh);
+    EMRKC_LAUNCH((k_inner<false>), dim3(blocks_for(N)), dim3(kBlock), 0, st, a, mesh);
   return hipGetLastError();
 }
 
@@ -1152,9 +1170,9 @@ template <template <class> class Model>
 static hipError_t head_batch_dispatch(bool mixed, const BatchInst *tab, const uint16_t *map, uint32_t nb,
                                       uint32_t Ntot, int step_off, hipStream_t st) {
   if (mixed)
-    hipLaunchKernelGGL((k_head_batch<Model, true>), dim3(nb), dim3(kBlock), 0, st, tab, map, Ntot, step_off);
+    EMRKC_LAUNCH((k_head_batch<Model, true>), dim3(nb), dim3(kBlock), 0, st, tab, map, Ntot, step_off);
   else
-    hipLaunchKernelGGL((k_head_batch<Model, false>), dim3(nb), dim3(kBlock), 0, st, tab, map, Ntot, step_off);
+    EMRKC_LAUNCH((k_head_batch<Model, false>), dim3(nb), dim3(kBlock), 0, st, tab, map, Ntot, step_off);
   return hipGetLastError();
 }
 
@@ -1169,9 +1187,9 @@ hipError_t launch_inner_batch(bool mixed, const BatchInst *tab, const uint16_t *
                               uint32_t Ntot, hipStream_t st) {
   (void)Ntot;
   if (mixed)
-    hipLaunchKernelGGL((k_inner_batch<true>), dim3(nblocks), dim3(kBlock), 0, st, tab, map);
+    EMRKC_LAUNCH((k_inner_batch<true>), dim3(nblocks), dim3(kBlock), 0, st, tab, map);
   else
-    hipLaunchKernelGGL((k_inner_batch<false>), dim3(nblocks), dim3(kBlock), 0, st, tab, map);
+    EMRKC_LAUNCH((k_inner_batch<false>), dim3(nblocks), dim3(kBlock), 0, st, tab, map);
   return hipGetLastError();
 }
 
@@ -1183,17 +1201,17 @@ static hipError_t fused_dispatch(bool mixed, const Grid &g, const FusedArgs &a, 
                    ntz = (g.n2 + T::TZ - 1) / T::TZ;
     const dim3 grid(ntx * nty * ntz);
     if (mixed)
-      hipLaunchKernelGGL((k_fused<Model, true, 3>), grid, dim3(kBlock), 0, st, a, g, ntx, nty);
+      EMRKC_LAUNCH((k_fused<Model, true, 3>), grid, dim3(kBlock), 0, st, a, g, ntx, nty);
     else
-      hipLaunchKernelGGL((k_fused<Model, false, 3>), grid, dim3(kBlock), 0, st, a, g, ntx, nty);
+      EMRKC_LAUNCH((k_fused<Model, false, 3>), grid, dim3(kBlock), 0, st, a, g, ntx, nty);
   } else {
     using T = Tile<2>;
     const uint32_t ntx = (g.n0 + T::TX - 1) / T::TX, nty = (g.n1 + T::TY - 1) / T::TY;
     const dim3 grid(ntx * nty);
     if (mixed)
-      hipLaunchKernelGGL((k_fused<Model, true, 2>), grid, dim3(kBlock), 0, st, a, g, ntx, nty);
+      EMRKC_LAUNCH((k_fused<Model, true, 2>), grid, dim3(kBlock), 0, st, a, g, ntx, nty);
     else
-      hipLaunchKernelGGL((k_fused<Model, false, 2>), grid, dim3(kBlock), 0, st, a, g, ntx, nty);
+      EMRKC_LAUNCH((k_fused<Model, false, 2>), grid, dim3(kBlock), 0, st, a, g, ntx, nty);
   }
   return hipGetLastError();
 }
@@ -1206,23 +1224,23 @@ hipError_t launch_fused(int model, bool mixed, const Mesh &mesh, const FusedArgs
 }
 
 hipError_t launch_clock_set(Clock *c, int64_t step, double t0, hipStream_t st) {
-  hipLaunchKernelGGL(k_clock_set, dim3(1), dim3(64), 0, st, c, step, t0);
+  EMRKC_LAUNCH(k_clock_set, dim3(1), dim3(64), 0, st, c, step, t0);
   return hipGetLastError();
 }
 
 hipError_t launch_copy_tick(const double *src, double *dst, uint32_t N, Clock *tick, int64_t tick_by,
                             hipStream_t st) {
   const uint32_t nb = src != nullptr ? blocks_for(N) : 1;
-  hipLaunchKernelGGL(k_copy_tick, dim3(nb), dim3(kBlock), 0, st, src, dst, N, tick, tick_by);
+  EMRKC_LAUNCH(k_copy_tick, dim3(nb), dim3(kBlock), 0, st, src, dst, N, tick, tick_by);
   return hipGetLastError();
 }
 
 hipError_t launch_apply_diffusion(bool mixed, const Mesh &mesh, const double *V, double *out, hipStream_t st) {
   const uint32_t N = mesh.kind == kGrid ? mesh.grid.N : mesh.ell.N;
   if (mixed)
-    hipLaunchKernelGGL((k_apply_diffusion<true>), dim3(blocks_for(N)), dim3(kBlock), 0, st, mesh, V, out);
+    EMRKC_LAUNCH((k_apply_diffusion<true>), dim3(blocks_for(N)), dim3(kBlock), 0, st, mesh, V, out);
   else
-    hipLaunchKernelGGL((k_apply_diffusion<false>), dim3(blocks_for(N)), dim3(kBlock), 0, st, mesh, V, out);
+    EMRKC_LAUNCH((k_apply_diffusion<false>), dim3(blocks_for(N)), dim3(kBlock), 0, st, mesh, V, out);
   return hipGetLastError();
 }
 
@@ -1234,7 +1252,7 @@ hipError_t launch_eval_rhs_slow(int model, bool mixed, uint32_t N, const double 
 }
 
 static hipError_t finish_reduce(uint32_t nparts, double *partials, double *result, hipStream_t st) {
-  hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(kBlock), 0, st, partials, nparts, result);
+  EMRKC_LAUNCH(k_reduce_final, dim3(1), dim3(kBlock), 0, st, partials, nparts, result);
   return hipGetLastError();
 }
 
@@ -1242,9 +1260,9 @@ hipError_t launch_norm2_state(bool mixed, uint32_t N, size_t stride, int nz, con
                               double *partials, double *result, hipStream_t st) {
   const uint32_t nb = blocks_for(N);
   if (mixed)
-    hipLaunchKernelGGL((k_norm2_state<true>), dim3(nb), dim3(kBlock), 0, st, N, nz, V, z, stride, partials);
+    EMRKC_LAUNCH((k_norm2_state<true>), dim3(nb), dim3(kBlock), 0, st, N, nz, V, z, stride, partials);
   else
-    hipLaunchKernelGGL((k_norm2_state<false>), dim3(nb), dim3(kBlock), 0, st, N, nz, V, z, stride, partials);
+    EMRKC_LAUNCH((k_norm2_state<false>), dim3(nb), dim3(kBlock), 0, st, N, nz, V, z, stride, partials);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   return finish_reduce(nb, partials, result, st);
@@ -1253,7 +1271,7 @@ hipError_t launch_norm2_state(bool mixed, uint32_t N, size_t stride, int nz, con
 hipError_t launch_norm2_random(uint64_t seed, uint64_t count, double *partials, double *result, hipStream_t st) {
   // grid sized like the state reductions: count / nz items per block is fine
   const uint32_t nb = blocks_for(count) > 65536u ? 65536u : blocks_for(count);
-  hipLaunchKernelGGL(k_norm2_random, dim3(nb), dim3(kBlock), 0, st, seed, count, partials);
+  EMRKC_LAUNCH(k_norm2_random, dim3(nb), dim3(kBlock), 0, st, seed, count, partials);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   return finish_reduce(nb, partials, result, st);
@@ -1261,7 +1279,7 @@ hipError_t launch_norm2_random(uint64_t seed, uint64_t count, double *partials, 
 
 hipError_t launch_powF_shift(uint32_t N, const double *yV, const double *vin, uint64_t seed, double q, double *zV,
                              hipStream_t st) {
-  hipLaunchKernelGGL(k_powF_shift, dim3(blocks_for(N)), dim3(kBlock), 0, st, N, yV, vin, seed, q, zV);
+  EMRKC_LAUNCH(k_powF_shift, dim3(blocks_for(N)), dim3(kBlock), 0, st, N, yV, vin, seed, q, zV);
   return hipGetLastError();
 }
 
@@ -1269,7 +1287,7 @@ hipError_t launch_powF_diff(bool mixed, const Mesh &mesh, const double *zV, cons
                             double *partials, double *result, hipStream_t st) {
   const uint32_t N = mesh.kind == kGrid ? mesh.grid.N : mesh.ell.N;
   const uint32_t nb = blocks_for(N);
-  hipLaunchKernelGGL((k_powF_diff<false>), dim3(nb), dim3(kBlock), 0, st, mesh, zV, yV, vout, partials);
+  EMRKC_LAUNCH((k_powF_diff<false>), dim3(nb), dim3(kBlock), 0, st, mesh, zV, yV, vout, partials);
   (void)mixed;
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
@@ -1295,14 +1313,14 @@ hipError_t launch_powS_iter(int model, bool mixed, uint32_t N, size_t stride, co
 
 hipError_t launch_elementary(int fn, bool mixed, const double *x, double *y, uint32_t n, hipStream_t st) {
   if (mixed)
-    hipLaunchKernelGGL(k_elementary<MathF32>, dim3(blocks_for(n)), dim3(kBlock), 0, st, fn, x, y, n);
+    EMRKC_LAUNCH(k_elementary<MathF32>, dim3(blocks_for(n)), dim3(kBlock), 0, st, fn, x, y, n);
   else
-    hipLaunchKernelGGL(k_elementary<MathF64>, dim3(blocks_for(n)), dim3(kBlock), 0, st, fn, x, y, n);
+    EMRKC_LAUNCH(k_elementary<MathF64>, dim3(blocks_for(n)), dim3(kBlock), 0, st, fn, x, y, n);
   return hipGetLastError();
 }
 
 hipError_t launch_finite_check(uint32_t N, const double *V, int *flag, hipStream_t st) {
-  hipLaunchKernelGGL(k_finite_check, dim3(blocks_for(N)), dim3(kBlock), 0, st, N, V, flag);
+  EMRKC_LAUNCH(k_finite_check, dim3(blocks_for(N)), dim3(kBlock), 0, st, N, V, flag);
   return hipGetLastError();
 }
 
