@@ -277,7 +277,7 @@ int emrkc_batch_set_rho(emrkc_ctx *ctx, const double *rho_F, const double *rho_S
 /* Times the candidate shapes for a few steps each (`reps` timed steps, on a
  * copy of `state`, which is not modified) and keeps the fastest head and
  * inner kernels, then the fused kernel if a step with it is faster.  A
- * candidate replaces an earlier one only when at least 5% faster.
+ * candidate replaces an earlier one only when at least 3% faster.
  * Candidates: tiles (three register budgets for the head), and columns of
  * 2, 3, 4, 8, 16 or 32 planes that leave at least 256 blocks.  Needs the
  * radii (the stage plan at dt decides whether the fused kernel applies).  Writes the choice to `variants`

@@ -1128,15 +1128,15 @@ extern "C" int emrkc_autotune(emrkc_ctx *c, const emrkc_state *st, double dt, in
     if (verbose)
       fprintf(stderr, "emrkc_autotune: head %d/%d %.5f ms, inner %d/%d %.5f ms\n", v[0], v[1], ms[0], v[2], v[3],
               ms[1]);
-    // a later candidate must be faster by 5% to replace the current choice
+    // a later candidate must be faster by 3% to replace the current choice
     // (the first candidates are the plain tiles), so that timing noise does
     // not pick among near-equals
-    if (ms[0] > 0 && ms[0] < 0.95 * best_h) {
+    if (ms[0] > 0 && ms[0] < 0.97 * best_h) {
       best_h = ms[0];
       choice[0] = v[0];
       choice[1] = v[1];
     }
-    if (ms[1] > 0 && ms[1] < 0.95 * best_i) {
+    if (ms[1] > 0 && ms[1] < 0.97 * best_i) {
       best_i = ms[1];
       choice[2] = v[2];
       choice[3] = v[3];
@@ -1162,7 +1162,7 @@ extern "C" int emrkc_autotune(emrkc_ctx *c, const emrkc_state *st, double dt, in
         if (verbose)
           fprintf(stderr, "emrkc_autotune: step %.5f ms separate, %.5f ms fused (fused kernel %.5f ms)\n", plain,
                   fused, ms[2]);
-        choice[4] = fused < 0.95 * plain ? 1 : 0;
+        choice[4] = fused < 0.97 * plain ? 1 : 0;
       }
     }
   }
