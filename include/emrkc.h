@@ -68,6 +68,16 @@ extern "C" {
                                    radii in double                           */
 
 #define EMRKC_CHECK_FINITE 1u   /* emrkc_step synchronises and checks V      */
+/* Stepping variants (flags):
+ * EMRKC_PROGRESSIVE — the progressive splitting of the auxiliary problem
+ *   (remark after eq. auxp_exp): the inner problem starts from y and carries
+ *   the exponential increment as a constant forcing; on the monodomain split
+ *   the gates then end at z + c'_m (z_E - z) instead of z_E.
+ * EMRKC_COND_A — (s, m, eta) from stability condition A of the stability
+ *   lemma: eta = (6 dt / l_s) m^2/(m^2 - 1) with the smallest m >= 2 such
+ *   that eta rho_F <= beta m^2 (single contexts only). */
+#define EMRKC_PROGRESSIVE 0x100u
+#define EMRKC_COND_A 0x200u
 
 /* ---- types -------------------------------------------------------------- */
 typedef struct emrkc_ctx emrkc_ctx;
@@ -114,7 +124,10 @@ typedef struct {
   double powiter_tol;     /* power-iteration tolerance (1e-2)                */
   double powiter_eps;     /* relative perturbation size (1e-8)               */
   int32_t powiter_max_iter; /* iteration limit per radius (100)             */
-  int32_t reserved0;
+  int32_t rho_every;      /* > 0: emrkc_step re-estimates both radii, warm
+                             started, before every step whose index is a
+                             positive multiple of rho_every (0: never;
+                             single contexts only)                         */
   uint64_t powiter_seed;  /* splitmix64 state of the start vector (0)        */
   double linear_a;        /* EMRKC_MODEL_LINEAR: i_ion = a V                 */
   double linear_lambda_E; /* EMRKC_MODEL_LINEAR: constant gate rate (< 0)    */
@@ -157,6 +170,10 @@ int emrkc_model_num_gates(int ionic_model);
  * not define are 0).  Each array must hold s + 1 doubles.  s in [1, 10000],
  * eps > 0. */
 int emrkc_rkc_coeffs(int s, double eps, double *mu, double *nu, double *kappa, double *c);
+
+/* Stage counts under stability condition A (see EMRKC_COND_A); s as in
+ * emrkc_stage_counts, m >= 2. */
+int emrkc_stage_counts_a(double dt, double rho_F, double rho_S, double eps, int *s, int *m, double *eta);
 
 /* Stage counts of the emRKC algorithm for given radii (get_stages twice):
  * s = max(1, ceil(sqrt(dt rho_S / beta))), eta = 2 dt / (beta s^2),

@@ -100,6 +100,10 @@ struct emrkc_ctx {
   void *d_SV2 = nullptr;
   bool use_fused = false;
   bool flat = false;
+  bool progressive = false;   // EMRKC_PROGRESSIVE
+  bool cond_a = false;        // EMRKC_COND_A
+  int rho_every = 0;          // params.rho_every
+  int64_t last_est_step = -1; // state step of the last re-estimate by emrkc_step
   void *d_z1 = nullptr;
   Clock *d_clock = nullptr;
   double *d_partials = nullptr;
@@ -234,6 +238,30 @@ static int get_stages(double dt, double rho, double eps, double *ls) {
   return (int)s;
 }
 
+extern "C" int emrkc_stage_counts_a(double dt, double rho_F, double rho_S, double eps, int *s, int *m,
+                                    double *eta) {
+  if (!(dt > 0) || !(rho_F >= 0) || !(rho_S >= 0) || !(eps > 0) || !isfinite(dt) || !isfinite(rho_F) ||
+      !isfinite(rho_S))
+    return EMRKC_EINVAL;
+  double ls;
+  const int ss = get_stages(dt, rho_S, eps, &ls);
+  const double beta = 2.0 - 4.0 * eps / 3.0;
+  // eta(m) decreases and beta m^2 grows with m: search upwards from 2
+  int mm = 2;
+  double e = 0;
+  for (;; ++mm) {
+    if (mm > 10000) return EMRKC_EUNSUPPORTED;
+    const double m2 = (double)mm * (double)mm;
+    e = (6.0 * dt / ls) * (m2 / (m2 - 1.0));
+    if (e * rho_F <= beta * m2) break;
+  }
+  if (ss > 10000) return EMRKC_EUNSUPPORTED;
+  if (s) *s = ss;
+  if (m) *m = mm;
+  if (eta) *eta = e;
+  return EMRKC_OK;
+}
+
 extern "C" int emrkc_stage_counts(double dt, double rho_F, double rho_S, double eps, int *s, int *m, double *eta) {
   if (!(dt > 0) || !(rho_F >= 0) || !(rho_S >= 0) || !(eps > 0) || !isfinite(dt) || !isfinite(rho_F) ||
       !isfinite(rho_S))
@@ -360,6 +388,7 @@ extern "C" int emrkc_create(const emrkc_mesh *mesh, const emrkc_conductivity *co
   if (!(p->eps > 0) || !(p->eps < 1) || !(p->rho_safety >= 1.0)) return EMRKC_EINVAL;
   if (p->precision != EMRKC_FP64 && p->precision != EMRKC_MIXED32) return EMRKC_EINVAL;
   if (!(p->powiter_tol > 0) || !(p->powiter_eps > 0) || p->powiter_max_iter < 1) return EMRKC_EINVAL;
+  if (p->rho_every < 0) return EMRKC_EINVAL;
   if (!isfinite(p->stim_amp) || !isfinite(p->stim_t_on) || !isfinite(p->stim_t_off)) return EMRKC_EINVAL;
   if (!isfinite(p->rho_F) || !isfinite(p->rho_S)) return EMRKC_EINVAL;
   if (ionic_model == EMRKC_MODEL_LINEAR && (!isfinite(p->linear_a) || !isfinite(p->linear_lambda_E) ||
@@ -402,6 +431,9 @@ extern "C" int emrkc_create(const emrkc_mesh *mesh, const emrkc_conductivity *co
   c->flags = p->flags;
   c->use_fused = getenv("EMRKC_FUSE") != nullptr || (p->flags & EMRKC_FUSE_FLAG) != 0;
   c->flat = (p->flags & EMRKC_FLAT_FLAG) != 0;
+  c->progressive = (p->flags & EMRKC_PROGRESSIVE) != 0;
+  c->cond_a = (p->flags & EMRKC_COND_A) != 0;
+  c->rho_every = p->rho_every;
   c->chi = p->chi;
   c->Cm = p->Cm;
   c->eps = p->eps;
@@ -574,7 +606,8 @@ extern "C" int emrkc_get_rho(const emrkc_ctx *c, double *rho_F, double *rho_S) {
 
 extern "C" int emrkc_stages(const emrkc_ctx *c, double dt, int *s, int *m, double *eta) {
   if (c == nullptr || !c->have_rho) return EMRKC_EINVAL;
-  return emrkc_stage_counts(dt, c->rho_F, c->rho_S, c->eps, s, m, eta);
+  return c->cond_a ? emrkc_stage_counts_a(dt, c->rho_F, c->rho_S, c->eps, s, m, eta)
+                   : emrkc_stage_counts(dt, c->rho_F, c->rho_S, c->eps, s, m, eta);
 }
 
 extern "C" int emrkc_last_stats(const emrkc_ctx *c, emrkc_stats *out) {
@@ -631,6 +664,8 @@ static HeadArgs make_head(emrkc_ctx *c, const StepPlan &P, double dt, int j, int
   h.cm_eta = P.cci[P.m] * P.eta;
   h.j1 = j == 1;
   h.m_is_one = P.m == 1;
+  h.progressive = c->progressive ? 1 : 0;
+  h.cm = P.cci[P.m];
   return h;
 }
 
@@ -811,8 +846,15 @@ static int build_batch_tables(emrkc_ctx *c, const emrkc_state *st, double dt, co
 
 // (s, m, eta) and the coefficient tables for dt; for a batch, s and eta are
 // common (from the largest rho_S) and m is the largest per-instance m.
+// (s, m, eta) of a single context under its stability condition (B unless
+// EMRKC_COND_A).
+static int select_stages(const emrkc_ctx *c, double dt, double rho_F, double rho_S, int *s, int *m, double *eta) {
+  return c->cond_a ? emrkc_stage_counts_a(dt, rho_F, rho_S, c->eps, s, m, eta)
+                   : emrkc_stage_counts(dt, rho_F, rho_S, c->eps, s, m, eta);
+}
+
 static int make_plan(emrkc_ctx *c, double dt, StepPlan &P) {
-  int rc = emrkc_stage_counts(dt, c->rho_F, c->rho_S, c->eps, &P.s, &P.m, &P.eta);
+  int rc = select_stages(c, dt, c->rho_F, c->rho_S, &P.s, &P.m, &P.eta);
   if (rc != EMRKC_OK) return fail(c, rc, "stage selection failed (dt=%g rho_F=%g rho_S=%g)", dt, c->rho_F, c->rho_S);
   if (c->batch) {
     if (P.s != 1) return fail(c, EMRKC_EUNSUPPORTED, "batched ensembles need s = 1 (dt=%g gives s=%d)", dt, P.s);
@@ -832,12 +874,37 @@ static int make_plan(emrkc_ctx *c, double dt, StepPlan &P) {
   return EMRKC_OK;
 }
 
+static int step_core(emrkc_ctx *c, emrkc_state *st, double dt, int64_t nsteps);
+
 extern "C" int emrkc_step(emrkc_ctx *c, emrkc_state *st, double dt, int64_t nsteps) {
   if (c == nullptr) return EMRKC_EINVAL;
   if (!state_ok(c, st)) return fail(c, EMRKC_EINVAL, "state buffers missing");
   if (!(dt > 0) || !isfinite(dt) || nsteps < 0) return fail(c, EMRKC_EINVAL, "invalid dt or nsteps");
   if (!c->have_rho) return fail(c, EMRKC_EINVAL, "spectral radii not set: call emrkc_estimate_rho or emrkc_set_rho");
   if (nsteps == 0) return EMRKC_OK;
+  if (c->rho_every <= 0) return step_core(c, st, dt, nsteps);
+  // re-estimate the radii (warm started) before every step whose index is a
+  // positive multiple of rho_every; runs of steps in between as usual.  A
+  // re-estimate that reaches the iteration limit keeps its best value.
+  const int64_t K = c->rho_every;
+  int64_t left = nsteps;
+  while (left > 0) {
+    if (st->step > 0 && st->step % K == 0 && c->last_est_step != st->step) {
+      st->t = state_time(st->t0, st->step, dt);
+      const int rc = emrkc_estimate_rho(c, st, nullptr, nullptr, nullptr, nullptr);
+      if (rc != EMRKC_OK && rc != EMRKC_ENOCONV) return rc;
+      c->last_est_step = st->step;
+    }
+    const int64_t next = (st->step / K + 1) * K;
+    const int64_t len = std::min(left, next - st->step);
+    const int rc = step_core(c, st, dt, len);
+    if (rc != EMRKC_OK) return rc;
+    left -= len;
+  }
+  return EMRKC_OK;
+}
+
+static int step_core(emrkc_ctx *c, emrkc_state *st, double dt, int64_t nsteps) {
   StepPlan P;
   int rc = make_plan(c, dt, P);
   if (rc != EMRKC_OK) return rc;
@@ -1470,6 +1537,8 @@ extern "C" int emrkc_create_batch(int n_inst, const emrkc_mesh *meshes, const em
   if (p0.precision != EMRKC_FP64 && p0.precision != EMRKC_MIXED32) return EMRKC_EINVAL;
   if (!(p0.eps > 0) || !(p0.eps < 1) || !(p0.rho_safety >= 1.0)) return EMRKC_EINVAL;
   if (!(p0.powiter_tol > 0) || !(p0.powiter_eps > 0) || p0.powiter_max_iter < 1) return EMRKC_EINVAL;
+  if (p0.rho_every != 0) return EMRKC_EUNSUPPORTED;        // ensembles keep the radii they are given
+  if (p0.flags & EMRKC_COND_A) return EMRKC_EUNSUPPORTED;  // one eta per outer stage for all instances
   int64_t Ntot = 0;
   for (int k = 0; k < n_inst; ++k) {
     const emrkc_mesh &m = meshes[k];
@@ -1501,6 +1570,7 @@ extern "C" int emrkc_create_batch(int n_inst, const emrkc_mesh *meshes, const em
   c->nv = 1 + c->ng + c->ns;
   c->mixed = p0.precision == EMRKC_MIXED32;
   c->flags = p0.flags;
+  c->progressive = (p0.flags & EMRKC_PROGRESSIVE) != 0;
   c->chi = p0.chi;
   c->Cm = p0.Cm;
   c->eps = p0.eps;
@@ -1707,6 +1777,8 @@ static int build_batch_tables(emrkc_ctx *c, const emrkc_state *st, double dt, co
           h.cm_eta = cc[I.m] * P.eta;
           h.j1 = 1;
           h.m_is_one = I.m == 1;
+          h.progressive = c->progressive ? 1 : 0;
+          h.cm = cc[I.m];
         } else {
           InnerArgs &a = b.in;
           a.t.nu = nu[k];

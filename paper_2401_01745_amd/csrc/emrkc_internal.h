@@ -61,6 +61,8 @@ struct HeadArgs {
   double cm_eta;        // c'_m * eta: inner end point of the frozen slow forcing
   int j1;               // stage j == 1
   int m_is_one;
+  int progressive;      // progressive splitting: gates end at z + c'_m (z_E - z)
+  double cm;            // c'_m
 };
 
 // Last inner stage k = m of stage j together with the outer V update.

@@ -171,6 +171,7 @@ __device__ __forceinline__ void head_node_z(const HeadArgs &a, uint32_t N, uint3
     double fbar;
     if (k < NG) {
       fbar = (double)(zE[k] - z[k]) * a.inv_eta;
+      if (a.progressive) fbar *= a.cm;
     } else {
       const double zs = (double)z[k];
       const double um = zs + a.cm_eta * (double)dS[k - NG];

@@ -28,6 +28,8 @@ EMRKC_FP64 = 0
 EMRKC_MIXED32 = 1
 PRECISIONS = {"fp64": EMRKC_FP64, "mixed": EMRKC_MIXED32}
 EMRKC_CHECK_FINITE = 1
+EMRKC_PROGRESSIVE = 0x100  # progressive splitting of the auxiliary problem
+EMRKC_COND_A = 0x200       # stage counts from stability condition A
 EMRKC_EAGER = 2          # library-internal flag: no HIP-graph replay
 EMRKC_FUSE = 4           # library-internal flag: fused tail+head kernel
 EMRKC_FLAT = 8           # library-internal flag: flat (untiled) grid kernels
@@ -48,7 +50,7 @@ class Params(C.Structure):
                 ("precision", C.c_int32), ("flags", C.c_uint32), ("stim_mask", C.c_void_p),
                 ("stim_amp", C.c_double), ("stim_t_on", C.c_double), ("stim_t_off", C.c_double),
                 ("rho_F", C.c_double), ("rho_S", C.c_double), ("powiter_tol", C.c_double),
-                ("powiter_eps", C.c_double), ("powiter_max_iter", C.c_int32), ("reserved0", C.c_int32),
+                ("powiter_eps", C.c_double), ("powiter_max_iter", C.c_int32), ("rho_every", C.c_int32),
                 ("powiter_seed", C.c_uint64), ("linear_a", C.c_double), ("linear_lambda_E", C.c_double)]
 
 
@@ -69,6 +71,8 @@ EXPORTS = {
     "emrkc_rkc_coeffs": (C.c_int, [C.c_int, C.c_double] + [C.POINTER(C.c_double)] * 4),
     "emrkc_stage_counts": (C.c_int, [C.c_double, C.c_double, C.c_double, C.c_double, C.POINTER(C.c_int),
                                      C.POINTER(C.c_int), C.POINTER(C.c_double)]),
+    "emrkc_stage_counts_a": (C.c_int, [C.c_double, C.c_double, C.c_double, C.c_double, C.POINTER(C.c_int),
+                                       C.POINTER(C.c_int), C.POINTER(C.c_double)]),
     "emrkc_eval_elementary": (C.c_int, [C.c_int, C.c_int, C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p]),
     "emrkc_autotune": (C.c_int, [C.c_void_p, C.POINTER(State), C.c_double, C.c_int, C.POINTER(C.c_int)]),
     "emrkc_get_variants": (C.c_int, [C.c_void_p, C.POINTER(C.c_int)]),
@@ -155,9 +159,10 @@ def emrkc_rkc_coeffs(s, eps=0.05):
     return [list(a) for a in arrs]
 
 
-def emrkc_stage_counts(dt, rho_F, rho_S, eps=0.05):
+def emrkc_stage_counts(dt, rho_F, rho_S, eps=0.05, cond="B"):
     s, m, eta = C.c_int(), C.c_int(), C.c_double()
-    _check(lib().emrkc_stage_counts(dt, rho_F, rho_S, eps, C.byref(s), C.byref(m), C.byref(eta)))
+    fn = lib().emrkc_stage_counts_a if cond == "A" else lib().emrkc_stage_counts
+    _check(fn(dt, rho_F, rho_S, eps, C.byref(s), C.byref(m), C.byref(eta)))
     return s.value, m.value, eta.value
 
 
@@ -364,10 +369,11 @@ class Simulation:
             pass
 
 
-def simulation_from_config(cfg, precision=None, rho=None, flags=0, stim_mask=None, **model_kw):
+def simulation_from_config(cfg, precision=None, rho=None, flags=0, stim_mask=None, rho_every=0, **model_kw):
     """Simulation for a structured-grid workload dictionary (see the
     workloads package).  ``rho`` = (rho_F, rho_S) fixes the spectral radii;
-    otherwise call ``estimate_rho``."""
+    otherwise call ``estimate_rho``.  ``rho_every`` > 0 re-estimates them
+    every that many steps."""
     import numpy as np
     from workloads.configs import stim_mask as make_mask
     prec = PRECISIONS[precision or cfg.get("precision", "fp64")]
@@ -388,6 +394,7 @@ def simulation_from_config(cfg, precision=None, rho=None, flags=0, stim_mask=Non
     p.stim_t_off = st["t_off"]
     if rho is not None:
         p.rho_F, p.rho_S = rho
+    p.rho_every = rho_every
     p.linear_a = model_kw.get("a", 0.0)
     p.linear_lambda_E = model_kw.get("lam_E", 0.0)
     return Simulation(mesh, cond, cfg["model"], p, keep=(mask,))

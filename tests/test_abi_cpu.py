@@ -82,6 +82,7 @@ def test_stage_counts_match_oracle():
         rF = 10 ** rng.uniform(-1, 5)
         rS = 10 ** rng.uniform(-2, 3)
         assert E.emrkc_stage_counts(dt, rF, rS) == stage_counts(dt, rF, rS)
+        assert E.emrkc_stage_counts(dt, rF, rS, cond="A") == stage_counts(dt, rF, rS, cond="A")
 
 
 def test_model_sizes():
@@ -120,6 +121,19 @@ def test_invalid_arguments_rejected_before_any_gpu_call():
     q = E.emrkc_default_params()
     q.powiter_max_iter = 0
     assert create(good, cond, 1, q) == E.EMRKC_EINVAL
+    q = E.emrkc_default_params()
+    q.rho_every = -1
+    assert create(good, cond, 1, q) == E.EMRKC_EINVAL
+    assert ctx.value is None
+    # ensembles: no condition-A stage counts, no periodic re-estimation
+    meshes = (E.Mesh * 1)(good)
+    conds = (E.Conductivity * 1)(cond)
+    for field, value, code in [("flags", E.EMRKC_COND_A, E.EMRKC_EUNSUPPORTED),
+                               ("rho_every", 5, E.EMRKC_EUNSUPPORTED)]:
+        q = E.emrkc_default_params()
+        setattr(q, field, value)
+        ps = (E.Params * 1)(q)
+        assert L.emrkc_create_batch(1, meshes, conds, 1, ps, C.byref(ctx)) == code
     assert ctx.value is None
     # calls on a null context
     assert L.emrkc_step(None, None, 0.1, 1) == E.EMRKC_EINVAL
@@ -130,4 +144,5 @@ def test_invalid_arguments_rejected_before_any_gpu_call():
     s = C.c_int()
     assert L.emrkc_stage_counts(-1.0, 1.0, 1.0, 0.05, C.byref(s), None, None) == E.EMRKC_EINVAL
     assert L.emrkc_stage_counts(0.1, float("nan"), 1.0, 0.05, C.byref(s), None, None) == E.EMRKC_EINVAL
+    assert L.emrkc_stage_counts_a(-1.0, 1.0, 1.0, 0.05, C.byref(s), None, None) == E.EMRKC_EINVAL
     assert L.emrkc_rkc_coeffs(0, 0.05, None, None, None, None) == E.EMRKC_EINVAL
