@@ -274,6 +274,18 @@ int emrkc_batch_info(const emrkc_ctx *ctx, double dt, int64_t *offsets, int *m, 
 /* Sets every instance's radii (taken as given). */
 int emrkc_batch_set_rho(emrkc_ctx *ctx, const double *rho_F, const double *rho_S);
 
+/* ---- reference stepping ----------------------------------------------------
+ * nsteps steps of EXEX-RL, the fine reference method of the error
+ * measurements (IMEX-RL algorithm of the numerical experiments with its
+ * diffusion solve replaced by an explicit update):
+ *   z_E^{n+1} = z_E^n + (e^{dt Lambda_E(V^n)} - 1)(z_E^n - z_inf(V^n)),
+ *   z_S^{n+1} = z_S^n + dt g_S(V^n, z_E^{n+1}, z_S^n),
+ *   V^{n+1} = V^n + dt [f_F(V^n) + Cm^{-1}(I_stim(t_n) - I_ion(V^n, z^{n+1}))],
+ * on the context's mesh, model and stimulus, t_n = t0 + n dt.  Needs no
+ * radii (stable only for dt below the explicit limit of the diffusion).
+ * Single contexts; same state layout and stream semantics as emrkc_step. */
+int emrkc_exexrl_step(emrkc_ctx *ctx, emrkc_state *state, double dt, int64_t nsteps);
+
 /* ---- kernel shapes --------------------------------------------------------
  * variants[5] = {head kernel, head planes per column, inner kernel, inner
  * planes per column, fused}.

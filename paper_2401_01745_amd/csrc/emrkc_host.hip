@@ -8,6 +8,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <functional>
 #include <map>
 #include <string>
 #include <tuple>
@@ -844,8 +845,6 @@ static int ensure_z1(emrkc_ctx *c) {
 
 static int build_batch_tables(emrkc_ctx *c, const emrkc_state *st, double dt, const StepPlan &P);
 
-// (s, m, eta) and the coefficient tables for dt; for a batch, s and eta are
-// common (from the largest rho_S) and m is the largest per-instance m.
 // (s, m, eta) of a single context under its stability condition (B unless
 // EMRKC_COND_A).
 static int select_stages(const emrkc_ctx *c, double dt, double rho_F, double rho_S, int *s, int *m, double *eta) {
@@ -853,6 +852,8 @@ static int select_stages(const emrkc_ctx *c, double dt, double rho_F, double rho
                    : emrkc_stage_counts(dt, rho_F, rho_S, c->eps, s, m, eta);
 }
 
+// (s, m, eta) and the coefficient tables for dt; for a batch, s and eta are
+// common (from the largest rho_S) and m is the largest per-instance m.
 static int make_plan(emrkc_ctx *c, double dt, StepPlan &P) {
   int rc = select_stages(c, dt, c->rho_F, c->rho_S, &P.s, &P.m, &P.eta);
   if (rc != EMRKC_OK) return fail(c, rc, "stage selection failed (dt=%g rho_F=%g rho_S=%g)", dt, c->rho_F, c->rho_S);
@@ -904,32 +905,30 @@ extern "C" int emrkc_step(emrkc_ctx *c, emrkc_state *st, double dt, int64_t nste
   return EMRKC_OK;
 }
 
-static int step_core(emrkc_ctx *c, emrkc_state *st, double dt, int64_t nsteps) {
-  StepPlan P;
-  int rc = make_plan(c, dt, P);
-  if (rc != EMRKC_OK) return rc;
-  if (c->batch && (rc = build_batch_tables(c, st, dt, P)) != EMRKC_OK) return rc;
-
+// Enqueues nsteps steps in chunks of up to 32 (enq(L, stream) enqueues L
+// steps); with graphs every chunk length is captured once per key and
+// replayed, the step time coming from the device clock.
+static int run_chunks(emrkc_ctx *c, const emrkc_state *st, double dt, int64_t nsteps, int key_s, int key_m,
+                      const std::function<int(int, hipStream_t)> &enq, bool *used_graph) {
+  int rc;
   HIP_TRY(c, launch_clock_set(c->d_clock, st->step, st->t0, c->stream));
   const bool eager = (c->flags & EMRKC_EAGER_FLAG) != 0 || getenv("EMRKC_EAGER") != nullptr;
-  // chunks of up to 32 steps; with graphs every chunk of one length is one
-  // captured graph replayed (the step time comes from the device clock)
   const int chunk = (int)std::min<int64_t>(nsteps, 32);
   const int64_t full = nsteps / chunk;
   const int rem = (int)(nsteps - full * chunk);
-  bool used_graph = false;
+  *used_graph = false;
   for (int pass = 0; pass < 2; ++pass) {
     const int len = pass == 0 ? chunk : rem;
     const int64_t reps = pass == 0 ? full : (rem > 0 ? 1 : 0);
     if (len <= 0 || reps <= 0) continue;
     if (eager) {
       for (int64_t r = 0; r < reps; ++r)
-        if ((rc = enqueue_chunk(c, st, P, dt, len, c->stream)) != EMRKC_OK) return rc;
+        if ((rc = enq(len, c->stream)) != EMRKC_OK) return rc;
       continue;
     }
     uint64_t dtb;
     memcpy(&dtb, &dt, sizeof dtb);
-    GraphKey key{P.s, P.m, len, dtb, st->V, st->z};
+    GraphKey key{key_s, key_m, len, dtb, st->V, st->z};
     hipGraphExec_t exec = nullptr;
     auto it = c->graphs.find(key);
     if (it != c->graphs.end()) {
@@ -937,7 +936,7 @@ static int step_core(emrkc_ctx *c, emrkc_state *st, double dt, int64_t nsteps) {
     } else {
       hipGraph_t graph = nullptr;
       HIP_TRY(c, hipStreamBeginCapture(c->capture, hipStreamCaptureModeThreadLocal));
-      const int erc = enqueue_chunk(c, st, P, dt, len, c->capture);
+      const int erc = enq(len, c->capture);
       hipError_t ee = hipStreamEndCapture(c->capture, &graph);
       if (erc != EMRKC_OK) {
         if (graph) (void)hipGraphDestroy(graph);
@@ -954,8 +953,32 @@ static int step_core(emrkc_ctx *c, emrkc_state *st, double dt, int64_t nsteps) {
       c->graphs[key] = exec;
     }
     for (int64_t r = 0; r < reps; ++r) HIP_TRY(c, hipGraphLaunch(exec, c->stream));
-    used_graph = true;
+    *used_graph = true;
   }
+  return EMRKC_OK;
+}
+
+// EMRKC_CHECK_FINITE: synchronises and reports a non-finite V.
+static int check_finite(emrkc_ctx *c, const emrkc_state *st) {
+  if (!(c->flags & EMRKC_CHECK_FINITE)) return EMRKC_OK;
+  HIP_TRY(c, hipMemsetAsync(c->d_flag, 0, sizeof(int), c->stream));
+  HIP_TRY(c, launch_finite_check((uint32_t)c->N, (const double *)st->V, c->d_flag, c->stream));
+  int flag = 0;
+  HIP_TRY(c, hipMemcpyAsync(&flag, c->d_flag, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  if (flag) return fail(c, EMRKC_ENONFINITE, "V holds a non-finite value after step %lld", (long long)st->step);
+  return EMRKC_OK;
+}
+
+static int step_core(emrkc_ctx *c, emrkc_state *st, double dt, int64_t nsteps) {
+  StepPlan P;
+  int rc = make_plan(c, dt, P);
+  if (rc != EMRKC_OK) return rc;
+  if (c->batch && (rc = build_batch_tables(c, st, dt, P)) != EMRKC_OK) return rc;
+  bool used_graph = false;
+  rc = run_chunks(c, st, dt, nsteps, P.s, P.m,
+                  [&](int L, hipStream_t strm) { return enqueue_chunk(c, st, P, dt, L, strm); }, &used_graph);
+  if (rc != EMRKC_OK) return rc;
   st->step += nsteps;
   st->t = state_time(st->t0, st->step, dt);
   c->last.s = P.s;
@@ -966,15 +989,49 @@ static int step_core(emrkc_ctx *c, emrkc_state *st, double dt, int64_t nsteps) {
                                  ? (int64_t)P.m - 1
                                  : (P.s == 1 && P.m == 1) ? 1 : (int64_t)P.s * P.m + (P.m == 1 ? 1 : 0);
   c->last.used_graph = used_graph ? 1 : 0;
-  if (c->flags & EMRKC_CHECK_FINITE) {
-    HIP_TRY(c, hipMemsetAsync(c->d_flag, 0, sizeof(int), c->stream));
-    HIP_TRY(c, launch_finite_check((uint32_t)c->N, (const double *)st->V, c->d_flag, c->stream));
-    int flag = 0;
-    HIP_TRY(c, hipMemcpyAsync(&flag, c->d_flag, sizeof(int), hipMemcpyDeviceToHost, c->stream));
-    HIP_TRY(c, hipStreamSynchronize(c->stream));
-    if (flag) return fail(c, EMRKC_ENONFINITE, "V holds a non-finite value after step %lld", (long long)st->step);
+  return check_finite(c, st);
+}
+
+// ---------------------------------------------------------------------------
+// EXEX-RL reference stepping
+// ---------------------------------------------------------------------------
+// L steps, one kernel each; V alternates the caller's buffer and d_V1 (the
+// kernel reads V^n with neighbours while writing V^{n+1}), z is updated in
+// place; the chunk ends with V in the caller's buffer and the clock ticked.
+static int enqueue_chunk_exexrl(emrkc_ctx *c, const emrkc_state *st, double dt, int L, hipStream_t strm) {
+  set_flat_kernels(c->flat);
+  double *X[2] = {(double *)st->V, c->d_V1};
+  for (int n = 0; n < L; ++n) {
+    ExArgs a{};
+    a.Vin = X[n % 2];
+    a.Vout = X[(n + 1) % 2];
+    a.z = st->z;
+    a.clock = c->d_clock;
+    a.step_off = n;
+    a.stim = stim_args(c);
+    a.mp = c->mp;
+    a.dt = dt;
+    a.Cm = c->Cm;
+    HIP_TRY(c, launch_exexrl(c->model, c->mixed, c->mesh, a, strm));
   }
+  HIP_TRY(c, launch_copy_tick(L % 2 ? X[1] : nullptr, X[0], (uint32_t)c->N, c->d_clock, L, strm));
   return EMRKC_OK;
+}
+
+extern "C" int emrkc_exexrl_step(emrkc_ctx *c, emrkc_state *st, double dt, int64_t nsteps) {
+  if (c == nullptr) return EMRKC_EINVAL;
+  if (!state_ok(c, st)) return fail(c, EMRKC_EINVAL, "state buffers missing");
+  if (!(dt > 0) || !isfinite(dt) || nsteps < 0) return fail(c, EMRKC_EINVAL, "invalid dt or nsteps");
+  if (c->batch) return fail(c, EMRKC_EUNSUPPORTED, "EXEX-RL stepping is for single contexts");
+  if (nsteps == 0) return EMRKC_OK;
+  bool used_graph = false;
+  const int rc = run_chunks(c, st, dt, nsteps, -1, 0,
+                            [&](int L, hipStream_t strm) { return enqueue_chunk_exexrl(c, st, dt, L, strm); },
+                            &used_graph);
+  if (rc != EMRKC_OK) return rc;
+  st->step += nsteps;
+  st->t = state_time(st->t0, st->step, dt);
+  return check_finite(c, st);
 }
 
 int KernelTimer::arm(emrkc_ctx *c, int k) {

@@ -94,6 +94,18 @@ struct FusedArgs {
   HeadArgs h;            // h.Vin unused: V comes from the tail
 };
 
+// One step of the EXEX-RL reference method at every node.
+struct ExArgs {
+  const double *Vin;    // V^n (read with neighbours)
+  double *Vout;         // V^{n+1}
+  void *z;              // z^n, overwritten with z^{n+1}
+  const Clock *clock;   // chunk base step and t0
+  int step_off;         // step index within the chunk
+  StimArgs stim;
+  ModelParams mp;
+  double dt, Cm;
+};
+
 // One instance of a batched (ensemble) launch.  Instances are concatenated:
 // node i of the instance is node off + i of every global array, component
 // planes are N_total apart.  Logical blocks tile0 .. tile0 + ntiles - 1 of
@@ -124,6 +136,7 @@ hipError_t launch_init_state(int model, bool mixed, uint32_t N, double *V, void 
                              hipStream_t st);
 hipError_t launch_head(int model, bool mixed, const Mesh &mesh, const HeadArgs &a, hipStream_t st);
 hipError_t launch_inner(bool mixed, const Mesh &mesh, const InnerArgs &a, hipStream_t st);
+hipError_t launch_exexrl(int model, bool mixed, const Mesh &mesh, const ExArgs &a, hipStream_t st);
 hipError_t launch_fused(int model, bool mixed, const Mesh &mesh, const FusedArgs &a, hipStream_t st);
 bool fused_supported(const Mesh &mesh);
 // Testing switch: use the flat (one node per thread, global-load stencil)

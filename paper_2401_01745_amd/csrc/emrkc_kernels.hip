@@ -210,6 +210,51 @@ __global__ __launch_bounds__(kBlock) void k_head(HeadArgs a, Mesh mesh) {
 }
 
 // ---------------------------------------------------------------------------
+// EXEX-RL reference step (the IMEX-RL algorithm of the numerical experiments
+// with its diffusion line taken explicitly): Rush-Larsen for the gates at
+// V^n, explicit Euler for the other ionic variables with the new gates,
+// explicit Euler for V with the ionic current at (V^n, z_E^{n+1}, z_S^{n+1}).
+// ---------------------------------------------------------------------------
+template <template <class> class Model, bool MIXED>
+__global__ __launch_bounds__(kBlock) void k_exexrl(ExArgs a, Mesh mesh) {
+  using M = MathOf<MIXED>;
+  using R = typename M::R;
+  using Mod = Model<M>;
+  constexpr int NG = Mod::NG, NS = Mod::NS, NZ = NG + NS;
+  const uint32_t N = mesh.kind == kGrid ? mesh.grid.N : mesh.ell.N;
+  const uint32_t i = node_index();
+  if (i >= N) return;
+  const double V = a.Vin[i];
+  const double tn = stage_time(a.clock, a.step_off, a.dt, 0.0);
+  const double Is = stimulus(a.stim, i, tn);
+  R *zp = (R *)a.z;
+  R z[NZ];
+#pragma unroll
+  for (int k = 0; k < NZ; ++k) z[k] = zp[(size_t)k * N + i];
+  R lam[NG], zinf[NG];
+  Mod::gates(R(V), a.mp, lam, zinf);
+  const R dt = R(a.dt);
+#pragma unroll
+  for (int g = 0; g < NG; ++g) z[g] = z[g] + M::expm1(dt * lam[g]) * (z[g] - zinf[g]);
+  R dS[NS > 0 ? NS : 1];
+  R iion = Mod::eval(R(V), z, z + NG, dS, a.mp);
+  if (NS > 0) {
+#pragma unroll
+    for (int k = 0; k < NS; ++k) z[NG + k] = z[NG + k] + dt * dS[k];
+    iion = Mod::eval(R(V), z, z + NG, dS, a.mp);
+  }
+#pragma unroll
+  for (int k = 0; k < NZ; ++k) zp[(size_t)k * N + i] = z[k];
+  double SV;
+  if (MIXED)
+    SV = (double)((R(Is) - R(a.Cm) * iion) * R(1.0 / a.Cm));
+  else
+    SV = (Is - a.Cm * (double)iion) / a.Cm;
+  const double FV = apply_op<MIXED>(mesh, a.Vin, i);
+  a.Vout[i] = V + a.dt * (FV + SV);
+}
+
+// ---------------------------------------------------------------------------
 // Inner stages
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ double load_sv(const void *SV, bool mixed, uint32_t i) {
@@ -1122,6 +1167,22 @@ hipError_t launch_init_state(int model, bool mixed, uint32_t N, double *V, void 
 
 hipError_t launch_head(int model, bool mixed, const Mesh &mesh, const HeadArgs &a, hipStream_t st) {
 #define CALL(M) head_dispatch<M>(mixed, mesh, a, st)
+  EMRKC_MODEL_SWITCH(model, CALL)
+#undef CALL
+}
+
+template <template <class> class Model>
+static hipError_t exexrl_dispatch(bool mixed, const Mesh &mesh, const ExArgs &a, hipStream_t st) {
+  const uint32_t N = mesh.kind == kGrid ? mesh.grid.N : mesh.ell.N;
+  if (mixed)
+    EMRKC_LAUNCH((k_exexrl<Model, true>), dim3(blocks_for(N)), dim3(kBlock), 0, st, a, mesh);
+  else
+    EMRKC_LAUNCH((k_exexrl<Model, false>), dim3(blocks_for(N)), dim3(kBlock), 0, st, a, mesh);
+  return hipGetLastError();
+}
+
+hipError_t launch_exexrl(int model, bool mixed, const Mesh &mesh, const ExArgs &a, hipStream_t st) {
+#define CALL(M) exexrl_dispatch<M>(mixed, mesh, a, st)
   EMRKC_MODEL_SWITCH(model, CALL)
 #undef CALL
 }

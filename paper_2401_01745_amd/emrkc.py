@@ -74,6 +74,7 @@ EXPORTS = {
     "emrkc_stage_counts_a": (C.c_int, [C.c_double, C.c_double, C.c_double, C.c_double, C.POINTER(C.c_int),
                                        C.POINTER(C.c_int), C.POINTER(C.c_double)]),
     "emrkc_eval_elementary": (C.c_int, [C.c_int, C.c_int, C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p]),
+    "emrkc_exexrl_step": (C.c_int, [C.c_void_p, C.POINTER(State), C.c_double, C.c_int64]),
     "emrkc_autotune": (C.c_int, [C.c_void_p, C.POINTER(State), C.c_double, C.c_int, C.POINTER(C.c_int)]),
     "emrkc_get_variants": (C.c_int, [C.c_void_p, C.POINTER(C.c_int)]),
     "emrkc_set_variants": (C.c_int, [C.c_void_p, C.POINTER(C.c_int)]),
@@ -241,6 +242,10 @@ def emrkc_profile_step(ctx, state, dt, nsteps):
     cnt = (C.c_int64 * 3)()
     _check(lib().emrkc_profile_step(ctx, C.byref(state), dt, int(nsteps), ms, cnt), ctx)
     return {k: (ms[i], cnt[i]) for i, k in enumerate(PROFILE_CLASSES)}
+
+
+def emrkc_exexrl_step(ctx, state, dt, nsteps):
+    return _check(lib().emrkc_exexrl_step(ctx, C.byref(state), dt, int(nsteps)), ctx)
 
 
 def emrkc_autotune(ctx, state, dt, reps=3):
