@@ -76,6 +76,15 @@ extern "C" {
  * EMRKC_COND_A — (s, m, eta) from stability condition A of the stability
  *   lemma: eta = (6 dt / l_s) m^2/(m^2 - 1) with the smallest m >= 2 such
  *   that eta rho_F <= beta m^2 (single contexts only). */
+/* Methods.  EMRKC_METHOD_MRKC is the mRKC method of the paper applied to
+ * the monodomain model (section "The mRKC method for the monodomain model"):
+ * the stiffest gate (gate 0 of every model here: the m gate, whose rates
+ * are the largest) joins the diffusion in the fast term, the other gates
+ * join f_S, and there is no exponential stage; emrkc_estimate_rho then
+ * estimates the radii of these two terms.  Double precision single
+ * contexts on the flat kernels only. */
+#define EMRKC_METHOD_EMRKC 0
+#define EMRKC_METHOD_MRKC 1
 #define EMRKC_PROGRESSIVE 0x100u
 #define EMRKC_COND_A 0x200u
 
@@ -131,6 +140,8 @@ typedef struct {
   uint64_t powiter_seed;  /* splitmix64 state of the start vector (0)        */
   double linear_a;        /* EMRKC_MODEL_LINEAR: i_ion = a V                 */
   double linear_lambda_E; /* EMRKC_MODEL_LINEAR: constant gate rate (< 0)    */
+  int32_t method;         /* EMRKC_METHOD_EMRKC (0) or EMRKC_METHOD_MRKC    */
+  int32_t reserved1;      /* 0                                              */
 } emrkc_params;
 
 /* Caller-owned state.  t0 and step define the time of the state as
@@ -273,6 +284,13 @@ int emrkc_batch_info(const emrkc_ctx *ctx, double dt, int64_t *offsets, int *m, 
 
 /* Sets every instance's radii (taken as given). */
 int emrkc_batch_set_rho(emrkc_ctx *ctx, const double *rho_F, const double *rho_S);
+
+/* The two terms of the mRKC split (see EMRKC_METHOD_MRKC) at (t, state):
+ * which = 0: f~_F = (f_F, rate of gate 0, 0 ...), which = 1: f~_S = (V part
+ * of f_S, 0, rates of gates 1.., g_S).  out is a device double[n_v * N] in
+ * the layout [V | z planes]; the context must be double precision and not a
+ * batch.  Allocates a work copy of the state on first use. */
+int emrkc_eval_mrkc_terms(emrkc_ctx *ctx, const emrkc_state *state, double t, int which, double *out);
 
 /* ---- reference stepping ----------------------------------------------------
  * nsteps steps of EXEX-RL, the fine reference method of the error

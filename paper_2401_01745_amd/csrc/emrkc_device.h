@@ -185,16 +185,23 @@ __device__ __forceinline__ void gate_from_rates(typename M::R a, typename M::R b
 // Classical Hodgkin-Huxley gates m, h, n (modern sign convention, rest near
 // -65 mV); the m rates are multiplied by km.
 template <class M>
-__device__ __forceinline__ void hh_core_gates(typename M::R V, typename M::R km,
-                                              typename M::R *lam, typename M::R *zinf) {
+__device__ __forceinline__ void hh_m_gate(typename M::R V, typename M::R km, typename M::R &lam,
+                                          typename M::R &zinf) {
   using R = typename M::R;
   R am = km * x_over_expm1<M>(-(V + R(40)) * R(0.1));
   R bm = km * (R(4) * M::exp(-(V + R(65)) * R(1.0 / 18.0)));
+  gate_from_rates<M>(am, bm, lam, zinf);
+}
+
+template <class M>
+__device__ __forceinline__ void hh_core_gates(typename M::R V, typename M::R km,
+                                              typename M::R *lam, typename M::R *zinf) {
+  using R = typename M::R;
+  hh_m_gate<M>(V, km, lam[0], zinf[0]);
   R ah = R(0.07) * M::exp(-(V + R(65)) * R(0.05));
   R bh = M::div(R(1), R(1) + M::exp(-(V + R(35)) * R(0.1)));
   R an = R(0.1) * x_over_expm1<M>(-(V + R(55)) * R(0.1));
   R bn = R(0.125) * M::exp(-(V + R(65)) * R(1.0 / 80.0));
-  gate_from_rates<M>(am, bm, lam[0], zinf[0]);
   gate_from_rates<M>(ah, bh, lam[1], zinf[1]);
   gate_from_rates<M>(an, bn, lam[2], zinf[2]);
 }
@@ -240,6 +247,10 @@ struct HHModel {
   static __device__ __forceinline__ void gates(R V, const ModelParams &, R *lam, R *zinf) {
     hh_core_gates<M>(V, R(1), lam, zinf);
   }
+  // gate 0 alone (the stiffest: m), as gates() computes it
+  static __device__ __forceinline__ void gate0(R V, const ModelParams &, R &lam, R &zinf) {
+    hh_m_gate<M>(V, R(1), lam, zinf);
+  }
   static __device__ __forceinline__ R eval(R V, const R *zE, const R *, R *, const ModelParams &) {
     R m = zE[0], h = zE[1], n = zE[2];
     R n2 = n * n;
@@ -257,6 +268,10 @@ struct LinearModel {
   static __device__ __forceinline__ void gates(R, const ModelParams &p, R *lam, R *zinf) {
     lam[0] = R(p.lin_lamE);
     zinf[0] = R(0);
+  }
+  static __device__ __forceinline__ void gate0(R, const ModelParams &p, R &lam, R &zinf) {
+    lam = R(p.lin_lamE);
+    zinf = R(0);
   }
   static __device__ __forceinline__ R eval(R V, const R *, const R *, R *, const ModelParams &p) {
     return R(p.lin_a) * V;
@@ -287,6 +302,9 @@ struct CrnSurrModel {
   using R = typename M::R;
   static constexpr int NG = 15, NS = 5;
   static constexpr double V_REST = -65.0;
+  static __device__ __forceinline__ void gate0(R V, const ModelParams &, R &lam, R &zinf) {
+    hh_m_gate<M>(V, R(15), lam, zinf);
+  }
   static __device__ __forceinline__ void gates(R V, const ModelParams &, R *lam, R *zinf) {
     hh_core_gates<M>(V, R(15), lam, zinf);
 #pragma unroll
@@ -344,6 +362,9 @@ struct TtpSurrModel {
   using R = typename M::R;
   static constexpr int NG = 12, NS = 6;
   static constexpr double V_REST = -65.0;
+  static __device__ __forceinline__ void gate0(R V, const ModelParams &, R &lam, R &zinf) {
+    hh_m_gate<M>(V, R(110), lam, zinf);
+  }
   static __device__ __forceinline__ void gates(R V, const ModelParams &, R *lam, R *zinf) {
     hh_core_gates<M>(V, R(110), lam, zinf);
 #pragma unroll

@@ -104,6 +104,15 @@ struct emrkc_ctx {
   bool progressive = false;   // EMRKC_PROGRESSIVE
   bool cond_a = false;        // EMRKC_COND_A
   int rho_every = 0;          // params.rho_every
+  int method = EMRKC_METHOD_EMRKC;
+  // mRKC: gate-0 inner buffers, and full-state vectors of its power iteration
+  double *d_W[2] = {nullptr, nullptr};
+  double *d_Y = nullptr, *d_FY = nullptr, *d_Wv = nullptr, *d_FW = nullptr;
+  double *d_mv[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
+  double *d_mpart = nullptr;
+  bool m_warm[2] = {false, false};
+  int m_sel[2] = {0, 0};
+  double m_raw[2] = {0, 0}, m_nv[2] = {0, 0};
   int64_t last_est_step = -1; // state step of the last re-estimate by emrkc_step
   void *d_z1 = nullptr;
   Clock *d_clock = nullptr;
@@ -361,7 +370,9 @@ static void free_ctx(emrkc_ctx *c) {
   c->graphs.clear();
   void *ptrs[] = {c->d_mask, c->d_ell_col, c->d_ell_w64, c->d_ell_w32, c->d_V1, c->d_U[0], c->d_U[1],
                   c->d_U[2], c->d_SV, c->d_SV2,   c->d_z1,      c->d_clock,   c->d_partials, c->d_result, c->d_flag,
-                  c->d_vF[0], c->d_vF[1], c->d_vS[0], c->d_vS[1], c->d_zV};
+                  c->d_vF[0], c->d_vF[1], c->d_vS[0], c->d_vS[1], c->d_zV,
+                  c->d_W[0], c->d_W[1], c->d_Y, c->d_FY, c->d_Wv, c->d_FW,
+                  c->d_mv[0][0], c->d_mv[0][1], c->d_mv[1][0], c->d_mv[1][1], c->d_mpart};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   if (c->capture) (void)hipStreamDestroy(c->capture);
@@ -390,6 +401,8 @@ extern "C" int emrkc_create(const emrkc_mesh *mesh, const emrkc_conductivity *co
   if (p->precision != EMRKC_FP64 && p->precision != EMRKC_MIXED32) return EMRKC_EINVAL;
   if (!(p->powiter_tol > 0) || !(p->powiter_eps > 0) || p->powiter_max_iter < 1) return EMRKC_EINVAL;
   if (p->rho_every < 0) return EMRKC_EINVAL;
+  if (p->method != EMRKC_METHOD_EMRKC && p->method != EMRKC_METHOD_MRKC) return EMRKC_EINVAL;
+  if (p->method == EMRKC_METHOD_MRKC && p->precision != EMRKC_FP64) return EMRKC_EUNSUPPORTED;
   if (!isfinite(p->stim_amp) || !isfinite(p->stim_t_on) || !isfinite(p->stim_t_off)) return EMRKC_EINVAL;
   if (!isfinite(p->rho_F) || !isfinite(p->rho_S)) return EMRKC_EINVAL;
   if (ionic_model == EMRKC_MODEL_LINEAR && (!isfinite(p->linear_a) || !isfinite(p->linear_lambda_E) ||
@@ -435,6 +448,7 @@ extern "C" int emrkc_create(const emrkc_mesh *mesh, const emrkc_conductivity *co
   c->progressive = (p->flags & EMRKC_PROGRESSIVE) != 0;
   c->cond_a = (p->flags & EMRKC_COND_A) != 0;
   c->rho_every = p->rho_every;
+  c->method = p->method;
   c->chi = p->chi;
   c->Cm = p->Cm;
   c->eps = p->eps;
@@ -820,6 +834,62 @@ static int enqueue_chunk_s1m1(emrkc_ctx *c, const emrkc_state *st, const StepPla
   return EMRKC_OK;
 }
 
+// One mRKC step, any (s, m): the buffer rotation of enqueue_step_generic,
+// with gate 0 carried through the inner stages in d_W[] (its w_0 is plane 0
+// of z_{j-1}, and its outer update lands in plane 0 of z_j at the last inner
+// stage; the head leaves that plane alone when m >= 2).
+static int enqueue_step_mrkc(emrkc_ctx *c, const emrkc_state *st, const StepPlan &P, double dt, int step_off,
+                             int64_t tick_by, hipStream_t strm, KernelTimer *tm) {
+  const int s = P.s, m = P.m;
+  double *X[2] = {(double *)st->V, c->d_V1};
+  void *Z[2] = {st->z, c->d_z1};
+  auto vidx = [&](int j) { return j == 0 ? 0 : (j < s ? j % 2 : 0); };
+  const bool final_copy = (m == 1) && (vidx(s - 1) == 0);
+  for (int j = 1; j <= s; ++j) {
+    const bool lastj = j == s;
+    double *Vin = X[vidx(j - 1)];
+    double *Vin2 = j >= 2 ? X[vidx(j - 2)] : nullptr;
+    double *Vdst = (lastj && final_copy) ? X[1] : X[vidx(j)];
+    MrkcHeadArgs ha{};
+    ha.h = make_head(c, P, dt, j, step_off);
+    ha.h.Vin = Vin;
+    ha.h.Vin2 = Vin2;
+    ha.h.zin = Z[vidx(j - 1)];
+    ha.h.zin2 = j >= 2 ? Z[vidx(j - 2)] : nullptr;
+    ha.h.zout = Z[vidx(j)];
+    ha.h.uout = m >= 2 ? c->d_U[0] : Vdst;
+    ha.wout = c->d_W[0];
+    TIMED(0, launch_mrkc_head(c->model, c->mesh, ha, strm));
+    for (int k = 2; k <= m; ++k) {
+      MrkcInnerArgs ia{};
+      InnerArgs &a = ia.a;
+      a.t = make_stage(P, dt, j, k);
+      a.t.uprev = c->d_U[(k - 2) % 2];
+      a.t.uprev2 = k == 2 ? Vin : c->d_U[(k - 3) % 2];
+      a.t.SV = c->d_SV;
+      a.t.Vin = Vin;
+      a.t.Vin2 = Vin2;
+      a.last = k == m;
+      a.out = a.last ? Vdst : c->d_U[(k - 1) % 2];
+      a.tick = (lastj && k == m && tick_by > 0) ? c->d_clock : nullptr;
+      a.tick_by = tick_by;
+      ia.wprev = c->d_W[(k - 2) % 2];
+      ia.wprev2 = k == 2 ? (const double *)ha.h.zin : c->d_W[(k - 3) % 2];
+      ia.wout = c->d_W[(k - 1) % 2];
+      ia.zq_in = (const double *)ha.h.zin;
+      ia.zq_in2 = (const double *)ha.h.zin2;
+      ia.zq_out = (double *)ha.h.zout;
+      ia.mp = c->mp;
+      TIMED(1, launch_mrkc_inner(c->model, c->mesh, ia, strm));
+    }
+  }
+  if (m == 1 && (final_copy || tick_by > 0)) {
+    HIP_TRY(c, launch_copy_tick(final_copy ? X[1] : nullptr, X[0], (uint32_t)c->N, tick_by > 0 ? c->d_clock : nullptr,
+                                tick_by, strm));
+  }
+  return EMRKC_OK;
+}
+
 static int enqueue_chunk_batch(emrkc_ctx *c, const emrkc_state *st, const StepPlan &P, double dt, int L,
                                hipStream_t strm, KernelTimer *tm);
 
@@ -827,6 +897,13 @@ static int enqueue_chunk(emrkc_ctx *c, const emrkc_state *st, const StepPlan &P,
                          KernelTimer *tm = nullptr) {
   set_flat_kernels(c->flat);
   if (c->batch) return enqueue_chunk_batch(c, st, P, dt, L, strm, tm);
+  if (c->method == EMRKC_METHOD_MRKC) {
+    for (int n = 0; n < L; ++n) {
+      int rc = enqueue_step_mrkc(c, st, P, dt, n, n == L - 1 ? L : 0, strm, tm);
+      if (rc != EMRKC_OK) return rc;
+    }
+    return EMRKC_OK;
+  }
   if (c->use_fused && P.s == 1 && P.m >= 2 && fused_supported(c->mesh))
     return enqueue_chunk_fused(c, st, P, dt, L, strm, tm);
   if (P.s == 1 && P.m == 1) return enqueue_chunk_s1m1(c, st, P, dt, L, strm, tm);
@@ -872,6 +949,10 @@ static int make_plan(emrkc_ctx *c, double dt, StepPlan &P) {
   rkc_coeffs(P.s, c->eps, P.mu, P.nu, P.ka, P.cc);
   rkc_coeffs(P.m, c->eps, P.mui, P.nui, P.kai, P.cci);
   if (P.s >= 2 && (rc = ensure_z1(c)) != EMRKC_OK) return rc;
+  if (c->method == EMRKC_METHOD_MRKC && c->d_W[0] == nullptr) {
+    const size_t vb = sizeof(double) * (size_t)c->N;
+    if ((rc = dalloc(c, (void **)&c->d_W[0], vb)) || (rc = dalloc(c, (void **)&c->d_W[1], vb))) return rc;
+  }
   return EMRKC_OK;
 }
 
@@ -1396,6 +1477,108 @@ static int alloc_rho_buffers(emrkc_ctx *c) {
   return EMRKC_OK;
 }
 
+// ---- mRKC: the power iteration on full-state vectors ----------------------
+// The oracle's Compute_Rho on f~_F and f~_S, literally: vectors of all n_v N
+// components (zero where a term has no component), the same splitmix64 start
+// over all of them, and the warm start kept per term.
+static int mrkc_buffers(emrkc_ctx *c) {
+  if (c->d_Y) return EMRKC_OK;
+  const uint64_t n = (uint64_t)c->nv * (uint64_t)c->N;
+  if (n >= (1ull << 32)) return fail(c, EMRKC_EUNSUPPORTED, "mRKC state vectors need n_v N < 2^32");
+  const size_t vb = sizeof(double) * n;
+  int rc;
+  if ((rc = dalloc(c, (void **)&c->d_Y, vb)) || (rc = dalloc(c, (void **)&c->d_FY, vb)) ||
+      (rc = dalloc(c, (void **)&c->d_Wv, vb)) || (rc = dalloc(c, (void **)&c->d_FW, vb)) ||
+      (rc = dalloc(c, (void **)&c->d_mpart, sizeof(double) * (n / 256 + 1))))
+    return rc;
+  return EMRKC_OK;
+}
+
+static int copy_to_full(emrkc_ctx *c, const emrkc_state *st) {
+  const size_t N = (size_t)c->N;
+  HIP_TRY(c, hipMemcpyAsync(c->d_Y, st->V, sizeof(double) * N, hipMemcpyDeviceToDevice, c->stream));
+  HIP_TRY(c, hipMemcpyAsync(c->d_Y + N, st->z, sizeof(double) * N * (size_t)(c->nv - 1), hipMemcpyDeviceToDevice,
+                            c->stream));
+  return EMRKC_OK;
+}
+
+static int estimate_mrkc(emrkc_ctx *c, const emrkc_state *st, int *iters_F, int *iters_S, bool *noconv) {
+  int rc;
+  if ((rc = mrkc_buffers(c)) != EMRKC_OK) return rc;
+  const uint64_t n = (uint64_t)c->nv * (uint64_t)c->N;
+  for (int w = 0; w < 2; ++w)
+    for (int b = 0; b < 2; ++b)
+      if (!c->d_mv[w][b] && (rc = dalloc(c, (void **)&c->d_mv[w][b], sizeof(double) * n))) return rc;
+  if ((rc = copy_to_full(c, st)) != EMRKC_OK) return rc;
+  const StimArgs stim = stim_args(c);
+  double ny2 = 0;
+  HIP_TRY(c, launch_vec_diff_norm(n, c->d_Y, nullptr, nullptr, c->d_mpart, c->d_result, c->stream));
+  if ((rc = fetch(c, &ny2))) return rc;
+  const double ny = sqrt(ny2);
+  const double delta = ny > 0 ? ny * c->pi_eps : c->pi_eps;
+  for (int which = 0; which < 2; ++which) {
+    bool &warm = c->m_warm[which];
+    int &sel = c->m_sel[which];
+    double nv;
+    if (warm) {
+      nv = c->m_nv[which];
+    } else {
+      double s2;
+      HIP_TRY(c, launch_norm2_random(c->pi_seed, n, c->d_mpart, c->d_result, c->stream));
+      if ((rc = fetch(c, &s2))) return rc;
+      nv = sqrt(s2);
+    }
+    HIP_TRY(c, launch_mrkc_rhs(c->model, which, c->mesh, (uint32_t)c->N, st->t, c->d_Y, c->d_FY, stim, c->Cm, c->mp,
+                               c->stream));
+    double q = delta / nv, rho = warm ? c->m_raw[which] : 0.0, rho_old = 0.0;
+    int it = 0;
+    while (fabs(rho - rho_old) >= c->pi_tol * rho) {
+      if (it >= c->pi_max_iter) {
+        *noconv = true;
+        break;
+      }
+      rho_old = rho;
+      const double *vin = warm ? c->d_mv[which][sel] : nullptr;
+      double *vout = c->d_mv[which][1 - sel];
+      HIP_TRY(c, launch_powF_shift((uint32_t)n, c->d_Y, vin, c->pi_seed, q, c->d_Wv, c->stream));
+      HIP_TRY(c, launch_mrkc_rhs(c->model, which, c->mesh, (uint32_t)c->N, st->t, c->d_Wv, c->d_FW, stim, c->Cm,
+                                 c->mp, c->stream));
+      HIP_TRY(c, launch_vec_diff_norm(n, c->d_FW, c->d_FY, vout, c->d_mpart, c->d_result, c->stream));
+      double s2;
+      if ((rc = fetch(c, &s2))) return rc;
+      sel = 1 - sel;
+      warm = true;
+      nv = sqrt(s2);
+      ++it;
+      if (nv == 0.0) {
+        rho = 0.0;
+        break;
+      }
+      q = delta / nv;
+      rho = nv / delta;
+    }
+    c->m_raw[which] = rho;
+    c->m_nv[which] = nv;
+    if (which == 0 && iters_F) *iters_F = it;
+    if (which == 1 && iters_S) *iters_S = it;
+  }
+  return EMRKC_OK;
+}
+
+extern "C" int emrkc_eval_mrkc_terms(emrkc_ctx *c, const emrkc_state *st, double t, int which, double *out) {
+  if (c == nullptr) return EMRKC_EINVAL;
+  if (!state_ok(c, st) || out == nullptr || (which != 0 && which != 1))
+    return fail(c, EMRKC_EINVAL, "invalid state, output or term");
+  if (c->batch || c->mixed) return fail(c, EMRKC_EUNSUPPORTED, "mRKC terms need a double precision single context");
+  int rc;
+  if ((rc = mrkc_buffers(c)) != EMRKC_OK) return rc;
+  if ((rc = copy_to_full(c, st)) != EMRKC_OK) return rc;
+  HIP_TRY(c, launch_mrkc_rhs(c->model, which, c->mesh, (uint32_t)c->N, t, c->d_Y, out, stim_args(c), c->Cm, c->mp,
+                             c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  return EMRKC_OK;
+}
+
 static int estimate_batch(emrkc_ctx *c, const emrkc_state *st, double *rho_F, double *rho_S, int *iters_F,
                           int *iters_S);
 
@@ -1406,6 +1589,17 @@ extern "C" int emrkc_estimate_rho(emrkc_ctx *c, const emrkc_state *st, double *r
   int rc = alloc_rho_buffers(c);
   if (rc != EMRKC_OK) return rc;
   if (c->batch) return estimate_batch(c, st, rho_F, rho_S, iters_F, iters_S);
+  if (c->method == EMRKC_METHOD_MRKC) {
+    bool noconv = false;
+    if ((rc = estimate_mrkc(c, st, iters_F, iters_S, &noconv)) != EMRKC_OK) return rc;
+    c->rho_F = c->safety * c->m_raw[0];
+    c->rho_S = c->safety * c->m_raw[1];
+    c->have_rho = true;
+    if (rho_F) *rho_F = c->rho_F;
+    if (rho_S) *rho_S = c->rho_S;
+    if (noconv) return fail(c, EMRKC_ENOCONV, "power iteration reached %d iterations", c->pi_max_iter);
+    return EMRKC_OK;
+  }
   RhoView v{};
   v.mesh = c->mesh;
   v.N = (uint32_t)c->N;
@@ -1595,6 +1789,7 @@ extern "C" int emrkc_create_batch(int n_inst, const emrkc_mesh *meshes, const em
   if (!(p0.eps > 0) || !(p0.eps < 1) || !(p0.rho_safety >= 1.0)) return EMRKC_EINVAL;
   if (!(p0.powiter_tol > 0) || !(p0.powiter_eps > 0) || p0.powiter_max_iter < 1) return EMRKC_EINVAL;
   if (p0.rho_every != 0) return EMRKC_EUNSUPPORTED;        // ensembles keep the radii they are given
+  if (p0.method != EMRKC_METHOD_EMRKC) return EMRKC_EUNSUPPORTED;
   if (p0.flags & EMRKC_COND_A) return EMRKC_EUNSUPPORTED;  // one eta per outer stage for all instances
   int64_t Ntot = 0;
   for (int k = 0; k < n_inst; ++k) {

@@ -106,6 +106,25 @@ struct ExArgs {
   double dt, Cm;
 };
 
+// mRKC (double precision): the head of outer stage j and the inner stages
+// carry the stiffest gate (gate 0), which sits in the fast term, next to V.
+struct MrkcHeadArgs {
+  HeadArgs h;           // as for emRKC (no exponential stage); zout plane 0
+                        // is written only when m == 1
+  double *wout;         // w_1, gate 0 after the first inner stage (m >= 2)
+};
+
+struct MrkcInnerArgs {
+  InnerArgs a;
+  const double *wprev;  // w_{k-1}
+  const double *wprev2; // w_{k-2} (w_0 = z_0 of stage j-1 when k == 2)
+  double *wout;         // w_k (not last)
+  const double *zq_in;  // gate 0 of z_{j-1}
+  const double *zq_in2; // gate 0 of z_{j-2} (j >= 2)
+  double *zq_out;       // gate 0 of z_j (last)
+  ModelParams mp;
+};
+
 // One instance of a batched (ensemble) launch.  Instances are concatenated:
 // node i of the instance is node off + i of every global array, component
 // planes are N_total apart.  Logical blocks tile0 .. tile0 + ntiles - 1 of
@@ -137,6 +156,17 @@ hipError_t launch_init_state(int model, bool mixed, uint32_t N, double *V, void 
 hipError_t launch_head(int model, bool mixed, const Mesh &mesh, const HeadArgs &a, hipStream_t st);
 hipError_t launch_inner(bool mixed, const Mesh &mesh, const InnerArgs &a, hipStream_t st);
 hipError_t launch_exexrl(int model, bool mixed, const Mesh &mesh, const ExArgs &a, hipStream_t st);
+hipError_t launch_mrkc_head(int model, const Mesh &mesh, const MrkcHeadArgs &a, hipStream_t st);
+hipError_t launch_mrkc_inner(int model, const Mesh &mesh, const MrkcInnerArgs &a, hipStream_t st);
+// The split terms of mRKC on a full double state y = [V | z planes]:
+// which = 0: f~_F = (f_F, gate-0 rate, 0), which = 1: f~_S = (f_S's V part,
+// 0, other gates' rates, g_S); out has the same layout.
+hipError_t launch_mrkc_rhs(int model, int which, const Mesh &mesh, uint32_t N, double t, const double *y,
+                           double *out, StimArgs stim, double Cm, ModelParams mp, hipStream_t st);
+// out = a - b over n entries (b == nullptr: b = 0; out == nullptr: not
+// stored), partial sums of out^2 per block (ceil(n/256) of them), final sum.
+hipError_t launch_vec_diff_norm(uint64_t n, const double *a, const double *b, double *out, double *partials,
+                                double *result, hipStream_t st);
 hipError_t launch_fused(int model, bool mixed, const Mesh &mesh, const FusedArgs &a, hipStream_t st);
 bool fused_supported(const Mesh &mesh);
 // Testing switch: use the flat (one node per thread, global-load stencil)

@@ -299,6 +299,119 @@ __global__ __launch_bounds__(kBlock) void k_inner(InnerArgs a, Mesh mesh) {
 }
 
 // ---------------------------------------------------------------------------
+// mRKC (double precision, flat kernels).  The fast term is f_F plus the rate
+// of gate 0 (the stiffest gate), the slow term f_S plus the rates of the
+// other gates; there is no exponential stage.  The head of outer stage j
+// evaluates the slow term at y_{j-1}, finishes the outer recurrence of every
+// component except V and gate 0 (their inner problems have constant
+// forcing, so they end at z + c'_m eta S), and takes the first inner stage
+// of V and gate 0; the inner stages advance both, with the gate-0 rate at
+// the current inner V.
+// ---------------------------------------------------------------------------
+template <template <class> class Model>
+__global__ __launch_bounds__(kBlock) void k_mrkc_head(MrkcHeadArgs ma, Mesh mesh) {
+  using M = MathF64;
+  using Mod = Model<M>;
+  constexpr int NG = Mod::NG, NS = Mod::NS, NZ = NG + NS;
+  const HeadArgs &a = ma.h;
+  const uint32_t N = mesh.kind == kGrid ? mesh.grid.N : mesh.ell.N;
+  const uint32_t i = node_index();
+  if (i >= N) return;
+  const double V = a.Vin[i];
+  const double tj = stage_time(a.clock, a.step_off, a.dt, a.c_prev);
+  const double Is = stimulus(a.stim, i, tj);
+  const double *zin = (const double *)a.zin;
+  const double *zin2 = (const double *)a.zin2;
+  double *zout = (double *)a.zout;
+  double z[NZ];
+#pragma unroll
+  for (int k = 0; k < NZ; ++k) z[k] = zin[(size_t)k * N + i];
+  double lam[NG], zinf[NG];
+  Mod::gates(V, a.mp, lam, zinf);
+  double dS[NS > 0 ? NS : 1];
+  const double iion = Mod::eval(V, z, z + NG, dS, a.mp);
+  const double SV = (Is - a.Cm * iion) / a.Cm;
+#pragma unroll
+  for (int k = 1; k < NZ; ++k) {
+    const double S = k < NG ? lam[k] * (z[k] - zinf[k]) : dS[k - NG];
+    const double um = z[k] + a.cm_eta * S;
+    const double fbar = (um - z[k]) * a.inv_eta;
+    zout[(size_t)k * N + i] =
+        a.j1 ? z[k] + a.mu_dt * fbar : a.nu * z[k] + a.kappa * zin2[(size_t)k * N + i] + a.mu_dt * fbar;
+  }
+  const double g0 = lam[0] * (z[0] - zinf[0]);
+  const double FV = apply_op<false>(mesh, a.Vin, i);
+  const double u1 = V + a.mu1_eta * (FV + SV);
+  const double w1 = z[0] + a.mu1_eta * g0;
+  if (a.m_is_one) {
+    const double fbarV = (u1 - V) * a.inv_eta;
+    const double fbarW = (w1 - z[0]) * a.inv_eta;
+    a.uout[i] = a.j1 ? V + a.mu_dt * fbarV : a.nu * V + a.kappa * a.Vin2[i] + a.mu_dt * fbarV;
+    zout[i] = a.j1 ? z[0] + a.mu_dt * fbarW : a.nu * z[0] + a.kappa * zin2[i] + a.mu_dt * fbarW;
+  } else {
+    a.uout[i] = u1;
+    ma.wout[i] = w1;
+    ((double *)a.SV)[i] = SV;
+  }
+}
+
+template <template <class> class Model>
+__global__ __launch_bounds__(kBlock) void k_mrkc_inner(MrkcInnerArgs ma, Mesh mesh) {
+  using M = MathF64;
+  using Mod = Model<M>;
+  const InnerArgs &a = ma.a;
+  const uint32_t N = mesh.kind == kGrid ? mesh.grid.N : mesh.ell.N;
+  const uint32_t i = node_index();
+  if (a.tick != nullptr && blockIdx.x == 0 && threadIdx.x == 0) a.tick->step += a.tick_by;
+  if (i >= N) return;
+  const double u = a.t.uprev[i];
+  const double w = ma.wprev[i];
+  double lam0, zinf0;
+  Mod::gate0(u, ma.mp, lam0, zinf0);
+  const double g = lam0 * (w - zinf0);
+  const double Fu = apply_op<false>(mesh, a.t.uprev, i);
+  const double uk = inner_combine(a.t, u, a.t.uprev2[i], Fu, load_sv(a.t.SV, false, i));
+  const double wk = inner_combine(a.t, w, ma.wprev2[i], g, 0.0);
+  if (a.last) {
+    a.out[i] = tail_combine(a.t, uk, a.t.Vin[i], a.t.j1 ? 0.0 : a.t.Vin2[i]);
+    ma.zq_out[i] = tail_combine(a.t, wk, ma.zq_in[i], a.t.j1 ? 0.0 : ma.zq_in2[i]);
+  } else {
+    a.out[i] = uk;
+    ma.wout[i] = wk;
+  }
+}
+
+template <template <class> class Model>
+__global__ __launch_bounds__(kBlock) void k_mrkc_rhs(int which, Mesh mesh, uint32_t N, double t, const double *y,
+                                                     double *out, StimArgs stim, double Cm, ModelParams mp) {
+  using M = MathF64;
+  using Mod = Model<M>;
+  constexpr int NG = Mod::NG, NS = Mod::NS, NZ = NG + NS;
+  const uint32_t i = node_index();
+  if (i >= N) return;
+  const double V = y[i];
+  double z[NZ];
+#pragma unroll
+  for (int k = 0; k < NZ; ++k) z[k] = y[(size_t)(k + 1) * N + i];
+  double lam[NG], zinf[NG];
+  Mod::gates(V, mp, lam, zinf);
+  if (which == 0) {
+    out[i] = apply_op<false>(mesh, y, i);
+    out[(size_t)N + i] = lam[0] * (z[0] - zinf[0]);
+#pragma unroll
+    for (int k = 1; k < NZ; ++k) out[(size_t)(k + 1) * N + i] = 0.0;
+    return;
+  }
+  double dS[NS > 0 ? NS : 1];
+  const double iion = Mod::eval(V, z, z + NG, dS, mp);
+  out[i] = (stimulus(stim, i, t) - Cm * iion) / Cm;
+  out[(size_t)N + i] = 0.0;
+#pragma unroll
+  for (int k = 1; k < NZ; ++k)
+    out[(size_t)(k + 1) * N + i] = k < NG ? lam[k] * (z[k] - zinf[k]) : dS[k - NG];
+}
+
+// ---------------------------------------------------------------------------
 // Fused tail + head on a structured grid.  Each block owns a TX x TY x TZ
 // tile; phase 1 computes V^n on the tile plus a one-node halo (mirrored at
 // the domain boundary) into LDS, phase 2 runs the head of the next step on
@@ -953,6 +1066,19 @@ __global__ __launch_bounds__(kBlock) void k_norm2_random(uint64_t seed, uint64_t
   if (threadIdx.x == 0) partials[blockIdx.x] = v;
 }
 
+__global__ __launch_bounds__(kBlock) void k_vec_diff_norm(uint64_t n, const double *a, const double *b, double *out,
+                                                          double *partials) {
+  const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  double v = 0.0;
+  if (i < n) {
+    const double d = b != nullptr ? a[i] - b[i] : a[i];
+    if (out != nullptr) out[i] = d;
+    v = d * d;
+  }
+  v = block_sum(v);
+  if (threadIdx.x == 0) partials[blockIdx.x] = v;
+}
+
 __global__ __launch_bounds__(kBlock) void k_powF_shift(uint32_t N, const double *yV, const double *vin,
                                                        uint64_t seed, double q, double *zV) {
   const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -1185,6 +1311,55 @@ hipError_t launch_exexrl(int model, bool mixed, const Mesh &mesh, const ExArgs &
 #define CALL(M) exexrl_dispatch<M>(mixed, mesh, a, st)
   EMRKC_MODEL_SWITCH(model, CALL)
 #undef CALL
+}
+
+template <template <class> class Model>
+static hipError_t mrkc_head_dispatch(const Mesh &mesh, const MrkcHeadArgs &a, hipStream_t st) {
+  const uint32_t N = mesh.kind == kGrid ? mesh.grid.N : mesh.ell.N;
+  EMRKC_LAUNCH((k_mrkc_head<Model>), dim3(blocks_for(N)), dim3(kBlock), 0, st, a, mesh);
+  return hipGetLastError();
+}
+
+hipError_t launch_mrkc_head(int model, const Mesh &mesh, const MrkcHeadArgs &a, hipStream_t st) {
+#define CALL(M) mrkc_head_dispatch<M>(mesh, a, st)
+  EMRKC_MODEL_SWITCH(model, CALL)
+#undef CALL
+}
+
+template <template <class> class Model>
+static hipError_t mrkc_inner_dispatch(const Mesh &mesh, const MrkcInnerArgs &a, hipStream_t st) {
+  const uint32_t N = mesh.kind == kGrid ? mesh.grid.N : mesh.ell.N;
+  EMRKC_LAUNCH((k_mrkc_inner<Model>), dim3(blocks_for(N)), dim3(kBlock), 0, st, a, mesh);
+  return hipGetLastError();
+}
+
+hipError_t launch_mrkc_inner(int model, const Mesh &mesh, const MrkcInnerArgs &a, hipStream_t st) {
+#define CALL(M) mrkc_inner_dispatch<M>(mesh, a, st)
+  EMRKC_MODEL_SWITCH(model, CALL)
+#undef CALL
+}
+
+template <template <class> class Model>
+static hipError_t mrkc_rhs_dispatch(int which, const Mesh &mesh, uint32_t N, double t, const double *y, double *out,
+                                    StimArgs stim, double Cm, ModelParams mp, hipStream_t st) {
+  EMRKC_LAUNCH((k_mrkc_rhs<Model>), dim3(blocks_for(N)), dim3(kBlock), 0, st, which, mesh, N, t, y, out, stim, Cm,
+               mp);
+  return hipGetLastError();
+}
+
+hipError_t launch_mrkc_rhs(int model, int which, const Mesh &mesh, uint32_t N, double t, const double *y,
+                           double *out, StimArgs stim, double Cm, ModelParams mp, hipStream_t st) {
+#define CALL(M) mrkc_rhs_dispatch<M>(which, mesh, N, t, y, out, stim, Cm, mp, st)
+  EMRKC_MODEL_SWITCH(model, CALL)
+#undef CALL
+}
+
+hipError_t launch_vec_diff_norm(uint64_t n, const double *a, const double *b, double *out, double *partials,
+                                double *result, hipStream_t st) {
+  const uint32_t nb = (uint32_t)((n + kBlock - 1) / kBlock);
+  EMRKC_LAUNCH(k_vec_diff_norm, dim3(nb), dim3(kBlock), 0, st, n, a, b, out, partials);
+  EMRKC_LAUNCH(k_reduce_final, dim3(1), dim3(kBlock), 0, st, partials, nb, result);
+  return hipGetLastError();
 }
 
 hipError_t launch_inner(bool mixed, const Mesh &mesh, const InnerArgs &a, hipStream_t st) {

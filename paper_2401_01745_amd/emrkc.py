@@ -29,6 +29,7 @@ EMRKC_MIXED32 = 1
 PRECISIONS = {"fp64": EMRKC_FP64, "mixed": EMRKC_MIXED32}
 EMRKC_CHECK_FINITE = 1
 EMRKC_PROGRESSIVE = 0x100  # progressive splitting of the auxiliary problem
+METHODS = {"emrkc": 0, "mrkc": 1}
 EMRKC_COND_A = 0x200       # stage counts from stability condition A
 EMRKC_EAGER = 2          # library-internal flag: no HIP-graph replay
 EMRKC_FUSE = 4           # library-internal flag: fused tail+head kernel
@@ -51,7 +52,8 @@ class Params(C.Structure):
                 ("stim_amp", C.c_double), ("stim_t_on", C.c_double), ("stim_t_off", C.c_double),
                 ("rho_F", C.c_double), ("rho_S", C.c_double), ("powiter_tol", C.c_double),
                 ("powiter_eps", C.c_double), ("powiter_max_iter", C.c_int32), ("rho_every", C.c_int32),
-                ("powiter_seed", C.c_uint64), ("linear_a", C.c_double), ("linear_lambda_E", C.c_double)]
+                ("powiter_seed", C.c_uint64), ("linear_a", C.c_double), ("linear_lambda_E", C.c_double),
+                ("method", C.c_int32), ("reserved1", C.c_int32)]
 
 
 class State(C.Structure):
@@ -74,6 +76,7 @@ EXPORTS = {
     "emrkc_stage_counts_a": (C.c_int, [C.c_double, C.c_double, C.c_double, C.c_double, C.POINTER(C.c_int),
                                        C.POINTER(C.c_int), C.POINTER(C.c_double)]),
     "emrkc_eval_elementary": (C.c_int, [C.c_int, C.c_int, C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p]),
+    "emrkc_eval_mrkc_terms": (C.c_int, [C.c_void_p, C.POINTER(State), C.c_double, C.c_int, C.c_void_p]),
     "emrkc_exexrl_step": (C.c_int, [C.c_void_p, C.POINTER(State), C.c_double, C.c_int64]),
     "emrkc_autotune": (C.c_int, [C.c_void_p, C.POINTER(State), C.c_double, C.c_int, C.POINTER(C.c_int)]),
     "emrkc_get_variants": (C.c_int, [C.c_void_p, C.POINTER(C.c_int)]),
@@ -244,6 +247,11 @@ def emrkc_profile_step(ctx, state, dt, nsteps):
     return {k: (ms[i], cnt[i]) for i, k in enumerate(PROFILE_CLASSES)}
 
 
+def emrkc_eval_mrkc_terms(ctx, state, t, which, out):
+    """out (CUDA float64 tensor of n_v N entries) = f~_F (which 0) or f~_S (1)."""
+    return _check(lib().emrkc_eval_mrkc_terms(ctx, C.byref(state), t, which, out.data_ptr()), ctx)
+
+
 def emrkc_exexrl_step(ctx, state, dt, nsteps):
     return _check(lib().emrkc_exexrl_step(ctx, C.byref(state), dt, int(nsteps)), ctx)
 
@@ -374,7 +382,8 @@ class Simulation:
             pass
 
 
-def simulation_from_config(cfg, precision=None, rho=None, flags=0, stim_mask=None, rho_every=0, **model_kw):
+def simulation_from_config(cfg, precision=None, rho=None, flags=0, stim_mask=None, rho_every=0, method="emrkc",
+                           **model_kw):
     """Simulation for a structured-grid workload dictionary (see the
     workloads package).  ``rho`` = (rho_F, rho_S) fixes the spectral radii;
     otherwise call ``estimate_rho``.  ``rho_every`` > 0 re-estimates them
@@ -400,12 +409,13 @@ def simulation_from_config(cfg, precision=None, rho=None, flags=0, stim_mask=Non
     if rho is not None:
         p.rho_F, p.rho_S = rho
     p.rho_every = rho_every
+    p.method = METHODS[method]
     p.linear_a = model_kw.get("a", 0.0)
     p.linear_lambda_E = model_kw.get("lam_E", 0.0)
     return Simulation(mesh, cond, cfg["model"], p, keep=(mask,))
 
 
-def simulation_from_tet_config(cfg, mesh, mask, precision=None, rho=None, flags=0):
+def simulation_from_tet_config(cfg, mesh, mask, precision=None, rho=None, flags=0, method="emrkc"):
     """Simulation for an unstructured P1 workload (see workloads.tetmesh)."""
     import numpy as np
     prec = PRECISIONS[precision or cfg.get("precision", "fp64")]
@@ -427,6 +437,7 @@ def simulation_from_tet_config(cfg, mesh, mask, precision=None, rho=None, flags=
     p.stim_t_off = st["t_off"]
     if rho is not None:
         p.rho_F, p.rho_S = rho
+    p.method = METHODS[method]
     return Simulation(m, cond, cfg["model"], p, keep=(coords, tets, fib, mask))
 
 
