@@ -53,20 +53,28 @@ def bytes_per_node(kind, nz, wz, m, mat=0):
         return 8 + 8 + sv + 8 + mat
     if kind == "tail":
         return 8 + (8 if m >= 3 else 0) + 8 + sv + 8 + mat
+    # mRKC (FP64): the head reads V and z, writes z except the stiffest gate,
+    # S_V, u_1 and w_1 (gate 0); the last inner stage (m = 2) reads u_1, V,
+    # S_V, w_1 and gate 0 of z, writes V and gate 0
+    if kind == "mrkc_head":
+        return 8 + 8 * nz + 8 * (nz - 1) + 8 + 8 + 8 + mat
+    if kind == "mrkc_tail":
+        return 8 + 8 + 8 + 8 + 8 + 8 + 8 + mat
     raise ValueError(kind)
 
 
 class Job:
-    def __init__(self, cfg, precision, stream, flags=0, tet=None, batch=None):
+    def __init__(self, cfg, precision, stream, flags=0, tet=None, batch=None, method="emrkc"):
         from paper_2401_01745_amd import emrkc as E
         self.E = E
         self.cfg = cfg
         if batch is not None:
             self.sim = E.simulation_from_batch(batch, precision=precision, flags=flags)
         elif tet is not None:
-            self.sim = E.simulation_from_tet_config(cfg, tet[0], tet[1], precision=precision, flags=flags)
+            self.sim = E.simulation_from_tet_config(cfg, tet[0], tet[1], precision=precision, flags=flags,
+                                                    method=method)
         else:
-            self.sim = E.simulation_from_config(cfg, precision=precision, flags=flags)
+            self.sim = E.simulation_from_config(cfg, precision=precision, flags=flags, method=method)
         E.emrkc_set_stream(self.sim.ctx, stream.cuda_stream)
         self.nsim = int(round(cfg["T"] / cfg["dt"]))
 
@@ -139,6 +147,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--method", default="emrkc", choices=["emrkc", "mrkc"],
+                    help="mrkc: the mRKC method (stiffest gate in the fast term), FP64, flat kernels")
     ap.add_argument("--variants", default=None,
                     help="kernel shapes 'head,head_planes,inner,inner_planes,fused' instead of autotuning")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
@@ -181,7 +191,7 @@ def main():
     with torch.cuda.stream(stream):
         log("bench: %s, N=%d, building FP64 context" % (cfg["name"], N))
         flags = 0
-        job = Job(cfg, "fp64", stream, flags, tet, batch)
+        job = Job(cfg, "fp64", stream, flags, tet, batch, method=args.method)
         forced = tuple(int(x) for x in args.variants.split(",")) if args.variants else None
         variants = job.tune(forced)
         log("bench: fp64 kernel shapes %s" % (variants,))
@@ -206,28 +216,36 @@ def main():
             off, ms, _, _ = E.emrkc_batch_info(job.sim.ctx, cfg["dt"])
             sizes = np.diff(off)
             db = int(sum(n * bytes_per_node("head", nz, 8, mk) for n, mk in zip(sizes, ms)))
+        elif args.method == "mrkc":
+            db = bytes_per_node("mrkc_head", nz, 8, m, mat) * N
         else:
             db = bytes_per_node(dom, nz, 8, m, mat) * N
         dom_gbs = db / (dom_ms * 1e-3) / 1e9
         prof_path = os.path.join(ROOT, "profiles", "traffic_k_%s_%s_fp64.json" % (dom, cfg["name"]))
         traffic = None
-        if os.path.exists(prof_path):
+        if args.method == "emrkc" and os.path.exists(prof_path):
             tr = json.load(open(prof_path))
             if tr.get("kernel_source_hash") == kernel_hash():
                 traffic = tr.get("bytes_per_launch")
-        head_kernel = ("k_head_batch" if batch is not None else "k_head" if tet is not None else
+        head_kernel = ("k_mrkc_head" if args.method == "mrkc" else
+                       "k_head_batch" if batch is not None else "k_head" if tet is not None else
                        {0: "k_head_tiled", 1: "k_head_march", 2: "k_head_march_lds", 3: "k_head_tiled_occ<6 waves/SIMD>",
                         4: "k_head_tiled_occ<8 waves/SIMD>"}[variants[0]])
         names = {"fused": "k_fused (last inner stage of step n-1 + exponential Euler, ionic model, outer z "
                           "recurrence and first inner stage of step n)",
-                 "head": "%s (exponential Euler, ionic model, outer z recurrence, first inner stage)" % head_kernel}
+                 "head": "%s (exponential Euler, ionic model, outer z recurrence, first inner stage)" % head_kernel
+                 if args.method == "emrkc" else
+                 "%s (ionic model and gate rates, outer z recurrence, first inner stage of V and the stiffest "
+                 "gate)" % head_kernel}
         # the inner kernel in this pass is the last inner stage (stencil +
         # Chebyshev recurrence + outer V update) when m == 2
         if batch is not None:
             ib = int(sum(n * bytes_per_node("tail", nz, 8, 2) for n, mk in zip(sizes, ms) if mk == 2))
+        elif args.method == "mrkc":
+            ib = bytes_per_node("mrkc_tail", nz, 8, m, mat) * N if m == 2 else None
         else:
             ib = bytes_per_node("tail" if m == 2 else "inner", nz, 8, m, mat) * N
-        inner_gbs = ib / (prof["inner"][0] * 1e-3) / 1e9 if prof["inner"][1] else None
+        inner_gbs = ib / (prof["inner"][0] * 1e-3) / 1e9 if prof["inner"][1] and ib else None
         roof = {"kernel": names[dom], "bound": "hbm", "achieved": round(dom_gbs, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(dom_gbs / HBM_PEAK_GBS, 4), "traffic": traffic,
                 "bytes_per_launch": db, "launch_ms": round(dom_ms, 5),
@@ -238,7 +256,7 @@ def main():
                                          "bytes_per_launch": ib}}
 
         mixed = None
-        if not args.no_mixed:
+        if not args.no_mixed and args.method == "emrkc":
             log("bench: mixed FP32 form")
             jm = Job(cfg, "mixed", stream, flags, tet, batch)
             variants_m = jm.tune(forced)
@@ -275,7 +293,7 @@ def main():
                                      if batch is not None else ("Q1 grid %s" % "x".join(map(str, cfg["n"]))),
                                      N, cfg["model"], cfg["chi"], cfg["Cm"], list(cfg["sigma"]), cfg["dt"], cfg["T"],
                                      job.nsim),
-                      "kernel_shapes": variants, "s": s, "m": m, "eta": eta, "rho_F": rF, "rho_S": rS, "powiter_iters": [itF, itS]},
+                      "method": args.method, "kernel_shapes": variants, "s": s, "m": m, "eta": eta, "rho_F": rF, "rho_S": rS, "powiter_iters": [itF, itS]},
            "roofline": roof, "mixed": mixed, "cpu_baseline": cpu}
     print(json.dumps(out), flush=True)
 

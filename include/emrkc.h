@@ -315,7 +315,8 @@ int emrkc_exexrl_step(emrkc_ctx *ctx, emrkc_state *state, double dt, int64_t nst
  * SIMD (fewer registers).
  * Inner kernel: 0 = 3-D tiles, 1 = z-marching columns.  Planes per column
  * in [1, 64] and at most n[2] for the column kernels, else 0.  Other meshes have
- * one head and one inner shape (entries 0..3 are 0).
+ * one head and one inner shape (entries 0..3 are 0), and so do mRKC
+ * contexts (flat kernels, no fused kernel).
  * fused = 1 (structured grids, single contexts): when s == 1 and m >= 2,
  * the last inner stage of each step and the head of the next are one
  * kernel on 3-D or 2-D tiles.

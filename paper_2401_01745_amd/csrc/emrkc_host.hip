@@ -1198,11 +1198,11 @@ static int copy_state(emrkc_ctx *c, const emrkc_state *src, StateCopy &cp) {
 // ---------------------------------------------------------------------------
 // Kernel shapes: variants[5] = {head kernel, head planes per column, inner
 // kernel, inner planes per column, fused tail+head}.
-static bool tunable(const emrkc_ctx *c) {  // the 3-D shapes
-  return !c->batch && c->mesh.kind == kGrid && c->dim == 3 && !c->flat;
+static bool tunable(const emrkc_ctx *c) {  // the 3-D shapes (emRKC)
+  return !c->batch && c->mesh.kind == kGrid && c->dim == 3 && !c->flat && c->method == EMRKC_METHOD_EMRKC;
 }
-static bool fusable(const emrkc_ctx *c) {  // the fused kernel (used when s == 1 and m >= 2)
-  return !c->batch && !c->flat && fused_supported(c->mesh);
+static bool fusable(const emrkc_ctx *c) {  // the fused kernel (emRKC, used when s == 1 and m >= 2)
+  return !c->batch && !c->flat && fused_supported(c->mesh) && c->method == EMRKC_METHOD_EMRKC;
 }
 
 static void get_variants(const emrkc_ctx *c, int *v) {
