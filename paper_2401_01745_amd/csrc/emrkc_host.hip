@@ -57,6 +57,7 @@ struct BatchDev {
   bool valid = false;
   uint64_t dt_bits = 0;
   const void *V = nullptr, *z = nullptr;  // state buffers the tables point into
+  int shape = 0;                          // tile shape the tables were built for
   int s = 0, m_max = 0;
   double eta = 0;
   BatchLaunch head[2];
@@ -105,6 +106,7 @@ struct emrkc_ctx {
   bool cond_a = false;        // EMRKC_COND_A
   int rho_every = 0;          // params.rho_every
   int method = EMRKC_METHOD_EMRKC;
+  int batch_shape = 0;        // tile shape of the batched kernels (0..2)
   // mRKC: gate-0 inner buffers, and full-state vectors of its power iteration
   double *d_W[2] = {nullptr, nullptr};
   double *d_Y = nullptr, *d_FY = nullptr, *d_Wv = nullptr, *d_FW = nullptr;
@@ -1206,6 +1208,11 @@ static bool fusable(const emrkc_ctx *c) {  // the fused kernel (emRKC, used when
 }
 
 static void get_variants(const emrkc_ctx *c, int *v) {
+  if (c->batch) {
+    v[0] = c->batch_shape;
+    v[1] = v[2] = v[3] = v[4] = 0;
+    return;
+  }
   const Grid &g = c->mesh.grid;
   const bool t = tunable(c);
   v[0] = t ? g.head_variant : 0;
@@ -1216,6 +1223,10 @@ static void get_variants(const emrkc_ctx *c, int *v) {
 }
 
 static int check_variants(const emrkc_ctx *c, const int *v) {
+  if (c->batch) {
+    if (v[0] < 0 || v[0] > 2) return EMRKC_EINVAL;
+    return (v[1] | v[2] | v[3] | v[4]) == 0 ? EMRKC_OK : EMRKC_EUNSUPPORTED;
+  }
   if (v[4] < 0 || v[4] > 1 || (v[4] == 1 && !fusable(c))) return EMRKC_EUNSUPPORTED;
   if (!tunable(c)) return (v[0] | v[1] | v[2] | v[3]) == 0 ? EMRKC_OK : EMRKC_EUNSUPPORTED;
   const int n2 = (int)c->mesh.grid.n2;
@@ -1231,6 +1242,11 @@ static int check_variants(const emrkc_ctx *c, const int *v) {
 }
 
 static void set_variants(emrkc_ctx *c, const int *v) {
+  if (c->batch) {
+    c->batch_shape = v[0];
+    clear_graphs(c);
+    return;
+  }
   if (tunable(c)) {
     Grid &g = c->mesh.grid;
     g.head_variant = v[0];
@@ -1287,6 +1303,41 @@ static int time_classes(emrkc_ctx *c, emrkc_state *st, const StepPlan &P, double
   return EMRKC_OK;
 }
 
+// Batched ensembles: the three tile shapes, compared by the time per step
+// (one head launch and m_max - 1 inner launches).
+static int autotune_batch(emrkc_ctx *c, const emrkc_state *st, double dt, int reps, const StepPlan &P,
+                          int *variants) {
+  int orig[5];
+  get_variants(c, orig);
+  StateCopy cp;
+  int rc = copy_state(c, st, cp);
+  if (rc != EMRKC_OK) return rc;
+  const bool verbose = getenv("EMRKC_VERBOSE") != nullptr;
+  double best = 1e300;
+  int choice = orig[0];
+  for (int shape = 0; shape < 3 && rc == EMRKC_OK; ++shape) {
+    const int v[5] = {shape, 0, 0, 0, 0};
+    set_variants(c, v);
+    if ((rc = build_batch_tables(c, &cp.st, dt, P)) != EMRKC_OK) break;
+    double ms[3];
+    if ((rc = time_classes(c, &cp.st, P, dt, reps, ms)) != EMRKC_OK) break;
+    const double step = ms[0] + (P.m - 1) * ms[1];
+    if (verbose)
+      fprintf(stderr, "emrkc_autotune: batch tiles %d: head %.5f ms, inner %.5f ms, step %.5f ms\n", shape, ms[0],
+              ms[1], step);
+    if (step < 0.97 * best) {
+      best = step;
+      choice = shape;
+    }
+  }
+  (void)hipStreamSynchronize(c->stream);
+  const int v[5] = {rc == EMRKC_OK ? choice : orig[0], 0, 0, 0, 0};
+  set_variants(c, v);
+  c->bdev.valid = false;  // the tables point into the state copy
+  if (rc == EMRKC_OK && variants) get_variants(c, variants);
+  return rc;
+}
+
 extern "C" int emrkc_autotune(emrkc_ctx *c, const emrkc_state *st, double dt, int reps, int *variants) {
   if (c == nullptr) return EMRKC_EINVAL;
   if (!state_ok(c, st)) return fail(c, EMRKC_EINVAL, "state buffers missing");
@@ -1295,6 +1346,7 @@ extern "C" int emrkc_autotune(emrkc_ctx *c, const emrkc_state *st, double dt, in
   StepPlan P;
   int rc = make_plan(c, dt, P);
   if (rc != EMRKC_OK) return rc;
+  if (c->batch) return autotune_batch(c, st, dt, reps, P, variants);
   const bool fuse_ok = fusable(c) && P.s == 1 && P.m >= 2;
   if (!tunable(c) && !fuse_ok) return emrkc_get_variants(c, variants);
   // shape candidates (3-D grids): 3-D tiles, and z-marching columns of zc
@@ -1979,7 +2031,9 @@ static int estimate_batch(emrkc_ctx *c, const emrkc_state *st, double *rho_F, do
 static int build_batch_tables(emrkc_ctx *c, const emrkc_state *st, double dt, const StepPlan &P) {
   uint64_t dtb;
   memcpy(&dtb, &dt, sizeof dtb);
-  if (c->bdev.valid && c->bdev.dt_bits == dtb && c->bdev.V == st->V && c->bdev.z == st->z) return EMRKC_OK;
+  if (c->bdev.valid && c->bdev.dt_bits == dtb && c->bdev.V == st->V && c->bdev.z == st->z &&
+      c->bdev.shape == c->batch_shape)
+    return EMRKC_OK;
   (void)hipStreamSynchronize(c->stream);
   clear_graphs(c);
   free_batch_tables(c);
@@ -2006,7 +2060,7 @@ static int build_batch_tables(emrkc_ctx *c, const emrkc_state *st, double dt, co
         b.g = I.mesh.grid;
         b.off = I.off;
         b.tile0 = (uint32_t)map.size();
-        const uint32_t nt = grid_tiles(b.g, b.ntx, b.nty);
+        const uint32_t nt = grid_tiles(b.g, b.ntx, b.nty, c->batch_shape);
         if (k == 1) {
           HeadArgs &h = b.h;
           h.Vin = X[par];
@@ -2061,6 +2115,7 @@ static int build_batch_tables(emrkc_ctx *c, const emrkc_state *st, double dt, co
   }
   c->bdev.valid = true;
   c->bdev.dt_bits = dtb;
+  c->bdev.shape = c->batch_shape;
   c->bdev.V = st->V;
   c->bdev.z = st->z;
   c->bdev.s = P.s;
@@ -2079,9 +2134,9 @@ static int enqueue_chunk_batch(emrkc_ctx *c, const emrkc_state *st, const StepPl
   for (int n = 0; n < L; ++n) {
     const int par = n % 2;
     const BatchLaunch &H = c->bdev.head[par];
-    TIMED(0, launch_head_batch(c->model, c->mixed, H.tab, H.map, H.nblocks, Ntot, n, strm));
+    TIMED(0, launch_head_batch(c->model, c->mixed, c->batch_shape, H.tab, H.map, H.nblocks, Ntot, n, strm));
     for (const BatchLaunch &B : c->bdev.inner[par])
-      if (B.nblocks) TIMED(1, launch_inner_batch(c->mixed, B.tab, B.map, B.nblocks, Ntot, strm));
+      if (B.nblocks) TIMED(1, launch_inner_batch(c->mixed, c->batch_shape, B.tab, B.map, B.nblocks, Ntot, strm));
   }
   double *X1 = c->d_V1;
   HIP_TRY(c, launch_copy_tick(L % 2 ? X1 : nullptr, (double *)st->V, Ntot, c->d_clock, L, strm));

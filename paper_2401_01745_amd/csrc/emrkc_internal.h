@@ -145,11 +145,12 @@ constexpr int MX = 32, MY = 8;
 // Events recorded by the next kernel launches of this thread around the
 // kernel's execution (profiling); nullptr to stop.
 void set_launch_events(hipEvent_t start, hipEvent_t stop);
-// Tiles of a grid in the LDS-tiled layout (3-D 16x4x4, 2-D 64x4).
-uint32_t grid_tiles(const Grid &g, uint32_t &ntx, uint32_t &nty);
-hipError_t launch_head_batch(int model, bool mixed, const BatchInst *tab, const uint16_t *map, uint32_t nblocks,
-                             uint32_t Ntot, int step_off, hipStream_t st);
-hipError_t launch_inner_batch(bool mixed, const BatchInst *tab, const uint16_t *map, uint32_t nblocks,
+// Tiles of a grid in the LDS-tiled layout of tile shape `shape` (0: 3-D
+// 16x4x4 / 2-D 64x4, 1: 32x4x2 / 32x8, 2: 8x8x4 / 128x2).
+uint32_t grid_tiles(const Grid &g, uint32_t &ntx, uint32_t &nty, int shape = 0);
+hipError_t launch_head_batch(int model, bool mixed, int shape, const BatchInst *tab, const uint16_t *map,
+                             uint32_t nblocks, uint32_t Ntot, int step_off, hipStream_t st);
+hipError_t launch_inner_batch(bool mixed, int shape, const BatchInst *tab, const uint16_t *map, uint32_t nblocks,
                               uint32_t Ntot, hipStream_t st);
 hipError_t launch_init_state(int model, bool mixed, uint32_t N, double *V, void *z, ModelParams mp,
                              hipStream_t st);

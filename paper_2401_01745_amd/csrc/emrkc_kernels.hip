@@ -418,11 +418,16 @@ __global__ __launch_bounds__(kBlock) void k_mrkc_rhs(int which, Mesh mesh, uint3
 // the tile's own nodes with f_F(V^n) taken from LDS.  The arithmetic is the
 // same as k_inner (last) followed by k_head.
 // ---------------------------------------------------------------------------
-template <int DIM>
+// Tile shapes of 256 nodes: SH = 0 (the default) 16x4x4 / 64x4, SH = 1
+// 32x4x2 / 32x8, SH = 2 8x8x4 / 128x2 (3-D / 2-D).
+template <int DIM, int SH = 0>
 struct Tile {
-  static constexpr int TX = DIM == 3 ? 16 : 64, TY = 4, TZ = DIM == 3 ? 4 : 1;
+  static constexpr int TX = DIM == 3 ? (SH == 0 ? 16 : SH == 1 ? 32 : 8) : (SH == 0 ? 64 : SH == 1 ? 32 : 128);
+  static constexpr int TY = DIM == 3 ? (SH == 2 ? 8 : 4) : (SH == 0 ? 4 : SH == 1 ? 8 : 2);
+  static constexpr int TZ = DIM == 3 ? (SH == 1 ? 2 : 4) : 1;
   static constexpr int SX = TX + 2, SY = TY + 2, SZ = DIM == 3 ? TZ + 2 : 1;
   static constexpr int NS = SX * SY * SZ;
+  static_assert(TX * TY * TZ == kBlock, "one node per thread");
 };
 
 __device__ __forceinline__ uint32_t mirror_any(int c, uint32_t n) {
@@ -473,9 +478,9 @@ __global__ __launch_bounds__(kBlock) void k_fused(FusedArgs a, Grid g, uint32_t 
 // evaluates the stencil from LDS; the arithmetic is the same as the flat
 // kernels'.
 // ---------------------------------------------------------------------------
-template <int DIM>
+template <int DIM, int SH = 0>
 __device__ __forceinline__ void tile_origin(uint32_t ntx, uint32_t nty, int &x0, int &y0, int &z0) {
-  using T = Tile<DIM>;
+  using T = Tile<DIM, SH>;
   const uint32_t b = xcd_block(blockIdx.x, gridDim.x);
   const uint32_t bx = b % ntx, byz = b / ntx;
   const uint32_t by = byz % nty, bz = byz / nty;
@@ -484,10 +489,10 @@ __device__ __forceinline__ void tile_origin(uint32_t ntx, uint32_t nty, int &x0,
   z0 = (int)(bz * T::TZ);
 }
 
-template <int DIM>
+template <int DIM, int SH = 0>
 __device__ __forceinline__ void stage_halo(double *sU, const double *__restrict__ u, const Grid &g, int x0, int y0,
                                            int z0) {
-  using T = Tile<DIM>;
+  using T = Tile<DIM, SH>;
   for (int r = threadIdx.x; r < T::NS; r += kBlock) {
     const int hx = r % T::SX, hy = (r / T::SX) % T::SY, hz = r / (T::SX * T::SY);
     const uint32_t gx = mirror_any(x0 + hx - 1, g.n0);
@@ -499,9 +504,9 @@ __device__ __forceinline__ void stage_halo(double *sU, const double *__restrict_
 
 // Own node of this thread in the tile: global index (or false when outside
 // the grid) and the LDS index of the node's centre.
-template <int DIM>
+template <int DIM, int SH = 0>
 __device__ __forceinline__ bool tile_node(const Grid &g, int x0, int y0, int z0, uint32_t &i, int &c) {
-  using T = Tile<DIM>;
+  using T = Tile<DIM, SH>;
   const int lx = threadIdx.x % T::TX, ly = (threadIdx.x / T::TX) % T::TY, lz = threadIdx.x / (T::TX * T::TY);
   const uint32_t gx = (uint32_t)(x0 + lx), gy = (uint32_t)(y0 + ly), gz = (uint32_t)(z0 + lz);
   if (gx >= g.n0 || gy >= g.n1 || (DIM == 3 && gz >= g.n2)) return false;
@@ -510,9 +515,9 @@ __device__ __forceinline__ bool tile_node(const Grid &g, int x0, int y0, int z0,
   return true;
 }
 
-template <int DIM, bool MIXED>
+template <int DIM, bool MIXED, int SH = 0>
 __device__ __forceinline__ double lds_stencil(const double *sU, const Grid &g, int c) {
-  using T = Tile<DIM>;
+  using T = Tile<DIM, SH>;
   return grid_stencil<DIM, MIXED>(g.w, [&](int dx, int dy, int dz) {
     return sU[c + (DIM == 3 ? dz * T::SX * T::SY : 0) + dy * T::SX + dx];
   });
@@ -898,9 +903,9 @@ __global__ __launch_bounds__(kBlock) void k_head_march_lds(HeadArgs a, Grid g, u
 // instance; each block finds its instance through a block map and runs the
 // LDS-tiled head or inner stage with that instance's grid and coefficients.
 // ---------------------------------------------------------------------------
-template <int DIM>
+template <int DIM, int SH>
 __device__ __forceinline__ void tile_xyz(const BatchInst &I, uint32_t tile, int &x0, int &y0, int &z0) {
-  using T = Tile<DIM>;
+  using T = Tile<DIM, SH>;
   const uint32_t bx = tile % I.ntx, byz = tile / I.ntx;
   const uint32_t by = byz % I.nty, bz = byz / I.nty;
   x0 = (int)(bx * T::TX);
@@ -908,61 +913,64 @@ __device__ __forceinline__ void tile_xyz(const BatchInst &I, uint32_t tile, int 
   z0 = (int)(bz * T::TZ);
 }
 
-template <template <class> class Model, bool MIXED, int DIM>
+template <template <class> class Model, bool MIXED, int DIM, int SH>
 __device__ __forceinline__ void head_tile(const BatchInst &I, const HeadArgs &h, uint32_t tile, double *sV,
                                           uint32_t Ntot) {
   int x0, y0, z0;
-  tile_xyz<DIM>(I, tile, x0, y0, z0);
-  stage_halo<DIM>(sV, h.Vin + I.off, I.g, x0, y0, z0);
+  tile_xyz<DIM, SH>(I, tile, x0, y0, z0);
+  stage_halo<DIM, SH>(sV, h.Vin + I.off, I.g, x0, y0, z0);
   __syncthreads();
   uint32_t i;
   int c;
-  if (!tile_node<DIM>(I.g, x0, y0, z0, i, c)) return;
-  head_node<Model, MIXED>(h, Ntot, I.off + i, sV[c], [&]() { return lds_stencil<DIM, MIXED>(sV, I.g, c); });
+  if (!tile_node<DIM, SH>(I.g, x0, y0, z0, i, c)) return;
+  head_node<Model, MIXED>(h, Ntot, I.off + i, sV[c], [&]() { return lds_stencil<DIM, MIXED, SH>(sV, I.g, c); });
 }
 
-constexpr int kBatchLds = Tile<3>::NS > Tile<2>::NS ? Tile<3>::NS : Tile<2>::NS;
+template <int SH>
+struct BatchLds {
+  static constexpr int NS = Tile<3, SH>::NS > Tile<2, SH>::NS ? Tile<3, SH>::NS : Tile<2, SH>::NS;
+};
 
-template <template <class> class Model, bool MIXED>
+template <template <class> class Model, bool MIXED, int SH>
 __global__ __launch_bounds__(kBlock) void k_head_batch(const BatchInst *__restrict__ tab,
                                                        const uint16_t *__restrict__ map, uint32_t Ntot, int step_off) {
-  __shared__ double sV[kBatchLds];
+  __shared__ double sV[BatchLds<SH>::NS];
   const uint32_t lb = xcd_block(blockIdx.x, gridDim.x);
   const BatchInst &I = tab[map[lb]];
   HeadArgs h = I.h;
   h.step_off = step_off;
   if (I.g.dim == 3)
-    head_tile<Model, MIXED, 3>(I, h, lb - I.tile0, sV, Ntot);
+    head_tile<Model, MIXED, 3, SH>(I, h, lb - I.tile0, sV, Ntot);
   else
-    head_tile<Model, MIXED, 2>(I, h, lb - I.tile0, sV, Ntot);
+    head_tile<Model, MIXED, 2, SH>(I, h, lb - I.tile0, sV, Ntot);
 }
 
-template <bool MIXED, int DIM>
+template <bool MIXED, int DIM, int SH>
 __device__ __forceinline__ void inner_tile(const BatchInst &I, uint32_t tile, double *sU) {
   int x0, y0, z0;
-  tile_xyz<DIM>(I, tile, x0, y0, z0);
+  tile_xyz<DIM, SH>(I, tile, x0, y0, z0);
   const InnerArgs &a = I.in;
-  stage_halo<DIM>(sU, a.t.uprev + I.off, I.g, x0, y0, z0);
+  stage_halo<DIM, SH>(sU, a.t.uprev + I.off, I.g, x0, y0, z0);
   __syncthreads();
   uint32_t il;
   int c;
-  if (!tile_node<DIM>(I.g, x0, y0, z0, il, c)) return;
+  if (!tile_node<DIM, SH>(I.g, x0, y0, z0, il, c)) return;
   const uint32_t i = I.off + il;
-  const double Fu = lds_stencil<DIM, MIXED>(sU, I.g, c);
+  const double Fu = lds_stencil<DIM, MIXED, SH>(sU, I.g, c);
   const double uk = inner_value(a.t, Fu, load_sv(a.t.SV, MIXED, i), i);
   a.out[i] = a.last ? tail_from_um(a.t, uk, i) : uk;
 }
 
-template <bool MIXED>
+template <bool MIXED, int SH>
 __global__ __launch_bounds__(kBlock) void k_inner_batch(const BatchInst *__restrict__ tab,
                                                         const uint16_t *__restrict__ map) {
-  __shared__ double sU[kBatchLds];
+  __shared__ double sU[BatchLds<SH>::NS];
   const uint32_t lb = xcd_block(blockIdx.x, gridDim.x);
   const BatchInst &I = tab[map[lb]];
   if (I.g.dim == 3)
-    inner_tile<MIXED, 3>(I, lb - I.tile0, sU);
+    inner_tile<MIXED, 3, SH>(I, lb - I.tile0, sU);
   else
-    inner_tile<MIXED, 2>(I, lb - I.tile0, sU);
+    inner_tile<MIXED, 2, SH>(I, lb - I.tile0, sU);
 }
 
 __global__ void k_clock_set(Clock *c, int64_t step, double t0) {
@@ -1173,9 +1181,9 @@ static inline uint32_t blocks_for(uint64_t n) { return (uint32_t)((n + kBlock - 
 
 uint32_t reduce_blocks(uint32_t n) { return blocks_for(n); }
 
-template <int DIM>
+template <int DIM, int SH = 0>
 static dim3 tile_grid(const Grid &g, uint32_t &ntx, uint32_t &nty) {
-  using T = Tile<DIM>;
+  using T = Tile<DIM, SH>;
   ntx = (g.n0 + T::TX - 1) / T::TX;
   nty = (g.n1 + T::TY - 1) / T::TY;
   const uint32_t ntz = DIM == 3 ? (g.n2 + T::TZ - 1) / T::TZ : 1;
@@ -1399,35 +1407,55 @@ hipError_t launch_inner(bool mixed, const Mesh &mesh, const InnerArgs &a, hipStr
 
 bool fused_supported(const Mesh &mesh) { return mesh.kind == kGrid; }
 
-uint32_t grid_tiles(const Grid &g, uint32_t &ntx, uint32_t &nty) {
-  return g.dim == 3 ? tile_grid<3>(g, ntx, nty).x : tile_grid<2>(g, ntx, nty).x;
+uint32_t grid_tiles(const Grid &g, uint32_t &ntx, uint32_t &nty, int shape) {
+  if (g.dim == 3)
+    return shape == 1 ? tile_grid<3, 1>(g, ntx, nty).x
+                      : shape == 2 ? tile_grid<3, 2>(g, ntx, nty).x : tile_grid<3, 0>(g, ntx, nty).x;
+  return shape == 1 ? tile_grid<2, 1>(g, ntx, nty).x
+                    : shape == 2 ? tile_grid<2, 2>(g, ntx, nty).x : tile_grid<2, 0>(g, ntx, nty).x;
 }
 
-template <template <class> class Model>
-static hipError_t head_batch_dispatch(bool mixed, const BatchInst *tab, const uint16_t *map, uint32_t nb,
-                                      uint32_t Ntot, int step_off, hipStream_t st) {
+template <template <class> class Model, int SH>
+static hipError_t head_batch_launch(bool mixed, const BatchInst *tab, const uint16_t *map, uint32_t nb,
+                                    uint32_t Ntot, int step_off, hipStream_t st) {
   if (mixed)
-    EMRKC_LAUNCH((k_head_batch<Model, true>), dim3(nb), dim3(kBlock), 0, st, tab, map, Ntot, step_off);
+    EMRKC_LAUNCH((k_head_batch<Model, true, SH>), dim3(nb), dim3(kBlock), 0, st, tab, map, Ntot, step_off);
   else
-    EMRKC_LAUNCH((k_head_batch<Model, false>), dim3(nb), dim3(kBlock), 0, st, tab, map, Ntot, step_off);
+    EMRKC_LAUNCH((k_head_batch<Model, false, SH>), dim3(nb), dim3(kBlock), 0, st, tab, map, Ntot, step_off);
   return hipGetLastError();
 }
 
-hipError_t launch_head_batch(int model, bool mixed, const BatchInst *tab, const uint16_t *map, uint32_t nblocks,
-                             uint32_t Ntot, int step_off, hipStream_t st) {
-#define CALL(M) head_batch_dispatch<M>(mixed, tab, map, nblocks, Ntot, step_off, st)
+template <template <class> class Model>
+static hipError_t head_batch_dispatch(bool mixed, int shape, const BatchInst *tab, const uint16_t *map, uint32_t nb,
+                                      uint32_t Ntot, int step_off, hipStream_t st) {
+  if (shape == 1) return head_batch_launch<Model, 1>(mixed, tab, map, nb, Ntot, step_off, st);
+  if (shape == 2) return head_batch_launch<Model, 2>(mixed, tab, map, nb, Ntot, step_off, st);
+  return head_batch_launch<Model, 0>(mixed, tab, map, nb, Ntot, step_off, st);
+}
+
+hipError_t launch_head_batch(int model, bool mixed, int shape, const BatchInst *tab, const uint16_t *map,
+                             uint32_t nblocks, uint32_t Ntot, int step_off, hipStream_t st) {
+#define CALL(M) head_batch_dispatch<M>(mixed, shape, tab, map, nblocks, Ntot, step_off, st)
   EMRKC_MODEL_SWITCH(model, CALL)
 #undef CALL
 }
 
-hipError_t launch_inner_batch(bool mixed, const BatchInst *tab, const uint16_t *map, uint32_t nblocks,
+template <int SH>
+static hipError_t inner_batch_launch(bool mixed, const BatchInst *tab, const uint16_t *map, uint32_t nblocks,
+                                     hipStream_t st) {
+  if (mixed)
+    EMRKC_LAUNCH((k_inner_batch<true, SH>), dim3(nblocks), dim3(kBlock), 0, st, tab, map);
+  else
+    EMRKC_LAUNCH((k_inner_batch<false, SH>), dim3(nblocks), dim3(kBlock), 0, st, tab, map);
+  return hipGetLastError();
+}
+
+hipError_t launch_inner_batch(bool mixed, int shape, const BatchInst *tab, const uint16_t *map, uint32_t nblocks,
                               uint32_t Ntot, hipStream_t st) {
   (void)Ntot;
-  if (mixed)
-    EMRKC_LAUNCH((k_inner_batch<true>), dim3(nblocks), dim3(kBlock), 0, st, tab, map);
-  else
-    EMRKC_LAUNCH((k_inner_batch<false>), dim3(nblocks), dim3(kBlock), 0, st, tab, map);
-  return hipGetLastError();
+  if (shape == 1) return inner_batch_launch<1>(mixed, tab, map, nblocks, st);
+  if (shape == 2) return inner_batch_launch<2>(mixed, tab, map, nblocks, st);
+  return inner_batch_launch<0>(mixed, tab, map, nblocks, st);
 }
 
 template <template <class> class Model>
