@@ -216,7 +216,7 @@ int emrkc_ell_width(const emrkc_ctx *ctx);
 const char *emrkc_last_error(const emrkc_ctx *ctx);
 
 /* Writes the model's uniform resting state (V and every z) into the state
- * buffers; sets t = t0 and leaves step unchanged. */
+ * buffers and restarts its clock: step = 0, t = t0. */
 int emrkc_init_state(emrkc_ctx *ctx, emrkc_state *state);
 
 /* Spectral radii of the Jacobians of f_F and f_S at `state` by the nonlinear
@@ -303,6 +303,27 @@ int emrkc_eval_mrkc_terms(emrkc_ctx *ctx, const emrkc_state *state, double t, in
  * radii (stable only for dt below the explicit limit of the diffusion).
  * Single contexts; same state layout and stream semantics as emrkc_step. */
 int emrkc_exexrl_step(emrkc_ctx *ctx, emrkc_state *state, double dt, int64_t nsteps);
+
+/* nsteps steps of IMEX-RL (algorithm "One step of the IMEX-RL method" of the
+ * numerical experiments): z as in emrkc_exexrl_step, then V^{n+1} from the
+ * implicit diffusion line
+ *   (I - dt F) V^{n+1} = V^n + dt Cm^{-1}(I_stim(t_n) - I_ion(V^n, z^{n+1})),
+ * F = (chi Cm M_L)^{-1} A with the lumped mass M_L.  The system is solved by
+ * conjugate gradients in the M_L-weighted inner product (in which I - dt F is
+ * symmetric positive definite), Jacobi preconditioned, started from V^n and
+ * stopped when the preconditioned residual norm falls below 1e-13 times that
+ * of the right-hand side; the solve is always in double precision.  Needs no
+ * radii and is stable for any dt.  The host reads two reduced scalars per
+ * iteration (a synchronisation each); V is updated in place and the context's
+ * work vectors hold the solver's vectors.  Allocates the lumped mass (grids)
+ * and the solver's extra vectors on first use.  Returns EMRKC_ENOCONV when a
+ * solve takes more than 2000 iterations (the state is then part-way through
+ * that step).  Single contexts; same state layout as emrkc_step. */
+int emrkc_imexrl_step(emrkc_ctx *ctx, emrkc_state *state, double dt, int64_t nsteps);
+
+/* Conjugate-gradient iterations summed over the steps of the last
+ * emrkc_imexrl_step call; -1 for NULL. */
+int64_t emrkc_imexrl_iterations(const emrkc_ctx *ctx);
 
 /* ---- kernel shapes --------------------------------------------------------
  * variants[5] = {head kernel, head planes per column, inner kernel, inner

@@ -30,14 +30,21 @@ def exexrl_run(prob, y0, t0, dt, nsteps):
     return y
 
 
-def imexrl_step(tn, y, dt, prob):
+def imexrl_matrix(dt, prob):
+    """I - dt F with F = (chi Cm M_L)^{-1} A (sparse, CSC)."""
+    import scipy.sparse as sp
+    Fm = sp.diags(1.0 / (prob.chi * prob.Cm * prob.ML)) @ prob.A
+    return (sp.identity(prob.N, format="csr") - dt * Fm).tocsc()
+
+
+def imexrl_step(tn, y, dt, prob, solve=None):
     """IMEX-RL (algorithm "One step of the IMEX-RL method"): the gates and
     the other ionic variables as in EXEX-RL, then V^{n+1} from the linear
     system Cm M (V^{n+1} - V^n)/dt = chi^{-1} A V^{n+1} + M (I_stim(t_n) -
     I_ion(V^n, z^{n+1})), i.e. (I - dt F) V^{n+1} = V^n + dt S with the
     lumped mass, F = (chi Cm M_L)^{-1} A and S = Cm^{-1}(I_stim - I_ion);
-    solved with a sparse direct solver."""
-    import scipy.sparse as sp
+    solved with a sparse direct solver (`solve`, a factorisation of
+    I - dt F for this dt, else a fresh solve)."""
     import scipy.sparse.linalg as spla
     V, zE, zS = prob.split(y)
     LE, zinf = prob.model.gates(V)
@@ -45,14 +52,15 @@ def imexrl_step(tn, y, dt, prob):
     zS1 = zS + dt * prob.model.g_S(V, zE1, zS) if prob.nS else zS
     I_ion = prob.Cm * prob.model.i_ion(V, zE1, zS1)
     rhs = V + dt * (prob.I_stim(tn) - I_ion) / prob.Cm
-    Fm = sp.diags(1.0 / (prob.chi * prob.Cm * prob.ML)) @ prob.A
-    B = (sp.identity(prob.N, format="csr") - dt * Fm).tocsc()
-    V1 = spla.spsolve(B, rhs)
+    V1 = solve(rhs) if solve is not None else spla.spsolve(imexrl_matrix(dt, prob), rhs)
     return np.concatenate([V1, zE1.reshape(-1), np.asarray(zS1).reshape(-1)])
 
 
 def imexrl_run(prob, y0, t0, dt, nsteps):
+    """nsteps IMEX-RL steps; I - dt F is factorised once (sparse LU)."""
+    import scipy.sparse.linalg as spla
+    solve = spla.splu(imexrl_matrix(dt, prob)).solve
     y = np.array(y0, dtype=np.float64, copy=True)
     for n in range(nsteps):
-        y = imexrl_step(t0 + n * dt, y, dt, prob)
+        y = imexrl_step(t0 + n * dt, y, dt, prob, solve)
     return y

@@ -107,6 +107,11 @@ struct emrkc_ctx {
   int rho_every = 0;          // params.rho_every
   int method = EMRKC_METHOD_EMRKC;
   int batch_shape = 0;        // tile shape of the batched kernels (0..2)
+  double *d_ML = nullptr;     // lumped mass (tets at creation, grids on first IMEX-RL step)
+  double *d_cgq = nullptr;    // IMEX-RL: the conjugate gradient's B p
+  double *d_Dsum = nullptr;   // IMEX-RL on tets: row sums of the operator's weights
+  double grid_dsum = 0.0;     // IMEX-RL on grids: the same sum (one value for every node)
+  int64_t cg_iters = 0;       // conjugate-gradient iterations of the last emrkc_imexrl_step
   // mRKC: gate-0 inner buffers, and full-state vectors of its power iteration
   double *d_W[2] = {nullptr, nullptr};
   double *d_Y = nullptr, *d_FY = nullptr, *d_Wv = nullptr, *d_FW = nullptr;
@@ -374,7 +379,7 @@ static void free_ctx(emrkc_ctx *c) {
                   c->d_U[2], c->d_SV, c->d_SV2,   c->d_z1,      c->d_clock,   c->d_partials, c->d_result, c->d_flag,
                   c->d_vF[0], c->d_vF[1], c->d_vS[0], c->d_vS[1], c->d_zV,
                   c->d_W[0], c->d_W[1], c->d_Y, c->d_FY, c->d_Wv, c->d_FW,
-                  c->d_mv[0][0], c->d_mv[0][1], c->d_mv[1][0], c->d_mv[1][1], c->d_mpart};
+                  c->d_mv[0][0], c->d_mv[0][1], c->d_mv[1][0], c->d_mv[1][1], c->d_mpart, c->d_ML, c->d_cgq, c->d_Dsum};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   if (c->capture) (void)hipStreamDestroy(c->capture);
@@ -592,6 +597,7 @@ extern "C" int emrkc_init_state(emrkc_ctx *c, emrkc_state *s) {
   if (c == nullptr) return EMRKC_EINVAL;
   if (!state_ok(c, s)) return fail(c, EMRKC_EINVAL, "state buffers missing");
   HIP_TRY(c, launch_init_state(c->model, c->mixed, (uint32_t)c->N, (double *)s->V, s->z, c->mp, c->stream));
+  s->step = 0;
   s->t = s->t0;
   return EMRKC_OK;
 }
@@ -1100,6 +1106,113 @@ static int enqueue_chunk_exexrl(emrkc_ctx *c, const emrkc_state *st, double dt, 
   HIP_TRY(c, launch_copy_tick(L % 2 ? X[1] : nullptr, X[0], (uint32_t)c->N, c->d_clock, L, strm));
   return EMRKC_OK;
 }
+
+// ---------------------------------------------------------------------------
+// IMEX-RL stepping: the pointwise part as in EXEX-RL, then the implicit
+// diffusion line (I - dt F) V^{n+1} = V^n + dt S by conjugate gradients in
+// the lumped-mass inner product (I - dt F is self-adjoint there), Jacobi
+// preconditioned, from V^n.
+// ---------------------------------------------------------------------------
+static int fetch(emrkc_ctx *c, double *out);
+
+constexpr double kCgTol = 1e-13;
+constexpr int kCgMaxIter = 2000;
+
+static int ensure_imexrl_data(emrkc_ctx *c) {
+  int rc;
+  if (!c->d_cgq && (rc = dalloc(c, (void **)&c->d_cgq, sizeof(double) * (size_t)c->N))) return rc;
+  if (c->mesh.kind == kEll) {
+    if (!c->d_ML) return fail(c, EMRKC_EUNSUPPORTED, "lumped mass missing");
+    if (!c->d_Dsum) {
+      if ((rc = dalloc(c, (void **)&c->d_Dsum, sizeof(double) * (size_t)c->N))) return rc;
+      HIP_TRY(c, launch_ell_rowsum(c->mesh.ell, c->d_Dsum, c->stream));
+    }
+    return EMRKC_OK;
+  }
+  const Grid &g = c->mesh.grid;
+  // every node of the tensor grid has the full set of neighbour offsets
+  // (boundary neighbours mirrored): 2 per axis, 4 per face diagonal, 8 corners
+  c->grid_dsum = c->dim == 3 ? 2 * (g.w[0] + g.w[1] + g.w[2]) + 4 * (g.w[3] + g.w[4] + g.w[5]) + 8 * g.w[6]
+                             : 2 * (g.w[0] + g.w[1]) + 4 * g.w[3];
+  if (c->d_ML) return EMRKC_OK;
+  // lumped mass of the tensor grid: product over the axes of h (interior
+  // node) or h/2 (end node)
+  std::vector<double> ML((size_t)c->N);
+  const uint32_t n[3] = {g.n0, g.n1, g.n2};
+  for (uint32_t k = 0; k < n[2]; ++k)
+    for (uint32_t j = 0; j < n[1]; ++j)
+      for (uint32_t i = 0; i < n[0]; ++i) {
+        const uint32_t ix[3] = {i, j, k};
+        double m = 1.0;
+        for (int d = 0; d < c->dim; ++d) m *= c->h[d] * ((ix[d] == 0 || ix[d] == n[d] - 1) ? 0.5 : 1.0);
+        ML[i + (size_t)n[0] * (j + (size_t)n[1] * k)] = m;
+      }
+  if ((rc = dalloc(c, (void **)&c->d_ML, ML.size() * sizeof(double)))) return rc;
+  HIP_TRY(c, hipMemcpy(c->d_ML, ML.data(), ML.size() * sizeof(double), hipMemcpyHostToDevice));
+  return EMRKC_OK;
+}
+
+static int fetch2(emrkc_ctx *c, double *out) {
+  HIP_TRY(c, hipMemcpyAsync(out, c->d_result, 2 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  return EMRKC_OK;
+}
+
+extern "C" int emrkc_imexrl_step(emrkc_ctx *c, emrkc_state *st, double dt, int64_t nsteps) {
+  if (c == nullptr) return EMRKC_EINVAL;
+  if (!state_ok(c, st)) return fail(c, EMRKC_EINVAL, "state buffers missing");
+  if (!(dt > 0) || !isfinite(dt) || nsteps < 0) return fail(c, EMRKC_EINVAL, "invalid dt or nsteps");
+  if (c->batch) return fail(c, EMRKC_EUNSUPPORTED, "IMEX-RL stepping is for single contexts");
+  int rc;
+  if ((rc = ensure_imexrl_data(c)) != EMRKC_OK) return rc;
+  const uint32_t N = (uint32_t)c->N;
+  double *x = (double *)st->V, *b = c->d_U[0], *r = c->d_U[1], *zv = c->d_U[2], *p = c->d_V1, *q = c->d_cgq;
+  // stop when the preconditioned residual norm is below kCgTol times that
+  // of the right-hand side
+  const double tol2 = kCgTol * kCgTol;
+  c->cg_iters = 0;
+  for (int64_t n = 0; n < nsteps; ++n) {
+    ImexArgs a{};
+    a.V = x;
+    a.rhs = b;
+    a.z = st->z;
+    a.t = state_time(st->t0, st->step, dt);
+    a.stim = stim_args(c);
+    a.mp = c->mp;
+    a.dt = dt;
+    a.Cm = c->Cm;
+    HIP_TRY(c, launch_imexrl_pre(c->model, c->mixed, N, a, c->stream));
+    HIP_TRY(c, launch_cg_init(c->mesh, c->d_ML, c->d_Dsum, c->grid_dsum, dt, x, b, r, zv, p, c->d_partials,
+                              c->d_result, c->stream));
+    double init[2];
+    if ((rc = fetch2(c, init))) return rc;
+    double rz = init[0];
+    const double stop = tol2 * init[1];
+    int it = 0;
+    while (rz > stop) {
+      if (!isfinite(rz)) return fail(c, EMRKC_ENONFINITE, "IMEX-RL solve at step %lld: non-finite residual",
+                                     (long long)st->step);
+      if (it++ >= kCgMaxIter)
+        return fail(c, EMRKC_ENOCONV, "IMEX-RL solve at step %lld: no convergence in %d iterations",
+                    (long long)st->step, kCgMaxIter);
+      double pq, rz_new;
+      HIP_TRY(c, launch_cg_apply(c->mesh, c->d_ML, dt, p, q, c->d_partials, c->d_result, c->stream));
+      if ((rc = fetch(c, &pq))) return rc;
+      HIP_TRY(c, launch_cg_update(N, c->d_ML, c->d_Dsum, c->grid_dsum, dt, rz / pq, x, r, zv, p, q, c->d_partials,
+                                  c->d_result, c->stream));
+      if ((rc = fetch(c, &rz_new))) return rc;
+      HIP_TRY(c, launch_cg_direction(N, rz_new / rz, zv, p, c->stream));
+      rz = rz_new;
+    }
+    c->cg_iters += it;
+    st->step += 1;
+    st->t = state_time(st->t0, st->step, dt);
+  }
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  return check_finite(c, st);
+}
+
+extern "C" int64_t emrkc_imexrl_iterations(const emrkc_ctx *c) { return c ? c->cg_iters : -1; }
 
 extern "C" int emrkc_exexrl_step(emrkc_ctx *c, emrkc_state *st, double dt, int64_t nsteps) {
   if (c == nullptr) return EMRKC_EINVAL;
@@ -1823,6 +1936,9 @@ static int build_p1(emrkc_ctx *c, const emrkc_mesh *mesh, const emrkc_conductivi
   c->mesh.ell.w64 = c->d_ell_w64;
   c->mesh.ell.w32 = c->d_ell_w32;
   c->dim = 3;
+  // lumped mass, for the implicit diffusion solve of IMEX-RL
+  if ((rc = dalloc(c, (void **)&c->d_ML, ML.size() * sizeof(double)))) return rc;
+  HIP_TRY(c, hipMemcpy(c->d_ML, ML.data(), ML.size() * sizeof(double), hipMemcpyHostToDevice));
   return EMRKC_OK;
 }
 

@@ -106,6 +106,19 @@ struct ExArgs {
   double dt, Cm;
 };
 
+// The pointwise part of an IMEX-RL step: gates by Rush-Larsen and the other
+// ionic variables by explicit Euler (z updated in place), and the right-hand
+// side V^n + dt Cm^{-1}(I_stim(t) - I_ion(V^n, z^{n+1})) of the diffusion line.
+struct ImexArgs {
+  const double *V;
+  double *rhs;
+  void *z;
+  double t;
+  StimArgs stim;
+  ModelParams mp;
+  double dt, Cm;
+};
+
 // mRKC (double precision): the head of outer stage j and the inner stages
 // carry the stiffest gate (gate 0), which sits in the fast term, next to V.
 struct MrkcHeadArgs {
@@ -158,6 +171,26 @@ hipError_t launch_head(int model, bool mixed, const Mesh &mesh, const HeadArgs &
 hipError_t launch_inner(bool mixed, const Mesh &mesh, const InnerArgs &a, hipStream_t st);
 hipError_t launch_exexrl(int model, bool mixed, const Mesh &mesh, const ExArgs &a, hipStream_t st);
 hipError_t launch_mrkc_head(int model, const Mesh &mesh, const MrkcHeadArgs &a, hipStream_t st);
+hipError_t launch_imexrl_pre(int model, bool mixed, uint32_t N, const ImexArgs &a, hipStream_t st);
+// Conjugate gradients for (I - dt F) x = b in the inner product weighted by
+// the lumped mass ML, preconditioned by the diagonal 1 + dt D_i (D_i from
+// Dsum, or dconst for every node when Dsum is null).  Each launcher leaves
+// the weighted sum it computes in result[0]:
+//   init:   r = b - (x - dt F x), z = r/diag, p = z;  sum ML r z  (result[1]: sum ML b b/diag)
+//   apply:  q = p - dt F p;                           sum ML p q
+//   update: x += alpha p, r -= alpha q, z = r/diag;   sum ML r z
+hipError_t launch_cg_init(const Mesh &mesh, const double *ML, const double *Dsum, double dconst, double dt,
+                          const double *x, const double *b, double *r, double *z, double *p, double *partials,
+                          double *result, hipStream_t st);
+hipError_t launch_cg_apply(const Mesh &mesh, const double *ML, double dt, const double *p, double *q,
+                           double *partials, double *result, hipStream_t st);
+hipError_t launch_cg_update(uint32_t N, const double *ML, const double *Dsum, double dconst, double dt,
+                            double alpha, double *x, double *r, double *z, const double *p, const double *q,
+                            double *partials, double *result, hipStream_t st);
+// p = z + beta p
+hipError_t launch_cg_direction(uint32_t N, double beta, const double *z, double *p, hipStream_t st);
+// out[i] = sum of row i's ELL weights
+hipError_t launch_ell_rowsum(const Ell &e, double *out, hipStream_t st);
 hipError_t launch_mrkc_inner(int model, const Mesh &mesh, const MrkcInnerArgs &a, hipStream_t st);
 // The split terms of mRKC on a full double state y = [V | z planes]:
 // which = 0: f~_F = (f_F, gate-0 rate, 0), which = 1: f~_S = (f_S's V part,

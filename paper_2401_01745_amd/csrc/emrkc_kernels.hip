@@ -254,6 +254,45 @@ __global__ __launch_bounds__(kBlock) void k_exexrl(ExArgs a, Mesh mesh) {
   a.Vout[i] = V + a.dt * (FV + SV);
 }
 
+// IMEX-RL pointwise part: the gate and slow-variable updates of k_exexrl,
+// then the right-hand side of the implicit diffusion line instead of the
+// explicit V update.
+template <template <class> class Model, bool MIXED>
+__global__ __launch_bounds__(kBlock) void k_imexrl_pre(ImexArgs a, uint32_t N) {
+  using M = MathOf<MIXED>;
+  using R = typename M::R;
+  using Mod = Model<M>;
+  constexpr int NG = Mod::NG, NS = Mod::NS, NZ = NG + NS;
+  const uint32_t i = node_index();
+  if (i >= N) return;
+  const double V = a.V[i];
+  const double Is = stimulus(a.stim, i, a.t);
+  R *zp = (R *)a.z;
+  R z[NZ];
+#pragma unroll
+  for (int k = 0; k < NZ; ++k) z[k] = zp[(size_t)k * N + i];
+  R lam[NG], zinf[NG];
+  Mod::gates(R(V), a.mp, lam, zinf);
+  const R dt = R(a.dt);
+#pragma unroll
+  for (int g = 0; g < NG; ++g) z[g] = z[g] + M::expm1(dt * lam[g]) * (z[g] - zinf[g]);
+  R dS[NS > 0 ? NS : 1];
+  R iion = Mod::eval(R(V), z, z + NG, dS, a.mp);
+  if (NS > 0) {
+#pragma unroll
+    for (int k = 0; k < NS; ++k) z[NG + k] = z[NG + k] + dt * dS[k];
+    iion = Mod::eval(R(V), z, z + NG, dS, a.mp);
+  }
+#pragma unroll
+  for (int k = 0; k < NZ; ++k) zp[(size_t)k * N + i] = z[k];
+  double SV;
+  if (MIXED)
+    SV = (double)((R(Is) - R(a.Cm) * iion) * R(1.0 / a.Cm));
+  else
+    SV = (Is - a.Cm * (double)iion) / a.Cm;
+  a.rhs[i] = V + a.dt * SV;
+}
+
 // ---------------------------------------------------------------------------
 // Inner stages
 // ---------------------------------------------------------------------------
@@ -1087,6 +1126,91 @@ __global__ __launch_bounds__(kBlock) void k_vec_diff_norm(uint64_t n, const doub
   if (threadIdx.x == 0) partials[blockIdx.x] = v;
 }
 
+// ---------------------------------------------------------------------------
+// Conjugate gradients for (I - dt F) x = b, F = (chi Cm M_L)^{-1} A, in the
+// inner product sum_i ML_i u_i v_i (in which I - dt F is symmetric positive
+// definite), preconditioned by its diagonal 1 + dt D_i, D_i = sum of the
+// node's neighbour weights (Dsum[i], or dconst on a uniform grid).  Always
+// double precision.  Each kernel leaves per-block partial sums.
+// ---------------------------------------------------------------------------
+struct CgDiag {
+  const double *Dsum;  // nullptr: every node has dconst
+  double dconst;
+  double dt;
+  __device__ __forceinline__ double at(uint32_t i) const { return 1.0 + dt * (Dsum ? Dsum[i] : dconst); }
+};
+
+__global__ __launch_bounds__(kBlock) void k_cg_init(Mesh mesh, const double *ML, CgDiag dg, const double *x,
+                                                    const double *b, double *r, double *z, double *p,
+                                                    double *partials) {
+  const uint32_t N = mesh.kind == kGrid ? mesh.grid.N : mesh.ell.N;
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  double rz = 0.0, bb = 0.0;
+  if (i < N) {
+    const double Bx = x[i] - dg.dt * apply_op<false>(mesh, x, i);
+    const double ri = b[i] - Bx;
+    const double di = dg.at(i);
+    const double zi = ri / di;
+    r[i] = ri;
+    z[i] = zi;
+    p[i] = zi;
+    rz = ML[i] * ri * zi;
+    bb = ML[i] * b[i] * (b[i] / di);
+  }
+  rz = block_sum(rz);
+  __syncthreads();  // block_sum's LDS slots are reused by the second sum
+  bb = block_sum(bb);
+  if (threadIdx.x == 0) {
+    partials[blockIdx.x] = rz;
+    partials[gridDim.x + blockIdx.x] = bb;
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_cg_apply(Mesh mesh, const double *ML, double dt, const double *p,
+                                                     double *q, double *partials) {
+  const uint32_t N = mesh.kind == kGrid ? mesh.grid.N : mesh.ell.N;
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  double pq = 0.0;
+  if (i < N) {
+    const double qi = p[i] - dt * apply_op<false>(mesh, p, i);
+    q[i] = qi;
+    pq = ML[i] * p[i] * qi;
+  }
+  pq = block_sum(pq);
+  if (threadIdx.x == 0) partials[blockIdx.x] = pq;
+}
+
+__global__ __launch_bounds__(kBlock) void k_cg_update(uint32_t N, const double *ML, CgDiag dg, double alpha,
+                                                      double *x, double *r, double *z, const double *p,
+                                                      const double *q, double *partials) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  double rz = 0.0;
+  if (i < N) {
+    x[i] = x[i] + alpha * p[i];
+    const double ri = r[i] - alpha * q[i];
+    const double zi = ri / dg.at(i);
+    r[i] = ri;
+    z[i] = zi;
+    rz = ML[i] * ri * zi;
+  }
+  rz = block_sum(rz);
+  if (threadIdx.x == 0) partials[blockIdx.x] = rz;
+}
+
+__global__ __launch_bounds__(kBlock) void k_cg_direction(uint32_t N, double beta, const double *z, double *p) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < N) p[i] = z[i] + beta * p[i];
+}
+
+// Row sums of the ELL weights (the D_i of the preconditioner).
+__global__ __launch_bounds__(kBlock) void k_ell_rowsum(Ell e, double *out) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= e.N) return;
+  double s = 0.0;
+  for (uint32_t k = 0; k < e.width; ++k) s += e.w64[(size_t)k * e.N + i];
+  out[i] = s;
+}
+
 __global__ __launch_bounds__(kBlock) void k_powF_shift(uint32_t N, const double *yV, const double *vin,
                                                        uint64_t seed, double q, double *zV) {
   const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -1367,6 +1491,62 @@ hipError_t launch_vec_diff_norm(uint64_t n, const double *a, const double *b, do
   const uint32_t nb = (uint32_t)((n + kBlock - 1) / kBlock);
   EMRKC_LAUNCH(k_vec_diff_norm, dim3(nb), dim3(kBlock), 0, st, n, a, b, out, partials);
   EMRKC_LAUNCH(k_reduce_final, dim3(1), dim3(kBlock), 0, st, partials, nb, result);
+  return hipGetLastError();
+}
+
+template <template <class> class Model>
+static hipError_t imexrl_dispatch(bool mixed, uint32_t N, const ImexArgs &a, hipStream_t st) {
+  if (mixed)
+    EMRKC_LAUNCH((k_imexrl_pre<Model, true>), dim3(blocks_for(N)), dim3(kBlock), 0, st, a, N);
+  else
+    EMRKC_LAUNCH((k_imexrl_pre<Model, false>), dim3(blocks_for(N)), dim3(kBlock), 0, st, a, N);
+  return hipGetLastError();
+}
+
+hipError_t launch_imexrl_pre(int model, bool mixed, uint32_t N, const ImexArgs &a, hipStream_t st) {
+#define CALL(M) imexrl_dispatch<M>(mixed, N, a, st)
+  EMRKC_MODEL_SWITCH(model, CALL)
+#undef CALL
+}
+
+static inline uint32_t mesh_nodes(const Mesh &m) { return m.kind == kGrid ? m.grid.N : m.ell.N; }
+
+hipError_t launch_cg_init(const Mesh &mesh, const double *ML, const double *Dsum, double dconst, double dt,
+                          const double *x, const double *b, double *r, double *z, double *p, double *partials,
+                          double *result, hipStream_t st) {
+  const uint32_t nb = blocks_for(mesh_nodes(mesh));
+  EMRKC_LAUNCH(k_cg_init, dim3(nb), dim3(kBlock), 0, st, mesh, ML, CgDiag{Dsum, dconst, dt}, x, b, r, z, p,
+               partials);
+  EMRKC_LAUNCH(k_reduce_final, dim3(1), dim3(kBlock), 0, st, partials, nb, result);
+  EMRKC_LAUNCH(k_reduce_final, dim3(1), dim3(kBlock), 0, st, partials + nb, nb, result + 1);
+  return hipGetLastError();
+}
+
+hipError_t launch_cg_apply(const Mesh &mesh, const double *ML, double dt, const double *p, double *q,
+                           double *partials, double *result, hipStream_t st) {
+  const uint32_t nb = blocks_for(mesh_nodes(mesh));
+  EMRKC_LAUNCH(k_cg_apply, dim3(nb), dim3(kBlock), 0, st, mesh, ML, dt, p, q, partials);
+  EMRKC_LAUNCH(k_reduce_final, dim3(1), dim3(kBlock), 0, st, partials, nb, result);
+  return hipGetLastError();
+}
+
+hipError_t launch_cg_update(uint32_t N, const double *ML, const double *Dsum, double dconst, double dt,
+                            double alpha, double *x, double *r, double *z, const double *p, const double *q,
+                            double *partials, double *result, hipStream_t st) {
+  const uint32_t nb = blocks_for(N);
+  EMRKC_LAUNCH(k_cg_update, dim3(nb), dim3(kBlock), 0, st, N, ML, CgDiag{Dsum, dconst, dt}, alpha, x, r, z, p, q,
+               partials);
+  EMRKC_LAUNCH(k_reduce_final, dim3(1), dim3(kBlock), 0, st, partials, nb, result);
+  return hipGetLastError();
+}
+
+hipError_t launch_cg_direction(uint32_t N, double beta, const double *z, double *p, hipStream_t st) {
+  EMRKC_LAUNCH(k_cg_direction, dim3(blocks_for(N)), dim3(kBlock), 0, st, N, beta, z, p);
+  return hipGetLastError();
+}
+
+hipError_t launch_ell_rowsum(const Ell &e, double *out, hipStream_t st) {
+  EMRKC_LAUNCH(k_ell_rowsum, dim3(blocks_for(e.N)), dim3(kBlock), 0, st, e, out);
   return hipGetLastError();
 }
 

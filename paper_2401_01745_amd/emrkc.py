@@ -78,6 +78,8 @@ EXPORTS = {
     "emrkc_eval_elementary": (C.c_int, [C.c_int, C.c_int, C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p]),
     "emrkc_eval_mrkc_terms": (C.c_int, [C.c_void_p, C.POINTER(State), C.c_double, C.c_int, C.c_void_p]),
     "emrkc_exexrl_step": (C.c_int, [C.c_void_p, C.POINTER(State), C.c_double, C.c_int64]),
+    "emrkc_imexrl_step": (C.c_int, [C.c_void_p, C.POINTER(State), C.c_double, C.c_int64]),
+    "emrkc_imexrl_iterations": (C.c_int64, [C.c_void_p]),
     "emrkc_autotune": (C.c_int, [C.c_void_p, C.POINTER(State), C.c_double, C.c_int, C.POINTER(C.c_int)]),
     "emrkc_get_variants": (C.c_int, [C.c_void_p, C.POINTER(C.c_int)]),
     "emrkc_set_variants": (C.c_int, [C.c_void_p, C.POINTER(C.c_int)]),
@@ -254,6 +256,14 @@ def emrkc_eval_mrkc_terms(ctx, state, t, which, out):
 
 def emrkc_exexrl_step(ctx, state, dt, nsteps):
     return _check(lib().emrkc_exexrl_step(ctx, C.byref(state), dt, int(nsteps)), ctx)
+
+
+def emrkc_imexrl_step(ctx, state, dt, nsteps):
+    return _check(lib().emrkc_imexrl_step(ctx, C.byref(state), dt, int(nsteps)), ctx)
+
+
+def emrkc_imexrl_iterations(ctx):
+    return int(lib().emrkc_imexrl_iterations(ctx))
 
 
 def emrkc_autotune(ctx, state, dt, reps=3):

@@ -1,0 +1,109 @@
+"""GPU IMEX-RL (implicit diffusion line by preconditioned conjugate
+gradients) against the oracle's IMEX-RL (sparse direct solve): grid slabs of
+the three models, the tetrahedral shell, step sizes far beyond the explicit
+limit, and agreement with emRKC on a firing slab."""
+import numpy as np
+import pytest
+
+from gpu_util import rel_errors
+from oracle.exexrl import imexrl_run
+from oracle.monodomain import build_grid_problem, build_tet_problem
+from workloads.configs import small_config
+from workloads.tetmesh import build_shell, small_shell_config
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-10
+
+
+@pytest.fixture(scope="module")
+def E():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    from paper_2401_01745_amd import emrkc
+    emrkc.lib()
+    return emrkc
+
+
+def _gpu_imexrl(E, sim, dt, chunks):
+    import torch
+    E.emrkc_init_state(sim.ctx, sim.state)
+    iters = []
+    for n in chunks:
+        E.emrkc_imexrl_step(sim.ctx, sim.state, dt, n)
+        iters.append(E.emrkc_imexrl_iterations(sim.ctx))
+    torch.cuda.synchronize()
+    return sim.V.cpu().numpy().copy(), sim.z.cpu().numpy().astype(np.float64), iters
+
+
+def _check(prob, y, V, z, tol=TOL):
+    Y = y.reshape(prob.nv, prob.N)
+    l2, mx = rel_errors(V, Y[0])
+    assert l2 <= tol and mx <= tol, (l2, mx)
+    for c in range(1, prob.nv):
+        zl2, zmx = rel_errors(z[c - 1], Y[c])
+        assert zl2 <= tol and zmx <= tol, (c, zl2, zmx)
+
+
+@pytest.mark.parametrize("model,n,dt,nsteps", [("CRN_SURR", (37, 29, 11), 0.05, 80),
+                                               ("TTP_SURR", (41, 19, 9), 0.05, 80),
+                                               ("HH", (33, 33), 0.01, 100),
+                                               ("CRN_SURR", (9, 7, 5), 0.5, 12)])
+def test_imexrl_grid_parity(E, model, n, dt, nsteps):
+    base = "c1_2d_hh" if len(n) == 2 else "c2_3d_crn"
+    cfg = small_config(base, n, model=model)
+    prob = build_grid_problem(cfg)
+    y = imexrl_run(prob, prob.uniform_state(), 0.0, dt, nsteps)
+    assert np.all(np.isfinite(y))
+    sim = E.simulation_from_config(cfg)
+    V, z, iters = _gpu_imexrl(E, sim, dt, [3, nsteps - 3])
+    assert sim.state.step == nsteps
+    sim.close()
+    assert all(k > 0 for k in iters)
+    _check(prob, y, V, z)
+
+
+def test_imexrl_shell_parity(E):
+    cfg = small_shell_config()
+    mesh, mask = build_shell(cfg)
+    prob = build_tet_problem(cfg, mesh, mask)
+    dt, nsteps = 0.05, 40
+    y = imexrl_run(prob, prob.uniform_state(), 0.0, dt, nsteps)
+    sim = E.simulation_from_tet_config(cfg, mesh, mask)
+    V, z, _ = _gpu_imexrl(E, sim, dt, [nsteps])
+    sim.close()
+    _check(prob, y, V, z)
+
+
+def test_zero_steps_and_invalid_arguments(E):
+    cfg = small_config("c2_3d_crn", (9, 7, 5))
+    sim = E.simulation_from_config(cfg)
+    E.emrkc_init_state(sim.ctx, sim.state)
+    V0 = sim.V.cpu().numpy().copy()
+    E.emrkc_imexrl_step(sim.ctx, sim.state, 0.05, 0)
+    assert np.array_equal(sim.V.cpu().numpy(), V0) and sim.state.step == 0
+    for dt, n in [(0.0, 1), (-1.0, 1), (float("nan"), 1), (0.05, -1)]:
+        with pytest.raises(E.EmrkcError):
+            E.emrkc_imexrl_step(sim.ctx, sim.state, dt, n)
+    sim.close()
+
+
+def test_imexrl_next_to_emrkc(E):
+    """IMEX-RL and emRKC at dt = 0.0125 ms on a firing slab are both first
+    order: their V at T = 4 ms differ by the order of their own errors (a
+    few percent at most) and not more."""
+    import torch
+    cfg = small_config("c2_3d_crn", (81, 41, 11), model="TTP_SURR")
+    T, dt = 4.0, 0.0125
+    n = int(round(T / dt))
+    sim = E.simulation_from_config(cfg)
+    Vi, _, _ = _gpu_imexrl(E, sim, dt, [n])
+    E.emrkc_init_state(sim.ctx, sim.state)  # restarts the clock as well
+    assert sim.state.step == 0 and sim.state.t == sim.state.t0
+    E.emrkc_estimate_rho(sim.ctx, sim.state)
+    E.emrkc_step(sim.ctx, sim.state, dt, n)
+    torch.cuda.synchronize()
+    Ve = sim.V.cpu().numpy().copy()
+    sim.close()
+    assert Vi.max() > 0.0
+    assert rel_errors(Vi, Ve)[0] < 0.05
