@@ -60,6 +60,24 @@ def bytes_per_node(kind, nz, wz, m, mat=0):
         return 8 + 8 * nz + 8 * (nz - 1) + 8 + 8 + 8 + mat
     if kind == "mrkc_tail":
         return 8 + 8 + 8 + 8 + 8 + 8 + 8 + mat
+    # IMEX-RL (FP64 solve); dsum = 8 on unstructured meshes (the row sums of
+    # the preconditioner), 0 on grids (one value)
+    #   pointwise: V read, z read and written, right-hand side written
+    #   cg_init  : x, b, ML (+ D) read, r, z, p written
+    #   cg_apply : p, ML read, q written
+    #   cg_update: x, r read and written, p, q, ML (+ D) read, z written
+    #   cg_direction: z read, p read and written
+    dsum = 8 if mat else 0
+    if kind == "cg_pointwise":
+        return 8 + 2 * nz * wz + 8
+    if kind == "cg_init":
+        return 8 + 8 + 8 + dsum + 24 + mat
+    if kind == "cg_apply":
+        return 8 + 8 + 8 + mat
+    if kind == "cg_update":
+        return 16 + 16 + 8 + 8 + 8 + dsum + 8
+    if kind == "cg_direction":
+        return 8 + 16
     raise ValueError(kind)
 
 
@@ -68,20 +86,25 @@ class Job:
         from paper_2401_01745_amd import emrkc as E
         self.E = E
         self.cfg = cfg
+        # IMEX-RL is a separate entry point on a plain (emRKC) context
+        cmethod = "emrkc" if method == "imexrl" else method
         if batch is not None:
             self.sim = E.simulation_from_batch(batch, precision=precision, flags=flags)
         elif tet is not None:
             self.sim = E.simulation_from_tet_config(cfg, tet[0], tet[1], precision=precision, flags=flags,
-                                                    method=method)
+                                                    method=cmethod)
         else:
-            self.sim = E.simulation_from_config(cfg, precision=precision, flags=flags, method=method)
+            self.sim = E.simulation_from_config(cfg, precision=precision, flags=flags, method=cmethod)
         E.emrkc_set_stream(self.sim.ctx, stream.cuda_stream)
         self.nsim = int(round(cfg["T"] / cfg["dt"]))
+        self.method = method
 
     def tune(self, variants=None):
         """Kernel shapes: given, or chosen by the library's autotuner on the
         resting state (outside the timed region, like compilation)."""
         E, s = self.E, self.sim
+        if self.method == "imexrl":
+            return None
         if variants is not None:
             E.emrkc_set_variants(s.ctx, variants)
             return tuple(variants)
@@ -94,6 +117,9 @@ class Job:
         s.state.t0 = 0.0
         s.state.step = 0
         E.emrkc_init_state(s.ctx, s.state)
+        if self.method == "imexrl":
+            E.emrkc_imexrl_step(s.ctx, s.state, self.cfg["dt"], self.nsim)
+            return E.emrkc_imexrl_iterations(s.ctx)
         rF, rS, itF, itS, _ = E.emrkc_estimate_rho(s.ctx, s.state)
         E.emrkc_step(s.ctx, s.state, self.cfg["dt"], self.nsim)
         return rF, rS, itF, itS
@@ -147,8 +173,9 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
-    ap.add_argument("--method", default="emrkc", choices=["emrkc", "mrkc"],
-                    help="mrkc: the mRKC method (stiffest gate in the fast term), FP64, flat kernels")
+    ap.add_argument("--method", default="emrkc", choices=["emrkc", "mrkc", "imexrl"],
+                    help="mrkc: the mRKC method (stiffest gate in the fast term), FP64, flat kernels; "
+                         "imexrl: the IMEX-RL method (implicit diffusion by preconditioned CG), FP64")
     ap.add_argument("--variants", default=None,
                     help="kernel shapes 'head,head_planes,inner,inner_planes,fused' instead of autotuning")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
@@ -188,6 +215,14 @@ def main():
         torch.cuda.synchronize()
         log("bench: calibration copy of %d MiB done" % args.calib_copy_mib)
         del src, dst
+    if args.method == "imexrl":
+        if batch is not None:
+            print("bench.py: IMEX-RL runs single contexts only (not the ensemble)", file=sys.stderr)
+            sys.exit(2)
+        with torch.cuda.stream(stream):
+            out = bench_imexrl(args, cfg, N, tet, stream, E, torch)
+        print(json.dumps(out), flush=True)
+        return
     with torch.cuda.stream(stream):
         log("bench: %s, N=%d, building FP64 context" % (cfg["name"], N))
         flags = 0
@@ -297,6 +332,79 @@ def main():
                       "method": args.method, "kernel_shapes": variants, "s": s, "m": m, "eta": eta, "rho_F": rF, "rho_S": rS, "powiter_iters": [itF, itS]},
            "roofline": roof, "mixed": mixed, "cpu_baseline": cpu}
     print(json.dumps(out), flush=True)
+
+
+def cpu_baseline_imexrl(cfg, seconds, tet=None):
+    """The FP64 oracle's IMEX-RL step for a bounded number of steps on the
+    full mesh, its implicit line solved by scipy's Jacobi-preconditioned
+    conjugate gradients on the symmetric form (a sparse LU of the 3-D
+    operator takes minutes to factorise at these sizes)."""
+    from oracle.exexrl import imexrl_cg_solver, imexrl_step
+    from oracle.monodomain import build_grid_problem, build_tet_problem
+    prob = build_tet_problem(cfg, *tet) if tet is not None else build_grid_problem(cfg, stim_mask=cfg.get("mask"))
+    solve = imexrl_cg_solver(cfg["dt"], prob)
+    y = prob.uniform_state()
+    n = 0
+    t0 = time.perf_counter()
+    while True:
+        y = imexrl_step(n * cfg["dt"], y, cfg["dt"], prob, solve)
+        n += 1
+        el = time.perf_counter() - t0
+        if el >= seconds or n >= 1000:
+            break
+    return prob.N * n / el, n, el, prob.N
+
+
+IMEXRL_KERNEL_NAMES = {"pointwise": "k_imexrl_pre", "cg_init": "k_cg_init", "cg_apply": "k_cg_apply",
+                       "cg_update": "k_cg_update", "cg_direction": "k_cg_direction"}
+
+
+def bench_imexrl(args, cfg, N, tet, stream, E, torch):
+    """IMEX-RL on the same workload: one bench step is one whole simulation
+    (resting state, T/dt steps, each a pointwise Rush-Larsen kernel and a
+    conjugate-gradient solve of the implicit diffusion line)."""
+    log("bench: %s, N=%d, IMEX-RL (FP64)" % (cfg["name"], N))
+    job = Job(cfg, "fp64", stream, 0, tet, None, method="imexrl")
+    elapsed, iters = time_jobs(job, args.warmup, args.steps, torch)
+    value = N * job.nsim * args.steps / elapsed
+    log("bench: imexrl %.3f ms per simulation (%d steps, %d CG iterations), %.4g node-steps/s" %
+        (1e3 * elapsed / args.steps, job.nsim, iters, value))
+    ksteps = max(1, min(args.kernel_steps // 4, job.nsim))
+    prof = E.emrkc_profile_imexrl(job.sim.ctx, job.sim.state, cfg["dt"], ksteps)
+    log("bench: kernel means (ms, launches): %s" % prof)
+    nz = job.sim.nv - 1
+    width = E.lib().emrkc_ell_width(job.sim.ctx) if tet is not None else 0
+    mat = width * (4 + 8)
+
+    def kbytes(k):
+        return bytes_per_node("cg_" + k.replace("cg_", ""), nz, 8, 0, mat) * N
+
+    total = {k: v[0] * v[1] for k, v in prof.items()}
+    dom = max(total, key=total.get)
+    dom_gbs = kbytes(dom) / (prof[dom][0] * 1e-3) / 1e9
+    roof = {"kernel": IMEXRL_KERNEL_NAMES[dom], "bound": "hbm", "achieved": round(dom_gbs, 1),
+            "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(dom_gbs / HBM_PEAK_GBS, 4), "traffic": None,
+            "bytes_per_launch": kbytes(dom), "launch_ms": round(prof[dom][0], 5),
+            "kernels_ms": {k: round(v[0], 5) for k, v in prof.items()},
+            "launches": {k: v[1] for k, v in prof.items()},
+            "kernels_GBs": {k: round(kbytes(k) / (v[0] * 1e-3) / 1e9, 1) for k, v in prof.items() if v[1]}}
+    job.sim.close()
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("bench: CPU oracle baseline (IMEX-RL)")
+        v, n, el, Ns = cpu_baseline_imexrl(cfg, args.cpu_seconds, tet)
+        cpu = {"value": v, "unit": "node-steps/s", "cores": 1, "kind": "oracle",
+               "sample": "%d IMEX-RL steps of the full %d-node mesh in %.1f s (numpy/scipy, CG solves to "
+                         "1e-13, single thread; host has %d logical CPUs)" % (n, Ns, el, os.cpu_count())}
+    mesh = (("P1 tetrahedral shell %s" % "x".join(map(str, cfg["dims"]))) if tet is not None
+            else ("Q1 grid %s" % "x".join(map(str, cfg["n"]))))
+    return {"metric": METRIC.replace("emRKC", "IMEX-RL"), "value": value, "unit": "node-steps/s", "n_gpus": 1,
+            "steps": args.steps, "warmup": args.warmup, "ms_per_step": 1e3 * elapsed / args.steps,
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+            "config": {"workload": "%s: %s (%d nodes), %s, dt=%g ms, T=%g ms; one bench step = init + %d IMEX-RL "
+                                   "steps" % (cfg["name"], mesh, N, cfg["model"], cfg["dt"], cfg["T"], job.nsim),
+                       "method": "imexrl", "cg_iterations_per_simulation": iters, "cg_tolerance": 1e-13},
+            "roofline": roof, "cpu_baseline": cpu}
 
 
 def kernel_hash():

@@ -56,6 +56,25 @@ def imexrl_step(tn, y, dt, prob, solve=None):
     return np.concatenate([V1, zE1.reshape(-1), np.asarray(zS1).reshape(-1)])
 
 
+def imexrl_cg_solver(dt, prob, rtol=1e-13):
+    """A solve of (I - dt F) x = rhs by scipy's conjugate gradients on the
+    equivalent symmetric positive definite system
+    (M_L - dt (chi Cm)^{-1} A) x = M_L rhs, Jacobi preconditioned, started
+    from zero (for meshes where a sparse LU is too slow)."""
+    import scipy.sparse as sp
+    import scipy.sparse.linalg as spla
+    K = (sp.diags(prob.ML) - (dt / (prob.chi * prob.Cm)) * prob.A).tocsr()
+    dinv = 1.0 / K.diagonal()
+    M = spla.LinearOperator(K.shape, matvec=lambda v: dinv * v, dtype=np.float64)
+
+    def solve(rhs):
+        x, info = spla.cg(K, prob.ML * rhs, rtol=rtol, atol=0.0, M=M, maxiter=10000)
+        if info != 0:
+            raise RuntimeError("IMEX-RL CG did not converge (info=%d)" % info)
+        return x
+    return solve
+
+
 def imexrl_run(prob, y0, t0, dt, nsteps):
     """nsteps IMEX-RL steps; I - dt F is factorised once (sparse LU)."""
     import scipy.sparse.linalg as spla

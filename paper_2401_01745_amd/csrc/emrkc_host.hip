@@ -112,6 +112,9 @@ struct emrkc_ctx {
   double *d_Dsum = nullptr;   // IMEX-RL on tets: row sums of the operator's weights
   double grid_dsum = 0.0;     // IMEX-RL on grids: the same sum (one value for every node)
   int64_t cg_iters = 0;       // conjugate-gradient iterations of the last emrkc_imexrl_step
+  int cg_guess = 0;           // iterations of the last solve (how many to enqueue ahead)
+  CgScalars *d_cgs = nullptr; // the solver's device scalars, and a pinned host copy
+  CgScalars *h_cgs = nullptr;
   // mRKC: gate-0 inner buffers, and full-state vectors of its power iteration
   double *d_W[2] = {nullptr, nullptr};
   double *d_Y = nullptr, *d_FY = nullptr, *d_Wv = nullptr, *d_FW = nullptr;
@@ -379,9 +382,10 @@ static void free_ctx(emrkc_ctx *c) {
                   c->d_U[2], c->d_SV, c->d_SV2,   c->d_z1,      c->d_clock,   c->d_partials, c->d_result, c->d_flag,
                   c->d_vF[0], c->d_vF[1], c->d_vS[0], c->d_vS[1], c->d_zV,
                   c->d_W[0], c->d_W[1], c->d_Y, c->d_FY, c->d_Wv, c->d_FW,
-                  c->d_mv[0][0], c->d_mv[0][1], c->d_mv[1][0], c->d_mv[1][1], c->d_mpart, c->d_ML, c->d_cgq, c->d_Dsum};
+                  c->d_mv[0][0], c->d_mv[0][1], c->d_mv[1][0], c->d_mv[1][1], c->d_mpart, c->d_ML, c->d_cgq, c->d_Dsum, c->d_cgs};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
+  if (c->h_cgs) (void)hipHostFree(c->h_cgs);
   if (c->capture) (void)hipStreamDestroy(c->capture);
 }
 
@@ -1113,8 +1117,6 @@ static int enqueue_chunk_exexrl(emrkc_ctx *c, const emrkc_state *st, double dt, 
 // the lumped-mass inner product (I - dt F is self-adjoint there), Jacobi
 // preconditioned, from V^n.
 // ---------------------------------------------------------------------------
-static int fetch(emrkc_ctx *c, double *out);
-
 constexpr double kCgTol = 1e-13;
 constexpr int kCgMaxIter = 2000;
 
@@ -1152,12 +1154,6 @@ static int ensure_imexrl_data(emrkc_ctx *c) {
   return EMRKC_OK;
 }
 
-static int fetch2(emrkc_ctx *c, double *out) {
-  HIP_TRY(c, hipMemcpyAsync(out, c->d_result, 2 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
-  HIP_TRY(c, hipStreamSynchronize(c->stream));
-  return EMRKC_OK;
-}
-
 extern "C" int emrkc_imexrl_step(emrkc_ctx *c, emrkc_state *st, double dt, int64_t nsteps) {
   if (c == nullptr) return EMRKC_EINVAL;
   if (!state_ok(c, st)) return fail(c, EMRKC_EINVAL, "state buffers missing");
@@ -1165,11 +1161,12 @@ extern "C" int emrkc_imexrl_step(emrkc_ctx *c, emrkc_state *st, double dt, int64
   if (c->batch) return fail(c, EMRKC_EUNSUPPORTED, "IMEX-RL stepping is for single contexts");
   int rc;
   if ((rc = ensure_imexrl_data(c)) != EMRKC_OK) return rc;
+  if (!c->h_cgs) {
+    HIP_TRY(c, hipHostMalloc((void **)&c->h_cgs, sizeof(CgScalars), hipHostMallocDefault));
+    if ((rc = dalloc(c, (void **)&c->d_cgs, sizeof(CgScalars)))) return rc;
+  }
   const uint32_t N = (uint32_t)c->N;
   double *x = (double *)st->V, *b = c->d_U[0], *r = c->d_U[1], *zv = c->d_U[2], *p = c->d_V1, *q = c->d_cgq;
-  // stop when the preconditioned residual norm is below kCgTol times that
-  // of the right-hand side
-  const double tol2 = kCgTol * kCgTol;
   c->cg_iters = 0;
   for (int64_t n = 0; n < nsteps; ++n) {
     ImexArgs a{};
@@ -1182,33 +1179,119 @@ extern "C" int emrkc_imexrl_step(emrkc_ctx *c, emrkc_state *st, double dt, int64
     a.dt = dt;
     a.Cm = c->Cm;
     HIP_TRY(c, launch_imexrl_pre(c->model, c->mixed, N, a, c->stream));
-    HIP_TRY(c, launch_cg_init(c->mesh, c->d_ML, c->d_Dsum, c->grid_dsum, dt, x, b, r, zv, p, c->d_partials,
-                              c->d_result, c->stream));
-    double init[2];
-    if ((rc = fetch2(c, init))) return rc;
-    double rz = init[0];
-    const double stop = tol2 * init[1];
-    int it = 0;
-    while (rz > stop) {
-      if (!isfinite(rz)) return fail(c, EMRKC_ENONFINITE, "IMEX-RL solve at step %lld: non-finite residual",
-                                     (long long)st->step);
-      if (it++ >= kCgMaxIter)
+    HIP_TRY(c, launch_cg_init(c->mesh, c->d_ML, c->d_Dsum, c->grid_dsum, dt, kCgTol * kCgTol, x, b, r, zv, p,
+                              c->d_partials, c->d_cgs, c->stream));
+    // enqueue as many iterations as the last solve needed (plus one), then
+    // look at the flag; continue in batches until the solve is done
+    int enq = 0, batch = std::max(c->cg_guess + 1, 4);
+    for (;;) {
+      const int k = std::min(batch, kCgMaxIter - enq);
+      if (k > 0) {
+        HIP_TRY(c, launch_cg_iterations(c->mesh, c->d_ML, c->d_Dsum, c->grid_dsum, dt, k, x, r, zv, p, q,
+                                        c->d_partials, c->d_cgs, c->stream));
+        enq += k;
+      }
+      HIP_TRY(c, hipMemcpyAsync(c->h_cgs, c->d_cgs, sizeof(CgScalars), hipMemcpyDeviceToHost, c->stream));
+      HIP_TRY(c, hipStreamSynchronize(c->stream));
+      const CgScalars &cs = *c->h_cgs;
+      if (cs.done == 2)
+        return fail(c, EMRKC_ENONFINITE, "IMEX-RL solve at step %lld: non-finite residual", (long long)st->step);
+      if (cs.done == 1) {
+        c->cg_guess = cs.iters;
+        c->cg_iters += cs.iters;
+        break;
+      }
+      if (enq >= kCgMaxIter)
         return fail(c, EMRKC_ENOCONV, "IMEX-RL solve at step %lld: no convergence in %d iterations",
                     (long long)st->step, kCgMaxIter);
-      double pq, rz_new;
-      HIP_TRY(c, launch_cg_apply(c->mesh, c->d_ML, dt, p, q, c->d_partials, c->d_result, c->stream));
-      if ((rc = fetch(c, &pq))) return rc;
-      HIP_TRY(c, launch_cg_update(N, c->d_ML, c->d_Dsum, c->grid_dsum, dt, rz / pq, x, r, zv, p, q, c->d_partials,
-                                  c->d_result, c->stream));
-      if ((rc = fetch(c, &rz_new))) return rc;
-      HIP_TRY(c, launch_cg_direction(N, rz_new / rz, zv, p, c->stream));
-      rz = rz_new;
+      batch = std::max(4, enq / 2);
     }
-    c->cg_iters += it;
     st->step += 1;
     st->t = state_time(st->t0, st->step, dt);
   }
-  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  return check_finite(c, st);
+}
+
+// IMEX-RL steps with HIP events on every pointwise and vector kernel: the
+// class means over the launches that did work (a solve's kernels after its
+// convergence return at once and are left out).
+extern "C" int emrkc_profile_imexrl(emrkc_ctx *c, emrkc_state *st, double dt, int64_t nsteps, double *ms,
+                                    int64_t *counts) {
+  if (c == nullptr) return EMRKC_EINVAL;
+  if (!state_ok(c, st)) return fail(c, EMRKC_EINVAL, "state buffers missing");
+  if (!(dt > 0) || !isfinite(dt) || nsteps < 1 || nsteps > 10000) return fail(c, EMRKC_EINVAL, "invalid dt or nsteps");
+  if (c->batch) return fail(c, EMRKC_EUNSUPPORTED, "IMEX-RL stepping is for single contexts");
+  int rc;
+  if ((rc = ensure_imexrl_data(c)) != EMRKC_OK) return rc;
+  if (!c->h_cgs) {
+    HIP_TRY(c, hipHostMalloc((void **)&c->h_cgs, sizeof(CgScalars), hipHostMallocDefault));
+    if ((rc = dalloc(c, (void **)&c->d_cgs, sizeof(CgScalars)))) return rc;
+  }
+  const uint32_t N = (uint32_t)c->N;
+  double *x = (double *)st->V, *b = c->d_U[0], *r = c->d_U[1], *zv = c->d_U[2], *p = c->d_V1, *q = c->d_cgq;
+  // classes: 0 pointwise (k_imexrl_pre), 1 k_cg_init, 2 k_cg_apply,
+  // 3 k_cg_update, 4 k_cg_direction
+  KernelTimer tm;
+  double sum[5] = {0, 0, 0, 0, 0};
+  int64_t cnt[5] = {0, 0, 0, 0, 0};
+  auto body = [&]() -> int {
+    for (int64_t n = 0; n < nsteps; ++n) {
+      ImexArgs a{};
+      a.V = x;
+      a.rhs = b;
+      a.z = st->z;
+      a.t = state_time(st->t0, st->step, dt);
+      a.stim = stim_args(c);
+      a.mp = c->mp;
+      a.dt = dt;
+      a.Cm = c->Cm;
+      KernelTimer *T = &tm;
+      {
+        KernelTimer *tm = T;
+        TIMED(0, launch_imexrl_pre(c->model, c->mixed, N, a, c->stream));
+        TIMED(1, launch_cg_init(c->mesh, c->d_ML, c->d_Dsum, c->grid_dsum, dt, kCgTol * kCgTol, x, b, r, zv, p,
+                                c->d_partials, c->d_cgs, c->stream));
+      }
+      // one iteration at a time, so that every timed launch did work
+      for (int it = 0;; ++it) {
+        HIP_TRY(c, hipMemcpyAsync(c->h_cgs, c->d_cgs, sizeof(CgScalars), hipMemcpyDeviceToHost, c->stream));
+        HIP_TRY(c, hipStreamSynchronize(c->stream));
+        if (c->h_cgs->done == 2) return fail(c, EMRKC_ENONFINITE, "IMEX-RL solve: non-finite residual");
+        if (c->h_cgs->done == 1) break;
+        if (it >= kCgMaxIter) return fail(c, EMRKC_ENOCONV, "IMEX-RL solve: no convergence");
+        for (int w = 0; w < kCgLaunches; ++w) {
+          const int cls = w == kCgApply ? 2 : w == kCgUpdate ? 3 : w == kCgDirection ? 4 : -1;
+          KernelTimer *tm = cls >= 0 ? T : nullptr;
+          TIMED(cls, launch_cg_step(w, c->mesh, c->d_ML, c->d_Dsum, c->grid_dsum, dt, x, r, zv, p, q,
+                                    c->d_partials, c->d_cgs, c->stream));
+        }
+      }
+      st->step += 1;
+      st->t = state_time(st->t0, st->step, dt);
+    }
+    return EMRKC_OK;
+  };
+  rc = body();
+  hipError_t e = hipStreamSynchronize(c->stream);
+  if (rc == EMRKC_OK && e == hipSuccess) {
+    for (size_t k = 0; k + 1 < tm.used; k += 2) {
+      float t_ms = 0;
+      if (hipEventElapsedTime(&t_ms, tm.ev[k], tm.ev[k + 1]) != hipSuccess) {
+        rc = fail(c, EMRKC_EHIP, "hipEventElapsedTime failed");
+        break;
+      }
+      const int cl = tm.cls[k / 2];
+      sum[cl] += t_ms;
+      cnt[cl] += 1;
+    }
+  }
+  for (hipEvent_t ev : tm.ev) (void)hipEventDestroy(ev);
+  if (e != hipSuccess) return fail(c, EMRKC_EHIP, "profiled steps failed: %s", hipGetErrorString(e));
+  if (rc != EMRKC_OK) return rc;
+  for (int k = 0; k < 5; ++k) {
+    if (ms) ms[k] = cnt[k] ? sum[k] / (double)cnt[k] : 0.0;
+    if (counts) counts[k] = cnt[k];
+  }
   return check_finite(c, st);
 }
 

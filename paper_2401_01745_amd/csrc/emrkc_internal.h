@@ -174,21 +174,28 @@ hipError_t launch_mrkc_head(int model, const Mesh &mesh, const MrkcHeadArgs &a, 
 hipError_t launch_imexrl_pre(int model, bool mixed, uint32_t N, const ImexArgs &a, hipStream_t st);
 // Conjugate gradients for (I - dt F) x = b in the inner product weighted by
 // the lumped mass ML, preconditioned by the diagonal 1 + dt D_i (D_i from
-// Dsum, or dconst for every node when Dsum is null).  Each launcher leaves
-// the weighted sum it computes in result[0]:
-//   init:   r = b - (x - dt F x), z = r/diag, p = z;  sum ML r z  (result[1]: sum ML b b/diag)
-//   apply:  q = p - dt F p;                           sum ML p q
-//   update: x += alpha p, r -= alpha q, z = r/diag;   sum ML r z
+// Dsum, or dconst for every node when Dsum is null), with its scalars on the
+// device.  done: 0 running, 1 converged (preconditioned residual norm
+// squared <= stop = tol2 * (b, b)), 2 non-finite residual.
+struct CgScalars {
+  double rz, rz_next, pq, stop;
+  int32_t iters, done;
+};
+// r = b - (x - dt F x), z = r/diag, p = z; initialises the scalars
 hipError_t launch_cg_init(const Mesh &mesh, const double *ML, const double *Dsum, double dconst, double dt,
-                          const double *x, const double *b, double *r, double *z, double *p, double *partials,
-                          double *result, hipStream_t st);
-hipError_t launch_cg_apply(const Mesh &mesh, const double *ML, double dt, const double *p, double *q,
-                           double *partials, double *result, hipStream_t st);
-hipError_t launch_cg_update(uint32_t N, const double *ML, const double *Dsum, double dconst, double dt,
-                            double alpha, double *x, double *r, double *z, const double *p, const double *q,
-                            double *partials, double *result, hipStream_t st);
-// p = z + beta p
-hipError_t launch_cg_direction(uint32_t N, double beta, const double *z, double *p, hipStream_t st);
+                          double tol2, const double *x, const double *b, double *r, double *z, double *p,
+                          double *partials, CgScalars *s, hipStream_t st);
+// `count` iterations (each a no-op once the solve is done):
+// q = p - dt F p; alpha = rz/pq; x += alpha p; r -= alpha q; z = r/diag;
+// rz' = (r, z); p = z + (rz'/rz) p
+// the launches of one iteration, in order (each one kernel launch)
+enum CgLaunch : int { kCgApply = 0, kCgPqFinal, kCgUpdate, kCgRzFinal, kCgDirection, kCgLaunches };
+hipError_t launch_cg_step(int which, const Mesh &mesh, const double *ML, const double *Dsum, double dconst,
+                          double dt, double *x, double *r, double *z, double *p, double *q, double *partials,
+                          CgScalars *s, hipStream_t st);
+hipError_t launch_cg_iterations(const Mesh &mesh, const double *ML, const double *Dsum, double dconst, double dt,
+                                int count, double *x, double *r, double *z, double *p, double *q,
+                                double *partials, CgScalars *s, hipStream_t st);
 // out[i] = sum of row i's ELL weights
 hipError_t launch_ell_rowsum(const Ell &e, double *out, hipStream_t st);
 hipError_t launch_mrkc_inner(int model, const Mesh &mesh, const MrkcInnerArgs &a, hipStream_t st);

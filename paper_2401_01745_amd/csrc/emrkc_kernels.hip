@@ -1131,7 +1131,11 @@ __global__ __launch_bounds__(kBlock) void k_vec_diff_norm(uint64_t n, const doub
 // inner product sum_i ML_i u_i v_i (in which I - dt F is symmetric positive
 // definite), preconditioned by its diagonal 1 + dt D_i, D_i = sum of the
 // node's neighbour weights (Dsum[i], or dconst on a uniform grid).  Always
-// double precision.  Each kernel leaves per-block partial sums.
+// double precision.  The scalars live on the device (CgScalars): each
+// vector kernel leaves per-block partial sums, a one-block kernel reduces
+// them in a fixed order and updates the scalars, and once the solve has
+// converged every later kernel of the solve returns at once, so the host
+// can enqueue iterations ahead and look at the flag once per batch.
 // ---------------------------------------------------------------------------
 struct CgDiag {
   const double *Dsum;  // nullptr: every node has dconst
@@ -1139,6 +1143,12 @@ struct CgDiag {
   double dt;
   __device__ __forceinline__ double at(uint32_t i) const { return 1.0 + dt * (Dsum ? Dsum[i] : dconst); }
 };
+
+__device__ __forceinline__ double block_total(const double *partials, uint32_t n) {
+  double v = 0.0;
+  for (uint32_t k = threadIdx.x; k < n; k += blockDim.x) v += partials[k];
+  return block_sum(v);  // valid in thread 0
+}
 
 __global__ __launch_bounds__(kBlock) void k_cg_init(Mesh mesh, const double *ML, CgDiag dg, const double *x,
                                                     const double *b, double *r, double *z, double *p,
@@ -1166,8 +1176,24 @@ __global__ __launch_bounds__(kBlock) void k_cg_init(Mesh mesh, const double *ML,
   }
 }
 
+__global__ __launch_bounds__(kBlock) void k_cg_init_final(const double *partials, uint32_t nb, double tol2,
+                                                          CgScalars *s) {
+  const double rz = block_total(partials, nb);
+  __syncthreads();
+  const double bb = block_total(partials + nb, nb);
+  if (threadIdx.x == 0) {
+    s->rz = rz;
+    s->rz_next = rz;
+    s->pq = 0.0;
+    s->stop = tol2 * bb;
+    s->iters = 0;
+    s->done = rz <= s->stop ? 1 : (isfinite(rz) ? 0 : 2);
+  }
+}
+
 __global__ __launch_bounds__(kBlock) void k_cg_apply(Mesh mesh, const double *ML, double dt, const double *p,
-                                                     double *q, double *partials) {
+                                                     double *q, double *partials, const CgScalars *s) {
+  if (s->done) return;
   const uint32_t N = mesh.kind == kGrid ? mesh.grid.N : mesh.ell.N;
   const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
   double pq = 0.0;
@@ -1180,9 +1206,22 @@ __global__ __launch_bounds__(kBlock) void k_cg_apply(Mesh mesh, const double *ML
   if (threadIdx.x == 0) partials[blockIdx.x] = pq;
 }
 
-__global__ __launch_bounds__(kBlock) void k_cg_update(uint32_t N, const double *ML, CgDiag dg, double alpha,
-                                                      double *x, double *r, double *z, const double *p,
-                                                      const double *q, double *partials) {
+// rz takes the value of the previous iteration's update here, after the
+// direction kernel that needed both has run.
+__global__ __launch_bounds__(kBlock) void k_cg_pq_final(const double *partials, uint32_t nb, CgScalars *s) {
+  if (s->done) return;
+  const double pq = block_total(partials, nb);
+  if (threadIdx.x == 0) {
+    s->rz = s->rz_next;
+    s->pq = pq;
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_cg_update(uint32_t N, const double *ML, CgDiag dg, double *x, double *r,
+                                                      double *z, const double *p, const double *q,
+                                                      double *partials, const CgScalars *s) {
+  if (s->done) return;
+  const double alpha = s->rz / s->pq;
   const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
   double rz = 0.0;
   if (i < N) {
@@ -1197,7 +1236,20 @@ __global__ __launch_bounds__(kBlock) void k_cg_update(uint32_t N, const double *
   if (threadIdx.x == 0) partials[blockIdx.x] = rz;
 }
 
-__global__ __launch_bounds__(kBlock) void k_cg_direction(uint32_t N, double beta, const double *z, double *p) {
+__global__ __launch_bounds__(kBlock) void k_cg_rz_final(const double *partials, uint32_t nb, CgScalars *s) {
+  if (s->done) return;
+  const double rz = block_total(partials, nb);
+  if (threadIdx.x == 0) {
+    s->rz_next = rz;
+    s->iters = s->iters + 1;
+    s->done = rz <= s->stop ? 1 : (isfinite(rz) ? 0 : 2);
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_cg_direction(uint32_t N, const double *z, double *p,
+                                                         const CgScalars *s) {
+  if (s->done) return;
+  const double beta = s->rz_next / s->rz;
   const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < N) p[i] = z[i] + beta * p[i];
 }
@@ -1512,37 +1564,52 @@ hipError_t launch_imexrl_pre(int model, bool mixed, uint32_t N, const ImexArgs &
 static inline uint32_t mesh_nodes(const Mesh &m) { return m.kind == kGrid ? m.grid.N : m.ell.N; }
 
 hipError_t launch_cg_init(const Mesh &mesh, const double *ML, const double *Dsum, double dconst, double dt,
-                          const double *x, const double *b, double *r, double *z, double *p, double *partials,
-                          double *result, hipStream_t st) {
+                          double tol2, const double *x, const double *b, double *r, double *z, double *p,
+                          double *partials, CgScalars *s, hipStream_t st) {
   const uint32_t nb = blocks_for(mesh_nodes(mesh));
   EMRKC_LAUNCH(k_cg_init, dim3(nb), dim3(kBlock), 0, st, mesh, ML, CgDiag{Dsum, dconst, dt}, x, b, r, z, p,
                partials);
-  EMRKC_LAUNCH(k_reduce_final, dim3(1), dim3(kBlock), 0, st, partials, nb, result);
-  EMRKC_LAUNCH(k_reduce_final, dim3(1), dim3(kBlock), 0, st, partials + nb, nb, result + 1);
+  EMRKC_LAUNCH(k_cg_init_final, dim3(1), dim3(kBlock), 0, st, partials, nb, tol2, s);
   return hipGetLastError();
 }
 
-hipError_t launch_cg_apply(const Mesh &mesh, const double *ML, double dt, const double *p, double *q,
-                           double *partials, double *result, hipStream_t st) {
-  const uint32_t nb = blocks_for(mesh_nodes(mesh));
-  EMRKC_LAUNCH(k_cg_apply, dim3(nb), dim3(kBlock), 0, st, mesh, ML, dt, p, q, partials);
-  EMRKC_LAUNCH(k_reduce_final, dim3(1), dim3(kBlock), 0, st, partials, nb, result);
-  return hipGetLastError();
-}
-
-hipError_t launch_cg_update(uint32_t N, const double *ML, const double *Dsum, double dconst, double dt,
-                            double alpha, double *x, double *r, double *z, const double *p, const double *q,
-                            double *partials, double *result, hipStream_t st) {
+hipError_t launch_cg_step(int which, const Mesh &mesh, const double *ML, const double *Dsum, double dconst,
+                          double dt, double *x, double *r, double *z, double *p, double *q, double *partials,
+                          CgScalars *s, hipStream_t st) {
+  const uint32_t N = mesh_nodes(mesh);
   const uint32_t nb = blocks_for(N);
-  EMRKC_LAUNCH(k_cg_update, dim3(nb), dim3(kBlock), 0, st, N, ML, CgDiag{Dsum, dconst, dt}, alpha, x, r, z, p, q,
-               partials);
-  EMRKC_LAUNCH(k_reduce_final, dim3(1), dim3(kBlock), 0, st, partials, nb, result);
+  switch (which) {
+    case kCgApply:
+      EMRKC_LAUNCH(k_cg_apply, dim3(nb), dim3(kBlock), 0, st, mesh, ML, dt, p, q, partials, s);
+      break;
+    case kCgPqFinal:
+      EMRKC_LAUNCH(k_cg_pq_final, dim3(1), dim3(kBlock), 0, st, partials, nb, s);
+      break;
+    case kCgUpdate:
+      EMRKC_LAUNCH(k_cg_update, dim3(nb), dim3(kBlock), 0, st, N, ML, CgDiag{Dsum, dconst, dt}, x, r, z, p, q,
+                   partials, s);
+      break;
+    case kCgRzFinal:
+      EMRKC_LAUNCH(k_cg_rz_final, dim3(1), dim3(kBlock), 0, st, partials, nb, s);
+      break;
+    case kCgDirection:
+      EMRKC_LAUNCH(k_cg_direction, dim3(nb), dim3(kBlock), 0, st, N, z, p, s);
+      break;
+    default:
+      return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 
-hipError_t launch_cg_direction(uint32_t N, double beta, const double *z, double *p, hipStream_t st) {
-  EMRKC_LAUNCH(k_cg_direction, dim3(blocks_for(N)), dim3(kBlock), 0, st, N, beta, z, p);
-  return hipGetLastError();
+hipError_t launch_cg_iterations(const Mesh &mesh, const double *ML, const double *Dsum, double dconst, double dt,
+                                int count, double *x, double *r, double *z, double *p, double *q,
+                                double *partials, CgScalars *s, hipStream_t st) {
+  for (int k = 0; k < count; ++k)
+    for (int w = 0; w < kCgLaunches; ++w) {
+      const hipError_t e = launch_cg_step(w, mesh, ML, Dsum, dconst, dt, x, r, z, p, q, partials, s, st);
+      if (e != hipSuccess) return e;
+    }
+  return hipSuccess;
 }
 
 hipError_t launch_ell_rowsum(const Ell &e, double *out, hipStream_t st) {

@@ -80,6 +80,8 @@ EXPORTS = {
     "emrkc_exexrl_step": (C.c_int, [C.c_void_p, C.POINTER(State), C.c_double, C.c_int64]),
     "emrkc_imexrl_step": (C.c_int, [C.c_void_p, C.POINTER(State), C.c_double, C.c_int64]),
     "emrkc_imexrl_iterations": (C.c_int64, [C.c_void_p]),
+    "emrkc_profile_imexrl": (C.c_int, [C.c_void_p, C.POINTER(State), C.c_double, C.c_int64,
+                                       C.POINTER(C.c_double), C.POINTER(C.c_int64)]),
     "emrkc_autotune": (C.c_int, [C.c_void_p, C.POINTER(State), C.c_double, C.c_int, C.POINTER(C.c_int)]),
     "emrkc_get_variants": (C.c_int, [C.c_void_p, C.POINTER(C.c_int)]),
     "emrkc_set_variants": (C.c_int, [C.c_void_p, C.POINTER(C.c_int)]),
@@ -264,6 +266,18 @@ def emrkc_imexrl_step(ctx, state, dt, nsteps):
 
 def emrkc_imexrl_iterations(ctx):
     return int(lib().emrkc_imexrl_iterations(ctx))
+
+
+IMEXRL_KERNELS = ("pointwise", "cg_init", "cg_apply", "cg_update", "cg_direction")
+
+
+def emrkc_profile_imexrl(ctx, state, dt, nsteps):
+    """Mean kernel durations (ms) and launch counts of IMEX-RL steps, by
+    kernel class."""
+    ms = (C.c_double * 5)()
+    cnt = (C.c_int64 * 5)()
+    _check(lib().emrkc_profile_imexrl(ctx, C.byref(state), dt, int(nsteps), ms, cnt), ctx)
+    return {k: (ms[i], int(cnt[i])) for i, k in enumerate(IMEXRL_KERNELS)}
 
 
 def emrkc_autotune(ctx, state, dt, reps=3):

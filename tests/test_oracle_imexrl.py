@@ -5,7 +5,7 @@ import numpy as np
 import pytest
 
 from oracle import fem
-from oracle.exexrl import exexrl_run, imexrl_run, imexrl_step
+from oracle.exexrl import exexrl_run, imexrl_cg_solver, imexrl_run, imexrl_step
 from oracle.monodomain import build_grid_problem
 from workloads.configs import small_config
 
@@ -72,3 +72,15 @@ def test_first_order_convergence_against_exexrl():
         errs.append(np.linalg.norm(y[:prob.N] - ref[:prob.N]) / np.linalg.norm(ref[:prob.N]))
     slopes = np.diff(np.log(errs)) / np.diff(np.log(dts))
     assert np.all((slopes > 0.8) & (slopes < 1.2)), (errs, slopes)
+
+
+@pytest.mark.parametrize("dt", [0.05, 1.0])
+def test_cg_solve_matches_direct_solve(dt):
+    """The symmetric CG form of the implicit line gives the LU solution."""
+    cfg = small_config("c2_3d_crn", (11, 9, 5))
+    prob = build_grid_problem(cfg)
+    rng = np.random.default_rng(5)
+    y = prob.uniform_state() * (1 + 1e-2 * rng.standard_normal(prob.nv * prob.N))
+    a = imexrl_step(0.3, y, dt, prob)
+    b = imexrl_step(0.3, y, dt, prob, imexrl_cg_solver(dt, prob))
+    assert np.abs(a - b).max() <= 1e-11 * np.abs(a).max()
