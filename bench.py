@@ -256,12 +256,15 @@ def main():
         else:
             db = bytes_per_node(dom, nz, 8, m, mat) * N
         dom_gbs = db / (dom_ms * 1e-3) / 1e9
+        # HBM bytes per launch from the committed rocprof counters, when they
+        # were taken on these kernel sources for the kernel shape chosen here
         prof_path = os.path.join(ROOT, "profiles", "traffic_k_%s_%s_fp64.json" % (dom, cfg["name"]))
         traffic = None
-        if args.method == "emrkc" and os.path.exists(prof_path):
+        if args.method == "emrkc" and batch is None and tet is None and os.path.exists(prof_path):
             tr = json.load(open(prof_path))
-            if tr.get("kernel_source_hash") == kernel_hash():
-                traffic = tr.get("bytes_per_launch")
+            ent = tr.get("by_shape", {}).get("%d,%d,%d" % (variants[0], variants[1], variants[4]))
+            if tr.get("kernel_source_hash") == kernel_hash() and ent is not None:
+                traffic = ent.get("bytes_per_launch")
         head_kernel = ("k_mrkc_head" if args.method == "mrkc" else
                        "k_head_batch<tile shape %d>" % variants[0] if batch is not None else
                        "k_head" if tet is not None else
