@@ -75,6 +75,21 @@ def test_imexrl_shell_parity(E):
     _check(prob, y, V, z)
 
 
+def test_imexrl_mixed_context(E):
+    """On a mixed-precision context (FP32 ionic state and model) the IMEX-RL
+    step keeps its FP64 solve; V stays within 1e-4 relative L2 of the FP64
+    context's."""
+    cfg = small_config("c2_3d_crn", (37, 29, 11))
+    dt, nsteps = 0.05, 80
+    out = {}
+    for prec in ("fp64", "mixed"):
+        sim = E.simulation_from_config(cfg, precision=prec)
+        out[prec] = _gpu_imexrl(E, sim, dt, [nsteps])[0]
+        sim.close()
+    assert out["fp64"].max() > 0.0
+    assert rel_errors(out["mixed"], out["fp64"])[0] < 1e-4
+
+
 def test_zero_steps_and_invalid_arguments(E):
     cfg = small_config("c2_3d_crn", (9, 7, 5))
     sim = E.simulation_from_config(cfg)
