@@ -63,21 +63,19 @@ def bytes_per_node(kind, nz, wz, m, mat=0):
     # IMEX-RL (FP64 solve); dsum = 8 on unstructured meshes (the row sums of
     # the preconditioner), 0 on grids (one value)
     #   pointwise: V read, z read and written, right-hand side written
-    #   cg_init  : x, b, ML (+ D) read, r, z, p written
-    #   cg_apply : p, ML read, q written
+    #   cg_init  : x, b, ML (+ D) read, r, z written
+    #   cg_apply : z, previous p, ML read, p and q written (the new
+    #              direction and the operator product in one kernel)
     #   cg_update: x, r read and written, p, q, ML (+ D) read, z written
-    #   cg_direction: z read, p read and written
     dsum = 8 if mat else 0
     if kind == "cg_pointwise":
         return 8 + 2 * nz * wz + 8
     if kind == "cg_init":
-        return 8 + 8 + 8 + dsum + 24 + mat
+        return 8 + 8 + 8 + dsum + 16 + mat
     if kind == "cg_apply":
-        return 8 + 8 + 8 + mat
+        return 8 + 8 + 8 + 16 + mat
     if kind == "cg_update":
         return 16 + 16 + 8 + 8 + 8 + dsum + 8
-    if kind == "cg_direction":
-        return 8 + 16
     raise ValueError(kind)
 
 
@@ -358,8 +356,9 @@ def cpu_baseline_imexrl(cfg, seconds, tet=None):
     return prob.N * n / el, n, el, prob.N
 
 
-IMEXRL_KERNEL_NAMES = {"pointwise": "k_imexrl_pre", "cg_init": "k_cg_init", "cg_apply": "k_cg_apply",
-                       "cg_update": "k_cg_update", "cg_direction": "k_cg_direction"}
+IMEXRL_KERNEL_NAMES = {"pointwise": "k_imexrl_pre", "cg_init": "k_cg_init",
+                       "cg_apply": "k_cg_dir_apply (new direction and operator product)",
+                       "cg_update": "k_cg_update"}
 
 
 def bench_imexrl(args, cfg, N, tet, stream, E, torch):

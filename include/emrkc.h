@@ -326,12 +326,12 @@ int emrkc_imexrl_step(emrkc_ctx *ctx, emrkc_state *state, double dt, int64_t nst
 int64_t emrkc_imexrl_iterations(const emrkc_ctx *ctx);
 
 /* nsteps IMEX-RL steps as emrkc_imexrl_step, launched one solver iteration
- * at a time with HIP events on each kernel; ms[5] receives the mean
- * duration and counts[5] the launch count of each kernel class: [0] the
+ * at a time with HIP events on each kernel; ms[4] receives the mean
+ * duration and counts[4] the launch count of each kernel class: [0] the
  * pointwise step (gates, slow variables, right-hand side), [1] the solver's
- * initial residual, [2] the operator product q = (I - dt F) p, [3] the
- * update of x, r and z, [4] the new direction.  1 <= nsteps <= 1e4; ms and
- * counts may be NULL.  Synchronises after every iteration. */
+ * initial residual, [2] the new direction p with the operator product
+ * q = (I - dt F) p, [3] the update of x, r and z.  1 <= nsteps <= 1e4; ms
+ * and counts may be NULL.  Synchronises after every iteration. */
 int emrkc_profile_imexrl(emrkc_ctx *ctx, emrkc_state *state, double dt, int64_t nsteps, double *ms,
                          int64_t *counts);
 

@@ -113,6 +113,8 @@ struct emrkc_ctx {
   double grid_dsum = 0.0;     // IMEX-RL on grids: the same sum (one value for every node)
   int64_t cg_iters = 0;       // conjugate-gradient iterations of the last emrkc_imexrl_step
   int cg_guess = 0;           // iterations of the last solve (how many to enqueue ahead)
+  double *d_cgp2 = nullptr;   // IMEX-RL: second direction buffer (directions alternate with d_V1)
+  double *d_cgpart = nullptr; // IMEX-RL: partial sums
   CgScalars *d_cgs = nullptr; // the solver's device scalars, and a pinned host copy
   CgScalars *h_cgs = nullptr;
   // mRKC: gate-0 inner buffers, and full-state vectors of its power iteration
@@ -382,7 +384,7 @@ static void free_ctx(emrkc_ctx *c) {
                   c->d_U[2], c->d_SV, c->d_SV2,   c->d_z1,      c->d_clock,   c->d_partials, c->d_result, c->d_flag,
                   c->d_vF[0], c->d_vF[1], c->d_vS[0], c->d_vS[1], c->d_zV,
                   c->d_W[0], c->d_W[1], c->d_Y, c->d_FY, c->d_Wv, c->d_FW,
-                  c->d_mv[0][0], c->d_mv[0][1], c->d_mv[1][0], c->d_mv[1][1], c->d_mpart, c->d_ML, c->d_cgq, c->d_Dsum, c->d_cgs};
+                  c->d_mv[0][0], c->d_mv[0][1], c->d_mv[1][0], c->d_mv[1][1], c->d_mpart, c->d_ML, c->d_cgq, c->d_Dsum, c->d_cgs, c->d_cgp2, c->d_cgpart};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   if (c->h_cgs) (void)hipHostFree(c->h_cgs);
@@ -1123,6 +1125,15 @@ constexpr int kCgMaxIter = 2000;
 static int ensure_imexrl_data(emrkc_ctx *c) {
   int rc;
   if (!c->d_cgq && (rc = dalloc(c, (void **)&c->d_cgq, sizeof(double) * (size_t)c->N))) return rc;
+  if (!c->d_cgp2 && (rc = dalloc(c, (void **)&c->d_cgp2, sizeof(double) * (size_t)c->N))) return rc;
+  if (!c->d_cgpart) {
+    const size_t nparts = std::max<size_t>(2 * (size_t)reduce_blocks((uint32_t)c->N), cg_apply_blocks(c->mesh));
+    if ((rc = dalloc(c, (void **)&c->d_cgpart, nparts * sizeof(double)))) return rc;
+  }
+  if (!c->h_cgs) {
+    HIP_TRY(c, hipHostMalloc((void **)&c->h_cgs, sizeof(CgScalars), hipHostMallocDefault));
+    if ((rc = dalloc(c, (void **)&c->d_cgs, sizeof(CgScalars)))) return rc;
+  }
   if (c->mesh.kind == kEll) {
     if (!c->d_ML) return fail(c, EMRKC_EUNSUPPORTED, "lumped mass missing");
     if (!c->d_Dsum) {
@@ -1161,12 +1172,9 @@ extern "C" int emrkc_imexrl_step(emrkc_ctx *c, emrkc_state *st, double dt, int64
   if (c->batch) return fail(c, EMRKC_EUNSUPPORTED, "IMEX-RL stepping is for single contexts");
   int rc;
   if ((rc = ensure_imexrl_data(c)) != EMRKC_OK) return rc;
-  if (!c->h_cgs) {
-    HIP_TRY(c, hipHostMalloc((void **)&c->h_cgs, sizeof(CgScalars), hipHostMallocDefault));
-    if ((rc = dalloc(c, (void **)&c->d_cgs, sizeof(CgScalars)))) return rc;
-  }
   const uint32_t N = (uint32_t)c->N;
-  double *x = (double *)st->V, *b = c->d_U[0], *r = c->d_U[1], *zv = c->d_U[2], *p = c->d_V1, *q = c->d_cgq;
+  double *x = (double *)st->V, *b = c->d_U[0], *r = c->d_U[1], *zv = c->d_U[2], *q = c->d_cgq;
+  double *const P[2] = {c->d_V1, c->d_cgp2};
   c->cg_iters = 0;
   for (int64_t n = 0; n < nsteps; ++n) {
     ImexArgs a{};
@@ -1179,16 +1187,16 @@ extern "C" int emrkc_imexrl_step(emrkc_ctx *c, emrkc_state *st, double dt, int64
     a.dt = dt;
     a.Cm = c->Cm;
     HIP_TRY(c, launch_imexrl_pre(c->model, c->mixed, N, a, c->stream));
-    HIP_TRY(c, launch_cg_init(c->mesh, c->d_ML, c->d_Dsum, c->grid_dsum, dt, kCgTol * kCgTol, x, b, r, zv, p,
-                              c->d_partials, c->d_cgs, c->stream));
+    HIP_TRY(c, launch_cg_init(c->mesh, c->d_ML, c->d_Dsum, c->grid_dsum, dt, kCgTol * kCgTol, x, b, r, zv,
+                              c->d_cgpart, c->d_cgs, c->stream));
     // enqueue as many iterations as the last solve needed (plus one), then
     // look at the flag; continue in batches until the solve is done
     int enq = 0, batch = std::max(c->cg_guess + 1, 4);
     for (;;) {
       const int k = std::min(batch, kCgMaxIter - enq);
       if (k > 0) {
-        HIP_TRY(c, launch_cg_iterations(c->mesh, c->d_ML, c->d_Dsum, c->grid_dsum, dt, k, x, r, zv, p, q,
-                                        c->d_partials, c->d_cgs, c->stream));
+        HIP_TRY(c, launch_cg_iterations(c->mesh, c->d_ML, c->d_Dsum, c->grid_dsum, dt, enq, k, x, r, zv, P, q,
+                                        c->d_cgpart, c->d_cgs, c->stream));
         enq += k;
       }
       HIP_TRY(c, hipMemcpyAsync(c->h_cgs, c->d_cgs, sizeof(CgScalars), hipMemcpyDeviceToHost, c->stream));
@@ -1223,17 +1231,14 @@ extern "C" int emrkc_profile_imexrl(emrkc_ctx *c, emrkc_state *st, double dt, in
   if (c->batch) return fail(c, EMRKC_EUNSUPPORTED, "IMEX-RL stepping is for single contexts");
   int rc;
   if ((rc = ensure_imexrl_data(c)) != EMRKC_OK) return rc;
-  if (!c->h_cgs) {
-    HIP_TRY(c, hipHostMalloc((void **)&c->h_cgs, sizeof(CgScalars), hipHostMallocDefault));
-    if ((rc = dalloc(c, (void **)&c->d_cgs, sizeof(CgScalars)))) return rc;
-  }
   const uint32_t N = (uint32_t)c->N;
-  double *x = (double *)st->V, *b = c->d_U[0], *r = c->d_U[1], *zv = c->d_U[2], *p = c->d_V1, *q = c->d_cgq;
-  // classes: 0 pointwise (k_imexrl_pre), 1 k_cg_init, 2 k_cg_apply,
-  // 3 k_cg_update, 4 k_cg_direction
+  double *x = (double *)st->V, *b = c->d_U[0], *r = c->d_U[1], *zv = c->d_U[2], *q = c->d_cgq;
+  double *const P[2] = {c->d_V1, c->d_cgp2};
+  // classes: 0 pointwise (k_imexrl_pre), 1 k_cg_init, 2 direction and
+  // operator (k_cg_dir_apply_*), 3 k_cg_update
   KernelTimer tm;
-  double sum[5] = {0, 0, 0, 0, 0};
-  int64_t cnt[5] = {0, 0, 0, 0, 0};
+  double sum[4] = {0, 0, 0, 0};
+  int64_t cnt[4] = {0, 0, 0, 0};
   auto body = [&]() -> int {
     for (int64_t n = 0; n < nsteps; ++n) {
       ImexArgs a{};
@@ -1249,8 +1254,8 @@ extern "C" int emrkc_profile_imexrl(emrkc_ctx *c, emrkc_state *st, double dt, in
       {
         KernelTimer *tm = T;
         TIMED(0, launch_imexrl_pre(c->model, c->mixed, N, a, c->stream));
-        TIMED(1, launch_cg_init(c->mesh, c->d_ML, c->d_Dsum, c->grid_dsum, dt, kCgTol * kCgTol, x, b, r, zv, p,
-                                c->d_partials, c->d_cgs, c->stream));
+        TIMED(1, launch_cg_init(c->mesh, c->d_ML, c->d_Dsum, c->grid_dsum, dt, kCgTol * kCgTol, x, b, r, zv,
+                                c->d_cgpart, c->d_cgs, c->stream));
       }
       // one iteration at a time, so that every timed launch did work
       for (int it = 0;; ++it) {
@@ -1260,10 +1265,10 @@ extern "C" int emrkc_profile_imexrl(emrkc_ctx *c, emrkc_state *st, double dt, in
         if (c->h_cgs->done == 1) break;
         if (it >= kCgMaxIter) return fail(c, EMRKC_ENOCONV, "IMEX-RL solve: no convergence");
         for (int w = 0; w < kCgLaunches; ++w) {
-          const int cls = w == kCgApply ? 2 : w == kCgUpdate ? 3 : w == kCgDirection ? 4 : -1;
+          const int cls = w == kCgApply ? 2 : w == kCgUpdate ? 3 : -1;  // the one-block reductions untimed
           KernelTimer *tm = cls >= 0 ? T : nullptr;
-          TIMED(cls, launch_cg_step(w, c->mesh, c->d_ML, c->d_Dsum, c->grid_dsum, dt, x, r, zv, p, q,
-                                    c->d_partials, c->d_cgs, c->stream));
+          TIMED(cls, launch_cg_step(w, c->mesh, c->d_ML, c->d_Dsum, c->grid_dsum, dt, x, r, zv, P[it & 1],
+                                    P[(it + 1) & 1], q, c->d_cgpart, c->d_cgs, c->stream));
         }
       }
       st->step += 1;
@@ -1288,7 +1293,7 @@ extern "C" int emrkc_profile_imexrl(emrkc_ctx *c, emrkc_state *st, double dt, in
   for (hipEvent_t ev : tm.ev) (void)hipEventDestroy(ev);
   if (e != hipSuccess) return fail(c, EMRKC_EHIP, "profiled steps failed: %s", hipGetErrorString(e));
   if (rc != EMRKC_OK) return rc;
-  for (int k = 0; k < 5; ++k) {
+  for (int k = 0; k < 4; ++k) {
     if (ms) ms[k] = cnt[k] ? sum[k] / (double)cnt[k] : 0.0;
     if (counts) counts[k] = cnt[k];
   }

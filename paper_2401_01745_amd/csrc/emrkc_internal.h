@@ -178,24 +178,32 @@ hipError_t launch_imexrl_pre(int model, bool mixed, uint32_t N, const ImexArgs &
 // device.  done: 0 running, 1 converged (preconditioned residual norm
 // squared <= stop = tol2 * (b, b)), 2 non-finite residual.
 struct CgScalars {
-  double rz, rz_next, pq, stop;
-  int32_t iters, done;
+  double rz, rz_prev, pq, stop;
+  int32_t iters, done, first, pad;
 };
-// r = b - (x - dt F x), z = r/diag, p = z; initialises the scalars
+// r = b - (x - dt F x), z = r/diag; initialises the scalars (first
+// iteration next); writes 2 x ceil(N/256) partial sums
 hipError_t launch_cg_init(const Mesh &mesh, const double *ML, const double *Dsum, double dconst, double dt,
-                          double tol2, const double *x, const double *b, double *r, double *z, double *p,
-                          double *partials, CgScalars *s, hipStream_t st);
-// `count` iterations (each a no-op once the solve is done):
-// q = p - dt F p; alpha = rz/pq; x += alpha p; r -= alpha q; z = r/diag;
-// rz' = (r, z); p = z + (rz'/rz) p
-// the launches of one iteration, in order (each one kernel launch)
-enum CgLaunch : int { kCgApply = 0, kCgPqFinal, kCgUpdate, kCgRzFinal, kCgDirection, kCgLaunches };
-hipError_t launch_cg_step(int which, const Mesh &mesh, const double *ML, const double *Dsum, double dconst,
-                          double dt, double *x, double *r, double *z, double *p, double *q, double *partials,
+                          double tol2, const double *x, const double *b, double *r, double *z, double *partials,
                           CgScalars *s, hipStream_t st);
+// the launches of an iteration, in order (each a no-op once the solve is
+// done; the vector kernels leave block partial sums, the one-block kernels
+// reduce them):
+//   kCgApply:   p = z + beta pprev (p = z on the first), q = p - dt F p
+//   kCgPqFinal: pq = (p, q)
+//   kCgUpdate:  alpha = rz/pq; x += alpha p; r -= alpha q; z = r/diag
+//   kCgRzFinal: rz' = (r, z), beta for the next direction, convergence flag
+enum CgLaunch : int { kCgApply = 0, kCgPqFinal, kCgUpdate, kCgRzFinal, kCgLaunches };
+hipError_t launch_cg_step(int which, const Mesh &mesh, const double *ML, const double *Dsum, double dconst,
+                          double dt, double *x, double *r, double *z, const double *pprev, double *p, double *q,
+                          double *partials, CgScalars *s, hipStream_t st);
+// `count` iterations numbered from first_index; iteration k reads the
+// direction from P[k % 2] and writes the new one to P[(k + 1) % 2]
 hipError_t launch_cg_iterations(const Mesh &mesh, const double *ML, const double *Dsum, double dconst, double dt,
-                                int count, double *x, double *r, double *z, double *p, double *q,
-                                double *partials, CgScalars *s, hipStream_t st);
+                                int64_t first_index, int count, double *x, double *r, double *z, double *const P[2],
+                                double *q, double *partials, CgScalars *s, hipStream_t st);
+// partial sums the kCgApply launch writes (one per block)
+uint32_t cg_apply_blocks(const Mesh &mesh);
 // out[i] = sum of row i's ELL weights
 hipError_t launch_ell_rowsum(const Ell &e, double *out, hipStream_t st);
 hipError_t launch_mrkc_inner(int model, const Mesh &mesh, const MrkcInnerArgs &a, hipStream_t st);

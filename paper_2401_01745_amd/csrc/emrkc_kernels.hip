@@ -1151,8 +1151,7 @@ __device__ __forceinline__ double block_total(const double *partials, uint32_t n
 }
 
 __global__ __launch_bounds__(kBlock) void k_cg_init(Mesh mesh, const double *ML, CgDiag dg, const double *x,
-                                                    const double *b, double *r, double *z, double *p,
-                                                    double *partials) {
+                                                    const double *b, double *r, double *z, double *partials) {
   const uint32_t N = mesh.kind == kGrid ? mesh.grid.N : mesh.ell.N;
   const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
   double rz = 0.0, bb = 0.0;
@@ -1163,7 +1162,6 @@ __global__ __launch_bounds__(kBlock) void k_cg_init(Mesh mesh, const double *ML,
     const double zi = ri / di;
     r[i] = ri;
     z[i] = zi;
-    p[i] = zi;
     rz = ML[i] * ri * zi;
     bb = ML[i] * b[i] * (b[i] / di);
   }
@@ -1183,43 +1181,87 @@ __global__ __launch_bounds__(kBlock) void k_cg_init_final(const double *partials
   const double bb = block_total(partials + nb, nb);
   if (threadIdx.x == 0) {
     s->rz = rz;
-    s->rz_next = rz;
+    s->rz_prev = rz;
     s->pq = 0.0;
     s->stop = tol2 * bb;
     s->iters = 0;
+    s->first = 1;
     s->done = rz <= s->stop ? 1 : (isfinite(rz) ? 0 : 2);
   }
 }
 
-__global__ __launch_bounds__(kBlock) void k_cg_apply(Mesh mesh, const double *ML, double dt, const double *p,
-                                                     double *q, double *partials, const CgScalars *s) {
-  if (s->done) return;
-  const uint32_t N = mesh.kind == kGrid ? mesh.grid.N : mesh.ell.N;
-  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+// One iteration's first half: the new direction p = z + beta p_prev (p = z
+// on the first iteration, where p_prev is not read), q = p - dt F p, and
+// alpha = (r, z) / (p, q) in the lumped-mass inner product.
+struct CgDirArgs {
+  const double *ML, *z, *pprev;
+  double *p, *q, *partials;
+  CgScalars *s;
+  double dt;
+};
+
+__device__ __forceinline__ double cg_beta(const CgScalars *s) { return s->first ? 0.0 : s->rz / s->rz_prev; }
+
+template <int DIM>
+__global__ __launch_bounds__(kBlock) void k_cg_dir_apply_tiled(CgDirArgs a, Grid g, uint32_t ntx, uint32_t nty) {
+  using T = Tile<DIM>;
+  if (a.s->done) return;
+  __shared__ double sP[T::NS];
+  const bool first = a.s->first != 0;
+  const double beta = cg_beta(a.s);
+  int x0, y0, z0;
+  tile_origin<DIM>(ntx, nty, x0, y0, z0);
+  for (int r = threadIdx.x; r < T::NS; r += kBlock) {
+    const int hx = r % T::SX, hy = (r / T::SX) % T::SY, hz = r / (T::SX * T::SY);
+    const uint32_t gx = mirror_any(x0 + hx - 1, g.n0);
+    const uint32_t gy = mirror_any(y0 + hy - 1, g.n1);
+    const uint32_t gz = DIM == 3 ? mirror_any(z0 + hz - 1, g.n2) : 0u;
+    const uint32_t j = gx + g.n0 * (gy + g.n1 * gz);
+    sP[r] = first ? a.z[j] : a.z[j] + beta * a.pprev[j];
+  }
+  __syncthreads();
+  uint32_t i;
+  int c;
   double pq = 0.0;
-  if (i < N) {
-    const double qi = p[i] - dt * apply_op<false>(mesh, p, i);
-    q[i] = qi;
-    pq = ML[i] * p[i] * qi;
+  if (tile_node<DIM>(g, x0, y0, z0, i, c)) {
+    const double pi = sP[c];
+    const double qi = pi - a.dt * lds_stencil<DIM, false>(sP, g, c);
+    a.p[i] = pi;
+    a.q[i] = qi;
+    pq = a.ML[i] * pi * qi;
   }
   pq = block_sum(pq);
-  if (threadIdx.x == 0) partials[blockIdx.x] = pq;
+  if (threadIdx.x == 0) a.partials[blockIdx.x] = pq;
 }
 
-// rz takes the value of the previous iteration's update here, after the
-// direction kernel that needed both has run.
-__global__ __launch_bounds__(kBlock) void k_cg_pq_final(const double *partials, uint32_t nb, CgScalars *s) {
-  if (s->done) return;
-  const double pq = block_total(partials, nb);
-  if (threadIdx.x == 0) {
-    s->rz = s->rz_next;
-    s->pq = pq;
+__global__ __launch_bounds__(kBlock) void k_cg_dir_apply_ell(CgDirArgs a, Ell e) {
+  if (a.s->done) return;
+  const bool first = a.s->first != 0;
+  const double beta = cg_beta(a.s);
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  double pq = 0.0;
+  if (i < e.N) {
+    auto pn = [&](uint32_t j) { return first ? a.z[j] : a.z[j] + beta * a.pprev[j]; };
+    const double pi = pn(i);
+    double acc = 0.0;
+    for (uint32_t k = 0; k < e.width; ++k) {
+      const uint32_t c = e.col[(size_t)k * e.N + i];
+      acc = __builtin_fma(e.w64[(size_t)k * e.N + i], pn(c) - pi, acc);
+    }
+    const double qi = pi - a.dt * acc;
+    a.p[i] = pi;
+    a.q[i] = qi;
+    pq = a.ML[i] * pi * qi;
   }
+  pq = block_sum(pq);
+  if (threadIdx.x == 0) a.partials[blockIdx.x] = pq;
 }
 
+// Second half: x += alpha p, r -= alpha q, z = r/diag, rz' = (r, z); the
+// last block rolls the scalars and sets the convergence flag.
 __global__ __launch_bounds__(kBlock) void k_cg_update(uint32_t N, const double *ML, CgDiag dg, double *x, double *r,
                                                       double *z, const double *p, const double *q,
-                                                      double *partials, const CgScalars *s) {
+                                                      double *partials, CgScalars *s) {
   if (s->done) return;
   const double alpha = s->rz / s->pq;
   const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -1236,22 +1278,24 @@ __global__ __launch_bounds__(kBlock) void k_cg_update(uint32_t N, const double *
   if (threadIdx.x == 0) partials[blockIdx.x] = rz;
 }
 
-__global__ __launch_bounds__(kBlock) void k_cg_rz_final(const double *partials, uint32_t nb, CgScalars *s) {
+// One-block reductions of the partial sums, in index order: pq, then rz'
+// with the scalars rolled and the convergence flag set.
+__global__ __launch_bounds__(kBlock) void k_cg_pq_final(const double *partials, uint32_t nb, CgScalars *s) {
   if (s->done) return;
-  const double rz = block_total(partials, nb);
-  if (threadIdx.x == 0) {
-    s->rz_next = rz;
-    s->iters = s->iters + 1;
-    s->done = rz <= s->stop ? 1 : (isfinite(rz) ? 0 : 2);
-  }
+  const double t = block_total(partials, nb);
+  if (threadIdx.x == 0) s->pq = t;
 }
 
-__global__ __launch_bounds__(kBlock) void k_cg_direction(uint32_t N, const double *z, double *p,
-                                                         const CgScalars *s) {
+__global__ __launch_bounds__(kBlock) void k_cg_rz_final(const double *partials, uint32_t nb, CgScalars *s) {
   if (s->done) return;
-  const double beta = s->rz_next / s->rz;
-  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < N) p[i] = z[i] + beta * p[i];
+  const double t = block_total(partials, nb);
+  if (threadIdx.x == 0) {
+    s->rz_prev = s->rz;
+    s->rz = t;
+    s->first = 0;
+    s->iters = s->iters + 1;
+    s->done = t <= s->stop ? 1 : (isfinite(t) ? 0 : 2);
+  }
 }
 
 // Row sums of the ELL weights (the D_i of the preconditioner).
@@ -1564,51 +1608,61 @@ hipError_t launch_imexrl_pre(int model, bool mixed, uint32_t N, const ImexArgs &
 static inline uint32_t mesh_nodes(const Mesh &m) { return m.kind == kGrid ? m.grid.N : m.ell.N; }
 
 hipError_t launch_cg_init(const Mesh &mesh, const double *ML, const double *Dsum, double dconst, double dt,
-                          double tol2, const double *x, const double *b, double *r, double *z, double *p,
-                          double *partials, CgScalars *s, hipStream_t st) {
+                          double tol2, const double *x, const double *b, double *r, double *z, double *partials,
+                          CgScalars *s, hipStream_t st) {
   const uint32_t nb = blocks_for(mesh_nodes(mesh));
-  EMRKC_LAUNCH(k_cg_init, dim3(nb), dim3(kBlock), 0, st, mesh, ML, CgDiag{Dsum, dconst, dt}, x, b, r, z, p,
-               partials);
+  EMRKC_LAUNCH(k_cg_init, dim3(nb), dim3(kBlock), 0, st, mesh, ML, CgDiag{Dsum, dconst, dt}, x, b, r, z, partials);
   EMRKC_LAUNCH(k_cg_init_final, dim3(1), dim3(kBlock), 0, st, partials, nb, tol2, s);
   return hipGetLastError();
 }
 
+// blocks of the direction/operator kernel (its partial sums)
+uint32_t cg_apply_blocks(const Mesh &mesh) {
+  if (mesh.kind == kEll) return blocks_for(mesh.ell.N);
+  uint32_t ntx, nty;
+  return grid_tiles(mesh.grid, ntx, nty, 0);
+}
+
 hipError_t launch_cg_step(int which, const Mesh &mesh, const double *ML, const double *Dsum, double dconst,
-                          double dt, double *x, double *r, double *z, double *p, double *q, double *partials,
-                          CgScalars *s, hipStream_t st) {
+                          double dt, double *x, double *r, double *z, const double *pprev, double *p, double *q,
+                          double *partials, CgScalars *s, hipStream_t st) {
   const uint32_t N = mesh_nodes(mesh);
-  const uint32_t nb = blocks_for(N);
-  switch (which) {
-    case kCgApply:
-      EMRKC_LAUNCH(k_cg_apply, dim3(nb), dim3(kBlock), 0, st, mesh, ML, dt, p, q, partials, s);
-      break;
-    case kCgPqFinal:
-      EMRKC_LAUNCH(k_cg_pq_final, dim3(1), dim3(kBlock), 0, st, partials, nb, s);
-      break;
-    case kCgUpdate:
-      EMRKC_LAUNCH(k_cg_update, dim3(nb), dim3(kBlock), 0, st, N, ML, CgDiag{Dsum, dconst, dt}, x, r, z, p, q,
-                   partials, s);
-      break;
-    case kCgRzFinal:
-      EMRKC_LAUNCH(k_cg_rz_final, dim3(1), dim3(kBlock), 0, st, partials, nb, s);
-      break;
-    case kCgDirection:
-      EMRKC_LAUNCH(k_cg_direction, dim3(nb), dim3(kBlock), 0, st, N, z, p, s);
-      break;
-    default:
-      return hipErrorInvalidValue;
+  if (which == kCgApply) {
+    const CgDirArgs a{ML, z, pprev, p, q, partials, s, dt};
+    if (mesh.kind == kEll) {
+      EMRKC_LAUNCH(k_cg_dir_apply_ell, dim3(blocks_for(N)), dim3(kBlock), 0, st, a, mesh.ell);
+    } else {
+      uint32_t ntx, nty;
+      const uint32_t nb = grid_tiles(mesh.grid, ntx, nty, 0);
+      if (mesh.grid.dim == 3)
+        EMRKC_LAUNCH(k_cg_dir_apply_tiled<3>, dim3(nb), dim3(kBlock), 0, st, a, mesh.grid, ntx, nty);
+      else
+        EMRKC_LAUNCH(k_cg_dir_apply_tiled<2>, dim3(nb), dim3(kBlock), 0, st, a, mesh.grid, ntx, nty);
+    }
+  } else if (which == kCgPqFinal) {
+    EMRKC_LAUNCH(k_cg_pq_final, dim3(1), dim3(kBlock), 0, st, partials, cg_apply_blocks(mesh), s);
+  } else if (which == kCgUpdate) {
+    EMRKC_LAUNCH(k_cg_update, dim3(blocks_for(N)), dim3(kBlock), 0, st, N, ML, CgDiag{Dsum, dconst, dt}, x, r, z, p,
+                 q, partials, s);
+  } else if (which == kCgRzFinal) {
+    EMRKC_LAUNCH(k_cg_rz_final, dim3(1), dim3(kBlock), 0, st, partials, blocks_for(N), s);
+  } else {
+    return hipErrorInvalidValue;
   }
   return hipGetLastError();
 }
 
 hipError_t launch_cg_iterations(const Mesh &mesh, const double *ML, const double *Dsum, double dconst, double dt,
-                                int count, double *x, double *r, double *z, double *p, double *q,
-                                double *partials, CgScalars *s, hipStream_t st) {
-  for (int k = 0; k < count; ++k)
+                                int64_t first_index, int count, double *x, double *r, double *z, double *const P[2],
+                                double *q, double *partials, CgScalars *s, hipStream_t st) {
+  for (int k = 0; k < count; ++k) {
+    const int64_t it = first_index + k;
+    double *pprev = P[it & 1], *p = P[(it + 1) & 1];
     for (int w = 0; w < kCgLaunches; ++w) {
-      const hipError_t e = launch_cg_step(w, mesh, ML, Dsum, dconst, dt, x, r, z, p, q, partials, s, st);
+      const hipError_t e = launch_cg_step(w, mesh, ML, Dsum, dconst, dt, x, r, z, pprev, p, q, partials, s, st);
       if (e != hipSuccess) return e;
     }
+  }
   return hipSuccess;
 }
 

@@ -268,14 +268,14 @@ def emrkc_imexrl_iterations(ctx):
     return int(lib().emrkc_imexrl_iterations(ctx))
 
 
-IMEXRL_KERNELS = ("pointwise", "cg_init", "cg_apply", "cg_update", "cg_direction")
+IMEXRL_KERNELS = ("pointwise", "cg_init", "cg_apply", "cg_update")
 
 
 def emrkc_profile_imexrl(ctx, state, dt, nsteps):
     """Mean kernel durations (ms) and launch counts of IMEX-RL steps, by
     kernel class."""
-    ms = (C.c_double * 5)()
-    cnt = (C.c_int64 * 5)()
+    ms = (C.c_double * 4)()
+    cnt = (C.c_int64 * 4)()
     _check(lib().emrkc_profile_imexrl(ctx, C.byref(state), dt, int(nsteps), ms, cnt), ctx)
     return {k: (ms[i], int(cnt[i])) for i, k in enumerate(IMEXRL_KERNELS)}
 
