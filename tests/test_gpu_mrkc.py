@@ -159,3 +159,28 @@ def test_stage_counts_next_to_emrkc(E):
     assert rFm > 5 * rFe
     assert rSm == pytest.approx(rSe, rel=3e-2)
     assert sm == se and mm > me
+
+
+@pytest.mark.parametrize("name,model", [("c1_2d_hh", None), ("c2_3d_crn", None), ("c2_3d_crn", "TTP_SURR"),
+                                        ("c5_3d_crn_large", None)])
+def test_stage_counts_table(E, name, model):
+    """emRKC against mRKC at full size: the radii each method estimates at
+    rest (f_F and f_S, and f~_F and f~_S) and the stage counts they give at
+    the workload's dt (run with -s for the table).  Moving the stiffest
+    gate into the fast term can only add to its radius."""
+    from workloads.configs import get_config
+    cfg = get_config(name) if model is None else get_config(name, model=model)
+    row = {}
+    for method in ("emrkc", "mrkc"):
+        sim = E.simulation_from_config(cfg, method=method)
+        E.emrkc_init_state(sim.ctx, sim.state)
+        rF, rS, itF, itS, _ = E.emrkc_estimate_rho(sim.ctx, sim.state, allow_noconv=True)
+        s, m = E.emrkc_stages(sim.ctx, cfg["dt"])[:2]
+        row[method] = (rF, rS, s, m, itF, itS)
+        sim.close()
+    print("\n  %s %s dt=%g: emRKC rho_F %.4g rho_S %.4g (s, m) = (%d, %d) its (%d, %d); "
+          "mRKC rho_F %.4g rho_S %.4g (s, m) = (%d, %d) its (%d, %d)"
+          % ((name, cfg["model"], cfg["dt"]) + row["emrkc"][:2] + row["emrkc"][2:4] + row["emrkc"][4:] + row["mrkc"][:2]
+             + row["mrkc"][2:4] + row["mrkc"][4:]))
+    assert row["mrkc"][0] >= 0.99 * row["emrkc"][0]
+    assert row["mrkc"][3] >= row["emrkc"][3]

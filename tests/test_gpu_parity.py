@@ -297,3 +297,29 @@ def test_c2_full_size_prefix_fp64(E):
     rF, rS, _, _ = oracle_rho(prob, prob.uniform_state())
     _compare_full(cfg, 10, (rF, rS))
 
+
+
+@pytest.mark.parametrize("n,rho", [((2, 2, 2), (200.0, 4.4)), ((2, 3), (1600.0, 0.9)), ((3, 2, 5), (300.0, 4.4)),
+                                   ((2, 2, 9), (60.0, 4.4))])
+def test_minimal_grids(E, n, rho):
+    """Grids with two nodes along an axis (every neighbour on that axis is a
+    mirrored boundary node, and one tile or column covers the grid with
+    most threads outside it) against the oracle; on 3-D grids every kernel
+    shape gives the same bits."""
+    base = "c1_2d_hh" if len(n) == 2 else "c2_3d_crn"
+    cfg = small_config(base, n)
+    if len(n) == 2:
+        cfg["h"] = (0.2, 0.2)
+    cfg["stim"]["width"] = 0.5 * min(cfg["h"][:len(n)])  # the corner node only: V varies over the grid
+    nsteps = 30
+    prob, y = oracle_run(cfg, nsteps, rho)
+    assert np.ptp(y[:prob.N]) > 0.1
+    V, z, _ = gpu_run(cfg, nsteps, rho)
+    Y = y.reshape(prob.nv, prob.N)
+    l2, mx = rel_errors(V, Y[0])
+    assert l2 <= 1e-10 and mx <= 1e-10, (l2, mx)
+    assert np.abs(z - Y[1:]).max() <= 1e-10 * np.abs(Y[1:]).max()
+    if len(n) == 3:
+        for v in [(1, 1, 1, 1, 0), (2, n[2], 1, n[2], 0), (2, 1, 0, 0, 1), (3, 0, 1, 2, 0)]:
+            V2, z2, _ = gpu_run(cfg, nsteps, rho, variants=v)
+            assert np.array_equal(V2, V) and np.array_equal(z2, z), v
