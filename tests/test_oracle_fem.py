@@ -63,6 +63,29 @@ def test_p1_single_reference_tet():
     assert np.abs(Me.sum(axis=1) - vol / 4).max() < 1e-16
 
 
+def test_p1_skewed_tet_against_barycentric_interpolation():
+    """A skewed tetrahedron (non-symmetric edge matrix): the element
+    stiffness equals |T| g_a . D g_b with the barycentric gradients g_a
+    obtained independently, as the linear parts of the affine functions
+    that interpolate the unit vectors at the vertices (solve of the 4x4
+    system [1 x y z]); the vectorised assembly of the one-element mesh gives
+    the same matrix, and K reproduces a linear field's flux exactly."""
+    xs = np.array([[0.1, -0.2, 0.05], [1.3, 0.4, -0.1], [0.2, 0.9, 0.3], [-0.1, 0.35, 1.1]])
+    D = fem.conductivity_from_fibre([0.8, -0.3, 0.5], 0.17, 0.019)
+    A = np.hstack([np.ones((4, 1)), xs])
+    coef = np.linalg.solve(A, np.eye(4))          # column a: lambda_a = c0 + g . x
+    g = coef[1:].T                                # row a: gradient of lambda_a
+    vol = abs(np.linalg.det(xs[1:] - xs[0])) / 6.0
+    ref = vol * g @ D @ g.T
+    Ke, _, v = fem.p1_tet_element(xs, D)
+    assert v == pytest.approx(vol, rel=1e-14)
+    assert np.abs(Ke - ref).max() <= 1e-14 * np.abs(ref).max()
+    K, _, _ = fem.assemble_p1_tets(xs, np.array([[0, 1, 2, 3]]), np.array([[0.8, -0.3, 0.5]]), 0.17, 0.019)
+    assert np.abs(K.toarray() - ref).max() <= 1e-14 * np.abs(ref).max()
+    grad = np.array([0.7, -1.2, 0.4])
+    assert np.abs(K @ (xs @ grad) - vol * g @ D @ grad).max() <= 1e-14
+
+
 def test_p1_fibre_conductivity():
     D = fem.conductivity_from_fibre([2.0, 0, 0], 0.17, 0.019)
     assert np.allclose(D, np.diag([0.17, 0.019, 0.019]), atol=1e-16)
