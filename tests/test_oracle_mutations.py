@@ -16,22 +16,30 @@ import test_oracle_models as T_models
 import test_oracle_mrkc as T_mrkc
 import test_oracle_powiter as T_pow
 import test_oracle_rkc as T_rkc
+import test_oracle_variants as T_var
 from oracle.ionic import HH
 
 # a planted mistake may overflow or divide by zero on its way to failing a pin
 pytestmark = pytest.mark.filterwarnings("ignore::RuntimeWarning")
 
 
-def _mutant(modname, old, new):
+def _mutant(modname, old, new, nth=None):
     """A fresh module built from `modname`'s source with `old` replaced by
-    `new` (which must occur exactly once)."""
+    `new`: `old` must occur exactly once, or nth picks its occurrence."""
     mod = importlib.import_module(modname)
     src = open(mod.__file__).read()
-    assert src.count(old) == 1, (modname, old)
+    if nth is None:
+        assert src.count(old) == 1, (modname, old)
+        src = src.replace(old, new)
+    else:
+        at = -1
+        for _ in range(nth + 1):
+            at = src.index(old, at + 1)
+        src = src[:at] + new + src[at + len(old):]
     m = type(mod)(modname)
     m.__package__ = mod.__package__
     m.__file__ = mod.__file__
-    exec(compile(src.replace(old, new), mod.__file__ + " [mutant]", "exec"), m.__dict__)
+    exec(compile(src, mod.__file__ + " [mutant]", "exec"), m.__dict__)
     return mod, m
 
 
@@ -117,6 +125,37 @@ CASES = [
     ("mrkc_gate_index", "oracle.mrkc", "self.gate = slice(N * (1 + stiff_gate), N * (2 + stiff_gate))",
      "self.gate = slice(N * stiff_gate, N * (1 + stiff_gate))",
      [T_mrkc.test_split_sums_to_the_full_right_hand_side]),
+    ("cond_a_factor", "oracle.emrkc", "eta = (6.0 * dt / ls) * (m * m / (m * m - 1.0))",
+     "eta = (2.0 * dt / ls) * (m * m / (m * m - 1.0))",
+     [T_var.test_cond_a_stage_counts_definition, T_var.test_cond_a_scalar_closed_form]),
+    ("progressive_forcing_sign", "oracle.emrkc", "forcing = prob.f_S(t, yE) + (yE - y) / eta",
+     "forcing = prob.f_S(t, yE) - (yE - y) / eta",
+     [T_var.test_progressive_scalar_closed_form, T_var.test_progressive_equals_standard_on_the_monodomain_split]),
+    ("progressive_start_at_yE", "oracle.emrkc", "u_eta = rkc_iteration(t, y, eta, f_u, m, eps)",
+     "u_eta = rkc_iteration(t, yE, eta, f_u, m, eps)",
+     [T_var.test_progressive_scalar_closed_form, T_var.test_progressive_equals_standard_on_the_monodomain_split]),
+    ("rho_every_at_step_zero", "oracle.emrkc", "if rho_every > 0 and n > 0 and n % rho_every == 0:",
+     "if rho_every > 0 and n % rho_every == 0:",
+     [T_var.test_rho_every_schedule_and_warm_start, T_var.test_rho_every_linear_model_warm_start]),
+    ("rho_every_cold_start", "oracle.emrkc",
+     'compute_rho(tn, y, prob.f_F, rho_state["vF"], rho_state["rF"])',
+     'compute_rho(tn, y, prob.f_F, rho_state["vF"])',
+     [T_var.test_rho_every_schedule_and_warm_start, T_var.test_rho_every_linear_model_warm_start]),
+    ("mrkc_outer_count", "oracle.mrkc", "return rkc_iteration(tn, yn, dt, fbar, s, eps)",
+     "return rkc_iteration(tn, yn, dt, fbar, m, eps)",
+     [T_mrkc.test_scalar_test_equation_closed_form, lambda: T_mrkc.test_linear_model_matrix_function((3, 3))]),
+    ("mrkc_slow_term_dropped", "oracle.mrkc", "return f_F(r, u) + fS_frozen", "return f_F(r, u)",
+     [T_mrkc.test_scalar_test_equation_closed_form, lambda: T_mrkc.test_linear_model_matrix_function((3, 3))]),
+    ("exexrl_gate_sign", "oracle.exexrl", "zE1 = zE + np.expm1(dt * LE) * (zE - zinf)",
+     "zE1 = zE + np.expm1(dt * LE) * (zinf - zE)",
+     [T_imex.test_first_order_convergence_against_exexrl], 0),
+    ("exexrl_diffusion_dropped", "oracle.exexrl",
+     "V1 = V + dt * (diff + (prob.I_stim(tn) - I_ion) / prob.Cm)",
+     "V1 = V + dt * ((prob.I_stim(tn) - I_ion) / prob.Cm)",
+     [T_imex.test_first_order_convergence_against_exexrl]),
+    ("imexrl_gate_sign", "oracle.exexrl", "zE1 = zE + np.expm1(dt * LE) * (zE - zinf)",
+     "zE1 = zE + np.expm1(dt * LE) * (zinf - zE)",
+     [lambda: T_imex.test_linear_model_cosine_mode_closed_form(0.5)], 1),
     ("imexrl_explicit_sign", "oracle.exexrl", "return (sp.identity(prob.N, format=\"csr\") - dt * Fm).tocsc()",
      "return (sp.identity(prob.N, format=\"csr\") + dt * Fm).tocsc()",
      [lambda: T_imex.test_linear_model_cosine_mode_closed_form(0.5),
@@ -126,8 +165,8 @@ CASES = [
 
 @pytest.mark.parametrize("case", CASES, ids=[c[0] for c in CASES])
 def test_planted_mistake_is_caught(monkeypatch, case):
-    _, modname, old, new, pins = case
-    mod, mutant = _mutant(modname, old, new)
+    _, modname, old, new, pins = case[:5]
+    mod, mutant = _mutant(modname, old, new, case[5] if len(case) > 5 else None)
     _install(monkeypatch, mod, mutant)
     failed = _some_pin_fails(pins)
     assert failed, "no pin caught the planted mistake %r -> %r in %s" % (old, new, modname)
