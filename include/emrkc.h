@@ -343,7 +343,8 @@ int emrkc_profile_imexrl(emrkc_ctx *ctx, emrkc_state *state, double dt, int64_t 
  * prefetched into registers, 2 = z-marching columns with that state staged
  * through LDS by direct global-to-LDS loads (grids with 8 N < 2^32 only),
  * 3 and 4 = the 3-D tiles compiled for at least 6 and 8 resident waves per
- * SIMD (fewer registers).
+ * SIMD (fewer registers), 5 = flat: one node per thread in index order,
+ * stencil operands read through the caches (the default on 3-D grids).
  * Inner kernel: 0 = 3-D tiles, 1 = z-marching columns.  Planes per column
  * in [1, 64] and at most n[2] for the column kernels, else 0.  Other meshes have
  * one head and one inner shape (entries 0..3 are 0), and so do mRKC
@@ -359,7 +360,8 @@ int emrkc_profile_imexrl(emrkc_ctx *ctx, emrkc_state *state, double dt, int64_t 
  * copy of `state`, which is not modified) and keeps the fastest head and
  * inner kernels, then the fused kernel if a step with it is faster.  A
  * candidate replaces an earlier one only when at least 3% faster.
- * Candidates: tiles (three register budgets for the head), and columns of
+ * Candidates: tiles (three register budgets for the head), the flat head,
+ * and columns of
  * 2, 3, 4, 8, 16 or 32 planes that leave at least 256 blocks; for a batch,
  * the three tile shapes, compared by the time per step.  Needs the
  * radii (the stage plan at dt decides whether the fused kernel applies).  Writes the choice to `variants`

@@ -510,9 +510,9 @@ extern "C" int emrkc_create(const emrkc_mesh *mesh, const emrkc_conductivity *co
       g.zc = zc;
       // short columns re-read too much halo: small grids keep 3-D tiles
       g.inner_variant = (c->dim == 3 && zc >= 4) ? 1 : 0;
-      // head: z-marching with the ionic state staged through LDS where the
-      // columns are long enough, else 3-D tiles (emrkc_autotune refines both)
-      g.head_variant = g.inner_variant ? ((uint64_t)g.N * sizeof(double) < (1ull << 32) ? 2 : 1) : 0;
+      // head: the flat kernel on 3-D grids (measured fastest on the 442k- and
+      // 36M-node slabs), 2-D tiles otherwise (emrkc_autotune refines both)
+      g.head_variant = c->dim == 3 ? 5 : 0;
       g.head_zc = g.zc;
     }
   } else {
@@ -1431,7 +1431,7 @@ static int check_variants(const emrkc_ctx *c, const int *v) {
   if (v[4] < 0 || v[4] > 1 || (v[4] == 1 && !fusable(c))) return EMRKC_EUNSUPPORTED;
   if (!tunable(c)) return (v[0] | v[1] | v[2] | v[3]) == 0 ? EMRKC_OK : EMRKC_EUNSUPPORTED;
   const int n2 = (int)c->mesh.grid.n2;
-  if (v[0] < 0 || v[0] > 4 || v[2] < 0 || v[2] > 1) return EMRKC_EINVAL;
+  if (v[0] < 0 || v[0] > 5 || v[2] < 0 || v[2] > 1) return EMRKC_EINVAL;
   // the LDS-staged head addresses a component plane with 32-bit byte offsets
   if (v[0] == 2 && (uint64_t)c->N * sizeof(double) >= (1ull << 32)) return EMRKC_EUNSUPPORTED;
   const bool head_cols = v[0] == 1 || v[0] == 2;
@@ -1555,6 +1555,7 @@ extern "C" int emrkc_autotune(emrkc_ctx *c, const emrkc_state *st, double dt, in
   // block per compute unit
   std::vector<std::pair<int, int>> heads{{0, 0}}, inners{{0, 0}};
   if (tunable(c)) {
+    heads.push_back({5, 0});  // flat
     heads.push_back({3, 0});  // tiles, 6 and 8 waves per SIMD
     heads.push_back({4, 0});
     const Grid &g = c->mesh.grid;

@@ -562,17 +562,29 @@ __device__ __forceinline__ double lds_stencil(const double *sU, const Grid &g, i
   });
 }
 
+// Tiled head at this thread's node of the tile at (x0, y0, z0): V with its
+// halo staged in LDS, then the node's head.  z planes are Nplane apart; the
+// node's index is off + its index in the grid g; Vg is V of that grid.
+// (Loading the node's ionic state before the barrier, as the inner stage
+// does with its operands, measured slower here: the state's registers are
+// held across the staging.)
+template <template <class> class Model, bool MIXED, int DIM, int SH>
+__device__ __forceinline__ void head_tiled_node(const HeadArgs &a, const Grid &g, uint32_t Nplane, uint32_t off,
+                                                const double *Vg, int x0, int y0, int z0, double *sV) {
+  stage_halo<DIM, SH>(sV, Vg, g, x0, y0, z0);
+  __syncthreads();
+  uint32_t il;
+  int c;
+  if (!tile_node<DIM, SH>(g, x0, y0, z0, il, c)) return;
+  head_node<Model, MIXED>(a, Nplane, off + il, sV[c], [&]() { return lds_stencil<DIM, MIXED, SH>(sV, g, c); });
+}
+
 template <template <class> class Model, bool MIXED, int DIM>
 __global__ __launch_bounds__(kBlock) void k_head_tiled(HeadArgs a, Grid g, uint32_t ntx, uint32_t nty) {
   __shared__ double sV[Tile<DIM>::NS];
   int x0, y0, z0;
   tile_origin<DIM>(ntx, nty, x0, y0, z0);
-  stage_halo<DIM>(sV, a.Vin, g, x0, y0, z0);
-  __syncthreads();
-  uint32_t i;
-  int c;
-  if (!tile_node<DIM>(g, x0, y0, z0, i, c)) return;
-  head_node<Model, MIXED>(a, g.N, i, sV[c], [&]() { return lds_stencil<DIM, MIXED>(sV, g, c); });
+  head_tiled_node<Model, MIXED, DIM, 0>(a, g, g.N, 0u, a.Vin, x0, y0, z0, sV);
 }
 
 // The tiled head compiled for at least WPE resident waves per SIMD (fewer
@@ -583,39 +595,8 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(WPE))) v
   __shared__ double sV[Tile<DIM>::NS];
   int x0, y0, z0;
   tile_origin<DIM>(ntx, nty, x0, y0, z0);
-  stage_halo<DIM>(sV, a.Vin, g, x0, y0, z0);
-  __syncthreads();
-  uint32_t i;
-  int c;
-  if (!tile_node<DIM>(g, x0, y0, z0, i, c)) return;
-  head_node<Model, MIXED>(a, g.N, i, sV[c], [&]() { return lds_stencil<DIM, MIXED>(sV, g, c); });
+  head_tiled_node<Model, MIXED, DIM, 0>(a, g, g.N, 0u, a.Vin, x0, y0, z0, sV);
 }
-
-template <bool MIXED, int DIM>
-__global__ __launch_bounds__(kBlock) void k_inner_tiled(InnerArgs a, Grid g, uint32_t ntx, uint32_t nty) {
-  __shared__ double sU[Tile<DIM>::NS];
-  if (a.tick != nullptr && blockIdx.x == 0 && threadIdx.x == 0) a.tick->step += a.tick_by;
-  int x0, y0, z0;
-  tile_origin<DIM>(ntx, nty, x0, y0, z0);
-  stage_halo<DIM>(sU, a.t.uprev, g, x0, y0, z0);
-  __syncthreads();
-  uint32_t i;
-  int c;
-  if (!tile_node<DIM>(g, x0, y0, z0, i, c)) return;
-  const double Fu = lds_stencil<DIM, MIXED>(sU, g, c);
-  const double uk = inner_value(a.t, Fu, load_sv(a.t.SV, MIXED, i), i);
-  a.out[i] = a.last ? tail_from_um(a.t, uk, i) : uk;
-}
-
-// ---------------------------------------------------------------------------
-// Inner stage on 3-D grids by z-marching columns (2.5-D): a block owns an
-// MX x MY column of zc planes and keeps the planes z-1, z, z+1 of u_{k-1}
-// (with a one-node mirrored halo in x and y) in an LDS ring; plane z+2 is
-// loaded into registers while plane z is computed.  Each plane is read
-// from memory once per column instead of once per neighbouring tile.
-// ---------------------------------------------------------------------------
-constexpr int MSX = MX + 2, MSY = MY + 2, MPL = MSX * MSY;
-constexpr int MSLOT = (MPL + kBlock - 1) / kBlock;
 
 // Pointwise operands of an inner stage at one node, loaded a plane ahead.
 struct InnerPoint {
@@ -641,6 +622,36 @@ __device__ __forceinline__ double inner_point(const InnerArgs &a, double uc, dou
   const double uk = inner_combine(a.t, uc, p.u2, Fu, p.sv);
   return a.last ? tail_combine(a.t, uk, p.vp, p.vp2) : uk;
 }
+
+// The node's pointwise operands are loaded before the halo is staged (both
+// in flight together; global loads cannot move across the barrier).
+template <bool MIXED, int DIM>
+__global__ __launch_bounds__(kBlock) void k_inner_tiled(InnerArgs a, Grid g, uint32_t ntx, uint32_t nty) {
+  __shared__ double sU[Tile<DIM>::NS];
+  if (a.tick != nullptr && blockIdx.x == 0 && threadIdx.x == 0) a.tick->step += a.tick_by;
+  int x0, y0, z0;
+  tile_origin<DIM>(ntx, nty, x0, y0, z0);
+  uint32_t i;
+  int c;
+  const bool own = tile_node<DIM>(g, x0, y0, z0, i, c);
+  InnerPoint pt{0.0, 0.0, 0.0, 0.0};
+  if (own) pt = load_point<MIXED>(a, i);
+  stage_halo<DIM>(sU, a.t.uprev, g, x0, y0, z0);
+  __syncthreads();
+  if (!own) return;
+  const double Fu = lds_stencil<DIM, MIXED>(sU, g, c);
+  a.out[i] = inner_point(a, sU[c], Fu, pt);
+}
+
+// ---------------------------------------------------------------------------
+// Inner stage on 3-D grids by z-marching columns (2.5-D): a block owns an
+// MX x MY column of zc planes and keeps the planes z-1, z, z+1 of u_{k-1}
+// (with a one-node mirrored halo in x and y) in an LDS ring; plane z+2 is
+// loaded into registers while plane z is computed.  Each plane is read
+// from memory once per column instead of once per neighbouring tile.
+// ---------------------------------------------------------------------------
+constexpr int MSX = MX + 2, MSY = MY + 2, MPL = MSX * MSY;
+constexpr int MSLOT = (MPL + kBlock - 1) / kBlock;
 
 template <bool MIXED>
 __global__ __launch_bounds__(kBlock) void k_inner_march(InnerArgs a, Grid g, uint32_t ncx, uint32_t ncy) {
@@ -957,12 +968,7 @@ __device__ __forceinline__ void head_tile(const BatchInst &I, const HeadArgs &h,
                                           uint32_t Ntot) {
   int x0, y0, z0;
   tile_xyz<DIM, SH>(I, tile, x0, y0, z0);
-  stage_halo<DIM, SH>(sV, h.Vin + I.off, I.g, x0, y0, z0);
-  __syncthreads();
-  uint32_t i;
-  int c;
-  if (!tile_node<DIM, SH>(I.g, x0, y0, z0, i, c)) return;
-  head_node<Model, MIXED>(h, Ntot, I.off + i, sV[c], [&]() { return lds_stencil<DIM, MIXED, SH>(sV, I.g, c); });
+  head_tiled_node<Model, MIXED, DIM, SH>(h, I.g, Ntot, I.off, h.Vin + I.off, x0, y0, z0, sV);
 }
 
 template <int SH>
@@ -989,15 +995,17 @@ __device__ __forceinline__ void inner_tile(const BatchInst &I, uint32_t tile, do
   int x0, y0, z0;
   tile_xyz<DIM, SH>(I, tile, x0, y0, z0);
   const InnerArgs &a = I.in;
-  stage_halo<DIM, SH>(sU, a.t.uprev + I.off, I.g, x0, y0, z0);
-  __syncthreads();
   uint32_t il;
   int c;
-  if (!tile_node<DIM, SH>(I.g, x0, y0, z0, il, c)) return;
+  const bool own = tile_node<DIM, SH>(I.g, x0, y0, z0, il, c);
   const uint32_t i = I.off + il;
+  InnerPoint pt{0.0, 0.0, 0.0, 0.0};
+  if (own) pt = load_point<MIXED>(a, i);
+  stage_halo<DIM, SH>(sU, a.t.uprev + I.off, I.g, x0, y0, z0);
+  __syncthreads();
+  if (!own) return;
   const double Fu = lds_stencil<DIM, MIXED, SH>(sU, I.g, c);
-  const double uk = inner_value(a.t, Fu, load_sv(a.t.SV, MIXED, i), i);
-  a.out[i] = a.last ? tail_from_um(a.t, uk, i) : uk;
+  a.out[i] = inner_point(a, sU[c], Fu, pt);
 }
 
 template <bool MIXED, int SH>
@@ -1416,7 +1424,10 @@ void set_flat_kernels(bool flat) { g_flat_kernels = flat; }
 template <template <class> class Model>
 static hipError_t head_dispatch(bool mixed, const Mesh &mesh, const HeadArgs &a, hipStream_t st) {
   const uint32_t N = mesh.kind == kGrid ? mesh.grid.N : mesh.ell.N;
-  if (mesh.kind == kGrid && !g_flat_kernels) {
+  // head shape 5 on grids: the flat kernel below (one node per thread in
+  // index order, stencil operands through the caches; no LDS staging, no
+  // block barrier, no tile padding)
+  if (mesh.kind == kGrid && !g_flat_kernels && mesh.grid.head_variant != 5) {
     uint32_t ntx, nty;
     const Grid &g = mesh.grid;
     if (g.dim == 3 && (g.head_variant == 1 || g.head_variant == 2)) {
