@@ -264,7 +264,8 @@ def main():
             if tr.get("kernel_source_hash") == kernel_hash() and ent is not None:
                 traffic = ent.get("bytes_per_launch")
         head_kernel = ("k_mrkc_head" if args.method == "mrkc" else
-                       "k_head_batch<tile shape %d>" % variants[0] if batch is not None else
+                       ("k_head_batch_flat" if variants[1] else "k_head_batch<tile shape %d>" % variants[0])
+                       if batch is not None else
                        "k_head" if tet is not None else
                        {0: "k_head_tiled", 1: "k_head_march", 2: "k_head_march_lds", 3: "k_head_tiled_occ<6 waves/SIMD>",
                         4: "k_head_tiled_occ<8 waves/SIMD>", 5: "k_head (flat)"}[variants[0]])

@@ -350,7 +350,9 @@ int emrkc_profile_imexrl(emrkc_ctx *ctx, emrkc_state *state, double dt, int64_t 
  * one head and one inner shape (entries 0..3 are 0), and so do mRKC
  * contexts (flat kernels, no fused kernel).  Batch contexts: variants[0] is
  * the tile shape of the batched head and inner kernels (0: 16x4x4 in 3-D,
- * 64x4 in 2-D; 1: 32x4x2 / 32x8; 2: 8x8x4 / 128x2), the others are 0.
+ * 64x4 in 2-D; 1: 32x4x2 / 32x8; 2: 8x8x4 / 128x2), variants[1] = 1 makes
+ * the head flat (blocks of 256 consecutive nodes of an instance, the
+ * inner stages keep the tiles), the others are 0.
  * fused = 1 (structured grids, single contexts): when s == 1 and m >= 2,
  * the last inner stage of each step and the head of the next are one
  * kernel on 3-D or 2-D tiles.
@@ -363,7 +365,8 @@ int emrkc_profile_imexrl(emrkc_ctx *ctx, emrkc_state *state, double dt, int64_t 
  * Candidates: tiles (three register budgets for the head), the flat head,
  * and columns of
  * 2, 3, 4, 8, 16 or 32 planes that leave at least 256 blocks; for a batch,
- * the three tile shapes, compared by the time per step.  Needs the
+ * the three tile shapes, then the flat head with the chosen shape,
+ * compared by the time per step.  Needs the
  * radii (the stage plan at dt decides whether the fused kernel applies).  Writes the choice to `variants`
  * (int[5]) when non-NULL.  Allocates a temporary copy of the state;
  * synchronises the stream.  Returns the fixed choice where nothing can be

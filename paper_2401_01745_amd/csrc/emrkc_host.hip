@@ -57,7 +57,7 @@ struct BatchDev {
   bool valid = false;
   uint64_t dt_bits = 0;
   const void *V = nullptr, *z = nullptr;  // state buffers the tables point into
-  int shape = 0;                          // tile shape the tables were built for
+  int shape = 0;                          // tile shape the tables were built for (+3: flat head)
   int s = 0, m_max = 0;
   double eta = 0;
   BatchLaunch head[2];
@@ -107,6 +107,7 @@ struct emrkc_ctx {
   int rho_every = 0;          // params.rho_every
   int method = EMRKC_METHOD_EMRKC;
   int batch_shape = 0;        // tile shape of the batched kernels (0..2)
+  bool batch_flat_head = true;   // batched head: flat kernel (measured faster) instead of the tiles
   double *d_ML = nullptr;     // lumped mass (tets at creation, grids on first IMEX-RL step)
   double *d_cgq = nullptr;    // IMEX-RL: the conjugate gradient's B p
   double *d_Dsum = nullptr;   // IMEX-RL on tets: row sums of the operator's weights
@@ -1411,7 +1412,8 @@ static bool fusable(const emrkc_ctx *c) {  // the fused kernel (emRKC, used when
 static void get_variants(const emrkc_ctx *c, int *v) {
   if (c->batch) {
     v[0] = c->batch_shape;
-    v[1] = v[2] = v[3] = v[4] = 0;
+    v[1] = c->batch_flat_head ? 1 : 0;
+    v[2] = v[3] = v[4] = 0;
     return;
   }
   const Grid &g = c->mesh.grid;
@@ -1425,8 +1427,8 @@ static void get_variants(const emrkc_ctx *c, int *v) {
 
 static int check_variants(const emrkc_ctx *c, const int *v) {
   if (c->batch) {
-    if (v[0] < 0 || v[0] > 2) return EMRKC_EINVAL;
-    return (v[1] | v[2] | v[3] | v[4]) == 0 ? EMRKC_OK : EMRKC_EUNSUPPORTED;
+    if (v[0] < 0 || v[0] > 2 || v[1] < 0 || v[1] > 1) return EMRKC_EINVAL;
+    return (v[2] | v[3] | v[4]) == 0 ? EMRKC_OK : EMRKC_EUNSUPPORTED;
   }
   if (v[4] < 0 || v[4] > 1 || (v[4] == 1 && !fusable(c))) return EMRKC_EUNSUPPORTED;
   if (!tunable(c)) return (v[0] | v[1] | v[2] | v[3]) == 0 ? EMRKC_OK : EMRKC_EUNSUPPORTED;
@@ -1445,6 +1447,7 @@ static int check_variants(const emrkc_ctx *c, const int *v) {
 static void set_variants(emrkc_ctx *c, const int *v) {
   if (c->batch) {
     c->batch_shape = v[0];
+    c->batch_flat_head = v[1] != 0;
     clear_graphs(c);
     return;
   }
@@ -1531,8 +1534,21 @@ static int autotune_batch(emrkc_ctx *c, const emrkc_state *st, double dt, int re
       choice = shape;
     }
   }
+  // the flat head with the chosen tiles for the inner stages
+  int flat = 0;
+  if (rc == EMRKC_OK) {
+    const int v[5] = {choice, 1, 0, 0, 0};
+    set_variants(c, v);
+    double ms[3];
+    if ((rc = build_batch_tables(c, &cp.st, dt, P)) == EMRKC_OK &&
+        (rc = time_classes(c, &cp.st, P, dt, reps, ms)) == EMRKC_OK) {
+      const double step = ms[0] + (P.m - 1) * ms[1];
+      if (verbose) fprintf(stderr, "emrkc_autotune: batch flat head: head %.5f ms, step %.5f ms\n", ms[0], step);
+      if (step < 0.97 * best) flat = 1;
+    }
+  }
   (void)hipStreamSynchronize(c->stream);
-  const int v[5] = {rc == EMRKC_OK ? choice : orig[0], 0, 0, 0, 0};
+  const int v[5] = {rc == EMRKC_OK ? choice : orig[0], rc == EMRKC_OK ? flat : orig[1], 0, 0, 0};
   set_variants(c, v);
   c->bdev.valid = false;  // the tables point into the state copy
   if (rc == EMRKC_OK && variants) get_variants(c, variants);
@@ -2236,8 +2252,9 @@ static int estimate_batch(emrkc_ctx *c, const emrkc_state *st, double *rho_F, do
 static int build_batch_tables(emrkc_ctx *c, const emrkc_state *st, double dt, const StepPlan &P) {
   uint64_t dtb;
   memcpy(&dtb, &dt, sizeof dtb);
+  const int shape_key = c->batch_shape + (c->batch_flat_head ? 3 : 0);
   if (c->bdev.valid && c->bdev.dt_bits == dtb && c->bdev.V == st->V && c->bdev.z == st->z &&
-      c->bdev.shape == c->batch_shape)
+      c->bdev.shape == shape_key)
     return EMRKC_OK;
   (void)hipStreamSynchronize(c->stream);
   clear_graphs(c);
@@ -2265,7 +2282,9 @@ static int build_batch_tables(emrkc_ctx *c, const emrkc_state *st, double dt, co
         b.g = I.mesh.grid;
         b.off = I.off;
         b.tile0 = (uint32_t)map.size();
-        const uint32_t nt = grid_tiles(b.g, b.ntx, b.nty, c->batch_shape);
+        // head launch with the flat kernel: blocks of 256 consecutive nodes
+        const uint32_t nt = (k == 1 && c->batch_flat_head) ? (b.g.N + 255u) / 256u
+                                                          : grid_tiles(b.g, b.ntx, b.nty, c->batch_shape);
         if (k == 1) {
           HeadArgs &h = b.h;
           h.Vin = X[par];
@@ -2320,7 +2339,7 @@ static int build_batch_tables(emrkc_ctx *c, const emrkc_state *st, double dt, co
   }
   c->bdev.valid = true;
   c->bdev.dt_bits = dtb;
-  c->bdev.shape = c->batch_shape;
+  c->bdev.shape = shape_key;
   c->bdev.V = st->V;
   c->bdev.z = st->z;
   c->bdev.s = P.s;
@@ -2339,7 +2358,8 @@ static int enqueue_chunk_batch(emrkc_ctx *c, const emrkc_state *st, const StepPl
   for (int n = 0; n < L; ++n) {
     const int par = n % 2;
     const BatchLaunch &H = c->bdev.head[par];
-    TIMED(0, launch_head_batch(c->model, c->mixed, c->batch_shape, H.tab, H.map, H.nblocks, Ntot, n, strm));
+    TIMED(0, launch_head_batch(c->model, c->mixed, c->batch_flat_head ? kBatchFlatHead : c->batch_shape, H.tab, H.map,
+                               H.nblocks, Ntot, n, strm));
     for (const BatchLaunch &B : c->bdev.inner[par])
       if (B.nblocks) TIMED(1, launch_inner_batch(c->mixed, c->batch_shape, B.tab, B.map, B.nblocks, Ntot, strm));
   }

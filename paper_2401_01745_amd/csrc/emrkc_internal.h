@@ -161,6 +161,9 @@ void set_launch_events(hipEvent_t start, hipEvent_t stop);
 // Tiles of a grid in the LDS-tiled layout of tile shape `shape` (0: 3-D
 // 16x4x4 / 2-D 64x4, 1: 32x4x2 / 32x8, 2: 8x8x4 / 128x2).
 uint32_t grid_tiles(const Grid &g, uint32_t &ntx, uint32_t &nty, int shape = 0);
+// shape kBatchFlatHead: the flat head, whose table maps blocks of 256
+// consecutive nodes of an instance (tile0 = the instance's first block)
+constexpr int kBatchFlatHead = 3;
 hipError_t launch_head_batch(int model, bool mixed, int shape, const BatchInst *tab, const uint16_t *map,
                              uint32_t nblocks, uint32_t Ntot, int step_off, hipStream_t st);
 hipError_t launch_inner_batch(bool mixed, int shape, const BatchInst *tab, const uint16_t *map, uint32_t nblocks,

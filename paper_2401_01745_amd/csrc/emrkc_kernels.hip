@@ -990,6 +990,27 @@ __global__ __launch_bounds__(kBlock) void k_head_batch(const BatchInst *__restri
     head_tile<Model, MIXED, 2, SH>(I, h, lb - I.tile0, sV, Ntot);
 }
 
+// Flat batched head: block b covers nodes 256 (b - tile0) .. of its
+// instance, one node per thread, stencil operands through the caches (no LDS
+// staging, no barrier).
+template <template <class> class Model, bool MIXED>
+__global__ __launch_bounds__(kBlock) void k_head_batch_flat(const BatchInst *__restrict__ tab,
+                                                            const uint16_t *__restrict__ map, uint32_t Ntot,
+                                                            int step_off) {
+  const uint32_t lb = xcd_block(blockIdx.x, gridDim.x);
+  const BatchInst &I = tab[map[lb]];
+  const uint32_t il = (lb - I.tile0) * kBlock + threadIdx.x;
+  if (il >= I.g.N) return;
+  HeadArgs h = I.h;
+  h.step_off = step_off;
+  const double *Vg = h.Vin + I.off;
+  head_node<Model, MIXED>(h, Ntot, I.off + il, Vg[il], [&]() {
+    uint32_t ix, iy, iz;
+    grid_coords(I.g, il, ix, iy, iz);
+    return I.g.dim == 3 ? grid_apply<3, MIXED>(Vg, I.g, ix, iy, iz) : grid_apply<2, MIXED>(Vg, I.g, ix, iy, iz);
+  });
+}
+
 template <bool MIXED, int DIM, int SH>
 __device__ __forceinline__ void inner_tile(const BatchInst &I, uint32_t tile, double *sU) {
   int x0, y0, z0;
@@ -1742,6 +1763,13 @@ static hipError_t head_batch_dispatch(bool mixed, int shape, const BatchInst *ta
                                       uint32_t Ntot, int step_off, hipStream_t st) {
   if (shape == 1) return head_batch_launch<Model, 1>(mixed, tab, map, nb, Ntot, step_off, st);
   if (shape == 2) return head_batch_launch<Model, 2>(mixed, tab, map, nb, Ntot, step_off, st);
+  if (shape == kBatchFlatHead) {
+    if (mixed)
+      EMRKC_LAUNCH((k_head_batch_flat<Model, true>), dim3(nb), dim3(kBlock), 0, st, tab, map, Ntot, step_off);
+    else
+      EMRKC_LAUNCH((k_head_batch_flat<Model, false>), dim3(nb), dim3(kBlock), 0, st, tab, map, Ntot, step_off);
+    return hipGetLastError();
+  }
   return head_batch_launch<Model, 0>(mixed, tab, map, nb, Ntot, step_off, st);
 }
 
