@@ -362,8 +362,8 @@ int emrkc_profile_imexrl(emrkc_ctx *ctx, emrkc_state *state, double dt, int64_t 
  * copy of `state`, which is not modified) and keeps the fastest head and
  * inner kernels, then the fused kernel if a step with it is faster.  A
  * candidate replaces an earlier one only when at least 3% faster.
- * Candidates: tiles (three register budgets for the head), the flat head,
- * and columns of
+ * Candidates: the flat head (first, the default), tiles (three register
+ * budgets for the head), and columns of
  * 2, 3, 4, 8, 16 or 32 planes that leave at least 256 blocks; for a batch,
  * the three tile shapes, then the flat head with the chosen shape,
  * compared by the time per step.  Needs the

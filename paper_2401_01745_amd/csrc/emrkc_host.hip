@@ -1569,10 +1569,12 @@ extern "C" int emrkc_autotune(emrkc_ctx *c, const emrkc_state *st, double dt, in
   // shape candidates (3-D grids): 3-D tiles, and z-marching columns of zc
   // planes for every zc in {2, 3, 4, 8, 16, 32} that leaves at least one
   // block per compute unit
-  std::vector<std::pair<int, int>> heads{{0, 0}}, inners{{0, 0}};
+  // the flat head (the default) is the first head candidate: another shape
+  // must beat it by the margin below
+  std::vector<std::pair<int, int>> heads{{5, 0}}, inners{{0, 0}};
   if (tunable(c)) {
-    heads.push_back({5, 0});  // flat
-    heads.push_back({3, 0});  // tiles, 6 and 8 waves per SIMD
+    heads.push_back({0, 0});  // tiles; and tiles for 6 and 8 waves per SIMD
+    heads.push_back({3, 0});
     heads.push_back({4, 0});
     const Grid &g = c->mesh.grid;
     const uint32_t cols = ((g.n0 + MX - 1) / MX) * ((g.n1 + MY - 1) / MY);
@@ -1604,8 +1606,8 @@ extern "C" int emrkc_autotune(emrkc_ctx *c, const emrkc_state *st, double dt, in
       fprintf(stderr, "emrkc_autotune: head %d/%d %.5f ms, inner %d/%d %.5f ms\n", v[0], v[1], ms[0], v[2], v[3],
               ms[1]);
     // a later candidate must be faster by 3% to replace the current choice
-    // (the first candidates are the plain tiles), so that timing noise does
-    // not pick among near-equals
+    // (the first candidates are the flat head and the tiled inner stage), so
+    // that timing noise does not pick among near-equals
     if (ms[0] > 0 && ms[0] < 0.97 * best_h) {
       best_h = ms[0];
       choice[0] = v[0];
