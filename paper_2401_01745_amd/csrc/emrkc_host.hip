@@ -1750,9 +1750,10 @@ static int alloc_rho_buffers(emrkc_ctx *c) {
 }
 
 // ---- mRKC: the power iteration on full-state vectors ----------------------
-// The oracle's Compute_Rho on f~_F and f~_S, literally: vectors of all n_v N
-// components (zero where a term has no component), the same splitmix64 start
-// over all of them, and the warm start kept per term.
+// Compute_Rho of the appendix applied to f~_F and f~_S as whole right-hand
+// sides: vectors of all n_v N components (zero where a term has no
+// component), the same splitmix64 start over all of them, and the warm
+// start kept per term.
 static int mrkc_buffers(emrkc_ctx *c) {
   if (c->d_Y) return EMRKC_OK;
   const uint64_t n = (uint64_t)c->nv * (uint64_t)c->N;
