@@ -56,6 +56,7 @@ extern "C" {
 /* ---- enumerations ------------------------------------------------------- */
 #define EMRKC_MESH_Q1_GRID 1    /* structured Q1 grid, 2-D or 3-D            */
 #define EMRKC_MESH_P1_TET 2     /* unstructured P1 tetrahedra                */
+#define EMRKC_MESH_CSR 3        /* assembled operator A = -K in CSR form     */
 
 #define EMRKC_MODEL_HH 1        /* classical Hodgkin-Huxley (N = 3 gates)     */
 #define EMRKC_MODEL_LINEAR 2    /* linear test model: i_ion = a V, 1 gate     */
@@ -98,7 +99,17 @@ typedef struct emrkc_ctx emrkc_ctx;
  * n_elems, coords[n_nodes][3], tets[n_elems][4] (0-based node indices,
  * any orientation) and fibres[n_elems][3] (fibre direction a_l, any
  * non-zero length); element conductivity D = sigma_l a a^T +
- * sigma_t (I - a a^T) (eq. def_D with sigma_n = sigma_t). */
+ * sigma_t (I - a a^T) (eq. def_D with sigma_n = sigma_t).
+ * For EMRKC_MESH_CSR (the semi-discrete system of section "Space
+ * discretization" with the matrices given): n_nodes = n, row_ptr[n + 1]
+ * (row_ptr[0] = 0, non-decreasing), col_idx[row_ptr[n]] (0-based, any
+ * order, duplicates summed) and values[row_ptr[n]] hold A = -K, already
+ * assembled with the conductivity (the conductivity argument is ignored
+ * and may be NULL); lumped_mass[n] > 0 is M_L.  f_F(V) = (chi Cm
+ * M_L)^{-1} A V.  Every row must sum to zero within 1e-10 of the sum of
+ * its magnitudes (A 1 = 0: a zero-flux stiffness operator), since the
+ * library applies A in difference form, sum_j A_ij (V_j - V_i); at most 64
+ * off-diagonal entries per row.  All arrays are host memory, copied. */
 typedef struct {
   int32_t kind;
   int32_t dim;
@@ -109,6 +120,10 @@ typedef struct {
   const double *coords;
   const int64_t *tets;
   const double *fibres;
+  const int64_t *row_ptr;      /* EMRKC_MESH_CSR */
+  const int32_t *col_idx;
+  const double *values;
+  const double *lumped_mass;
 } emrkc_mesh;
 
 /* Effective conductivities (eq. def_D).  Q1 grids use D = diag(sigma_l,

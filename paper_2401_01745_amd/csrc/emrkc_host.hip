@@ -403,6 +403,7 @@ static int dalloc(emrkc_ctx *c, void **p, size_t bytes) {
 }
 
 static int build_p1(emrkc_ctx *c, const emrkc_mesh *mesh, const emrkc_conductivity *cond);
+static int build_csr(emrkc_ctx *c, const emrkc_mesh *mesh);
 
 extern "C" int emrkc_create(const emrkc_mesh *mesh, const emrkc_conductivity *cond, int ionic_model,
                             const emrkc_params *p, emrkc_ctx **out) {
@@ -440,6 +441,10 @@ extern "C" int emrkc_create(const emrkc_mesh *mesh, const emrkc_conductivity *co
     if (cond == nullptr || mesh->n_nodes < 4 || mesh->n_elems < 1 || !mesh->coords || !mesh->tets || !mesh->fibres)
       return EMRKC_EINVAL;
     if (!(cond->sigma_l >= 0) || !(cond->sigma_t >= 0) || !isfinite(cond->sigma_l) || !isfinite(cond->sigma_t))
+      return EMRKC_EINVAL;
+    N = mesh->n_nodes;
+  } else if (mesh->kind == EMRKC_MESH_CSR) {
+    if (mesh->n_nodes < 2 || !mesh->row_ptr || !mesh->col_idx || !mesh->values || !mesh->lumped_mass)
       return EMRKC_EINVAL;
     N = mesh->n_nodes;
   } else {
@@ -516,8 +521,11 @@ extern "C" int emrkc_create(const emrkc_mesh *mesh, const emrkc_conductivity *co
       g.head_variant = c->dim == 3 ? 5 : 0;
       g.head_zc = g.zc;
     }
-  } else {
+  } else if (mesh->kind == EMRKC_MESH_P1_TET) {
     rc = build_p1(c, mesh, cond);
+    if (rc != EMRKC_OK) goto error;
+  } else {
+    rc = build_csr(c, mesh);
     if (rc != EMRKC_OK) goto error;
   }
 
@@ -1940,6 +1948,9 @@ extern "C" int emrkc_eval_rhs_slow(emrkc_ctx *c, const emrkc_state *st, double t
 // first appearance in the element list; unused slots repeat the row index
 // with weight 0.
 // ---------------------------------------------------------------------------
+static int upload_ell(emrkc_ctx *c, int64_t N, int maxdeg, const std::vector<uint32_t> &ncol,
+                      const std::vector<double> &aval, const std::vector<uint8_t> &deg, const std::vector<double> &ML);
+
 static int build_p1(emrkc_ctx *c, const emrkc_mesh *mesh, const emrkc_conductivity *cond) {
   const int64_t N = mesh->n_nodes, E = mesh->n_elems;
   const double *X = mesh->coords;
@@ -2011,11 +2022,20 @@ static int build_p1(emrkc_ctx *c, const emrkc_mesh *mesh, const emrkc_conductivi
       }
     }
   }
-  uint32_t width = 1;
-  for (int64_t i = 0; i < N; ++i) {
+  for (int64_t i = 0; i < N; ++i)
     if (!(ML[i] > 0)) return fail(c, EMRKC_EINVAL, "node %lld belongs to no element", (long long)i);
-    width = std::max<uint32_t>(width, deg[i]);
-  }
+  // the off-diagonal entries of A = -K
+  for (double &v : nval) v = -v;
+  return upload_ell(c, N, kMaxDeg, ncol, nval, deg, ML);
+}
+
+// The ELL operator (chi Cm M_L)^{-1} A in difference form from the
+// off-diagonal entries of A: row i has deg[i] neighbours ncol[i maxdeg + k]
+// with values aval[i maxdeg + k]; also keeps M_L on the device.
+static int upload_ell(emrkc_ctx *c, int64_t N, int maxdeg, const std::vector<uint32_t> &ncol,
+                      const std::vector<double> &aval, const std::vector<uint8_t> &deg, const std::vector<double> &ML) {
+  uint32_t width = 1;
+  for (int64_t i = 0; i < N; ++i) width = std::max<uint32_t>(width, deg[i]);
   const double chiCm = c->chi * c->Cm;
   std::vector<uint32_t> col((size_t)width * N);
   std::vector<double> w64((size_t)width * N);
@@ -2024,8 +2044,8 @@ static int build_p1(emrkc_ctx *c, const emrkc_mesh *mesh, const emrkc_conductivi
     for (uint32_t k = 0; k < width; ++k) {
       const bool used = k < deg[i];
       const size_t o = (size_t)k * N + i;
-      col[o] = used ? ncol[(size_t)i * kMaxDeg + k] : (uint32_t)i;
-      w64[o] = used ? -nval[(size_t)i * kMaxDeg + k] / (chiCm * ML[i]) : 0.0;
+      col[o] = used ? ncol[(size_t)i * maxdeg + k] : (uint32_t)i;
+      w64[o] = used ? aval[(size_t)i * maxdeg + k] / (chiCm * ML[i]) : 0.0;
       w32[o] = (float)w64[o];
     }
   }
@@ -2048,6 +2068,51 @@ static int build_p1(emrkc_ctx *c, const emrkc_mesh *mesh, const emrkc_conductivi
   if ((rc = dalloc(c, (void **)&c->d_ML, ML.size() * sizeof(double)))) return rc;
   HIP_TRY(c, hipMemcpy(c->d_ML, ML.data(), ML.size() * sizeof(double), hipMemcpyHostToDevice));
   return EMRKC_OK;
+}
+
+// Assembled operator A = -K (CSR) and lumped mass given by the caller:
+// off-diagonal entries (duplicates summed) become the ELL difference form;
+// rows must sum to zero, which makes the diagonal implied.
+static int build_csr(emrkc_ctx *c, const emrkc_mesh *mesh) {
+  const int64_t N = mesh->n_nodes;
+  const int64_t *rp = mesh->row_ptr;
+  constexpr int kMaxDeg = 64;
+  if (rp[0] != 0) return fail(c, EMRKC_EINVAL, "CSR row_ptr[0] must be 0");
+  std::vector<uint32_t> ncol((size_t)N * kMaxDeg);
+  std::vector<double> aval((size_t)N * kMaxDeg, 0.0);
+  std::vector<uint8_t> deg((size_t)N, 0);
+  std::vector<double> ML((size_t)N);
+  for (int64_t i = 0; i < N; ++i) {
+    if (rp[i + 1] < rp[i]) return fail(c, EMRKC_EINVAL, "CSR row_ptr decreases at row %lld", (long long)i);
+    const double m = mesh->lumped_mass[i];
+    if (!(m > 0) || !isfinite(m)) return fail(c, EMRKC_EINVAL, "lumped mass of node %lld is not positive", (long long)i);
+    ML[i] = m;
+    double sum = 0.0, mag = 0.0;
+    for (int64_t e = rp[i]; e < rp[i + 1]; ++e) {
+      const int64_t j = mesh->col_idx[e];
+      const double v = mesh->values[e];
+      if (j < 0 || j >= N) return fail(c, EMRKC_EINVAL, "CSR column %lld out of range in row %lld", (long long)j,
+                                       (long long)i);
+      if (!isfinite(v)) return fail(c, EMRKC_EINVAL, "CSR value not finite in row %lld", (long long)i);
+      sum += v;
+      mag += fabs(v);
+      if (j == i) continue;
+      const size_t row = (size_t)i * kMaxDeg;
+      int k = 0;
+      while (k < deg[i] && ncol[row + k] != (uint32_t)j) ++k;
+      if (k == deg[i]) {
+        if (k == kMaxDeg)
+          return fail(c, EMRKC_EUNSUPPORTED, "row %lld has more than %d off-diagonal entries", (long long)i, kMaxDeg);
+        ncol[row + k] = (uint32_t)j;
+        deg[i] = (uint8_t)(k + 1);
+      }
+      aval[row + k] += v;
+    }
+    if (fabs(sum) > 1e-10 * mag)
+      return fail(c, EMRKC_EINVAL, "CSR row %lld does not sum to zero (%g of %g): A 1 = 0 is required", (long long)i,
+                  sum, mag);
+  }
+  return upload_ell(c, N, kMaxDeg, ncol, aval, deg, ML);
 }
 
 // ---------------------------------------------------------------------------

@@ -23,6 +23,7 @@ ERROR_NAMES = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EHIP", -4: "ENONFINITE"
 
 EMRKC_MESH_Q1_GRID = 1
 EMRKC_MESH_P1_TET = 2
+EMRKC_MESH_CSR = 3
 MODELS = {"HH": 1, "LINEAR": 2, "CRN_SURR": 3, "TTP_SURR": 4}
 EMRKC_FP64 = 0
 EMRKC_MIXED32 = 1
@@ -39,7 +40,8 @@ EMRKC_FLAT = 8           # library-internal flag: flat (untiled) grid kernels
 class Mesh(C.Structure):
     _fields_ = [("kind", C.c_int32), ("dim", C.c_int32), ("n", C.c_int64 * 3), ("h", C.c_double * 3),
                 ("n_nodes", C.c_int64), ("n_elems", C.c_int64), ("coords", C.c_void_p),
-                ("tets", C.c_void_p), ("fibres", C.c_void_p)]
+                ("tets", C.c_void_p), ("fibres", C.c_void_p), ("row_ptr", C.c_void_p), ("col_idx", C.c_void_p),
+                ("values", C.c_void_p), ("lumped_mass", C.c_void_p)]
 
 
 class Conductivity(C.Structure):
@@ -437,6 +439,52 @@ def simulation_from_config(cfg, precision=None, rho=None, flags=0, stim_mask=Non
     p.linear_a = model_kw.get("a", 0.0)
     p.linear_lambda_E = model_kw.get("lam_E", 0.0)
     return Simulation(mesh, cond, cfg["model"], p, keep=(mask,))
+
+
+def csr_mesh(row_ptr, col_idx, values, lumped_mass):
+    """CSR mesh struct (A = -K and M_L given); the numpy arrays must stay
+    alive during emrkc_create."""
+    import numpy as np
+    m = Mesh()
+    m.kind = EMRKC_MESH_CSR
+    m.n_nodes = lumped_mass.shape[0]
+    assert row_ptr.dtype == np.int64 and col_idx.dtype == np.int32
+    assert values.dtype == np.float64 and lumped_mass.dtype == np.float64
+    for a in (row_ptr, col_idx, values, lumped_mass):
+        assert a.flags.c_contiguous
+    m.row_ptr = row_ptr.ctypes.data
+    m.col_idx = col_idx.ctypes.data
+    m.values = values.ctypes.data
+    m.lumped_mass = lumped_mass.ctypes.data
+    return m
+
+
+def simulation_from_csr(A, ML, chi, Cm, model, stim_mask=None, stim=None, precision="fp64", rho=None, flags=0,
+                        method="emrkc"):
+    """Simulation for an assembled operator: A = -K (scipy sparse, any
+    format) and the lumped mass ML; stim = dict(amp, t_on, t_off)."""
+    import numpy as np
+    Ac = A.tocsr()
+    row_ptr = np.ascontiguousarray(Ac.indptr, dtype=np.int64)
+    col_idx = np.ascontiguousarray(Ac.indices, dtype=np.int32)
+    values = np.ascontiguousarray(Ac.data, dtype=np.float64)
+    ml = np.ascontiguousarray(ML, dtype=np.float64)
+    m = csr_mesh(row_ptr, col_idx, values, ml)
+    p = emrkc_default_params()
+    p.chi = chi
+    p.Cm = Cm
+    p.precision = PRECISIONS[precision]
+    p.flags = flags
+    keep = [row_ptr, col_idx, values, ml]
+    if stim_mask is not None:
+        mask = np.ascontiguousarray(stim_mask, dtype=np.uint8)
+        p.stim_mask = mask.ctypes.data
+        keep.append(mask)
+        p.stim_amp, p.stim_t_on, p.stim_t_off = stim["amp"], stim["t_on"], stim["t_off"]
+    if rho is not None:
+        p.rho_F, p.rho_S = rho
+    p.method = METHODS[method]
+    return Simulation(m, None, model, p, keep=tuple(keep))
 
 
 def simulation_from_tet_config(cfg, mesh, mask, precision=None, rho=None, flags=0, method="emrkc"):

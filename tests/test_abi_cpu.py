@@ -124,6 +124,24 @@ def test_invalid_arguments_rejected_before_any_gpu_call():
     q = E.emrkc_default_params()
     q.rho_every = -1
     assert create(good, cond, 1, q) == E.EMRKC_EINVAL
+    # assembled operators: arrays missing, or fewer than two nodes
+    import numpy as np
+    rp = np.array([0, 1, 2], np.int64)
+    ci = np.array([1, 0], np.int32)
+    va = np.array([1.0, 1.0])
+    ml = np.array([1.0, 1.0])
+    csr = E.csr_mesh(rp, ci, va, ml)
+    for field in ("row_ptr", "col_idx", "values", "lumped_mass"):
+        m = E.csr_mesh(rp, ci, va, ml)
+        setattr(m, field, None)
+        assert create(m, None, 3, p) == E.EMRKC_EINVAL
+    m = E.csr_mesh(rp, ci, va, ml)
+    m.n_nodes = 1
+    assert create(m, None, 3, p) == E.EMRKC_EINVAL
+    unknown = E.csr_mesh(rp, ci, va, ml)
+    unknown.kind = 9
+    assert create(unknown, None, 3, p) == E.EMRKC_EINVAL
+    assert csr.kind == E.EMRKC_MESH_CSR
     assert ctx.value is None
     # ensembles: no condition-A stage counts, no periodic re-estimation
     meshes = (E.Mesh * 1)(good)
