@@ -258,11 +258,18 @@ def main():
         # were taken on these kernel sources for the kernel shape chosen here
         prof_path = os.path.join(ROOT, "profiles", "traffic_k_%s_%s_fp64.json" % (dom, cfg["name"]))
         traffic = None
+        valu = None
         if args.method == "emrkc" and batch is None and tet is None and os.path.exists(prof_path):
             tr = json.load(open(prof_path))
             ent = tr.get("by_shape", {}).get("%d,%d,%d" % (variants[0], variants[1], variants[4]))
             if tr.get("kernel_source_hash") == kernel_hash() and ent is not None:
                 traffic = ent.get("bytes_per_launch")
+                if "valu_busy" in ent:
+                    # the FP64 vector ALU side of the same kernel (rocprof
+                    # SQ_INSTS_VALU over its profiled duration; one wave64
+                    # instruction per 4 cycles on 1024 SIMDs at 2.4 GHz)
+                    valu = {"instr_per_wave": ent["valu_instr_per_wave"], "busy_frac": ent["valu_busy"],
+                            "peak": "78.6 TFLOP/s FP64 vector", "source": tr.get("source")}
         head_kernel = ("k_mrkc_head" if args.method == "mrkc" else
                        ("k_head_batch_flat" if variants[1] else "k_head_batch<tile shape %d>" % variants[0])
                        if batch is not None else
@@ -286,7 +293,7 @@ def main():
         inner_gbs = ib / (prof["inner"][0] * 1e-3) / 1e9 if prof["inner"][1] and ib else None
         roof = {"kernel": names[dom], "bound": "hbm", "achieved": round(dom_gbs, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(dom_gbs / HBM_PEAK_GBS, 4), "traffic": traffic,
-                "bytes_per_launch": db, "launch_ms": round(dom_ms, 5),
+                "bytes_per_launch": db, "launch_ms": round(dom_ms, 5), "valu": valu,
                 "kernels_ms": {k: round(v[0], 5) for k, v in prof.items()},
                 "launches": {k: v[1] for k, v in prof.items()},
                 "inner_stencil_kernel": {"achieved_GBs": round(inner_gbs, 1) if inner_gbs else None,
