@@ -64,9 +64,10 @@ extern "C" {
 #define EMRKC_MODEL_TTP_SURR 4  /* TTP-shaped surrogate: 12 gates + 6 slow    */
 
 #define EMRKC_FP64 0            /* every quantity in double                  */
-#define EMRKC_MIXED32 1         /* z and ionic/diffusion arithmetic in float,
-                                   V, recurrences, coefficients and spectral
-                                   radii in double                           */
+#define EMRKC_MIXED32 1         /* z, the ionic arithmetic and the tetrahedral
+                                   operator's weights and products in float;
+                                   V, grid stencils, recurrences, coefficients
+                                   and spectral radii in double              */
 
 #define EMRKC_CHECK_FINITE 1u   /* emrkc_step synchronises and checks V      */
 /* Stepping variants (flags):
@@ -359,7 +360,9 @@ int emrkc_profile_imexrl(emrkc_ctx *ctx, emrkc_state *state, double dt, int64_t 
  * through LDS by direct global-to-LDS loads (grids with 8 N < 2^32 only),
  * 3 and 4 = the 3-D tiles compiled for at least 6 and 8 resident waves per
  * SIMD (fewer registers), 5 = flat: one node per thread in index order,
- * stencil operands read through the caches (the default on 3-D grids).
+ * stencil operands read through the caches (the default on 3-D grids), 6 =
+ * the flat head compiled for one more resident wave per SIMD (7 in the
+ * mixed precision, 6 in FP64).
  * Inner kernel: 0 = 3-D tiles, 1 = z-marching columns.  Planes per column
  * in [1, 64] and at most n[2] for the column kernels, else 0.  Other meshes have
  * one head and one inner shape (entries 0..3 are 0), and so do mRKC
@@ -377,8 +380,9 @@ int emrkc_profile_imexrl(emrkc_ctx *ctx, emrkc_state *state, double dt, int64_t 
  * copy of `state`, which is not modified) and keeps the fastest head and
  * inner kernels, then the fused kernel if a step with it is faster.  A
  * candidate replaces an earlier one only when at least 3% faster.
- * Candidates: the flat head (first, the default), tiles (three register
- * budgets for the head), and columns of
+ * Candidates: the flat head (first, the default; then its variant for one
+ * more wave per SIMD), tiles (three register budgets for the head), and
+ * columns of
  * 2, 3, 4, 8, 16 or 32 planes that leave at least 256 blocks; for a batch,
  * the three tile shapes, then the flat head with the chosen shape,
  * compared by the time per step.  Needs the

@@ -438,7 +438,8 @@ struct Grid {
   // inner-stage and head kernels for 3-D grids: 0 = 3-D tiles, 1 = z-marching
   // columns of zc (head_zc) planes per block (2.5-D); heads also 2 = columns
   // with the ionic state staged through LDS, 3/4 = tiles for 6/8 waves per
-  // SIMD, 5 = flat (one node per thread); chosen by the host
+  // SIMD, 5 = flat (one node per thread), 6 = flat for one more wave per
+  // SIMD; chosen by the host
   int inner_variant;
   uint32_t zc;
   int head_variant;
@@ -455,46 +456,44 @@ __device__ __forceinline__ uint32_t mirror_hi(uint32_t i, uint32_t n) { return i
 // (chi Cm M_L)^{-1} (A u) at one node in difference form sum_o w_o (u_o - u_c),
 // grouped by offset class.  get(dx, dy, dz) returns the neighbour value with
 // the boundary already resolved: the zero-flux boundary of the lumped Q1
-// operator equals the interior formula with mirrored neighbours.  FP64:
-// differences and products in double.  Mixed: differences in double (V
-// carries a resting offset of about -65 mV), products and sums in float.
-__device__ __forceinline__ double fma_t(double a, double b, double c) { return __builtin_fma(a, b, c); }
-__device__ __forceinline__ float fma_t(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
-
+// operator equals the interior formula with mirrored neighbours.  Both
+// precisions take it in double: the weights are kernel arguments, so a float
+// form would save no memory traffic, and on gfx950 unpacked float arithmetic
+// issues at the double rate, so its conversions would only add instructions.
+//
 // Written with explicit fused multiply-adds in a fixed order and no further
 // contraction, so that the flat, LDS-tiled and z-marching kernels round
 // identically.
-template <int DIM, bool MIXED, class Get>
+template <int DIM, class Get>
 __device__ __forceinline__ double grid_stencil(const double *w, Get get) {
 #pragma clang fp contract(off)
-  using T = typename std::conditional<MIXED, float, double>::type;
   const double uc = get(0, 0, 0);
-  auto d = [&](int dx, int dy, int dz) { return (T)(get(dx, dy, dz) - uc); };
+  auto d = [&](int dx, int dy, int dz) { return get(dx, dy, dz) - uc; };
   if (DIM == 2) {
-    const T f = d(-1, 0, 0) + d(1, 0, 0);
-    const T e = d(0, -1, 0) + d(0, 1, 0);
-    const T c = (d(-1, -1, 0) + d(1, -1, 0)) + (d(-1, 1, 0) + d(1, 1, 0));
-    return (double)fma_t((T)w[3], c, fma_t((T)w[1], e, (T)w[0] * f));
+    const double f = d(-1, 0, 0) + d(1, 0, 0);
+    const double e = d(0, -1, 0) + d(0, 1, 0);
+    const double c = (d(-1, -1, 0) + d(1, -1, 0)) + (d(-1, 1, 0) + d(1, 1, 0));
+    return __builtin_fma(w[3], c, __builtin_fma(w[1], e, w[0] * f));
   }
-  const T fx = d(-1, 0, 0) + d(1, 0, 0);
-  const T fy = d(0, -1, 0) + d(0, 1, 0);
-  const T fz = d(0, 0, -1) + d(0, 0, 1);
-  const T exy = (d(-1, -1, 0) + d(1, -1, 0)) + (d(-1, 1, 0) + d(1, 1, 0));
-  const T exz = (d(-1, 0, -1) + d(1, 0, -1)) + (d(-1, 0, 1) + d(1, 0, 1));
-  const T eyz = (d(0, -1, -1) + d(0, 1, -1)) + (d(0, -1, 1) + d(0, 1, 1));
-  const T cm = (d(-1, -1, -1) + d(1, -1, -1)) + (d(-1, 1, -1) + d(1, 1, -1));
-  const T cp = (d(-1, -1, 1) + d(1, -1, 1)) + (d(-1, 1, 1) + d(1, 1, 1));
-  T r = (T)w[0] * fx;
-  r = fma_t((T)w[1], fy, r);
-  r = fma_t((T)w[2], fz, r);
-  r = fma_t((T)w[3], exy, r);
-  r = fma_t((T)w[4], exz, r);
-  r = fma_t((T)w[5], eyz, r);
-  return (double)fma_t((T)w[6], cm + cp, r);
+  const double fx = d(-1, 0, 0) + d(1, 0, 0);
+  const double fy = d(0, -1, 0) + d(0, 1, 0);
+  const double fz = d(0, 0, -1) + d(0, 0, 1);
+  const double exy = (d(-1, -1, 0) + d(1, -1, 0)) + (d(-1, 1, 0) + d(1, 1, 0));
+  const double exz = (d(-1, 0, -1) + d(1, 0, -1)) + (d(-1, 0, 1) + d(1, 0, 1));
+  const double eyz = (d(0, -1, -1) + d(0, 1, -1)) + (d(0, -1, 1) + d(0, 1, 1));
+  const double cm = (d(-1, -1, -1) + d(1, -1, -1)) + (d(-1, 1, -1) + d(1, 1, -1));
+  const double cp = (d(-1, -1, 1) + d(1, -1, 1)) + (d(-1, 1, 1) + d(1, 1, 1));
+  double r = w[0] * fx;
+  r = __builtin_fma(w[1], fy, r);
+  r = __builtin_fma(w[2], fz, r);
+  r = __builtin_fma(w[3], exy, r);
+  r = __builtin_fma(w[4], exz, r);
+  r = __builtin_fma(w[5], eyz, r);
+  return __builtin_fma(w[6], cm + cp, r);
 }
 
 // The stencil on a global array at node (ix, iy, iz).
-template <int DIM, bool MIXED>
+template <int DIM>
 __device__ __forceinline__ double grid_apply(const double *__restrict__ u, const Grid &g, uint32_t ix,
                                              uint32_t iy, uint32_t iz) {
   const uint32_t xs[3] = {mirror_lo(ix), ix, mirror_hi(ix, g.n0)};
@@ -507,7 +506,7 @@ __device__ __forceinline__ double grid_apply(const double *__restrict__ u, const
     zs[1] = iz * s2;
     zs[2] = mirror_hi(iz, g.n2) * s2;
   }
-  return grid_stencil<DIM, MIXED>(g.w, [&](int dx, int dy, int dz) {
+  return grid_stencil<DIM>(g.w, [&](int dx, int dy, int dz) {
     return u[zs[dz + 1] + ys[dy + 1] + xs[dx + 1]];
   });
 }

@@ -78,8 +78,8 @@ __device__ __forceinline__ double apply_op(const Mesh &mesh, const double *__res
   if (mesh.kind == kGrid) {
     uint32_t ix, iy, iz;
     grid_coords(mesh.grid, i, ix, iy, iz);
-    return mesh.grid.dim == 3 ? grid_apply<3, MIXED>(u, mesh.grid, ix, iy, iz)
-                              : grid_apply<2, MIXED>(u, mesh.grid, ix, iy, iz);
+    return mesh.grid.dim == 3 ? grid_apply<3>(u, mesh.grid, ix, iy, iz)
+                              : grid_apply<2>(u, mesh.grid, ix, iy, iz);
   }
   return ell_apply<MIXED>(mesh.ell, u, i);
 }
@@ -163,11 +163,20 @@ __device__ __forceinline__ void head_node_z(const HeadArgs &a, uint32_t N, uint3
 
   // outer recurrence of z with the averaged force (u_eta - y)/eta; the
   // inner iteration leaves gates at z_E and moves the slow variables by
-  // c'_m eta g_S (f_F has no z component)
+  // c'_m eta g_S (f_F has no z component).  Mixed form, first outer stage:
+  // the gate update z + (mu dt / eta)(z_E - z) is one float FMA on the float
+  // gate (its rounding stays at the level of the float storage it is written
+  // to); later stages, whose coefficients nu and kappa can exceed 1, and the
+  // slow variables recur in double.
   R *zout = (R *)a.zout;
   const R *zin2 = (const R *)a.zin2;
+  const float gate_c = (float)(a.mu_dt * a.inv_eta * (a.progressive ? a.cm : 1.0));
 #pragma unroll
   for (int k = 0; k < NZ; ++k) {
+    if (MIXED && k < NG && a.j1) {
+      zout[(size_t)k * N + i] = R(__builtin_fmaf(gate_c, (float)(zE[k] - z[k]), (float)z[k]));
+      continue;
+    }
     double fbar;
     if (k < NG) {
       fbar = (double)(zE[k] - z[k]) * a.inv_eta;
@@ -201,12 +210,27 @@ __device__ __forceinline__ void head_node_z(const HeadArgs &a, uint32_t N, uint3
 }
 
 template <template <class> class Model, bool MIXED>
-__global__ __launch_bounds__(kBlock) void k_head(HeadArgs a, Mesh mesh) {
+__device__ __forceinline__ void head_flat(const HeadArgs &a, const Mesh &mesh) {
   const uint32_t N = mesh.kind == kGrid ? mesh.grid.N : mesh.ell.N;
   const uint32_t i = node_index();
   if (i >= N) return;
   const double V = a.Vin[i];
   head_node<Model, MIXED>(a, N, i, V, [&]() { return apply_op<MIXED>(mesh, a.Vin, i); });
+}
+
+template <template <class> class Model, bool MIXED>
+__global__ __launch_bounds__(kBlock) void k_head(HeadArgs a, Mesh mesh) {
+  head_flat<Model, MIXED>(a, mesh);
+}
+
+// The flat head compiled for one more resident wave per SIMD than the
+// register allocation of k_head gives (7 mixed, 6 FP64; the FP64 form may
+// spill a few registers): on grids of about one round of waves the extra
+// wave removes the tail round.
+template <template <class> class Model, bool MIXED>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(MIXED ? 7 : 6))) void k_head_occ(
+    HeadArgs a, Mesh mesh) {
+  head_flat<Model, MIXED>(a, mesh);
 }
 
 // ---------------------------------------------------------------------------
@@ -490,7 +514,7 @@ __global__ __launch_bounds__(kBlock) void k_fused(FusedArgs a, Grid g, uint32_t 
     const uint32_t gy = mirror_any(y0 + hy - 1, g.n1);
     const uint32_t gz = DIM == 3 ? mirror_any(z0 + hz - 1, g.n2) : 0u;
     const uint32_t i = gx + g.n0 * (gy + g.n1 * gz);
-    const double Fu = grid_apply<DIM, MIXED>(a.t.uprev, g, gx, gy, gz);
+    const double Fu = grid_apply<DIM>(a.t.uprev, g, gx, gy, gz);
     const double um = inner_value(a.t, Fu, load_sv(a.t.SV, MIXED, i), i);
     sV[r] = tail_from_um(a.t, um, i);
   }
@@ -504,7 +528,7 @@ __global__ __launch_bounds__(kBlock) void k_fused(FusedArgs a, Grid g, uint32_t 
   const double V = sV[c];
   a.Vout[i] = V;
   head_node<Model, MIXED>(a.h, g.N, i, V, [&]() {
-    return grid_stencil<DIM, MIXED>(g.w, [&](int dx, int dy, int dz) {
+    return grid_stencil<DIM>(g.w, [&](int dx, int dy, int dz) {
       return sV[c + (DIM == 3 ? dz * T::SX * T::SY : 0) + dy * T::SX + dx];
     });
   });
@@ -554,10 +578,10 @@ __device__ __forceinline__ bool tile_node(const Grid &g, int x0, int y0, int z0,
   return true;
 }
 
-template <int DIM, bool MIXED, int SH = 0>
+template <int DIM, int SH = 0>
 __device__ __forceinline__ double lds_stencil(const double *sU, const Grid &g, int c) {
   using T = Tile<DIM, SH>;
-  return grid_stencil<DIM, MIXED>(g.w, [&](int dx, int dy, int dz) {
+  return grid_stencil<DIM>(g.w, [&](int dx, int dy, int dz) {
     return sU[c + (DIM == 3 ? dz * T::SX * T::SY : 0) + dy * T::SX + dx];
   });
 }
@@ -576,7 +600,7 @@ __device__ __forceinline__ void head_tiled_node(const HeadArgs &a, const Grid &g
   uint32_t il;
   int c;
   if (!tile_node<DIM, SH>(g, x0, y0, z0, il, c)) return;
-  head_node<Model, MIXED>(a, Nplane, off + il, sV[c], [&]() { return lds_stencil<DIM, MIXED, SH>(sV, g, c); });
+  head_node<Model, MIXED>(a, Nplane, off + il, sV[c], [&]() { return lds_stencil<DIM, SH>(sV, g, c); });
 }
 
 template <template <class> class Model, bool MIXED, int DIM>
@@ -639,7 +663,7 @@ __global__ __launch_bounds__(kBlock) void k_inner_tiled(InnerArgs a, Grid g, uin
   stage_halo<DIM>(sU, a.t.uprev, g, x0, y0, z0);
   __syncthreads();
   if (!own) return;
-  const double Fu = lds_stencil<DIM, MIXED>(sU, g, c);
+  const double Fu = lds_stencil<DIM>(sU, g, c);
   a.out[i] = inner_point(a, sU[c], Fu, pt);
 }
 
@@ -712,7 +736,7 @@ __global__ __launch_bounds__(kBlock) void k_inner_march(InnerArgs a, Grid g, uin
     }
     if (own) {
       const double *pm = ring[(z + 2) % 3], *pc = ring[z % 3], *pp = ring[(z + 1) % 3];
-      const double Fu = grid_stencil<3, MIXED>(g.w, [&](int dx, int dy, int dz) {
+      const double Fu = grid_stencil<3>(g.w, [&](int dx, int dy, int dz) {
         const double *pl = dz < 0 ? pm : (dz > 0 ? pp : pc);
         return pl[c + dy * MSX + dx];
       });
@@ -785,7 +809,7 @@ __global__ __launch_bounds__(kBlock) void k_head_march(HeadArgs a, Grid g, uint3
     if (own) {
       const double *pm = ring[(z + 2) % 3], *pc = ring[z % 3], *pp = ring[(z + 1) % 3];
       head_node_z<Model, MIXED>(a, g.N, i, pc[c], cz.z, stimulus(a.stim, i, tj), [&]() {
-        return grid_stencil<3, MIXED>(g.w, [&](int dx, int dy, int dz) {
+        return grid_stencil<3>(g.w, [&](int dx, int dy, int dz) {
           const double *pl = dz < 0 ? pm : (dz > 0 ? pp : pc);
           return pl[c + dy * MSX + dx];
         });
@@ -938,7 +962,7 @@ __global__ __launch_bounds__(kBlock) void k_head_march_lds(HeadArgs a, Grid g, u
     if (own) {
       const double *pm = ring[(z + 2) % 3], *pc = ring[z % 3], *pp = ring[(z + 1) % 3];
       head_node_z<Model, MIXED>(a, g.N, i, pc[c], zc, mcur != 0 ? a.stim.amp : 0.0, [&]() {
-        return grid_stencil<3, MIXED>(g.w, [&](int dx, int dy, int dz) {
+        return grid_stencil<3>(g.w, [&](int dx, int dy, int dz) {
           const double *pl = dz < 0 ? pm : (dz > 0 ? pp : pc);
           return pl[c + dy * MSX + dx];
         });
@@ -1007,7 +1031,7 @@ __global__ __launch_bounds__(kBlock) void k_head_batch_flat(const BatchInst *__r
   head_node<Model, MIXED>(h, Ntot, I.off + il, Vg[il], [&]() {
     uint32_t ix, iy, iz;
     grid_coords(I.g, il, ix, iy, iz);
-    return I.g.dim == 3 ? grid_apply<3, MIXED>(Vg, I.g, ix, iy, iz) : grid_apply<2, MIXED>(Vg, I.g, ix, iy, iz);
+    return I.g.dim == 3 ? grid_apply<3>(Vg, I.g, ix, iy, iz) : grid_apply<2>(Vg, I.g, ix, iy, iz);
   });
 }
 
@@ -1025,7 +1049,7 @@ __device__ __forceinline__ void inner_tile(const BatchInst &I, uint32_t tile, do
   stage_halo<DIM, SH>(sU, a.t.uprev + I.off, I.g, x0, y0, z0);
   __syncthreads();
   if (!own) return;
-  const double Fu = lds_stencil<DIM, MIXED, SH>(sU, I.g, c);
+  const double Fu = lds_stencil<DIM, SH>(sU, I.g, c);
   a.out[i] = inner_point(a, sU[c], Fu, pt);
 }
 
@@ -1254,7 +1278,7 @@ __global__ __launch_bounds__(kBlock) void k_cg_dir_apply_tiled(CgDirArgs a, Grid
   double pq = 0.0;
   if (tile_node<DIM>(g, x0, y0, z0, i, c)) {
     const double pi = sP[c];
-    const double qi = pi - a.dt * lds_stencil<DIM, false>(sP, g, c);
+    const double qi = pi - a.dt * lds_stencil<DIM>(sP, g, c);
     a.p[i] = pi;
     a.q[i] = qi;
     pq = a.ML[i] * pi * qi;
@@ -1445,10 +1469,11 @@ void set_flat_kernels(bool flat) { g_flat_kernels = flat; }
 template <template <class> class Model>
 static hipError_t head_dispatch(bool mixed, const Mesh &mesh, const HeadArgs &a, hipStream_t st) {
   const uint32_t N = mesh.kind == kGrid ? mesh.grid.N : mesh.ell.N;
-  // head shape 5 on grids: the flat kernel below (one node per thread in
-  // index order, stencil operands through the caches; no LDS staging, no
-  // block barrier, no tile padding)
-  if (mesh.kind == kGrid && !g_flat_kernels && mesh.grid.head_variant != 5) {
+  // head shapes 5 and 6 on grids: the flat kernels below (one node per
+  // thread in index order, stencil operands through the caches; no LDS
+  // staging, no block barrier, no tile padding)
+  const bool flat = mesh.kind != kGrid || g_flat_kernels || mesh.grid.head_variant >= 5;
+  if (!flat) {
     uint32_t ntx, nty;
     const Grid &g = mesh.grid;
     if (g.dim == 3 && (g.head_variant == 1 || g.head_variant == 2)) {
@@ -1495,10 +1520,16 @@ static hipError_t head_dispatch(bool mixed, const Mesh &mesh, const HeadArgs &a,
     }
     return hipGetLastError();
   }
-  if (mixed)
+  if (mesh.kind == kGrid && !g_flat_kernels && mesh.grid.head_variant == 6) {
+    if (mixed)
+      EMRKC_LAUNCH((k_head_occ<Model, true>), dim3(blocks_for(N)), dim3(kBlock), 0, st, a, mesh);
+    else
+      EMRKC_LAUNCH((k_head_occ<Model, false>), dim3(blocks_for(N)), dim3(kBlock), 0, st, a, mesh);
+  } else if (mixed) {
     EMRKC_LAUNCH((k_head<Model, true>), dim3(blocks_for(N)), dim3(kBlock), 0, st, a, mesh);
-  else
+  } else {
     EMRKC_LAUNCH((k_head<Model, false>), dim3(blocks_for(N)), dim3(kBlock), 0, st, a, mesh);
+  }
   return hipGetLastError();
 }
 

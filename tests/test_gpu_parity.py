@@ -206,7 +206,7 @@ def test_graph_eager_fused_split_and_repeat_are_bitwise_identical(E, n, rho, pre
         # ragged columns and plane counts that do not divide n[2]
         for v in [(1, 4, 1, 4, 0), (2, 4, 1, 4, 0), (2, 2, 1, 3, 0), (1, n[2], 1, n[2], 0), (2, 5, 0, 0, 0),
                   (0, 0, 1, 2, 0), (2, 3, 1, 4, 1), (3, 0, 1, 4, 0), (4, 0, 0, 0, 1), (5, 0, 1, 4, 0),
-                  (5, 0, 0, 0, 1), (5, 0, 1, 3, 0), (0, 0, 0, 0, 0)]:
+                  (5, 0, 0, 0, 1), (5, 0, 1, 3, 0), (6, 0, 1, 3, 0), (6, 0, 0, 0, 0), (0, 0, 0, 0, 0)]:
             runs.append(gpu_run(cfg, 80, rho, precision=precision, variants=v)[:2])
     assert st1.used_graph == 1 and st2.used_graph == 0
     assert st1.kernels_per_step == st1.m and st5.kernels_per_step == st5.m - 1
@@ -227,7 +227,7 @@ def test_autotune_keeps_state_and_results(E):
     v = E.emrkc_autotune(sim.ctx, sim.state, cfg["dt"], reps=2)
     assert torch.equal(sim.V, V0) and torch.equal(sim.z, z0)
     assert v == E.emrkc_get_variants(sim.ctx)
-    assert len(v) == 5 and v[0] in (0, 1, 2, 3, 4, 5) and v[2] in (0, 1) and v[4] in (0, 1)
+    assert len(v) == 5 and v[0] in (0, 1, 2, 3, 4, 5, 6) and v[2] in (0, 1) and v[4] in (0, 1)
     assert (v[0] in (1, 2)) == (v[1] > 0) and (v[2] == 0) == (v[3] == 0)
     E.emrkc_step(sim.ctx, sim.state, cfg["dt"], 30)
     torch.cuda.synchronize()
@@ -322,6 +322,6 @@ def test_minimal_grids(E, n, rho):
     assert np.abs(z - Y[1:]).max() <= 1e-10 * np.abs(Y[1:]).max()
     if len(n) == 3:
         for v in [(1, 1, 1, 1, 0), (2, n[2], 1, n[2], 0), (2, 1, 0, 0, 1), (3, 0, 1, 2, 0), (0, 0, 0, 0, 0),
-                  (5, 0, 1, 1, 0), (5, 0, 0, 0, 0)]:
+                  (5, 0, 1, 1, 0), (5, 0, 0, 0, 0), (6, 0, 1, 1, 0)]:
             V2, z2, _ = gpu_run(cfg, nsteps, rho, variants=v)
             assert np.array_equal(V2, V) and np.array_equal(z2, z), v
