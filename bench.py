@@ -276,7 +276,7 @@ def main():
                        "k_head" if tet is not None else
                        {0: "k_head_tiled", 1: "k_head_march", 2: "k_head_march_lds", 3: "k_head_tiled_occ<6 waves/SIMD>",
                         4: "k_head_tiled_occ<8 waves/SIMD>", 5: "k_head (flat)",
-                        6: "k_head_occ (flat, one more wave per SIMD)"}[variants[0]])
+                        6: "k_head_occ (flat, 7 waves per SIMD)"}[variants[0]])
         names = {"fused": "k_fused (last inner stage of step n-1 + exponential Euler, ionic model, outer z "
                           "recurrence and first inner stage of step n)",
                  "head": "%s (exponential Euler, ionic model, outer z recurrence, first inner stage)" % head_kernel

@@ -361,8 +361,8 @@ int emrkc_profile_imexrl(emrkc_ctx *ctx, emrkc_state *state, double dt, int64_t 
  * 3 and 4 = the 3-D tiles compiled for at least 6 and 8 resident waves per
  * SIMD (fewer registers), 5 = flat: one node per thread in index order,
  * stencil operands read through the caches (the default on 3-D grids), 6 =
- * the flat head compiled for one more resident wave per SIMD (7 in the
- * mixed precision, 6 in FP64).
+ * the flat head compiled for at least 7 resident waves per SIMD (mixed
+ * precision only; EMRKC_EUNSUPPORTED in FP64, where it would spill).
  * Inner kernel: 0 = 3-D tiles, 1 = z-marching columns.  Planes per column
  * in [1, 64] and at most n[2] for the column kernels, else 0.  Other meshes have
  * one head and one inner shape (entries 0..3 are 0), and so do mRKC
@@ -380,8 +380,8 @@ int emrkc_profile_imexrl(emrkc_ctx *ctx, emrkc_state *state, double dt, int64_t 
  * copy of `state`, which is not modified) and keeps the fastest head and
  * inner kernels, then the fused kernel if a step with it is faster.  A
  * candidate replaces an earlier one only when at least 3% faster.
- * Candidates: the flat head (first, the default; then its variant for one
- * more wave per SIMD), tiles (three register budgets for the head), and
+ * Candidates: the flat head (first, the default; then, in the mixed
+ * precision, its 7-wave form), tiles (three register budgets for the head), and
  * columns of
  * 2, 3, 4, 8, 16 or 32 planes that leave at least 256 blocks; for a batch,
  * the three tile shapes, then the flat head with the chosen shape,

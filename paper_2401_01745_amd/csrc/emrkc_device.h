@@ -438,8 +438,8 @@ struct Grid {
   // inner-stage and head kernels for 3-D grids: 0 = 3-D tiles, 1 = z-marching
   // columns of zc (head_zc) planes per block (2.5-D); heads also 2 = columns
   // with the ionic state staged through LDS, 3/4 = tiles for 6/8 waves per
-  // SIMD, 5 = flat (one node per thread), 6 = flat for one more wave per
-  // SIMD; chosen by the host
+  // SIMD, 5 = flat (one node per thread), 6 = flat for 7 waves per SIMD
+  // (mixed precision only); chosen by the host
   int inner_variant;
   uint32_t zc;
   int head_variant;

@@ -1442,6 +1442,7 @@ static int check_variants(const emrkc_ctx *c, const int *v) {
   if (!tunable(c)) return (v[0] | v[1] | v[2] | v[3]) == 0 ? EMRKC_OK : EMRKC_EUNSUPPORTED;
   const int n2 = (int)c->mesh.grid.n2;
   if (v[0] < 0 || v[0] > 6 || v[2] < 0 || v[2] > 1) return EMRKC_EINVAL;
+  if (v[0] == 6 && !c->mixed) return EMRKC_EUNSUPPORTED;  // a mixed-precision kernel
   // the LDS-staged head addresses a component plane with 32-bit byte offsets
   if (v[0] == 2 && (uint64_t)c->N * sizeof(double) >= (1ull << 32)) return EMRKC_EUNSUPPORTED;
   const bool head_cols = v[0] == 1 || v[0] == 2;
@@ -1581,7 +1582,7 @@ extern "C" int emrkc_autotune(emrkc_ctx *c, const emrkc_state *st, double dt, in
   // must beat it by the margin below
   std::vector<std::pair<int, int>> heads{{5, 0}}, inners{{0, 0}};
   if (tunable(c)) {
-    heads.push_back({6, 0});  // the flat head for one more wave per SIMD
+    if (c->mixed) heads.push_back({6, 0});  // the flat head for 7 waves per SIMD
     heads.push_back({0, 0});  // tiles; and tiles for 6 and 8 waves per SIMD
     heads.push_back({3, 0});
     heads.push_back({4, 0});

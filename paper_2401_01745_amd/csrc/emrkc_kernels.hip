@@ -223,14 +223,14 @@ __global__ __launch_bounds__(kBlock) void k_head(HeadArgs a, Mesh mesh) {
   head_flat<Model, MIXED>(a, mesh);
 }
 
-// The flat head compiled for one more resident wave per SIMD than the
-// register allocation of k_head gives (7 mixed, 6 FP64; the FP64 form may
-// spill a few registers): on grids of about one round of waves the extra
-// wave removes the tail round.
-template <template <class> class Model, bool MIXED>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(MIXED ? 7 : 6))) void k_head_occ(
-    HeadArgs a, Mesh mesh) {
-  head_flat<Model, MIXED>(a, mesh);
+// The mixed-precision flat head compiled for at least 7 resident waves per
+// SIMD (at most 72 registers): on grids of about one round of waves the
+// extra wave removes the tail round.  (The FP64 head would spill at the
+// corresponding budget, and gains nothing.)
+template <template <class> class Model>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(7))) void k_head_occ(HeadArgs a,
+                                                                                               Mesh mesh) {
+  head_flat<Model, true>(a, mesh);
 }
 
 // ---------------------------------------------------------------------------
@@ -1520,11 +1520,9 @@ static hipError_t head_dispatch(bool mixed, const Mesh &mesh, const HeadArgs &a,
     }
     return hipGetLastError();
   }
-  if (mesh.kind == kGrid && !g_flat_kernels && mesh.grid.head_variant == 6) {
-    if (mixed)
-      EMRKC_LAUNCH((k_head_occ<Model, true>), dim3(blocks_for(N)), dim3(kBlock), 0, st, a, mesh);
-    else
-      EMRKC_LAUNCH((k_head_occ<Model, false>), dim3(blocks_for(N)), dim3(kBlock), 0, st, a, mesh);
+  // shape 6 exists for mixed contexts only (the host rejects it for FP64)
+  if (mixed && mesh.kind == kGrid && !g_flat_kernels && mesh.grid.head_variant == 6) {
+    EMRKC_LAUNCH((k_head_occ<Model>), dim3(blocks_for(N)), dim3(kBlock), 0, st, a, mesh);
   } else if (mixed) {
     EMRKC_LAUNCH((k_head<Model, true>), dim3(blocks_for(N)), dim3(kBlock), 0, st, a, mesh);
   } else {

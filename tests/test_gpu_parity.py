@@ -206,8 +206,11 @@ def test_graph_eager_fused_split_and_repeat_are_bitwise_identical(E, n, rho, pre
         # ragged columns and plane counts that do not divide n[2]
         for v in [(1, 4, 1, 4, 0), (2, 4, 1, 4, 0), (2, 2, 1, 3, 0), (1, n[2], 1, n[2], 0), (2, 5, 0, 0, 0),
                   (0, 0, 1, 2, 0), (2, 3, 1, 4, 1), (3, 0, 1, 4, 0), (4, 0, 0, 0, 1), (5, 0, 1, 4, 0),
-                  (5, 0, 0, 0, 1), (5, 0, 1, 3, 0), (6, 0, 1, 3, 0), (6, 0, 0, 0, 0), (0, 0, 0, 0, 0)]:
+                  (5, 0, 0, 0, 1), (5, 0, 1, 3, 0), (0, 0, 0, 0, 0)]:
             runs.append(gpu_run(cfg, 80, rho, precision=precision, variants=v)[:2])
+        if precision == "mixed":  # the 7-wave flat head exists in the mixed precision only
+            for v in [(6, 0, 1, 3, 0), (6, 0, 0, 0, 0), (6, 0, 0, 0, 1)]:
+                runs.append(gpu_run(cfg, 80, rho, precision=precision, variants=v)[:2])
     assert st1.used_graph == 1 and st2.used_graph == 0
     assert st1.kernels_per_step == st1.m and st5.kernels_per_step == st5.m - 1
     for V, z in runs:
@@ -239,6 +242,8 @@ def test_autotune_keeps_state_and_results(E):
         E.emrkc_set_variants(sim.ctx, (1, 34, 0, 0, 0))
     with pytest.raises(E.EmrkcError):
         E.emrkc_set_variants(sim.ctx, (0, 0, 0, 0, 2))
+    with pytest.raises(E.EmrkcError):  # the 7-wave flat head is a mixed-precision kernel
+        E.emrkc_set_variants(sim.ctx, (6, 0, 0, 0, 0))
     sim.close()
 
 
@@ -322,6 +327,6 @@ def test_minimal_grids(E, n, rho):
     assert np.abs(z - Y[1:]).max() <= 1e-10 * np.abs(Y[1:]).max()
     if len(n) == 3:
         for v in [(1, 1, 1, 1, 0), (2, n[2], 1, n[2], 0), (2, 1, 0, 0, 1), (3, 0, 1, 2, 0), (0, 0, 0, 0, 0),
-                  (5, 0, 1, 1, 0), (5, 0, 0, 0, 0), (6, 0, 1, 1, 0)]:
+                  (5, 0, 1, 1, 0), (5, 0, 0, 0, 0)]:
             V2, z2, _ = gpu_run(cfg, nsteps, rho, variants=v)
             assert np.array_equal(V2, V) and np.array_equal(z2, z), v
