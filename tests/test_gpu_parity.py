@@ -152,6 +152,18 @@ def test_stage_plans(E, rho, dt, sm):
     assert (stats.s, stats.m) == sm
 
 
+@pytest.mark.parametrize("rho,dt,sm", [((51.0, 100.0), 0.05, (2, 1)), ((2000.0, 300.0), 0.05, (3, 3)),
+                                       ((51.0, 700.0), 0.05, (5, 1)), ((150.0, 30.0), 0.1, (2, 2))])
+def test_stage_plans_mixed(E, rho, dt, sm):
+    """The mixed precision through s >= 2 outer stages against the FP64
+    oracle: its first-stage gate update is a float FMA and its later stages
+    recur in double; both stay within the mixed-precision bound (FP32
+    ionic state: a few 1e-6 relative over 60 steps)."""
+    cfg = small_config("c2_3d_crn", (23, 17, 7), dt=dt)
+    _, _, _, stats = _compare_full(cfg, 60, rho, tol=2e-5, precision="mixed")
+    assert (stats.s, stats.m) == sm
+
+
 def test_linear_model_closed_form_on_gpu(E):
     """LINEAR model from a cosine mode: V_{n} = P_s(dt Phi_m(eta lF)(lF + lS))^n V0
     (the scalar stability analysis applied per eigenmode)."""
