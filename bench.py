@@ -161,6 +161,25 @@ def cpu_baseline(cfg, seconds, tet=None):
     return prob.N * n / el, n, el, stage_counts(cfg["dt"], rF, rS), prob.N
 
 
+def copy_bandwidth(torch, stream, mib=1024, reps=5):
+    """GB/s (read + write bytes) of torch's device-to-device copy of `mib` MiB."""
+    src = torch.ones(mib << 18, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    best = None
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        dst.copy_(src)
+        e1.record(stream)
+        e1.synchronize()
+        ms = e0.elapsed_time(e1)
+        best = ms if best is None else min(best, ms)
+    del src, dst
+    torch.cuda.empty_cache()
+    return 2.0 * (mib << 20) / (best * 1e-3) / 1e9
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -318,6 +337,15 @@ def main():
             log("bench: mixed %.4g node-steps/s, V rel L2 %.3e" % (value_m, mixed["V_rel_l2_vs_fp64"]))
             jm.sim.close()
         job.sim.close()
+
+    # the practical bandwidth ceiling on this GPU: a plain device-to-device
+    # copy of 1 GiB (the HIP runtime's copy kernel), best of 5, timed on the
+    # same stream outside the timed region
+    with torch.cuda.stream(stream):
+        copy_gbs = copy_bandwidth(torch, stream)
+    roof["copy_GBs"] = round(copy_gbs, 1)
+    roof["frac_of_copy"] = round(roof["achieved"] / copy_gbs, 4)
+    log("bench: device copy %.1f GB/s; dominant kernel at %.1f%% of it" % (copy_gbs, 100 * roof["frac_of_copy"]))
 
     cpu = None
     if not args.no_cpu_baseline:
