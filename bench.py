@@ -278,7 +278,7 @@ def main():
         prof_path = os.path.join(ROOT, "profiles", "traffic_k_%s_%s_fp64.json" % (dom, cfg["name"]))
         traffic = None
         valu = None
-        if args.method == "emrkc" and batch is None and tet is None and os.path.exists(prof_path):
+        if args.method == "emrkc" and os.path.exists(prof_path):
             tr = json.load(open(prof_path))
             ent = tr.get("by_shape", {}).get("%d,%d,%d" % (variants[0], variants[1], variants[4]))
             if tr.get("kernel_source_hash") == kernel_hash() and ent is not None:
