@@ -100,6 +100,21 @@ def test_csr_emrkc_parity(E, model, n, deg):
     _check(prob, y, V, z)
 
 
+def test_csr_emrkc_mixed(E):
+    """The mixed precision on an assembled operator (float ELL weights and
+    products, float ionic state) against the FP64 oracle."""
+    A, ML, mask = random_laplacian(3000, 6, seed=3000)
+    prob = _oracle(A, ML, mask, "CRN_SURR")
+    rho = _rho(prob)
+    dt, nsteps = 0.05, 60
+    y = emrkc_run(prob, prob.uniform_state(), 0.0, dt, nsteps, *rho)
+    V, z = _run(E, A, ML, mask, "CRN_SURR", rho, dt, nsteps, precision="mixed")
+    Y = y.reshape(prob.nv, prob.N)
+    l2, mx = rel_errors(V, Y[0])
+    assert l2 <= 1e-5 and mx <= 1e-4, (l2, mx)
+    assert np.abs(z - Y[1:]).max() <= 1e-4 * np.abs(Y[1:]).max()
+
+
 def test_csr_imexrl_parity(E):
     A, ML, mask = random_laplacian(2500, 6, seed=7)
     prob = _oracle(A, ML, mask, "CRN_SURR")
