@@ -8,7 +8,8 @@ formula here is written out again, in numpy, from the paper (section
 and the nonlinear power iteration of the appendix).
 
 Functions whose results have no independent pin say "parity unpinned" in
-their docstrings.  Full nonlinear trajectories of the ionic models are
+their docstrings.  Nonlinear trajectories are pinned on a single cell (first
+order convergence to a library ODE integrator); with diffusion they are
 parity unpinned beyond the properties checked in the tests (uniform states,
 convergence order, brute force on tiny meshes).
 """

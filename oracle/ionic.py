@@ -20,8 +20,10 @@ reproduce those models' sizes (20 and 18 ionic variables, split 15+5 and
 12+6 between gates and other variables) and their stiffness (largest gate
 rate about 130/ms and 1000/ms), with an HH excitable core whose
 conductances are scaled to cardiac magnitudes (one tenth of the squid-axon
-values), extra gated currents and concentration-like slow variables.  Their full nonlinear
-trajectories are parity unpinned.
+values), extra gated currents and concentration-like slow variables.  Their formulas are
+definitions of this project; their single-cell trajectories are pinned
+against a library ODE integrator in the tests, multi-node trajectories are
+parity unpinned.
 """
 import numpy as np
 

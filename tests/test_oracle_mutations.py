@@ -9,6 +9,7 @@ import sys
 
 import pytest
 
+import test_oracle_cell_ode as T_cell
 import test_oracle_emrkc as T_emrkc
 import test_oracle_fem as T_fem
 import test_oracle_imexrl as T_imex
@@ -160,6 +161,14 @@ CASES = [
      "return (sp.identity(prob.N, format=\"csr\") + dt * Fm).tocsc()",
      [lambda: T_imex.test_linear_model_cosine_mode_closed_form(0.5),
       T_imex.test_implicit_diffusion_is_bounded_at_large_steps]),
+    # the V equation without the 1/Cm (invisible wherever Cm = 1)
+    ("fS_membrane_capacitance", "oracle.monodomain", "out[:self.N] = (self.I_stim(t) - I_ion) / self.Cm",
+     "out[:self.N] = self.I_stim(t) - I_ion",
+     [lambda: T_cell.test_single_cell_converges_to_radau_solution(*T_cell.CASES[1])]),
+    # the stimulus with the wrong sign
+    ("fS_stimulus_sign", "oracle.monodomain", "out[:self.N] = (self.I_stim(t) - I_ion) / self.Cm",
+     "out[:self.N] = (-self.I_stim(t) - I_ion) / self.Cm",
+     [lambda: T_cell.test_single_cell_converges_to_radau_solution(*T_cell.CASES[0])]),
 ]
 
 
