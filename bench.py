@@ -134,12 +134,13 @@ def time_jobs(job, warmup, steps, torch):
     return time.perf_counter() - t0, info
 
 
-def cpu_baseline(cfg, seconds, tet=None):
+def cpu_baseline(cfg, seconds, tet=None, method="emrkc"):
     """The FP64 oracle on the same workload, timed for a bounded number of
-    emRKC steps on the full mesh (assembly and radii excluded).  For the
-    ensemble the sample is its first instance."""
+    emRKC (or mRKC) steps on the full mesh (assembly and radii excluded).
+    For the ensemble the sample is its first instance."""
     from oracle.emrkc import emrkc_step, stage_counts
     from oracle.monodomain import build_grid_problem, build_tet_problem
+    from oracle.mrkc import MrkcSplit, mrkc_step
     from oracle.powiter import compute_rho, random_unit_interval
     if tet is not None:
         prob = build_tet_problem(cfg, *tet)
@@ -147,13 +148,17 @@ def cpu_baseline(cfg, seconds, tet=None):
         prob = build_grid_problem(cfg, stim_mask=cfg.get("mask"))
     y = prob.uniform_state()
     v0 = random_unit_interval(y.size, 0)
-    _, rF, _, _ = compute_rho(0.0, y, prob.f_F, v0.copy())
-    _, rS, _, _ = compute_rho(0.0, y, prob.f_S, v0.copy())
+    split = MrkcSplit(prob) if method == "mrkc" else prob
+    _, rF, _, _ = compute_rho(0.0, y, split.f_F, v0.copy())
+    _, rS, _, _ = compute_rho(0.0, y, split.f_S, v0.copy())
     rF, rS = 1.05 * rF, 1.05 * rS
     n = 0
     t0 = time.perf_counter()
     while True:
-        y = emrkc_step(n * cfg["dt"], y, cfg["dt"], prob, rF, rS)
+        if method == "mrkc":
+            y = mrkc_step(n * cfg["dt"], y, cfg["dt"], split.f_F, split.f_S, rF, rS)
+        else:
+            y = emrkc_step(n * cfg["dt"], y, cfg["dt"], prob, rF, rS)
         n += 1
         el = time.perf_counter() - t0
         if el >= seconds or n >= 1000:
@@ -275,10 +280,11 @@ def main():
         dom_gbs = db / (dom_ms * 1e-3) / 1e9
         # HBM bytes per launch from the committed rocprof counters, when they
         # were taken on these kernel sources for the kernel shape chosen here
-        prof_path = os.path.join(ROOT, "profiles", "traffic_k_%s_%s_fp64.json" % (dom, cfg["name"]))
+        prof_path = os.path.join(ROOT, "profiles", "traffic_k_%s%s_%s_fp64.json"
+                                 % ("mrkc_" if args.method == "mrkc" else "", dom, cfg["name"]))
         traffic = None
         valu = None
-        if args.method == "emrkc" and os.path.exists(prof_path):
+        if args.method in ("emrkc", "mrkc") and os.path.exists(prof_path):
             tr = json.load(open(prof_path))
             ent = tr.get("by_shape", {}).get("%d,%d,%d" % (variants[0], variants[1], variants[4]))
             if tr.get("kernel_source_hash") == kernel_hash() and ent is not None:
@@ -347,26 +353,27 @@ def main():
     roof["frac_of_copy"] = round(roof["achieved"] / copy_gbs, 4)
     log("bench: device copy %.1f GB/s; dominant kernel at %.1f%% of it" % (copy_gbs, 100 * roof["frac_of_copy"]))
 
+    mname = "mRKC" if args.method == "mrkc" else "emRKC"
     cpu = None
     if not args.no_cpu_baseline:
         log("bench: CPU oracle baseline")
-        v, n, el, sm, Ns = cpu_baseline(cfg, args.cpu_seconds, tet)
+        v, n, el, sm, Ns = cpu_baseline(cfg, args.cpu_seconds, tet, args.method)
         what = ("the full %d-node mesh" % Ns) if Ns == N else ("instance 0 (%d nodes) of the ensemble" % Ns)
         cpu = {"value": v, "unit": "node-steps/s", "cores": 1, "kind": "oracle",
-               "sample": "%d emRKC steps of %s in %.1f s (numpy/scipy, single thread; host has %d logical CPUs)"
-                         % (n, what, el, os.cpu_count())}
+               "sample": "%d %s steps of %s in %.1f s (numpy/scipy, single thread; host has %d logical CPUs)"
+                         % (n, mname, what, el, os.cpu_count())}
 
-    out = {"metric": METRIC, "value": value, "unit": "node-steps/s", "n_gpus": 1, "steps": args.steps,
+    out = {"metric": METRIC.replace("emRKC", mname), "value": value, "unit": "node-steps/s", "n_gpus": 1, "steps": args.steps,
            "warmup": args.warmup, "ms_per_step": 1e3 * elapsed / args.steps, "higher_is_better": True,
            "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
            "config": {"workload": "%s: %s (%d nodes), %s, chi=%g/mm, Cm=%g uF/mm^2, sigma=%s, dt=%g ms, "
-                                  "T=%g ms; one bench step = init + power iteration + %d emRKC steps"
+                                  "T=%g ms; one bench step = init + power iteration + %d %s steps"
                                   % (cfg["name"], ("P1 tetrahedral shell %s" % "x".join(map(str, cfg["dims"])))
                                      if tet is not None else
                                      ("ensemble of %d 2-D/3-D Q1 slabs, one batched context" % len(batch))
                                      if batch is not None else ("Q1 grid %s" % "x".join(map(str, cfg["n"]))),
                                      N, cfg["model"], cfg["chi"], cfg["Cm"], list(cfg["sigma"]), cfg["dt"], cfg["T"],
-                                     job.nsim),
+                                     job.nsim, mname),
                       "method": args.method, "kernel_shapes": variants, "s": s, "m": m, "eta": eta, "rho_F": rF, "rho_S": rS, "powiter_iters": [itF, itS]},
            "roofline": roof, "mixed": mixed, "cpu_baseline": cpu}
     print(json.dumps(out), flush=True)
