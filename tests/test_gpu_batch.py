@@ -135,3 +135,48 @@ def test_batch_autotune(ens):
         with pytest.raises(E.EmrkcError):
             E.emrkc_set_variants(sim.ctx, bad)
     sim.close()
+
+
+def test_full_ensemble_in_the_bench_configuration():
+    """The 64-instance ensemble at full size (7.0 M nodes) in the shapes the
+    benchmark times (flat batched head, 32x4x2 / 32x8 tiles for the inner
+    stage), radii from the library's own power iteration: every instance
+    equals its own single-context run bit for bit (a property at any size),
+    and the three smallest instances, sampled, equal their oracle runs to
+    1e-10."""
+    import torch
+    from paper_2401_01745_amd import emrkc as E
+    from workloads.ensemble import ensemble
+    cfgs = ensemble()
+    dt, nsteps = cfgs[0]["dt"], 20
+    print("full ensemble:", len(cfgs), "instances", flush=True)
+    sim = E.simulation_from_batch(cfgs)
+    E.emrkc_set_variants(sim.ctx, (1, 1, 0, 0, 0))
+    E.emrkc_init_state(sim.ctx, sim.state)
+    E.emrkc_estimate_rho(sim.ctx, sim.state)
+    off, m, rF, rS = E.emrkc_batch_info(sim.ctx, dt)
+    rSmax = max(rS)
+    E.emrkc_step(sim.ctx, sim.state, dt, nsteps)
+    torch.cuda.synchronize()
+    V = sim.V.cpu().numpy().copy()
+    assert off[-1] == V.size and V.size > 6_900_000
+    sizes = [off[k + 1] - off[k] for k in range(len(cfgs))]
+    sample = sorted(range(len(cfgs)), key=lambda k: sizes[k])[:3]
+    for k, cfg in enumerate(cfgs):
+        sl = slice(off[k], off[k + 1])
+        zk = sim.z[:, sl].cpu().numpy().astype(np.float64)
+        one = E.simulation_from_config(cfg, rho=(rF[k], rSmax), stim_mask=cfg["mask"])
+        E.emrkc_init_state(one.ctx, one.state)
+        E.emrkc_step(one.ctx, one.state, dt, nsteps)
+        torch.cuda.synchronize()
+        assert np.array_equal(one.V.cpu().numpy(), V[sl]), k
+        assert np.array_equal(one.z.cpu().numpy().astype(np.float64), zk), k
+        one.close()
+        if k in sample:
+            prob = build_grid_problem(cfg, stim_mask=cfg["mask"])
+            y = emrkc_run(prob, prob.uniform_state(), 0.0, dt, nsteps, rF[k], rSmax)
+            Y = y.reshape(prob.nv, prob.N)
+            l2, mx = rel_errors(V[sl], Y[0])
+            assert l2 <= 1e-10 and mx <= 1e-10, (k, l2, mx)
+            assert np.abs(zk - Y[1:]).max() <= 1e-10 * np.abs(Y[1:]).max(), k
+    sim.close()
