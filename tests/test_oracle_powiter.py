@@ -81,3 +81,30 @@ def test_max_iter_reports_non_convergence_and_zero_state_uses_eps():
     assert it == 1 and not ok and rho > 0
     v2, rho2, it2, ok2 = compute_rho(0.0, y, prob.f_F, v, rho)
     assert ok2 and it2 >= 1
+
+
+@pytest.mark.parametrize("name", ["CRN_SURR", "TTP_SURR"])
+def test_rho_S_surrogates_against_jacobian_eigenvalues(name):
+    """The nonlinear power iteration on f_S of the surrogates (whose slow
+    variables couple back into V) estimates the spectral radius of f_S's
+    Jacobian within its tolerance (1e-2): against the largest eigenvalue
+    magnitude of a central-difference Jacobian from numpy's dense
+    eigensolver.  Two nodes at different potentials: f_S is pointwise, so
+    the radius is the larger of the two nodes' blocks."""
+    import scipy.sparse as sp
+    from oracle.ionic import make_model
+    model = make_model(name)
+    prob = Monodomain(sp.csr_matrix((2, 2)), np.ones(2), 140.0, 0.01, model)
+    y = prob.uniform_state().copy()
+    y[0], y[1] = -40.0, 10.0
+    n = y.size
+    J = np.zeros((n, n))
+    for j in range(n):
+        h = 1e-6 * max(1.0, abs(y[j]))
+        e = np.zeros(n)
+        e[j] = h
+        J[:, j] = (prob.f_S(0.0, y + e) - prob.f_S(0.0, y - e)) / (2 * h)
+    lam = np.abs(np.linalg.eigvals(J)).max()
+    _, rho, it, ok = compute_rho(0.0, y, prob.f_S, random_unit_interval(n, 0))
+    assert ok and it < 20
+    assert abs(rho - lam) <= 1e-2 * lam, (rho, lam)
