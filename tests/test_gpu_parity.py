@@ -342,3 +342,38 @@ def test_minimal_grids(E, n, rho):
                   (5, 0, 1, 1, 0), (5, 0, 0, 0, 0)]:
             V2, z2, _ = gpu_run(cfg, nsteps, rho, variants=v)
             assert np.array_equal(V2, V) and np.array_equal(z2, z), v
+
+
+def test_zero_conductivity_decouples_the_cells(E):
+    """sigma = 0, a degenerate case of the method: f_F = 0, the power
+    iteration reports rho_F = 0 and the stage plan has one inner stage; every
+    node then follows its own cell ODE.  The run equals the oracle's with the
+    same radii to 1e-10, and all stimulated nodes (and all others) stay equal."""
+    import torch
+    from oracle.emrkc import emrkc_run
+    from oracle.monodomain import build_grid_problem
+    from workloads.configs import stim_mask
+    cfg = small_config("c2_3d_crn", (9, 7, 5))
+    cfg["sigma"] = (0.0, 0.0, 0.0)
+    cfg["stim"]["width"] = 0.25   # a corner of 3 x 3 x 3 nodes
+    sim = E.simulation_from_config(cfg)
+    E.emrkc_init_state(sim.ctx, sim.state)
+    rF, rS, _, _, _ = E.emrkc_estimate_rho(sim.ctx, sim.state)
+    assert rF == 0.0 and rS > 1.0
+    s, m, _ = E.emrkc_stages(sim.ctx, cfg["dt"])[:3]
+    assert (s, m) == (1, 1)
+    nsteps = 40
+    E.emrkc_step(sim.ctx, sim.state, cfg["dt"], nsteps)
+    torch.cuda.synchronize()
+    V = sim.V.cpu().numpy().copy()
+    z = sim.z.cpu().numpy().astype(np.float64)
+    sim.close()
+    prob = build_grid_problem(cfg)
+    y = emrkc_run(prob, prob.uniform_state(), 0.0, cfg["dt"], nsteps, rF, rS)
+    Y = y.reshape(prob.nv, prob.N)
+    l2, mx = rel_errors(V, Y[0])
+    assert l2 <= 1e-10 and mx <= 1e-10, (l2, mx)
+    assert np.abs(z - Y[1:]).max() <= 1e-10 * np.abs(Y[1:]).max()
+    mask = stim_mask(cfg).astype(bool)
+    assert 0 < mask.sum() < mask.size
+    assert np.ptp(V[mask]) == 0.0 and np.ptp(V[~mask]) == 0.0 and V[mask][0] > V[~mask][0] + 10.0
