@@ -176,6 +176,33 @@ def emrkc_stage_counts(dt, rho_F, rho_S, eps=0.05, cond="B"):
     return s.value, m.value, eta.value
 
 
+def emrkc_stage_counts_a(dt, rho_F, rho_S, eps=0.05):
+    """(s, m, eta) under stability condition A."""
+    return emrkc_stage_counts(dt, rho_F, rho_S, eps, cond="A")
+
+
+def emrkc_num_nodes(ctx):
+    return lib().emrkc_num_nodes(ctx)
+
+
+def emrkc_num_vars(ctx):
+    return lib().emrkc_num_vars(ctx)
+
+
+def emrkc_ell_width(ctx):
+    return lib().emrkc_ell_width(ctx)
+
+
+def emrkc_batch_size(ctx):
+    return lib().emrkc_batch_size(ctx)
+
+
+def emrkc_last_error(ctx):
+    """The context's last error message ('' when none)."""
+    msg = lib().emrkc_last_error(ctx)
+    return msg.decode() if msg else ""
+
+
 ELEMENTARY = {"exp": 0, "expm1": 1, "log": 2}
 
 

@@ -31,6 +31,17 @@ def test_every_declared_symbol_is_exported():
     for n in names:
         assert hasattr(L, n), n
         assert n in E.EXPORTS, n
+        assert callable(getattr(E, n, None)), n   # the binding has the same names
+
+
+def test_accessors_on_null_context():
+    assert E.emrkc_num_nodes(None) == -1
+    assert E.emrkc_num_vars(None) == -1
+    assert E.emrkc_ell_width(None) == -1
+    assert E.emrkc_batch_size(None) < 0
+    assert isinstance(E.emrkc_last_error(None), str)
+    s, m, eta = E.emrkc_stage_counts_a(0.05, 51.0, 4.4)
+    assert s == 1 and m >= 2 and eta > 0
 
 
 def test_struct_layout_matches_header(tmp_path):
