@@ -528,6 +528,7 @@ extern "C" int emrkc_create(const emrkc_mesh *mesh, const emrkc_conductivity *co
     rc = build_csr(c, mesh);
     if (rc != EMRKC_OK) goto error;
   }
+  c->mesh.flat = c->flat ? 1 : 0;
 
   {
     const size_t vb = sizeof(double) * (size_t)N;
@@ -918,7 +919,6 @@ static int enqueue_chunk_batch(emrkc_ctx *c, const emrkc_state *st, const StepPl
 
 static int enqueue_chunk(emrkc_ctx *c, const emrkc_state *st, const StepPlan &P, double dt, int L, hipStream_t strm,
                          KernelTimer *tm = nullptr) {
-  set_flat_kernels(c->flat);
   if (c->batch) return enqueue_chunk_batch(c, st, P, dt, L, strm, tm);
   if (c->method == EMRKC_METHOD_MRKC) {
     for (int n = 0; n < L; ++n) {
@@ -1103,7 +1103,6 @@ static int step_core(emrkc_ctx *c, emrkc_state *st, double dt, int64_t nsteps) {
 // kernel reads V^n with neighbours while writing V^{n+1}), z is updated in
 // place; the chunk ends with V in the caller's buffer and the clock ticked.
 static int enqueue_chunk_exexrl(emrkc_ctx *c, const emrkc_state *st, double dt, int L, hipStream_t strm) {
-  set_flat_kernels(c->flat);
   double *X[2] = {(double *)st->V, c->d_V1};
   for (int n = 0; n < L; ++n) {
     ExArgs a{};

@@ -36,6 +36,7 @@ enum MeshKind : int { kGrid = 1, kEll = 2 };
 
 struct Mesh {
   int kind;
+  int flat;  // grids: use the flat global-load kernels only (a context's testing switch)
   Grid grid;
   Ell ell;
 };
@@ -223,7 +224,6 @@ hipError_t launch_fused(int model, bool mixed, const Mesh &mesh, const FusedArgs
 bool fused_supported(const Mesh &mesh);
 // Testing switch: use the flat (one node per thread, global-load stencil)
 // kernels on grids instead of the LDS-tiled ones.  Process-wide.
-void set_flat_kernels(bool flat);
 hipError_t launch_clock_set(Clock *c, int64_t step, double t0, hipStream_t st);
 hipError_t launch_copy_tick(const double *src, double *dst, uint32_t N, Clock *tick, int64_t tick_by,
                             hipStream_t st);

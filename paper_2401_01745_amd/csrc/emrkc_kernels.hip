@@ -1463,8 +1463,6 @@ static dim3 tile_grid(const Grid &g, uint32_t &ntx, uint32_t &nty) {
   return dim3(ntx * nty * ntz);
 }
 
-static bool g_flat_kernels = false;
-void set_flat_kernels(bool flat) { g_flat_kernels = flat; }
 
 template <template <class> class Model>
 static hipError_t head_dispatch(bool mixed, const Mesh &mesh, const HeadArgs &a, hipStream_t st) {
@@ -1472,7 +1470,7 @@ static hipError_t head_dispatch(bool mixed, const Mesh &mesh, const HeadArgs &a,
   // head shapes 5 and 6 on grids: the flat kernels below (one node per
   // thread in index order, stencil operands through the caches; no LDS
   // staging, no block barrier, no tile padding)
-  const bool flat = mesh.kind != kGrid || g_flat_kernels || mesh.grid.head_variant >= 5;
+  const bool flat = mesh.kind != kGrid || mesh.flat || mesh.grid.head_variant >= 5;
   if (!flat) {
     uint32_t ntx, nty;
     const Grid &g = mesh.grid;
@@ -1521,7 +1519,7 @@ static hipError_t head_dispatch(bool mixed, const Mesh &mesh, const HeadArgs &a,
     return hipGetLastError();
   }
   // shape 6 exists for mixed contexts only (the host rejects it for FP64)
-  if (mixed && mesh.kind == kGrid && !g_flat_kernels && mesh.grid.head_variant == 6) {
+  if (mixed && mesh.kind == kGrid && !mesh.flat && mesh.grid.head_variant == 6) {
     EMRKC_LAUNCH((k_head_occ<Model>), dim3(blocks_for(N)), dim3(kBlock), 0, st, a, mesh);
   } else if (mixed) {
     EMRKC_LAUNCH((k_head<Model, true>), dim3(blocks_for(N)), dim3(kBlock), 0, st, a, mesh);
@@ -1734,7 +1732,7 @@ hipError_t launch_ell_rowsum(const Ell &e, double *out, hipStream_t st) {
 
 hipError_t launch_inner(bool mixed, const Mesh &mesh, const InnerArgs &a, hipStream_t st) {
   const uint32_t N = mesh.kind == kGrid ? mesh.grid.N : mesh.ell.N;
-  if (mesh.kind == kGrid && !g_flat_kernels) {
+  if (mesh.kind == kGrid && !mesh.flat) {
     uint32_t ntx, nty;
     const Grid &g = mesh.grid;
     if (g.dim == 3 && g.inner_variant == 1) {
