@@ -70,6 +70,17 @@ extern "C" {
                                    and spectral radii in double              */
 
 #define EMRKC_CHECK_FINITE 1u   /* emrkc_step synchronises and checks V      */
+/* Diagnostic flags (results are bit-identical with and without them):
+ * EMRKC_EAGER — launch every kernel directly, never from a captured HIP graph;
+ * EMRKC_FUSE — use the fused kernel (last inner stage + next head) where it
+ *   applies, without asking the autotuner;
+ * EMRKC_FLAT — structured grids use the flat (untiled) kernels only.
+ * The environment variables EMRKC_EAGER and EMRKC_FUSE (any value) act like
+ * the flags for every context; EMRKC_VERBOSE makes emrkc_autotune print its
+ * timings to stderr. */
+#define EMRKC_EAGER 2u
+#define EMRKC_FUSE 4u
+#define EMRKC_FLAT 8u
 /* Stepping variants (flags):
  * EMRKC_PROGRESSIVE — the progressive splitting of the auxiliary problem
  *   (remark after eq. auxp_exp): the inner problem starts from y and carries

@@ -19,9 +19,9 @@
 
 using namespace emrkc;
 
-#define EMRKC_EAGER_FLAG 2u     // internal: never capture graphs (testing)
-#define EMRKC_FUSE_FLAG 4u      // internal: fused tail+head kernel (s == 1, m >= 2, grids)
-#define EMRKC_FLAT_FLAG 8u      // internal: flat global-load kernels on grids (testing)
+#define EMRKC_EAGER_FLAG EMRKC_EAGER  // never capture graphs
+#define EMRKC_FUSE_FLAG EMRKC_FUSE    // fused tail+head kernel (s == 1, m >= 2, grids)
+#define EMRKC_FLAT_FLAG EMRKC_FLAT    // flat global-load kernels on grids
 
 struct GraphKey {
   int s, m, chunk;

@@ -32,9 +32,9 @@ EMRKC_CHECK_FINITE = 1
 EMRKC_PROGRESSIVE = 0x100  # progressive splitting of the auxiliary problem
 METHODS = {"emrkc": 0, "mrkc": 1}
 EMRKC_COND_A = 0x200       # stage counts from stability condition A
-EMRKC_EAGER = 2          # library-internal flag: no HIP-graph replay
-EMRKC_FUSE = 4           # library-internal flag: fused tail+head kernel
-EMRKC_FLAT = 8           # library-internal flag: flat (untiled) grid kernels
+EMRKC_EAGER = 2          # diagnostic flag: no HIP-graph replay
+EMRKC_FUSE = 4           # diagnostic flag: fused tail+head kernel
+EMRKC_FLAT = 8           # diagnostic flag: flat (untiled) grid kernels
 
 
 class Mesh(C.Structure):
