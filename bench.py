@@ -336,7 +336,20 @@ def main():
             value_m = N * jm.nsim * max(1, args.steps // 2) / el_m
             Vm = jm.sim.V.cpu().numpy()
             d = Vm - V64
+            # the mixed form's head kernel: its own launch time and algorithmic
+            # bandwidth (z and S_V in float; ELL weights in float on tets)
+            pm = E.emrkc_profile_step(jm.sim.ctx, jm.sim.state, cfg["dt"], args.kernel_steps)
+            mat_m = width * (4 + 4)
+            if batch is not None:
+                off_m, ms_m, _, _ = E.emrkc_batch_info(jm.sim.ctx, cfg["dt"])
+                dbm = int(sum(n * bytes_per_node("head", nz, 4, mk) for n, mk in zip(np.diff(off_m), ms_m)))
+            else:
+                dbm = bytes_per_node("head", nz, 4, E.emrkc_stages(jm.sim.ctx, cfg["dt"])[1], mat_m) * N
+            head_m = {"launch_ms": round(pm["head"][0], 5), "bytes_per_launch": dbm,
+                      "achieved_GBs": round(dbm / (pm["head"][0] * 1e-3) / 1e9, 1),
+                      "frac": round(dbm / (pm["head"][0] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)} if pm["head"][1] else None
             mixed = {"value": value_m, "speedup_vs_fp64": round(value_m / value, 3), "kernel_shapes": variants_m,
+                     "head_kernel": head_m,
                      "V_rel_l2_vs_fp64": float(np.linalg.norm(d) / np.linalg.norm(V64)),
                      "V_rel_max_vs_fp64": float(np.abs(d).max() / np.abs(V64).max()),
                      "reference": "GPU FP64 path at T (matches the FP64 oracle to 1e-10 in the parity tests)"}
