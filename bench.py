@@ -1,16 +1,22 @@
 """Benchmark of the emRKC hot path on one MI355X.
 
-One bench step is one whole simulation of the 3-D cuboid workload
-(201 x 71 x 31 Q1 nodes = 442,401 nodes, CRN surrogate with 21 variables,
-dt = 0.05 ms, T = 50 ms): resting-state initialisation, spectral-radius
-estimation by power iteration, and 1000 emRKC steps (outer RKC stages with
-the fused ionic/Rush-Larsen head kernel and the inner diffusion stages),
-replayed from HIP graphs.  Throughput is node-steps per second of the whole
-job.  The same line carries the dominant kernel's roofline (timed with HIP
-events in a separate pass of eagerly launched kernels), the mixed FP32 form
-with its error in V, and the FP64 oracle timed on the host cores.
+One bench step is one whole simulation of the large slab workload (the
+largest configuration that fits one GPU: 601 x 601 x 101 Q1 nodes =
+36,481,301 nodes, CRN surrogate with 21 variables, planar stimulus on the
+x = 0 face, dt = 0.05 ms, T = 20 ms): resting-state initialisation,
+spectral-radius estimation by power iteration, and 400 emRKC steps (outer
+RKC stages with the fused ionic/Rush-Larsen head kernel and the inner
+diffusion stages), replayed from HIP graphs.  Throughput is node-steps per
+second of the whole job.  The same line carries the dominant kernel's
+roofline (timed with HIP events in a separate pass of eagerly launched
+kernels), the measured copy and 3-read/1-write stream bandwidths of the
+device, the mixed FP32 form with its error in V, and the FP64 oracle timed
+on the host cores.  On the slab the solution depends on x alone, so the
+oracle's run on the 601 x 2 x 2 reduction of the same grid gives the exact
+reference V at T for every node; the error of both forms against it is
+reported.
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--config NAME]
 """
 import argparse
 import json
@@ -134,10 +140,29 @@ def time_jobs(job, warmup, steps, torch):
     return time.perf_counter() - t0, info
 
 
+# Largest grid the CPU leg assembles whole (nodes).  Beyond it the oracle is
+# timed on a sub-slab of the first planes of the same grid: assembling the
+# 36.5M-node slab takes the oracle about 2.5 minutes and 55 GB, and one of
+# its steps about half a minute.
+CPU_MAX_NODES = 2_000_000
+
+
+def cpu_sample_config(cfg):
+    """The workload the CPU leg times: cfg itself, or for a 3-D grid above
+    CPU_MAX_NODES its first k z-planes (same spacing, conductivity, model
+    and stimulus rule), with k the largest that stays within the bound."""
+    if cfg.get("kind") != "grid" or int(np.prod(cfg["n"])) <= CPU_MAX_NODES or cfg["dim"] != 3:
+        return cfg, None
+    n0, n1, n2 = cfg["n"]
+    k = max(2, min(n2, CPU_MAX_NODES // (n0 * n1)))
+    return dict(cfg, n=(n0, n1, k)), k
+
+
 def cpu_baseline(cfg, seconds, tet=None, method="emrkc"):
     """The FP64 oracle on the same workload, timed for a bounded number of
-    emRKC (or mRKC) steps on the full mesh (assembly and radii excluded).
-    For the ensemble the sample is its first instance."""
+    emRKC (or mRKC) steps (assembly and radii excluded), on the full mesh or
+    on the sub-slab of cpu_sample_config.  For the ensemble the sample is
+    its first instance."""
     from oracle.emrkc import emrkc_step, stage_counts
     from oracle.monodomain import build_grid_problem, build_tet_problem
     from oracle.mrkc import MrkcSplit, mrkc_step
@@ -145,6 +170,7 @@ def cpu_baseline(cfg, seconds, tet=None, method="emrkc"):
     if tet is not None:
         prob = build_tet_problem(cfg, *tet)
     else:
+        cfg, _ = cpu_sample_config(cfg)
         prob = build_grid_problem(cfg, stim_mask=cfg.get("mask"))
     y = prob.uniform_state()
     v0 = random_unit_interval(y.size, 0)
@@ -164,6 +190,67 @@ def cpu_baseline(cfg, seconds, tet=None, method="emrkc"):
         if el >= seconds or n >= 1000:
             break
     return prob.N * n / el, n, el, stage_counts(cfg["dt"], rF, rS), prob.N
+
+
+def planar_reduction(cfg):
+    """For a 3-D grid whose stimulus is a whole x-face band (uniform in y
+    and z) and whose initial state is uniform, the solution depends on x
+    alone: the zero-flux Q1 operator maps a field constant in y and z to
+    the operator of the n0 x 2 x 2 grid of the same spacing (the y and z
+    difference terms vanish, the mirrored mass weights sum to one).  Returns
+    that reduced workload, or None when the reduction does not apply."""
+    st = cfg.get("stim", {})
+    if cfg.get("kind") != "grid" or cfg.get("dim") != 3 or st.get("kind") != "face" or st.get("axis") != 0:
+        return None
+    return dict(cfg, n=(cfg["n"][0], 2, 2), name=cfg["name"] + "_x_reduction")
+
+
+def oracle_reference_V(cfg, nsteps, rho_F, rho_S):
+    """V at T from the FP64 oracle on the reduction of planar_reduction
+    (an x-profile of n0 values), run with the given radii (the method uses
+    them only through its stage counts (s, m)), or None."""
+    red = planar_reduction(cfg)
+    if red is None:
+        return None
+    from oracle.emrkc import emrkc_run
+    from oracle.monodomain import build_grid_problem
+    prob = build_grid_problem(red)
+    y = emrkc_run(prob, prob.uniform_state(), 0.0, cfg["dt"], nsteps, rho_F, rho_S)
+    return y[:prob.N].reshape(2, 2, cfg["n"][0])[0, 0].copy()
+
+
+def errors_vs_profile(V, ref, n, torch):
+    """(relative L2, relative max) of the device vector V on an n0 x n1 x n2
+    grid against the x-profile ref broadcast over y and z."""
+    r = torch.from_numpy(ref).to(V.device)
+    d = V.view(n[2], n[1], n[0]) - r.view(1, 1, -1)
+    ref_l2 = float(np.linalg.norm(ref)) * float(np.sqrt(n[1] * n[2]))
+    return float(torch.linalg.vector_norm(d).item()) / ref_l2, float(d.abs().max().item()) / float(np.abs(ref).max())
+
+
+def stream_bandwidth(torch, stream, mib=1024, reps=5):
+    """GB/s of a 3-read/1-write stream over FP64 vectors of `mib` MiB each
+    (d = a + b c, torch's addcmul), best of `reps`: the traffic pattern of
+    the inner stages, as a practical ceiling next to the plain copy."""
+    n = mib << 17
+    a = torch.ones(n, dtype=torch.float64, device="cuda")
+    b = torch.full((n,), 0.5, dtype=torch.float64, device="cuda")
+    c = torch.full((n,), 2.0, dtype=torch.float64, device="cuda")
+    d = torch.empty_like(a)
+    torch.addcmul(a, b, c, out=d)
+    best = None
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        torch.addcmul(a, b, c, out=d)
+        e1.record(stream)
+        e1.synchronize()
+        ms = e0.elapsed_time(e1)
+        best = ms if best is None else min(best, ms)
+    assert float(d[n // 2].item()) == 2.0
+    del a, b, c, d
+    torch.cuda.empty_cache()
+    return 4.0 * (mib << 20) / (best * 1e-3) / 1e9
 
 
 def copy_bandwidth(torch, stream, mib=1024, reps=5):
@@ -190,7 +277,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--config", default="c2_3d_crn")
+    ap.add_argument("--config", default="c5_3d_crn_large")
     ap.add_argument("--kernel-steps", type=int, default=200)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -257,7 +344,8 @@ def main():
         value = N * job.nsim * args.steps / elapsed
         log("bench: fp64 %.3f ms per simulation (%d steps), %.4g node-steps/s, s=%d m=%d" %
             (1e3 * elapsed / args.steps, job.nsim, value, s, m))
-        V64 = job.sim.V.cpu().numpy().copy()
+        V64 = job.sim.V.clone()
+        radii64 = E.emrkc_get_rho(job.sim.ctx)
 
         # per-launch kernel durations: HIP events around every kernel on the
         # job's stream, over kernel-steps further steps of the same
@@ -334,7 +422,9 @@ def main():
             log("bench: mixed kernel shapes %s" % (variants_m,))
             el_m, _ = time_jobs(jm, 1, max(1, args.steps // 2), torch)
             value_m = N * jm.nsim * max(1, args.steps // 2) / el_m
-            Vm = jm.sim.V.cpu().numpy()
+            Vm = jm.sim.V.clone()
+            radiim = E.emrkc_get_rho(jm.sim.ctx)
+            sm_m = E.emrkc_stages(jm.sim.ctx, cfg["dt"])[:2]
             d = Vm - V64
             # the mixed form's head kernel: its own launch time and algorithmic
             # bandwidth (z and S_V in float; ELL weights in float on tets)
@@ -350,31 +440,63 @@ def main():
                       "frac": round(dbm / (pm["head"][0] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)} if pm["head"][1] else None
             mixed = {"value": value_m, "speedup_vs_fp64": round(value_m / value, 3), "kernel_shapes": variants_m,
                      "head_kernel": head_m,
-                     "V_rel_l2_vs_fp64": float(np.linalg.norm(d) / np.linalg.norm(V64)),
-                     "V_rel_max_vs_fp64": float(np.abs(d).max() / np.abs(V64).max()),
+                     "s_m": list(sm_m),
+                     "V_rel_l2_vs_fp64": float(torch.linalg.vector_norm(d).item() /
+                                               torch.linalg.vector_norm(V64).item()),
+                     "V_rel_max_vs_fp64": float(d.abs().max().item() / V64.abs().max().item()),
+                     "V_rel_l2_vs_oracle": None, "V_rel_max_vs_oracle": None,
                      "reference": "GPU FP64 path at T (matches the FP64 oracle to 1e-10 in the parity tests)"}
+            del d
             log("bench: mixed %.4g node-steps/s, V rel L2 %.3e" % (value_m, mixed["V_rel_l2_vs_fp64"]))
             jm.sim.close()
         job.sim.close()
+        torch.cuda.synchronize()
+        torch.cuda.empty_cache()
 
     # the practical bandwidth ceiling on this GPU: a plain device-to-device
     # copy of 1 GiB (the HIP runtime's copy kernel), best of 5, timed on the
     # same stream outside the timed region
     with torch.cuda.stream(stream):
         copy_gbs = copy_bandwidth(torch, stream)
+        stream_gbs = stream_bandwidth(torch, stream)
     roof["copy_GBs"] = round(copy_gbs, 1)
     roof["frac_of_copy"] = round(roof["achieved"] / copy_gbs, 4)
-    log("bench: device copy %.1f GB/s; dominant kernel at %.1f%% of it" % (copy_gbs, 100 * roof["frac_of_copy"]))
+    roof["stream3r1w_GBs"] = round(stream_gbs, 1)
+    roof["frac_of_stream"] = round(roof["achieved"] / stream_gbs, 4)
+    log("bench: device copy %.1f GB/s, 3-read/1-write stream %.1f GB/s; dominant kernel at %.1f%% / %.1f%% of them"
+        % (copy_gbs, stream_gbs, 100 * roof["frac_of_copy"], 100 * roof["frac_of_stream"]))
 
     mname = "mRKC" if args.method == "mrkc" else "emRKC"
     cpu = None
+    fp64_err = None
     if not args.no_cpu_baseline:
         log("bench: CPU oracle baseline")
         v, n, el, sm, Ns = cpu_baseline(cfg, args.cpu_seconds, tet, args.method)
-        what = ("the full %d-node mesh" % Ns) if Ns == N else ("instance 0 (%d nodes) of the ensemble" % Ns)
+        sub = cpu_sample_config(cfg)[1] if (tet is None and batch is None) else None
+        what = (("the full %d-node mesh" % Ns) if Ns == N else
+                ("the first %d z-planes of the grid (%s, %d nodes)"
+                 % (sub, "x".join(map(str, cpu_sample_config(cfg)[0]["n"])), Ns)) if sub else
+                ("instance 0 (%d nodes) of the ensemble" % Ns))
         cpu = {"value": v, "unit": "node-steps/s", "cores": 1, "kind": "oracle",
                "sample": "%d %s steps of %s in %.1f s (numpy/scipy, single thread; host has %d logical CPUs)"
                          % (n, mname, what, el, os.cpu_count())}
+        # the oracle's V at T on the x-reduction of a planar-wave grid: the
+        # error of both forms in every node at the full length of the run
+        if args.method == "emrkc" and planar_reduction(cfg) is not None:
+            log("bench: FP64 oracle on the %s reduction, %d steps" % ("x".join(map(str, planar_reduction(cfg)["n"])),
+                                                                     job.nsim))
+            ref = oracle_reference_V(cfg, job.nsim, *radii64)
+            e2, emax = errors_vs_profile(V64, ref, cfg["n"], torch)
+            fp64_err = {"V_rel_l2_vs_oracle": e2, "V_rel_max_vs_oracle": emax, "s_m": [s, m],
+                        "reference": "FP64 oracle on the %s grid (the planar wave depends on x alone), %d steps"
+                                     % ("x".join(map(str, planar_reduction(cfg)["n"])), job.nsim)}
+            log("bench: fp64 V vs oracle: rel L2 %.3e, rel max %.3e" % (e2, emax))
+            if mixed is not None:
+                if tuple(mixed["s_m"]) != (s, m):
+                    ref = oracle_reference_V(cfg, job.nsim, *radiim)
+                e2, emax = errors_vs_profile(Vm, ref, cfg["n"], torch)
+                mixed.update(V_rel_l2_vs_oracle=e2, V_rel_max_vs_oracle=emax, reference=fp64_err["reference"])
+                log("bench: mixed V vs oracle: rel L2 %.3e, rel max %.3e" % (e2, emax))
 
     out = {"metric": METRIC.replace("emRKC", mname), "value": value, "unit": "node-steps/s", "n_gpus": 1, "steps": args.steps,
            "warmup": args.warmup, "ms_per_step": 1e3 * elapsed / args.steps, "higher_is_better": True,
@@ -388,7 +510,7 @@ def main():
                                      N, cfg["model"], cfg["chi"], cfg["Cm"], list(cfg["sigma"]), cfg["dt"], cfg["T"],
                                      job.nsim, mname),
                       "method": args.method, "kernel_shapes": variants, "s": s, "m": m, "eta": eta, "rho_F": rF, "rho_S": rS, "powiter_iters": [itF, itS]},
-           "roofline": roof, "mixed": mixed, "cpu_baseline": cpu}
+           "roofline": roof, "fp64_error": fp64_err, "mixed": mixed, "cpu_baseline": cpu}
     print(json.dumps(out), flush=True)
 
 

@@ -100,16 +100,54 @@ def test_batch_estimate_rho_per_instance(ens):
     sim.close()
 
 
-def test_batch_mixed_precision(ens):
+def test_batch_mixed_precision_against_oracle_per_instance(ens):
+    """The mixed form of the ensemble, every instance against its own FP64
+    oracle run: 1e-4 relative L2 in V (ten times that on the maximum, which
+    sits at the front), and the float-stored ionic state within 1e-3 of each
+    component's range."""
+    cfgs, probs, rhos = ens
+    rF = [r[0] for r in rhos]
+    rSmax = max(r[1] for r in rhos)
+    rS = [rSmax] * len(rhos)
+    nsteps = 80
+    V, z, off, m = run_batch(cfgs, (rF, rS), nsteps, precision="mixed")
+    for k, (cfg, prob) in enumerate(zip(cfgs, probs)):
+        y = emrkc_run(prob, prob.uniform_state(), 0.0, cfg["dt"], nsteps, rF[k], rSmax)
+        Y = y.reshape(prob.nv, prob.N)
+        sl = slice(off[k], off[k + 1])
+        l2, mx = rel_errors(V[sl], Y[0])
+        print("instance %d (%d nodes, m=%d): mixed V rel L2 %.3e, rel max %.3e" % (k, prob.N, m[k], l2, mx))
+        assert l2 <= 1e-4 and mx <= 1e-3, (k, l2, mx)
+        for c in range(1, prob.nv):
+            dz = np.abs(z[c - 1, sl] - Y[c]).max()
+            assert dz <= 1e-3 * np.abs(Y[c]).max() + 1e-6, (k, c, dz)
+
+
+def test_batch_refuses_more_than_one_outer_stage(ens):
+    """The instances advance with one common outer stage count, which the
+    batched kernels support for s = 1 only: a dt whose radii need s >= 2 is
+    refused, the state is left as it was, and the error names the reason."""
+    import torch
+    from paper_2401_01745_amd import emrkc as E
     cfgs, probs, rhos = ens
     rF = [r[0] for r in rhos]
     rS = [max(r[1] for r in rhos)] * len(rhos)
-    V, z, off, m = run_batch(cfgs, (rF, rS), 80, precision="mixed")
-    V64, _, _, _ = run_batch(cfgs, (rF, rS), 80)
-    for k in range(len(cfgs)):
-        sl = slice(off[k], off[k + 1])
-        l2, mx = rel_errors(V[sl], V64[sl])
-        assert l2 <= 1e-4, (k, l2)
+    dt = 0.5                                   # dt rho_S well above beta: s >= 2
+    assert E.emrkc_stage_counts(dt, rF[0], rS[0])[0] >= 2
+    sim = E.simulation_from_batch(cfgs, rho=(rF, rS))
+    E.emrkc_init_state(sim.ctx, sim.state)
+    V0, z0 = sim.V.clone(), sim.z.clone()
+    with pytest.raises(E.EmrkcError) as ei:
+        E.emrkc_step(sim.ctx, sim.state, dt, 3)
+    assert ei.value.code == E.EMRKC_EUNSUPPORTED
+    assert "s = 1" in str(ei.value)
+    torch.cuda.synchronize()
+    assert torch.equal(sim.V, V0) and torch.equal(sim.z, z0)
+    assert sim.state.step == 0
+    # the supported dt still runs on the same context
+    E.emrkc_step(sim.ctx, sim.state, cfgs[0]["dt"], 2)
+    assert sim.state.step == 2
+    sim.close()
 
 
 def test_batch_autotune(ens):

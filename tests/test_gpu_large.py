@@ -1,10 +1,13 @@
-"""Full-size checks on the large 60 x 60 x 10 mm slab (601 x 601 x 101 Q1
-nodes, 36.5 M nodes).  With the planar stimulus on the x = 0 face and a
-uniform initial state the solution depends on x only: the Q1 operator with
-zero-flux boundary maps a field constant in y and z to the 1-D operator
-along x (the y/z difference terms vanish and the mirrored mass weights sum to
-one).  Every one of the 36.5 M nodes is therefore compared with the oracle
-run on the 601 x 2 x 2 grid of the same spacing."""
+"""Full-size, full-length checks on the large 60 x 60 x 10 mm slab (601 x
+601 x 101 Q1 nodes, 36.5 M nodes, 400 steps to T = 20 ms).  With the planar
+stimulus on the x = 0 face and a uniform initial state the solution depends
+on x only: the Q1 operator with zero-flux boundary maps a field constant in
+y and z to the 1-D operator along x (the y/z difference terms vanish and the
+mirrored mass weights sum to one; pinned in the oracle by
+tests/test_bench_cpu.py).  Every one of the 36.5 M nodes is therefore
+compared with the oracle run on the 601 x 2 x 2 grid of the same spacing,
+over the whole run: stimulus, upstroke and the front travelling 18 mm
+along the fibres."""
 import numpy as np
 import pytest
 
@@ -14,32 +17,53 @@ from workloads.configs import get_config
 
 pytestmark = [pytest.mark.gpu, pytest.mark.slow]
 
+NSTEPS = 400                        # T = 20 ms
+_REF = {}
 
-@pytest.mark.parametrize("precision,tol", [("fp64", 1e-10), ("mixed", 5e-5)])
-def test_c5_full_size_planar_wave_against_1d_oracle(precision, tol):
+
+def _oracle_profile(cfg, rho):
+    key = rho
+    if key not in _REF:
+        c1 = dict(cfg, n=(601, 2, 2))
+        prob = build_grid_problem(c1)
+        y = emrkc_run(prob, prob.uniform_state(), 0.0, cfg["dt"], NSTEPS, *rho)
+        _REF[key] = (prob.nv, y.reshape(prob.nv, 2, 2, 601)[:, 0, 0, :].copy())
+    return _REF[key]
+
+
+# FP64: 1e-10 relative in every node; mixed: 1e-4 relative L2 in V (and a
+# bound on the pointwise maximum, which sits at the front)
+@pytest.mark.parametrize("precision,tol_l2,tol_max", [("fp64", 1e-10, 1e-10), ("mixed", 1e-4, 1e-3)])
+def test_c5_full_size_full_length_planar_wave_against_1d_oracle(precision, tol_l2, tol_max):
     import torch
     from paper_2401_01745_amd import emrkc as E
     cfg = get_config("c5_3d_crn_large")
-    nsteps = 40                       # 2 ms: the stimulus window and the upstroke
     rho = (1.05 * 4 * 0.17 / 0.01 / (cfg["chi"] * cfg["Cm"]), 4.6)
-    # oracle on the 1-D reduction
-    c1 = dict(cfg, n=(601, 2, 2))
-    prob = build_grid_problem(c1)
-    y = emrkc_run(prob, prob.uniform_state(), 0.0, cfg["dt"], nsteps, *rho)
-    Y = y.reshape(prob.nv, 2, 2, 601)[:, 0, 0, :]
-    assert Y[0].max() > 0.0
-    # the library on the full slab
+    nv, Y = _oracle_profile(cfg, rho)
+    # the front (about 0.9 mm/ms along the fibres) is past x = 15 mm at T
+    assert Y[0].max() > 0.0 and np.nonzero(Y[0] > -40.0)[0].max() >= 150, Y[0][::20]
+    print("case: c5 601x601x101, %s, %d steps" % (precision, NSTEPS), flush=True)
     sim = E.simulation_from_config(cfg, precision=precision, rho=rho)
+    assert E.emrkc_stages(sim.ctx, cfg["dt"])[:2] == (1, 2)
     E.emrkc_init_state(sim.ctx, sim.state)
-    E.emrkc_step(sim.ctx, sim.state, cfg["dt"], nsteps)
+    E.emrkc_step(sim.ctx, sim.state, cfg["dt"], NSTEPS)
     torch.cuda.synchronize()
     V = sim.V.view(101, 601, 601)
-    ref = torch.from_numpy(Y[0]).cuda()
-    dV = (V - ref.view(1, 1, 601)).abs().max().item()
-    assert dV <= tol * np.abs(Y[0]).max(), dV
-    for c in range(1, prob.nv):
+    ref = torch.from_numpy(Y[0]).cuda().view(1, 1, 601)
+    d = V - ref
+    l2 = torch.linalg.vector_norm(d).item() / (np.linalg.norm(Y[0]) * np.sqrt(101 * 601))
+    mx = d.abs().max().item() / np.abs(Y[0]).max()
+    print("%s: V rel L2 %.3e, rel max %.3e" % (precision, l2, mx))
+    assert l2 <= tol_l2 and mx <= tol_max, (l2, mx)
+    del d
+    for c in range(1, nv):
         zc = sim.z[c - 1].view(101, 601, 601).double()
         refc = torch.from_numpy(Y[c]).cuda().view(1, 1, 601)
         dz = (zc - refc).abs().max().item()
-        assert dz <= tol * max(np.abs(Y[c]).max(), 1e-300) + (1e-7 if precision == "mixed" else 0), (c, dz)
+        scale = max(np.abs(Y[c]).max(), 1e-300)
+        if precision == "fp64":
+            assert dz <= 1e-10 * scale, (c, dz, scale)
+        else:
+            # float storage: 1e-3 of the component's range plus its rounding
+            assert dz <= 1e-3 * scale + 1e-6, (c, dz, scale)
     sim.close()

@@ -58,7 +58,10 @@ def test_small_shell_run(small, precision, tol, rhoF):
     torch.cuda.synchronize()
     Y = y.reshape(prob.nv, prob.N)
     l2, mx = rel_errors(sim.V.cpu().numpy(), Y[0])
-    assert l2 <= tol and mx <= 10 * tol, (l2, mx)
+    print("shell %s rhoF=%s: V rel L2 %.3e, rel max %.3e" % (precision, rhoF, l2, mx))
+    # FP64: the parity bound on both norms; mixed: 1e-4 relative L2 and ten
+    # times that on the pointwise maximum, which sits at the front
+    assert l2 <= tol and mx <= (tol if precision == "fp64" else 10 * tol), (l2, mx)
     st = E.emrkc_last_stats(sim.ctx)
     assert st.s == 1 and st.m == {None: 1, 100.0: 2, 900.0: 5}[rhoF]
     sim.close()
