@@ -173,7 +173,10 @@ typedef struct {
 
 /* Caller-owned state.  t0 and step define the time of the state as
  * t = t0 + step*dt (computed, never accumulated); emrkc_step advances step
- * and writes t.  V and z are device pointers laid out as described above. */
+ * and writes t.  A stepping call whose dt differs from the one the state
+ * was advanced with (step != 0 and t != t0 + step*dt) first moves t0 to
+ * t - step*dt, so the clock continues from t and step keeps counting.
+ * V and z are device pointers laid out as described above. */
 typedef struct {
   double t0;
   int64_t step;
@@ -243,7 +246,10 @@ int emrkc_ell_width(const emrkc_ctx *ctx);
 const char *emrkc_last_error(const emrkc_ctx *ctx);
 
 /* Writes the model's uniform resting state (V and every z) into the state
- * buffers and restarts its clock: step = 0, t = t0. */
+ * buffers and restarts its clock: step = 0, t = t0.  The initial values are
+ * those the ionic model defines (section "Computational setup": the
+ * simulations start from the model's own initial state; for the models
+ * here that is their resting state, see the model list above). */
 int emrkc_init_state(emrkc_ctx *ctx, emrkc_state *state);
 
 /* Spectral radii of the Jacobians of f_F and f_S at `state` by the nonlinear
@@ -260,7 +266,11 @@ int emrkc_estimate_rho(emrkc_ctx *ctx, const emrkc_state *state, double *rho_F, 
 int emrkc_set_rho(emrkc_ctx *ctx, double rho_F, double rho_S);
 int emrkc_get_rho(const emrkc_ctx *ctx, double *rho_F, double *rho_S);
 
-/* (s, m, eta) that emrkc_step would use for dt with the stored radii. */
+/* (s, m, eta) that emrkc_step would use for dt with the stored radii: the
+ * two get_stages calls at the head of the emRKC algorithm ("One step of
+ * the emRKC method"), s from dt rho_S, eta = 2 dt / (beta s^2) and m from
+ * eta rho_F, under stability condition B (condition A with EMRKC_COND_A);
+ * the formulas are those of emrkc_stage_counts. */
 int emrkc_stages(const emrkc_ctx *ctx, double dt, int *s, int *m, double *eta);
 
 /* Advances `state` by nsteps >= 0 emRKC steps of size dt > 0 (emRKC_Step of

@@ -23,6 +23,10 @@ using namespace emrkc;
 #define EMRKC_FUSE_FLAG EMRKC_FUSE    // fused tail+head kernel (s == 1, m >= 2, grids)
 #define EMRKC_FLAT_FLAG EMRKC_FLAT    // flat global-load kernels on grids
 
+// Largest node count of a context: the kernels index nodes with 32-bit
+// unsigned integers and form sums of an index and a plane stride.
+constexpr int64_t kMaxNodes = ((int64_t)1 << 31) - 1;
+
 struct GraphKey {
   int s, m, chunk;
   uint64_t dt_bits;
@@ -30,6 +34,14 @@ struct GraphKey {
   bool operator<(const GraphKey &o) const {
     return std::tie(s, m, chunk, dt_bits, V, z) < std::tie(o.s, o.m, o.chunk, o.dt_bits, o.V, o.z);
   }
+};
+
+// Stage counts and coefficient tables of one emRKC step.
+struct StepPlan {
+  int s, m;
+  double eta;
+  std::vector<double> mu, nu, ka, cc;      // outer, index j
+  std::vector<double> mui, nui, kai, cci;  // inner, index k
 };
 
 // One instance of a batched ensemble.
@@ -206,15 +218,13 @@ extern "C" int emrkc_model_num_vars(int m) {
 extern "C" int emrkc_model_num_gates(int m) { return model_gates(m) < 0 ? EMRKC_EINVAL : model_gates(m); }
 
 // get_coeffs of the RKC algorithm with Chebyshev values by their
-// three-term recurrences (T_j and T_j').
-static void rkc_coeffs(int s, double eps, std::vector<double> &mu, std::vector<double> &nu,
-                       std::vector<double> &kappa, std::vector<double> &c) {
-  mu.assign(s + 1, 0.0);
-  nu.assign(s + 1, 0.0);
-  kappa.assign(s + 1, 0.0);
-  c.assign(s + 1, 0.0);
+// three-term recurrences (T_j and T_j').  Every array holds s + 1 entries;
+// mu, nu, kappa and c are overwritten (0 where the algorithm defines no
+// value), T, dT and b are work space.
+static void rkc_coeffs_into(int s, double eps, double *mu, double *nu, double *kappa, double *c, double *T,
+                            double *dT, double *b) {
+  for (int j = 0; j <= s; ++j) mu[j] = nu[j] = kappa[j] = c[j] = 0.0;
   const double w0 = 1.0 + eps / ((double)s * (double)s);
-  std::vector<double> T(s + 1), dT(s + 1);
   T[0] = 1.0;
   dT[0] = 0.0;
   if (s >= 1) {
@@ -226,7 +236,6 @@ static void rkc_coeffs(int s, double eps, std::vector<double> &mu, std::vector<d
     dT[j] = 2.0 * T[j - 1] + 2.0 * w0 * dT[j - 1] - dT[j - 2];
   }
   const double w1 = T[s] / dT[s];
-  std::vector<double> b(s + 1);
   for (int j = 0; j <= s; ++j) b[j] = 1.0 / T[j];
   mu[1] = w1 / w0;
   c[1] = mu[1];
@@ -236,6 +245,17 @@ static void rkc_coeffs(int s, double eps, std::vector<double> &mu, std::vector<d
     kappa[j] = -b[j] / b[j - 2];
     c[j] = nu[j] * c[j - 1] + kappa[j] * c[j - 2] + mu[j];
   }
+}
+
+static void rkc_coeffs(int s, double eps, std::vector<double> &mu, std::vector<double> &nu,
+                       std::vector<double> &kappa, std::vector<double> &c) {
+  mu.resize(s + 1);
+  nu.resize(s + 1);
+  kappa.resize(s + 1);
+  c.resize(s + 1);
+  std::vector<double> work(3 * (size_t)(s + 1));
+  rkc_coeffs_into(s, eps, mu.data(), nu.data(), kappa.data(), c.data(), work.data(), work.data() + (s + 1),
+                  work.data() + 2 * (s + 1));
 }
 
 extern "C" int emrkc_rkc_coeffs(int s, double eps, double *mu, double *nu, double *kappa, double *c) {
@@ -432,6 +452,9 @@ extern "C" int emrkc_create(const emrkc_mesh *mesh, const emrkc_conductivity *co
     for (int d = 0; d < mesh->dim; ++d) {
       if (mesh->n[d] < 2 || mesh->n[d] > (1 << 30) || !(mesh->h[d] > 0) || !isfinite(mesh->h[d]))
         return EMRKC_EINVAL;
+      // 32-bit node indices on the device; checked before the product so
+      // that it cannot overflow
+      if (mesh->n[d] > kMaxNodes / N) return EMRKC_EUNSUPPORTED;
       N *= mesh->n[d];
     }
     const double sg[3] = {cond->sigma_l, cond->sigma_t, cond->sigma_n};
@@ -450,7 +473,7 @@ extern "C" int emrkc_create(const emrkc_mesh *mesh, const emrkc_conductivity *co
   } else {
     return EMRKC_EINVAL;
   }
-  if (N >= (int64_t)1 << 31) return EMRKC_EUNSUPPORTED;  // 32-bit node indices on the device
+  if (N > kMaxNodes) return EMRKC_EUNSUPPORTED;  // 32-bit node indices on the device
 
   emrkc_ctx *c = new (std::nothrow) emrkc_ctx();
   if (c == nullptr) return EMRKC_ENOMEM;
@@ -609,6 +632,15 @@ static double state_time(double t0, int64_t step, double dt) {
   return t0 + (double)step * dt;
 }
 
+// The clock of a state is t0 + step*dt, and every stepping call writes
+// t = t0 + step*dt on return.  A state advanced with one step size and then
+// stepped with another no longer satisfies t == t0 + step*dt for the new
+// dt: move t0 so that the clock continues from t (step keeps counting).
+static void rebase_clock(emrkc_state *st, double dt) {
+#pragma clang fp contract(off)
+  if (st->step != 0 && state_time(st->t0, st->step, dt) != st->t) st->t0 = st->t - (double)st->step * dt;
+}
+
 extern "C" int emrkc_init_state(emrkc_ctx *c, emrkc_state *s) {
   if (c == nullptr) return EMRKC_EINVAL;
   if (!state_ok(c, s)) return fail(c, EMRKC_EINVAL, "state buffers missing");
@@ -658,13 +690,6 @@ extern "C" int emrkc_last_stats(const emrkc_ctx *c, emrkc_stats *out) {
 // ---------------------------------------------------------------------------
 // emRKC steps as sequences of launches
 // ---------------------------------------------------------------------------
-struct StepPlan {
-  int s, m;
-  double eta;
-  std::vector<double> mu, nu, ka, cc;      // outer, index j
-  std::vector<double> mui, nui, kai, cci;  // inner, index k
-};
-
 struct KernelTimer {
   std::vector<hipEvent_t> ev;  // pairs (start, stop)
   std::vector<int> cls;        // 0 = head, 1 = inner, 2 = fused
@@ -987,6 +1012,7 @@ extern "C" int emrkc_step(emrkc_ctx *c, emrkc_state *st, double dt, int64_t nste
   if (!(dt > 0) || !isfinite(dt) || nsteps < 0) return fail(c, EMRKC_EINVAL, "invalid dt or nsteps");
   if (!c->have_rho) return fail(c, EMRKC_EINVAL, "spectral radii not set: call emrkc_estimate_rho or emrkc_set_rho");
   if (nsteps == 0) return EMRKC_OK;
+  rebase_clock(st, dt);
   if (c->rho_every <= 0) return step_core(c, st, dt, nsteps);
   // re-estimate the radii (warm started) before every step whose index is a
   // positive multiple of rho_every; runs of steps in between as usual.  A
@@ -1074,6 +1100,17 @@ static int check_finite(emrkc_ctx *c, const emrkc_state *st) {
   return EMRKC_OK;
 }
 
+static void set_last_stats(emrkc_ctx *c, const StepPlan &P, bool used_graph) {
+  c->last.s = P.s;
+  c->last.m = P.m;
+  c->last.eta = P.eta;
+  c->last.kernels_per_step = c->batch ? (int64_t)P.m
+                              : (c->use_fused && P.s == 1 && P.m >= 2 && fused_supported(c->mesh))
+                                 ? (int64_t)P.m - 1
+                                 : (P.s == 1 && P.m == 1) ? 1 : (int64_t)P.s * P.m + (P.m == 1 ? 1 : 0);
+  c->last.used_graph = used_graph ? 1 : 0;
+}
+
 static int step_core(emrkc_ctx *c, emrkc_state *st, double dt, int64_t nsteps) {
   StepPlan P;
   int rc = make_plan(c, dt, P);
@@ -1085,14 +1122,7 @@ static int step_core(emrkc_ctx *c, emrkc_state *st, double dt, int64_t nsteps) {
   if (rc != EMRKC_OK) return rc;
   st->step += nsteps;
   st->t = state_time(st->t0, st->step, dt);
-  c->last.s = P.s;
-  c->last.m = P.m;
-  c->last.eta = P.eta;
-  c->last.kernels_per_step = c->batch ? (int64_t)P.m
-                              : (c->use_fused && P.s == 1 && P.m >= 2 && fused_supported(c->mesh))
-                                 ? (int64_t)P.m - 1
-                                 : (P.s == 1 && P.m == 1) ? 1 : (int64_t)P.s * P.m + (P.m == 1 ? 1 : 0);
-  c->last.used_graph = used_graph ? 1 : 0;
+  set_last_stats(c, P, used_graph);
   return check_finite(c, st);
 }
 
@@ -1180,6 +1210,7 @@ extern "C" int emrkc_imexrl_step(emrkc_ctx *c, emrkc_state *st, double dt, int64
   if (c->batch) return fail(c, EMRKC_EUNSUPPORTED, "IMEX-RL stepping is for single contexts");
   int rc;
   if ((rc = ensure_imexrl_data(c)) != EMRKC_OK) return rc;
+  rebase_clock(st, dt);
   const uint32_t N = (uint32_t)c->N;
   double *x = (double *)st->V, *b = c->d_U[0], *r = c->d_U[1], *zv = c->d_U[2], *q = c->d_cgq;
   double *const P[2] = {c->d_V1, c->d_cgp2};
@@ -1239,6 +1270,7 @@ extern "C" int emrkc_profile_imexrl(emrkc_ctx *c, emrkc_state *st, double dt, in
   if (c->batch) return fail(c, EMRKC_EUNSUPPORTED, "IMEX-RL stepping is for single contexts");
   int rc;
   if ((rc = ensure_imexrl_data(c)) != EMRKC_OK) return rc;
+  rebase_clock(st, dt);
   const uint32_t N = (uint32_t)c->N;
   double *x = (double *)st->V, *b = c->d_U[0], *r = c->d_U[1], *zv = c->d_U[2], *q = c->d_cgq;
   double *const P[2] = {c->d_V1, c->d_cgp2};
@@ -1316,6 +1348,7 @@ extern "C" int emrkc_exexrl_step(emrkc_ctx *c, emrkc_state *st, double dt, int64
   if (!(dt > 0) || !isfinite(dt) || nsteps < 0) return fail(c, EMRKC_EINVAL, "invalid dt or nsteps");
   if (c->batch) return fail(c, EMRKC_EUNSUPPORTED, "EXEX-RL stepping is for single contexts");
   if (nsteps == 0) return EMRKC_OK;
+  rebase_clock(st, dt);
   bool used_graph = false;
   const int rc = run_chunks(c, st, dt, nsteps, -1, 0,
                             [&](int L, hipStream_t strm) { return enqueue_chunk_exexrl(c, st, dt, L, strm); },
@@ -1348,6 +1381,7 @@ extern "C" int emrkc_profile_step(emrkc_ctx *c, emrkc_state *st, double dt, int6
   int rc = make_plan(c, dt, P);
   if (rc != EMRKC_OK) return rc;
   if (c->batch && (rc = build_batch_tables(c, st, dt, P)) != EMRKC_OK) return rc;
+  rebase_clock(st, dt);
   HIP_TRY(c, launch_clock_set(c->d_clock, st->step, st->t0, c->stream));
   KernelTimer tm;
   rc = enqueue_chunk(c, st, P, dt, (int)nsteps, c->stream, &tm);
@@ -2142,6 +2176,7 @@ extern "C" int emrkc_create_batch(int n_inst, const emrkc_mesh *meshes, const em
     int64_t N = 1;
     for (int d = 0; d < m.dim; ++d) {
       if (m.n[d] < 2 || m.n[d] > (1 << 30) || !(m.h[d] > 0) || !isfinite(m.h[d])) return EMRKC_EINVAL;
+      if (m.n[d] > kMaxNodes / N) return EMRKC_EUNSUPPORTED;  // before the product: no overflow
       N *= m.n[d];
     }
     if (!(p.chi > 0) || !(p.Cm > 0) || !isfinite(p.chi) || !isfinite(p.Cm)) return EMRKC_EINVAL;
@@ -2149,9 +2184,9 @@ extern "C" int emrkc_create_batch(int n_inst, const emrkc_mesh *meshes, const em
     const double sg[3] = {conds[k].sigma_l, conds[k].sigma_t, conds[k].sigma_n};
     for (int d = 0; d < m.dim; ++d)
       if (!(sg[d] >= 0) || !isfinite(sg[d])) return EMRKC_EINVAL;
+    if (N > kMaxNodes - Ntot) return EMRKC_EUNSUPPORTED;
     Ntot += N;
   }
-  if (Ntot >= (int64_t)1 << 31) return EMRKC_EUNSUPPORTED;
 
   emrkc_ctx *c = new (std::nothrow) emrkc_ctx();
   if (c == nullptr) return EMRKC_ENOMEM;

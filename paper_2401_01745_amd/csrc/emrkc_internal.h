@@ -221,9 +221,9 @@ hipError_t launch_mrkc_rhs(int model, int which, const Mesh &mesh, uint32_t N, d
 hipError_t launch_vec_diff_norm(uint64_t n, const double *a, const double *b, double *out, double *partials,
                                 double *result, hipStream_t st);
 hipError_t launch_fused(int model, bool mixed, const Mesh &mesh, const FusedArgs &a, hipStream_t st);
+// The fused kernel stages its tile in LDS: grids only, and not under the
+// flat-kernel switch (mesh.flat), which covers every grid kernel.
 bool fused_supported(const Mesh &mesh);
-// Testing switch: use the flat (one node per thread, global-load stencil)
-// kernels on grids instead of the LDS-tiled ones.  Process-wide.
 hipError_t launch_clock_set(Clock *c, int64_t step, double t0, hipStream_t st);
 hipError_t launch_copy_tick(const double *src, double *dst, uint32_t N, Clock *tick, int64_t tick_by,
                             hipStream_t st);

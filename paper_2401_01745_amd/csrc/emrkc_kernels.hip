@@ -1765,7 +1765,7 @@ hipError_t launch_inner(bool mixed, const Mesh &mesh, const InnerArgs &a, hipStr
   return hipGetLastError();
 }
 
-bool fused_supported(const Mesh &mesh) { return mesh.kind == kGrid; }
+bool fused_supported(const Mesh &mesh) { return mesh.kind == kGrid && !mesh.flat; }
 
 uint32_t grid_tiles(const Grid &g, uint32_t &ntx, uint32_t &nty, int shape) {
   if (g.dim == 3)

@@ -154,6 +154,12 @@ def test_invalid_arguments_rejected_before_any_gpu_call():
     assert create(unknown, None, 3, p) == E.EMRKC_EINVAL
     assert csr.kind == E.EMRKC_MESH_CSR
     assert ctx.value is None
+    # node counts beyond 32-bit device indices, including products that
+    # would wrap a 64-bit integer (2^22 * 2^21 * 2^21 = 2^64)
+    for n in [(1 << 22, 1 << 21, 1 << 21), (1 << 30, 1 << 30, 1 << 30), (46341, 46341), (1 << 11, 1 << 10, 1 << 10)]:
+        huge = E.grid_mesh(n, (0.1,) * len(n))
+        assert create(huge, cond, 1, p) == E.EMRKC_EUNSUPPORTED, n
+    assert ctx.value is None
     # ensembles: no condition-A stage counts, no periodic re-estimation
     meshes = (E.Mesh * 1)(good)
     conds = (E.Conductivity * 1)(cond)
@@ -163,6 +169,14 @@ def test_invalid_arguments_rejected_before_any_gpu_call():
         setattr(q, field, value)
         ps = (E.Params * 1)(q)
         assert L.emrkc_create_batch(1, meshes, conds, 1, ps, C.byref(ctx)) == code
+    # ensembles whose instances, or whose total, exceed 32-bit node indices
+    ps = (E.Params * 3)(p, p, p)
+    big = (E.Mesh * 1)(E.grid_mesh((1 << 22, 1 << 21, 1 << 21), (0.1, 0.1, 0.1)))
+    assert L.emrkc_create_batch(1, big, conds, 1, ps, C.byref(ctx)) == E.EMRKC_EUNSUPPORTED
+    third = E.grid_mesh((1 << 15, 1 << 15), (0.1, 0.1))  # 2^30 nodes each: three exceed 2^31 - 1
+    three = (E.Mesh * 3)(third, third, third)
+    assert L.emrkc_create_batch(3, three, (E.Conductivity * 3)(cond, cond, cond), 1, ps, C.byref(ctx)) == \
+        E.EMRKC_EUNSUPPORTED
     assert ctx.value is None
     # calls on a null context
     assert L.emrkc_step(None, None, 0.1, 1) == E.EMRKC_EINVAL

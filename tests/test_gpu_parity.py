@@ -212,7 +212,10 @@ def test_graph_eager_fused_split_and_repeat_are_bitwise_identical(E, n, rho, pre
     V5, z5, st5 = gpu_run(cfg, 80, rho, precision=precision, flags=E.EMRKC_FUSE)
     V6, z6, _ = gpu_run(cfg, 80, rho, precision=precision, flags=E.EMRKC_FLAT)
     V7, z7, _ = gpu_run(cfg, 80, rho, precision=precision, flags=E.EMRKC_FLAT | E.EMRKC_EAGER)
-    runs = [(V2, z2), (V3, z3), (V4, z4), (V5, z5), (V6, z6), (V7, z7)]
+    # the flat switch covers every grid kernel: with it the fused request
+    # falls back to separate flat head and inner launches
+    V8, z8, st8 = gpu_run(cfg, 80, rho, precision=precision, flags=E.EMRKC_FLAT | E.EMRKC_FUSE)
+    runs = [(V2, z2), (V3, z3), (V4, z4), (V5, z5), (V6, z6), (V7, z7), (V8, z8)]
     if len(n) == 3:
         # z-marching head (register and LDS-staged) and inner kernels with
         # ragged columns and plane counts that do not divide n[2]
@@ -225,6 +228,7 @@ def test_graph_eager_fused_split_and_repeat_are_bitwise_identical(E, n, rho, pre
                 runs.append(gpu_run(cfg, 80, rho, precision=precision, variants=v)[:2])
     assert st1.used_graph == 1 and st2.used_graph == 0
     assert st1.kernels_per_step == st1.m and st5.kernels_per_step == st5.m - 1
+    assert st8.kernels_per_step == st8.m
     for V, z in runs:
         assert np.array_equal(V, V1) and np.array_equal(z, z1)
 
@@ -377,3 +381,41 @@ def test_zero_conductivity_decouples_the_cells(E):
     mask = stim_mask(cfg).astype(bool)
     assert 0 < mask.sum() < mask.size
     assert np.ptp(V[mask]) == 0.0 and np.ptp(V[~mask]) == 0.0 and V[mask][0] > V[~mask][0] + 10.0
+
+
+@pytest.mark.parametrize("method", ["emrkc", "exexrl"])
+def test_step_size_change_continues_the_clock(E, method):
+    """A state advanced with one step size and then stepped with another
+    continues from its own time: the second call's stage times and the end
+    of the stimulus window are those of the oracle started at t1 = n1 dt1
+    with dt2 (without the rebase the window would close 0.36 ms late)."""
+    import torch
+    from oracle.emrkc import emrkc_run
+    from oracle.exexrl import exexrl_step
+    cfg = small_config("c2_3d_crn", (21, 11, 7))
+    cfg["stim"] = dict(cfg["stim"], t_off=1.21)  # no stage time within 1e-3 of it
+    rho = (51.0, 4.4)
+    # EXEX-RL's explicit diffusion needs dt < 2 / rho_F (about 0.04 ms here)
+    dt1, n1, dt2, n2 = (0.05, 12, 0.02, 40) if method == "emrkc" else (0.03, 20, 0.02, 40)
+    sim = E.simulation_from_config(cfg, rho=rho)
+    E.emrkc_init_state(sim.ctx, sim.state)
+    step = E.emrkc_step if method == "emrkc" else E.emrkc_exexrl_step
+    step(sim.ctx, sim.state, dt1, n1)
+    step(sim.ctx, sim.state, dt2, n2)
+    torch.cuda.synchronize()
+    V = sim.V.cpu().numpy()
+    assert sim.state.step == n1 + n2
+    assert abs(sim.state.t - (n1 * dt1 + n2 * dt2)) < 1e-13
+    sim.close()
+    prob = build_grid_problem(cfg)
+    y = prob.uniform_state()
+    if method == "emrkc":
+        y = emrkc_run(prob, y, 0.0, dt1, n1, *rho)
+        y = emrkc_run(prob, y, n1 * dt1, dt2, n2, *rho)
+    else:
+        for n in range(n1):
+            y = exexrl_step(n * dt1, y, dt1, prob)
+        for n in range(n2):
+            y = exexrl_step(n1 * dt1 + n * dt2, y, dt2, prob)
+    l2, mx = rel_errors(V, y[:prob.N])
+    assert l2 < FP64_TOL and mx < FP64_TOL, (l2, mx)
