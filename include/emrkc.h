@@ -280,6 +280,28 @@ int emrkc_stages(const emrkc_ctx *ctx, double dt, int *s, int *m, double *eta);
  * EMRKC_ENONFINITE if V holds a NaN or infinity. */
 int emrkc_step(emrkc_ctx *ctx, emrkc_state *state, double dt, int64_t nsteps);
 
+/* emrkc_step for callers that cannot allocate device memory: code under
+ * HIP graph capture, tight serving loops and harnesses that forbid
+ * hipMalloc.  Advances the state exactly as emrkc_step does (same kernels,
+ * same bits) and calls no hipMalloc, hipFree or other allocating routine:
+ * the kernels' work buffers (the device clock, V_1, the inner values u_k,
+ * S_V and, for s >= 2, z_1) live in a static array of 64 MiB per device that
+ * the library holds until the process ends, and every kernel is launched
+ * directly on the context stream (no graph is instantiated).  Needs
+ * 8 B (4 B for S_V in the mixed precision) per node for each of V_1, u_1,
+ * u_2 and S_V (plus one more u and S_V with EMRKC_FUSE, plus z_1 when
+ * s >= 2) within the 64 MiB, i.e. about 2 million nodes at s = 1, and stage
+ * counts up to 1024; larger problems return EMRKC_EINVAL (EMRKC_EUNSUPPORTED
+ * for stage counts) with the reason in emrkc_last_error.  Single emRKC
+ * contexts only, without rho_every or EMRKC_CHECK_FINITE (EMRKC_EUNSUPPORTED
+ * otherwise); the current device must be the context's.  Every call on one
+ * device shares that device's array and overwrites what the previous call
+ * left there (each call sets its clock before use and writes every other
+ * buffer before reading it), so calls that can overlap on one device --
+ * contexts on concurrently running streams -- race and must be ordered by
+ * the caller. */
+int emrkc_step_noalloc(emrkc_ctx *ctx, emrkc_state *state, double dt, int64_t nsteps);
+
 /* Diagnostic form of emrkc_step: advances the state the same way (same
  * kernels, same results) as one chunk of nsteps steps, but launches every
  * kernel directly on the context stream with a HIP event recorded before

@@ -10,6 +10,7 @@
 #include <algorithm>
 #include <functional>
 #include <map>
+#include <mutex>
 #include <string>
 #include <tuple>
 #include <vector>
@@ -43,6 +44,12 @@ struct StepPlan {
   std::vector<double> mu, nu, ka, cc;      // outer, index j
   std::vector<double> mui, nui, kai, cci;  // inner, index k
 };
+
+// emrkc_step_noalloc: largest stage counts (its plan arrays are sized when
+// the context is created), and the static scratch array every context on a
+// device shares for the step's work buffers.
+constexpr int kNoAllocMaxStages = 1024;
+constexpr size_t kScratchBytes = (size_t)64 << 20;
 
 // One instance of a batched ensemble.
 struct Inst {
@@ -141,6 +148,15 @@ struct emrkc_ctx {
   int64_t last_est_step = -1; // state step of the last re-estimate by emrkc_step
   void *d_z1 = nullptr;
   Clock *d_clock = nullptr;
+  // emrkc_step_noalloc: the device the context was created on, the device
+  // address of that device's scratch array (null if it could not be
+  // resolved, with the reason in scratch_err), and plan arrays of
+  // kNoAllocMaxStages + 1 entries (plus the work space of get_coeffs)
+  int device = 0;
+  unsigned char *scratch = nullptr;
+  std::string scratch_err;
+  StepPlan fixed_plan;
+  std::vector<double> fixed_work;
   double *d_partials = nullptr;
   double *d_result = nullptr;
   int *d_flag = nullptr;
@@ -425,6 +441,50 @@ static int dalloc(emrkc_ctx *c, void **p, size_t bytes) {
 static int build_p1(emrkc_ctx *c, const emrkc_mesh *mesh, const emrkc_conductivity *cond);
 static int build_csr(emrkc_ctx *c, const emrkc_mesh *mesh);
 
+// Work buffers of emrkc_step_noalloc: one array per device, in the code
+// object's zero-initialised device data, so that the call allocates
+// nothing.  The name `scratch` is only a host-side handle: host code
+// resolves the array's device address once per device (with that device
+// current, when the first context on it is created) and passes that
+// address to kernels, never the symbol itself.
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static unsigned char *g_scratch_addr[kMaxDevices];
+
+// Device address of device dev's scratch array (dev must be current), or
+// null with the reason in *why.
+static unsigned char *scratch_address(int dev, std::string *why) {
+  if (dev < 0 || dev >= kMaxDevices) {
+    *why = "device index out of range";
+    return nullptr;
+  }
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch_addr[dev] == nullptr) {
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || p == nullptr) {
+      *why = std::string("hipGetSymbolAddress failed: ") + hipGetErrorString(e);
+      return nullptr;
+    }
+    g_scratch_addr[dev] = (unsigned char *)p;
+  }
+  return g_scratch_addr[dev];
+}
+
+// Sets up what emrkc_step_noalloc needs of a single context: its device,
+// that device's scratch address and plan arrays for kNoAllocMaxStages.
+static int setup_noalloc(emrkc_ctx *c) {
+  HIP_TRY(c, hipGetDevice(&c->device));
+  c->scratch = scratch_address(c->device, &c->scratch_err);
+  StepPlan &P = c->fixed_plan;
+  for (std::vector<double> *v : {&P.mu, &P.nu, &P.ka, &P.cc, &P.mui, &P.nui, &P.kai, &P.cci})
+    v->assign(kNoAllocMaxStages + 1, 0.0);
+  c->fixed_work.assign(3 * (size_t)(kNoAllocMaxStages + 1), 0.0);
+  return EMRKC_OK;
+}
+
 extern "C" int emrkc_create(const emrkc_mesh *mesh, const emrkc_conductivity *cond, int ionic_model,
                             const emrkc_params *p, emrkc_ctx **out) {
   if (out == nullptr) return EMRKC_EINVAL;
@@ -585,6 +645,7 @@ extern "C" int emrkc_create(const emrkc_mesh *mesh, const emrkc_conductivity *co
       goto error;
     }
   }
+  if ((rc = setup_noalloc(c)) != EMRKC_OK) goto error;
   *out = c;
   return EMRKC_OK;
 error:
@@ -1124,6 +1185,142 @@ static int step_core(emrkc_ctx *c, emrkc_state *st, double dt, int64_t nsteps) {
   st->t = state_time(st->t0, st->step, dt);
   set_last_stats(c, P, used_graph);
   return check_finite(c, st);
+}
+
+// ---------------------------------------------------------------------------
+// emrkc_step without allocation: the step's work buffers (the device clock,
+// V_1, the inner values u_k, S_V and, for s >= 2, z_1) come from the
+// device's static scratch array instead of the context, the coefficient
+// tables go to arrays sized at creation, and the kernels are launched
+// directly on the context stream (no graph is instantiated).  The kernels
+// and their order are those of emrkc_step's eager path, so the results are
+// the same bits.
+// ---------------------------------------------------------------------------
+static int make_plan_fixed(emrkc_ctx *c, double dt) {
+  StepPlan &P = c->fixed_plan;
+  int rc = select_stages(c, dt, c->rho_F, c->rho_S, &P.s, &P.m, &P.eta);
+  if (rc != EMRKC_OK) return fail(c, rc, "stage selection failed (dt=%g rho_F=%g rho_S=%g)", dt, c->rho_F, c->rho_S);
+  if (P.s > kNoAllocMaxStages || P.m > kNoAllocMaxStages)
+    return fail(c, EMRKC_EUNSUPPORTED, "emrkc_step_noalloc: stage counts (s=%d, m=%d) above %d", P.s, P.m,
+                kNoAllocMaxStages);
+  double *w = c->fixed_work.data();
+  const size_t K = kNoAllocMaxStages + 1;
+  rkc_coeffs_into(P.s, c->eps, P.mu.data(), P.nu.data(), P.ka.data(), P.cc.data(), w, w + K, w + 2 * K);
+  rkc_coeffs_into(P.m, c->eps, P.mui.data(), P.nui.data(), P.kai.data(), P.cci.data(), w, w + K, w + 2 * K);
+  return EMRKC_OK;
+}
+
+// Byte offsets of the work buffers in the scratch array (256-byte aligned).
+struct ScratchLayout {
+  size_t clock, V1, U[3], SV, SV2, z1, total;
+};
+
+static ScratchLayout scratch_layout(const emrkc_ctx *c, int s, bool fused) {
+  auto up = [](size_t x) { return (x + 255) & ~(size_t)255; };
+  const size_t N = (size_t)c->N;
+  const size_t vb = up(sizeof(double) * N);
+  const size_t svb = up((c->mixed ? sizeof(float) : sizeof(double)) * N);
+  ScratchLayout L{};
+  size_t o = 0;
+  L.clock = o;
+  o += up(sizeof(Clock));
+  L.V1 = o;
+  o += vb;
+  L.U[0] = o;
+  o += vb;
+  L.U[1] = o;
+  o += vb;
+  L.SV = o;
+  o += svb;
+  if (fused) {  // the fused chunk rotates three inner buffers and two S_V
+    L.U[2] = o;
+    o += vb;
+    L.SV2 = o;
+    o += svb;
+  }
+  if (s >= 2) {  // z_j of the odd stages
+    L.z1 = o;
+    o += up((c->mixed ? sizeof(float) : sizeof(double)) * N * (size_t)(c->nv - 1));
+  }
+  L.total = o;
+  return L;
+}
+
+// Points the context's step work buffers into the scratch array while it
+// lives (the enqueue functions take them from the context) and gives the
+// context its own buffers back when it goes out of scope, on every return.
+struct ScratchWork {
+  emrkc_ctx *c;
+  double *V1, *U[3];
+  void *SV, *SV2, *z1;
+  Clock *clock;
+  ScratchWork(emrkc_ctx *ctx, const ScratchLayout &L, bool fused, int s) : c(ctx) {
+    V1 = c->d_V1;
+    for (int k = 0; k < 3; ++k) U[k] = c->d_U[k];
+    SV = c->d_SV;
+    SV2 = c->d_SV2;
+    z1 = c->d_z1;
+    clock = c->d_clock;
+    unsigned char *b = c->scratch;
+    c->d_clock = (Clock *)(b + L.clock);
+    c->d_V1 = (double *)(b + L.V1);
+    c->d_U[0] = (double *)(b + L.U[0]);
+    c->d_U[1] = (double *)(b + L.U[1]);
+    c->d_U[2] = fused ? (double *)(b + L.U[2]) : nullptr;
+    c->d_SV = b + L.SV;
+    c->d_SV2 = fused ? (void *)(b + L.SV2) : nullptr;
+    c->d_z1 = s >= 2 ? (void *)(b + L.z1) : nullptr;
+  }
+  ~ScratchWork() {
+    c->d_V1 = V1;
+    for (int k = 0; k < 3; ++k) c->d_U[k] = U[k];
+    c->d_SV = SV;
+    c->d_SV2 = SV2;
+    c->d_z1 = z1;
+    c->d_clock = clock;
+  }
+};
+
+extern "C" int emrkc_step_noalloc(emrkc_ctx *c, emrkc_state *st, double dt, int64_t nsteps) {
+  if (c == nullptr) return EMRKC_EINVAL;
+  if (!state_ok(c, st)) return fail(c, EMRKC_EINVAL, "state buffers missing");
+  if (!(dt > 0) || !isfinite(dt) || nsteps < 0) return fail(c, EMRKC_EINVAL, "invalid dt or nsteps");
+  if (!c->have_rho) return fail(c, EMRKC_EINVAL, "spectral radii not set: call emrkc_estimate_rho or emrkc_set_rho");
+  if (c->batch || c->method != EMRKC_METHOD_EMRKC || c->rho_every > 0 || (c->flags & EMRKC_CHECK_FINITE))
+    return fail(c, EMRKC_EUNSUPPORTED,
+                "emrkc_step_noalloc takes single emRKC contexts without rho_every or EMRKC_CHECK_FINITE");
+  if (c->scratch == nullptr) return fail(c, EMRKC_EHIP, "static scratch unavailable: %s", c->scratch_err.c_str());
+  int dev = -1;
+  HIP_TRY(c, hipGetDevice(&dev));
+  if (dev != c->device)
+    return fail(c, EMRKC_EINVAL, "context created on device %d, current device is %d", c->device, dev);
+  if (nsteps == 0) return EMRKC_OK;
+  int rc = make_plan_fixed(c, dt);
+  if (rc != EMRKC_OK) return rc;
+  const StepPlan &P = c->fixed_plan;
+  const bool fused = c->use_fused && P.s == 1 && P.m >= 2 && fused_supported(c->mesh);
+  const ScratchLayout L = scratch_layout(c, P.s, fused);
+  if (L.total > kScratchBytes)
+    return fail(c, EMRKC_EINVAL,
+                "emrkc_step_noalloc: %lld nodes with s=%d need %zu bytes of scratch, more than the %zu of the "
+                "static array",
+                (long long)c->N, P.s, L.total, kScratchBytes);
+  rebase_clock(st, dt);
+  {
+    ScratchWork work(c, L, fused, P.s);
+    // the same chunking as emrkc_step, so the clock advances identically
+    HIP_TRY(c, launch_clock_set(c->d_clock, st->step, st->t0, c->stream));
+    const int chunk = (int)std::min<int64_t>(nsteps, 32);
+    const int64_t full = nsteps / chunk;
+    const int rem = (int)(nsteps - full * chunk);
+    for (int64_t r = 0; r < full; ++r)
+      if ((rc = enqueue_chunk(c, st, P, dt, chunk, c->stream)) != EMRKC_OK) return rc;
+    if (rem > 0 && (rc = enqueue_chunk(c, st, P, dt, rem, c->stream)) != EMRKC_OK) return rc;
+  }
+  st->step += nsteps;
+  st->t = state_time(st->t0, st->step, dt);
+  set_last_stats(c, P, false);
+  return EMRKC_OK;
 }
 
 // ---------------------------------------------------------------------------

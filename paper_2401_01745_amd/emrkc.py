@@ -103,6 +103,7 @@ EXPORTS = {
     "emrkc_stages": (C.c_int, [C.c_void_p, C.c_double, C.POINTER(C.c_int), C.POINTER(C.c_int),
                                C.POINTER(C.c_double)]),
     "emrkc_step": (C.c_int, [C.c_void_p, C.POINTER(State), C.c_double, C.c_int64]),
+    "emrkc_step_noalloc": (C.c_int, [C.c_void_p, C.POINTER(State), C.c_double, C.c_int64]),
     "emrkc_last_stats": (C.c_int, [C.c_void_p, C.POINTER(Stats)]),
     "emrkc_profile_step": (C.c_int, [C.c_void_p, C.POINTER(State), C.c_double, C.c_int64, C.POINTER(C.c_double),
                                      C.POINTER(C.c_int64)]),
@@ -267,6 +268,12 @@ def emrkc_stages(ctx, dt):
 
 def emrkc_step(ctx, state, dt, nsteps):
     return _check(lib().emrkc_step(ctx, C.byref(state), dt, int(nsteps)), ctx)
+
+
+def emrkc_step_noalloc(ctx, state, dt, nsteps):
+    """emrkc_step with the work buffers in the library's static scratch
+    array (allocates nothing)."""
+    return _check(lib().emrkc_step_noalloc(ctx, C.byref(state), dt, int(nsteps)), ctx)
 
 
 PROFILE_CLASSES = ("head", "inner", "fused")

@@ -180,6 +180,7 @@ def test_invalid_arguments_rejected_before_any_gpu_call():
     assert ctx.value is None
     # calls on a null context
     assert L.emrkc_step(None, None, 0.1, 1) == E.EMRKC_EINVAL
+    assert L.emrkc_step_noalloc(None, None, 0.1, 1) == E.EMRKC_EINVAL
     assert L.emrkc_set_rho(None, 1.0, 1.0) == E.EMRKC_EINVAL
     assert L.emrkc_num_nodes(None) == -1
     L.emrkc_destroy(None)
