@@ -53,6 +53,16 @@ def bytes_per_node(kind, nz, wz, m, mat=0):
     sv = 4 if wz == 4 else 8
     if kind == "head":
         return 8 + 2 * nz * wz + (8 if m == 1 else sv + 8) + mat
+    # the split stage (m >= 2, 3-D grids): the pointwise head reads V and z,
+    # writes z and S_V; the two-stage inner kernel reads V (u_0) and S_V and
+    # writes V_j (m == 2) or u_1 and u_2 (m >= 3)
+    if kind == "head_pw":
+        return 8 + 2 * nz * wz + sv
+    if kind == "inner12":
+        return 8 + sv + (8 if m == 2 else 16)
+    # u_1 as an inner-kernel launch (head shape 8): reads u_0 = V and S_V, writes u_1
+    if kind == "inner1":
+        return 8 + sv + 8
     if kind == "fused":
         return 8 + (8 if m >= 3 else 0) + 8 + sv + 2 * nz * wz + sv + 8 + 8 + 2 * mat
     if kind == "inner":
@@ -355,6 +365,8 @@ def main():
         log("bench: kernel means (ms, launches): %s" % prof)
         dom = "fused" if prof["fused"][1] > prof["head"][1] else "head"
         dom_ms = prof[dom][0]
+        # the split stage: pointwise head + two-stage inner kernel (shape 7)
+        split = batch is None and tet is None and args.method == "emrkc" and variants[0] in (7, 8) and m >= 2
         width = E.lib().emrkc_ell_width(job.sim.ctx) if tet is not None else 0
         mat = width * (4 + 8)
         if batch is not None:
@@ -363,6 +375,8 @@ def main():
             db = int(sum(n * bytes_per_node("head", nz, 8, mk) for n, mk in zip(sizes, ms)))
         elif args.method == "mrkc":
             db = bytes_per_node("mrkc_head", nz, 8, m, mat) * N
+        elif split:
+            db = bytes_per_node("head_pw", nz, 8, m) * N
         else:
             db = bytes_per_node(dom, nz, 8, m, mat) * N
         dom_gbs = db / (dom_ms * 1e-3) / 1e9
@@ -389,10 +403,12 @@ def main():
                        "k_head" if tet is not None else
                        {0: "k_head_tiled", 1: "k_head_march", 2: "k_head_march_lds", 3: "k_head_tiled_occ<6 waves/SIMD>",
                         4: "k_head_tiled_occ<8 waves/SIMD>", 5: "k_head (flat)",
-                        6: "k_head_occ (flat, 7 waves per SIMD)"}[variants[0]])
+                        6: "k_head_occ (flat, 7 waves per SIMD)", 7: "k_head_pw (pointwise)",
+                        8: "k_head_pw (pointwise)"}[variants[0]])
         names = {"fused": "k_fused (last inner stage of step n-1 + exponential Euler, ionic model, outer z "
                           "recurrence and first inner stage of step n)",
-                 "head": "%s (exponential Euler, ionic model, outer z recurrence, first inner stage)" % head_kernel
+                 "head": ("%s (exponential Euler, ionic model, outer z recurrence, S_V)" % head_kernel if split else
+                          "%s (exponential Euler, ionic model, outer z recurrence, first inner stage)" % head_kernel)
                  if args.method == "emrkc" else
                  "%s (ionic model and gate rates, outer z recurrence, first inner stage of V and the stiffest "
                  "gate)" % head_kernel}
@@ -400,6 +416,10 @@ def main():
         # Chebyshev recurrence + outer V update) when m == 2
         if batch is not None:
             ib = int(sum(n * bytes_per_node("tail", nz, 8, 2) for n, mk in zip(sizes, ms) if mk == 2))
+        elif split and variants[0] == 7:
+            ib = bytes_per_node("inner12", nz, 8, m) * N if m == 2 else None
+        elif split:  # u_1 launch and the last inner stage, mean bytes per launch
+            ib = (bytes_per_node("inner1", nz, 8, m) + bytes_per_node("tail", nz, 8, m)) * N // 2 if m == 2 else None
         elif args.method == "mrkc":
             ib = bytes_per_node("mrkc_tail", nz, 8, m, mat) * N if m == 2 else None
         else:
@@ -410,7 +430,11 @@ def main():
                 "bytes_per_launch": db, "launch_ms": round(dom_ms, 5), "valu": valu,
                 "kernels_ms": {k: round(v[0], 5) for k, v in prof.items()},
                 "launches": {k: v[1] for k, v in prof.items()},
-                "inner_stencil_kernel": {"achieved_GBs": round(inner_gbs, 1) if inner_gbs else None,
+                "inner_stencil_kernel": {"kernel": "k_inner12_march (first two inner stages and the outer V update)"
+                                         if split and variants[0] == 7 else
+                                         "first inner stage and last inner stage with the outer V update (mean)"
+                                         if split else "last inner stage and the outer V update",
+                                         "achieved_GBs": round(inner_gbs, 1) if inner_gbs else None,
                                          "frac": round(inner_gbs / HBM_PEAK_GBS, 4) if inner_gbs else None,
                                          "bytes_per_launch": ib}}
 
@@ -434,12 +458,24 @@ def main():
                 off_m, ms_m, _, _ = E.emrkc_batch_info(jm.sim.ctx, cfg["dt"])
                 dbm = int(sum(n * bytes_per_node("head", nz, 4, mk) for n, mk in zip(np.diff(off_m), ms_m)))
             else:
-                dbm = bytes_per_node("head", nz, 4, E.emrkc_stages(jm.sim.ctx, cfg["dt"])[1], mat_m) * N
+                mm = E.emrkc_stages(jm.sim.ctx, cfg["dt"])[1]
+                split_m = tet is None and variants_m[0] in (7, 8) and mm >= 2
+                dbm = bytes_per_node("head_pw" if split_m else "head", nz, 4, mm, mat_m) * N
             head_m = {"launch_ms": round(pm["head"][0], 5), "bytes_per_launch": dbm,
                       "achieved_GBs": round(dbm / (pm["head"][0] * 1e-3) / 1e9, 1),
                       "frac": round(dbm / (pm["head"][0] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)} if pm["head"][1] else None
+            inner_m = None
+            if batch is None and pm["inner"][1]:
+                mm = E.emrkc_stages(jm.sim.ctx, cfg["dt"])[1]
+                ibm = (bytes_per_node("inner12", nz, 4, mm) if (tet is None and variants_m[0] == 7 and mm == 2) else
+                       (bytes_per_node("inner1", nz, 4, mm) + bytes_per_node("tail", nz, 4, mm)) // 2
+                       if (tet is None and variants_m[0] == 8 and mm == 2) else
+                       bytes_per_node("tail", nz, 4, mm, mat_m) if mm == 2 else None)
+                if ibm:
+                    inner_m = {"launch_ms": round(pm["inner"][0], 5), "bytes_per_launch": ibm * N,
+                               "achieved_GBs": round(ibm * N / (pm["inner"][0] * 1e-3) / 1e9, 1)}
             mixed = {"value": value_m, "speedup_vs_fp64": round(value_m / value, 3), "kernel_shapes": variants_m,
-                     "head_kernel": head_m,
+                     "head_kernel": head_m, "inner_kernel": inner_m,
                      "s_m": list(sm_m),
                      "V_rel_l2_vs_fp64": float(torch.linalg.vector_norm(d).item() /
                                                torch.linalg.vector_norm(V64).item()),

@@ -439,7 +439,10 @@ struct Grid {
   // columns of zc (head_zc) planes per block (2.5-D); heads also 2 = columns
   // with the ionic state staged through LDS, 3/4 = tiles for 6/8 waves per
   // SIMD, 5 = flat (one node per thread), 6 = flat for 7 waves per SIMD
-  // (mixed precision only); chosen by the host
+  // (mixed precision only), 7 and 8 = the split stage with a pointwise head
+  // (7: one kernel for the first two inner stages in columns of head_zc
+  // planes; 8: the first inner stage as a launch of the inner kernel);
+  // chosen by the host
   int inner_variant;
   uint32_t zc;
   int head_variant;

@@ -807,6 +807,15 @@ static TailArgs make_stage(const StepPlan &P, double dt, int j, int k) {
   return t;
 }
 
+// Head shape 8 (3-D grids, m >= 2): the pointwise head writes z_j and S_V,
+// and the first inner stage u_1 = u_0 + mu'_1 eta (f_F(u_0) + S_V) is an
+// inner-kernel launch of its own (the grid's inner shape), ahead of the
+// usual inner stages; the buffers follow the generic step.
+static bool u1_split_mode(const emrkc_ctx *c, const StepPlan &P) {
+  return c->method == EMRKC_METHOD_EMRKC && !c->batch && split_supported(c->mesh) &&
+         c->mesh.grid.head_variant == 8 && P.m >= 2;
+}
+
 // One step, any (s, m), with separate head and inner kernels.
 //
 // V_j lives in X[j % 2] for j < s (X[0] = the caller's V, X[1] a library
@@ -837,7 +846,22 @@ static int enqueue_step_generic(emrkc_ctx *c, const emrkc_state *st, const StepP
     h.zin2 = j >= 2 ? Z[zidx(j - 2)] : nullptr;
     h.zout = Z[zidx(j)];
     h.uout = m >= 2 ? c->d_U[0] : Vdst;
-    TIMED(0, launch_head(c->model, c->mixed, c->mesh, h, strm));
+    if (u1_split_mode(c, P)) {
+      // head shape 8: the pointwise head, then u_1 by the inner kernel
+      h.uout = nullptr;
+      TIMED(0, launch_head_pw(c->model, c->mixed, c->mesh, h, strm));
+      InnerArgs a{};
+      a.t = make_stage(P, dt, j, 1);
+      a.t.mu_eta = P.mui[1] * P.eta;
+      a.t.uprev = Vin;
+      a.t.uprev2 = Vin;
+      a.t.SV = c->d_SV;
+      a.first = 1;
+      a.out = c->d_U[0];
+      TIMED(1, launch_inner(c->mixed, c->mesh, a, strm));
+    } else {
+      TIMED(0, launch_head(c->model, c->mixed, c->mesh, h, strm));
+    }
     for (int k = 2; k <= m; ++k) {
       InnerArgs a{};
       a.t = make_stage(P, dt, j, k);
@@ -857,6 +881,99 @@ static int enqueue_step_generic(emrkc_ctx *c, const emrkc_state *st, const StepP
     HIP_TRY(c, launch_copy_tick(final_copy ? X[1] : nullptr, X[0], (uint32_t)c->N, tick_by > 0 ? c->d_clock : nullptr,
                                 tick_by, strm));
   }
+  return EMRKC_OK;
+}
+
+// The split stage (3-D grids, head shape 7, m >= 2): the pointwise head
+// writes z_j and S_V only, and k_inner12_march forms u_1 and u_2 in one
+// pass (for m == 2 with the outer V update).  That kernel reads V_{j-1} with
+// a halo, so with m == 2 it cannot write V_j over V_{j-1}: the buffers
+// follow the rule of the m == 1 path (the last stage writes X[1] and copies
+// when V_{s-1} is in X[0]); with m >= 3 the last inner stage reads u with a
+// halo and V pointwise, as in the generic step.
+static bool split_mode(const emrkc_ctx *c, const StepPlan &P) {
+  return c->method == EMRKC_METHOD_EMRKC && !c->batch && split_supported(c->mesh) &&
+         c->mesh.grid.head_variant == 7 && P.m >= 2;
+}
+
+static Inner12Args make_inner12(emrkc_ctx *c, const StepPlan &P, double dt, int j, const double *Vin,
+                                const double *Vin2) {
+  Inner12Args a{};
+  a.t = make_stage(P, dt, j, 2);
+  a.V = Vin;
+  a.Vin2 = Vin2;
+  a.SV = c->d_SV;
+  a.mu1_eta = P.mui[1] * P.eta;
+  a.last = P.m == 2;
+  a.out = P.m == 2 ? nullptr : c->d_U[1];
+  a.u1out = P.m == 2 ? nullptr : c->d_U[0];
+  return a;
+}
+
+static int enqueue_step_split(emrkc_ctx *c, const emrkc_state *st, const StepPlan &P, double dt, int step_off,
+                              int64_t tick_by, hipStream_t strm, KernelTimer *tm) {
+  const int s = P.s, m = P.m;
+  double *X[2] = {(double *)st->V, c->d_V1};
+  void *Z[2] = {st->z, c->d_z1};
+  auto vidx = [&](int j) { return j == 0 ? 0 : (j < s ? j % 2 : 0); };
+  const bool final_copy = m == 2 && vidx(s - 1) == 0;
+  for (int j = 1; j <= s; ++j) {
+    const bool lastj = j == s;
+    double *Vin = X[vidx(j - 1)];
+    double *Vin2 = j >= 2 ? X[vidx(j - 2)] : nullptr;
+    double *Vdst = (lastj && final_copy) ? X[1] : X[vidx(j)];
+    HeadArgs h = make_head(c, P, dt, j, step_off);
+    h.Vin = Vin;
+    h.Vin2 = Vin2;
+    h.zin = Z[vidx(j - 1)];
+    h.zin2 = j >= 2 ? Z[vidx(j - 2)] : nullptr;
+    h.zout = Z[vidx(j)];
+    h.uout = nullptr;
+    TIMED(0, launch_head_pw(c->model, c->mixed, c->mesh, h, strm));
+    Inner12Args a = make_inner12(c, P, dt, j, Vin, Vin2);
+    if (m == 2) a.out = Vdst;
+    a.tick = (lastj && m == 2 && tick_by > 0 && !final_copy) ? c->d_clock : nullptr;
+    a.tick_by = tick_by;
+    TIMED(1, launch_inner12(c->mixed, c->mesh, a, strm));
+    for (int k = 3; k <= m; ++k) {
+      InnerArgs b{};
+      b.t = make_stage(P, dt, j, k);
+      b.t.uprev = c->d_U[(k - 2) % 2];
+      b.t.uprev2 = c->d_U[(k - 3) % 2];
+      b.t.SV = c->d_SV;
+      b.t.Vin = Vin;
+      b.t.Vin2 = Vin2;
+      b.last = k == m;
+      b.out = b.last ? Vdst : c->d_U[(k - 1) % 2];
+      b.tick = (lastj && k == m && tick_by > 0) ? c->d_clock : nullptr;
+      b.tick_by = tick_by;
+      TIMED(1, launch_inner(c->mixed, c->mesh, b, strm));
+    }
+  }
+  if (final_copy)
+    HIP_TRY(c, launch_copy_tick(X[1], X[0], (uint32_t)c->N, tick_by > 0 ? c->d_clock : nullptr, tick_by, strm));
+  return EMRKC_OK;
+}
+
+// L split steps with s == 1 and m == 2: V^n alternates X[n % 2] (the inner
+// kernel reads V^n with a halo while it writes V^{n+1}); an odd chunk ends
+// with one copy back to X[0].
+static int enqueue_chunk_split_s1m2(emrkc_ctx *c, const emrkc_state *st, const StepPlan &P, double dt, int L,
+                                    hipStream_t strm, KernelTimer *tm) {
+  double *X[2] = {(double *)st->V, c->d_V1};
+  for (int n = 0; n < L; ++n) {
+    HeadArgs h = make_head(c, P, dt, 1, n);
+    h.Vin = X[n % 2];
+    h.zin = h.zout = st->z;
+    h.uout = nullptr;
+    TIMED(0, launch_head_pw(c->model, c->mixed, c->mesh, h, strm));
+    Inner12Args a = make_inner12(c, P, dt, 1, X[n % 2], nullptr);
+    a.out = X[(n + 1) % 2];
+    a.tick = (n == L - 1 && L % 2 == 0) ? c->d_clock : nullptr;
+    a.tick_by = L;
+    TIMED(1, launch_inner12(c->mixed, c->mesh, a, strm));
+  }
+  if (L % 2) HIP_TRY(c, launch_copy_tick(X[1], X[0], (uint32_t)c->N, c->d_clock, L, strm));
   return EMRKC_OK;
 }
 
@@ -1013,6 +1130,14 @@ static int enqueue_chunk(emrkc_ctx *c, const emrkc_state *st, const StepPlan &P,
     }
     return EMRKC_OK;
   }
+  if (split_mode(c, P)) {
+    if (P.s == 1 && P.m == 2) return enqueue_chunk_split_s1m2(c, st, P, dt, L, strm, tm);
+    for (int n = 0; n < L; ++n) {
+      int rc = enqueue_step_split(c, st, P, dt, n, n == L - 1 ? L : 0, strm, tm);
+      if (rc != EMRKC_OK) return rc;
+    }
+    return EMRKC_OK;
+  }
   if (c->use_fused && P.s == 1 && P.m >= 2 && fused_supported(c->mesh))
     return enqueue_chunk_fused(c, st, P, dt, L, strm, tm);
   if (P.s == 1 && P.m == 1) return enqueue_chunk_s1m1(c, st, P, dt, L, strm, tm);
@@ -1165,7 +1290,12 @@ static void set_last_stats(emrkc_ctx *c, const StepPlan &P, bool used_graph) {
   c->last.s = P.s;
   c->last.m = P.m;
   c->last.eta = P.eta;
+  // split steps: s (head + m - 1 inner kernels), plus the copy when m == 2
+  // and V_{s-1} ends in the caller's buffer (s odd, s > 1; s == 1 alternates)
+  const int64_t split = (int64_t)P.s * P.m + (P.m == 2 && P.s > 1 && P.s % 2 == 1 ? 1 : 0);
   c->last.kernels_per_step = c->batch ? (int64_t)P.m
+                              : split_mode(c, P) ? split
+                              : u1_split_mode(c, P) ? (int64_t)P.s * (P.m + 1)
                               : (c->use_fused && P.s == 1 && P.m >= 2 && fused_supported(c->mesh))
                                  ? (int64_t)P.m - 1
                                  : (P.s == 1 && P.m == 1) ? 1 : (int64_t)P.s * P.m + (P.m == 1 ? 1 : 0);
@@ -1657,7 +1787,7 @@ static void get_variants(const emrkc_ctx *c, int *v) {
   const Grid &g = c->mesh.grid;
   const bool t = tunable(c);
   v[0] = t ? g.head_variant : 0;
-  v[1] = t && (g.head_variant == 1 || g.head_variant == 2) ? (int)g.head_zc : 0;
+  v[1] = t && (g.head_variant == 1 || g.head_variant == 2 || g.head_variant == 7) ? (int)g.head_zc : 0;
   v[2] = t ? g.inner_variant : 0;
   v[3] = t && g.inner_variant ? (int)g.zc : 0;
   v[4] = c->use_fused ? 1 : 0;
@@ -1671,11 +1801,12 @@ static int check_variants(const emrkc_ctx *c, const int *v) {
   if (v[4] < 0 || v[4] > 1 || (v[4] == 1 && !fusable(c))) return EMRKC_EUNSUPPORTED;
   if (!tunable(c)) return (v[0] | v[1] | v[2] | v[3]) == 0 ? EMRKC_OK : EMRKC_EUNSUPPORTED;
   const int n2 = (int)c->mesh.grid.n2;
-  if (v[0] < 0 || v[0] > 6 || v[2] < 0 || v[2] > 1) return EMRKC_EINVAL;
-  if (v[0] == 6 && !c->mixed) return EMRKC_EUNSUPPORTED;  // a mixed-precision kernel
+  if (v[0] < 0 || v[0] > 8 || v[2] < 0 || v[2] > 1) return EMRKC_EINVAL;
+  if (v[0] == 6 && !c->mixed) return EMRKC_EUNSUPPORTED;       // a mixed-precision kernel
+  if (v[0] >= 7 && v[4] != 0) return EMRKC_EINVAL;             // the split stage replaces the fused kernel
   // the LDS-staged head addresses a component plane with 32-bit byte offsets
   if (v[0] == 2 && (uint64_t)c->N * sizeof(double) >= (1ull << 32)) return EMRKC_EUNSUPPORTED;
-  const bool head_cols = v[0] == 1 || v[0] == 2;
+  const bool head_cols = v[0] == 1 || v[0] == 2 || v[0] == 7;
   if (head_cols && (v[1] < 1 || v[1] > 64 || v[1] > n2)) return EMRKC_EINVAL;
   if (v[2] != 0 && (v[3] < 1 || v[3] > 64 || v[3] > n2)) return EMRKC_EINVAL;
   if (!head_cols && v[1] != 0) return EMRKC_EINVAL;
@@ -1693,7 +1824,7 @@ static void set_variants(emrkc_ctx *c, const int *v) {
   if (tunable(c)) {
     Grid &g = c->mesh.grid;
     g.head_variant = v[0];
-    g.head_zc = (v[0] == 1 || v[0] == 2) ? (uint32_t)v[1] : 1u;
+    g.head_zc = (v[0] == 1 || v[0] == 2 || v[0] == 7) ? (uint32_t)v[1] : 1u;
     g.inner_variant = v[2];
     g.zc = v[2] ? (uint32_t)v[3] : 1u;
   }
@@ -1859,9 +1990,60 @@ extern "C" int emrkc_autotune(emrkc_ctx *c, const emrkc_state *st, double dt, in
       choice[3] = v[3];
     }
   }
+  // the split stage (m >= 2): the pointwise head and the two-stage inner
+  // kernel with columns of zc planes, compared by the time per step
+  bool split_chosen = false;
+  if (rc == EMRKC_OK && tunable(c) && P.m >= 2) {
+    const double plain = best_h + (P.m - 1) * best_i;
+    double best_split = 1e300;
+    int best_zc = 0;
+    const Grid &g = c->mesh.grid;
+    const uint32_t cols = ((g.n0 + MX - 1) / MX) * ((g.n1 + MY - 1) / MY);
+    for (int zc : {4, 8, 16, 32, 64}) {
+      if (zc > (int)g.n2 || cols * ((g.n2 + zc - 1) / zc) < 256) continue;
+      const int vs[5] = {7, zc, choice[2], choice[3], 0};
+      set_variants(c, vs);
+      double ms[3];
+      rc = time_classes(c, &cp.st, P, dt, reps, ms);
+      if (rc != EMRKC_OK) break;
+      const double step = ms[0] + (P.m - 1) * ms[1];
+      if (verbose)
+        fprintf(stderr, "emrkc_autotune: split %d planes: head %.5f ms, inner %.5f ms, step %.5f ms (separate %.5f)\n",
+                zc, ms[0], ms[1], step, plain);
+      if (step < best_split) {
+        best_split = step;
+        best_zc = zc;
+      }
+    }
+    // shape 8: the pointwise head and u_1 by the chosen inner kernel
+    double step8 = 1e300;
+    if (rc == EMRKC_OK) {
+      const int v8[5] = {8, 0, choice[2], choice[3], 0};
+      set_variants(c, v8);
+      double ms[3];
+      rc = time_classes(c, &cp.st, P, dt, reps, ms);
+      if (rc == EMRKC_OK) {
+        step8 = ms[0] + P.m * ms[1];
+        if (verbose)
+          fprintf(stderr, "emrkc_autotune: split with u_1 launch: head %.5f ms, inner %.5f ms, step %.5f ms\n", ms[0],
+                  ms[1], step8);
+      }
+    }
+    if (rc == EMRKC_OK && std::min(best_split, step8) < 0.97 * plain) {
+      if (step8 <= best_split) {
+        choice[0] = 8;
+        choice[1] = 0;
+      } else {
+        choice[0] = 7;
+        choice[1] = best_zc;
+      }
+      choice[4] = 0;
+      split_chosen = true;
+    }
+  }
   // fused tail+head (s == 1, m >= 2): one kernel per step in place of the
   // head and the last inner stage; compared by the time per step
-  if (rc == EMRKC_OK && fuse_ok) {
+  if (rc == EMRKC_OK && fuse_ok && !split_chosen) {
     double ms[3];
     choice[4] = 0;
     set_variants(c, choice);

@@ -83,6 +83,22 @@ struct InnerArgs {
   TailArgs t;            // uprev, uprev2, SV and the inner coefficients are used for every k
   double *out;           // u_k, or V_j when last
   int last;
+  int first;             // k == 1 of the split stage: u_1 = u_0 + mu'_1 eta (f_F(u_0) + S_V), mu_eta = mu'_1 eta, uprev = u_0
+  Clock *tick;           // when non-null, block 0 adds tick_by to the chunk base step
+  int64_t tick_by;
+};
+
+// First two inner stages of the split stage (3-D grids, m >= 2): u_1 from
+// V_{j-1} and S_V, u_2 from u_1, and for m == 2 the outer V update.
+struct Inner12Args {
+  TailArgs t;            // coefficients of inner stage 2 and of the outer update (uprev unused)
+  const double *V;       // V_{j-1} = u_0 (read with a two-node halo)
+  const double *Vin2;    // V_{j-2} (m == 2, j >= 2)
+  const void *SV;
+  double mu1_eta;        // mu'_1 eta
+  double *out;           // V_j (m == 2) or u_2
+  double *u1out;         // u_1 (m >= 3)
+  int last;              // m == 2
   Clock *tick;           // when non-null, block 0 adds tick_by to the chunk base step
   int64_t tick_by;
 };
@@ -224,6 +240,11 @@ hipError_t launch_fused(int model, bool mixed, const Mesh &mesh, const FusedArgs
 // The fused kernel stages its tile in LDS: grids only, and not under the
 // flat-kernel switch (mesh.flat), which covers every grid kernel.
 bool fused_supported(const Mesh &mesh);
+// The split stage: the pointwise head k_head_pw (z and S_V only) and the
+// two-stage inner kernel k_inner12_march; 3-D grids, not under mesh.flat.
+bool split_supported(const Mesh &mesh);
+hipError_t launch_head_pw(int model, bool mixed, const Mesh &mesh, const HeadArgs &a, hipStream_t st);
+hipError_t launch_inner12(bool mixed, const Mesh &mesh, const Inner12Args &a, hipStream_t st);
 hipError_t launch_clock_set(Clock *c, int64_t step, double t0, hipStream_t st);
 hipError_t launch_copy_tick(const double *src, double *dst, uint32_t N, Clock *tick, int64_t tick_by,
                             hipStream_t st);

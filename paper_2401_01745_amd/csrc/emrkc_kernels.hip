@@ -105,6 +105,14 @@ __global__ __launch_bounds__(kBlock) void k_init_state(uint32_t N, double *V, vo
   for (int s = 0; s < NS; ++s) z[(size_t)(NG + s) * N + i] = R(Mod::slow_rest(s));
 }
 
+// First inner stage u_1 = u_0 + mu'_1 eta (f_F(u_0) + S_V) with one fused
+// multiply-add, the same in every kernel that forms it (the head, or the
+// two-stage inner kernel of the split stage), so that they round alike.
+__device__ __forceinline__ double first_inner(double mu1_eta, double u0, double Fu0, double sv) {
+#pragma clang fp contract(off)
+  return __builtin_fma(mu1_eta, Fu0 + sv, u0);
+}
+
 // ---------------------------------------------------------------------------
 // Outer-stage head at one node, given V_{j-1} and f_F(V_{j-1}) there
 // ---------------------------------------------------------------------------
@@ -123,21 +131,22 @@ struct HeadZ {
   }
 };
 
-template <template <class> class Model, bool MIXED, class FVf>
+template <template <class> class Model, bool MIXED, bool SV_ONLY = false, class FVf>
 __device__ __forceinline__ void head_node_z(const HeadArgs &a, uint32_t N, uint32_t i, double V,
                                             const typename MathOf<MIXED>::R *z, double Is, FVf FVfun);
 
-template <template <class> class Model, bool MIXED, class FVf>
+template <template <class> class Model, bool MIXED, bool SV_ONLY = false, class FVf>
 __device__ __forceinline__ void head_node(const HeadArgs &a, uint32_t N, uint32_t i, double V, FVf FVfun) {
   HeadZ<Model, MIXED> hz;
   hz.load(a.zin, N, i);
   const double tj = stage_time(a.clock, a.step_off, a.dt, a.c_prev);
-  head_node_z<Model, MIXED>(a, N, i, V, hz.z, stimulus(a.stim, i, tj), FVfun);
+  head_node_z<Model, MIXED, SV_ONLY>(a, N, i, V, hz.z, stimulus(a.stim, i, tj), FVfun);
 }
 
 // The head at node i with z_{j-1} and the stimulus current I_stim(t_j) at
-// the node given.
-template <template <class> class Model, bool MIXED, class FVf>
+// the node given.  SV_ONLY: the pointwise head of the split stage (m >= 2),
+// which stores S_V and leaves the first inner stage to k_inner12_march.
+template <template <class> class Model, bool MIXED, bool SV_ONLY, class FVf>
 __device__ __forceinline__ void head_node_z(const HeadArgs &a, uint32_t N, uint32_t i, double V,
                                             const typename MathOf<MIXED>::R *z, double Is, FVf FVfun) {
   using M = MathOf<MIXED>;
@@ -194,9 +203,17 @@ __device__ __forceinline__ void head_node_z(const HeadArgs &a, uint32_t N, uint3
     zout[(size_t)k * N + i] = R(zj);
   }
 
-  // first inner stage u_1 = u_0 + mu'_1 eta (f_F(u_0) + S_V), u_0 = V
+  if (SV_ONLY) {
+    if (MIXED)
+      ((float *)a.SV)[i] = (float)SV;
+    else
+      ((double *)a.SV)[i] = SV;
+    return;
+  }
+  // first inner stage u_1 = u_0 + mu'_1 eta (f_F(u_0) + S_V), u_0 = V (in
+  // the mixed precision S_V is a float value, so it equals what is stored)
   const double FV = FVfun();
-  const double u1 = V + a.mu1_eta * (FV + SV);
+  const double u1 = first_inner(a.mu1_eta, V, FV, SV);
   if (a.m_is_one) {
     const double fbarV = (u1 - V) * a.inv_eta;
     a.uout[i] = a.j1 ? V + a.mu_dt * fbarV : a.nu * V + a.kappa * a.Vin2[i] + a.mu_dt * fbarV;
@@ -231,6 +248,18 @@ template <template <class> class Model>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(7))) void k_head_occ(HeadArgs a,
                                                                                                Mesh mesh) {
   head_flat<Model, true>(a, mesh);
+}
+
+// Pointwise head of the split stage (m >= 2): exponential Euler, ionic
+// model, outer z recurrence and S_V at each node, in index order with no
+// stencil (the first inner stage moves to k_inner12_march).  On the large
+// slab this keeps the head a pure stream of the ionic state: the 27 V
+// operands of the flat head cost it about a tenth of its time.
+template <template <class> class Model, bool MIXED>
+__global__ __launch_bounds__(kBlock) void k_head_pw(HeadArgs a, uint32_t N) {
+  const uint32_t i = node_index();
+  if (i >= N) return;
+  head_node<Model, MIXED, true>(a, N, i, a.Vin[i], []() { return 0.0; });
 }
 
 // ---------------------------------------------------------------------------
@@ -357,7 +386,12 @@ __global__ __launch_bounds__(kBlock) void k_inner(InnerArgs a, Mesh mesh) {
   if (a.tick != nullptr && blockIdx.x == 0 && threadIdx.x == 0) a.tick->step += a.tick_by;
   if (i >= N) return;
   const double Fu = apply_op<MIXED>(mesh, a.t.uprev, i);
-  const double uk = inner_value(a.t, Fu, load_sv(a.t.SV, MIXED, i), i);
+  const double sv = load_sv(a.t.SV, MIXED, i);
+  if (a.first) {
+    a.out[i] = first_inner(a.t.mu_eta, a.t.uprev[i], Fu, sv);
+    return;
+  }
+  const double uk = inner_value(a.t, Fu, sv, i);
   a.out[i] = a.last ? tail_from_um(a.t, uk, i) : uk;
 }
 
@@ -630,7 +664,7 @@ struct InnerPoint {
 template <bool MIXED>
 __device__ __forceinline__ InnerPoint load_point(const InnerArgs &a, uint32_t i) {
   InnerPoint p;
-  p.u2 = a.t.uprev2[i];
+  p.u2 = a.first ? 0.0 : a.t.uprev2[i];
   p.sv = load_sv(a.t.SV, MIXED, i);
   p.vp = 0.0;
   p.vp2 = 0.0;
@@ -641,8 +675,10 @@ __device__ __forceinline__ InnerPoint load_point(const InnerArgs &a, uint32_t i)
   return p;
 }
 
-// inner_value / tail_from_um with the operands given (same expressions)
+// inner_value / tail_from_um with the operands given (same expressions);
+// the first inner stage (a.first) is u_1 = u_0 + mu'_1 eta (f_F(u_0) + S_V)
 __device__ __forceinline__ double inner_point(const InnerArgs &a, double uc, double Fu, const InnerPoint &p) {
+  if (a.first) return first_inner(a.t.mu_eta, uc, Fu, p.sv);
   const double uk = inner_combine(a.t, uc, p.u2, Fu, p.sv);
   return a.last ? tail_combine(a.t, uk, p.vp, p.vp2) : uk;
 }
@@ -746,6 +782,177 @@ __global__ __launch_bounds__(kBlock) void k_inner_march(InnerArgs a, Grid g, uin
   }
 }
 
+// ---------------------------------------------------------------------------
+// First two inner stages of the split stage on 3-D grids, by z-marching
+// columns: u_1 = u_0 + mu'_1 eta (f_F(u_0) + S_V) with u_0 = V_{j-1}, then
+// u_2 = nu'_2 u_1 + kappa'_2 u_0 + mu'_2 eta (f_F(u_1) + S_V), and, when
+// m == 2, the outer V update.  A block owns an MX x MY column of zc planes
+// and keeps in LDS four planes of V_{j-1} with a two-node halo in x and y
+// and three planes of u_1 with a one-node halo; u_1 is formed on the halo
+// from the V planes.  V plane z+3 and the halo's S_V of plane z+2 are
+// loaded into registers while plane z is computed.  Positions beyond the
+// grid are reflected at both ends (mirror2; at most twice, for two-node
+// axes), so that u_1 on the halo equals u_1 at the reflected node: the
+// stencil's sums pair opposite neighbours, and exchanging the two members
+// of every pair leaves each sum's bits unchanged.
+// ---------------------------------------------------------------------------
+constexpr int VSX = MX + 4, VSY = MY + 4, VPL = VSX * VSY;
+constexpr int VSLOT = (VPL + kBlock - 1) / kBlock;
+
+__device__ __forceinline__ uint32_t mirror2(int c, uint32_t n) {
+  int r = c < 0 ? -c : c;
+  r = r > (int)n - 1 ? 2 * ((int)n - 1) - r : r;
+  r = r < 0 ? -r : r;
+  return (uint32_t)(r > (int)n - 1 ? (int)n - 1 : r);
+}
+
+template <bool MIXED>
+__global__ __launch_bounds__(kBlock) void k_inner12_march(Inner12Args a, Grid g, uint32_t ncx, uint32_t ncy) {
+  __shared__ double vring[4][VPL];  // slot of V plane p: (p + 8) % 4, p >= -2
+  __shared__ double uring[3][MPL];  // slot of u_1 plane p: (p + 6) % 3, p >= -1
+  if (a.tick != nullptr && blockIdx.x == 0 && threadIdx.x == 0) a.tick->step += a.tick_by;
+  const uint32_t b = xcd_block(blockIdx.x, gridDim.x);
+  const uint32_t bx = b % ncx, byz = b / ncx;
+  const uint32_t by = byz % ncy, bz = byz / ncy;
+  const int x0 = (int)(bx * MX), y0 = (int)(by * MY);
+  const int zb = (int)(bz * g.zc);
+  const int ze = min(zb + (int)g.zc, (int)g.n2);
+  const uint32_t plane = g.n0 * g.n1;
+  // this thread's V staging slots (two-node halo) and u_1 slots (one-node
+  // halo; global in-plane offset for S_V, V-ring index of the centre)
+  uint32_t voff[VSLOT];
+  bool vact[VSLOT];
+#pragma unroll
+  for (int k = 0; k < VSLOT; ++k) {
+    const int r = threadIdx.x + k * kBlock;
+    vact[k] = r < VPL;
+    const int hx = r % VSX, hy = r / VSX;
+    voff[k] = vact[k] ? mirror2(x0 + hx - 2, g.n0) + g.n0 * mirror2(y0 + hy - 2, g.n1) : 0u;
+  }
+  uint32_t uoff[MSLOT];
+  int uvc[MSLOT];
+  bool uact[MSLOT];
+#pragma unroll
+  for (int k = 0; k < MSLOT; ++k) {
+    const int r = threadIdx.x + k * kBlock;
+    uact[k] = r < MPL;
+    const int hx = r % MSX, hy = r / MSX;
+    uoff[k] = uact[k] ? mirror_any(x0 + hx - 1, g.n0) + g.n0 * mirror_any(y0 + hy - 1, g.n1) : 0u;
+    uvc[k] = (hy + 1) * VSX + (hx + 1);
+  }
+  const double *__restrict__ V = a.V;
+  auto vplane = [&](int z) { return (size_t)mirror2(z, g.n2) * plane; };
+  auto uplane = [&](int z) { return (size_t)mirror_any(z, g.n2) * plane; };
+  auto stage_v = [&](int z) {
+    double *dst = vring[(z + 8) % 4];
+    const size_t pz = vplane(z);
+#pragma unroll
+    for (int k = 0; k < VSLOT; ++k)
+      if (vact[k]) dst[threadIdx.x + k * kBlock] = V[pz + voff[k]];
+  };
+  auto load_svh = [&](int z, double *sv) {
+    const size_t pz = uplane(z);
+#pragma unroll
+    for (int k = 0; k < MSLOT; ++k) sv[k] = uact[k] ? load_sv(a.SV, MIXED, pz + uoff[k]) : 0.0;
+  };
+  // u_1 on the halo plane p from V planes p-1, p, p+1
+  auto form_u1 = [&](int p, const double *sv) {
+    const double *vm = vring[(p + 7) % 4], *vc = vring[(p + 8) % 4], *vp = vring[(p + 9) % 4];
+    double *dst = uring[(p + 6) % 3];
+#pragma unroll
+    for (int k = 0; k < MSLOT; ++k) {
+      if (!uact[k]) continue;
+      const int c = uvc[k];
+      const double Fv = grid_stencil<3>(g.w, [&](int dx, int dy, int dz) {
+        const double *pl = dz < 0 ? vm : (dz > 0 ? vp : vc);
+        return pl[c + dy * VSX + dx];
+      });
+      dst[threadIdx.x + k * kBlock] = first_inner(a.mu1_eta, vc[c], Fv, sv[k]);
+    }
+  };
+  double sv[MSLOT];
+  stage_v(zb - 2);
+  stage_v(zb - 1);
+  stage_v(zb);
+  stage_v(zb + 1);
+  load_svh(zb - 1, sv);
+  __syncthreads();
+  form_u1(zb - 1, sv);
+  load_svh(zb, sv);
+  form_u1(zb, sv);
+  // operands of the first iteration
+  double vpre[VSLOT];
+  {
+    const size_t pz = vplane(zb + 2);
+#pragma unroll
+    for (int k = 0; k < VSLOT; ++k) vpre[k] = vact[k] ? V[pz + voff[k]] : 0.0;
+  }
+  load_svh(zb + 1, sv);
+  const int lx = threadIdx.x % MX, ly = threadIdx.x / MX;
+  const uint32_t gx = (uint32_t)(x0 + lx), gy = (uint32_t)(y0 + ly);
+  const bool own = gx < g.n0 && gy < g.n1;
+  const int c = (ly + 1) * MSX + (lx + 1);
+  const int cv = (ly + 2) * VSX + (lx + 2);
+  uint32_t i = gx + g.n0 * gy + plane * (uint32_t)zb;
+  double sv_own = 0.0, v2_own = 0.0;
+  if (own) {
+    sv_own = load_sv(a.SV, MIXED, i);
+    if (a.last && !a.t.j1) v2_own = a.Vin2[i];
+  }
+  __syncthreads();  // the pre-loop's u_1 planes read V plane zb - 2, whose slot is refilled next
+  for (int z = zb; z < ze; ++z, i += plane) {
+    {
+      double *dst = vring[(z + 10) % 4];
+#pragma unroll
+      for (int k = 0; k < VSLOT; ++k)
+        if (vact[k]) dst[threadIdx.x + k * kBlock] = vpre[k];
+    }
+    double svh[MSLOT];
+#pragma unroll
+    for (int k = 0; k < MSLOT; ++k) svh[k] = sv[k];
+    const double sv_cur = sv_own, v2_cur = v2_own;
+    if (z + 1 < ze) {
+      const size_t pz = vplane(z + 3);
+#pragma unroll
+      for (int k = 0; k < VSLOT; ++k) vpre[k] = vact[k] ? V[pz + voff[k]] : 0.0;
+      load_svh(z + 2, sv);
+      if (own) {
+        sv_own = load_sv(a.SV, MIXED, i + plane);
+        if (a.last && !a.t.j1) v2_own = a.Vin2[i + plane];
+      }
+    }
+    __syncthreads();
+    form_u1(z + 1, svh);
+    __syncthreads();
+    if (own) {
+      const double *um = uring[(z + 5) % 3], *uc = uring[(z + 6) % 3], *up = uring[(z + 7) % 3];
+      const double Fu = grid_stencil<3>(g.w, [&](int dx, int dy, int dz) {
+        const double *pl = dz < 0 ? um : (dz > 0 ? up : uc);
+        return pl[c + dy * MSX + dx];
+      });
+      const double u0 = vring[(z + 8) % 4][cv];
+      const double u1 = uc[c];
+      const double u2 = inner_combine(a.t, u1, u0, Fu, sv_cur);
+      if (a.last) {
+        a.out[i] = tail_combine(a.t, u2, u0, v2_cur);
+      } else {
+        a.u1out[i] = u1;
+        a.out[i] = u2;
+      }
+    }
+  }
+}
+
+typedef __attribute__((address_space(3))) void lds_void_t;
+typedef __attribute__((address_space(1))) void glb_void_t;
+
+// `lds` is an LDS byte address (an offset into the workgroup's LDS, which
+// may be 0); it is converted to an LDS pointer directly, never through a
+// generic pointer, whose null value would map to the LDS null (-1).
+__device__ __forceinline__ void lds_dma_dword(const void *src, uint32_t lds) {
+  __builtin_amdgcn_global_load_lds((glb_void_t *)src, (lds_void_t *)(uintptr_t)lds, 4, 0, 0);
+}
+
 // Head on 3-D grids by z-marching columns: the MX x MY column layout and
 // LDS ring of V_{j-1} of k_inner_march, with the ionic state z_{j-1} of the
 // next plane loaded into registers while the current plane is computed, so
@@ -825,15 +1032,6 @@ __global__ __launch_bounds__(kBlock) void k_head_march(HeadArgs a, Grid g, uint3
 // flight), and reads the current plane's slice into registers first.  Only
 // the wave that loads a slice reads it, so the slices need no barrier; the
 // V ring is shared as in k_inner_march.
-typedef __attribute__((address_space(3))) void lds_void_t;
-typedef __attribute__((address_space(1))) void glb_void_t;
-
-// `lds` is an LDS byte address (an offset into the workgroup's LDS, which
-// may be 0); it is converted to an LDS pointer directly, never through a
-// generic pointer, whose null value would map to the LDS null (-1).
-__device__ __forceinline__ void lds_dma_dword(const void *src, uint32_t lds) {
-  __builtin_amdgcn_global_load_lds((glb_void_t *)src, (lds_void_t *)(uintptr_t)lds, 4, 0, 0);
-}
 // Waits (and orders the compiler's memory accesses) for this wave's
 // outstanding vector-memory loads, including the LDS copies, or for its LDS
 // reads.
@@ -1766,6 +1964,38 @@ hipError_t launch_inner(bool mixed, const Mesh &mesh, const InnerArgs &a, hipStr
 }
 
 bool fused_supported(const Mesh &mesh) { return mesh.kind == kGrid && !mesh.flat; }
+
+bool split_supported(const Mesh &mesh) { return mesh.kind == kGrid && !mesh.flat && mesh.grid.dim == 3; }
+
+template <template <class> class Model>
+static hipError_t head_pw_dispatch(bool mixed, uint32_t N, const HeadArgs &a, hipStream_t st) {
+  if (mixed)
+    EMRKC_LAUNCH((k_head_pw<Model, true>), dim3(blocks_for(N)), dim3(kBlock), 0, st, a, N);
+  else
+    EMRKC_LAUNCH((k_head_pw<Model, false>), dim3(blocks_for(N)), dim3(kBlock), 0, st, a, N);
+  return hipGetLastError();
+}
+
+hipError_t launch_head_pw(int model, bool mixed, const Mesh &mesh, const HeadArgs &a, hipStream_t st) {
+  if (!split_supported(mesh)) return hipErrorInvalidValue;
+#define CALL(M) head_pw_dispatch<M>(mixed, mesh.grid.N, a, st)
+  EMRKC_MODEL_SWITCH(model, CALL)
+#undef CALL
+}
+
+hipError_t launch_inner12(bool mixed, const Mesh &mesh, const Inner12Args &a, hipStream_t st) {
+  if (!split_supported(mesh)) return hipErrorInvalidValue;
+  // columns of head_zc planes (the split head shape's plane count)
+  Grid g = mesh.grid;
+  g.zc = g.head_zc;
+  const uint32_t ncx = (g.n0 + MX - 1) / MX, ncy = (g.n1 + MY - 1) / MY, ncz = (g.n2 + g.zc - 1) / g.zc;
+  if (mixed) {
+    EMRKC_LAUNCH((k_inner12_march<true>), dim3(ncx * ncy * ncz), dim3(kBlock), 0, st, a, g, ncx, ncy);
+  } else {
+    EMRKC_LAUNCH((k_inner12_march<false>), dim3(ncx * ncy * ncz), dim3(kBlock), 0, st, a, g, ncx, ncy);
+  }
+  return hipGetLastError();
+}
 
 uint32_t grid_tiles(const Grid &g, uint32_t &ntx, uint32_t &nty, int shape) {
   if (g.dim == 3)

@@ -146,10 +146,17 @@ def test_2d_wave_fp64(E):
 def test_stage_plans(E, rho, dt, sm):
     """Outer stages s >= 2 and single inner stages m = 1 (buffer rotation
     and the final copy) against the oracle.  Radii are over-estimates of the
-    true ones (rho_F = 48.6, rho_S = 4.2), which keeps every case stable."""
+    true ones (rho_F = 48.6, rho_S = 4.2), which keeps every case stable.
+    Plans with m >= 2 also run the split stage (pointwise head, two-stage
+    inner kernel; its own buffer rule for s >= 2): the same bits."""
     cfg = small_config("c2_3d_crn", (23, 17, 7), dt=dt)
-    _, _, _, stats = _compare_full(cfg, 60, rho)
+    _, _, V, stats = _compare_full(cfg, 60, rho)
     assert (stats.s, stats.m) == sm
+    if sm[1] >= 2:
+        for v in [(7, 3, 1, 4, 0), (8, 0, 1, 4, 0)]:
+            V7, _, st7 = gpu_run(cfg, 60, rho, variants=v)
+            assert (st7.s, st7.m) == sm
+            assert np.array_equal(V7, V), v
 
 
 @pytest.mark.parametrize("rho,dt,sm", [((51.0, 100.0), 0.05, (2, 1)), ((2000.0, 300.0), 0.05, (3, 3)),
@@ -221,7 +228,12 @@ def test_graph_eager_fused_split_and_repeat_are_bitwise_identical(E, n, rho, pre
         # ragged columns and plane counts that do not divide n[2]
         for v in [(1, 4, 1, 4, 0), (2, 4, 1, 4, 0), (2, 2, 1, 3, 0), (1, n[2], 1, n[2], 0), (2, 5, 0, 0, 0),
                   (0, 0, 1, 2, 0), (2, 3, 1, 4, 1), (3, 0, 1, 4, 0), (4, 0, 0, 0, 1), (5, 0, 1, 4, 0),
-                  (5, 0, 0, 0, 1), (5, 0, 1, 3, 0), (0, 0, 0, 0, 0)]:
+                  (5, 0, 0, 0, 1), (5, 0, 1, 3, 0), (0, 0, 0, 0, 0),
+                  # the split stage: pointwise head with the two-stage inner
+                  # kernel in ragged columns of 4, 2, 3 and all planes (7),
+                  # or with u_1 as a launch of the inner kernel (8)
+                  (7, 4, 1, 4, 0), (7, 2, 0, 0, 0), (7, 3, 1, 2, 0), (7, n[2], 1, 3, 0),
+                  (8, 0, 1, 4, 0), (8, 0, 0, 0, 0), (8, 0, 1, 2, 0)]:
             runs.append(gpu_run(cfg, 80, rho, precision=precision, variants=v)[:2])
         if precision == "mixed":  # the 7-wave flat head exists in the mixed precision only
             for v in [(6, 0, 1, 3, 0), (6, 0, 0, 0, 0), (6, 0, 0, 0, 1)]:
@@ -229,6 +241,10 @@ def test_graph_eager_fused_split_and_repeat_are_bitwise_identical(E, n, rho, pre
     assert st1.used_graph == 1 and st2.used_graph == 0
     assert st1.kernels_per_step == st1.m and st5.kernels_per_step == st5.m - 1
     assert st8.kernels_per_step == st8.m
+    if len(n) == 3:  # the split stage with an odd call split (ping-pong and the final copy)
+        V9, z9, st9 = gpu_run(cfg, 80, rho, precision=precision, chunks=[1, 33, 7, 39], variants=(7, 3, 1, 4, 0))
+        assert st9.kernels_per_step == st9.m
+        assert np.array_equal(V9, V1) and np.array_equal(z9, z1)
     for V, z in runs:
         assert np.array_equal(V, V1) and np.array_equal(z, z1)
 
@@ -343,7 +359,7 @@ def test_minimal_grids(E, n, rho):
     assert np.abs(z - Y[1:]).max() <= 1e-10 * np.abs(Y[1:]).max()
     if len(n) == 3:
         for v in [(1, 1, 1, 1, 0), (2, n[2], 1, n[2], 0), (2, 1, 0, 0, 1), (3, 0, 1, 2, 0), (0, 0, 0, 0, 0),
-                  (5, 0, 1, 1, 0), (5, 0, 0, 0, 0)]:
+                  (5, 0, 1, 1, 0), (5, 0, 0, 0, 0), (7, 1, 0, 0, 0), (7, n[2], 1, 1, 0), (8, 0, 0, 0, 0)]:
             V2, z2, _ = gpu_run(cfg, nsteps, rho, variants=v)
             assert np.array_equal(V2, V) and np.array_equal(z2, z), v
 
