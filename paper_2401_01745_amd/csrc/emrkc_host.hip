@@ -8,6 +8,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <array>
 #include <functional>
 #include <map>
 #include <mutex>
@@ -977,6 +978,124 @@ static int enqueue_chunk_split_s1m2(emrkc_ctx *c, const emrkc_state *st, const S
   return EMRKC_OK;
 }
 
+// All inner stages of a stage in one launch (2-D grids, inner shape 2,
+// 2 <= m <= kInnerAllMaxM): the head as usual (u_1 into U[0]), then
+// k_inner_all2d, which reads V_{j-1} with a halo and so writes V_j to the
+// other buffer: s == 1 alternates X[n % 2] over a chunk (an odd chunk ends
+// with one copy), s >= 2 rotates as the generic step with the final copy
+// of the m == 1 rule.
+static bool inner_all_mode(const emrkc_ctx *c, const StepPlan &P) {
+  return c->method == EMRKC_METHOD_EMRKC && !c->batch && inner_all_supported(c->mesh, P.m) &&
+         c->mesh.grid.inner_variant >= 2 && c->mesh.grid.inner_variant <= 4;
+}
+
+// Inner shape 4 with s == 1: one kernel per step (the inner stages of step
+// n and the head of step n + 1), after a head for the chunk's first step
+// and before a last inner-stage kernel; u_1, S_V and V alternate buffers.
+static bool step2d_mode(const emrkc_ctx *c, const StepPlan &P) {
+  return inner_all_mode(c, P) && c->mesh.grid.inner_variant == 4 && P.s == 1;
+}
+
+static InnerAllArgs make_inner_all(emrkc_ctx *c, const StepPlan &P, double dt, int j) {
+  InnerAllArgs a{};
+  a.t = make_stage(P, dt, j, P.m);
+  for (int k = 2; k <= P.m; ++k) {
+    a.nu[k] = P.nui[k];
+    a.kappa[k] = P.kai[k];
+    a.mu_eta[k] = P.mui[k] * P.eta;
+  }
+  a.m = P.m;
+  a.u1 = c->d_U[0];
+  a.SV = c->d_SV;
+  return a;
+}
+
+static int enqueue_chunk_inner_all(emrkc_ctx *c, const emrkc_state *st, const StepPlan &P, double dt, int L,
+                                   hipStream_t strm, KernelTimer *tm) {
+  const int s = P.s;
+  double *X[2] = {(double *)st->V, c->d_V1};
+  void *Z[2] = {st->z, c->d_z1};
+  if (step2d_mode(c, P)) {
+    double *Ub[2] = {c->d_U[0], c->d_U[1]};
+    void *S[2] = {c->d_SV, c->d_SV2};
+    if (!Ub[0] || !Ub[1] || !S[0] || !S[1])
+      return fail(c, EMRKC_EINVAL, "one-kernel 2-D step: a u_1 or S_V work buffer is missing");
+    HeadArgs h = make_head(c, P, dt, 1, 0);
+    h.Vin = X[0];
+    h.zin = h.zout = st->z;
+    h.SV = S[0];
+    h.uout = Ub[0];
+    TIMED(0, launch_head(c->model, c->mixed, c->mesh, h, strm));
+    for (int n = 0; n + 1 < L; ++n) {
+      InnerAllArgs a = make_inner_all(c, P, dt, 1);
+      a.u1 = Ub[n % 2];
+      a.V = X[n % 2];
+      a.SV = S[n % 2];
+      a.out = X[(n + 1) % 2];
+      HeadArgs hn = make_head(c, P, dt, 1, n + 1);
+      hn.zin = hn.zout = st->z;
+      hn.SV = S[(n + 1) % 2];
+      hn.uout = Ub[(n + 1) % 2];
+      TIMED(2, launch_step2d(c->model, c->mixed, c->mesh, a, hn, strm));
+    }
+    InnerAllArgs a = make_inner_all(c, P, dt, 1);
+    a.u1 = Ub[(L - 1) % 2];
+    a.V = X[(L - 1) % 2];
+    a.SV = S[(L - 1) % 2];
+    a.out = X[L % 2];
+    a.tick = L % 2 == 0 ? c->d_clock : nullptr;
+    a.tick_by = L;
+    TIMED(1, launch_inner_all(c->mixed, c->mesh, a, strm));
+    if (L % 2) HIP_TRY(c, launch_copy_tick(X[1], X[0], (uint32_t)c->N, c->d_clock, L, strm));
+    return EMRKC_OK;
+  }
+  if (s == 1) {
+    for (int n = 0; n < L; ++n) {
+      HeadArgs h = make_head(c, P, dt, 1, n);
+      h.Vin = X[n % 2];
+      h.zin = h.zout = st->z;
+      h.uout = c->d_U[0];
+      TIMED(0, launch_head(c->model, c->mixed, c->mesh, h, strm));
+      InnerAllArgs a = make_inner_all(c, P, dt, 1);
+      a.V = X[n % 2];
+      a.out = X[(n + 1) % 2];
+      a.tick = (n == L - 1 && L % 2 == 0) ? c->d_clock : nullptr;
+      a.tick_by = L;
+      TIMED(1, launch_inner_all(c->mixed, c->mesh, a, strm));
+    }
+    if (L % 2) HIP_TRY(c, launch_copy_tick(X[1], X[0], (uint32_t)c->N, c->d_clock, L, strm));
+    return EMRKC_OK;
+  }
+  auto vidx = [&](int j) { return j == 0 ? 0 : (j < s ? j % 2 : 0); };
+  const bool final_copy = vidx(s - 1) == 0;
+  for (int n = 0; n < L; ++n) {
+    for (int j = 1; j <= s; ++j) {
+      const bool lastj = j == s;
+      double *Vin = X[vidx(j - 1)];
+      double *Vin2 = j >= 2 ? X[vidx(j - 2)] : nullptr;
+      double *Vdst = (lastj && final_copy) ? X[1] : X[vidx(j)];
+      HeadArgs h = make_head(c, P, dt, j, n);
+      h.Vin = Vin;
+      h.Vin2 = Vin2;
+      h.zin = Z[vidx(j - 1)];
+      h.zin2 = j >= 2 ? Z[vidx(j - 2)] : nullptr;
+      h.zout = Z[vidx(j)];
+      h.uout = c->d_U[0];
+      TIMED(0, launch_head(c->model, c->mixed, c->mesh, h, strm));
+      InnerAllArgs a = make_inner_all(c, P, dt, j);
+      a.V = Vin;
+      a.Vin2 = Vin2;
+      a.out = Vdst;
+      a.tick = (lastj && n == L - 1 && !final_copy) ? c->d_clock : nullptr;
+      a.tick_by = L;
+      TIMED(1, launch_inner_all(c->mixed, c->mesh, a, strm));
+    }
+    if (final_copy)
+      HIP_TRY(c, launch_copy_tick(X[1], X[0], (uint32_t)c->N, n == L - 1 ? c->d_clock : nullptr, L, strm));
+  }
+  return EMRKC_OK;
+}
+
 // L steps with s == 1 and m >= 2 on a grid: head of step 0, then for each
 // later step one fused kernel (last inner stage of the previous step + head
 // of this step), and the last inner stage of step L-1 on its own.  Within
@@ -991,6 +1110,8 @@ static int enqueue_chunk_fused(emrkc_ctx *c, const emrkc_state *st, const StepPl
   double *X[2] = {(double *)st->V, c->d_V1};
   double *B[3] = {c->d_U[0], c->d_U[1], c->d_U[2]};
   void *S[2] = {c->d_SV, c->d_SV2};
+  if (!B[0] || !B[1] || !B[2] || !S[0] || !S[1])
+    return fail(c, EMRKC_EINVAL, "fused chunk: an inner or S_V work buffer is missing");
   int base = 0;
   auto inner_range = [&](int n, int b) -> int {
     for (int k = 2; k <= m - 1; ++k) {
@@ -1130,6 +1251,7 @@ static int enqueue_chunk(emrkc_ctx *c, const emrkc_state *st, const StepPlan &P,
     }
     return EMRKC_OK;
   }
+  if (inner_all_mode(c, P)) return enqueue_chunk_inner_all(c, st, P, dt, L, strm, tm);
   if (split_mode(c, P)) {
     if (P.s == 1 && P.m == 2) return enqueue_chunk_split_s1m2(c, st, P, dt, L, strm, tm);
     for (int n = 0; n < L; ++n) {
@@ -1296,6 +1418,8 @@ static void set_last_stats(emrkc_ctx *c, const StepPlan &P, bool used_graph) {
   c->last.kernels_per_step = c->batch ? (int64_t)P.m
                               : split_mode(c, P) ? split
                               : u1_split_mode(c, P) ? (int64_t)P.s * (P.m + 1)
+                              : step2d_mode(c, P) ? 1
+                              : inner_all_mode(c, P) ? (int64_t)2 * P.s + (P.s > 1 && P.s % 2 == 1 ? 1 : 0)
                               : (c->use_fused && P.s == 1 && P.m >= 2 && fused_supported(c->mesh))
                                  ? (int64_t)P.m - 1
                                  : (P.s == 1 && P.m == 1) ? 1 : (int64_t)P.s * P.m + (P.m == 1 ? 1 : 0);
@@ -1428,7 +1552,8 @@ extern "C" int emrkc_step_noalloc(emrkc_ctx *c, emrkc_state *st, double dt, int6
   int rc = make_plan_fixed(c, dt);
   if (rc != EMRKC_OK) return rc;
   const StepPlan &P = c->fixed_plan;
-  const bool fused = c->use_fused && P.s == 1 && P.m >= 2 && fused_supported(c->mesh);
+  // (the one-kernel 2-D step alternates S_V buffers as the fused chunk does)
+  const bool fused = (c->use_fused && P.s == 1 && P.m >= 2 && fused_supported(c->mesh)) || step2d_mode(c, P);
   const ScratchLayout L = scratch_layout(c, P.s, fused);
   if (L.total > kScratchBytes)
     return fail(c, EMRKC_EINVAL,
@@ -1773,6 +1898,9 @@ static int copy_state(emrkc_ctx *c, const emrkc_state *src, StateCopy &cp) {
 static bool tunable(const emrkc_ctx *c) {  // the 3-D shapes (emRKC)
   return !c->batch && c->mesh.kind == kGrid && c->dim == 3 && !c->flat && c->method == EMRKC_METHOD_EMRKC;
 }
+static bool planar(const emrkc_ctx *c) {  // 2-D grids: inner shape 0 (tiles) or 2 (all stages in one launch)
+  return !c->batch && c->mesh.kind == kGrid && c->dim == 2 && !c->flat && c->method == EMRKC_METHOD_EMRKC;
+}
 static bool fusable(const emrkc_ctx *c) {  // the fused kernel (emRKC, used when s == 1 and m >= 2)
   return !c->batch && !c->flat && fused_supported(c->mesh) && c->method == EMRKC_METHOD_EMRKC;
 }
@@ -1788,7 +1916,7 @@ static void get_variants(const emrkc_ctx *c, int *v) {
   const bool t = tunable(c);
   v[0] = t ? g.head_variant : 0;
   v[1] = t && (g.head_variant == 1 || g.head_variant == 2 || g.head_variant == 7) ? (int)g.head_zc : 0;
-  v[2] = t ? g.inner_variant : 0;
+  v[2] = t || planar(c) ? g.inner_variant : 0;
   v[3] = t && g.inner_variant ? (int)g.zc : 0;
   v[4] = c->use_fused ? 1 : 0;
 }
@@ -1799,6 +1927,10 @@ static int check_variants(const emrkc_ctx *c, const int *v) {
     return (v[2] | v[3] | v[4]) == 0 ? EMRKC_OK : EMRKC_EUNSUPPORTED;
   }
   if (v[4] < 0 || v[4] > 1 || (v[4] == 1 && !fusable(c))) return EMRKC_EUNSUPPORTED;
+  if (planar(c)) {
+    if ((v[0] | v[1] | v[3]) != 0 || (v[2] != 0 && (v[2] < 2 || v[2] > 4))) return EMRKC_EUNSUPPORTED;
+    return v[2] != 0 && v[4] != 0 ? EMRKC_EINVAL : EMRKC_OK;  // one or the other
+  }
   if (!tunable(c)) return (v[0] | v[1] | v[2] | v[3]) == 0 ? EMRKC_OK : EMRKC_EUNSUPPORTED;
   const int n2 = (int)c->mesh.grid.n2;
   if (v[0] < 0 || v[0] > 8 || v[2] < 0 || v[2] > 1) return EMRKC_EINVAL;
@@ -1821,6 +1953,7 @@ static void set_variants(emrkc_ctx *c, const int *v) {
     clear_graphs(c);
     return;
   }
+  if (planar(c)) c->mesh.grid.inner_variant = v[2];
   if (tunable(c)) {
     Grid &g = c->mesh.grid;
     g.head_variant = v[0];
@@ -1925,6 +2058,69 @@ static int autotune_batch(emrkc_ctx *c, const emrkc_state *st, double dt, int re
   return rc;
 }
 
+// Wall time per step of `reps` eagerly launched steps on state st
+// (advanced), launch gaps included: what decides on small, launch-bound
+// grids.
+static int time_steps(emrkc_ctx *c, emrkc_state *st, const StepPlan &P, double dt, int reps, double *ms) {
+  HIP_TRY(c, launch_clock_set(c->d_clock, st->step, st->t0, c->stream));
+  int rc = enqueue_chunk(c, st, P, dt, 2, c->stream, nullptr);  // untimed: first launches
+  if (rc != EMRKC_OK) return rc;
+  hipEvent_t e0, e1;
+  HIP_TRY(c, hipEventCreate(&e0));
+  if (hipEventCreate(&e1) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return fail(c, EMRKC_EHIP, "hipEventCreate failed");
+  }
+  hipError_t e = hipEventRecord(e0, c->stream);
+  if (e == hipSuccess) {
+    rc = enqueue_chunk(c, st, P, dt, reps, c->stream, nullptr);
+    e = hipEventRecord(e1, c->stream);
+  }
+  if (e == hipSuccess) e = hipEventSynchronize(e1);
+  float t = 0;
+  if (e == hipSuccess && rc == EMRKC_OK) e = hipEventElapsedTime(&t, e0, e1);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (e != hipSuccess) return fail(c, EMRKC_EHIP, "autotuning steps failed: %s", hipGetErrorString(e));
+  if (rc != EMRKC_OK) return rc;
+  *ms = t / reps;
+  return EMRKC_OK;
+}
+
+// 2-D grids: separate inner-stage launches (the default), the fused kernel
+// (s == 1) and all inner stages in one launch, compared by the wall time of
+// a run of steps; a later candidate must be 3% faster to replace the choice.
+static int autotune_planar(emrkc_ctx *c, const emrkc_state *st, double dt, int reps, const StepPlan &P,
+                           int *variants) {
+  int orig[5];
+  get_variants(c, orig);
+  StateCopy cp;
+  int rc = copy_state(c, st, cp);
+  if (rc != EMRKC_OK) return rc;
+  const bool verbose = getenv("EMRKC_VERBOSE") != nullptr;
+  std::vector<std::array<int, 5>> cands{{0, 0, 0, 0, 0}, {0, 0, 2, 0, 0}, {0, 0, 3, 0, 0}};
+  if (P.s == 1) cands.push_back({0, 0, 4, 0, 0});
+  if (fusable(c) && P.s == 1) cands.push_back({0, 0, 0, 0, 1});
+  double best = 1e300;
+  std::array<int, 5> choice = cands[0];
+  for (const auto &v : cands) {
+    set_variants(c, v.data());
+    double ms = 0;
+    if ((rc = time_steps(c, &cp.st, P, dt, reps, &ms)) != EMRKC_OK) break;
+    if (verbose)
+      fprintf(stderr, "emrkc_autotune: 2-D shapes (%d,%d,%d,%d,%d): %.5f ms per step\n", v[0], v[1], v[2], v[3], v[4],
+              ms);
+    if (ms < 0.97 * best) {
+      best = ms;
+      choice = v;
+    }
+  }
+  (void)hipStreamSynchronize(c->stream);
+  set_variants(c, rc == EMRKC_OK ? choice.data() : orig);
+  if (rc == EMRKC_OK && variants) get_variants(c, variants);
+  return rc;
+}
+
 extern "C" int emrkc_autotune(emrkc_ctx *c, const emrkc_state *st, double dt, int reps, int *variants) {
   if (c == nullptr) return EMRKC_EINVAL;
   if (!state_ok(c, st)) return fail(c, EMRKC_EINVAL, "state buffers missing");
@@ -1934,6 +2130,7 @@ extern "C" int emrkc_autotune(emrkc_ctx *c, const emrkc_state *st, double dt, in
   int rc = make_plan(c, dt, P);
   if (rc != EMRKC_OK) return rc;
   if (c->batch) return autotune_batch(c, st, dt, reps, P, variants);
+  if (planar(c) && inner_all_supported(c->mesh, P.m)) return autotune_planar(c, st, dt, reps, P, variants);
   const bool fuse_ok = fusable(c) && P.s == 1 && P.m >= 2;
   if (!tunable(c) && !fuse_ok) return emrkc_get_variants(c, variants);
   // shape candidates (3-D grids): 3-D tiles, and z-marching columns of zc

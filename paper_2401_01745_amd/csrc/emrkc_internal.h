@@ -88,6 +88,23 @@ struct InnerArgs {
   int64_t tick_by;
 };
 
+// Every inner stage k = 2..m of one outer stage in one launch (2-D grids,
+// 2 <= m <= kInnerAllMaxM): each block owns a 16 x 16 tile and recomputes
+// u_k on the tile plus a halo of m - k nodes from u_1 on a halo of m - 1.
+constexpr int kInnerAllMaxM = 9;
+struct InnerAllArgs {
+  TailArgs t;            // outer coefficients of stage j (inv_eta, mu_dt, nu_o, kappa_o, j1)
+  const double *u1;      // u_1 (read on the tile and an m - 1 halo)
+  const double *V;       // u_0 = V_{j-1} (read on an m - 2 halo)
+  const double *Vin2;    // V_{j-2} (j >= 2)
+  const void *SV;
+  double *out;           // V_j
+  double nu[kInnerAllMaxM + 1], kappa[kInnerAllMaxM + 1], mu_eta[kInnerAllMaxM + 1];  // inner stage k
+  int m;
+  Clock *tick;           // when non-null, block 0 adds tick_by to the chunk base step
+  int64_t tick_by;
+};
+
 // First two inner stages of the split stage (3-D grids, m >= 2): u_1 from
 // V_{j-1} and S_V, u_2 from u_1, and for m == 2 the outer V update.
 struct Inner12Args {
@@ -243,6 +260,13 @@ bool fused_supported(const Mesh &mesh);
 // The split stage: the pointwise head k_head_pw (z and S_V only) and the
 // two-stage inner kernel k_inner12_march; 3-D grids, not under mesh.flat.
 bool split_supported(const Mesh &mesh);
+// 2-D grids (not mesh.flat): all inner stages of a stage in one launch
+bool inner_all_supported(const Mesh &mesh, int m);
+hipError_t launch_inner_all(bool mixed, const Mesh &mesh, const InnerAllArgs &a, hipStream_t st);
+// The inner stages of step n (s == 1, 8 x 8 tiles) and the head of step
+// n + 1 in one kernel (2-D grids, inner shape 4)
+hipError_t launch_step2d(int model, bool mixed, const Mesh &mesh, const InnerAllArgs &a, const HeadArgs &h,
+                         hipStream_t st);
 hipError_t launch_head_pw(int model, bool mixed, const Mesh &mesh, const HeadArgs &a, hipStream_t st);
 hipError_t launch_inner12(bool mixed, const Mesh &mesh, const Inner12Args &a, hipStream_t st);
 hipError_t launch_clock_set(Clock *c, int64_t step, double t0, hipStream_t st);

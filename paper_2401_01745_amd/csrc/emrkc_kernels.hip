@@ -953,6 +953,139 @@ __device__ __forceinline__ void lds_dma_dword(const void *src, uint32_t lds) {
   __builtin_amdgcn_global_load_lds((glb_void_t *)src, (lds_void_t *)(uintptr_t)lds, 4, 0, 0);
 }
 
+// ---------------------------------------------------------------------------
+// All inner stages of an outer stage in one launch on 2-D grids (the small,
+// launch-bound unit-square case): a block owns a 16 x 16 (inner shape 2) or
+// 8 x 8 (inner shape 3, four times the blocks) tile and holds u_1
+// on the tile plus a halo of m - 1 nodes, and V_{j-1} and S_V on a halo of
+// m - 2, in LDS; stage k forms u_k on a halo of m - k from u_{k-1} and
+// u_{k-2}, and the last one the outer V update on the tile.  The halo work
+// is repeated by neighbouring blocks instead of exchanged, so one launch and
+// m - 1 block barriers replace m - 1 launches.  Positions beyond the grid
+// are reflected at its edges (repeatedly for narrow grids); a value there
+// equals the value at the reflected node, since the stencil's sums pair
+// opposite neighbours.  V_j goes to another buffer than V_{j-1}, which
+// neighbouring blocks still read.
+// ---------------------------------------------------------------------------
+constexpr int kAllR = 16 + 2 * (kInnerAllMaxM - 1);       // LDS frame edge (32) for tiles up to 16 x 16
+
+__device__ __forceinline__ uint32_t reflect(int c, uint32_t n) {
+  const int p = 2 * ((int)n - 1);  // period of the reflected sequence (n >= 2)
+  int r = c % p;
+  r = r < 0 ? r + p : r;
+  return (uint32_t)(r > (int)n - 1 ? p - r : r);
+}
+
+// The inner stages k = 2..m of one tile: u_1 is read on a halo of
+// m - 1 + e nodes, V_{j-1} and S_V on m - 2 + e, and the last stage gives
+// V_j on a halo of e (0, or 1 when the next step's head follows in the same
+// kernel): the tile's nodes to a.out and, when vn is given, every position
+// of the halo to vn (frame layout).  U holds three frames.
+template <bool MIXED, int kAllT>
+__device__ __forceinline__ void inner_all_tile(const InnerAllArgs &a, const Grid &g, int x0, int y0, int e,
+                                               double (*U)[kAllR * kAllR], double *sV, double *sS, double *vn) {
+  const int m = a.m, rmax = m - 1 + e;
+  const int F = kAllT + 2 * rmax;  // frame edge used; frame (0, 0) is node (x0 - rmax, y0 - rmax)
+  // u_1 on the whole frame, V and S_V on the frame less one ring; all of a
+  // thread's loads are issued before the first is stored (one latency)
+  constexpr int kPass = (kAllR * kAllR + kBlock - 1) / kBlock;
+  double lu[kPass], lv[kPass], ls[kPass];
+#pragma unroll
+  for (int k = 0; k < kPass; ++k) {
+    const int p = threadIdx.x + k * kBlock;
+    lu[k] = lv[k] = ls[k] = 0.0;
+    if (p < F * F) {
+      const int fx = p % F, fy = p / F;
+      const uint32_t i = reflect(x0 + fx - rmax, g.n0) + g.n0 * reflect(y0 + fy - rmax, g.n1);
+      lu[k] = a.u1[i];
+      if (fx >= 1 && fx < F - 1 && fy >= 1 && fy < F - 1) {
+        lv[k] = a.V[i];
+        ls[k] = load_sv(a.SV, MIXED, i);
+      }
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < kPass; ++k) {
+    const int p = threadIdx.x + k * kBlock;
+    if (p < F * F) {
+      const int q = (p / F) * kAllR + p % F;
+      U[1][q] = lu[k];
+      sV[q] = lv[k];
+      sS[q] = ls[k];
+    }
+  }
+  __syncthreads();
+  // u_{k-2} is V for k = 2; buffers rotate: prev2, prev, next
+  const double *prev2 = sV, *prev = U[1];
+  int nexti = 2;
+  for (int k = 2; k <= m; ++k) {
+    const int r = m - k + e;       // halo of u_k
+    const int lo = rmax - r, w = kAllT + 2 * r;
+    TailArgs t = a.t;
+    t.nu = a.nu[k];
+    t.kappa = a.kappa[k];
+    t.mu_eta = a.mu_eta[k];
+    double *next = U[nexti];
+    for (int p = threadIdx.x; p < w * w; p += kBlock) {
+      const int fx = lo + p % w, fy = lo + p / w;
+      const int q = fy * kAllR + fx;
+      const double Fu = grid_stencil<2>(g.w, [&](int dx, int dy, int) { return prev[q + dy * kAllR + dx]; });
+      const double uk = inner_combine(t, prev[q], prev2[q], Fu, sS[q]);
+      if (k < m) {
+        next[q] = uk;
+      } else {
+        // outer V update on the halo of e (reflected positions as elsewhere)
+        const int gxs = x0 + fx - rmax, gys = y0 + fy - rmax;
+        const uint32_t i = reflect(gxs, g.n0) + g.n0 * reflect(gys, g.n1);
+        const double Vj = tail_combine(t, uk, sV[q], t.j1 ? 0.0 : a.Vin2[i]);
+        if (vn != nullptr) vn[q] = Vj;
+        const bool tile = fx >= rmax && fx < rmax + kAllT && fy >= rmax && fy < rmax + kAllT;
+        if (tile && gxs < (int)g.n0 && gys < (int)g.n1) a.out[i] = Vj;
+      }
+    }
+    __syncthreads();
+    prev2 = prev;
+    prev = next;
+    nexti = (nexti + 1) % 3;
+  }
+}
+
+template <bool MIXED, int kAllT>
+__global__ __launch_bounds__(kBlock) void k_inner_all2d(InnerAllArgs a, Grid g, uint32_t ntx) {
+  static_assert(kAllT <= 16, "the LDS frame holds tiles up to 16 x 16");
+  __shared__ double U[3][kAllR * kAllR];
+  __shared__ double sV[kAllR * kAllR];
+  __shared__ double sS[kAllR * kAllR];
+  if (a.tick != nullptr && blockIdx.x == 0 && threadIdx.x == 0) a.tick->step += a.tick_by;
+  const uint32_t b = xcd_block(blockIdx.x, gridDim.x);
+  inner_all_tile<MIXED, kAllT>(a, g, (int)((b % ntx) * kAllT), (int)((b / ntx) * kAllT), 0, U, sV, sS, nullptr);
+}
+
+// One kernel per step on small 2-D grids (s == 1): the inner stages of step
+// n on the tile (V^{n+1} on a one-node halo, in LDS) and then the head of
+// step n + 1 at the tile's nodes, whose f_F(V^{n+1}) is the stencil on that
+// halo.  u_1, S_V and V alternate between two buffers from step to step
+// (read with halos while the next ones are written); z is updated in place.
+template <template <class> class Model, bool MIXED, int kAllT>
+__global__ __launch_bounds__(kBlock) void k_step2d(InnerAllArgs a, HeadArgs h, Grid g, uint32_t ntx) {
+  __shared__ double U[3][kAllR * kAllR];
+  __shared__ double sV[kAllR * kAllR];
+  __shared__ double sS[kAllR * kAllR];
+  __shared__ double sVn[kAllR * kAllR];
+  const uint32_t b = xcd_block(blockIdx.x, gridDim.x);
+  const int x0 = (int)((b % ntx) * kAllT), y0 = (int)((b / ntx) * kAllT);
+  inner_all_tile<MIXED, kAllT>(a, g, x0, y0, 1, U, sV, sS, sVn);
+  if (threadIdx.x >= kAllT * kAllT) return;
+  const int lx = threadIdx.x % kAllT, ly = threadIdx.x / kAllT;
+  const uint32_t gx = (uint32_t)(x0 + lx), gy = (uint32_t)(y0 + ly);
+  if (gx >= g.n0 || gy >= g.n1) return;
+  const int rmax = a.m;  // the halo of u_1 in this kernel
+  const int q = (ly + rmax) * kAllR + (lx + rmax);
+  head_node<Model, MIXED>(h, g.N, gx + g.n0 * gy, sVn[q], [&]() {
+    return grid_stencil<2>(g.w, [&](int dx, int dy, int) { return sVn[q + dy * kAllR + dx]; });
+  });
+}
+
 // Head on 3-D grids by z-marching columns: the MX x MY column layout and
 // LDS ring of V_{j-1} of k_inner_march, with the ionic state z_{j-1} of the
 // next plane loaded into registers while the current plane is computed, so
@@ -1966,6 +2099,47 @@ hipError_t launch_inner(bool mixed, const Mesh &mesh, const InnerArgs &a, hipStr
 bool fused_supported(const Mesh &mesh) { return mesh.kind == kGrid && !mesh.flat; }
 
 bool split_supported(const Mesh &mesh) { return mesh.kind == kGrid && !mesh.flat && mesh.grid.dim == 3; }
+
+bool inner_all_supported(const Mesh &mesh, int m) {
+  return mesh.kind == kGrid && !mesh.flat && mesh.grid.dim == 2 && m >= 2 && m <= kInnerAllMaxM;
+}
+
+template <template <class> class Model>
+static hipError_t step2d_dispatch(bool mixed, const Grid &g, const InnerAllArgs &a, const HeadArgs &h,
+                                  hipStream_t st) {
+  const uint32_t ntx = (g.n0 + 7) / 8, nty = (g.n1 + 7) / 8;
+  if (mixed)
+    EMRKC_LAUNCH((k_step2d<Model, true, 8>), dim3(ntx * nty), dim3(kBlock), 0, st, a, h, g, ntx);
+  else
+    EMRKC_LAUNCH((k_step2d<Model, false, 8>), dim3(ntx * nty), dim3(kBlock), 0, st, a, h, g, ntx);
+  return hipGetLastError();
+}
+
+hipError_t launch_step2d(int model, bool mixed, const Mesh &mesh, const InnerAllArgs &a, const HeadArgs &h,
+                         hipStream_t st) {
+  if (!inner_all_supported(mesh, a.m)) return hipErrorInvalidValue;
+#define CALL(M) step2d_dispatch<M>(mixed, mesh.grid, a, h, st)
+  EMRKC_MODEL_SWITCH(model, CALL)
+#undef CALL
+}
+
+hipError_t launch_inner_all(bool mixed, const Mesh &mesh, const InnerAllArgs &a, hipStream_t st) {
+  if (!inner_all_supported(mesh, a.m)) return hipErrorInvalidValue;
+  const Grid &g = mesh.grid;
+  const uint32_t T = g.inner_variant == 2 ? 16 : 8;  // shapes 3 and 4: 8 x 8 tiles
+  const uint32_t ntx = (g.n0 + T - 1) / T, nty = (g.n1 + T - 1) / T;
+  if (T == 8) {
+    if (mixed)
+      EMRKC_LAUNCH((k_inner_all2d<true, 8>), dim3(ntx * nty), dim3(kBlock), 0, st, a, g, ntx);
+    else
+      EMRKC_LAUNCH((k_inner_all2d<false, 8>), dim3(ntx * nty), dim3(kBlock), 0, st, a, g, ntx);
+  } else if (mixed) {
+    EMRKC_LAUNCH((k_inner_all2d<true, 16>), dim3(ntx * nty), dim3(kBlock), 0, st, a, g, ntx);
+  } else {
+    EMRKC_LAUNCH((k_inner_all2d<false, 16>), dim3(ntx * nty), dim3(kBlock), 0, st, a, g, ntx);
+  }
+  return hipGetLastError();
+}
 
 template <template <class> class Model>
 static hipError_t head_pw_dispatch(bool mixed, uint32_t N, const HeadArgs &a, hipStream_t st) {

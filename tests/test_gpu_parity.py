@@ -110,14 +110,43 @@ def _compare_full(cfg, nsteps, rho, tol=FP64_TOL, model_kw=None, track=None, **k
     return prob, Y, V, stats
 
 
-def test_c1_full_run_fp64(E):
+@pytest.mark.parametrize("variants", [None, (0, 0, 2, 0, 0), (0, 0, 3, 0, 0), (0, 0, 4, 0, 0)])
+def test_c1_full_run_fp64(E, variants):
     """Unit-square HH workload (65 x 65, 100 steps of 0.05 ms) with the
-    oracle's own spectral radii: s = 1, m = 7."""
+    oracle's own spectral radii: s = 1, m = 7; separate inner-stage launches
+    and all six inner stages in one launch (16 x 16 tiles with reflected
+    halos of up to 6 nodes)."""
     cfg = get_config("c1_2d_hh")
     prob = build_grid_problem(cfg)
     rF, rS, _, _ = oracle_rho(prob, prob.uniform_state())
-    _, _, _, stats = _compare_full(cfg, 100, (rF, rS))
+    _, _, _, stats = _compare_full(cfg, 100, (rF, rS), variants=variants)
     assert (stats.s, stats.m) == (1, 7)
+    assert stats.kernels_per_step == (7 if variants is None else 1 if variants[2] == 4 else 2)
+
+
+@pytest.mark.parametrize("rho,sm", [((900.0, 100.0), (2, 3)), ((1600.0, 300.0), (3, 3)), ((2900.0, 4.4), (1, 9)),
+                                    ((5000.0, 4.4), (1, 12))])
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_inner_stages_in_one_launch(E, rho, sm, precision):
+    """2-D grids: all inner stages of a stage in one launch equal the
+    separate launches bit for bit for s >= 2 (its buffer rule, with the
+    final copy for s = 3), up to the largest stage count it takes (m = 9),
+    and beyond it (m = 12: separate launches), in both precisions; FP64 also
+    against the oracle."""
+    cfg = small_config("c2_3d_crn", (37, 29))
+    cfg["dim"] = 2
+    V1, z1, st1 = gpu_run(cfg, 30, rho, precision=precision)
+    shape = 4 if sm[0] == 1 else 2 + (sm[0] % 2)
+    V2, z2, st2 = gpu_run(cfg, 30, rho, precision=precision, variants=(0, 0, shape, 0, 0), chunks=[3, 27])
+    assert (st1.s, st1.m) == sm and (st2.s, st2.m) == sm
+    s, m = sm
+    assert st2.kernels_per_step == ((1 if shape == 4 else 2 * s + (1 if s > 1 and s % 2 else 0)) if m <= 9
+                                    else s * m)
+    assert np.array_equal(V1, V2) and np.array_equal(z1, z2)
+    if precision == "fp64":
+        _, y = oracle_run(cfg, 30, rho)
+        l2, mx = rel_errors(V2, y[:V2.size])
+        assert l2 < FP64_TOL and mx < FP64_TOL, (l2, mx)
 
 
 @pytest.mark.parametrize("model,n", [("CRN_SURR", (37, 29, 11)), ("TTP_SURR", (41, 19, 9))])
@@ -241,6 +270,15 @@ def test_graph_eager_fused_split_and_repeat_are_bitwise_identical(E, n, rho, pre
     assert st1.used_graph == 1 and st2.used_graph == 0
     assert st1.kernels_per_step == st1.m and st5.kernels_per_step == st5.m - 1
     assert st8.kernels_per_step == st8.m
+    if len(n) == 2:  # all inner stages in one launch, also over an odd call split
+        runs.append(gpu_run(cfg, 80, rho, precision=precision, variants=(0, 0, 2, 0, 0))[:2])
+        runs.append(gpu_run(cfg, 80, rho, precision=precision, variants=(0, 0, 3, 0, 0))[:2])
+        V11, z11, st11 = gpu_run(cfg, 80, rho, precision=precision, chunks=[1, 33, 7, 39], variants=(0, 0, 4, 0, 0))
+        assert st11.kernels_per_step == 1
+        runs.append((V11, z11))
+        V10, z10, st10 = gpu_run(cfg, 80, rho, precision=precision, chunks=[1, 33, 7, 39], variants=(0, 0, 2, 0, 0))
+        assert st10.kernels_per_step == 2
+        assert np.array_equal(V10, V1) and np.array_equal(z10, z1)
     if len(n) == 3:  # the split stage with an odd call split (ping-pong and the final copy)
         V9, z9, st9 = gpu_run(cfg, 80, rho, precision=precision, chunks=[1, 33, 7, 39], variants=(7, 3, 1, 4, 0))
         assert st9.kernels_per_step == st9.m
@@ -357,6 +395,11 @@ def test_minimal_grids(E, n, rho):
     l2, mx = rel_errors(V, Y[0])
     assert l2 <= 1e-10 and mx <= 1e-10, (l2, mx)
     assert np.abs(z - Y[1:]).max() <= 1e-10 * np.abs(Y[1:]).max()
+    if len(n) == 2:  # all inner stages in one launch: reflected halos reach across the whole grid
+        for v in [(0, 0, 2, 0, 0), (0, 0, 3, 0, 0), (0, 0, 4, 0, 0)]:
+            V2, z2, st2 = gpu_run(cfg, nsteps, rho, variants=v)
+            assert st2.kernels_per_step == (1 if v[2] == 4 else 2)
+            assert np.array_equal(V2, V) and np.array_equal(z2, z), v
     if len(n) == 3:
         for v in [(1, 1, 1, 1, 0), (2, n[2], 1, n[2], 0), (2, 1, 0, 0, 1), (3, 0, 1, 2, 0), (0, 0, 0, 0, 0),
                   (5, 0, 1, 1, 0), (5, 0, 0, 0, 0), (7, 1, 0, 0, 0), (7, n[2], 1, 1, 0), (8, 0, 0, 0, 0)]:

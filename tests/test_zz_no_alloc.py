@@ -23,9 +23,11 @@ def E():
     return emrkc
 
 
-def run(E, cfg, nsteps, rho, precision="fp64", noalloc=False, flags=0, chunks=None):
+def run(E, cfg, nsteps, rho, precision="fp64", noalloc=False, flags=0, chunks=None, variants=None):
     import torch
     sim = E.simulation_from_config(cfg, precision=precision, rho=rho, flags=flags)
+    if variants is not None:
+        E.emrkc_set_variants(sim.ctx, variants)
     E.emrkc_init_state(sim.ctx, sim.state)
     step = E.emrkc_step_noalloc if noalloc else E.emrkc_step
     for n in (chunks or [nsteps]):
@@ -66,7 +68,7 @@ def test_two_calls_in_a_row_second_smaller_match_emrkc_step(E):
     check_pair(E, big, 7, rho)
 
 
-@pytest.mark.parametrize("case", ["mixed", "fused", "s3", "m1_2d", "splits"])
+@pytest.mark.parametrize("case", ["mixed", "fused", "s3", "m1_2d", "splits", "step2d", "split3d"])
 def test_other_step_plans_match_emrkc_step(E, case):
     """Mixed precision (float S_V and z_1), the fused chunk (three inner
     buffers, two S_V), s = 3 outer stages (z_1 in the scratch array), the
@@ -88,6 +90,13 @@ def test_other_step_plans_match_emrkc_step(E, case):
     elif case == "splits":
         kw = dict(chunks=[1, 33, 7, 2])
         nsteps = 43
+    elif case == "step2d":  # one kernel per step on a 2-D grid (alternating S_V buffers)
+        cfg = small_config("c2_3d_crn", (37, 11))
+        cfg["dim"] = 2
+        rho = (900.0, 4.4)
+        kw = dict(variants=(0, 0, 4, 0, 0))
+    elif case == "split3d":  # pointwise head and u_1 by the inner kernel
+        kw = dict(variants=(8, 0, 1, 4, 0))
     _, st = check_pair(E, cfg, nsteps, rho, **kw)
     if case == "s3":
         assert st.s == 3
