@@ -442,7 +442,9 @@ struct Grid {
   // (mixed precision only), 7 and 8 = the split stage with a pointwise head
   // (7: one kernel for the first two inner stages in columns of head_zc
   // planes; 8: the first inner stage as a launch of the inner kernel);
-  // chosen by the host
+  // on 2-D grids inner 2/3 = all inner stages of a stage in one launch
+  // (16 x 16 / 8 x 8 tiles), 4 = one kernel per step (s == 1); chosen by
+  // the host
   int inner_variant;
   uint32_t zc;
   int head_variant;

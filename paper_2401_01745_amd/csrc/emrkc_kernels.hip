@@ -736,27 +736,36 @@ __global__ __launch_bounds__(kBlock) void k_inner_march(InnerArgs a, Grid g, uin
   }
   const double *__restrict__ u = a.t.uprev;
   auto gplane = [&](int z) { return (size_t)mirror_any(z, g.n2) * plane; };
-  auto stage = [&](double *dst, int z) {
-    const size_t pz = gplane(z);
-#pragma unroll
-    for (int k = 0; k < MSLOT; ++k)
-      if (act[k]) dst[threadIdx.x + k * kBlock] = u[pz + off[k]];
-  };
-  stage(ring[(zb + 2) % 3], zb - 1);   // slot of plane p is p mod 3 (p >= -1)
-  stage(ring[zb % 3], zb);
-  double pre[MSLOT];
+  // Every load is unconditional (inactive slots read offset 0 of the plane,
+  // nodes outside the grid the nearest node, values never used), so that
+  // the loads of the first three planes and of the first node's operands
+  // are all in flight together, and the compiler can count the loads it
+  // waits for.
+  double pre[MSLOT], s0[MSLOT], s1[MSLOT];
   {
-    const size_t pz = gplane(zb + 1);
+    const size_t pa = gplane(zb - 1), pb = gplane(zb), pc = gplane(zb + 1);
 #pragma unroll
-    for (int k = 0; k < MSLOT; ++k) pre[k] = act[k] ? u[pz + off[k]] : 0.0;
+    for (int k = 0; k < MSLOT; ++k) {
+      s0[k] = u[pa + off[k]];
+      s1[k] = u[pb + off[k]];
+      pre[k] = u[pc + off[k]];
+    }
   }
   const int lx = threadIdx.x % MX, ly = threadIdx.x / MX;
   const uint32_t gx = (uint32_t)(x0 + lx), gy = (uint32_t)(y0 + ly);
   const bool own = gx < g.n0 && gy < g.n1;
   const int c = (ly + 1) * MSX + (lx + 1);
-  uint32_t i = gx + g.n0 * gy + plane * (uint32_t)zb;
-  InnerPoint pt{0.0, 0.0, 0.0, 0.0};
-  if (own) pt = load_point<MIXED>(a, i);
+  // the node whose operands are loaded: this thread's own node, or the
+  // nearest node of the grid for threads beyond its edge
+  uint32_t i = min(gx, g.n0 - 1) + g.n0 * min(gy, g.n1 - 1) + plane * (uint32_t)zb;
+  InnerPoint pt = load_point<MIXED>(a, i);
+  // slot of plane p is p mod 3 (p >= -1)
+#pragma unroll
+  for (int k = 0; k < MSLOT; ++k)
+    if (act[k]) {
+      ring[(zb + 2) % 3][threadIdx.x + k * kBlock] = s0[k];
+      ring[zb % 3][threadIdx.x + k * kBlock] = s1[k];
+    }
   for (int z = zb; z < ze; ++z, i += plane) {
     double *nxt = ring[(z + 1) % 3];
 #pragma unroll
@@ -767,8 +776,8 @@ __global__ __launch_bounds__(kBlock) void k_inner_march(InnerArgs a, Grid g, uin
     if (z + 1 < ze) {
       const size_t pz = gplane(z + 2);
 #pragma unroll
-      for (int k = 0; k < MSLOT; ++k) pre[k] = act[k] ? u[pz + off[k]] : 0.0;
-      if (own) pt = load_point<MIXED>(a, i + plane);
+      for (int k = 0; k < MSLOT; ++k) pre[k] = u[pz + off[k]];
+      pt = load_point<MIXED>(a, i + plane);
     }
     if (own) {
       const double *pm = ring[(z + 2) % 3], *pc = ring[z % 3], *pp = ring[(z + 1) % 3];
