@@ -349,8 +349,19 @@ __global__ __launch_bounds__(kBlock) void k_imexrl_pre(ImexArgs a, uint32_t N) {
 // ---------------------------------------------------------------------------
 // Inner stages
 // ---------------------------------------------------------------------------
+// Every array the kernels touch is in global memory.  A pointer that a
+// kernel reads from a table in memory (the batched kernels' instance
+// records) is generic, and the compiler issues flat instructions through
+// it, which also count against the LDS counter so that every LDS access
+// waits for them; the global-pointer form below gives global instructions.
+// (Pointers in kernel arguments are global to the compiler already.)
+template <class T>
+__device__ __forceinline__ __attribute__((address_space(1))) T *gptr(T *p) {
+  return (__attribute__((address_space(1))) T *)(uintptr_t)p;
+}
+
 __device__ __forceinline__ double load_sv(const void *SV, bool mixed, uint32_t i) {
-  return mixed ? (double)((const float *)SV)[i] : ((const double *)SV)[i];
+  return mixed ? (double)gptr((const float *)SV)[i] : gptr((const double *)SV)[i];
 }
 
 // u_k = nu u_{k-1} + kappa u_{k-2} + mu eta (f_F(u_{k-1}) + S_V)
@@ -586,16 +597,28 @@ __device__ __forceinline__ void tile_origin(uint32_t ntx, uint32_t nty, int &x0,
   z0 = (int)(bz * T::TZ);
 }
 
+// All of a thread's halo loads are issued before the first is stored (one
+// memory latency instead of one per load); slots beyond the halo load its
+// last position again and store nothing.
 template <int DIM, int SH = 0>
 __device__ __forceinline__ void stage_halo(double *sU, const double *__restrict__ u, const Grid &g, int x0, int y0,
                                            int z0) {
   using T = Tile<DIM, SH>;
-  for (int r = threadIdx.x; r < T::NS; r += kBlock) {
+  constexpr int NSL = (T::NS + kBlock - 1) / kBlock;
+  double v[NSL];
+#pragma unroll
+  for (int k = 0; k < NSL; ++k) {
+    const int r = min((int)threadIdx.x + k * kBlock, T::NS - 1);
     const int hx = r % T::SX, hy = (r / T::SX) % T::SY, hz = r / (T::SX * T::SY);
     const uint32_t gx = mirror_any(x0 + hx - 1, g.n0);
     const uint32_t gy = mirror_any(y0 + hy - 1, g.n1);
     const uint32_t gz = DIM == 3 ? mirror_any(z0 + hz - 1, g.n2) : 0u;
-    sU[r] = u[gx + g.n0 * (gy + g.n1 * gz)];
+    v[k] = gptr(u)[gx + g.n0 * (gy + g.n1 * gz)];
+  }
+#pragma unroll
+  for (int k = 0; k < NSL; ++k) {
+    const int r = (int)threadIdx.x + k * kBlock;
+    if (r < T::NS) sU[r] = v[k];
   }
 }
 
@@ -664,13 +687,15 @@ struct InnerPoint {
 template <bool MIXED>
 __device__ __forceinline__ InnerPoint load_point(const InnerArgs &a, uint32_t i) {
   InnerPoint p;
-  p.u2 = a.first ? 0.0 : a.t.uprev2[i];
+  p.u2 = a.first ? 0.0 : gptr(a.t.uprev2)[i];
   p.sv = load_sv(a.t.SV, MIXED, i);
   p.vp = 0.0;
   p.vp2 = 0.0;
   if (a.last) {
-    p.vp = a.t.uprev2 == a.t.Vin ? p.u2 : a.t.Vin[i];  // m == 2: u_0 is V_{j-1}
-    if (!a.t.j1) p.vp2 = a.t.Vin2[i];
+    // m == 2: u_0 is V_{j-1}, taken from u2 where it is used (a copy here
+    // would wait for that load before the next ones are issued)
+    if (a.t.uprev2 != a.t.Vin) p.vp = gptr(a.t.Vin)[i];
+    if (!a.t.j1) p.vp2 = gptr(a.t.Vin2)[i];
   }
   return p;
 }
@@ -680,7 +705,7 @@ __device__ __forceinline__ InnerPoint load_point(const InnerArgs &a, uint32_t i)
 __device__ __forceinline__ double inner_point(const InnerArgs &a, double uc, double Fu, const InnerPoint &p) {
   if (a.first) return first_inner(a.t.mu_eta, uc, Fu, p.sv);
   const double uk = inner_combine(a.t, uc, p.u2, Fu, p.sv);
-  return a.last ? tail_combine(a.t, uk, p.vp, p.vp2) : uk;
+  return a.last ? tail_combine(a.t, uk, a.t.uprev2 == a.t.Vin ? p.u2 : p.vp, p.vp2) : uk;
 }
 
 // The node's pointwise operands are loaded before the halo is staged (both
@@ -713,11 +738,12 @@ __global__ __launch_bounds__(kBlock) void k_inner_tiled(InnerArgs a, Grid g, uin
 constexpr int MSX = MX + 2, MSY = MY + 2, MPL = MSX * MSY;
 constexpr int MSLOT = (MPL + kBlock - 1) / kBlock;
 
+// One column (block b of the grid's columns, x fastest) of the z-marching
+// inner stage; the grid's nodes start at index `base` of every array (a
+// batched instance), and ring is the block's LDS.
 template <bool MIXED>
-__global__ __launch_bounds__(kBlock) void k_inner_march(InnerArgs a, Grid g, uint32_t ncx, uint32_t ncy) {
-  __shared__ double ring[3][MPL];
-  if (a.tick != nullptr && blockIdx.x == 0 && threadIdx.x == 0) a.tick->step += a.tick_by;
-  const uint32_t b = xcd_block(blockIdx.x, gridDim.x);
+__device__ __forceinline__ void inner_march_col(const InnerArgs &a, const Grid &g, uint32_t base, uint32_t b,
+                                                uint32_t ncx, uint32_t ncy, double (*ring)[MPL]) {
   const uint32_t bx = b % ncx, byz = b / ncx;
   const uint32_t by = byz % ncy, bz = byz / ncy;
   const int x0 = (int)(bx * MX), y0 = (int)(by * MY);
@@ -734,7 +760,8 @@ __global__ __launch_bounds__(kBlock) void k_inner_march(InnerArgs a, Grid g, uin
     const int hx = r % MSX, hy = r / MSX;
     off[k] = act[k] ? mirror_any(x0 + hx - 1, g.n0) + g.n0 * mirror_any(y0 + hy - 1, g.n1) : 0u;
   }
-  const double *__restrict__ u = a.t.uprev;
+  const auto u = gptr(a.t.uprev + base);
+  const auto out = gptr(a.out + base);
   auto gplane = [&](int z) { return (size_t)mirror_any(z, g.n2) * plane; };
   // Every load is unconditional (inactive slots read offset 0 of the plane,
   // nodes outside the grid the nearest node, values never used), so that
@@ -758,7 +785,7 @@ __global__ __launch_bounds__(kBlock) void k_inner_march(InnerArgs a, Grid g, uin
   // the node whose operands are loaded: this thread's own node, or the
   // nearest node of the grid for threads beyond its edge
   uint32_t i = min(gx, g.n0 - 1) + g.n0 * min(gy, g.n1 - 1) + plane * (uint32_t)zb;
-  InnerPoint pt = load_point<MIXED>(a, i);
+  InnerPoint pt = load_point<MIXED>(a, base + i);
   // slot of plane p is p mod 3 (p >= -1)
 #pragma unroll
   for (int k = 0; k < MSLOT; ++k)
@@ -777,7 +804,7 @@ __global__ __launch_bounds__(kBlock) void k_inner_march(InnerArgs a, Grid g, uin
       const size_t pz = gplane(z + 2);
 #pragma unroll
       for (int k = 0; k < MSLOT; ++k) pre[k] = u[pz + off[k]];
-      pt = load_point<MIXED>(a, i + plane);
+      pt = load_point<MIXED>(a, base + i + plane);
     }
     if (own) {
       const double *pm = ring[(z + 2) % 3], *pc = ring[z % 3], *pp = ring[(z + 1) % 3];
@@ -785,10 +812,17 @@ __global__ __launch_bounds__(kBlock) void k_inner_march(InnerArgs a, Grid g, uin
         const double *pl = dz < 0 ? pm : (dz > 0 ? pp : pc);
         return pl[c + dy * MSX + dx];
       });
-      a.out[i] = inner_point(a, pc[c], Fu, cur);
+      out[i] = inner_point(a, pc[c], Fu, cur);
     }
     __syncthreads();
   }
+}
+
+template <bool MIXED>
+__global__ __launch_bounds__(kBlock) void k_inner_march(InnerArgs a, Grid g, uint32_t ncx, uint32_t ncy) {
+  __shared__ double ring[3][MPL];
+  if (a.tick != nullptr && blockIdx.x == 0 && threadIdx.x == 0) a.tick->step += a.tick_by;
+  inner_march_col<MIXED>(a, g, 0u, xcd_block(blockIdx.x, gridDim.x), ncx, ncy, ring);
 }
 
 // ---------------------------------------------------------------------------
@@ -1327,6 +1361,15 @@ __device__ __forceinline__ void tile_xyz(const BatchInst &I, uint32_t tile, int 
   z0 = (int)(bz * T::TZ);
 }
 
+// Table slot of logical block lb: the u16 map is read as 32-bit words, a
+// scalar load (its allocation holds an even number of entries), and the
+// instance record is then copied by value, so that its fields are loaded
+// together rather than one dependent load at a time where they are used.
+__device__ __forceinline__ uint32_t batch_slot(const uint16_t *__restrict__ map, uint32_t lb) {
+  const uint32_t w = ((const uint32_t *)map)[lb >> 1];
+  return (lb & 1u) ? (w >> 16) : (w & 0xffffu);
+}
+
 template <template <class> class Model, bool MIXED, int DIM, int SH>
 __device__ __forceinline__ void head_tile(const BatchInst &I, const HeadArgs &h, uint32_t tile, double *sV,
                                           uint32_t Ntot) {
@@ -1345,7 +1388,7 @@ __global__ __launch_bounds__(kBlock) void k_head_batch(const BatchInst *__restri
                                                        const uint16_t *__restrict__ map, uint32_t Ntot, int step_off) {
   __shared__ double sV[BatchLds<SH>::NS];
   const uint32_t lb = xcd_block(blockIdx.x, gridDim.x);
-  const BatchInst &I = tab[map[lb]];
+  BatchInst I = tab[batch_slot(map, lb)];
   HeadArgs h = I.h;
   h.step_off = step_off;
   if (I.g.dim == 3)
@@ -1362,7 +1405,7 @@ __global__ __launch_bounds__(kBlock) void k_head_batch_flat(const BatchInst *__r
                                                             const uint16_t *__restrict__ map, uint32_t Ntot,
                                                             int step_off) {
   const uint32_t lb = xcd_block(blockIdx.x, gridDim.x);
-  const BatchInst &I = tab[map[lb]];
+  BatchInst I = tab[batch_slot(map, lb)];
   const uint32_t il = (lb - I.tile0) * kBlock + threadIdx.x;
   if (il >= I.g.N) return;
   HeadArgs h = I.h;
@@ -1390,19 +1433,24 @@ __device__ __forceinline__ void inner_tile(const BatchInst &I, uint32_t tile, do
   __syncthreads();
   if (!own) return;
   const double Fu = lds_stencil<DIM, SH>(sU, I.g, c);
-  a.out[i] = inner_point(a, sU[c], Fu, pt);
+  gptr(a.out)[i] = inner_point(a, sU[c], Fu, pt);
 }
 
+// Inner stage of the batch: LDS tiles, or for 3-D instances whose table
+// entry says so (inner_variant 1) z-marching columns of g.zc planes.
 template <bool MIXED, int SH>
 __global__ __launch_bounds__(kBlock) void k_inner_batch(const BatchInst *__restrict__ tab,
                                                         const uint16_t *__restrict__ map) {
-  __shared__ double sU[BatchLds<SH>::NS];
+  constexpr int NL = BatchLds<SH>::NS > 3 * MPL ? BatchLds<SH>::NS : 3 * MPL;
+  __shared__ double lds[NL];
   const uint32_t lb = xcd_block(blockIdx.x, gridDim.x);
-  const BatchInst &I = tab[map[lb]];
-  if (I.g.dim == 3)
-    inner_tile<MIXED, 3, SH>(I, lb - I.tile0, sU);
+  BatchInst I = tab[batch_slot(map, lb)];
+  if (I.g.dim == 3 && I.g.inner_variant == 1)
+    inner_march_col<MIXED>(I.in, I.g, I.off, lb - I.tile0, I.ntx, I.nty, (double (*)[MPL])lds);
+  else if (I.g.dim == 3)
+    inner_tile<MIXED, 3, SH>(I, lb - I.tile0, lds);
   else
-    inner_tile<MIXED, 2, SH>(I, lb - I.tile0, sU);
+    inner_tile<MIXED, 2, SH>(I, lb - I.tile0, lds);
 }
 
 __global__ void k_clock_set(Clock *c, int64_t step, double t0) {
