@@ -498,8 +498,8 @@ __device__ __forceinline__ double grid_stencil(const double *w, Get get) {
 }
 
 // The stencil on a global array at node (ix, iy, iz).
-template <int DIM>
-__device__ __forceinline__ double grid_apply(const double *__restrict__ u, const Grid &g, uint32_t ix,
+template <int DIM, class P>
+__device__ __forceinline__ double grid_apply(P u, const Grid &g, uint32_t ix,
                                              uint32_t iy, uint32_t iz) {
   const uint32_t xs[3] = {mirror_lo(ix), ix, mirror_hi(ix, g.n0)};
   const uint32_t s1 = g.n0;

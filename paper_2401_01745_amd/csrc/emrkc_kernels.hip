@@ -32,14 +32,26 @@ using MathOf = typename std::conditional<MIXED, MathF32, MathF64>::type;
 
 // Stage time t_n + c_{j-1} dt with t_n = t0 + n dt, n = chunk base + offset,
 // without contraction so that host and device obtain the same double.
+// Every array the kernels touch is in global memory.  A pointer that a
+// kernel reads from a table in memory (the batched kernels' instance
+// records) is generic, and the compiler issues flat instructions through
+// it, which also count against the LDS counter so that every LDS access
+// waits for them; the global-pointer form below gives global instructions.
+// (Pointers in kernel arguments are global to the compiler already.)
+template <class T>
+__device__ __forceinline__ __attribute__((address_space(1))) T *gptr(T *p) {
+  return (__attribute__((address_space(1))) T *)(uintptr_t)p;
+}
+
 __device__ __forceinline__ double stage_time(const Clock *c, int step_off, double dt, double c_prev) {
 #pragma clang fp contract(off)
-  const double tn = c->t0 + (double)(c->step + step_off) * dt;
+  const auto g = gptr(c);
+  const double tn = g->t0 + (double)(g->step + step_off) * dt;
   return tn + c_prev * dt;
 }
 
 __device__ __forceinline__ double stimulus(const StimArgs &s, uint32_t i, double t) {
-  return (s.mask != nullptr && s.mask[i] != 0 && s.t_on <= t && t <= s.t_off) ? s.amp : 0.0;
+  return (s.mask != nullptr && gptr(s.mask)[i] != 0 && s.t_on <= t && t <= s.t_off) ? s.amp : 0.0;
 }
 
 __device__ __forceinline__ uint32_t node_index() {
@@ -125,7 +137,7 @@ struct HeadZ {
   static constexpr int NZ = Model<MathOf<MIXED>>::NG + Model<MathOf<MIXED>>::NS;
   R z[NZ];
   __device__ __forceinline__ void load(const void *zin, uint32_t N, uint32_t i) {
-    const R *p = (const R *)zin;
+    const auto p = gptr((const R *)zin);
 #pragma unroll
     for (int k = 0; k < NZ; ++k) z[k] = p[(size_t)k * N + i];
   }
@@ -177,8 +189,8 @@ __device__ __forceinline__ void head_node_z(const HeadArgs &a, uint32_t N, uint3
   // gate (its rounding stays at the level of the float storage it is written
   // to); later stages, whose coefficients nu and kappa can exceed 1, and the
   // slow variables recur in double.
-  R *zout = (R *)a.zout;
-  const R *zin2 = (const R *)a.zin2;
+  const auto zout = gptr((R *)a.zout);
+  const auto zin2 = gptr((const R *)a.zin2);
   const float gate_c = (float)(a.mu_dt * a.inv_eta * (a.progressive ? a.cm : 1.0));
 #pragma unroll
   for (int k = 0; k < NZ; ++k) {
@@ -205,9 +217,9 @@ __device__ __forceinline__ void head_node_z(const HeadArgs &a, uint32_t N, uint3
 
   if (SV_ONLY) {
     if (MIXED)
-      ((float *)a.SV)[i] = (float)SV;
+      gptr((float *)a.SV)[i] = (float)SV;
     else
-      ((double *)a.SV)[i] = SV;
+      gptr((double *)a.SV)[i] = SV;
     return;
   }
   // first inner stage u_1 = u_0 + mu'_1 eta (f_F(u_0) + S_V), u_0 = V (in
@@ -216,13 +228,13 @@ __device__ __forceinline__ void head_node_z(const HeadArgs &a, uint32_t N, uint3
   const double u1 = first_inner(a.mu1_eta, V, FV, SV);
   if (a.m_is_one) {
     const double fbarV = (u1 - V) * a.inv_eta;
-    a.uout[i] = a.j1 ? V + a.mu_dt * fbarV : a.nu * V + a.kappa * a.Vin2[i] + a.mu_dt * fbarV;
+    gptr(a.uout)[i] = a.j1 ? V + a.mu_dt * fbarV : a.nu * V + a.kappa * gptr(a.Vin2)[i] + a.mu_dt * fbarV;
   } else {
-    a.uout[i] = u1;
+    gptr(a.uout)[i] = u1;
     if (MIXED)
-      ((float *)a.SV)[i] = (float)SV;
+      gptr((float *)a.SV)[i] = (float)SV;
     else
-      ((double *)a.SV)[i] = SV;
+      gptr((double *)a.SV)[i] = SV;
   }
 }
 
@@ -349,17 +361,6 @@ __global__ __launch_bounds__(kBlock) void k_imexrl_pre(ImexArgs a, uint32_t N) {
 // ---------------------------------------------------------------------------
 // Inner stages
 // ---------------------------------------------------------------------------
-// Every array the kernels touch is in global memory.  A pointer that a
-// kernel reads from a table in memory (the batched kernels' instance
-// records) is generic, and the compiler issues flat instructions through
-// it, which also count against the LDS counter so that every LDS access
-// waits for them; the global-pointer form below gives global instructions.
-// (Pointers in kernel arguments are global to the compiler already.)
-template <class T>
-__device__ __forceinline__ __attribute__((address_space(1))) T *gptr(T *p) {
-  return (__attribute__((address_space(1))) T *)(uintptr_t)p;
-}
-
 __device__ __forceinline__ double load_sv(const void *SV, bool mixed, uint32_t i) {
   return mixed ? (double)gptr((const float *)SV)[i] : gptr((const double *)SV)[i];
 }
@@ -1410,7 +1411,7 @@ __global__ __launch_bounds__(kBlock) void k_head_batch_flat(const BatchInst *__r
   if (il >= I.g.N) return;
   HeadArgs h = I.h;
   h.step_off = step_off;
-  const double *Vg = h.Vin + I.off;
+  const auto Vg = gptr(h.Vin + I.off);
   head_node<Model, MIXED>(h, Ntot, I.off + il, Vg[il], [&]() {
     uint32_t ix, iy, iz;
     grid_coords(I.g, il, ix, iy, iz);
