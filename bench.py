@@ -65,6 +65,14 @@ def bytes_per_node(kind, nz, wz, m, mat=0):
         return 8 + sv + 8
     if kind == "fused":
         return 8 + (8 if m >= 3 else 0) + 8 + sv + 2 * nz * wz + sv + 8 + 8 + 2 * mat
+    # 2-D grids, all inner stages of a stage in one launch: u_1, V and S_V
+    # read (with halos staged in LDS), V_j written; u_2 .. u_{m-1} never
+    # leave LDS.  One kernel per step adds the next step's head without its
+    # V read: z read and written, S_V and u_1 written
+    if kind == "inner_all":
+        return 8 + 8 + sv + 8
+    if kind == "step2d":
+        return 8 + 8 + sv + 8 + 2 * nz * wz + sv + 8
     if kind == "inner":
         return 8 + 8 + sv + 8 + mat
     if kind == "tail":
@@ -367,6 +375,11 @@ def main():
         dom_ms = prof[dom][0]
         # the split stage: pointwise head + two-stage inner kernel (shape 7)
         split = batch is None and tet is None and args.method == "emrkc" and variants[0] in (7, 8) and m >= 2
+        # 2-D grids: all inner stages in one launch (inner shapes 2, 3), or
+        # one kernel per step (shape 4, whose launches are the fused class)
+        planar2d = (batch is None and tet is None and args.method == "emrkc" and cfg.get("dim") == 2
+                    and variants[2] in (2, 3, 4) and m >= 2)
+        step2d = planar2d and variants[2] == 4
         width = E.lib().emrkc_ell_width(job.sim.ctx) if tet is not None else 0
         mat = width * (4 + 8)
         if batch is not None:
@@ -377,6 +390,8 @@ def main():
             db = bytes_per_node("mrkc_head", nz, 8, m, mat) * N
         elif split:
             db = bytes_per_node("head_pw", nz, 8, m) * N
+        elif step2d and dom == "fused":
+            db = bytes_per_node("step2d", nz, 8, m) * N
         else:
             db = bytes_per_node(dom, nz, 8, m, mat) * N
         dom_gbs = db / (dom_ms * 1e-3) / 1e9
@@ -405,7 +420,9 @@ def main():
                         4: "k_head_tiled_occ<8 waves/SIMD>", 5: "k_head (flat)",
                         6: "k_head_occ (flat, 7 waves per SIMD)", 7: "k_head_pw (pointwise)",
                         8: "k_head_pw (pointwise)"}[variants[0]])
-        names = {"fused": "k_fused (last inner stage of step n-1 + exponential Euler, ionic model, outer z "
+        names = {"fused": "k_step2d (all inner stages and the outer V update of step n-1 + exponential Euler, "
+                          "ionic model, outer z recurrence and first inner stage of step n)" if step2d else
+                          "k_fused (last inner stage of step n-1 + exponential Euler, ionic model, outer z "
                           "recurrence and first inner stage of step n)",
                  "head": ("%s (exponential Euler, ionic model, outer z recurrence, S_V)" % head_kernel if split else
                           "%s (exponential Euler, ionic model, outer z recurrence, first inner stage)" % head_kernel)
@@ -420,6 +437,8 @@ def main():
             ib = bytes_per_node("inner12", nz, 8, m) * N if m == 2 else None
         elif split:  # u_1 launch and the last inner stage, mean bytes per launch
             ib = (bytes_per_node("inner1", nz, 8, m) + bytes_per_node("tail", nz, 8, m)) * N // 2 if m == 2 else None
+        elif planar2d:  # all inner stages in one launch (s == 1); with shape 4 only the chunk's last step
+            ib = bytes_per_node("inner_all", nz, 8, m) * N if s == 1 else None
         elif args.method == "mrkc":
             ib = bytes_per_node("mrkc_tail", nz, 8, m, mat) * N if m == 2 else None
         else:
@@ -432,6 +451,9 @@ def main():
                 "launches": {k: v[1] for k, v in prof.items()},
                 "inner_stencil_kernel": {"kernel": "k_inner12_march (first two inner stages and the outer V update)"
                                          if split and variants[0] == 7 else
+                                         "k_inner_all2d (all %d inner stages and the outer V update, %dx%d tiles)"
+                                         % (m - 1, 16 if variants[2] == 2 else 8, 16 if variants[2] == 2 else 8)
+                                         if planar2d else
                                          "first inner stage and last inner stage with the outer V update (mean)"
                                          if split else "last inner stage and the outer V update",
                                          "achieved_GBs": round(inner_gbs, 1) if inner_gbs else None,

@@ -129,6 +129,7 @@ struct emrkc_ctx {
   int batch_shape = 0;        // tile shape of the batched kernels (0..2)
   bool batch_flat_head = true;   // batched head: flat kernel (measured faster) instead of the tiles
   int batch_march_zc = 0;        // > 0: inner stages of 3-D instances by z-marching columns of this many planes
+  bool batch_pairs = false;      // inner stages with two tiles per block
   double *d_ML = nullptr;     // lumped mass (tets at creation, grids on first IMEX-RL step)
   double *d_cgq = nullptr;    // IMEX-RL: the conjugate gradient's B p
   double *d_Dsum = nullptr;   // IMEX-RL on tets: row sums of the operator's weights
@@ -1910,7 +1911,7 @@ static void get_variants(const emrkc_ctx *c, int *v) {
   if (c->batch) {
     v[0] = c->batch_shape;
     v[1] = c->batch_flat_head ? 1 : 0;
-    v[2] = c->batch_march_zc > 0 ? 1 : 0;
+    v[2] = c->batch_march_zc > 0 ? 1 : c->batch_pairs ? 2 : 0;
     v[3] = c->batch_march_zc;
     v[4] = 0;
     return;
@@ -1926,9 +1927,9 @@ static void get_variants(const emrkc_ctx *c, int *v) {
 
 static int check_variants(const emrkc_ctx *c, const int *v) {
   if (c->batch) {
-    if (v[0] < 0 || v[0] > 2 || v[1] < 0 || v[1] > 1 || v[2] < 0 || v[2] > 1) return EMRKC_EINVAL;
+    if (v[0] < 0 || v[0] > 2 || v[1] < 0 || v[1] > 1 || v[2] < 0 || v[2] > 2) return EMRKC_EINVAL;
     if (v[2] == 1 && (v[3] < 1 || v[3] > 64)) return EMRKC_EINVAL;  // planes per marching column
-    if (v[2] == 0 && v[3] != 0) return EMRKC_EINVAL;
+    if (v[2] != 1 && v[3] != 0) return EMRKC_EINVAL;
     return v[4] == 0 ? EMRKC_OK : EMRKC_EUNSUPPORTED;
   }
   if (v[4] < 0 || v[4] > 1 || (v[4] == 1 && !fusable(c))) return EMRKC_EUNSUPPORTED;
@@ -1955,7 +1956,8 @@ static void set_variants(emrkc_ctx *c, const int *v) {
   if (c->batch) {
     c->batch_shape = v[0];
     c->batch_flat_head = v[1] != 0;
-    c->batch_march_zc = v[2] ? v[3] : 0;
+    c->batch_march_zc = v[2] == 1 ? v[3] : 0;
+    c->batch_pairs = v[2] == 2;
     clear_graphs(c);
     return;
   }
@@ -2075,12 +2077,28 @@ static int autotune_batch(emrkc_ctx *c, const emrkc_state *st, double dt, int re
       if (ms[0] < 0.97 * head_t) flat = 1;
     }
   }
+  // inner stages with two tiles per block
+  double best_in = inner_t;
+  int pairs = 0;
+  if (rc == EMRKC_OK && P.m >= 2) {
+    const int v[5] = {choice, flat, 2, 0, 0};
+    set_variants(c, v);
+    double ms[3];
+    if ((rc = build_batch_tables(c, &cp.st, dt, P)) == EMRKC_OK &&
+        (rc = time_classes_best(c, &cp.st, P, dt, reps, ms)) == EMRKC_OK) {
+      if (verbose) fprintf(stderr, "emrkc_autotune: batch two tiles per block: inner %.5f ms (tiles %.5f ms)\n", ms[1],
+                           inner_t);
+      if (ms[1] < 0.97 * best_in) {
+        best_in = ms[1];
+        pairs = 1;
+      }
+    }
+  }
   // inner stages of 3-D instances by z-marching columns (zc planes; 64 =
   // whole columns)
   int zc_choice = 0;
   bool any3d = false;
   for (auto &I : c->inst) any3d = any3d || I.mesh.grid.dim == 3;
-  double best_in = inner_t;
   for (int zc : {4, 8, 64}) {
     if (rc != EMRKC_OK || !any3d || P.m < 2) break;
     const int v[5] = {choice, flat, 1, zc, 0};
@@ -2097,8 +2115,9 @@ static int autotune_batch(emrkc_ctx *c, const emrkc_state *st, double dt, int re
     }
   }
   (void)hipStreamSynchronize(c->stream);
-  const int v[5] = {rc == EMRKC_OK ? choice : orig[0], rc == EMRKC_OK ? flat : orig[1],
-                    rc == EMRKC_OK ? (zc_choice ? 1 : 0) : orig[2], rc == EMRKC_OK ? zc_choice : orig[3], 0};
+  const int mode = zc_choice ? 1 : pairs ? 2 : 0;
+  const int v[5] = {rc == EMRKC_OK ? choice : orig[0], rc == EMRKC_OK ? flat : orig[1], rc == EMRKC_OK ? mode : orig[2],
+                    rc == EMRKC_OK ? zc_choice : orig[3], 0};
   set_variants(c, v);
   c->bdev.valid = false;  // the tables point into the state copy
   if (rc == EMRKC_OK && variants) get_variants(c, variants);
@@ -2994,7 +3013,8 @@ static int estimate_batch(emrkc_ctx *c, const emrkc_state *st, double *rho_F, do
 static int build_batch_tables(emrkc_ctx *c, const emrkc_state *st, double dt, const StepPlan &P) {
   uint64_t dtb;
   memcpy(&dtb, &dt, sizeof dtb);
-  const int shape_key = c->batch_shape + (c->batch_flat_head ? 3 : 0) + 8 * c->batch_march_zc;
+  const int shape_key =
+      c->batch_shape + (c->batch_flat_head ? 3 : 0) + 8 * c->batch_march_zc + (c->batch_pairs ? 1024 : 0);
   if (c->bdev.valid && c->bdev.dt_bits == dtb && c->bdev.V == st->V && c->bdev.z == st->z &&
       c->bdev.shape == shape_key)
     return EMRKC_OK;
@@ -3039,6 +3059,9 @@ static int build_batch_tables(emrkc_ctx *c, const emrkc_state *st, double dt, co
           b.ntx = (b.g.n0 + MX - 1) / MX;
           b.nty = (b.g.n1 + MY - 1) / MY;
           nt = b.ntx * b.nty * ((b.g.n2 + b.g.zc - 1) / b.g.zc);
+        } else if (k >= 2 && c->batch_pairs) {  // two tiles per block
+          b.g.inner_variant = 2;
+          nt = (grid_tiles(b.g, b.ntx, b.nty, c->batch_shape) + 1) / 2;
         } else {
           nt = grid_tiles(b.g, b.ntx, b.nty, c->batch_shape);
         }
@@ -3118,7 +3141,9 @@ static int enqueue_chunk_batch(emrkc_ctx *c, const emrkc_state *st, const StepPl
     TIMED(0, launch_head_batch(c->model, c->mixed, c->batch_flat_head ? kBatchFlatHead : c->batch_shape, H.tab, H.map,
                                H.nblocks, Ntot, n, strm));
     for (const BatchLaunch &B : c->bdev.inner[par])
-      if (B.nblocks) TIMED(1, launch_inner_batch(c->mixed, c->batch_shape, B.tab, B.map, B.nblocks, Ntot, strm));
+      if (B.nblocks)
+        TIMED(1, launch_inner_batch(c->mixed, c->batch_shape, c->batch_march_zc > 0 ? 1 : c->batch_pairs ? 2 : 0,
+                                    B.tab, B.map, B.nblocks, Ntot, strm));
   }
   double *X1 = c->d_V1;
   HIP_TRY(c, launch_copy_tick(L % 2 ? X1 : nullptr, (double *)st->V, Ntot, c->d_clock, L, strm));

@@ -200,8 +200,10 @@ uint32_t grid_tiles(const Grid &g, uint32_t &ntx, uint32_t &nty, int shape = 0);
 constexpr int kBatchFlatHead = 3;
 hipError_t launch_head_batch(int model, bool mixed, int shape, const BatchInst *tab, const uint16_t *map,
                              uint32_t nblocks, uint32_t Ntot, int step_off, hipStream_t st);
-hipError_t launch_inner_batch(bool mixed, int shape, const BatchInst *tab, const uint16_t *map, uint32_t nblocks,
-                              uint32_t Ntot, hipStream_t st);
+// mode: the tables' layout: 0 one tile per block, 1 z-marching columns for
+// the 3-D instances (their entries have inner_variant 1), 2 two tiles per block
+hipError_t launch_inner_batch(bool mixed, int shape, int mode, const BatchInst *tab, const uint16_t *map,
+                              uint32_t nblocks, uint32_t Ntot, hipStream_t st);
 hipError_t launch_init_state(int model, bool mixed, uint32_t N, double *V, void *z, ModelParams mp,
                              hipStream_t st);
 hipError_t launch_head(int model, bool mixed, const Mesh &mesh, const HeadArgs &a, hipStream_t st);

@@ -602,25 +602,36 @@ __device__ __forceinline__ void tile_origin(uint32_t ntx, uint32_t nty, int &x0,
 // memory latency instead of one per load); slots beyond the halo load its
 // last position again and store nothing.
 template <int DIM, int SH = 0>
+struct Halo {
+  using T = Tile<DIM, SH>;
+  static constexpr int NSL = (T::NS + kBlock - 1) / kBlock;
+  double v[NSL];
+  __device__ __forceinline__ void load(const double *__restrict__ u, const Grid &g, int x0, int y0, int z0) {
+#pragma unroll
+    for (int k = 0; k < NSL; ++k) {
+      const int r = min((int)threadIdx.x + k * kBlock, T::NS - 1);
+      const int hx = r % T::SX, hy = (r / T::SX) % T::SY, hz = r / (T::SX * T::SY);
+      const uint32_t gx = mirror_any(x0 + hx - 1, g.n0);
+      const uint32_t gy = mirror_any(y0 + hy - 1, g.n1);
+      const uint32_t gz = DIM == 3 ? mirror_any(z0 + hz - 1, g.n2) : 0u;
+      v[k] = gptr(u)[gx + g.n0 * (gy + g.n1 * gz)];
+    }
+  }
+  __device__ __forceinline__ void store(double *sU) const {
+#pragma unroll
+    for (int k = 0; k < NSL; ++k) {
+      const int r = (int)threadIdx.x + k * kBlock;
+      if (r < T::NS) sU[r] = v[k];
+    }
+  }
+};
+
+template <int DIM, int SH = 0>
 __device__ __forceinline__ void stage_halo(double *sU, const double *__restrict__ u, const Grid &g, int x0, int y0,
                                            int z0) {
-  using T = Tile<DIM, SH>;
-  constexpr int NSL = (T::NS + kBlock - 1) / kBlock;
-  double v[NSL];
-#pragma unroll
-  for (int k = 0; k < NSL; ++k) {
-    const int r = min((int)threadIdx.x + k * kBlock, T::NS - 1);
-    const int hx = r % T::SX, hy = (r / T::SX) % T::SY, hz = r / (T::SX * T::SY);
-    const uint32_t gx = mirror_any(x0 + hx - 1, g.n0);
-    const uint32_t gy = mirror_any(y0 + hy - 1, g.n1);
-    const uint32_t gz = DIM == 3 ? mirror_any(z0 + hz - 1, g.n2) : 0u;
-    v[k] = gptr(u)[gx + g.n0 * (gy + g.n1 * gz)];
-  }
-#pragma unroll
-  for (int k = 0; k < NSL; ++k) {
-    const int r = (int)threadIdx.x + k * kBlock;
-    if (r < T::NS) sU[r] = v[k];
-  }
+  Halo<DIM, SH> h;
+  h.load(u, g, x0, y0, z0);
+  h.store(sU);
 }
 
 // Own node of this thread in the tile: global index (or false when outside
@@ -1437,21 +1448,62 @@ __device__ __forceinline__ void inner_tile(const BatchInst &I, uint32_t tile, do
   gptr(a.out)[i] = inner_point(a, sU[c], Fu, pt);
 }
 
-// Inner stage of the batch: LDS tiles, or for 3-D instances whose table
-// entry says so (inner_variant 1) z-marching columns of g.zc planes.
-template <bool MIXED, int SH>
+// Two tiles of an instance per block (tiles 2 pair and 2 pair + 1): the
+// operands and halos of both are loaded before one barrier, so each wave
+// keeps twice the loads in flight and the instance lookup serves two tiles.
+template <bool MIXED, int DIM, int SH>
+__device__ __forceinline__ void inner_tile_pair(const BatchInst &I, uint32_t pair, double *sU) {
+  using T = Tile<DIM, SH>;
+  const uint32_t ntz = DIM == 3 ? (I.g.n2 + T::TZ - 1) / T::TZ : 1u;
+  const uint32_t ta = 2 * pair;
+  const bool hasb = ta + 1 < I.ntx * I.nty * ntz;
+  int xa, ya, za, xb, yb, zb;
+  tile_xyz<DIM, SH>(I, ta, xa, ya, za);
+  tile_xyz<DIM, SH>(I, hasb ? ta + 1 : ta, xb, yb, zb);
+  const InnerArgs &a = I.in;
+  uint32_t ila = 0, ilb = 0;
+  int ca = 0, cb = 0;
+  const bool owna = tile_node<DIM, SH>(I.g, xa, ya, za, ila, ca);
+  const bool ownb = tile_node<DIM, SH>(I.g, xb, yb, zb, ilb, cb) && hasb;
+  InnerPoint pa{0.0, 0.0, 0.0, 0.0}, pb{0.0, 0.0, 0.0, 0.0};
+  if (owna) pa = load_point<MIXED>(a, I.off + ila);
+  if (ownb) pb = load_point<MIXED>(a, I.off + ilb);
+  Halo<DIM, SH> ha, hb;
+  ha.load(a.t.uprev + I.off, I.g, xa, ya, za);
+  if (hasb) hb.load(a.t.uprev + I.off, I.g, xb, yb, zb);
+  ha.store(sU);
+  if (hasb) hb.store(sU + T::NS);
+  __syncthreads();
+  const auto out = gptr(a.out + I.off);
+  if (owna) out[ila] = inner_point(a, sU[ca], lds_stencil<DIM, SH>(sU, I.g, ca), pa);
+  if (ownb) out[ilb] = inner_point(a, sU[T::NS + cb], lds_stencil<DIM, SH>(sU + T::NS, I.g, cb), pb);
+}
+
+// Inner stage of the batch, by the mode the tables were built for: LDS
+// tiles, one per block (MODE 0) or two (MODE 2), or (MODE 1) z-marching
+// columns of g.zc planes for the 3-D instances, whose table entries have
+// inner_variant 1, and tiles for the others.  Each mode is its own kernel:
+// the registers of one form would lower the occupancy of another.
+template <bool MIXED, int SH, int MODE>
 __global__ __launch_bounds__(kBlock) void k_inner_batch(const BatchInst *__restrict__ tab,
                                                         const uint16_t *__restrict__ map) {
-  constexpr int NL = BatchLds<SH>::NS > 3 * MPL ? BatchLds<SH>::NS : 3 * MPL;
+  constexpr int NT = (MODE == 2 ? 2 : 1) * BatchLds<SH>::NS;
+  constexpr int NL = MODE == 1 && NT < 3 * MPL ? 3 * MPL : NT;
   __shared__ double lds[NL];
   const uint32_t lb = xcd_block(blockIdx.x, gridDim.x);
   BatchInst I = tab[batch_slot(map, lb)];
-  if (I.g.dim == 3 && I.g.inner_variant == 1)
+  if (MODE == 2) {
+    if (I.g.dim == 3)
+      inner_tile_pair<MIXED, 3, SH>(I, lb - I.tile0, lds);
+    else
+      inner_tile_pair<MIXED, 2, SH>(I, lb - I.tile0, lds);
+  } else if (MODE == 1 && I.g.dim == 3 && I.g.inner_variant == 1) {
     inner_march_col<MIXED>(I.in, I.g, I.off, lb - I.tile0, I.ntx, I.nty, (double (*)[MPL])lds);
-  else if (I.g.dim == 3)
+  } else if (I.g.dim == 3) {
     inner_tile<MIXED, 3, SH>(I, lb - I.tile0, lds);
-  else
+  } else {
     inner_tile<MIXED, 2, SH>(I, lb - I.tile0, lds);
+  }
 }
 
 __global__ void k_clock_set(Clock *c, int64_t step, double t0) {
@@ -2269,22 +2321,30 @@ hipError_t launch_head_batch(int model, bool mixed, int shape, const BatchInst *
 #undef CALL
 }
 
-template <int SH>
-static hipError_t inner_batch_launch(bool mixed, const BatchInst *tab, const uint16_t *map, uint32_t nblocks,
-                                     hipStream_t st) {
+template <int SH, int MODE>
+static hipError_t inner_batch_mode(bool mixed, const BatchInst *tab, const uint16_t *map, uint32_t nblocks,
+                                   hipStream_t st) {
   if (mixed)
-    EMRKC_LAUNCH((k_inner_batch<true, SH>), dim3(nblocks), dim3(kBlock), 0, st, tab, map);
+    EMRKC_LAUNCH((k_inner_batch<true, SH, MODE>), dim3(nblocks), dim3(kBlock), 0, st, tab, map);
   else
-    EMRKC_LAUNCH((k_inner_batch<false, SH>), dim3(nblocks), dim3(kBlock), 0, st, tab, map);
+    EMRKC_LAUNCH((k_inner_batch<false, SH, MODE>), dim3(nblocks), dim3(kBlock), 0, st, tab, map);
   return hipGetLastError();
 }
 
-hipError_t launch_inner_batch(bool mixed, int shape, const BatchInst *tab, const uint16_t *map, uint32_t nblocks,
-                              uint32_t Ntot, hipStream_t st) {
+template <int SH>
+static hipError_t inner_batch_launch(bool mixed, int mode, const BatchInst *tab, const uint16_t *map,
+                                     uint32_t nblocks, hipStream_t st) {
+  if (mode == 1) return inner_batch_mode<SH, 1>(mixed, tab, map, nblocks, st);
+  if (mode == 2) return inner_batch_mode<SH, 2>(mixed, tab, map, nblocks, st);
+  return inner_batch_mode<SH, 0>(mixed, tab, map, nblocks, st);
+}
+
+hipError_t launch_inner_batch(bool mixed, int shape, int mode, const BatchInst *tab, const uint16_t *map,
+                              uint32_t nblocks, uint32_t Ntot, hipStream_t st) {
   (void)Ntot;
-  if (shape == 1) return inner_batch_launch<1>(mixed, tab, map, nblocks, st);
-  if (shape == 2) return inner_batch_launch<2>(mixed, tab, map, nblocks, st);
-  return inner_batch_launch<0>(mixed, tab, map, nblocks, st);
+  if (shape == 1) return inner_batch_launch<1>(mixed, mode, tab, map, nblocks, st);
+  if (shape == 2) return inner_batch_launch<2>(mixed, mode, tab, map, nblocks, st);
+  return inner_batch_launch<0>(mixed, mode, tab, map, nblocks, st);
 }
 
 template <template <class> class Model>

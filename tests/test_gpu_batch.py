@@ -67,10 +67,12 @@ def test_batch_equals_single_runs_bitwise_and_graph_equals_eager(ens):
     V3, z3, _, _ = run_batch(cfgs, (rF, rS), 41, chunks=[3, 32, 6])
     assert np.array_equal(V, V2) and np.array_equal(z, z2)
     assert np.array_equal(V, V3) and np.array_equal(z, z3)
-    # every tile shape of the batched kernels, the flat batched head, and
+    # every tile shape of the batched kernels, the flat batched head,
     # z-marching columns for the 3-D instances' inner stages (11 planes:
-    # ragged columns of 4 and 3 planes, whole columns) give the same bits
-    for shape in (1, 2, (0, 1, 0, 0, 0), (2, 1, 0, 0, 0), (1, 1, 1, 4, 0), (0, 0, 1, 64, 0), (2, 1, 1, 3, 0)):
+    # ragged columns of 4 and 3 planes, whole columns) and two tiles per
+    # block for the inner stages give the same bits
+    for shape in (1, 2, (0, 1, 0, 0, 0), (2, 1, 0, 0, 0), (1, 1, 1, 4, 0), (0, 0, 1, 64, 0), (2, 1, 1, 3, 0),
+                  (1, 1, 2, 0, 0), (0, 0, 2, 0, 0), (2, 1, 2, 0, 0)):
         V4, z4, _, _ = run_batch(cfgs, (rF, rS), 41, shape=shape)
         assert np.array_equal(V, V4) and np.array_equal(z, z4), shape
     # single-instance contexts with the same masks
@@ -166,13 +168,13 @@ def test_batch_autotune(ens):
     V0, z0 = sim.V.clone(), sim.z.clone()
     v = E.emrkc_autotune(sim.ctx, sim.state, cfgs[0]["dt"], reps=2)
     assert v[0] in (0, 1, 2) and v[1] in (0, 1) and v[4] == 0
-    assert (v[2], v[3]) in ((0, 0), (1, 4), (1, 8), (1, 64))
+    assert (v[2], v[3]) in ((0, 0), (2, 0), (1, 4), (1, 8), (1, 64))
     assert torch.equal(sim.V, V0) and torch.equal(sim.z, z0)
     E.emrkc_step(sim.ctx, sim.state, cfgs[0]["dt"], 20)
     torch.cuda.synchronize()
     assert np.array_equal(sim.V.cpu().numpy(), V)
     for bad in [(3, 0, 0, 0, 0), (0, 2, 0, 0, 0), (0, 0, 1, 0, 0), (0, 0, 0, 4, 0), (0, 0, 1, 65, 0),
-                (0, 0, 2, 4, 0)]:
+                (0, 0, 2, 4, 0), (0, 0, 3, 0, 0)]:
         with pytest.raises(E.EmrkcError):
             E.emrkc_set_variants(sim.ctx, bad)
     sim.close()
@@ -201,14 +203,16 @@ def test_full_ensemble_in_the_bench_configuration():
     torch.cuda.synchronize()
     V = sim.V.cpu().numpy().copy()
     assert off[-1] == V.size and V.size > 6_900_000
-    # the 3-D instances' inner stages in z-marching columns: the same bits
-    sim2 = E.simulation_from_batch(cfgs, rho=(rF, rS))
-    E.emrkc_set_variants(sim2.ctx, (1, 1, 1, 64, 0))
-    E.emrkc_init_state(sim2.ctx, sim2.state)
-    E.emrkc_step(sim2.ctx, sim2.state, dt, nsteps)
-    torch.cuda.synchronize()
-    assert torch.equal(sim2.V, sim.V) and torch.equal(sim2.z, sim.z)
-    sim2.close()
+    # the 3-D instances' inner stages in z-marching columns, and two tiles
+    # per block for the inner stages: the same bits
+    for v in [(1, 1, 1, 64, 0), (1, 1, 2, 0, 0)]:
+        sim2 = E.simulation_from_batch(cfgs, rho=(rF, rS))
+        E.emrkc_set_variants(sim2.ctx, v)
+        E.emrkc_init_state(sim2.ctx, sim2.state)
+        E.emrkc_step(sim2.ctx, sim2.state, dt, nsteps)
+        torch.cuda.synchronize()
+        assert torch.equal(sim2.V, sim.V) and torch.equal(sim2.z, sim.z), v
+        sim2.close()
     sizes = [off[k + 1] - off[k] for k in range(len(cfgs))]
     sample = sorted(range(len(cfgs)), key=lambda k: sizes[k])[:3]
     for k, cfg in enumerate(cfgs):
