@@ -401,10 +401,12 @@ def main():
                                  % ("mrkc_" if args.method == "mrkc" else "", dom, cfg["name"]))
         traffic = None
         valu = None
+        tr_ok = None  # the counters file, when taken on these sources
         if args.method in ("emrkc", "mrkc") and os.path.exists(prof_path):
             tr = json.load(open(prof_path))
             ent = tr.get("by_shape", {}).get("%d,%d,%d" % (variants[0], variants[1], variants[4]))
             if tr.get("kernel_source_hash") == kernel_hash() and ent is not None:
+                tr_ok = tr
                 traffic = ent.get("bytes_per_launch")
                 if "valu_busy" in ent:
                     # the FP64 vector ALU side of the same kernel (rocprof
@@ -458,7 +460,8 @@ def main():
                                          if split else "last inner stage and the outer V update",
                                          "achieved_GBs": round(inner_gbs, 1) if inner_gbs else None,
                                          "frac": round(inner_gbs / HBM_PEAK_GBS, 4) if inner_gbs else None,
-                                         "bytes_per_launch": ib}}
+                                         "bytes_per_launch": ib,
+                                         "traffic": counted(tr_ok, "inner", variants)}}
 
         mixed = None
         if not args.no_mixed and args.method == "emrkc":
@@ -496,6 +499,10 @@ def main():
                 if ibm:
                     inner_m = {"launch_ms": round(pm["inner"][0], 5), "bytes_per_launch": ibm * N,
                                "achieved_GBs": round(ibm * N / (pm["inner"][0] * 1e-3) / 1e9, 1)}
+            if head_m is not None:
+                head_m["traffic"] = counted(tr_ok, "mixed", variants_m, "head")
+            if inner_m is not None:
+                inner_m["traffic"] = counted(tr_ok, "mixed", variants_m, "inner")
             mixed = {"value": value_m, "speedup_vs_fp64": round(value_m / value, 3), "kernel_shapes": variants_m,
                      "head_kernel": head_m, "inner_kernel": inner_m,
                      "s_m": list(sm_m),
@@ -644,6 +651,17 @@ def bench_imexrl(args, cfg, N, tet, stream, E, torch):
                                    "steps" % (cfg["name"], mesh, N, cfg["model"], cfg["dt"], cfg["T"], job.nsim),
                        "method": "imexrl", "cg_iterations_per_simulation": iters, "cg_tolerance": 1e-13},
             "roofline": roof, "cpu_baseline": cpu}
+
+
+def counted(tr, part, variants, sub=None):
+    """HBM bytes per launch from the committed counters (None when they were
+    not taken on these kernel sources or for these kernel shapes)."""
+    if tr is None:
+        return None
+    ent = tr.get(part, {}).get("%d,%d,%d" % (variants[0], variants[1], variants[4]))
+    if ent is not None and sub is not None:
+        ent = ent.get(sub)
+    return ent.get("bytes_per_launch") if ent else None
 
 
 def kernel_hash():
