@@ -405,34 +405,53 @@ int emrkc_profile_imexrl(emrkc_ctx *ctx, emrkc_state *state, double dt, int64_t 
  * SIMD (fewer registers), 5 = flat: one node per thread in index order,
  * stencil operands read through the caches (the default on 3-D grids), 6 =
  * the flat head compiled for at least 7 resident waves per SIMD (mixed
- * precision only; EMRKC_EUNSUPPORTED in FP64, where it would spill).
+ * precision only; EMRKC_EUNSUPPORTED in FP64, where it would spill); 7 and
+ * 8 = the split stage (m >= 2): a pointwise head (exponential Euler, ionic
+ * model, outer z recurrence and S_V, no stencil), with the first two inner
+ * stages in one column kernel of `head planes` planes (7) or the first
+ * inner stage as one more launch of the inner kernel (8, head planes 0).
  * Inner kernel: 0 = 3-D tiles, 1 = z-marching columns.  Planes per column
- * in [1, 64] and at most n[2] for the column kernels, else 0.  Other meshes have
- * one head and one inner shape (entries 0..3 are 0), and so do mRKC
- * contexts (flat kernels, no fused kernel).  Batch contexts: variants[0] is
- * the tile shape of the batched head and inner kernels (0: 16x4x4 in 3-D,
- * 64x4 in 2-D; 1: 32x4x2 / 32x8; 2: 8x8x4 / 128x2), variants[1] = 1 makes
- * the head flat (blocks of 256 consecutive nodes of an instance, the
- * inner stages keep the tiles), the others are 0.
+ * in [1, 64] and at most n[2] for the column kernels, else 0.
+ * On 2-D structured grids (emRKC, single contexts) the head is the 2-D tile
+ * kernel (entries 0, 1 and 3 are 0) and the inner kernel is 0 = 2-D tiles,
+ * one launch per inner stage; 2 = all inner stages of an outer stage in one
+ * launch (2 <= m <= 9; 16x16 tiles, u_1, V and S_V staged with halos of up
+ * to m nodes); 3 = the same with 8x8 tiles; 4 = as 3 and, when s == 1, the
+ * head of the next step in the same kernel (one launch per step); with m
+ * outside [2, 9] the separate launches are used.  Shapes 2-4 exclude fused.
+ * Other meshes have one head and one inner shape (entries 0..3 are 0), and
+ * so do mRKC contexts (flat kernels, no fused kernel).  Batch contexts:
+ * variants[0] is the tile shape of the batched head and inner kernels (0:
+ * 16x4x4 in 3-D, 64x4 in 2-D; 1: 32x4x2 / 32x8; 2: 8x8x4 / 128x2),
+ * variants[1] = 1 makes the head flat (blocks of 256 consecutive nodes of
+ * an instance), variants[2] selects the inner stages' layout: 0 = one tile
+ * per block, 1 = z-marching columns of variants[3] planes (1..64) for the
+ * 3-D instances (tiles for the others), 2 = two tiles per block;
+ * variants[3] is 0 unless variants[2] == 1, variants[4] is 0.
  * fused = 1 (structured grids, single contexts): when s == 1 and m >= 2,
  * the last inner stage of each step and the head of the next are one
  * kernel on 3-D or 2-D tiles.
  * Every variant gives bit-identical results; only speed differs. */
 
 /* Times the candidate shapes for a few steps each (`reps` timed steps, on a
- * copy of `state`, which is not modified) and keeps the fastest head and
- * inner kernels, then the fused kernel if a step with it is faster.  A
- * candidate replaces an earlier one only when at least 3% faster.
- * Candidates: the flat head (first, the default; then, in the mixed
- * precision, its 7-wave form), tiles (three register budgets for the head), and
- * columns of
- * 2, 3, 4, 8, 16 or 32 planes that leave at least 256 blocks; for a batch,
- * the three tile shapes, then the flat head with the chosen shape,
- * compared by the time per step.  Needs the
- * radii (the stage plan at dt decides whether the fused kernel applies).  Writes the choice to `variants`
- * (int[5]) when non-NULL.  Allocates a temporary copy of the state;
- * synchronises the stream.  Returns the fixed choice where nothing can be
- * tuned. */
+ * copy of `state`, which is not modified; every timing is the faster of two
+ * repetitions) and keeps the fastest.  3-D grids: the head and inner kernels
+ * by their own launch times (the flat head and the 3-D tiles first: a later
+ * candidate must be at least 3% faster), then the split stage (shape 7 with
+ * columns of 4..64 planes, shape 8 with each inner candidate, chosen by the
+ * inner launches' time) against the separate kernels by the time per step
+ * (at least 1% faster), then the fused kernel (3%).  Head candidates: the
+ * flat head (in the mixed precision also its 7-wave form), tiles (three
+ * register budgets), and columns of 2, 3, 4, 8, 16 or 32 planes that leave
+ * at least 256 blocks; inner candidates: tiles and those columns.  2-D
+ * grids with 2 <= m <= 9: the 2-D shapes 0, 2, 3, 4 (4 when s == 1) and the
+ * fused kernel by the wall time per step of eagerly launched steps.  A
+ * batch: the three tile shapes by the time per step, the flat head by the
+ * head's time, then two tiles per block and z-marching columns of 4, 8 or
+ * 64 planes by the inner stage's time.  Needs the radii (the stage plan at
+ * dt decides which shapes apply).  Writes the choice to `variants` (int[5])
+ * when non-NULL.  Allocates a temporary copy of the state; synchronises the
+ * stream.  Returns the fixed choice where nothing can be tuned. */
 int emrkc_autotune(emrkc_ctx *ctx, const emrkc_state *state, double dt, int reps, int *variants);
 
 int emrkc_get_variants(const emrkc_ctx *ctx, int *variants);   /* int[5] */
