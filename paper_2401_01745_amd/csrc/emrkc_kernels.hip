@@ -898,17 +898,25 @@ __global__ __launch_bounds__(kBlock) void k_inner12_march(Inner12Args a, Grid g,
   const double *__restrict__ V = a.V;
   auto vplane = [&](int z) { return (size_t)mirror2(z, g.n2) * plane; };
   auto uplane = [&](int z) { return (size_t)mirror_any(z, g.n2) * plane; };
-  auto stage_v = [&](int z) {
-    double *dst = vring[(z + 8) % 4];
+  // Every load is unconditional (inactive slots read offset 0 of the plane,
+  // threads beyond the grid the nearest node; nothing they load is used),
+  // so that the prologue's loads are all in flight together and the
+  // compiler can count the loads it waits for.
+  auto load_v = [&](int z, double *v) {
     const size_t pz = vplane(z);
 #pragma unroll
+    for (int k = 0; k < VSLOT; ++k) v[k] = V[pz + voff[k]];
+  };
+  auto put_v = [&](int z, const double *v) {
+    double *dst = vring[(z + 8) % 4];
+#pragma unroll
     for (int k = 0; k < VSLOT; ++k)
-      if (vact[k]) dst[threadIdx.x + k * kBlock] = V[pz + voff[k]];
+      if (vact[k]) dst[threadIdx.x + k * kBlock] = v[k];
   };
   auto load_svh = [&](int z, double *sv) {
     const size_t pz = uplane(z);
 #pragma unroll
-    for (int k = 0; k < MSLOT; ++k) sv[k] = uact[k] ? load_sv(a.SV, MIXED, pz + uoff[k]) : 0.0;
+    for (int k = 0; k < MSLOT; ++k) sv[k] = load_sv(a.SV, MIXED, pz + uoff[k]);
   };
   // u_1 on the halo plane p from V planes p-1, p, p+1
   auto form_u1 = [&](int p, const double *sv) {
@@ -925,35 +933,35 @@ __global__ __launch_bounds__(kBlock) void k_inner12_march(Inner12Args a, Grid g,
       dst[threadIdx.x + k * kBlock] = first_inner(a.mu1_eta, vc[c], Fv, sv[k]);
     }
   };
-  double sv[MSLOT];
-  stage_v(zb - 2);
-  stage_v(zb - 1);
-  stage_v(zb);
-  stage_v(zb + 1);
-  load_svh(zb - 1, sv);
-  __syncthreads();
-  form_u1(zb - 1, sv);
-  load_svh(zb, sv);
-  form_u1(zb, sv);
-  // operands of the first iteration
-  double vpre[VSLOT];
-  {
-    const size_t pz = vplane(zb + 2);
-#pragma unroll
-    for (int k = 0; k < VSLOT; ++k) vpre[k] = vact[k] ? V[pz + voff[k]] : 0.0;
-  }
+  // the prologue: V planes zb - 2 .. zb + 2, the halo's S_V of planes
+  // zb - 1 .. zb + 1 and the first node's operands, all loaded at once
+  double v0[VSLOT], v1[VSLOT], v2[VSLOT], v3[VSLOT], vpre[VSLOT];
+  double svm[MSLOT], sv0[MSLOT], sv[MSLOT];
+  load_v(zb - 2, v0);
+  load_v(zb - 1, v1);
+  load_v(zb, v2);
+  load_v(zb + 1, v3);
+  load_v(zb + 2, vpre);
+  load_svh(zb - 1, svm);
+  load_svh(zb, sv0);
   load_svh(zb + 1, sv);
   const int lx = threadIdx.x % MX, ly = threadIdx.x / MX;
   const uint32_t gx = (uint32_t)(x0 + lx), gy = (uint32_t)(y0 + ly);
   const bool own = gx < g.n0 && gy < g.n1;
   const int c = (ly + 1) * MSX + (lx + 1);
   const int cv = (ly + 2) * VSX + (lx + 2);
-  uint32_t i = gx + g.n0 * gy + plane * (uint32_t)zb;
-  double sv_own = 0.0, v2_own = 0.0;
-  if (own) {
-    sv_own = load_sv(a.SV, MIXED, i);
-    if (a.last && !a.t.j1) v2_own = a.Vin2[i];
-  }
+  // the node whose operands are loaded: this thread's own node, or the
+  // nearest node of the grid for threads beyond its edge
+  uint32_t i = min(gx, g.n0 - 1) + g.n0 * min(gy, g.n1 - 1) + plane * (uint32_t)zb;
+  const bool need_v2 = a.last && !a.t.j1;
+  double sv_own = load_sv(a.SV, MIXED, i), v2_own = need_v2 ? a.Vin2[i] : 0.0;
+  put_v(zb - 2, v0);
+  put_v(zb - 1, v1);
+  put_v(zb, v2);
+  put_v(zb + 1, v3);
+  __syncthreads();
+  form_u1(zb - 1, svm);
+  form_u1(zb, sv0);
   __syncthreads();  // the pre-loop's u_1 planes read V plane zb - 2, whose slot is refilled next
   for (int z = zb; z < ze; ++z, i += plane) {
     {
@@ -967,14 +975,10 @@ __global__ __launch_bounds__(kBlock) void k_inner12_march(Inner12Args a, Grid g,
     for (int k = 0; k < MSLOT; ++k) svh[k] = sv[k];
     const double sv_cur = sv_own, v2_cur = v2_own;
     if (z + 1 < ze) {
-      const size_t pz = vplane(z + 3);
-#pragma unroll
-      for (int k = 0; k < VSLOT; ++k) vpre[k] = vact[k] ? V[pz + voff[k]] : 0.0;
+      load_v(z + 3, vpre);
       load_svh(z + 2, sv);
-      if (own) {
-        sv_own = load_sv(a.SV, MIXED, i + plane);
-        if (a.last && !a.t.j1) v2_own = a.Vin2[i + plane];
-      }
+      sv_own = load_sv(a.SV, MIXED, i + plane);
+      if (need_v2) v2_own = a.Vin2[i + plane];
     }
     __syncthreads();
     form_u1(z + 1, svh);
