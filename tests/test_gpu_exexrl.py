@@ -72,10 +72,12 @@ def test_exexrl_shell_parity(E):
 
 def test_emrkc_first_order_against_gpu_reference(E):
     """Relative L2 error of V at T = 4 ms (a wave in the slab) for emRKC at
-    dt = 0.05, 0.025, 0.0125 ms against EXEX-RL at 1e-4 ms: the error falls
-    at least at first order per halving (the wave front makes the coarse
-    steps pre-asymptotic: the oracle shows slopes between 1 and 2 here and
-    a floor near 4e-3 set by the reference's own first-order error)."""
+    dt = 0.05, 0.025, 0.0125 ms against EXEX-RL at 1e-4 ms: the method is
+    first order in dt, so each halving must cut the error at least by the
+    first-order factor (with 20% slack for the reference's own error, a
+    floor near 4e-3); a faster drop at the coarse steps is the wave front's
+    pre-asymptotic behaviour (the oracle shows slopes between 1 and 2 here),
+    not a failure, so no upper bound is placed on it."""
     import torch
     cfg = small_config("c2_3d_crn", (81, 41, 11), model="TTP_SURR")
     T = 4.0
@@ -94,5 +96,5 @@ def test_emrkc_first_order_against_gpu_reference(E):
         errs.append(rel_errors(sim.V.cpu().numpy(), Vref)[0])
         sim.close()
     slopes = np.diff(np.log(errs)) / np.diff(np.log(dts))
-    assert np.all((slopes > 0.8) & (slopes < 2.5)), (errs, slopes)
+    assert np.all(slopes > 0.8), (errs, slopes)
     assert errs[-1] < 0.05
