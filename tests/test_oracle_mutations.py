@@ -137,11 +137,11 @@ CASES = [
      [T_var.test_progressive_scalar_closed_form, T_var.test_progressive_equals_standard_on_the_monodomain_split]),
     ("rho_every_at_step_zero", "oracle.emrkc", "if rho_every > 0 and n > 0 and n % rho_every == 0:",
      "if rho_every > 0 and n % rho_every == 0:",
-     [T_var.test_rho_every_schedule_and_warm_start, T_var.test_rho_every_linear_model_warm_start]),
+     [T_var.test_rho_every_estimates_at_the_scheduled_states, T_var.test_rho_every_linear_model_warm_start]),
     ("rho_every_cold_start", "oracle.emrkc",
      'compute_rho(tn, y, prob.f_F, rho_state["vF"], rho_state["rF"])',
      'compute_rho(tn, y, prob.f_F, rho_state["vF"])',
-     [T_var.test_rho_every_schedule_and_warm_start, T_var.test_rho_every_linear_model_warm_start]),
+     [T_var.test_rho_every_estimates_at_the_scheduled_states, T_var.test_rho_every_linear_model_warm_start]),
     ("mrkc_outer_count", "oracle.mrkc", "return rkc_iteration(tn, yn, dt, fbar, s, eps)",
      "return rkc_iteration(tn, yn, dt, fbar, m, eps)",
      [T_mrkc.test_scalar_test_equation_closed_form, lambda: T_mrkc.test_linear_model_matrix_function((3, 3))]),
