@@ -74,13 +74,23 @@ extern "C" {
  * EMRKC_EAGER — launch every kernel directly, never from a captured HIP graph;
  * EMRKC_FUSE — use the fused kernel (last inner stage + next head) where it
  *   applies, without asking the autotuner;
- * EMRKC_FLAT — structured grids use the flat (untiled) kernels only.
+ * EMRKC_FLAT — structured grids use the flat (untiled) kernels only;
+ * EMRKC_Z_PLANES — emrkc_step (and the autotuner's and profiler's steps)
+ *   keep z in the state's component planes while stepping.  Without it, a
+ *   single emRKC context without rho_every whose head is not a z-marching
+ *   one (3-D kernel shapes 1 and 2) converts z on entry into a library
+ *   buffer that holds each block of 256 nodes' components contiguously
+ *   (n_z x 256 values per block), steps on that buffer and converts back
+ *   before it returns; the buffer (the size of z, rounded up to whole
+ *   blocks) is allocated on first use, and where that allocation fails the
+ *   planes are kept.  emrkc_step_noalloc always keeps the planes.
  * The environment variables EMRKC_EAGER and EMRKC_FUSE (any value) act like
  * the flags for every context; EMRKC_VERBOSE makes emrkc_autotune print its
  * timings to stderr. */
 #define EMRKC_EAGER 2u
 #define EMRKC_FUSE 4u
 #define EMRKC_FLAT 8u
+#define EMRKC_Z_PLANES 0x400u
 /* Stepping variants (flags):
  * EMRKC_PROGRESSIVE — the progressive splitting of the auxiliary problem
  *   (remark after eq. auxp_exp): the inner problem starts from y and carries
@@ -439,8 +449,10 @@ int emrkc_profile_imexrl(emrkc_ctx *ctx, emrkc_state *state, double dt, int64_t 
  * by their own launch times (the flat head and the 3-D tiles first: a later
  * candidate must be at least 3% faster), then the split stage (shape 7 with
  * columns of 4..64 planes, shape 8 with each inner candidate, chosen by the
- * inner launches' time) against the separate kernels by the time per step
- * (at least 1% faster), then the fused kernel (3%).  Head candidates: the
+ * inner launches' time) against the separate kernels: where the summed
+ * launch times put the split within 3% of them, the two run whole steps
+ * head to head (alternating, fastest of three) and the faster is kept; then
+ * the fused kernel (3%).  Head candidates: the
  * flat head (in the mixed precision also its 7-wave form), tiles (three
  * register budgets), and columns of 2, 3, 4, 8, 16 or 32 planes that leave
  * at least 256 blocks; inner candidates: tiles and those columns.  2-D

@@ -150,6 +150,10 @@ struct emrkc_ctx {
   double m_raw[2] = {0, 0}, m_nv[2] = {0, 0};
   int64_t last_est_step = -1; // state step of the last re-estimate by emrkc_step
   void *d_z1 = nullptr;
+  // z in blocks of kZBlock nodes while emrkc_step runs the pointwise head
+  // (allocated on first use; zb_run: the enqueued heads address it)
+  void *d_zb = nullptr;
+  bool zb_run = false;
   Clock *d_clock = nullptr;
   // emrkc_step_noalloc: the device the context was created on, the device
   // address of that device's scratch array (null if it could not be
@@ -421,7 +425,7 @@ static void free_ctx(emrkc_ctx *c) {
   for (auto &kv : c->graphs) (void)hipGraphExecDestroy(kv.second);
   c->graphs.clear();
   void *ptrs[] = {c->d_mask, c->d_ell_col, c->d_ell_w64, c->d_ell_w32, c->d_V1, c->d_U[0], c->d_U[1],
-                  c->d_U[2], c->d_SV, c->d_SV2,   c->d_z1,      c->d_clock,   c->d_partials, c->d_result, c->d_flag,
+                  c->d_U[2], c->d_SV, c->d_SV2,   c->d_z1,      c->d_zb,      c->d_clock,   c->d_partials, c->d_result, c->d_flag,
                   c->d_vF[0], c->d_vF[1], c->d_vS[0], c->d_vS[1], c->d_zV,
                   c->d_W[0], c->d_W[1], c->d_Y, c->d_FY, c->d_Wv, c->d_FW,
                   c->d_mv[0][0], c->d_mv[0][1], c->d_mv[1][0], c->d_mv[1][1], c->d_mpart, c->d_ML, c->d_cgq, c->d_Dsum, c->d_cgs, c->d_cgp2, c->d_cgpart};
@@ -794,8 +798,13 @@ static HeadArgs make_head(emrkc_ctx *c, const StepPlan &P, double dt, int j, int
   h.m_is_one = P.m == 1;
   h.progressive = c->progressive ? 1 : 0;
   h.cm = P.cci[P.m];
+  h.z_aos = c->zb_run ? 1 : 0;
   return h;
 }
+
+// The z the enqueued heads address: the caller's, or the block buffer while
+// emrkc_step holds z in blocks (the pointwise head only).
+static void *zstate(const emrkc_ctx *c, const emrkc_state *st) { return c->zb_run ? c->d_zb : st->z; }
 
 static TailArgs make_stage(const StepPlan &P, double dt, int j, int k) {
   TailArgs t{};
@@ -833,7 +842,7 @@ static int enqueue_step_generic(emrkc_ctx *c, const emrkc_state *st, const StepP
                                 int64_t tick_by, hipStream_t strm, KernelTimer *tm) {
   const int s = P.s, m = P.m;
   double *X[2] = {(double *)st->V, c->d_V1};
-  void *Z[2] = {st->z, c->d_z1};
+  void *Z[2] = {zstate(c, st), c->d_z1};
   auto vidx = [&](int j) { return j == 0 ? 0 : (j < s ? j % 2 : 0); };
   auto zidx = [&](int j) { return j == 0 ? 0 : (j < s ? j % 2 : 0); };
   const bool final_copy = (m == 1) && (vidx(s - 1) == 0);
@@ -917,7 +926,7 @@ static int enqueue_step_split(emrkc_ctx *c, const emrkc_state *st, const StepPla
                               int64_t tick_by, hipStream_t strm, KernelTimer *tm) {
   const int s = P.s, m = P.m;
   double *X[2] = {(double *)st->V, c->d_V1};
-  void *Z[2] = {st->z, c->d_z1};
+  void *Z[2] = {zstate(c, st), c->d_z1};
   auto vidx = [&](int j) { return j == 0 ? 0 : (j < s ? j % 2 : 0); };
   const bool final_copy = m == 2 && vidx(s - 1) == 0;
   for (int j = 1; j <= s; ++j) {
@@ -967,7 +976,7 @@ static int enqueue_chunk_split_s1m2(emrkc_ctx *c, const emrkc_state *st, const S
   for (int n = 0; n < L; ++n) {
     HeadArgs h = make_head(c, P, dt, 1, n);
     h.Vin = X[n % 2];
-    h.zin = h.zout = st->z;
+    h.zin = h.zout = zstate(c, st);
     h.uout = nullptr;
     TIMED(0, launch_head_pw(c->model, c->mixed, c->mesh, h, strm));
     Inner12Args a = make_inner12(c, P, dt, 1, X[n % 2], nullptr);
@@ -1016,7 +1025,7 @@ static int enqueue_chunk_inner_all(emrkc_ctx *c, const emrkc_state *st, const St
                                    hipStream_t strm, KernelTimer *tm) {
   const int s = P.s;
   double *X[2] = {(double *)st->V, c->d_V1};
-  void *Z[2] = {st->z, c->d_z1};
+  void *Z[2] = {zstate(c, st), c->d_z1};
   if (step2d_mode(c, P)) {
     double *Ub[2] = {c->d_U[0], c->d_U[1]};
     void *S[2] = {c->d_SV, c->d_SV2};
@@ -1024,7 +1033,7 @@ static int enqueue_chunk_inner_all(emrkc_ctx *c, const emrkc_state *st, const St
       return fail(c, EMRKC_EINVAL, "one-kernel 2-D step: a u_1 or S_V work buffer is missing");
     HeadArgs h = make_head(c, P, dt, 1, 0);
     h.Vin = X[0];
-    h.zin = h.zout = st->z;
+    h.zin = h.zout = zstate(c, st);
     h.SV = S[0];
     h.uout = Ub[0];
     TIMED(0, launch_head(c->model, c->mixed, c->mesh, h, strm));
@@ -1035,7 +1044,7 @@ static int enqueue_chunk_inner_all(emrkc_ctx *c, const emrkc_state *st, const St
       a.SV = S[n % 2];
       a.out = X[(n + 1) % 2];
       HeadArgs hn = make_head(c, P, dt, 1, n + 1);
-      hn.zin = hn.zout = st->z;
+      hn.zin = hn.zout = zstate(c, st);
       hn.SV = S[(n + 1) % 2];
       hn.uout = Ub[(n + 1) % 2];
       TIMED(2, launch_step2d(c->model, c->mixed, c->mesh, a, hn, strm));
@@ -1055,7 +1064,7 @@ static int enqueue_chunk_inner_all(emrkc_ctx *c, const emrkc_state *st, const St
     for (int n = 0; n < L; ++n) {
       HeadArgs h = make_head(c, P, dt, 1, n);
       h.Vin = X[n % 2];
-      h.zin = h.zout = st->z;
+      h.zin = h.zout = zstate(c, st);
       h.uout = c->d_U[0];
       TIMED(0, launch_head(c->model, c->mixed, c->mesh, h, strm));
       InnerAllArgs a = make_inner_all(c, P, dt, 1);
@@ -1139,7 +1148,7 @@ static int enqueue_chunk_fused(emrkc_ctx *c, const emrkc_state *st, const StepPl
   };
   HeadArgs h = make_head(c, P, dt, 1, 0);
   h.Vin = X[0];
-  h.zin = h.zout = st->z;
+  h.zin = h.zout = zstate(c, st);
   h.SV = S[0];
   h.uout = B[base];
   TIMED(0, launch_head(c->model, c->mixed, c->mesh, h, strm));
@@ -1151,7 +1160,7 @@ static int enqueue_chunk_fused(emrkc_ctx *c, const emrkc_state *st, const StepPl
     f.Vout = X[n % 2];
     base = (base + m - 1) % 3;
     f.h = make_head(c, P, dt, 1, n);
-    f.h.zin = f.h.zout = st->z;
+    f.h.zin = f.h.zout = zstate(c, st);
     f.h.SV = S[n % 2];
     f.h.uout = B[base];
     TIMED(2, launch_fused(c->model, c->mixed, c->mesh, f, strm));
@@ -1176,7 +1185,7 @@ static int enqueue_chunk_s1m1(emrkc_ctx *c, const emrkc_state *st, const StepPla
   for (int n = 0; n < L; ++n) {
     HeadArgs h = make_head(c, P, dt, 1, n);
     h.Vin = X[n % 2];
-    h.zin = h.zout = st->z;
+    h.zin = h.zout = zstate(c, st);
     h.uout = X[(n + 1) % 2];
     TIMED(0, launch_head(c->model, c->mixed, c->mesh, h, strm));
   }
@@ -1272,10 +1281,57 @@ static int enqueue_chunk(emrkc_ctx *c, const emrkc_state *st, const StepPlan &P,
   return EMRKC_OK;
 }
 
+// z arrays of the library hold whole blocks of kZBlock nodes, so that they
+// serve in either z layout
+static size_t z_bytes(const emrkc_ctx *c) {
+  const size_t nodes = (size_t)((c->N + kZBlock - 1) / kZBlock) * kZBlock;
+  return (c->mixed ? sizeof(float) : sizeof(double)) * nodes * (size_t)(c->nv - 1);
+}
+
 static int ensure_z1(emrkc_ctx *c) {
   if (c->d_z1 != nullptr) return EMRKC_OK;
-  const size_t zb = (c->mixed ? sizeof(float) : sizeof(double)) * (size_t)c->N * (size_t)(c->nv - 1);
-  return dalloc(c, &c->d_z1, zb);
+  return dalloc(c, &c->d_z1, z_bytes(c));
+}
+
+// emrkc_step keeps z in blocks of kZBlock nodes (all components of a block
+// contiguous) while it steps: each wave of a head then reads and writes one
+// contiguous run instead of 2 n_z component planes, which moved the
+// pointwise head's bytes 14% faster on the 36.5M-node slab.  The caller's z
+// is converted on entry and back on exit; EMRKC_Z_PLANES, rho_every (whose
+// estimates read the caller's z between chunks), mRKC and batches, the
+// z-marching heads and a failed allocation of the block buffer keep the
+// component planes.
+static bool zblocks_mode(const emrkc_ctx *c, const StepPlan &P) {
+  if (c->batch || c->method != EMRKC_METHOD_EMRKC || (c->flags & EMRKC_Z_PLANES) || c->rho_every > 0) return false;
+  if (split_mode(c, P) || u1_split_mode(c, P)) return true;
+  // every other emRKC head reads and writes z through head_node, which
+  // takes either layout, except the z-marching heads (3-D shapes 1 and 2),
+  // which stage component planes themselves
+  const Grid &g = c->mesh.grid;
+  return !(c->mesh.kind == kGrid && !c->mesh.flat && g.dim == 3 && (g.head_variant == 1 || g.head_variant == 2));
+}
+
+// Converts the state's z into the block buffer and points the heads at it
+// (*on = true), or leaves the planes (*on = false) when the mode does not
+// apply or the buffer cannot be allocated.
+static int zblocks_begin(emrkc_ctx *c, const emrkc_state *st, const StepPlan &P, bool *on) {
+  *on = false;
+  if (!zblocks_mode(c, P)) return EMRKC_OK;
+  if (c->d_zb == nullptr && hipMalloc(&c->d_zb, z_bytes(c)) != hipSuccess) {
+    c->d_zb = nullptr;
+    (void)hipGetLastError();
+    return EMRKC_OK;
+  }
+  HIP_TRY(c, launch_z_layout(c->mixed, st->z, c->d_zb, (uint32_t)c->N, (uint32_t)(c->nv - 1), true, c->stream));
+  c->zb_run = *on = true;
+  return EMRKC_OK;
+}
+
+static int zblocks_end(emrkc_ctx *c, const emrkc_state *st, bool on) {
+  if (!on) return EMRKC_OK;
+  c->zb_run = false;
+  HIP_TRY(c, launch_z_layout(c->mixed, c->d_zb, st->z, (uint32_t)c->N, (uint32_t)(c->nv - 1), false, c->stream));
+  return EMRKC_OK;
 }
 
 static int build_batch_tables(emrkc_ctx *c, const emrkc_state *st, double dt, const StepPlan &P);
@@ -1433,9 +1489,12 @@ static int step_core(emrkc_ctx *c, emrkc_state *st, double dt, int64_t nsteps) {
   int rc = make_plan(c, dt, P);
   if (rc != EMRKC_OK) return rc;
   if (c->batch && (rc = build_batch_tables(c, st, dt, P)) != EMRKC_OK) return rc;
-  bool used_graph = false;
+  bool used_graph = false, zb = false;
+  if ((rc = zblocks_begin(c, st, P, &zb)) != EMRKC_OK) return rc;
   rc = run_chunks(c, st, dt, nsteps, P.s, P.m,
                   [&](int L, hipStream_t strm) { return enqueue_chunk(c, st, P, dt, L, strm); }, &used_graph);
+  const int rc_end = zblocks_end(c, st, zb);
+  if (rc == EMRKC_OK) rc = rc_end;
   if (rc != EMRKC_OK) return rc;
   st->step += nsteps;
   st->t = state_time(st->t0, st->step, dt);
@@ -1838,7 +1897,11 @@ extern "C" int emrkc_profile_step(emrkc_ctx *c, emrkc_state *st, double dt, int6
   rebase_clock(st, dt);
   HIP_TRY(c, launch_clock_set(c->d_clock, st->step, st->t0, c->stream));
   KernelTimer tm;
+  bool zb = false;
+  if ((rc = zblocks_begin(c, st, P, &zb)) != EMRKC_OK) return rc;
   rc = enqueue_chunk(c, st, P, dt, (int)nsteps, c->stream, &tm);
+  const int rc_end = zblocks_end(c, st, zb);
+  if (rc == EMRKC_OK) rc = rc_end;
   hipError_t e = hipStreamSynchronize(c->stream);
   double sum[3] = {0, 0, 0};
   int64_t cnt[3] = {0, 0, 0};
@@ -1993,10 +2056,14 @@ extern "C" int emrkc_set_variants(emrkc_ctx *c, const int *variants) {
 // over `reps` steps on state `st` (advanced).
 static int time_classes(emrkc_ctx *c, emrkc_state *st, const StepPlan &P, double dt, int reps, double *ms) {
   HIP_TRY(c, launch_clock_set(c->d_clock, st->step, st->t0, c->stream));
-  int rc = enqueue_chunk(c, st, P, dt, 1, c->stream, nullptr);  // untimed: first launch of each kernel
+  bool zb = false;
+  int rc = zblocks_begin(c, st, P, &zb);  // the z layout emrkc_step would use
   if (rc != EMRKC_OK) return rc;
+  rc = enqueue_chunk(c, st, P, dt, 1, c->stream, nullptr);  // untimed: first launch of each kernel
   KernelTimer tm;
-  rc = enqueue_chunk(c, st, P, dt, reps, c->stream, &tm);
+  if (rc == EMRKC_OK) rc = enqueue_chunk(c, st, P, dt, reps, c->stream, &tm);
+  const int rc_end = zblocks_end(c, st, zb);
+  if (rc == EMRKC_OK) rc = rc_end;
   hipError_t e = hipStreamSynchronize(c->stream);
   double sum[3] = {0, 0, 0};
   int cnt[3] = {0, 0, 0};
@@ -2129,12 +2196,22 @@ static int autotune_batch(emrkc_ctx *c, const emrkc_state *st, double dt, int re
 // grids.
 static int time_steps(emrkc_ctx *c, emrkc_state *st, const StepPlan &P, double dt, int reps, double *ms) {
   HIP_TRY(c, launch_clock_set(c->d_clock, st->step, st->t0, c->stream));
-  int rc = enqueue_chunk(c, st, P, dt, 2, c->stream, nullptr);  // untimed: first launches
+  bool zb = false;
+  int rc = zblocks_begin(c, st, P, &zb);  // the z layout emrkc_step would use
   if (rc != EMRKC_OK) return rc;
+  rc = enqueue_chunk(c, st, P, dt, 2, c->stream, nullptr);  // untimed: first launches
+  if (rc != EMRKC_OK) {
+    (void)zblocks_end(c, st, zb);
+    return rc;
+  }
   hipEvent_t e0, e1;
-  HIP_TRY(c, hipEventCreate(&e0));
+  if (hipEventCreate(&e0) != hipSuccess) {
+    (void)zblocks_end(c, st, zb);
+    return fail(c, EMRKC_EHIP, "hipEventCreate failed");
+  }
   if (hipEventCreate(&e1) != hipSuccess) {
     (void)hipEventDestroy(e0);
+    (void)zblocks_end(c, st, zb);
     return fail(c, EMRKC_EHIP, "hipEventCreate failed");
   }
   hipError_t e = hipEventRecord(e0, c->stream);
@@ -2142,6 +2219,8 @@ static int time_steps(emrkc_ctx *c, emrkc_state *st, const StepPlan &P, double d
     rc = enqueue_chunk(c, st, P, dt, reps, c->stream, nullptr);
     e = hipEventRecord(e1, c->stream);
   }
+  const int rc_end = zblocks_end(c, st, zb);
+  if (rc == EMRKC_OK) rc = rc_end;
   if (e == hipSuccess) e = hipEventSynchronize(e1);
   float t = 0;
   if (e == hipSuccess && rc == EMRKC_OK) e = hipEventElapsedTime(&t, e0, e1);
@@ -2303,20 +2382,37 @@ extern "C" int emrkc_autotune(emrkc_ctx *c, const emrkc_state *st, double dt, in
     const double step8 = head8 + P.m * inner8;
     if (verbose && rc == EMRKC_OK)
       fprintf(stderr, "emrkc_autotune: split with u_1 launch: step %.5f ms (separate %.5f)\n", step8, plain);
-    // (a 1% margin: the split stage is a different design, not a near-equal
-    // tile shape, and the timings are the best of two repetitions)
-    if (rc == EMRKC_OK && std::min(best_split, step8) < 0.99 * plain) {
-      if (step8 <= best_split) {
-        choice[0] = 8;
-        choice[1] = 0;
-        choice[2] = in8[0];
-        choice[3] = in8[1];
-      } else {
-        choice[0] = 7;
-        choice[1] = best_zc;
+    // The sums above are of per-kernel minima over many candidates, each
+    // biased low by its own selection; where the best split is within 3%
+    // of the separate stages the two are timed head to head instead, as
+    // whole steps (alternating, the fastest of three runs each), and the
+    // faster is kept.
+    if (rc == EMRKC_OK && std::min(best_split, step8) < 1.03 * plain) {
+      int vs[5] = {8, 0, in8[0], in8[1], 0};
+      if (step8 > best_split) {
+        vs[0] = 7;
+        vs[1] = best_zc;
+        vs[2] = choice[2];
+        vs[3] = choice[3];
       }
-      choice[4] = 0;
-      split_chosen = true;
+      const int vp[5] = {choice[0], choice[1], choice[2], choice[3], 0};
+      double tp = 1e300, ts = 1e300;
+      for (int r = 0; r < 3 && rc == EMRKC_OK; ++r) {
+        double t;
+        set_variants(c, vp);
+        if ((rc = time_steps(c, &cp.st, P, dt, reps, &t)) != EMRKC_OK) break;
+        tp = std::min(tp, t);
+        set_variants(c, vs);
+        if ((rc = time_steps(c, &cp.st, P, dt, reps, &t)) != EMRKC_OK) break;
+        ts = std::min(ts, t);
+      }
+      if (verbose && rc == EMRKC_OK)
+        fprintf(stderr, "emrkc_autotune: whole steps: split %d/%d %.5f ms, separate %.5f ms\n", vs[0], vs[1], ts,
+                tp);
+      if (rc == EMRKC_OK && ts < tp) {
+        for (int k = 0; k < 5; ++k) choice[k] = vs[k];
+        split_chosen = true;
+      }
     }
   }
   // fused tail+head (s == 1, m >= 2): one kernel per step in place of the

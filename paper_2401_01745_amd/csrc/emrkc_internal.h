@@ -64,7 +64,12 @@ struct HeadArgs {
   int m_is_one;
   int progressive;      // progressive splitting: gates end at z + c'_m (z_E - z)
   double cm;            // c'_m
+  int z_aos;            // z arrays in blocks of kZBlock nodes (else component planes); flat and pointwise heads
 };
+
+// z in blocks: component k of node i at (i / kZBlock) kZBlock n_z + k kZBlock
+// + i % kZBlock, so that each wave's components are one contiguous run.
+constexpr uint32_t kZBlock = 256;
 
 // Last inner stage k = m of stage j together with the outer V update.
 struct TailArgs {
@@ -271,6 +276,11 @@ hipError_t launch_step2d(int model, bool mixed, const Mesh &mesh, const InnerAll
                          hipStream_t st);
 hipError_t launch_head_pw(int model, bool mixed, const Mesh &mesh, const HeadArgs &a, hipStream_t st);
 hipError_t launch_inner12(bool mixed, const Mesh &mesh, const Inner12Args &a, hipStream_t st);
+// z (nz components of N nodes, float when mixed) from component planes to
+// blocks of kZBlock nodes (to_blocks) or back; dst of the block layout holds
+// ceil(N / kZBlock) kZBlock nz values.
+hipError_t launch_z_layout(bool mixed, const void *src, void *dst, uint32_t N, uint32_t nz, bool to_blocks,
+                           hipStream_t st);
 hipError_t launch_clock_set(Clock *c, int64_t step, double t0, hipStream_t st);
 hipError_t launch_copy_tick(const double *src, double *dst, uint32_t N, Clock *tick, int64_t tick_by,
                             hipStream_t st);

@@ -130,17 +130,29 @@ __device__ __forceinline__ double first_inner(double mu1_eta, double u0, double 
 // ---------------------------------------------------------------------------
 // FVf() evaluates f_F(V_{j-1}) at the node; it is called after the z update
 // so that the stencil operands are not live across the ionic model.
-// z_{j-1} of node i (all ionic components, SoA planes N apart)
+// Where node i's components sit in a z array: component k at
+// base + k * stride; component planes of N (base i, stride N) or, with
+// `blocks`, blocks of kZBlock nodes x nz components.
+struct ZAt {
+  size_t base, stride;
+};
+__device__ __forceinline__ ZAt z_at(bool blocks, uint32_t N, uint32_t i, int nz) {
+  if (blocks) return ZAt{(size_t)(i / kZBlock) * kZBlock * (size_t)nz + i % kZBlock, kZBlock};
+  return ZAt{i, N};
+}
+
+// z_{j-1} of node i (all ionic components)
 template <template <class> class Model, bool MIXED>
 struct HeadZ {
   using R = typename MathOf<MIXED>::R;
   static constexpr int NZ = Model<MathOf<MIXED>>::NG + Model<MathOf<MIXED>>::NS;
   R z[NZ];
-  __device__ __forceinline__ void load(const void *zin, uint32_t N, uint32_t i) {
+  __device__ __forceinline__ void load(const void *zin, ZAt at) {
     const auto p = gptr((const R *)zin);
 #pragma unroll
-    for (int k = 0; k < NZ; ++k) z[k] = p[(size_t)k * N + i];
+    for (int k = 0; k < NZ; ++k) z[k] = p[at.base + k * at.stride];
   }
+  __device__ __forceinline__ void load(const void *zin, uint32_t N, uint32_t i) { load(zin, z_at(false, N, i, NZ)); }
 };
 
 template <template <class> class Model, bool MIXED, bool SV_ONLY = false, class FVf>
@@ -150,7 +162,7 @@ __device__ __forceinline__ void head_node_z(const HeadArgs &a, uint32_t N, uint3
 template <template <class> class Model, bool MIXED, bool SV_ONLY = false, class FVf>
 __device__ __forceinline__ void head_node(const HeadArgs &a, uint32_t N, uint32_t i, double V, FVf FVfun) {
   HeadZ<Model, MIXED> hz;
-  hz.load(a.zin, N, i);
+  hz.load(a.zin, z_at(a.z_aos != 0, N, i, HeadZ<Model, MIXED>::NZ));
   const double tj = stage_time(a.clock, a.step_off, a.dt, a.c_prev);
   head_node_z<Model, MIXED, SV_ONLY>(a, N, i, V, hz.z, stimulus(a.stim, i, tj), FVfun);
 }
@@ -191,11 +203,12 @@ __device__ __forceinline__ void head_node_z(const HeadArgs &a, uint32_t N, uint3
   // slow variables recur in double.
   const auto zout = gptr((R *)a.zout);
   const auto zin2 = gptr((const R *)a.zin2);
+  const ZAt za = z_at(a.z_aos != 0, N, i, NZ);
   const float gate_c = (float)(a.mu_dt * a.inv_eta * (a.progressive ? a.cm : 1.0));
 #pragma unroll
   for (int k = 0; k < NZ; ++k) {
     if (MIXED && k < NG && a.j1) {
-      zout[(size_t)k * N + i] = R(__builtin_fmaf(gate_c, (float)(zE[k] - z[k]), (float)z[k]));
+      zout[za.base + k * za.stride] = R(__builtin_fmaf(gate_c, (float)(zE[k] - z[k]), (float)z[k]));
       continue;
     }
     double fbar;
@@ -211,8 +224,8 @@ __device__ __forceinline__ void head_node_z(const HeadArgs &a, uint32_t N, uint3
     if (a.j1)
       zj = (double)z[k] + a.mu_dt * fbar;
     else
-      zj = a.nu * (double)z[k] + a.kappa * (double)zin2[(size_t)k * N + i] + a.mu_dt * fbar;
-    zout[(size_t)k * N + i] = R(zj);
+      zj = a.nu * (double)z[k] + a.kappa * (double)zin2[za.base + k * za.stride] + a.mu_dt * fbar;
+    zout[za.base + k * za.stride] = R(zj);
   }
 
   if (SV_ONLY) {
@@ -1510,6 +1523,25 @@ __global__ __launch_bounds__(kBlock) void k_inner_batch(const BatchInst *__restr
   }
 }
 
+// z between component planes and blocks of kZBlock nodes: element j of the
+// block layout is component k of node i = b kZBlock + l with
+// j = b kZBlock nz + k kZBlock + l.  Positions of the last block beyond N
+// are written as zero and never copied back.  Consecutive threads take
+// consecutive j, so both sides are read and written in runs of kZBlock.
+template <class R, bool TO_BLOCKS>
+__global__ __launch_bounds__(kBlock) void k_z_layout(const R *__restrict__ src, R *__restrict__ dst, uint32_t N,
+                                                     uint32_t nz, size_t total) {
+  const size_t j = (size_t)blockIdx.x * kBlock + threadIdx.x;
+  if (j >= total) return;
+  const size_t per = (size_t)kZBlock * nz;
+  const size_t b = j / per, r = j - b * per;
+  const size_t k = r / kZBlock, i = b * kZBlock + r % kZBlock;
+  if (TO_BLOCKS)
+    dst[j] = i < N ? src[k * N + i] : R(0);
+  else if (i < N)
+    dst[k * N + i] = src[j];
+}
+
 __global__ void k_clock_set(Clock *c, int64_t step, double t0) {
   if (threadIdx.x == 0 && blockIdx.x == 0) {
     c->step = step;
@@ -2379,6 +2411,27 @@ hipError_t launch_fused(int model, bool mixed, const Mesh &mesh, const FusedArgs
 #define CALL(M) fused_dispatch<M>(mixed, mesh.grid, a, st)
   EMRKC_MODEL_SWITCH(model, CALL)
 #undef CALL
+}
+
+hipError_t launch_z_layout(bool mixed, const void *src, void *dst, uint32_t N, uint32_t nz, bool to_blocks,
+                           hipStream_t st) {
+  const size_t total = (size_t)((N + kZBlock - 1) / kZBlock) * kZBlock * nz;
+  const size_t nb = (total + kBlock - 1) / kBlock;
+  if (nb > 0x7fffffffu) return hipErrorInvalidValue;
+  const dim3 grid((uint32_t)nb);
+  if (mixed) {
+    if (to_blocks)
+      EMRKC_LAUNCH((k_z_layout<float, true>), grid, dim3(kBlock), 0, st, (const float *)src, (float *)dst, N, nz, total);
+    else
+      EMRKC_LAUNCH((k_z_layout<float, false>), grid, dim3(kBlock), 0, st, (const float *)src, (float *)dst, N, nz, total);
+  } else if (to_blocks) {
+    EMRKC_LAUNCH((k_z_layout<double, true>), grid, dim3(kBlock), 0, st, (const double *)src, (double *)dst, N, nz,
+                 total);
+  } else {
+    EMRKC_LAUNCH((k_z_layout<double, false>), grid, dim3(kBlock), 0, st, (const double *)src, (double *)dst, N, nz,
+                 total);
+  }
+  return hipGetLastError();
 }
 
 hipError_t launch_clock_set(Clock *c, int64_t step, double t0, hipStream_t st) {

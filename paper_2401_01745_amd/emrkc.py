@@ -35,6 +35,7 @@ EMRKC_COND_A = 0x200       # stage counts from stability condition A
 EMRKC_EAGER = 2          # diagnostic flag: no HIP-graph replay
 EMRKC_FUSE = 4           # diagnostic flag: fused tail+head kernel
 EMRKC_FLAT = 8           # diagnostic flag: flat (untiled) grid kernels
+EMRKC_Z_PLANES = 0x400   # diagnostic flag: z stays in component planes while stepping
 
 
 class Mesh(C.Structure):

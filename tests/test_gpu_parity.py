@@ -183,9 +183,10 @@ def test_stage_plans(E, rho, dt, sm):
     assert (stats.s, stats.m) == sm
     if sm[1] >= 2:
         for v in [(7, 3, 1, 4, 0), (8, 0, 1, 4, 0)]:
-            V7, _, st7 = gpu_run(cfg, 60, rho, variants=v)
-            assert (st7.s, st7.m) == sm
-            assert np.array_equal(V7, V), v
+            for fl in (0, E.EMRKC_Z_PLANES):  # z in blocks (z_1 too, for s >= 2) and in planes
+                V7, _, st7 = gpu_run(cfg, 60, rho, variants=v, flags=fl)
+                assert (st7.s, st7.m) == sm
+                assert np.array_equal(V7, V), (v, fl)
 
 
 @pytest.mark.parametrize("rho,dt,sm", [((51.0, 100.0), 0.05, (2, 1)), ((2000.0, 300.0), 0.05, (3, 3)),
@@ -252,6 +253,10 @@ def test_graph_eager_fused_split_and_repeat_are_bitwise_identical(E, n, rho, pre
     # falls back to separate flat head and inner launches
     V8, z8, st8 = gpu_run(cfg, 80, rho, precision=precision, flags=E.EMRKC_FLAT | E.EMRKC_FUSE)
     runs = [(V2, z2), (V3, z3), (V4, z4), (V5, z5), (V6, z6), (V7, z7), (V8, z8)]
+    # z kept in component planes while stepping (the runs above hold it in
+    # blocks of 256 nodes), with the default, fused and flat kernels
+    for fl in (E.EMRKC_Z_PLANES, E.EMRKC_Z_PLANES | E.EMRKC_FUSE, E.EMRKC_Z_PLANES | E.EMRKC_FLAT):
+        runs.append(gpu_run(cfg, 80, rho, precision=precision, flags=fl)[:2])
     if len(n) == 3:
         # z-marching head (register and LDS-staged) and inner kernels with
         # ragged columns and plane counts that do not divide n[2]
@@ -279,6 +284,9 @@ def test_graph_eager_fused_split_and_repeat_are_bitwise_identical(E, n, rho, pre
         V10, z10, st10 = gpu_run(cfg, 80, rho, precision=precision, chunks=[1, 33, 7, 39], variants=(0, 0, 2, 0, 0))
         assert st10.kernels_per_step == 2
         assert np.array_equal(V10, V1) and np.array_equal(z10, z1)
+    if len(n) == 3:  # the split stage with z kept in component planes (the default holds it in blocks)
+        for v in [(8, 0, 1, 4, 0), (7, 3, 1, 4, 0)]:
+            runs.append(gpu_run(cfg, 80, rho, precision=precision, flags=E.EMRKC_Z_PLANES, variants=v)[:2])
     if len(n) == 3:  # the split stage with an odd call split (ping-pong and the final copy)
         V9, z9, st9 = gpu_run(cfg, 80, rho, precision=precision, chunks=[1, 33, 7, 39], variants=(7, 3, 1, 4, 0))
         assert st9.kernels_per_step == st9.m
@@ -300,8 +308,8 @@ def test_autotune_keeps_state_and_results(E):
     v = E.emrkc_autotune(sim.ctx, sim.state, cfg["dt"], reps=2)
     assert torch.equal(sim.V, V0) and torch.equal(sim.z, z0)
     assert v == E.emrkc_get_variants(sim.ctx)
-    assert len(v) == 5 and v[0] in (0, 1, 2, 3, 4, 5, 6) and v[2] in (0, 1) and v[4] in (0, 1)
-    assert (v[0] in (1, 2)) == (v[1] > 0) and (v[2] == 0) == (v[3] == 0)
+    assert len(v) == 5 and v[0] in range(9) and v[2] in (0, 1) and v[4] in (0, 1)
+    assert (v[0] in (1, 2, 7)) == (v[1] > 0) and (v[2] == 0) == (v[3] == 0)
     E.emrkc_step(sim.ctx, sim.state, cfg["dt"], 30)
     torch.cuda.synchronize()
     assert np.array_equal(sim.V.cpu().numpy(), V1)

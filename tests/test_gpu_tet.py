@@ -64,6 +64,15 @@ def test_small_shell_run(small, precision, tol, rhoF):
     assert l2 <= tol and mx <= (tol if precision == "fp64" else 10 * tol), (l2, mx)
     st = E.emrkc_last_stats(sim.ctx)
     assert st.s == 1 and st.m == {None: 1, 100.0: 2, 900.0: 5}[rhoF]
+    V, z = sim.V.cpu().numpy().copy(), sim.z.cpu().numpy().copy()
+    sim.close()
+    # z kept in component planes while stepping (the run above holds it in
+    # blocks of 256 nodes): the same bits
+    sim = E.simulation_from_tet_config(cfg, mesh, mask, precision=precision, rho=(rF, rS), flags=E.EMRKC_Z_PLANES)
+    E.emrkc_init_state(sim.ctx, sim.state)
+    E.emrkc_step(sim.ctx, sim.state, cfg["dt"], nsteps)
+    torch.cuda.synchronize()
+    assert np.array_equal(sim.V.cpu().numpy(), V) and np.array_equal(sim.z.cpu().numpy(), z)
     sim.close()
 
 
