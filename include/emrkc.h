@@ -78,12 +78,15 @@ extern "C" {
  * EMRKC_Z_PLANES — emrkc_step (and the autotuner's and profiler's steps)
  *   keep z in the state's component planes while stepping.  Without it, a
  *   single emRKC context without rho_every whose head is not a z-marching
- *   one (3-D kernel shapes 1 and 2) converts z on entry into a library
- *   buffer that holds each block of 256 nodes' components contiguously
- *   (n_z x 256 values per block), steps on that buffer and converts back
- *   before it returns; the buffer (the size of z, rounded up to whole
- *   blocks) is allocated on first use, and where that allocation fails the
- *   planes are kept.  emrkc_step_noalloc always keeps the planes.
+ *   one (3-D kernel shapes 1 and 2) and whose z array holds at least
+ *   256 MiB converts z on entry into a library buffer that holds each
+ *   block of 256 nodes' components contiguously (n_z x 256 values per
+ *   block), steps on that buffer and converts back before it returns; the
+ *   buffer (the size of z, rounded up to whole blocks) is allocated on
+ *   first use, and where that allocation fails the planes are kept.
+ *   emrkc_step_noalloc always keeps the planes.
+ * EMRKC_Z_BLOCKS — the block layout above also for z arrays below 256 MiB
+ *   (EMRKC_Z_PLANES takes precedence).
  * The environment variables EMRKC_EAGER and EMRKC_FUSE (any value) act like
  * the flags for every context; EMRKC_VERBOSE makes emrkc_autotune print its
  * timings to stderr. */
@@ -91,6 +94,7 @@ extern "C" {
 #define EMRKC_FUSE 4u
 #define EMRKC_FLAT 8u
 #define EMRKC_Z_PLANES 0x400u
+#define EMRKC_Z_BLOCKS 0x800u
 /* Stepping variants (flags):
  * EMRKC_PROGRESSIVE — the progressive splitting of the auxiliary problem
  *   (remark after eq. auxp_exp): the inner problem starts from y and carries

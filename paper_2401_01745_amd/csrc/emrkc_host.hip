@@ -1300,9 +1300,16 @@ static int ensure_z1(emrkc_ctx *c) {
 // is converted on entry and back on exit; EMRKC_Z_PLANES, rho_every (whose
 // estimates read the caller's z between chunks), mRKC and batches, the
 // z-marching heads and a failed allocation of the block buffer keep the
-// component planes.
+// component planes.  So does a z array below kZBlocksMinBytes unless
+// EMRKC_Z_BLOCKS asks for blocks: it is served from the 256 MB last-level
+// cache in either layout (the 3-D grid of 442k nodes, 71 MB of z, steps at
+// the same rate in both), so the two conversion launches per call would
+// buy nothing.
+constexpr size_t kZBlocksMinBytes = size_t(256) << 20;
+
 static bool zblocks_mode(const emrkc_ctx *c, const StepPlan &P) {
   if (c->batch || c->method != EMRKC_METHOD_EMRKC || (c->flags & EMRKC_Z_PLANES) || c->rho_every > 0) return false;
+  if (!(c->flags & EMRKC_Z_BLOCKS) && z_bytes(c) < kZBlocksMinBytes) return false;
   if (split_mode(c, P) || u1_split_mode(c, P)) return true;
   // every other emRKC head reads and writes z through head_node, which
   // takes either layout, except the z-marching heads (3-D shapes 1 and 2),

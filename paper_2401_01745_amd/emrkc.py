@@ -36,6 +36,7 @@ EMRKC_EAGER = 2          # diagnostic flag: no HIP-graph replay
 EMRKC_FUSE = 4           # diagnostic flag: fused tail+head kernel
 EMRKC_FLAT = 8           # diagnostic flag: flat (untiled) grid kernels
 EMRKC_Z_PLANES = 0x400   # diagnostic flag: z stays in component planes while stepping
+EMRKC_Z_BLOCKS = 0x800   # diagnostic flag: z in blocks of 256 nodes also for small z arrays
 
 
 class Mesh(C.Structure):

@@ -183,7 +183,7 @@ def test_stage_plans(E, rho, dt, sm):
     assert (stats.s, stats.m) == sm
     if sm[1] >= 2:
         for v in [(7, 3, 1, 4, 0), (8, 0, 1, 4, 0)]:
-            for fl in (0, E.EMRKC_Z_PLANES):  # z in blocks (z_1 too, for s >= 2) and in planes
+            for fl in (E.EMRKC_Z_BLOCKS, E.EMRKC_Z_PLANES):  # z in blocks (z_1 too, for s >= 2) and in planes
                 V7, _, st7 = gpu_run(cfg, 60, rho, variants=v, flags=fl)
                 assert (st7.s, st7.m) == sm
                 assert np.array_equal(V7, V), (v, fl)
@@ -253,10 +253,14 @@ def test_graph_eager_fused_split_and_repeat_are_bitwise_identical(E, n, rho, pre
     # falls back to separate flat head and inner launches
     V8, z8, st8 = gpu_run(cfg, 80, rho, precision=precision, flags=E.EMRKC_FLAT | E.EMRKC_FUSE)
     runs = [(V2, z2), (V3, z3), (V4, z4), (V5, z5), (V6, z6), (V7, z7), (V8, z8)]
-    # z kept in component planes while stepping (the runs above hold it in
-    # blocks of 256 nodes), with the default, fused and flat kernels
-    for fl in (E.EMRKC_Z_PLANES, E.EMRKC_Z_PLANES | E.EMRKC_FUSE, E.EMRKC_Z_PLANES | E.EMRKC_FLAT):
+    # z in blocks of 256 nodes while stepping (the runs above keep these
+    # small z arrays in component planes), with the default, fused and flat
+    # kernels, eager launches and an odd call split (a conversion each way
+    # per call)
+    ZB = E.EMRKC_Z_BLOCKS
+    for fl in (ZB, ZB | E.EMRKC_FUSE, ZB | E.EMRKC_FLAT, ZB | E.EMRKC_EAGER):
         runs.append(gpu_run(cfg, 80, rho, precision=precision, flags=fl)[:2])
+    runs.append(gpu_run(cfg, 80, rho, precision=precision, flags=ZB, chunks=[1, 33, 7, 39])[:2])
     if len(n) == 3:
         # z-marching head (register and LDS-staged) and inner kernels with
         # ragged columns and plane counts that do not divide n[2]
@@ -269,9 +273,12 @@ def test_graph_eager_fused_split_and_repeat_are_bitwise_identical(E, n, rho, pre
                   (7, 4, 1, 4, 0), (7, 2, 0, 0, 0), (7, 3, 1, 2, 0), (7, n[2], 1, 3, 0),
                   (8, 0, 1, 4, 0), (8, 0, 0, 0, 0), (8, 0, 1, 2, 0)]:
             runs.append(gpu_run(cfg, 80, rho, precision=precision, variants=v)[:2])
+            if v[0] not in (1, 2):  # every head but the z-marching ones also with z in blocks
+                runs.append(gpu_run(cfg, 80, rho, precision=precision, variants=v, flags=ZB)[:2])
         if precision == "mixed":  # the 7-wave flat head exists in the mixed precision only
             for v in [(6, 0, 1, 3, 0), (6, 0, 0, 0, 0), (6, 0, 0, 0, 1)]:
                 runs.append(gpu_run(cfg, 80, rho, precision=precision, variants=v)[:2])
+                runs.append(gpu_run(cfg, 80, rho, precision=precision, variants=v, flags=ZB)[:2])
     assert st1.used_graph == 1 and st2.used_graph == 0
     assert st1.kernels_per_step == st1.m and st5.kernels_per_step == st5.m - 1
     assert st8.kernels_per_step == st8.m
@@ -284,9 +291,9 @@ def test_graph_eager_fused_split_and_repeat_are_bitwise_identical(E, n, rho, pre
         V10, z10, st10 = gpu_run(cfg, 80, rho, precision=precision, chunks=[1, 33, 7, 39], variants=(0, 0, 2, 0, 0))
         assert st10.kernels_per_step == 2
         assert np.array_equal(V10, V1) and np.array_equal(z10, z1)
-    if len(n) == 3:  # the split stage with z kept in component planes (the default holds it in blocks)
+    if len(n) == 3:  # the split stage with z in blocks over an odd call split
         for v in [(8, 0, 1, 4, 0), (7, 3, 1, 4, 0)]:
-            runs.append(gpu_run(cfg, 80, rho, precision=precision, flags=E.EMRKC_Z_PLANES, variants=v)[:2])
+            runs.append(gpu_run(cfg, 80, rho, precision=precision, flags=ZB, variants=v, chunks=[1, 33, 7, 39])[:2])
     if len(n) == 3:  # the split stage with an odd call split (ping-pong and the final copy)
         V9, z9, st9 = gpu_run(cfg, 80, rho, precision=precision, chunks=[1, 33, 7, 39], variants=(7, 3, 1, 4, 0))
         assert st9.kernels_per_step == st9.m

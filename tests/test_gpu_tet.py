@@ -66,9 +66,9 @@ def test_small_shell_run(small, precision, tol, rhoF):
     assert st.s == 1 and st.m == {None: 1, 100.0: 2, 900.0: 5}[rhoF]
     V, z = sim.V.cpu().numpy().copy(), sim.z.cpu().numpy().copy()
     sim.close()
-    # z kept in component planes while stepping (the run above holds it in
-    # blocks of 256 nodes): the same bits
-    sim = E.simulation_from_tet_config(cfg, mesh, mask, precision=precision, rho=(rF, rS), flags=E.EMRKC_Z_PLANES)
+    # z in blocks of 256 nodes while stepping (the run above keeps this
+    # small z array in component planes): the same bits
+    sim = E.simulation_from_tet_config(cfg, mesh, mask, precision=precision, rho=(rF, rS), flags=E.EMRKC_Z_BLOCKS)
     E.emrkc_init_state(sim.ctx, sim.state)
     E.emrkc_step(sim.ctx, sim.state, cfg["dt"], nsteps)
     torch.cuda.synchronize()
