@@ -451,8 +451,9 @@ struct Grid {
   uint32_t head_zc;
   // weights of (chi Cm M_L)^{-1} A on neighbour differences, by offset class
   // (|ox|, |oy|, |oz|): w[0]=100, w[1]=010, w[2]=001, w[3]=110, w[4]=101,
-  // w[5]=011, w[6]=111 (2-D uses w[0], w[1], w[3]).
-  double w[7];
+  // w[5]=011, w[6]=111 (2-D uses w[0], w[1], w[3]); w[7] = w[2] + 2 (w[4] +
+  // w[5]) + 4 w[6], the total weight of one neighbouring plane (3-D).
+  double w[8];
 };
 
 __device__ __forceinline__ uint32_t mirror_lo(uint32_t i) { return i > 0 ? i - 1 : 1; }
@@ -466,35 +467,57 @@ __device__ __forceinline__ uint32_t mirror_hi(uint32_t i, uint32_t n) { return i
 // form would save no memory traffic, and on gfx950 unpacked float arithmetic
 // issues at the double rate, so its conversions would only add instructions.
 //
+// In 3-D every plane of the 3 x 3 x 3 neighbourhood enters through three
+// numbers at the node's (x, y) (PlaneTerms): its centre value c, and the
+// weighted in-plane differences to c (edges and corners) as the node's own
+// plane (o) and as a neighbouring plane (t).  A difference to a neighbour in
+// plane z +- 1 is split as (u_o - c_{z+-1}) + (c_{z+-1} - u_c), so
+//   F = o_z + (t_{z-1} + t_{z+1}) + w[7] ((c_{z-1} - c_z) + (c_{z+1} - c_z)).
+// A z-marching kernel forms each plane's terms once and keeps them, instead
+// of reading 27 values per node.
+//
 // Written with explicit fused multiply-adds in a fixed order and no further
 // contraction, so that the flat, LDS-tiled and z-marching kernels round
 // identically.
+struct PlaneTerms {
+  double c, o, t;
+};
+
+template <class Get2>
+__device__ __forceinline__ PlaneTerms plane_terms(const double *w, Get2 get) {
+#pragma clang fp contract(off)
+  const double c = get(0, 0);
+  const double ex = (get(-1, 0) - c) + (get(1, 0) - c);
+  const double ey = (get(0, -1) - c) + (get(0, 1) - c);
+  const double cr = ((get(-1, -1) - c) + (get(1, -1) - c)) + ((get(-1, 1) - c) + (get(1, 1) - c));
+  PlaneTerms p;
+  p.c = c;
+  p.o = __builtin_fma(w[3], cr, __builtin_fma(w[1], ey, w[0] * ex));
+  p.t = __builtin_fma(w[6], cr, __builtin_fma(w[5], ey, w[4] * ex));
+  return p;
+}
+
+__device__ __forceinline__ double plane_combine(const double *w, const PlaneTerms &m, const PlaneTerms &o,
+                                                const PlaneTerms &p) {
+#pragma clang fp contract(off)
+  return __builtin_fma(w[7], (m.c - o.c) + (p.c - o.c), o.o + (m.t + p.t));
+}
+
 template <int DIM, class Get>
 __device__ __forceinline__ double grid_stencil(const double *w, Get get) {
 #pragma clang fp contract(off)
-  const double uc = get(0, 0, 0);
-  auto d = [&](int dx, int dy, int dz) { return get(dx, dy, dz) - uc; };
   if (DIM == 2) {
-    const double f = d(-1, 0, 0) + d(1, 0, 0);
-    const double e = d(0, -1, 0) + d(0, 1, 0);
-    const double c = (d(-1, -1, 0) + d(1, -1, 0)) + (d(-1, 1, 0) + d(1, 1, 0));
+    const double uc = get(0, 0, 0);
+    auto d = [&](int dx, int dy) { return get(dx, dy, 0) - uc; };
+    const double f = d(-1, 0) + d(1, 0);
+    const double e = d(0, -1) + d(0, 1);
+    const double c = (d(-1, -1) + d(1, -1)) + (d(-1, 1) + d(1, 1));
     return __builtin_fma(w[3], c, __builtin_fma(w[1], e, w[0] * f));
   }
-  const double fx = d(-1, 0, 0) + d(1, 0, 0);
-  const double fy = d(0, -1, 0) + d(0, 1, 0);
-  const double fz = d(0, 0, -1) + d(0, 0, 1);
-  const double exy = (d(-1, -1, 0) + d(1, -1, 0)) + (d(-1, 1, 0) + d(1, 1, 0));
-  const double exz = (d(-1, 0, -1) + d(1, 0, -1)) + (d(-1, 0, 1) + d(1, 0, 1));
-  const double eyz = (d(0, -1, -1) + d(0, 1, -1)) + (d(0, -1, 1) + d(0, 1, 1));
-  const double cm = (d(-1, -1, -1) + d(1, -1, -1)) + (d(-1, 1, -1) + d(1, 1, -1));
-  const double cp = (d(-1, -1, 1) + d(1, -1, 1)) + (d(-1, 1, 1) + d(1, 1, 1));
-  double r = w[0] * fx;
-  r = __builtin_fma(w[1], fy, r);
-  r = __builtin_fma(w[2], fz, r);
-  r = __builtin_fma(w[3], exy, r);
-  r = __builtin_fma(w[4], exz, r);
-  r = __builtin_fma(w[5], eyz, r);
-  return __builtin_fma(w[6], cm + cp, r);
+  const PlaneTerms m = plane_terms(w, [&](int dx, int dy) { return get(dx, dy, -1); });
+  const PlaneTerms o = plane_terms(w, [&](int dx, int dy) { return get(dx, dy, 0); });
+  const PlaneTerms p = plane_terms(w, [&](int dx, int dy) { return get(dx, dy, 1); });
+  return plane_combine(w, m, o, p);
 }
 
 // The stencil on a global array at node (ix, iy, iz).

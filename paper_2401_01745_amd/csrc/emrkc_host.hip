@@ -386,7 +386,7 @@ static void grid_weights(int dim, const double *h, const double *sig, double chi
     }
     return -g / chiCm;
   };
-  for (int k = 0; k < 7; ++k) w[k] = 0.0;
+  for (int k = 0; k < 8; ++k) w[k] = 0.0;
   w[0] = G(1, 0, 0);
   w[1] = G(0, 1, 0);
   w[3] = G(1, 1, 0);
@@ -395,6 +395,9 @@ static void grid_weights(int dim, const double *h, const double *sig, double chi
     w[4] = G(1, 0, 1);
     w[5] = G(0, 1, 1);
     w[6] = G(1, 1, 1);
+    // the weight of one neighbouring plane's centre difference in the
+    // plane-by-plane form of the 3-D stencil
+    w[7] = w[2] + 2.0 * (w[4] + w[5]) + 4.0 * w[6];
   }
 }
 

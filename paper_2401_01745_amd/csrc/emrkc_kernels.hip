@@ -854,18 +854,25 @@ __global__ __launch_bounds__(kBlock) void k_inner_march(InnerArgs a, Grid g, uin
 // First two inner stages of the split stage on 3-D grids, by z-marching
 // columns: u_1 = u_0 + mu'_1 eta (f_F(u_0) + S_V) with u_0 = V_{j-1}, then
 // u_2 = nu'_2 u_1 + kappa'_2 u_0 + mu'_2 eta (f_F(u_1) + S_V), and, when
-// m == 2, the outer V update.  A block owns an MX x MY column of zc planes
-// and keeps in LDS four planes of V_{j-1} with a two-node halo in x and y
-// and three planes of u_1 with a one-node halo; u_1 is formed on the halo
-// from the V planes.  V plane z+3 and the halo's S_V of plane z+2 are
-// loaded into registers while plane z is computed.  Positions beyond the
-// grid are reflected at both ends (mirror2; at most twice, for two-node
-// axes), so that u_1 on the halo equals u_1 at the reflected node: the
-// stencil's sums pair opposite neighbours, and exchanging the two members
-// of every pair leaves each sum's bits unchanged.
+// m == 2, the outer V update.  A block owns an MX x MY column of zc planes.
+// V_{j-1} is staged in LDS with a two-node halo in x and y (a ring of four
+// planes), and u_1 is formed on a one-node halo from the stencil's plane
+// terms of V (grid_stencil), each plane's terms formed once per halo
+// position and kept: in registers for the first kBlock positions, in a
+// thread-private LDS ring for the remaining ones.  The newest u_1 plane
+// goes to LDS, and the node's own u_1 plane terms stay in registers, so
+// each plane costs 9 LDS reads per halo position and per node instead of
+// 27.  V plane z+3 and the halo's S_V of plane z+2 are loaded into
+// registers while plane z is computed.  Positions beyond the grid are
+// reflected at both ends (mirror2; at most twice, for two-node axes), so
+// that u_1 on the halo equals u_1 at the reflected node: the plane terms
+// pair opposite neighbours, and exchanging the two members of every pair
+// (or the planes above and below) leaves each sum's bits unchanged.
 // ---------------------------------------------------------------------------
 constexpr int VSX = MX + 4, VSY = MY + 4, VPL = VSX * VSY;
 constexpr int VSLOT = (VPL + kBlock - 1) / kBlock;
+constexpr int UXTRA = MPL - kBlock;  // halo positions beyond one per thread
+static_assert(UXTRA > 0 && UXTRA <= kBlock, "one or two u_1 halo positions per thread");
 
 __device__ __forceinline__ uint32_t mirror2(int c, uint32_t n) {
   int r = c < 0 ? -c : c;
@@ -875,9 +882,11 @@ __device__ __forceinline__ uint32_t mirror2(int c, uint32_t n) {
 }
 
 template <bool MIXED>
-__global__ __launch_bounds__(kBlock) void k_inner12_march(Inner12Args a, Grid g, uint32_t ncx, uint32_t ncy) {
-  __shared__ double vring[4][VPL];  // slot of V plane p: (p + 8) % 4, p >= -2
-  __shared__ double uring[3][MPL];  // slot of u_1 plane p: (p + 6) % 3, p >= -1
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(5))) void k_inner12_march(
+    Inner12Args a, Grid g, uint32_t ncx, uint32_t ncy) {
+  __shared__ double vring[4][VPL];     // V plane p in slot (p + 8) % 4, p >= -2
+  __shared__ double uring[MPL];        // the newest u_1 plane
+  __shared__ double xring[3][3][UXTRA];  // V plane terms (c, o, t) of plane p at the extra positions, slot (p + 6) % 3
   if (a.tick != nullptr && blockIdx.x == 0 && threadIdx.x == 0) a.tick->step += a.tick_by;
   const uint32_t b = xcd_block(blockIdx.x, gridDim.x);
   const uint32_t bx = b % ncx, byz = b / ncx;
@@ -886,8 +895,7 @@ __global__ __launch_bounds__(kBlock) void k_inner12_march(Inner12Args a, Grid g,
   const int zb = (int)(bz * g.zc);
   const int ze = min(zb + (int)g.zc, (int)g.n2);
   const uint32_t plane = g.n0 * g.n1;
-  // this thread's V staging slots (two-node halo) and u_1 slots (one-node
-  // halo; global in-plane offset for S_V, V-ring index of the centre)
+  // V staging slots (two-node halo)
   uint32_t voff[VSLOT];
   bool vact[VSLOT];
 #pragma unroll
@@ -897,24 +905,25 @@ __global__ __launch_bounds__(kBlock) void k_inner12_march(Inner12Args a, Grid g,
     const int hx = r % VSX, hy = r / VSX;
     voff[k] = vact[k] ? mirror2(x0 + hx - 2, g.n0) + g.n0 * mirror2(y0 + hy - 2, g.n1) : 0u;
   }
-  uint32_t uoff[MSLOT];
-  int uvc[MSLOT];
-  bool uact[MSLOT];
+  // u_1 halo positions: threadIdx.x, and kBlock + threadIdx.x for the
+  // first UXTRA threads (global in-plane offset for S_V, V-ring index)
+  const bool xact = threadIdx.x < UXTRA;
+  uint32_t uoff[2];
+  int ucv[2];
 #pragma unroll
-  for (int k = 0; k < MSLOT; ++k) {
-    const int r = threadIdx.x + k * kBlock;
-    uact[k] = r < MPL;
+  for (int k = 0; k < 2; ++k) {
+    const int r = k == 0 ? (int)threadIdx.x : (xact ? kBlock + (int)threadIdx.x : 0);
     const int hx = r % MSX, hy = r / MSX;
-    uoff[k] = uact[k] ? mirror_any(x0 + hx - 1, g.n0) + g.n0 * mirror_any(y0 + hy - 1, g.n1) : 0u;
-    uvc[k] = (hy + 1) * VSX + (hx + 1);
+    uoff[k] = mirror2(x0 + hx - 1, g.n0) + g.n0 * mirror2(y0 + hy - 1, g.n1);
+    ucv[k] = (hy + 1) * VSX + (hx + 1);
   }
-  const double *__restrict__ V = a.V;
+  const auto V = gptr(a.V);
   auto vplane = [&](int z) { return (size_t)mirror2(z, g.n2) * plane; };
-  auto uplane = [&](int z) { return (size_t)mirror_any(z, g.n2) * plane; };
   // Every load is unconditional (inactive slots read offset 0 of the plane,
-  // threads beyond the grid the nearest node; nothing they load is used),
-  // so that the prologue's loads are all in flight together and the
-  // compiler can count the loads it waits for.
+  // threads beyond the grid the nearest node, planes beyond the column
+  // reflected; nothing they load is used), so that the prologue's loads are
+  // all in flight together and the compiler can count the loads it waits
+  // for.
   auto load_v = [&](int z, double *v) {
     const size_t pz = vplane(z);
 #pragma unroll
@@ -927,29 +936,44 @@ __global__ __launch_bounds__(kBlock) void k_inner12_march(Inner12Args a, Grid g,
       if (vact[k]) dst[threadIdx.x + k * kBlock] = v[k];
   };
   auto load_svh = [&](int z, double *sv) {
-    const size_t pz = uplane(z);
+    const size_t pz = vplane(z);
 #pragma unroll
-    for (int k = 0; k < MSLOT; ++k) sv[k] = load_sv(a.SV, MIXED, pz + uoff[k]);
+    for (int k = 0; k < 2; ++k) sv[k] = load_sv(a.SV, MIXED, pz + uoff[k]);
   };
-  // u_1 on the halo plane p from V planes p-1, p, p+1
-  auto form_u1 = [&](int p, const double *sv) {
-    const double *vm = vring[(p + 7) % 4], *vc = vring[(p + 8) % 4], *vp = vring[(p + 9) % 4];
-    double *dst = uring[(p + 6) % 3];
-#pragma unroll
-    for (int k = 0; k < MSLOT; ++k) {
-      if (!uact[k]) continue;
-      const int c = uvc[k];
-      const double Fv = grid_stencil<3>(g.w, [&](int dx, int dy, int dz) {
-        const double *pl = dz < 0 ? vm : (dz > 0 ? vp : vc);
-        return pl[c + dy * VSX + dx];
-      });
-      dst[threadIdx.x + k * kBlock] = first_inner(a.mu1_eta, vc[c], Fv, sv[k]);
-    }
+  // V plane terms of plane z at halo position k
+  auto vterms = [&](int z, int k) {
+    const double *src = vring[(z + 8) % 4];
+    const int cc = ucv[k];
+    return plane_terms(g.w, [&](int dx, int dy) { return src[cc + dy * VSX + dx]; });
   };
+  auto xput = [&](int z, const PlaneTerms &v) {
+    double(*dst)[UXTRA] = xring[(z + 6) % 3];
+    dst[0][threadIdx.x] = v.c;
+    dst[1][threadIdx.x] = v.o;
+    dst[2][threadIdx.x] = v.t;
+  };
+  auto xget = [&](int z) {
+    double(*src)[UXTRA] = xring[(z + 6) % 3];
+    return PlaneTerms{src[0][threadIdx.x], src[1][threadIdx.x], src[2][threadIdx.x]};
+  };
+  // u_1 at halo position k of the plane whose V terms are o (m below, p above)
+  auto put_u = [&](int k, const PlaneTerms &m, const PlaneTerms &o, const PlaneTerms &p, double sv) {
+    uring[threadIdx.x + k * kBlock] = first_inner(a.mu1_eta, o.c, plane_combine(g.w, m, o, p), sv);
+  };
+  const int lx = threadIdx.x % MX, ly = threadIdx.x / MX;
+  const uint32_t gx = (uint32_t)(x0 + lx), gy = (uint32_t)(y0 + ly);
+  const bool own = gx < g.n0 && gy < g.n1;
+  const int cu = (ly + 1) * MSX + (lx + 1);
+  const int cv = (ly + 2) * VSX + (lx + 2);
+  auto uterms = [&]() { return plane_terms(g.w, [&](int dx, int dy) { return uring[cu + dy * MSX + dx]; }); };
+  // the node whose operands are loaded: this thread's own node, or the
+  // nearest node of the grid for threads beyond its edge
+  uint32_t i = min(gx, g.n0 - 1) + g.n0 * min(gy, g.n1 - 1) + plane * (uint32_t)zb;
+  const bool need_v2 = a.last && !a.t.j1;
   // the prologue: V planes zb - 2 .. zb + 2, the halo's S_V of planes
   // zb - 1 .. zb + 1 and the first node's operands, all loaded at once
   double v0[VSLOT], v1[VSLOT], v2[VSLOT], v3[VSLOT], vpre[VSLOT];
-  double svm[MSLOT], sv0[MSLOT], sv[MSLOT];
+  double svm[2], sv0[2], svpre[2];
   load_v(zb - 2, v0);
   load_v(zb - 1, v1);
   load_v(zb, v2);
@@ -957,61 +981,75 @@ __global__ __launch_bounds__(kBlock) void k_inner12_march(Inner12Args a, Grid g,
   load_v(zb + 2, vpre);
   load_svh(zb - 1, svm);
   load_svh(zb, sv0);
-  load_svh(zb + 1, sv);
-  const int lx = threadIdx.x % MX, ly = threadIdx.x / MX;
-  const uint32_t gx = (uint32_t)(x0 + lx), gy = (uint32_t)(y0 + ly);
-  const bool own = gx < g.n0 && gy < g.n1;
-  const int c = (ly + 1) * MSX + (lx + 1);
-  const int cv = (ly + 2) * VSX + (lx + 2);
-  // the node whose operands are loaded: this thread's own node, or the
-  // nearest node of the grid for threads beyond its edge
-  uint32_t i = min(gx, g.n0 - 1) + g.n0 * min(gy, g.n1 - 1) + plane * (uint32_t)zb;
-  const bool need_v2 = a.last && !a.t.j1;
-  double sv_own = load_sv(a.SV, MIXED, i), v2_own = need_v2 ? a.Vin2[i] : 0.0;
+  load_svh(zb + 1, svpre);
+  const auto Vin2 = gptr(a.Vin2);
+  const auto out = gptr(a.out);
+  double sv_own = load_sv(a.SV, MIXED, i), v2_own = need_v2 ? Vin2[i] : 0.0;
   put_v(zb - 2, v0);
   put_v(zb - 1, v1);
   put_v(zb, v2);
   put_v(zb + 1, v3);
   __syncthreads();
-  form_u1(zb - 1, svm);
-  form_u1(zb, sv0);
-  __syncthreads();  // the pre-loop's u_1 planes read V plane zb - 2, whose slot is refilled next
+  // u_1 planes zb - 1 and zb; kept: V terms of planes zb and zb + 1 (C, D)
+  PlaneTerms C, D;
+  {
+    const PlaneTerms A = vterms(zb - 2, 0), B = vterms(zb - 1, 0);
+    C = vterms(zb, 0);
+    D = vterms(zb + 1, 0);
+    put_u(0, A, B, C, svm[0]);
+    if (xact) {
+      const PlaneTerms xa = vterms(zb - 2, 1), xb = vterms(zb - 1, 1), xc = vterms(zb, 1), xd = vterms(zb + 1, 1);
+      put_u(1, xa, xb, xc, svm[1]);
+      xput(zb, xc);
+      xput(zb + 1, xd);
+    }
+  }
+  __syncthreads();
+  PlaneTerms um = uterms();  // u_1 terms of plane z - 1
+  __syncthreads();
+  put_u(0, vterms(zb - 1, 0), C, D, sv0[0]);
+  if (xact) put_u(1, vterms(zb - 1, 1), xget(zb), xget(zb + 1), sv0[1]);
+  __syncthreads();
+  PlaneTerms uo = uterms();  // u_1 terms of plane z
   for (int z = zb; z < ze; ++z, i += plane) {
-    {
-      double *dst = vring[(z + 10) % 4];
-#pragma unroll
-      for (int k = 0; k < VSLOT; ++k)
-        if (vact[k]) dst[threadIdx.x + k * kBlock] = vpre[k];
-    }
-    double svh[MSLOT];
-#pragma unroll
-    for (int k = 0; k < MSLOT; ++k) svh[k] = sv[k];
+    // V plane z + 2 into the slot of plane z - 2, whose last readers
+    // finished before the barriers of the previous plane
+    put_v(z + 2, vpre);
+    __syncthreads();
+    const double svh0 = svpre[0], svh1 = svpre[1];
     const double sv_cur = sv_own, v2_cur = v2_own;
+    load_v(z + 3, vpre);
+    load_svh(z + 2, svpre);
     if (z + 1 < ze) {
-      load_v(z + 3, vpre);
-      load_svh(z + 2, sv);
       sv_own = load_sv(a.SV, MIXED, i + plane);
-      if (need_v2) v2_own = a.Vin2[i + plane];
+      if (need_v2) v2_own = Vin2[i + plane];
+    }
+    // u_1 plane z + 1 (the ring's only plane: its readers finished before
+    // this plane's first barrier)
+    const PlaneTerms E = vterms(z + 2, 0);
+    put_u(0, C, D, E, svh0);
+    if (xact) {
+      const PlaneTerms xe = vterms(z + 2, 1);
+      put_u(1, xget(z), xget(z + 1), xe, svh1);
+      xput(z + 2, xe);
     }
     __syncthreads();
-    form_u1(z + 1, svh);
-    __syncthreads();
+    const PlaneTerms up = uterms();
     if (own) {
-      const double *um = uring[(z + 5) % 3], *uc = uring[(z + 6) % 3], *up = uring[(z + 7) % 3];
-      const double Fu = grid_stencil<3>(g.w, [&](int dx, int dy, int dz) {
-        const double *pl = dz < 0 ? um : (dz > 0 ? up : uc);
-        return pl[c + dy * MSX + dx];
-      });
+      const double Fu = plane_combine(g.w, um, uo, up);
       const double u0 = vring[(z + 8) % 4][cv];
-      const double u1 = uc[c];
-      const double u2 = inner_combine(a.t, u1, u0, Fu, sv_cur);
+      const double u2 = inner_combine(a.t, uo.c, u0, Fu, sv_cur);
       if (a.last) {
-        a.out[i] = tail_combine(a.t, u2, u0, v2_cur);
+        out[i] = tail_combine(a.t, u2, u0, v2_cur);
       } else {
-        a.u1out[i] = u1;
-        a.out[i] = u2;
+        gptr(a.u1out)[i] = uo.c;
+        out[i] = u2;
       }
     }
+    C = D;
+    D = E;
+    um = uo;
+    uo = up;
   }
 }
 
