@@ -1018,8 +1018,11 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(5))) voi
     __syncthreads();
     const double svh0 = svpre[0], svh1 = svpre[1];
     const double sv_cur = sv_own, v2_cur = v2_own;
-    load_v(z + 3, vpre);
-    load_svh(z + 2, svpre);
+    // the column needs V up to plane ze + 1 and S_V up to ze: the last
+    // plane's loads repeat the previous plane's (served by L2) instead of
+    // fetching planes nothing uses
+    load_v(min(z + 3, ze + 1), vpre);
+    load_svh(min(z + 2, ze), svpre);
     if (z + 1 < ze) {
       sv_own = load_sv(a.SV, MIXED, i + plane);
       if (need_v2) v2_own = Vin2[i + plane];
