@@ -884,9 +884,12 @@ __device__ __forceinline__ uint32_t mirror2(int c, uint32_t n) {
 template <bool MIXED>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(5))) void k_inner12_march(
     Inner12Args a, Grid g, uint32_t ncx, uint32_t ncy) {
-  __shared__ double vring[4][VPL];     // V plane p in slot (p + 8) % 4, p >= -2
-  __shared__ double uring[MPL];        // the newest u_1 plane
-  __shared__ double xring[3][3][UXTRA];  // V plane terms (c, o, t) of plane p at the extra positions, slot (p + 6) % 3
+  // ring slots are numbered from the column's first plane zb: plane zb + c
+  // sits in slot c mod 4 (c >= -2), so that with the loop unrolled by four
+  // every slot index is a constant
+  __shared__ double vring[4][VPL];       // V planes
+  __shared__ double uring[MPL];          // the newest u_1 plane
+  __shared__ double xring[4][3][UXTRA];  // V plane terms (c, o, t) at the extra positions
   if (a.tick != nullptr && blockIdx.x == 0 && threadIdx.x == 0) a.tick->step += a.tick_by;
   const uint32_t b = xcd_block(blockIdx.x, gridDim.x);
   const uint32_t bx = b % ncx, byz = b / ncx;
@@ -929,8 +932,8 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(5))) voi
 #pragma unroll
     for (int k = 0; k < VSLOT; ++k) v[k] = V[pz + voff[k]];
   };
-  auto put_v = [&](int z, const double *v) {
-    double *dst = vring[(z + 8) % 4];
+  auto put_v = [&](int s, const double *v) {
+    double *dst = vring[s];
 #pragma unroll
     for (int k = 0; k < VSLOT; ++k)
       if (vact[k]) dst[threadIdx.x + k * kBlock] = v[k];
@@ -940,21 +943,19 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(5))) voi
 #pragma unroll
     for (int k = 0; k < 2; ++k) sv[k] = load_sv(a.SV, MIXED, pz + uoff[k]);
   };
-  // V plane terms of plane z at halo position k
-  auto vterms = [&](int z, int k) {
-    const double *src = vring[(z + 8) % 4];
+  // V plane terms of the plane in slot s at halo position k
+  auto vterms = [&](int s, int k) {
+    const double *src = vring[s];
     const int cc = ucv[k];
     return plane_terms(g.w, [&](int dx, int dy) { return src[cc + dy * VSX + dx]; });
   };
-  auto xput = [&](int z, const PlaneTerms &v) {
-    double(*dst)[UXTRA] = xring[(z + 6) % 3];
-    dst[0][threadIdx.x] = v.c;
-    dst[1][threadIdx.x] = v.o;
-    dst[2][threadIdx.x] = v.t;
+  auto xput = [&](int s, const PlaneTerms &v) {
+    xring[s][0][threadIdx.x] = v.c;
+    xring[s][1][threadIdx.x] = v.o;
+    xring[s][2][threadIdx.x] = v.t;
   };
-  auto xget = [&](int z) {
-    double(*src)[UXTRA] = xring[(z + 6) % 3];
-    return PlaneTerms{src[0][threadIdx.x], src[1][threadIdx.x], src[2][threadIdx.x]};
+  auto xget = [&](int s) {
+    return PlaneTerms{xring[s][0][threadIdx.x], xring[s][1][threadIdx.x], xring[s][2][threadIdx.x]};
   };
   // u_1 at halo position k of the plane whose V terms are o (m below, p above)
   auto put_u = [&](int k, const PlaneTerms &m, const PlaneTerms &o, const PlaneTerms &p, double sv) {
@@ -985,36 +986,38 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(5))) voi
   const auto Vin2 = gptr(a.Vin2);
   const auto out = gptr(a.out);
   double sv_own = load_sv(a.SV, MIXED, i), v2_own = need_v2 ? Vin2[i] : 0.0;
-  put_v(zb - 2, v0);
-  put_v(zb - 1, v1);
-  put_v(zb, v2);
-  put_v(zb + 1, v3);
+  put_v(2, v0);  // planes zb - 2 .. zb + 1
+  put_v(3, v1);
+  put_v(0, v2);
+  put_v(1, v3);
   __syncthreads();
   // u_1 planes zb - 1 and zb; kept: V terms of planes zb and zb + 1 (C, D)
   PlaneTerms C, D;
   {
-    const PlaneTerms A = vterms(zb - 2, 0), B = vterms(zb - 1, 0);
-    C = vterms(zb, 0);
-    D = vterms(zb + 1, 0);
+    const PlaneTerms A = vterms(2, 0), B = vterms(3, 0);
+    C = vterms(0, 0);
+    D = vterms(1, 0);
     put_u(0, A, B, C, svm[0]);
     if (xact) {
-      const PlaneTerms xa = vterms(zb - 2, 1), xb = vterms(zb - 1, 1), xc = vterms(zb, 1), xd = vterms(zb + 1, 1);
+      const PlaneTerms xa = vterms(2, 1), xb = vterms(3, 1), xc = vterms(0, 1), xd = vterms(1, 1);
       put_u(1, xa, xb, xc, svm[1]);
-      xput(zb, xc);
-      xput(zb + 1, xd);
+      xput(0, xc);
+      xput(1, xd);
     }
   }
   __syncthreads();
   PlaneTerms um = uterms();  // u_1 terms of plane z - 1
   __syncthreads();
-  put_u(0, vterms(zb - 1, 0), C, D, sv0[0]);
-  if (xact) put_u(1, vterms(zb - 1, 1), xget(zb), xget(zb + 1), sv0[1]);
+  put_u(0, vterms(3, 0), C, D, sv0[0]);
+  if (xact) put_u(1, vterms(3, 1), xget(0), xget(1), sv0[1]);
   __syncthreads();
   PlaneTerms uo = uterms();  // u_1 terms of plane z
-  for (int z = zb; z < ze; ++z, i += plane) {
+  // plane z = zb + 4q + r; R is r as a constant
+  auto body = [&](int z, auto R) {
+    constexpr int r = decltype(R)::value;
     // V plane z + 2 into the slot of plane z - 2, whose last readers
     // finished before the barriers of the previous plane
-    put_v(z + 2, vpre);
+    put_v((r + 2) & 3, vpre);
     __syncthreads();
     const double svh0 = svpre[0], svh1 = svpre[1];
     const double sv_cur = sv_own, v2_cur = v2_own;
@@ -1029,18 +1032,18 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(5))) voi
     }
     // u_1 plane z + 1 (the ring's only plane: its readers finished before
     // this plane's first barrier)
-    const PlaneTerms E = vterms(z + 2, 0);
+    const PlaneTerms E = vterms((r + 2) & 3, 0);
     put_u(0, C, D, E, svh0);
     if (xact) {
-      const PlaneTerms xe = vterms(z + 2, 1);
-      put_u(1, xget(z), xget(z + 1), xe, svh1);
-      xput(z + 2, xe);
+      const PlaneTerms xe = vterms((r + 2) & 3, 1);
+      put_u(1, xget(r & 3), xget((r + 1) & 3), xe, svh1);
+      xput((r + 2) & 3, xe);
     }
     __syncthreads();
     const PlaneTerms up = uterms();
     if (own) {
       const double Fu = plane_combine(g.w, um, uo, up);
-      const double u0 = vring[(z + 8) % 4][cv];
+      const double u0 = vring[r & 3][cv];
       const double u2 = inner_combine(a.t, uo.c, u0, Fu, sv_cur);
       if (a.last) {
         out[i] = tail_combine(a.t, u2, u0, v2_cur);
@@ -1053,6 +1056,13 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(5))) voi
     D = E;
     um = uo;
     uo = up;
+    i += plane;
+  };
+  for (int z = zb; z < ze; z += 4) {
+    body(z, std::integral_constant<int, 0>());
+    if (z + 1 < ze) body(z + 1, std::integral_constant<int, 1>());
+    if (z + 2 < ze) body(z + 2, std::integral_constant<int, 2>());
+    if (z + 3 < ze) body(z + 3, std::integral_constant<int, 3>());
   }
 }
 
