@@ -396,7 +396,7 @@ def main():
             db = bytes_per_node(dom, nz, 8, m, mat) * N
         dom_gbs = db / (dom_ms * 1e-3) / 1e9
         # HBM bytes per launch from the committed rocprof counters, when they
-        # were taken on these kernel sources for the kernel shape chosen here
+        # were taken on these library sources for the kernel shape chosen here
         prof_path = os.path.join(ROOT, "profiles", "traffic_k_%s%s_%s_fp64.json"
                                  % ("mrkc_" if args.method == "mrkc" else "", dom, cfg["name"]))
         traffic = None
@@ -655,7 +655,7 @@ def bench_imexrl(args, cfg, N, tet, stream, E, torch):
 
 def counted(tr, part, variants, sub=None):
     """HBM bytes per launch from the committed counters (None when they were
-    not taken on these kernel sources or for these kernel shapes)."""
+    not taken on these library sources or for these kernel shapes)."""
     if tr is None:
         return None
     ent = tr.get(part, {}).get("%d,%d,%d" % (variants[0], variants[1], variants[4]))
@@ -665,9 +665,12 @@ def counted(tr, part, variants, sub=None):
 
 
 def kernel_hash():
+    """Hash of the library's sources: the kernels and the host code, which
+    chooses their launch shapes and the data layout they read (z in blocks
+    or in component planes)."""
     import hashlib
     h = hashlib.sha256()
-    for f in ("emrkc_kernels.hip", "emrkc_device.h", "emrkc_internal.h"):
+    for f in ("emrkc_kernels.hip", "emrkc_device.h", "emrkc_internal.h", "emrkc_host.hip"):
         h.update(open(os.path.join(ROOT, "paper_2401_01745_amd", "csrc", f), "rb").read())
     return h.hexdigest()[:16]
 

@@ -76,14 +76,15 @@ extern "C" {
  *   applies, without asking the autotuner;
  * EMRKC_FLAT — structured grids use the flat (untiled) kernels only;
  * EMRKC_Z_PLANES — emrkc_step (and the autotuner's and profiler's steps)
- *   keep z in the state's component planes while stepping.  Without it, a
- *   single emRKC context without rho_every whose head is not a z-marching
- *   one (3-D kernel shapes 1 and 2) and whose z array holds at least
- *   256 MiB converts z on entry into a library buffer that holds each
- *   block of 256 nodes' components contiguously (n_z x 256 values per
- *   block), steps on that buffer and converts back before it returns; the
- *   buffer (the size of z, rounded up to whole blocks) is allocated on
- *   first use, and where that allocation fails the planes are kept.
+ *   keep z in the state's component planes while stepping.  Without it, an
+ *   emRKC context without rho_every (a single context whose head is not a
+ *   z-marching one, 3-D kernel shapes 1 and 2, or a batch) whose z array
+ *   holds at least 256 MiB converts z on entry into a library buffer that
+ *   holds each block of 256 nodes' components contiguously (n_z x 256
+ *   values per block), steps on that buffer and converts back before it
+ *   returns; the buffer (the size of z, rounded up to whole blocks) is
+ *   allocated on first use, and where that allocation fails the planes are
+ *   kept.
  *   emrkc_step_noalloc always keeps the planes.
  * EMRKC_Z_BLOCKS — the block layout above also for z arrays below 256 MiB
  *   (EMRKC_Z_PLANES takes precedence).

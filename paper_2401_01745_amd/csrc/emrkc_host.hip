@@ -1301,9 +1301,9 @@ static int ensure_z1(emrkc_ctx *c) {
 // contiguous run instead of 2 n_z component planes, which moved the
 // pointwise head's bytes 14% faster on the 36.5M-node slab.  The caller's z
 // is converted on entry and back on exit; EMRKC_Z_PLANES, rho_every (whose
-// estimates read the caller's z between chunks), mRKC and batches, the
-// z-marching heads and a failed allocation of the block buffer keep the
-// component planes.  So does a z array below kZBlocksMinBytes unless
+// estimates read the caller's z between chunks), mRKC, the z-marching
+// heads and a failed allocation of the block buffer keep the component
+// planes.  So does a z array below kZBlocksMinBytes unless
 // EMRKC_Z_BLOCKS asks for blocks: it is served from the 256 MB last-level
 // cache in either layout (the 3-D grid of 442k nodes, 71 MB of z, steps at
 // the same rate in both), so the two conversion launches per call would
@@ -1311,8 +1311,11 @@ static int ensure_z1(emrkc_ctx *c) {
 constexpr size_t kZBlocksMinBytes = size_t(256) << 20;
 
 static bool zblocks_mode(const emrkc_ctx *c, const StepPlan &P) {
-  if (c->batch || c->method != EMRKC_METHOD_EMRKC || (c->flags & EMRKC_Z_PLANES) || c->rho_every > 0) return false;
+  if (c->method != EMRKC_METHOD_EMRKC || (c->flags & EMRKC_Z_PLANES) || c->rho_every > 0) return false;
   if (!(c->flags & EMRKC_Z_BLOCKS) && z_bytes(c) < kZBlocksMinBytes) return false;
+  // both batched heads read z through head_node (the tables are built
+  // after the layout is chosen, with the buffer it uses)
+  if (c->batch) return true;
   if (split_mode(c, P) || u1_split_mode(c, P)) return true;
   // every other emRKC head reads and writes z through head_node, which
   // takes either layout, except the z-marching heads (3-D shapes 1 and 2),
@@ -1498,9 +1501,13 @@ static int step_core(emrkc_ctx *c, emrkc_state *st, double dt, int64_t nsteps) {
   StepPlan P;
   int rc = make_plan(c, dt, P);
   if (rc != EMRKC_OK) return rc;
-  if (c->batch && (rc = build_batch_tables(c, st, dt, P)) != EMRKC_OK) return rc;
   bool used_graph = false, zb = false;
   if ((rc = zblocks_begin(c, st, P, &zb)) != EMRKC_OK) return rc;
+  // a batch's tables name the z buffer the layout uses: built after it
+  if (c->batch && (rc = build_batch_tables(c, st, dt, P)) != EMRKC_OK) {
+    (void)zblocks_end(c, st, zb);
+    return rc;
+  }
   rc = run_chunks(c, st, dt, nsteps, P.s, P.m,
                   [&](int L, hipStream_t strm) { return enqueue_chunk(c, st, P, dt, L, strm); }, &used_graph);
   const int rc_end = zblocks_end(c, st, zb);
@@ -1903,12 +1910,15 @@ extern "C" int emrkc_profile_step(emrkc_ctx *c, emrkc_state *st, double dt, int6
   StepPlan P;
   int rc = make_plan(c, dt, P);
   if (rc != EMRKC_OK) return rc;
-  if (c->batch && (rc = build_batch_tables(c, st, dt, P)) != EMRKC_OK) return rc;
   rebase_clock(st, dt);
   HIP_TRY(c, launch_clock_set(c->d_clock, st->step, st->t0, c->stream));
   KernelTimer tm;
   bool zb = false;
   if ((rc = zblocks_begin(c, st, P, &zb)) != EMRKC_OK) return rc;
+  if (c->batch && (rc = build_batch_tables(c, st, dt, P)) != EMRKC_OK) {
+    (void)zblocks_end(c, st, zb);
+    return rc;
+  }
   rc = enqueue_chunk(c, st, P, dt, (int)nsteps, c->stream, &tm);
   const int rc_end = zblocks_end(c, st, zb);
   if (rc == EMRKC_OK) rc = rc_end;
@@ -2069,7 +2079,8 @@ static int time_classes(emrkc_ctx *c, emrkc_state *st, const StepPlan &P, double
   bool zb = false;
   int rc = zblocks_begin(c, st, P, &zb);  // the z layout emrkc_step would use
   if (rc != EMRKC_OK) return rc;
-  rc = enqueue_chunk(c, st, P, dt, 1, c->stream, nullptr);  // untimed: first launch of each kernel
+  if (c->batch) rc = build_batch_tables(c, st, dt, P);
+  if (rc == EMRKC_OK) rc = enqueue_chunk(c, st, P, dt, 1, c->stream, nullptr);  // untimed: first launches
   KernelTimer tm;
   if (rc == EMRKC_OK) rc = enqueue_chunk(c, st, P, dt, reps, c->stream, &tm);
   const int rc_end = zblocks_end(c, st, zb);
@@ -2128,7 +2139,6 @@ static int autotune_batch(emrkc_ctx *c, const emrkc_state *st, double dt, int re
   for (int shape = 0; shape < 3 && rc == EMRKC_OK; ++shape) {
     const int v[5] = {shape, 0, 0, 0, 0};
     set_variants(c, v);
-    if ((rc = build_batch_tables(c, &cp.st, dt, P)) != EMRKC_OK) break;
     double ms[3];
     if ((rc = time_classes_best(c, &cp.st, P, dt, reps, ms)) != EMRKC_OK) break;
     const double step = ms[0] + (P.m - 1) * ms[1];
@@ -2148,8 +2158,7 @@ static int autotune_batch(emrkc_ctx *c, const emrkc_state *st, double dt, int re
     const int v[5] = {choice, 1, 0, 0, 0};
     set_variants(c, v);
     double ms[3];
-    if ((rc = build_batch_tables(c, &cp.st, dt, P)) == EMRKC_OK &&
-        (rc = time_classes_best(c, &cp.st, P, dt, reps, ms)) == EMRKC_OK) {
+    if ((rc = time_classes_best(c, &cp.st, P, dt, reps, ms)) == EMRKC_OK) {
       if (verbose) fprintf(stderr, "emrkc_autotune: batch flat head: head %.5f ms (tiled %.5f ms)\n", ms[0], head_t);
       if (ms[0] < 0.97 * head_t) flat = 1;
     }
@@ -2161,8 +2170,7 @@ static int autotune_batch(emrkc_ctx *c, const emrkc_state *st, double dt, int re
     const int v[5] = {choice, flat, 2, 0, 0};
     set_variants(c, v);
     double ms[3];
-    if ((rc = build_batch_tables(c, &cp.st, dt, P)) == EMRKC_OK &&
-        (rc = time_classes_best(c, &cp.st, P, dt, reps, ms)) == EMRKC_OK) {
+    if ((rc = time_classes_best(c, &cp.st, P, dt, reps, ms)) == EMRKC_OK) {
       if (verbose) fprintf(stderr, "emrkc_autotune: batch two tiles per block: inner %.5f ms (tiles %.5f ms)\n", ms[1],
                            inner_t);
       if (ms[1] < 0.97 * best_in) {
@@ -2180,7 +2188,6 @@ static int autotune_batch(emrkc_ctx *c, const emrkc_state *st, double dt, int re
     if (rc != EMRKC_OK || !any3d || P.m < 2) break;
     const int v[5] = {choice, flat, 1, zc, 0};
     set_variants(c, v);
-    if ((rc = build_batch_tables(c, &cp.st, dt, P)) != EMRKC_OK) break;
     double ms[3];
     if ((rc = time_classes_best(c, &cp.st, P, dt, reps, ms)) != EMRKC_OK) break;
     if (verbose)
@@ -2209,7 +2216,8 @@ static int time_steps(emrkc_ctx *c, emrkc_state *st, const StepPlan &P, double d
   bool zb = false;
   int rc = zblocks_begin(c, st, P, &zb);  // the z layout emrkc_step would use
   if (rc != EMRKC_OK) return rc;
-  rc = enqueue_chunk(c, st, P, dt, 2, c->stream, nullptr);  // untimed: first launches
+  if (c->batch) rc = build_batch_tables(c, st, dt, P);
+  if (rc == EMRKC_OK) rc = enqueue_chunk(c, st, P, dt, 2, c->stream, nullptr);  // untimed: first launches
   if (rc != EMRKC_OK) {
     (void)zblocks_end(c, st, zb);
     return rc;
@@ -3121,7 +3129,8 @@ static int build_batch_tables(emrkc_ctx *c, const emrkc_state *st, double dt, co
   memcpy(&dtb, &dt, sizeof dtb);
   const int shape_key =
       c->batch_shape + (c->batch_flat_head ? 3 : 0) + 8 * c->batch_march_zc + (c->batch_pairs ? 1024 : 0);
-  if (c->bdev.valid && c->bdev.dt_bits == dtb && c->bdev.V == st->V && c->bdev.z == st->z &&
+  void *const zbuf = zstate(c, st);  // the state's z, or the block buffer while a call steps on it
+  if (c->bdev.valid && c->bdev.dt_bits == dtb && c->bdev.V == st->V && c->bdev.z == zbuf &&
       c->bdev.shape == shape_key)
     return EMRKC_OK;
   (void)hipStreamSynchronize(c->stream);
@@ -3174,7 +3183,8 @@ static int build_batch_tables(emrkc_ctx *c, const emrkc_state *st, double dt, co
         if (k == 1) {
           HeadArgs &h = b.h;
           h.Vin = X[par];
-          h.zin = h.zout = st->z;
+          h.zin = h.zout = zbuf;
+          h.z_aos = c->zb_run ? 1 : 0;
           h.SV = c->d_SV;
           h.uout = I.m == 1 ? X[1 - par] : c->d_U[0];
           h.clock = c->d_clock;
@@ -3227,7 +3237,7 @@ static int build_batch_tables(emrkc_ctx *c, const emrkc_state *st, double dt, co
   c->bdev.dt_bits = dtb;
   c->bdev.shape = shape_key;
   c->bdev.V = st->V;
-  c->bdev.z = st->z;
+  c->bdev.z = zbuf;
   c->bdev.s = P.s;
   c->bdev.m_max = P.m;
   c->bdev.eta = P.eta;

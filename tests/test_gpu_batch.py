@@ -75,6 +75,14 @@ def test_batch_equals_single_runs_bitwise_and_graph_equals_eager(ens):
                   (1, 1, 2, 0, 0), (0, 0, 2, 0, 0), (2, 1, 2, 0, 0)):
         V4, z4, _, _ = run_batch(cfgs, (rF, rS), 41, shape=shape)
         assert np.array_equal(V, V4) and np.array_equal(z, z4), shape
+    # z in blocks of 256 nodes while stepping (an ensemble this small keeps
+    # the component planes by default): tiled and flat batched heads, eager
+    # launches and a call split (a conversion each way per call)
+    ZB = E.EMRKC_Z_BLOCKS
+    for shape, fl, ch in [(None, ZB, None), ((1, 1, 0, 0, 0), ZB, None), ((2, 1, 2, 0, 0), ZB, None),
+                          ((0, 0, 1, 4, 0), ZB | E.EMRKC_EAGER, None), (None, ZB, [3, 32, 6])]:
+        V5, z5, _, _ = run_batch(cfgs, (rF, rS), 41, shape=shape, flags=fl, chunks=ch)
+        assert np.array_equal(V, V5) and np.array_equal(z, z5), (shape, fl, ch)
     # single-instance contexts with the same masks
     import torch
     for k, cfg in enumerate(cfgs):
@@ -108,12 +116,16 @@ def test_batch_mixed_precision_against_oracle_per_instance(ens):
     oracle run: 1e-4 relative L2 in V (ten times that on the maximum, which
     sits at the front), and the float-stored ionic state within 1e-3 of each
     component's range."""
+    from paper_2401_01745_amd import emrkc as E
     cfgs, probs, rhos = ens
     rF = [r[0] for r in rhos]
     rSmax = max(r[1] for r in rhos)
     rS = [rSmax] * len(rhos)
     nsteps = 80
     V, z, off, m = run_batch(cfgs, (rF, rS), nsteps, precision="mixed")
+    # the same bits with float z in blocks of 256 nodes while stepping
+    Vb, zb, _, _ = run_batch(cfgs, (rF, rS), nsteps, precision="mixed", flags=E.EMRKC_Z_BLOCKS)
+    assert np.array_equal(V, Vb) and np.array_equal(z, zb)
     for k, (cfg, prob) in enumerate(zip(cfgs, probs)):
         y = emrkc_run(prob, prob.uniform_state(), 0.0, cfg["dt"], nsteps, rF[k], rSmax)
         Y = y.reshape(prob.nv, prob.N)
