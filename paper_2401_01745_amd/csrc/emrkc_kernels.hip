@@ -705,15 +705,21 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(WPE))) v
 }
 
 // Pointwise operands of an inner stage at one node, loaded a plane ahead.
+// S_V stays in its storage type (float in the mixed form) until it is used:
+// converting it where it is loaded would wait for the load there, which
+// undoes the prefetch of the next plane's operands
+template <bool MIXED>
 struct InnerPoint {
-  double u2, sv, vp, vp2;
+  double u2;
+  typename std::conditional<MIXED, float, double>::type sv;
+  double vp, vp2;
 };
 
 template <bool MIXED>
-__device__ __forceinline__ InnerPoint load_point(const InnerArgs &a, uint32_t i) {
-  InnerPoint p;
+__device__ __forceinline__ InnerPoint<MIXED> load_point(const InnerArgs &a, uint32_t i) {
+  InnerPoint<MIXED> p;
   p.u2 = a.first ? 0.0 : gptr(a.t.uprev2)[i];
-  p.sv = load_sv(a.t.SV, MIXED, i);
+  p.sv = gptr((const decltype(p.sv) *)a.t.SV)[i];
   p.vp = 0.0;
   p.vp2 = 0.0;
   if (a.last) {
@@ -727,9 +733,11 @@ __device__ __forceinline__ InnerPoint load_point(const InnerArgs &a, uint32_t i)
 
 // inner_value / tail_from_um with the operands given (same expressions);
 // the first inner stage (a.first) is u_1 = u_0 + mu'_1 eta (f_F(u_0) + S_V)
-__device__ __forceinline__ double inner_point(const InnerArgs &a, double uc, double Fu, const InnerPoint &p) {
-  if (a.first) return first_inner(a.t.mu_eta, uc, Fu, p.sv);
-  const double uk = inner_combine(a.t, uc, p.u2, Fu, p.sv);
+template <bool MIXED>
+__device__ __forceinline__ double inner_point(const InnerArgs &a, double uc, double Fu, const InnerPoint<MIXED> &p) {
+  const double sv = (double)p.sv;
+  if (a.first) return first_inner(a.t.mu_eta, uc, Fu, sv);
+  const double uk = inner_combine(a.t, uc, p.u2, Fu, sv);
   return a.last ? tail_combine(a.t, uk, a.t.uprev2 == a.t.Vin ? p.u2 : p.vp, p.vp2) : uk;
 }
 
@@ -744,7 +752,7 @@ __global__ __launch_bounds__(kBlock) void k_inner_tiled(InnerArgs a, Grid g, uin
   uint32_t i;
   int c;
   const bool own = tile_node<DIM>(g, x0, y0, z0, i, c);
-  InnerPoint pt{0.0, 0.0, 0.0, 0.0};
+  InnerPoint<MIXED> pt{};
   if (own) pt = load_point<MIXED>(a, i);
   stage_halo<DIM>(sU, a.t.uprev, g, x0, y0, z0);
   __syncthreads();
@@ -810,7 +818,7 @@ __device__ __forceinline__ void inner_march_col(const InnerArgs &a, const Grid &
   // the node whose operands are loaded: this thread's own node, or the
   // nearest node of the grid for threads beyond its edge
   uint32_t i = min(gx, g.n0 - 1) + g.n0 * min(gy, g.n1 - 1) + plane * (uint32_t)zb;
-  InnerPoint pt = load_point<MIXED>(a, base + i);
+  InnerPoint<MIXED> pt = load_point<MIXED>(a, base + i);
   // slot of plane p is p mod 3 (p >= -1)
 #pragma unroll
   for (int k = 0; k < MSLOT; ++k)
@@ -824,7 +832,7 @@ __device__ __forceinline__ void inner_march_col(const InnerArgs &a, const Grid &
     for (int k = 0; k < MSLOT; ++k)
       if (act[k]) nxt[threadIdx.x + k * kBlock] = pre[k];
     __syncthreads();
-    const InnerPoint cur = pt;
+    const InnerPoint<MIXED> cur = pt;
     if (z + 1 < ze) {
       const size_t pz = gplane(z + 2);
 #pragma unroll
@@ -938,10 +946,14 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(5))) voi
     for (int k = 0; k < VSLOT; ++k)
       if (vact[k]) dst[threadIdx.x + k * kBlock] = v[k];
   };
-  auto load_svh = [&](int z, double *sv) {
+  // S_V is kept in its storage type (float in the mixed form) until it is
+  // used: a conversion at the load would wait for the load there
+  using SR = typename std::conditional<MIXED, float, double>::type;
+  const auto SVg = gptr((const SR *)a.SV);
+  auto load_svh = [&](int z, SR *sv) {
     const size_t pz = vplane(z);
 #pragma unroll
-    for (int k = 0; k < 2; ++k) sv[k] = load_sv(a.SV, MIXED, pz + uoff[k]);
+    for (int k = 0; k < 2; ++k) sv[k] = SVg[pz + uoff[k]];
   };
   // V plane terms of the plane in slot s at halo position k
   auto vterms = [&](int s, int k) {
@@ -974,7 +986,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(5))) voi
   // the prologue: V planes zb - 2 .. zb + 2, the halo's S_V of planes
   // zb - 1 .. zb + 1 and the first node's operands, all loaded at once
   double v0[VSLOT], v1[VSLOT], v2[VSLOT], v3[VSLOT], vpre[VSLOT];
-  double svm[2], sv0[2], svpre[2];
+  SR svm[2], sv0[2], svpre[2];
   load_v(zb - 2, v0);
   load_v(zb - 1, v1);
   load_v(zb, v2);
@@ -985,7 +997,8 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(5))) voi
   load_svh(zb + 1, svpre);
   const auto Vin2 = gptr(a.Vin2);
   const auto out = gptr(a.out);
-  double sv_own = load_sv(a.SV, MIXED, i), v2_own = need_v2 ? Vin2[i] : 0.0;
+  SR sv_own = SVg[i];
+  double v2_own = need_v2 ? Vin2[i] : 0.0;
   put_v(2, v0);  // planes zb - 2 .. zb + 1
   put_v(3, v1);
   put_v(0, v2);
@@ -1019,15 +1032,16 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(5))) voi
     // finished before the barriers of the previous plane
     put_v((r + 2) & 3, vpre);
     __syncthreads();
-    const double svh0 = svpre[0], svh1 = svpre[1];
-    const double sv_cur = sv_own, v2_cur = v2_own;
+    const SR svh0 = svpre[0], svh1 = svpre[1];
+    const SR sv_cur = sv_own;
+    const double v2_cur = v2_own;
     // the column needs V up to plane ze + 1 and S_V up to ze: the last
     // plane's loads repeat the previous plane's (served by L2) instead of
     // fetching planes nothing uses
     load_v(min(z + 3, ze + 1), vpre);
     load_svh(min(z + 2, ze), svpre);
     if (z + 1 < ze) {
-      sv_own = load_sv(a.SV, MIXED, i + plane);
+      sv_own = SVg[i + plane];
       if (need_v2) v2_own = Vin2[i + plane];
     }
     // u_1 plane z + 1 (the ring's only plane: its readers finished before
@@ -1044,7 +1058,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(5))) voi
     if (own) {
       const double Fu = plane_combine(g.w, um, uo, up);
       const double u0 = vring[r & 3][cv];
-      const double u2 = inner_combine(a.t, uo.c, u0, Fu, sv_cur);
+      const double u2 = inner_combine(a.t, uo.c, u0, Fu, (double)sv_cur);
       if (a.last) {
         out[i] = tail_combine(a.t, u2, u0, v2_cur);
       } else {
@@ -1112,18 +1126,23 @@ __device__ __forceinline__ void inner_all_tile(const InnerAllArgs &a, const Grid
   // u_1 on the whole frame, V and S_V on the frame less one ring; all of a
   // thread's loads are issued before the first is stored (one latency)
   constexpr int kPass = (kAllR * kAllR + kBlock - 1) / kBlock;
-  double lu[kPass], lv[kPass], ls[kPass];
+  // S_V in its storage type until it is stored (a conversion at the load
+  // would wait for it before the next loads)
+  using SR = typename std::conditional<MIXED, float, double>::type;
+  double lu[kPass], lv[kPass];
+  SR ls[kPass];
 #pragma unroll
   for (int k = 0; k < kPass; ++k) {
     const int p = threadIdx.x + k * kBlock;
-    lu[k] = lv[k] = ls[k] = 0.0;
+    lu[k] = lv[k] = 0.0;
+    ls[k] = SR(0);
     if (p < F * F) {
       const int fx = p % F, fy = p / F;
       const uint32_t i = reflect(x0 + fx - rmax, g.n0) + g.n0 * reflect(y0 + fy - rmax, g.n1);
       lu[k] = a.u1[i];
       if (fx >= 1 && fx < F - 1 && fy >= 1 && fy < F - 1) {
         lv[k] = a.V[i];
-        ls[k] = load_sv(a.SV, MIXED, i);
+        ls[k] = gptr((const SR *)a.SV)[i];
       }
     }
   }
@@ -1134,7 +1153,7 @@ __device__ __forceinline__ void inner_all_tile(const InnerAllArgs &a, const Grid
       const int q = (p / F) * kAllR + p % F;
       U[1][q] = lu[k];
       sV[q] = lv[k];
-      sS[q] = ls[k];
+      sS[q] = (double)ls[k];
     }
   }
   __syncthreads();
@@ -1507,7 +1526,7 @@ __device__ __forceinline__ void inner_tile(const BatchInst &I, uint32_t tile, do
   int c;
   const bool own = tile_node<DIM, SH>(I.g, x0, y0, z0, il, c);
   const uint32_t i = I.off + il;
-  InnerPoint pt{0.0, 0.0, 0.0, 0.0};
+  InnerPoint<MIXED> pt{};
   if (own) pt = load_point<MIXED>(a, i);
   stage_halo<DIM, SH>(sU, a.t.uprev + I.off, I.g, x0, y0, z0);
   __syncthreads();
@@ -1533,7 +1552,7 @@ __device__ __forceinline__ void inner_tile_pair(const BatchInst &I, uint32_t pai
   int ca = 0, cb = 0;
   const bool owna = tile_node<DIM, SH>(I.g, xa, ya, za, ila, ca);
   const bool ownb = tile_node<DIM, SH>(I.g, xb, yb, zb, ilb, cb) && hasb;
-  InnerPoint pa{0.0, 0.0, 0.0, 0.0}, pb{0.0, 0.0, 0.0, 0.0};
+  InnerPoint<MIXED> pa{}, pb{};
   if (owna) pa = load_point<MIXED>(a, I.off + ila);
   if (ownb) pb = load_point<MIXED>(a, I.off + ilb);
   Halo<DIM, SH> ha, hb;
