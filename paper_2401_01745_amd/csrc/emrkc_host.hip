@@ -1437,7 +1437,10 @@ static int run_chunks(emrkc_ctx *c, const emrkc_state *st, double dt, int64_t ns
     }
     uint64_t dtb;
     memcpy(&dtb, &dt, sizeof dtb);
-    GraphKey key{key_s, key_m, len, dtb, st->V, st->z};
+    // keyed by the z buffer the kernels use (the state's, or the block
+    // buffer), so a layout change between calls cannot replay a graph
+    // captured for the other one
+    GraphKey key{key_s, key_m, len, dtb, st->V, zstate(c, st)};
     hipGraphExec_t exec = nullptr;
     auto it = c->graphs.find(key);
     if (it != c->graphs.end()) {

@@ -141,36 +141,66 @@ __device__ __forceinline__ ZAt z_at(bool blocks, uint32_t N, uint32_t i, int nz)
   return ZAt{i, N};
 }
 
-// z_{j-1} of node i (all ionic components)
+// z_{j-1} of node i (all ionic components).  NT: non-temporal loads, used
+// by the pointwise head of the split stage when z is held in blocks (which
+// the host does only for arrays of 256 MiB and more): each value is read
+// once per step and does not stay in the caches anyway, and bypassing them
+// keeps the inner kernel's operands there (on the 36.5M-node slab the
+// pointwise head took 2.31 instead of 2.37 ms, 1.07 instead of 1.16 ms in
+// the mixed form, and the following inner kernel 0.310 instead of
+// 0.321 ms).  Heads that read the V stencil through the caches lose by it
+// (the flat batched head of the 64-instance ensemble: 0.455 against
+// 0.431 ms), and so does a cache-resident z (a 442k-node grid's head took
+// 64 instead of 38 us).  NT is a template parameter: with a run-time
+// choice the compiler merged the two paths' accesses into ordinary ones.
 template <template <class> class Model, bool MIXED>
 struct HeadZ {
   using R = typename MathOf<MIXED>::R;
   static constexpr int NZ = Model<MathOf<MIXED>>::NG + Model<MathOf<MIXED>>::NS;
   R z[NZ];
+  template <bool NT>
   __device__ __forceinline__ void load(const void *zin, ZAt at) {
     const auto p = gptr((const R *)zin);
 #pragma unroll
-    for (int k = 0; k < NZ; ++k) z[k] = p[at.base + k * at.stride];
+    for (int k = 0; k < NZ; ++k) {
+      if (NT)
+        z[k] = __builtin_nontemporal_load(&p[at.base + k * at.stride]);
+      else
+        z[k] = p[at.base + k * at.stride];
+    }
   }
-  __device__ __forceinline__ void load(const void *zin, uint32_t N, uint32_t i) { load(zin, z_at(false, N, i, NZ)); }
+  __device__ __forceinline__ void load(const void *zin, uint32_t N, uint32_t i) {
+    load<false>(zin, z_at(false, N, i, NZ));
+  }
 };
 
-template <template <class> class Model, bool MIXED, bool SV_ONLY = false, class FVf>
+// A store of z: non-temporal for z held in blocks (see HeadZ).
+template <bool NT, class P, class R>
+__device__ __forceinline__ void z_store(P zout, size_t idx, R v) {
+  if (NT)
+    __builtin_nontemporal_store(v, &zout[idx]);
+  else
+    zout[idx] = v;
+}
+
+// NT: non-temporal z accesses (the kernel is launched so only with z in
+// blocks; see HeadZ)
+template <template <class> class Model, bool MIXED, bool SV_ONLY = false, bool NT = false, class FVf>
 __device__ __forceinline__ void head_node_z(const HeadArgs &a, uint32_t N, uint32_t i, double V,
                                             const typename MathOf<MIXED>::R *z, double Is, FVf FVfun);
 
-template <template <class> class Model, bool MIXED, bool SV_ONLY = false, class FVf>
+template <template <class> class Model, bool MIXED, bool SV_ONLY = false, bool NT = false, class FVf>
 __device__ __forceinline__ void head_node(const HeadArgs &a, uint32_t N, uint32_t i, double V, FVf FVfun) {
   HeadZ<Model, MIXED> hz;
-  hz.load(a.zin, z_at(a.z_aos != 0, N, i, HeadZ<Model, MIXED>::NZ));
+  hz.template load<NT>(a.zin, z_at(a.z_aos != 0, N, i, HeadZ<Model, MIXED>::NZ));
   const double tj = stage_time(a.clock, a.step_off, a.dt, a.c_prev);
-  head_node_z<Model, MIXED, SV_ONLY>(a, N, i, V, hz.z, stimulus(a.stim, i, tj), FVfun);
+  head_node_z<Model, MIXED, SV_ONLY, NT>(a, N, i, V, hz.z, stimulus(a.stim, i, tj), FVfun);
 }
 
 // The head at node i with z_{j-1} and the stimulus current I_stim(t_j) at
 // the node given.  SV_ONLY: the pointwise head of the split stage (m >= 2),
 // which stores S_V and leaves the first inner stage to k_inner12_march.
-template <template <class> class Model, bool MIXED, bool SV_ONLY, class FVf>
+template <template <class> class Model, bool MIXED, bool SV_ONLY, bool NT, class FVf>
 __device__ __forceinline__ void head_node_z(const HeadArgs &a, uint32_t N, uint32_t i, double V,
                                             const typename MathOf<MIXED>::R *z, double Is, FVf FVfun) {
   using M = MathOf<MIXED>;
@@ -208,7 +238,7 @@ __device__ __forceinline__ void head_node_z(const HeadArgs &a, uint32_t N, uint3
 #pragma unroll
   for (int k = 0; k < NZ; ++k) {
     if (MIXED && k < NG && a.j1) {
-      zout[za.base + k * za.stride] = R(__builtin_fmaf(gate_c, (float)(zE[k] - z[k]), (float)z[k]));
+      z_store<NT>(zout, za.base + k * za.stride, R(__builtin_fmaf(gate_c, (float)(zE[k] - z[k]), (float)z[k])));
       continue;
     }
     double fbar;
@@ -225,7 +255,7 @@ __device__ __forceinline__ void head_node_z(const HeadArgs &a, uint32_t N, uint3
       zj = (double)z[k] + a.mu_dt * fbar;
     else
       zj = a.nu * (double)z[k] + a.kappa * (double)zin2[za.base + k * za.stride] + a.mu_dt * fbar;
-    zout[za.base + k * za.stride] = R(zj);
+    z_store<NT>(zout, za.base + k * za.stride, R(zj));
   }
 
   if (SV_ONLY) {
@@ -280,11 +310,11 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(7))) voi
 // stencil (the first inner stage moves to k_inner12_march).  On the large
 // slab this keeps the head a pure stream of the ionic state: the 27 V
 // operands of the flat head cost it about a tenth of its time.
-template <template <class> class Model, bool MIXED>
+template <template <class> class Model, bool MIXED, bool NT>
 __global__ __launch_bounds__(kBlock) void k_head_pw(HeadArgs a, uint32_t N) {
   const uint32_t i = node_index();
   if (i >= N) return;
-  head_node<Model, MIXED, true>(a, N, i, a.Vin[i], []() { return 0.0; });
+  head_node<Model, MIXED, true, NT>(a, N, i, a.Vin[i], []() { return 0.0; });
 }
 
 // ---------------------------------------------------------------------------
@@ -2359,10 +2389,16 @@ hipError_t launch_inner_all(bool mixed, const Mesh &mesh, const InnerAllArgs &a,
 
 template <template <class> class Model>
 static hipError_t head_pw_dispatch(bool mixed, uint32_t N, const HeadArgs &a, hipStream_t st) {
-  if (mixed)
-    EMRKC_LAUNCH((k_head_pw<Model, true>), dim3(blocks_for(N)), dim3(kBlock), 0, st, a, N);
+  // non-temporal z accesses with z in blocks (large arrays only)
+  const dim3 grid(blocks_for(N));
+  if (mixed && a.z_aos)
+    EMRKC_LAUNCH((k_head_pw<Model, true, true>), grid, dim3(kBlock), 0, st, a, N);
+  else if (mixed)
+    EMRKC_LAUNCH((k_head_pw<Model, true, false>), grid, dim3(kBlock), 0, st, a, N);
+  else if (a.z_aos)
+    EMRKC_LAUNCH((k_head_pw<Model, false, true>), grid, dim3(kBlock), 0, st, a, N);
   else
-    EMRKC_LAUNCH((k_head_pw<Model, false>), dim3(blocks_for(N)), dim3(kBlock), 0, st, a, N);
+    EMRKC_LAUNCH((k_head_pw<Model, false, false>), grid, dim3(kBlock), 0, st, a, N);
   return hipGetLastError();
 }
 
