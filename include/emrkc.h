@@ -206,7 +206,8 @@ typedef struct {
   double eta;             /* inner integration length                         */
   int64_t kernels_per_step;
   int32_t used_graph;     /* 1 if the steps were replayed from a HIP graph    */
-  int32_t reserved0;
+  int32_t z_blocks;       /* 1 if z was held in blocks of 256 nodes while the
+                             call stepped (see EMRKC_Z_PLANES)                */
 } emrkc_stats;
 
 /* ---- host-only helpers (no GPU needed) ---------------------------------- */

@@ -1482,7 +1482,7 @@ static int check_finite(emrkc_ctx *c, const emrkc_state *st) {
   return EMRKC_OK;
 }
 
-static void set_last_stats(emrkc_ctx *c, const StepPlan &P, bool used_graph) {
+static void set_last_stats(emrkc_ctx *c, const StepPlan &P, bool used_graph, bool z_blocks = false) {
   c->last.s = P.s;
   c->last.m = P.m;
   c->last.eta = P.eta;
@@ -1498,6 +1498,7 @@ static void set_last_stats(emrkc_ctx *c, const StepPlan &P, bool used_graph) {
                                  ? (int64_t)P.m - 1
                                  : (P.s == 1 && P.m == 1) ? 1 : (int64_t)P.s * P.m + (P.m == 1 ? 1 : 0);
   c->last.used_graph = used_graph ? 1 : 0;
+  c->last.z_blocks = z_blocks ? 1 : 0;
 }
 
 static int step_core(emrkc_ctx *c, emrkc_state *st, double dt, int64_t nsteps) {
@@ -1518,7 +1519,7 @@ static int step_core(emrkc_ctx *c, emrkc_state *st, double dt, int64_t nsteps) {
   if (rc != EMRKC_OK) return rc;
   st->step += nsteps;
   st->t = state_time(st->t0, st->step, dt);
-  set_last_stats(c, P, used_graph);
+  set_last_stats(c, P, used_graph, zb);
   return check_finite(c, st);
 }
 

@@ -67,7 +67,7 @@ class State(C.Structure):
 
 class Stats(C.Structure):
     _fields_ = [("s", C.c_int32), ("m", C.c_int32), ("eta", C.c_double), ("kernels_per_step", C.c_int64),
-                ("used_graph", C.c_int32), ("reserved0", C.c_int32)]
+                ("used_graph", C.c_int32), ("z_blocks", C.c_int32)]
 
 
 EXPORTS = {

@@ -31,6 +31,9 @@ def run_batch(cfgs, rho, nsteps, precision="fp64", flags=0, chunks=None, shape=N
     for n in (chunks or [nsteps]):
         E.emrkc_step(sim.ctx, sim.state, cfgs[0]["dt"], n)
     torch.cuda.synchronize()
+    # the layout the calls stepped with: blocks when asked for (these
+    # ensembles are small enough to keep the planes otherwise)
+    assert E.emrkc_last_stats(sim.ctx).z_blocks == (1 if flags & E.EMRKC_Z_BLOCKS else 0)
     off, m, rF, rS = E.emrkc_batch_info(sim.ctx, cfgs[0]["dt"])
     out = sim.V.cpu().numpy().copy(), sim.z.cpu().numpy().astype(np.float64), off, m
     sim.close()
@@ -213,6 +216,7 @@ def test_full_ensemble_in_the_bench_configuration():
     rSmax = max(rS)
     E.emrkc_step(sim.ctx, sim.state, dt, nsteps)
     torch.cuda.synchronize()
+    assert E.emrkc_last_stats(sim.ctx).z_blocks == 1  # 1.0 GB of z: stepped in blocks
     V = sim.V.cpu().numpy().copy()
     assert off[-1] == V.size and V.size > 6_900_000
     # the 3-D instances' inner stages in z-marching columns, and two tiles

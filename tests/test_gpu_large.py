@@ -48,6 +48,8 @@ def test_c5_full_size_full_length_planar_wave_against_1d_oracle(precision, tol_l
     E.emrkc_init_state(sim.ctx, sim.state)
     E.emrkc_step(sim.ctx, sim.state, cfg["dt"], NSTEPS)
     torch.cuda.synchronize()
+    # a z array this large (5.8 GB FP64, 2.9 GB mixed) is stepped in blocks
+    assert E.emrkc_last_stats(sim.ctx).z_blocks == 1
     V = sim.V.view(101, 601, 601)
     ref = torch.from_numpy(Y[0]).cuda().view(1, 1, 601)
     d = V - ref

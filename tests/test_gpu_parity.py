@@ -186,6 +186,7 @@ def test_stage_plans(E, rho, dt, sm):
             for fl in (E.EMRKC_Z_BLOCKS, E.EMRKC_Z_PLANES):  # z in blocks (z_1 too, for s >= 2) and in planes
                 V7, _, st7 = gpu_run(cfg, 60, rho, variants=v, flags=fl)
                 assert (st7.s, st7.m) == sm
+                assert st7.z_blocks == (1 if fl == E.EMRKC_Z_BLOCKS else 0)
                 assert np.array_equal(V7, V), (v, fl)
 
 
@@ -258,8 +259,11 @@ def test_graph_eager_fused_split_and_repeat_are_bitwise_identical(E, n, rho, pre
     # kernels, eager launches and an odd call split (a conversion each way
     # per call)
     ZB = E.EMRKC_Z_BLOCKS
+    assert st1.z_blocks == 0
     for fl in (ZB, ZB | E.EMRKC_FUSE, ZB | E.EMRKC_FLAT, ZB | E.EMRKC_EAGER):
-        runs.append(gpu_run(cfg, 80, rho, precision=precision, flags=fl)[:2])
+        Vb, zb, stb = gpu_run(cfg, 80, rho, precision=precision, flags=fl)
+        assert stb.z_blocks == 1, fl
+        runs.append((Vb, zb))
     runs.append(gpu_run(cfg, 80, rho, precision=precision, flags=ZB, chunks=[1, 33, 7, 39])[:2])
     if len(n) == 3:
         # z-marching head (register and LDS-staged) and inner kernels with
