@@ -305,6 +305,9 @@ def main():
                          "imexrl: the IMEX-RL method (implicit diffusion by preconditioned CG), FP64")
     ap.add_argument("--variants", default=None,
                     help="kernel shapes 'head,head_planes,inner,inner_planes,fused' instead of autotuning")
+    ap.add_argument("--z-layout", default="auto", choices=["auto", "blocks", "planes"],
+                    help="ionic state layout while stepping: the library's choice (blocks of 256 nodes for z "
+                         "arrays of 256 MiB and more), or forced; counted traffic is reported for auto only")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="copy a buffer of this size once (calibrates rocprof FETCH/WRITE counters)")
     args = ap.parse_args()
@@ -352,12 +355,13 @@ def main():
         return
     with torch.cuda.stream(stream):
         log("bench: %s, N=%d, building FP64 context" % (cfg["name"], N))
-        flags = 0
+        flags = {"auto": 0, "blocks": E.EMRKC_Z_BLOCKS, "planes": E.EMRKC_Z_PLANES}[args.z_layout]
         job = Job(cfg, "fp64", stream, flags, tet, batch, method=args.method)
         forced = tuple(int(x) for x in args.variants.split(",")) if args.variants else None
         variants = job.tune(forced)
         log("bench: fp64 kernel shapes %s" % (variants,))
         elapsed, (rF, rS, itF, itS) = time_jobs(job, args.warmup, args.steps, torch)
+        z_blocks = bool(E.emrkc_last_stats(job.sim.ctx).z_blocks)  # the layout the timed steps used
         s, m, eta = E.emrkc_stages(job.sim.ctx, cfg["dt"])
         value = N * job.nsim * args.steps / elapsed
         log("bench: fp64 %.3f ms per simulation (%d steps), %.4g node-steps/s, s=%d m=%d" %
@@ -402,7 +406,7 @@ def main():
         traffic = None
         valu = None
         tr_ok = None  # the counters file, when taken on these sources
-        if args.method in ("emrkc", "mrkc") and os.path.exists(prof_path):
+        if args.method in ("emrkc", "mrkc") and args.z_layout == "auto" and os.path.exists(prof_path):
             tr = json.load(open(prof_path))
             ent = tr.get("by_shape", {}).get("%d,%d,%d" % (variants[0], variants[1], variants[4]))
             if tr.get("kernel_source_hash") == kernel_hash() and ent is not None:
@@ -574,7 +578,8 @@ def main():
                                      if batch is not None else ("Q1 grid %s" % "x".join(map(str, cfg["n"]))),
                                      N, cfg["model"], cfg["chi"], cfg["Cm"], list(cfg["sigma"]), cfg["dt"], cfg["T"],
                                      job.nsim, mname),
-                      "method": args.method, "kernel_shapes": variants, "s": s, "m": m, "eta": eta, "rho_F": rF, "rho_S": rS, "powiter_iters": [itF, itS]},
+                      "method": args.method, "kernel_shapes": variants, "s": s, "m": m, "eta": eta, "rho_F": rF, "rho_S": rS, "powiter_iters": [itF, itS],
+                      "z_layout": "blocks of 256 nodes" if z_blocks else "component planes"},
            "roofline": roof, "fp64_error": fp64_err, "mixed": mixed, "cpu_baseline": cpu}
     print(json.dumps(out), flush=True)
 
