@@ -198,8 +198,17 @@ def test_stage_plans_mixed(E, rho, dt, sm):
     recur in double; both stay within the mixed-precision bound (FP32
     ionic state: a few 1e-6 relative over 60 steps)."""
     cfg = small_config("c2_3d_crn", (23, 17, 7), dt=dt)
-    _, _, _, stats = _compare_full(cfg, 60, rho, tol=2e-5, precision="mixed")
+    _, _, V, stats = _compare_full(cfg, 60, rho, tol=2e-5, precision="mixed")
     assert (stats.s, stats.m) == sm
+    # float z (and z_1 for s >= 2, read back as z_{j-2}) in blocks and in
+    # planes, with the flat head and with the split stage: the same bits
+    for v in [None, (7, 3, 1, 4, 0), (8, 0, 1, 4, 0)] if sm[1] >= 2 else [None]:
+        runs = [gpu_run(cfg, 60, rho, precision="mixed", variants=v, flags=fl)
+                for fl in (E.EMRKC_Z_BLOCKS, E.EMRKC_Z_PLANES)]
+        assert runs[0][2].z_blocks == 1 and runs[1][2].z_blocks == 0
+        for Vr, zr, _ in runs:
+            assert np.array_equal(Vr, V), v
+        assert np.array_equal(runs[0][1], runs[1][1]), v
 
 
 def test_linear_model_closed_form_on_gpu(E):
