@@ -22,8 +22,11 @@ namespace emrkc {
 // forms below (all on finite arguments):
 //   * exp / expm1: reduction x = k ln2 + r, |r| <= ln2/2, with ln2 split in
 //     a rounded part and its remainder and both products taken with fused
-//     multiply-adds (Cody and Waite); e^r - 1 from its Taylor series to
-//     degree 13 (remainder below 5e-18 relative) and reconstruction
+//     multiply-adds (Cody and Waite); e^r - 1 = r + r^2 p(r) with p the
+//     degree-9 minimax polynomial of (e^r - 1 - r)/r^2 on [-ln2/2, ln2/2]
+//     (Remez exchange, coefficients from gen_exp_minimax.py: its error
+//     1.0e-16 in p is at most 1.2e-17 relative in e^r; the degree-13 Taylor
+//     form it replaces took two more fused multiply-adds) and reconstruction
 //     e^x = 2^k (1 + q), e^x - 1 = 2^k q + (2^k - 1) (exact for k = 0, so
 //     expm1 keeps full relative accuracy near 0).  About 1 ulp (exp) and 3
 //     ulp (expm1); e^x underflows to 0 below -745 and overflows above 709.8;
@@ -48,19 +51,18 @@ __device__ __forceinline__ double expm1_reduced(double x, int &k) {
   const double kd = __builtin_rint(x * kLog2E);
   double r = __builtin_fma(-kd, kLn2Hi, x);
   r = __builtin_fma(-kd, kLn2Lo, r);
-  // q = r + r^2 (1/2! + r/3! + ... + r^11/13!)
-  double p = 1.0 / 6227020800.0;
-  p = __builtin_fma(p, r, 1.0 / 479001600.0);
-  p = __builtin_fma(p, r, 1.0 / 39916800.0);
-  p = __builtin_fma(p, r, 1.0 / 3628800.0);
-  p = __builtin_fma(p, r, 1.0 / 362880.0);
-  p = __builtin_fma(p, r, 1.0 / 40320.0);
-  p = __builtin_fma(p, r, 1.0 / 5040.0);
-  p = __builtin_fma(p, r, 1.0 / 720.0);
-  p = __builtin_fma(p, r, 1.0 / 120.0);
-  p = __builtin_fma(p, r, 1.0 / 24.0);
-  p = __builtin_fma(p, r, 1.0 / 6.0);
-  p = __builtin_fma(p, r, 0.5);
+  // q = r + r^2 p(r), p the degree-9 minimax polynomial of (e^r - 1 - r)/r^2
+  // on [-ln2/2, ln2/2] (Remez exchange; gen_exp_minimax.py)
+  double p = 0x1.af631ec60423bp-26;
+  p = __builtin_fma(p, r, 0x1.28917d2f3a399p-22);
+  p = __builtin_fma(p, r, 0x1.71ddf6ba48e19p-19);
+  p = __builtin_fma(p, r, 0x1.a019b913fad3ap-16);
+  p = __builtin_fma(p, r, 0x1.a01a01b009f52p-13);
+  p = __builtin_fma(p, r, 0x1.6c16c1788a1f2p-10);
+  p = __builtin_fma(p, r, 0x1.111111110f808p-7);
+  p = __builtin_fma(p, r, 0x1.5555555553d67p-5);
+  p = __builtin_fma(p, r, 0x1.5555555555558p-3);
+  p = __builtin_fma(p, r, 0x1.0000000000001p-1);
   k = (int)kd;  // saturates for |x| > 1.4e9, where 2^k is 0 or inf anyway
   return __builtin_fma(p * r, r, r);
 }
