@@ -213,22 +213,30 @@ struct SigmoidGate {
   double A, Va, inv_sa, Vb, inv_sb;
 };
 
+// Lambda and z_inf of a surrogate gate from its two exponentials ep, eq in
+// double (one reciprocal serves both: no overflow in double)
+__device__ __forceinline__ void sigmoid_from_exps(double A, double ep, double eq, double &lam, double &zinf) {
+  const double p = 1.0 + ep, q = 1.0 + eq;
+  const double pq = p * q, spq = p + q;
+  const double r = detail::rcp_f64(pq * spq);
+  lam = -A * (spq * spq) * r;
+  zinf = q * (pq * r);
+}
+
 template <class M>
 __device__ __forceinline__ void sigmoid_gate(typename M::R V, const SigmoidGate &g,
                                              typename M::R &lam, typename M::R &zinf) {
   using R = typename M::R;
   // alpha = A/p, beta = A/q with p = 1 + e^{-(V-Va)/sa}, q = 1 + e^{(V-Vb)/sb}:
   // Lambda = -A (p+q)/(p q), z_inf = q/(p+q)
-  const R p = R(1) + M::exp(-(V - R(g.Va)) * R(g.inv_sa));
-  const R q = R(1) + M::exp((V - R(g.Vb)) * R(g.inv_sb));
-  const R pq = p * q, spq = p + q;
-  if (sizeof(R) == 8) {
-    const R r = M::rcp(pq * spq);  // one reciprocal serves both (no overflow in double)
-    lam = -R(g.A) * (spq * spq) * r;
-    zinf = q * (pq * r);
+  const R ep = M::exp(-(V - R(g.Va)) * R(g.inv_sa));
+  const R eq = M::exp((V - R(g.Vb)) * R(g.inv_sb));
+  if constexpr (sizeof(R) == 8) {
+    sigmoid_from_exps(g.A, ep, eq, lam, zinf);
   } else {
-    lam = -R(g.A) * spq * M::rcp(pq);
-    zinf = q * M::rcp(spq);
+    const R p = R(1) + ep, q = R(1) + eq;
+    lam = -R(g.A) * (p + q) * M::rcp(p * q);
+    zinf = q * M::rcp(p + q);
   }
 }
 
@@ -284,7 +292,7 @@ struct LinearModel {
 // CRN-shaped surrogate: V, 15 gates (m, h, n, g3..g14), 5 slow variables
 // (Na_i, K_i, Ca_i, Ca_up, Ca_rel).  Project-written; not the published
 // Courtemanche-Ramirez-Nattel model.
-__device__ __constant__ static const SigmoidGate kCrnGates[12] = {
+static constexpr SigmoidGate kCrnGates[12] = {
     {2.0, -20.0, 1.0 / 10.0, -12.0, 1.0 / 13.0},
     {0.06, -50.0, 1.0 / -8.0, -58.0, 1.0 / -10.4},
     {0.4, -10.0, 1.0 / 12.0, -2.0, 1.0 / 15.6},
@@ -299,6 +307,66 @@ __device__ __constant__ static const SigmoidGate kCrnGates[12] = {
     {0.04, 0.0, 1.0 / 10.0, 8.0, 1.0 / 13.0},
 };
 
+// The gates of the CRN surrogate in double precision, the same rates as
+// hh_core_gates (scaled by 15) and sigmoid_gate over kCrnGates; f(g, Lambda,
+// z_inf) is called once per gate.  Each rate exponential is e^{aV + b}, and
+// most slopes a recur (1/10, 1/13, 1/8, 1/10.4 and 1/20) or are twice
+// another one (1/6, 1/7.8, 1/10 and 1/13 against 1/12, 1/15.6, 1/20 and
+// 1/26).  So e^{aV + b} is formed as e^{aV} e^b, with e^b a compile-time
+// constant, e^{2aV} as the square of e^{aV} and e^{-aV} as its reciprocal:
+// 15 exponentials (the two expm1 of the x/(e^x - 1) rates among them) and 4
+// reciprocals in place of 30 exponentials.  Each factor adds at most a
+// rounding or two, so every rate stays within a few ulp of the direct form.
+// The constants e^b are exp_f64 of constant arguments, which the compiler
+// evaluates.  The gates are taken group by group of shared exponentials, so
+// that each group is consumed (by f) before the next one is formed.
+template <class F>
+__device__ __forceinline__ void crn_gates_f64(double V, F f) {
+  using detail::exp_f64;
+  using detail::rcp_f64;
+  auto sig = [&](int g, double ep, double eq) {
+    double lam, zinf;
+    sigmoid_from_exps(kCrnGates[g].A, ep, eq, lam, zinf);
+    f(3 + g, lam, zinf);
+  };
+  auto hh = [&](int g, double al, double be) {
+    double lam, zinf;
+    gate_from_rates<MathF64>(al, be, lam, zinf);
+    f(g, lam, zinf);
+  };
+  {  // slopes 1/20, 1/10, 1/26 and 1/13
+    const double E20 = exp_f64(V * (1.0 / 20.0)), r20 = rcp_f64(E20);  // e^{+-V/20}
+    const double E10 = E20 * E20, r10 = r20 * r20;                     // e^{+-V/10}
+    const double E26 = exp_f64(V * (1.0 / 26.0)), r26 = rcp_f64(E26);  // e^{+-V/26}
+    const double E13 = E26 * E26, r13 = r26 * r26;                     // e^{+-V/13}
+    hh(1, r20 * (0.07 * exp_f64(-65.0 / 20.0)), rcp_f64(1.0 + r10 * exp_f64(-3.5)));  // h
+    sig(0, r10 * exp_f64(-2.0), E13 * exp_f64(12.0 / 13.0));
+    sig(3, E10 * exp_f64(4.0), r13 * exp_f64(-48.0 / 13.0));
+    sig(7, E20 * exp_f64(2.0), r26 * exp_f64(-48.0 / 26.0));
+    sig(10, E10 * exp_f64(3.0), r13 * exp_f64(-38.0 / 13.0));
+    sig(11, r10, E13 * exp_f64(-8.0 / 13.0));
+    sig(9, r13 * exp_f64(5.0 / 13.0), exp_f64((V - 13.0) * (1.0 / 16.9)));
+  }
+  {  // slopes 1/8 and 1/10.4
+    const double E8 = exp_f64(V * 0.125), r8 = rcp_f64(E8);                  // e^{+-V/8}
+    const double E104 = exp_f64(V * (1.0 / 10.4)), r104 = rcp_f64(E104);     // e^{+-V/10.4}
+    sig(1, E8 * exp_f64(50.0 / 8.0), r104 * exp_f64(-58.0 / 10.4));
+    sig(6, r8 * exp_f64(-15.0 / 8.0), E104 * exp_f64(7.0 / 10.4));
+  }
+  {  // slopes 1/12, 1/6, 1/15.6 and 1/7.8
+    const double r12 = exp_f64(V * (-1.0 / 12.0)), r6 = r12 * r12;     // e^{-V/12}, e^{-V/6}
+    const double E156 = exp_f64(V * (1.0 / 15.6)), E78 = E156 * E156;  // e^{V/15.6}, e^{V/7.8}
+    sig(2, r12 * exp_f64(-10.0 / 12.0), E156 * exp_f64(2.0 / 15.6));
+    sig(4, r6 * exp_f64(-15.0 / 6.0), E78 * exp_f64(7.0 / 7.8));
+  }
+  // slopes of one rate each
+  sig(5, exp_f64((V + 30.0) * (1.0 / 7.0)), exp_f64(-(V + 38.0) * (1.0 / 9.1)));
+  sig(8, exp_f64(-(V - 10.0) * (1.0 / 15.0)), exp_f64((V - 18.0) * (1.0 / 19.5)));
+  hh(0, 15.0 * x_over_expm1<MathF64>(-(V + 40.0) * 0.1),
+     15.0 * (4.0 * exp_f64(-(V + 65.0) * (1.0 / 18.0))));  // m
+  hh(2, 0.1 * x_over_expm1<MathF64>(-(V + 55.0) * 0.1), 0.125 * exp_f64(-(V + 65.0) * (1.0 / 80.0)));  // n
+}
+
 template <class M>
 struct CrnSurrModel {
   using R = typename M::R;
@@ -308,9 +376,16 @@ struct CrnSurrModel {
     hh_m_gate<M>(V, R(15), lam, zinf);
   }
   static __device__ __forceinline__ void gates(R V, const ModelParams &, R *lam, R *zinf) {
-    hh_core_gates<M>(V, R(15), lam, zinf);
+    if constexpr (std::is_same<R, double>::value) {
+      crn_gates_f64(V, [&](int g, double l, double zi) {
+        lam[g] = l;
+        zinf[g] = zi;
+      });
+    } else {
+      hh_core_gates<M>(V, R(15), lam, zinf);
 #pragma unroll
-    for (int g = 0; g < 12; ++g) sigmoid_gate<M>(V, kCrnGates[g], lam[3 + g], zinf[3 + g]);
+      for (int g = 0; g < 12; ++g) sigmoid_gate<M>(V, kCrnGates[g], lam[3 + g], zinf[3 + g]);
+    }
   }
   static __device__ __forceinline__ R eval(R V, const R *g, const R *zS, R *dS, const ModelParams &) {
     const R Na = zS[0], K = zS[1], Ca = zS[2], Cup = zS[3], Crel = zS[4];

@@ -184,3 +184,40 @@ def test_stage_counts_table(E, name, model):
              + row["mrkc"][2:4] + row["mrkc"][4:]))
     assert row["mrkc"][0] >= 0.99 * row["emrkc"][0]
     assert row["mrkc"][3] >= row["emrkc"][3]
+
+
+@pytest.mark.parametrize("model", ["CRN_SURR", "TTP_SURR", "HH"])
+def test_gate_terms_over_the_voltage_range(E, model):
+    """Every gate's Lambda (z - z_inf), node by node, over V from -120 to 80
+    mV (both removable singularities of x/(e^x - 1) included, and points
+    within 1e-9 mV of them) with gates drawn on [0, 1]: the split's fast
+    term holds the stiff gate, its slow term the others.  Bound per node:
+    1e-13 of |Lambda| (|z| + |z_inf|), a few hundred ulp, against O(1) for a
+    wrong rate constant, sign or slope."""
+    import torch
+    cfg = small_config("c2_3d_crn", (41, 25, 5), model=model)
+    prob = build_grid_problem(cfg)
+    N, nE = prob.N, prob.nE
+    rng = np.random.default_rng(11)
+    V = np.linspace(-120.0, 80.0, N)
+    special = np.array([-40.0, -55.0, -40.0 + 1e-9, -40.0 - 1e-9, -55.0 + 1e-9, -55.0 - 1e-9, -35.0, -65.0])
+    V[rng.choice(N, special.size, replace=False)] = special
+    Y = prob.uniform_state().reshape(prob.nv, N).copy()
+    Y[0] = V
+    Y[1:1 + nE] = rng.uniform(0.0, 1.0, (nE, N))
+    y = Y.reshape(-1)
+    lam, zinf = prob.model.gates(V)
+    sp = MrkcSplit(prob, 0)
+    sim = E.simulation_from_config(cfg, rho=(1.0, 1.0), method="mrkc")
+    sim.V.copy_(torch.from_numpy(Y[0].copy()))
+    sim.z.copy_(torch.from_numpy(Y[1:].copy()))
+    out = torch.empty(prob.nv * N, dtype=torch.float64, device="cuda")
+    for which, f, gates in [(0, sp.f_F, [0]), (1, sp.f_S, range(1, nE))]:
+        E.emrkc_eval_mrkc_terms(sim.ctx, sim.state, 0.5, which, out)
+        got = out.cpu().numpy().reshape(prob.nv, N)
+        ref = f(0.5, y).reshape(prob.nv, N)
+        for g in gates:
+            bound = 1e-13 * np.abs(lam[g]) * (np.abs(Y[1 + g]) + np.abs(zinf[g]))
+            err = np.abs(got[1 + g] - ref[1 + g])
+            assert np.all(err <= bound), (which, g, (err / bound).max(), V[np.argmax(err / bound)])
+    sim.close()
